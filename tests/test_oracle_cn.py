@@ -1,0 +1,93 @@
+"""Pins of the oracle's Crank-Nicolson + PCG (eq_CN, Algorithm 1)."""
+import json
+import os
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from oracle import cn, fd, phif
+from workloads import gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _direct(A, B, u0, dt, steps, react):
+    lu = spla.splu(A.tocsc())
+    u = u0.ravel().copy()
+    for _ in range(steps):
+        u = lu.solve(cn.cn_rhs(B, u, dt, react))
+    return u
+
+
+def test_cn_sine_mode_closed_form():
+    """Constant a, u0 = v11: u^k = G^k v11 (closed form in tests/golden)."""
+    g = json.load(open(os.path.join(GOLD, "cn_sine_mode_32.json")))
+    w = gen.workload("heat2d-32")
+    A, B = fd.cn_matrices(w.a_cells, w.dt)
+    F = phif.phif_build(A, w.n, 2, 8, w.eps)
+    us, iters, rel = cn.cn_solve(A, B, w.u0, w.dt, g["steps"], lambda r: phif.phif_apply(F, r),
+                                 1e-12)
+    v = w.u0.ravel()
+    for k in range(g["steps"] + 1):
+        assert np.allclose(us[k], g["G"] ** k * v, rtol=0, atol=1e-11)
+    assert np.isclose(us[-1].max(), g["max_u10"], rtol=1e-10)
+    assert max(iters) <= 3
+
+
+def test_cn_matches_sparse_direct_solve_with_reaction():
+    n = 24
+    a = gen.grf_coefficient(n, 2, 0.1, 11)
+    u0 = gen.bumps(n, 2, 4, 12)
+    dt = 1e-2
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, 2, 4, 1e-4)
+    react = (1, 1.0, 1.0)
+    us, iters, _ = cn.cn_solve(A, B, u0, dt, 5, lambda r: phif.phif_apply(F, r), 1e-12, react)
+    ud = _direct(A, B, u0, dt, 5, react)
+    assert np.linalg.norm(us[-1] - ud) <= 1e-10 * np.linalg.norm(ud)
+
+
+def test_reaction_pointwise():
+    u = np.array([-0.5, 0.0, 0.3, 1.0, 2.0])
+    assert np.allclose(cn.reaction(u, 1, 2.0, 4.0), [2.0 * x * (1 - x / 4.0) for x in u])
+    assert np.all(cn.reaction(u, 0, 1.0, 1.0) == 0)
+
+
+def test_pcg_exact_preconditioner_one_iteration_and_zero_rhs():
+    n = 15
+    a = gen.iid_loguniform_cells(n, 2, 4)
+    A, _ = fd.cn_matrices(a, 0.1)
+    F = phif.phif_build(A, n, 2, 4, 0.0)     # eps = 0: no compression, F = A
+    b = np.random.default_rng(0).normal(size=n * n)
+    res = cn.pcg(A, b, lambda r: phif.phif_apply(F, r), 1e-12)
+    assert res.converged and res.iters == 1
+    res0 = cn.pcg(A, np.zeros(n * n), lambda r: phif.phif_apply(F, r), 1e-12)
+    assert res0.iters == 0 and not res0.x.any()
+
+
+def test_pcg_unpreconditioned_matches_textbook_cg_solution():
+    n = 10
+    A, _ = fd.cn_matrices(np.ones((n + 1, n + 1)), 0.01)
+    b = np.arange(n * n, dtype=float)
+    res = cn.pcg(A, b, lambda r: r, 1e-13, maxit=1000)
+    assert np.allclose(res.x, spla.spsolve(A.tocsc(), b), rtol=1e-11)
+    # CG in exact arithmetic terminates in at most as many steps as distinct eigenvalues
+    assert res.iters <= n * n
+
+
+def test_second_order_in_space_and_time():
+    """Halving h and dt together divides the error of u(T) by about 4 (a = 1, exact PDE
+    solution e^{-2 pi^2 t} sin(pi x) sin(pi y)); second order as stated in Sec. 2.1."""
+    def err(n):
+        h = 1.0 / (n + 1)
+        dt = h
+        T = 0.05
+        steps = int(round(T / dt))
+        dt = T / steps
+        A, B = fd.cn_matrices(np.ones((n + 1, n + 1)), dt)
+        u0 = gen.sine_mode(n, 2)
+        ud = _direct(A, B, u0, dt, steps, (0, 0, 0))
+        exact = np.exp(-2 * np.pi ** 2 * T) * u0.ravel()
+        return np.abs(ud - exact).max()
+    e1, e2 = err(15), err(31)
+    assert 3.0 < e1 / e2 < 5.0

@@ -1,0 +1,173 @@
+"""Pins of the oracle's PHIF (Sec. 2.2) and ID (eq2_5).
+
+The block oracle is checked against (a) the dense-literal transcription of the paper's N x N
+factor matrices, (b) the exact inverse when eps = 0 (the method then degenerates to a nested
+dissection block Cholesky and F = A), (c) the structural identities the paper states after each
+step, (d) symmetry and positive definiteness of F^-1, and (e) geometric counts of active DOFs.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import cn, fd, geometry, interp, phif, phif_dense
+from workloads import gen
+
+
+def _problem(n, dim, seed=7, dt=0.05):
+    a = gen.iid_loguniform_cells(n, dim, seed)
+    A, B = fd.cn_matrices(a, dt)
+    return A, B
+
+
+CASES = [(15, 2, 4), (7, 3, 4), (8, 3, 4)]
+
+
+@pytest.mark.parametrize("n,dim,m", CASES)
+@pytest.mark.parametrize("eps", [0.0, 1e-6, 1e-3])
+def test_block_oracle_equals_dense_literal(n, dim, m, eps):
+    A, _ = _problem(n, dim)
+    F = phif.phif_build(A, n, dim, m, eps)
+    D = phif_dense.phif_dense(A.toarray(), n, dim, m, eps)
+    Fi = phif.phif_dense_inverse(F)
+    assert np.linalg.norm(Fi - D.Finv) <= 1e-12 * np.linalg.norm(D.Finv)
+    # same skeleton sizes on every edge
+    ranks_block = [sorted(len(s.skel) for s in lv.skels) for lv in F.levels]
+    ranks_dense = [sorted(k for _, k in r) for r in D.ranks]
+    assert ranks_block == ranks_dense
+
+
+@pytest.mark.parametrize("n,dim,m", [(15, 2, 4), (32, 2, 8), (8, 3, 4)])
+def test_eps_zero_reproduces_exact_inverse(n, dim, m):
+    A, _ = _problem(n, dim, seed=3)
+    Ad = A.toarray()
+    F = phif.phif_build(A, n, dim, m, 0.0)
+    Fi = phif.phif_dense_inverse(F)
+    assert np.linalg.norm(Fi - np.linalg.inv(Ad)) <= 1e-11 * np.linalg.norm(np.linalg.inv(Ad))
+    D = phif_dense.phif_dense(Ad, n, dim, m, 0.0)
+    assert np.linalg.norm(D.F - Ad) <= 1e-11 * np.linalg.norm(Ad)   # eqA with nothing dropped
+
+
+def test_structural_identities_after_each_step():
+    n, dim, m, eps = 15, 2, 4, 1e-4
+    A, _ = _problem(n, dim, seed=9)
+    D = phif_dense.phif_dense(A.toarray(), n, dim, m, eps)
+    N = n * n
+    for lev, step, Amat, info in D.snapshots:
+        scale = np.abs(Amat).max()
+        if step == 1:
+            # eq2_3: interiors become identity blocks decoupled from everything else
+            for I in info["cells"]:
+                rest = np.setdiff1d(np.arange(N), I)
+                assert np.allclose(Amat[np.ix_(I, I)], np.eye(len(I)), atol=1e-12)
+                assert np.abs(Amat[np.ix_(I, rest)]).max() <= 1e-12 * scale
+        if step == 2:
+            # jacobi-precond / eq3_2: every edge and corner diagonal block is the identity
+            for g in info["groups"]:
+                assert np.allclose(Amat[np.ix_(g, g)], np.eye(len(g)), atol=1e-12)
+        if step == 3:
+            # eq2_9: redundant DOFs end up as identity rows decoupled from the rest
+            for (g, skel, red, T) in info["edges"]:
+                rest = np.setdiff1d(np.arange(N), red)
+                assert np.allclose(Amat[np.ix_(red, red)], np.eye(len(red)), atol=1e-12)
+                if len(red):
+                    assert np.abs(Amat[np.ix_(red, rest)]).max() <= 1e-12 * scale
+                # X = I - T (I + T^T T)^-1 T^T on the skeleton block
+                X = np.eye(len(skel)) - T @ np.linalg.solve(np.eye(len(red)) + T.T @ T, T.T)
+                assert np.allclose(Amat[np.ix_(skel, skel)], X, atol=1e-12)
+    # eq3_4: A_L is the identity outside the root block
+    out = np.setdiff1d(np.arange(N), D.root_idx)
+    assert np.allclose(D.AL[np.ix_(out, out)], np.eye(len(out)), atol=1e-12)
+
+
+def test_id_residual_bound_eq2_5():
+    """||A_{R,I~} - A_{R,I^} T|| <= 10 eps ||A_{R,I}|| for every edge (the dropped block)."""
+    n, dim, m = 15, 2, 4
+    A, _ = _problem(n, dim, seed=13)
+    for eps in [1e-2, 1e-4, 1e-6]:
+        D = phif_dense.phif_dense(A.toarray(), n, dim, m, eps)
+        for lev, step, Amat, info in D.snapshots:
+            if step != 3:
+                continue
+        # recompute from the step-2 snapshot of each level
+        snaps = {(l, s): (Am, inf) for l, s, Am, inf in D.snapshots}
+        for lev in range(len(D.Rs)):
+            A2, _ = snaps[(lev, 2)]
+            _, inf3 = snaps[(lev, 3)]
+            for (g, skel, red, T) in inf3["edges"]:
+                rest = np.setdiff1d(np.arange(A2.shape[0]), g)
+                active_rows = rest[np.abs(A2[np.ix_(rest, g)]).sum(axis=1) > 0]
+                Mblk = A2[np.ix_(active_rows, g)]
+                if len(red) == 0:
+                    continue
+                res = A2[np.ix_(active_rows, red)] - A2[np.ix_(active_rows, skel)] @ T
+                assert np.linalg.norm(res, 2) <= 10 * eps * np.linalg.norm(Mblk, 2)
+
+
+def test_id_on_exactly_low_rank_matrix():
+    rng = np.random.default_rng(1)
+    U = rng.normal(size=(40, 3))
+    V = rng.normal(size=(3, 9))
+    Mlow = U @ V
+    sk, rd, T = interp.interp_decomp(Mlow, 1e-10)
+    assert len(sk) == 3 and len(rd) == 6
+    assert np.allclose(Mlow[:, rd], Mlow[:, sk] @ T, atol=1e-10)
+    sk0, rd0, T0 = interp.interp_decomp(np.zeros((5, 4)), 1e-6)
+    assert len(sk0) == 0 and len(rd0) == 4
+    skf, rdf, _ = interp.interp_decomp(rng.normal(size=(20, 5)), 0.0)
+    assert len(skf) == 5 and len(rdf) == 0
+
+
+@pytest.mark.parametrize("n,dim,m,eps", [(15, 2, 4, 1e-3), (32, 2, 8, 1e-6), (8, 3, 4, 1e-3)])
+def test_inverse_symmetric_positive_definite(n, dim, m, eps):
+    A, _ = _problem(n, dim, seed=21)
+    F = phif.phif_build(A, n, dim, m, eps)
+    Fi = phif.phif_dense_inverse(F)
+    assert np.linalg.norm(Fi - Fi.T) <= 1e-13 * np.linalg.norm(Fi)
+    sla.cholesky(0.5 * (Fi + Fi.T), lower=True)   # raises if not SPD
+
+
+def test_inverse_error_decreases_with_eps():
+    n, dim, m = 31, 2, 4
+    A, _ = _problem(n, dim, seed=2, dt=0.1)
+    Ad = A.toarray()
+    errs = []
+    for eps in [1e-2, 1e-4, 1e-6, 0.0]:
+        F = phif.phif_build(A, n, dim, m, eps)
+        E = np.eye(A.shape[0]) - Ad @ phif.phif_dense_inverse(F)
+        errs.append(np.linalg.norm(E, 2))
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < 1e-10 and errs[2] < 1e-3
+
+
+@pytest.mark.parametrize("n,dim,m", [(32, 2, 8), (31, 2, 4), (16, 3, 4)])
+def test_active_counts_match_geometry_at_eps_zero(n, dim, m):
+    """With no compression, level l eliminates exactly the DOFs with no coordinate in S_l that
+    survived level l-1 (those with a coordinate in S_{l-1}); brute-force count over the grid."""
+    A, _ = _problem(n, dim, seed=5)
+    F = phif.phif_build(A, n, dim, m, 0.0)
+    L = geometry.num_levels(n, m)
+    pts = np.array(np.meshgrid(*([np.arange(1, n + 1)] * dim), indexing="ij")).reshape(dim, -1).T
+    alive = np.ones(len(pts), bool)
+    for lev in range(L):
+        S = set(geometry.separators(n, m, lev).tolist())
+        on = np.array([any(int(c) in S for c in p) for p in pts])
+        before = alive.sum()
+        alive = alive & on
+        assert F.active_counts[lev] == (before, alive.sum(), alive.sum())
+    assert len(F.root_idx) == alive.sum()
+    if (n, dim, m) == (32, 2, 8):
+        assert F.active_counts[0][0] - F.active_counts[0][1] == 841   # 29^2 interiors
+
+
+def test_iterations_do_not_grow_with_n():
+    """Sec. 3: PHIF-PCG iteration counts are essentially independent of N."""
+    its = []
+    for n in [31, 63, 127]:
+        a = gen.grf_coefficient(n, 2, 0.1, 17)
+        A, B = fd.cn_matrices(a, 1.0 / (n + 1))
+        F = phif.phif_build(A, n, 2, 8, 1e-3)
+        u0 = gen.bumps(n, 2, 3, 18)
+        _, it, _ = cn.cn_solve(A, B, u0, 1.0 / (n + 1), 2, lambda r: phif.phif_apply(F, r), 1e-12)
+        its.append(np.mean(it))
+    assert max(its) - min(its) <= 1.5
+    assert max(its) <= 8

@@ -1,0 +1,168 @@
+"""Seeded generators for the synthetic parabolic workloads.
+
+Grid convention (shared by every consumer as plain data):
+  * ``n`` interior nodes per dimension, spacing h = 1/(n+1), node j (1-based) at x = j*h;
+    zero Dirichlet values on the boundary nodes j = 0 and j = n+1.
+  * Node arrays have shape (n,)*d in C order with the x index fastest (last axis = x).
+  * Coefficient arrays live on the (n+1)^d cells between nodes; cell c (0-based) spans
+    [c*h, (c+1)*h] per axis and is sampled at its centre (c+1/2)*h.
+
+All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def node_coords(n: int, dim: int) -> list[np.ndarray]:
+    """Coordinates of interior nodes, as an ``np.meshgrid`` list ordered (x, y[, z])."""
+    h = 1.0 / (n + 1)
+    x = h * np.arange(1, n + 1)
+    # C order with x fastest: axes are (z, y, x) in 3D and (y, x) in 2D.
+    grids = np.meshgrid(*([x] * dim), indexing="ij")
+    return grids[::-1]  # -> [x, y(, z)] each of shape (n,)*dim
+
+
+def cell_centres(n: int, dim: int) -> list[np.ndarray]:
+    """Centres of the (n+1)^dim cells, same ordering convention as ``node_coords``."""
+    h = 1.0 / (n + 1)
+    c = h * (np.arange(n + 1) + 0.5)
+    grids = np.meshgrid(*([c] * dim), indexing="ij")
+    return grids[::-1]
+
+
+def grf_coefficient(n: int, dim: int, length: float, seed: int, lo: float = 0.1,
+                    hi: float = 10.0, features: int = 1024) -> np.ndarray:
+    """Lognormal-type smooth field a = exp(g) on the cells, mapped to [lo, hi].
+
+    g is a random-Fourier-feature draw of a Gaussian field with squared-exponential covariance
+    of length ``length``: g(x) = sqrt(2/K) sum_k cos(w_k . x + b_k), w_k ~ N(0, length^-2 I),
+    b_k ~ U(0, 2 pi).  g is min-max normalised and mapped so that log a spans
+    [log lo, log hi] exactly (contrast hi/lo).
+    """
+    rng = _rng(seed)
+    w = rng.normal(0.0, 1.0 / length, size=(features, dim))
+    b = rng.uniform(0.0, 2.0 * np.pi, size=features)
+    pts = np.stack([c.ravel() for c in cell_centres(n, dim)], axis=1)  # (P, dim) as (x, y, z)
+    g = np.zeros(pts.shape[0])
+    chunk = 1 << 15
+    for s in range(0, pts.shape[0], chunk):
+        g[s:s + chunk] = np.cos(pts[s:s + chunk] @ w.T + b).sum(axis=1)
+    g *= np.sqrt(2.0 / features)
+    t = (g - g.min()) / (g.max() - g.min())
+    a = np.exp(np.log(lo) + (np.log(hi) - np.log(lo)) * t)
+    return a.reshape((n + 1,) * dim)
+
+
+def iid_loguniform_cells(n: int, dim: int, seed: int, lo_exp: float = -2.0,
+                         hi_exp: float = 2.0) -> np.ndarray:
+    """Per-cell iid 10^U(lo_exp, hi_exp) on the (n+1)^dim cells."""
+    rng = _rng(seed)
+    return 10.0 ** rng.uniform(lo_exp, hi_exp, size=(n + 1,) * dim)
+
+
+def iid_uniform_nodes(n: int, dim: int, seed: int) -> np.ndarray:
+    rng = _rng(seed)
+    return rng.uniform(0.0, 1.0, size=(n,) * dim)
+
+
+def sine_mode(n: int, dim: int, p: int = 1) -> np.ndarray:
+    """prod_d sin(p pi x_d) at the interior nodes."""
+    u = np.ones((n,) * dim)
+    for c in node_coords(n, dim):
+        u = u * np.sin(p * np.pi * c)
+    return u
+
+
+def bumps(n: int, dim: int, count: int, seed: int, width2: float = 0.005) -> np.ndarray:
+    """clip(sum_i exp(-|x - c_i|^2 / width2), 0, 1), c_i ~ U(0.1, 0.9)^dim."""
+    rng = _rng(seed)
+    centres = rng.uniform(0.1, 0.9, size=(count, dim))
+    xs = node_coords(n, dim)
+    u = np.zeros((n,) * dim)
+    for c in centres:
+        r2 = np.zeros((n,) * dim)
+        for d in range(dim):
+            r2 = r2 + (xs[d] - c[d]) ** 2
+        u += np.exp(-r2 / width2)
+    return np.clip(u, 0.0, 1.0)
+
+
+@dataclass
+class Workload:
+    """One synthetic parabolic solve: grid, coefficient, initial state and solver settings."""
+
+    name: str
+    dim: int
+    n: int
+    a_cells: np.ndarray
+    u0: np.ndarray
+    dt: float
+    steps: int
+    eps: float
+    rtol: float
+    reaction: tuple = (0, 0.0, 0.0)  # (kind, k1, k2): 0 none, 1 k1*u*(1-u/k2)
+    leaf: int = 8
+    store: str = "f32"
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.dim
+
+
+def _heat_small() -> Workload:
+    n = 32
+    return Workload("heat2d-32", 2, n, np.ones((n + 1, n + 1)), sine_mode(n, 2), 1e-2, 10,
+                    1e-6, 1e-10, store="f64")
+
+
+def _fisher_256() -> Workload:
+    n = 256
+    return Workload("fisher2d-256", 2, n, grf_coefficient(n, 2, 0.1, 2001),
+                    bumps(n, 2, 10, 2002), 1e-3, 100, 1e-4, 1e-8, reaction=(1, 1.0, 1.0))
+
+
+def _heat_1024(eps: float = 1e-3) -> Workload:
+    n = 1024
+    return Workload("heat2d-1024", 2, n, iid_loguniform_cells(n, 2, 3001),
+                    iid_uniform_nodes(n, 2, 3002), 1e-1, 20, eps, 1e-8)
+
+
+def _heat3d_64() -> Workload:
+    n = 64
+    rng = _rng(4002)
+    u0 = sine_mode(n, 3) + 0.1 * rng.normal(size=(n,) * 3)
+    return Workload("heat3d-64", 3, n, grf_coefficient(n, 3, 0.15, 4001), u0, 1e-2, 20,
+                    1e-4, 1e-8)
+
+
+def serving_requests(count: int = 256, seed_base: int = 5000) -> list[Workload]:
+    """Independent 2D Fisher-KPP solves of mixed size for the serving workload."""
+    out = []
+    for i in range(count):
+        rng = _rng(seed_base + 10 * i)
+        n = int(rng.choice([64, 128, 256, 512]))
+        dt = float(rng.choice([1e-3, 1e-2, 1e-1]))
+        a = grf_coefficient(n, 2, 0.1, seed_base + 10 * i + 1)
+        u0 = bumps(n, 2, 10, seed_base + 10 * i + 2)
+        out.append(Workload(f"req{i}", 2, n, a, u0, dt, 50, 1e-4, 1e-8, reaction=(1, 1.0, 1.0)))
+    return out
+
+
+WORKLOADS = {
+    "heat2d-32": _heat_small,
+    "fisher2d-256": _fisher_256,
+    "heat2d-1024": _heat_1024,
+    "heat3d-64": _heat3d_64,
+}
+
+
+def workload(name: str, **kw) -> Workload:
+    return WORKLOADS[name](**kw)
