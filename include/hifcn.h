@@ -1,0 +1,136 @@
+/* hifcn.h -- HIF-preconditioned Crank-Nicolson solves on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Feliu-Faba & Ying, "Hierarchical Interpolative Factorization Preconditioner for
+ * Parabolic Equations".  The equation u_t = div(a grad u) + r(u) (Sec. 1, eq1) on the unit
+ * square/cube with zero Dirichlet data is discretised by the five/seven-point stencil (Sec. 2)
+ * and stepped by Crank-Nicolson with explicit reaction (Sec. 2.1, eq_CN):
+ *     (I - dt/2 M) u^{k+1} = (I + dt/2 M) u^k + dt r(u^k).
+ * Each step is solved by CG preconditioned with the inverse of the recursively preconditioned
+ * hierarchical interpolative factorization F of A = I - dt/2 M (Sec. 2.2, eqAinv; Algorithm 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Grids: n interior nodes per axis (equal on every axis), h = 1/(n+1); node arrays are
+ *     FP64, C-contiguous, shape n^dim with the x index fastest.  The coefficient a lives on the
+ *     (n+1)^dim cells between nodes (same ordering); a link's coefficient is the mean of the
+ *     cells sharing it.
+ *   - Pointers named *_dev are DEVICE pointers owned by the caller; the library never frees
+ *     them.  Host pointers are named explicitly.  A handle owns all device memory it allocates.
+ *   - Every call is ordered on the HIP stream passed as `hip_stream` (a hipStream_t; NULL =
+ *     the null stream) and may return before the GPU work ends, except where stated.
+ *   - Errors are reported only through the status code; no exception crosses this boundary.
+ *     hif_last_error() returns a thread-local message for the last non-OK status.  On error
+ *     an output handle is set to NULL and caller buffers are untouched, except as stated for
+ *     HIF_ERR_NO_CONV.
+ *   - One handle may be used by one host thread / stream at a time.
+ */
+#ifndef HIFCN_H
+#define HIFCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t dim;    /* 2 or 3 */
+  int32_t n[3];   /* interior nodes per axis; n[0] == n[1] (== n[2] in 3D) is required */
+  int32_t leaf;   /* leaf cell size m: L = max{l : m 2^l <= n+1} levels, separators at k m 2^l */
+} hif_grid_t;
+
+/* Storage precision of the factor blocks used by hif_apply (the build is always FP64;
+ * FP32/BF16 forms accumulate in FP32, the FP64 form in FP64). */
+typedef enum { HIF_STORE_F64 = 0, HIF_STORE_F32 = 1, HIF_STORE_BF16 = 2 } hif_store_t;
+
+typedef enum {
+  HIF_OK = 0,
+  HIF_ERR_ARG = 1,      /* invalid argument (grid, sizes, NULL pointer, bad blob) */
+  HIF_ERR_OOM = 2,      /* device allocation failed */
+  HIF_ERR_NOT_SPD = 3,  /* a Cholesky pivot was not positive (A not SPD, e.g. a <= 0) */
+  HIF_ERR_NO_CONV = 4,  /* PCG hit maxit or produced a non-finite residual */
+  HIF_ERR_HIP = 5       /* a HIP runtime call failed */
+} hif_status_t;
+
+typedef struct hif_handle_s* hif_handle_t;
+
+/* Reaction term r(u) (eq1, eq_nr): kind 0 -> none; kind 1 -> k1 u (1 - u/k2). */
+typedef struct { int32_t kind; double k1; double k2; } hif_reaction_t;
+
+/* PCG options (Algorithm 1): stop when ||r_i||_2 <= rtol ||g||_2 (recurrence residual),
+ * x0 = 0, at most maxit iterations.  warm_start must be 0 (reserved). */
+typedef struct { double rtol; int32_t maxit; int32_t warm_start; } hif_cg_opts_t;
+
+/* Build the PHIF factor of A = I - dt/2 M (Sec. 2.2: per level cell elimination, block Jacobi,
+ * edge/face skeletonization by ID at relative precision eps; root Cholesky) on the GPU in FP64
+ * and store its blocks in `store` precision.  a_cells_dev: (n+1)^dim FP64 values > 0.
+ * Synchronises `hip_stream` (the level structure depends on the ranks found).
+ * Errors: HIF_ERR_ARG (grid, dt <= 0, eps < 0), HIF_ERR_NOT_SPD, HIF_ERR_OOM, HIF_ERR_HIP. */
+hif_status_t hif_factor(const double* a_cells_dev, double dt, const hif_grid_t* grid,
+                        double eps, hif_store_t store, void* hip_stream, hif_handle_t* out);
+
+/* Test fixture: like hif_factor, but the factor blocks are read from `blob_host` (nbytes, host
+ * memory) written in the HIFB format below instead of being built, so that hif_apply can be
+ * checked independently of the build.  Synchronises `hip_stream`.
+ *
+ * HIFB format (little endian; i32 = int32, f64 = IEEE double; matrices row-major, full):
+ *   i32 magic 0x42464948 ("HIFB"), i32 version 1, i32 dim, i32 n, i32 leaf, i32 nlevels
+ *   per level: i32 ncell,  per cell : i32 nI, i32 nB, i32 I[nI], i32 B[nB],
+ *                                     f64 L[nI*nI] (chol(A_II), lower), f64 G[nI*nB] (L^-1 A_IB)
+ *              i32 ngroup, per group: i32 n, i32 idx[n], f64 Lg[n*n] (chol(A_gg), lower)
+ *              i32 nskel,  per edge : i32 nr, i32 k, i32 red[nr], i32 skel[k],
+ *                                     f64 T[k*nr], f64 Ls[nr*nr] (chol(I + T^T T), lower)
+ *   i32 nroot, i32 root[nroot], f64 Lr[nroot*nroot]
+ * DOF ids are global node indices (C order, x fastest).  Every skeletonized edge must also
+ * appear, with the same DOF set, among the groups of its level. */
+hif_status_t hif_import(const double* a_cells_dev, double dt, const hif_grid_t* grid,
+                        const void* blob_host, size_t nbytes, hif_store_t store,
+                        void* hip_stream, hif_handle_t* out);
+
+/* y = F^-1 x (eqAinv: forward sweep E^T C^T K^T over levels 0..L-1, root solve, backward sweep
+ * K C E over levels L-1..0).  x_dev, y_dev: N FP64 values; may alias. */
+hif_status_t hif_apply(hif_handle_t h, const double* x_dev, double* y_dev, void* hip_stream);
+
+/* y = A x with A = I - dt/2 M (five/seven-point stencil, Sec. 2).  x_dev, y_dev must not alias. */
+hif_status_t hif_spmv(hif_handle_t h, const double* x_dev, double* y_dev, void* hip_stream);
+
+/* One Crank-Nicolson step (eq_CN, Algorithm 1): g = (I + dt/2 M)u + dt r(u), then PCG with
+ * preconditioner F^-1 from x0 = 0; u_dev (N FP64) is replaced by u^{k+1}.  *iters_host and
+ * *relres_host (may be NULL) receive the iteration count and ||r||/||g||.  Synchronises the
+ * stream.  HIF_ERR_NO_CONV: u_dev holds the last iterate and *iters_host = maxit. */
+hif_status_t cn_step(hif_handle_t h, const hif_reaction_t* r, const hif_cg_opts_t* opts,
+                     double* u_dev, int32_t* iters_host, double* relres_host, void* hip_stream);
+
+/* nsteps Crank-Nicolson steps; iters_host[nsteps], relres_host[nsteps] (host arrays, may be
+ * NULL) receive per-step statistics, copied once at the end.  Synchronises the stream at
+ * most a few times per step (PCG convergence checks) and at the end. */
+hif_status_t cn_solve(hif_handle_t h, const hif_reaction_t* r, const hif_cg_opts_t* opts,
+                      double* u_dev, int32_t nsteps, int32_t* iters_host, double* relres_host,
+                      void* hip_stream);
+
+/* Stored factor bytes (unpadded, in the storage precision): the algorithmic bytes one sweep of
+ * hif_apply reads; one apply reads them twice. */
+size_t hif_factor_bytes(hif_handle_t h);
+
+/* Structure summary: number of levels, root size and stored factor entries. */
+typedef struct {
+  int32_t levels;
+  int32_t root;
+  int64_t entries;
+  int64_t N;
+  int32_t store;
+  int32_t dim;
+} hif_info_t;
+hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
+
+/* Releases every device allocation of the handle (synchronises the device first). */
+void hif_destroy(hif_handle_t h);
+
+/* Thread-local message describing the last non-OK status returned on this thread. */
+const char* hif_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIFCN_H */

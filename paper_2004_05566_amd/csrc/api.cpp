@@ -1,0 +1,260 @@
+// C-ABI entry points of libhifcn (declared in include/hifcn.h).
+#include <cmath>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace hifcn {
+
+void gpu_build(Handle& h, const double* a_cells, hif_store_t store, hipStream_t s);
+void launch_cg_copy_rz(Handle& h, hipStream_t s);
+int vec_blocks(int64_t N);
+
+Handle::~Handle() {
+  if (host_flag) (void)hipHostFree(host_flag);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hif_status_t fail(hif_status_t s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+template <typename F>
+hif_status_t guarded(F&& f) {
+  try {
+    f();
+    return HIF_OK;
+  } catch (const HifError& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HIF_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HIF_ERR_HIP, e.what());
+  }
+}
+
+int levels_for(int n, int m) {
+  int L = 0;
+  while ((int64_t)m * (2LL << L) <= n + 1) ++L;
+  return L;
+}
+
+std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_grid_t* grid,
+                                    double eps, hipStream_t s) {
+  HIF_REQUIRE(grid != nullptr && a_cells != nullptr, HIF_ERR_ARG, "NULL argument");
+  HIF_REQUIRE(grid->dim == 2 || grid->dim == 3, HIF_ERR_ARG, "dim must be 2 or 3");
+  const int n = grid->n[0];
+  HIF_REQUIRE(n >= 1 && grid->n[1] == n && (grid->dim == 2 || grid->n[2] == n), HIF_ERR_ARG,
+              "the grid must have the same number of interior nodes on every axis");
+  HIF_REQUIRE(grid->leaf >= 2, HIF_ERR_ARG, "leaf size must be at least 2");
+  HIF_REQUIRE(dt > 0 && std::isfinite(dt), HIF_ERR_ARG, "dt must be positive");
+  HIF_REQUIRE(eps >= 0 && std::isfinite(eps), HIF_ERR_ARG, "eps must be >= 0");
+  auto h = std::make_unique<Handle>();
+  h->dim = grid->dim;
+  h->n = n;
+  h->leaf = grid->leaf;
+  h->L = levels_for(n, grid->leaf);
+  h->N = 1;
+  for (int d = 0; d < h->dim; ++d) h->N *= n;
+  HIF_REQUIRE(h->N < (int64_t)INT32_MAX, HIF_ERR_ARG, "grid too large");
+  h->dt = dt;
+  h->h = 1.0 / (n + 1);
+  h->eps = eps;
+  const int64_t per = h->N / n * (n + 1);
+  h->links.alloc(per * h->dim);
+  launch_links(a_cells, h->dim, n, dt / (2.0 * h->h * h->h), h->links.p, s);
+  h->nblk = vec_blocks(h->N);
+  h->x.alloc(h->N);
+  h->r.alloc(h->N);
+  h->z.alloc(h->N);
+  h->p0.alloc(h->N);
+  h->p1.alloc(h->N);
+  h->q.alloc(h->N);
+  h->partials.alloc(h->nblk);
+  h->st.alloc(1);
+  h->counter.alloc(1);
+  HIF_CHECK(hipMemsetAsync(h->counter.p, 0, sizeof(uint32_t), s));
+  HIF_CHECK(hipMemsetAsync(h->st.p, 0, sizeof(CgState), s));
+  h->step_iters.alloc(1);
+  h->step_relres.alloc(1);
+  HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 4 * sizeof(int32_t),
+                          hipHostMallocDefault));
+  return h;
+}
+
+// One Crank-Nicolson step on the device; the host waits only to test convergence.
+void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u, int step,
+                 hipStream_t s) {
+  const int kind = r ? r->kind : 0;
+  const double k1 = r ? r->k1 : 0, k2 = r ? r->k2 : 1;
+  launch_cg_rhs(h, u, kind, k1, k2, o->rtol, o->maxit, s);
+  const int* done = &h.st.p->done;
+  launch_cg_copy_rz(h, s);
+  hif_apply_inplace(h.f, h.z.p, done, s);
+  launch_cg_dot_rz(h, s);
+  int launched = 0;
+  int chunk = std::max(1, h.last_iters);
+  while (true) {
+    for (int c = 0; c < chunk && launched < o->maxit; ++c, ++launched) {
+      double* pin = (launched & 1) ? h.p1.p : h.p0.p;
+      double* pout = (launched & 1) ? h.p0.p : h.p1.p;
+      launch_cg_dir_spmv(h, pin, pout, s);
+      launch_cg_update(h, pout, s);
+      launch_cg_copy_rz(h, s);
+      hif_apply_inplace(h.f, h.z.p, done, s);
+      launch_cg_dot_rz(h, s);
+    }
+    HIF_CHECK(hipGetLastError());
+    // [iters, done, status] are adjacent in CgState
+    HIF_CHECK(hipMemcpyAsync(h.host_flag, &h.st.p->iters, 3 * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+    HIF_CHECK(hipStreamSynchronize(s));
+    if (h.host_flag[1] || launched >= o->maxit) break;
+    chunk = 1;
+  }
+  h.last_iters = h.host_flag[0];
+  launch_cg_finish(h, u, step, s);
+}
+
+void check_opts(const hif_cg_opts_t* o) {
+  HIF_REQUIRE(o != nullptr, HIF_ERR_ARG, "NULL cg options");
+  HIF_REQUIRE(o->rtol > 0 && o->maxit > 0, HIF_ERR_ARG, "rtol and maxit must be positive");
+  HIF_REQUIRE(o->warm_start == 0, HIF_ERR_ARG, "warm_start is reserved and must be 0");
+}
+
+void check_reaction(const hif_reaction_t* r) {
+  if (!r) return;
+  HIF_REQUIRE(r->kind == 0 || r->kind == 1, HIF_ERR_ARG, "unknown reaction kind");
+  HIF_REQUIRE(r->kind == 0 || r->k2 != 0.0, HIF_ERR_ARG, "k2 must be non-zero");
+}
+
+}  // namespace
+}  // namespace hifcn
+
+using namespace hifcn;
+
+extern "C" {
+
+hif_status_t hif_factor(const double* a_cells_dev, double dt, const hif_grid_t* grid, double eps,
+                        hif_store_t store, void* hip_stream, hif_handle_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    HIF_REQUIRE(out != nullptr, HIF_ERR_ARG, "NULL output handle");
+    HIF_REQUIRE(store >= HIF_STORE_F64 && store <= HIF_STORE_BF16, HIF_ERR_ARG, "bad store");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    auto h = make_handle(a_cells_dev, dt, grid, eps, s);
+    gpu_build(*h, a_cells_dev, store, s);
+    *out = reinterpret_cast<hif_handle_t>(h.release());
+  });
+}
+
+hif_status_t hif_import(const double* a_cells_dev, double dt, const hif_grid_t* grid,
+                        const void* blob_host, size_t nbytes, hif_store_t store, void* hip_stream,
+                        hif_handle_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    HIF_REQUIRE(out != nullptr, HIF_ERR_ARG, "NULL output handle");
+    HIF_REQUIRE(store >= HIF_STORE_F64 && store <= HIF_STORE_BF16, HIF_ERR_ARG, "bad store");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    auto h = make_handle(a_cells_dev, dt, grid, 0.0, s);
+    FactorHost fh = import_blob(blob_host, nbytes, h->dim, h->n, h->leaf);
+    HIF_REQUIRE((int)fh.lv.size() == h->L, HIF_ERR_ARG, "HIFB level count does not match grid");
+    upload_factor(fh, store, h->f, s);
+    *out = reinterpret_cast<hif_handle_t>(h.release());
+  });
+}
+
+hif_status_t hif_apply(hif_handle_t hh, const double* x, double* y, void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && x && y, HIF_ERR_ARG, "NULL argument");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (x != y)
+      HIF_CHECK(hipMemcpyAsync(y, x, h.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hif_apply_inplace(h.f, y, nullptr, s);
+  });
+}
+
+hif_status_t hif_spmv(hif_handle_t hh, const double* x, double* y, void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && x && y, HIF_ERR_ARG, "NULL argument");
+    HIF_REQUIRE(x != y, HIF_ERR_ARG, "hif_spmv: x and y must not alias");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    launch_spmv(h, x, y, static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+hif_status_t cn_solve(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u,
+                      int32_t nsteps, int32_t* iters, double* relres, void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && u, HIF_ERR_ARG, "NULL argument");
+    HIF_REQUIRE(nsteps >= 0, HIF_ERR_ARG, "nsteps must be >= 0");
+    check_opts(o);
+    check_reaction(r);
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if ((int64_t)h.step_iters.n < nsteps) {
+      h.step_iters.alloc(std::max(1, nsteps));
+      h.step_relres.alloc(std::max(1, nsteps));
+    }
+    int failed_step = -1;
+    for (int k = 0; k < nsteps; ++k) {
+      cn_step_dev(h, r, o, u, k, s);
+      if (h.host_flag[2] != 0) { failed_step = k; break; }
+    }
+    const int done_steps = failed_step >= 0 ? failed_step + 1 : nsteps;
+    std::vector<int32_t> it(std::max(1, done_steps));
+    std::vector<double> rr(std::max(1, done_steps));
+    if (done_steps) {
+      HIF_CHECK(hipMemcpyAsync(it.data(), h.step_iters.p, done_steps * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+      HIF_CHECK(hipMemcpyAsync(rr.data(), h.step_relres.p, done_steps * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIF_CHECK(hipStreamSynchronize(s));
+    for (int k = 0; k < done_steps; ++k) {
+      if (iters) iters[k] = it[k];
+      if (relres) relres[k] = rr[k];
+    }
+    HIF_REQUIRE(failed_step < 0, HIF_ERR_NO_CONV,
+                "PCG did not converge at step " + std::to_string(failed_step));
+  });
+}
+
+hif_status_t cn_step(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u,
+                     int32_t* iters, double* relres, void* hip_stream) {
+  return cn_solve(hh, r, o, u, 1, iters, relres, hip_stream);
+}
+
+size_t hif_factor_bytes(hif_handle_t hh) {
+  if (!hh) return 0;
+  const Handle& h = *reinterpret_cast<const Handle*>(hh);
+  return (size_t)h.f.nvals * store_elem_bytes(h.f.store);
+}
+
+hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && info, HIF_ERR_ARG, "NULL argument");
+    const Handle& h = *reinterpret_cast<const Handle*>(hh);
+    info->levels = (int32_t)h.f.lv.size();
+    info->root = h.f.nroot;
+    info->entries = h.f.nvals;
+    info->N = h.N;
+    info->store = (int32_t)h.f.store;
+    info->dim = h.dim;
+  });
+}
+
+void hif_destroy(hif_handle_t hh) {
+  if (!hh) return;
+  (void)hipDeviceSynchronize();
+  delete reinterpret_cast<Handle*>(hh);
+}
+
+const char* hif_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Shared host/device helpers of the hifcn library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hifcn.h"
+
+namespace hifcn {
+
+// ---------------------------------------------------------------------------------------------
+// Errors: internal code throws HifError; the C entry points translate it to a status code.
+struct HifError : std::runtime_error {
+  hif_status_t status;
+  HifError(hif_status_t s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define HIF_CHECK(expr)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      throw ::hifcn::HifError(e_ == hipErrorOutOfMemory ? HIF_ERR_OOM : HIF_ERR_HIP,          \
+                              std::string(#expr) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+#define HIF_REQUIRE(cond, status, msg)                                                        \
+  do {                                                                                        \
+    if (!(cond)) throw ::hifcn::HifError((status), (msg));                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Owning device buffer.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) HIF_CHECK(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    if (h.size() != n) alloc(h.size());
+    if (n) HIF_CHECK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Storage element types of the factor blocks.
+struct bf16_t { uint16_t bits; };
+
+template <typename C> __device__ __forceinline__ C load_as(const double* p) { return (C)(*p); }
+template <typename C> __device__ __forceinline__ C load_as(const float* p) { return (C)(*p); }
+template <typename C> __device__ __forceinline__ C load_as(const bf16_t* p) {
+  return (C)__uint_as_float(((uint32_t)p->bits) << 16);
+}
+
+// Round-to-nearest-even FP32 -> BF16 (host and device).
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16 | ((u & 0xffff) ? 0x40 : 0));
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+inline size_t store_elem_bytes(hif_store_t s) {
+  return s == HIF_STORE_F64 ? 8 : (s == HIF_STORE_F32 ? 4 : 2);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Descriptors of one level of the factor, as read by the apply kernels.  Offsets are element
+// offsets into the handle's index array (int32) and value array (storage type).
+struct CellDesc {
+  int32_t nI, nB;      // interior and boundary sizes
+  int32_t offI, offB;  // index lists (global DOF ids)
+  int32_t offV;        // values: packed column-major lower L^-1 (nI(nI+1)/2), then
+                       //         H = A_BI A_II^-1 column-major (nB x nI, H[j*nB + b])
+  int32_t offCB;       // first slot of this cell's boundary contributions
+  int32_t pad0, pad1;
+};
+
+struct GroupDesc {
+  int32_t n, nr;       // group size, number of redundant DOFs (0: not skeletonized)
+  int32_t offIdx;      // DOF ids, group order (the order of L_g)
+  int32_t offPerm;     // positions in group order: redundant first (nr), then skeleton
+  int32_t offV;        // values: packed L_g^-1 (n(n+1)/2), T column-major (k x nr, T[j*k + s]),
+                       //         packed L_s^-1 (nr(nr+1)/2), with k = n - nr
+  int32_t offGP;       // gather map: ptr[n+1] (relative), then slots[] into the contributions
+  int32_t pad0, pad1;
+};
+
+__host__ __device__ inline int64_t tri_count(int64_t n) { return n * (n + 1) / 2; }
+// start of column j of a packed column-major lower triangle of order n
+__host__ __device__ inline int colstart(int j, int n) { return j * n - (j * (j - 1)) / 2; }
+
+}  // namespace hifcn

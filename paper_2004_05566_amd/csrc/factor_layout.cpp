@@ -1,0 +1,286 @@
+// Factor layout on the device: reading the HIFB test blob and uploading a factor.
+//
+// The apply kernels read, per level, one descriptor per cell and per separator group and the
+// blocks of the factors E_l, C_l, K_l (Sec. 2.2) in explicit-inverse form:
+//   cell  : packed L^-1 and H = A_BI A_II^-1 = G^T L^-1  (E_l of eq2_3)
+//   group : packed L_g^-1                                  (C_l of jacobi-precond)
+//   edge  : T and packed L_s^-1, L_s = chol(I + T^T T)     (K_l of eq_T, eq2_9)
+//   root  : packed L_r^-1                                  (A_L of eq3_4)
+// Explicit triangular inverses turn every sweep stage into small matrix-vector products with
+// no serial triangular-solve chain.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <unordered_map>
+
+#include "kernels.hpp"
+
+namespace hifcn {
+
+namespace {
+
+struct Reader {
+  const unsigned char* p;
+  size_t n, pos = 0;
+  int32_t i32() {
+    HIF_REQUIRE(pos + 4 <= n, HIF_ERR_ARG, "HIFB blob truncated");
+    int32_t v;
+    std::memcpy(&v, p + pos, 4);
+    pos += 4;
+    return v;
+  }
+  void i32s(std::vector<int32_t>& v, size_t k) {
+    v.resize(k);
+    HIF_REQUIRE(pos + 4 * k <= n, HIF_ERR_ARG, "HIFB blob truncated");
+    if (k) std::memcpy(v.data(), p + pos, 4 * k);
+    pos += 4 * k;
+  }
+  void f64s(std::vector<double>& v, size_t k) {
+    v.resize(k);
+    HIF_REQUIRE(pos + 8 * k <= n, HIF_ERR_ARG, "HIFB blob truncated");
+    if (k) std::memcpy(v.data(), p + pos, 8 * k);
+    pos += 8 * k;
+  }
+};
+
+// Inverse of a row-major lower-triangular matrix (host, FP64, forward substitution).
+std::vector<double> tri_inverse(const std::vector<double>& L, int n) {
+  std::vector<double> X((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    HIF_REQUIRE(L[(size_t)j * n + j] > 0.0, HIF_ERR_NOT_SPD, "non-positive Cholesky pivot in blob");
+    X[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0;
+      for (int k = j; k < i; ++k) s += L[(size_t)i * n + k] * X[(size_t)k * n + j];
+      X[(size_t)i * n + j] = -s / L[(size_t)i * n + i];
+    }
+  }
+  return X;
+}
+
+void push_packed(std::vector<double>& out, const std::vector<double>& M, int n) {
+  for (int j = 0; j < n; ++j)
+    for (int i = j; i < n; ++i) out.push_back(M[(size_t)i * n + j]);
+}
+
+}  // namespace
+
+FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf) {
+  HIF_REQUIRE(blob != nullptr, HIF_ERR_ARG, "NULL blob");
+  Reader rd{static_cast<const unsigned char*>(blob), nbytes};
+  HIF_REQUIRE(rd.i32() == 0x42464948, HIF_ERR_ARG, "bad HIFB magic");
+  HIF_REQUIRE(rd.i32() == 1, HIF_ERR_ARG, "unsupported HIFB version");
+  HIF_REQUIRE(rd.i32() == dim && rd.i32() == n && rd.i32() == leaf, HIF_ERR_ARG,
+              "HIFB grid does not match the grid argument");
+  const int nlev = rd.i32();
+  HIF_REQUIRE(nlev >= 0 && nlev < 32, HIF_ERR_ARG, "bad level count");
+  const int64_t N = (int64_t)std::pow((double)n, dim);
+  FactorHost fh;
+  auto check_ids = [&](const std::vector<int32_t>& v) {
+    for (int32_t d : v) HIF_REQUIRE(d >= 0 && d < N, HIF_ERR_ARG, "DOF id out of range");
+  };
+  std::vector<int32_t> I, B, ids, red, skel;
+  std::vector<double> Lm, Gm, Tm;
+  for (int l = 0; l < nlev; ++l) {
+    LevelHost lh;
+    // ---- cells
+    const int ncell = rd.i32();
+    HIF_REQUIRE(ncell >= 0, HIF_ERR_ARG, "bad cell count");
+    int64_t cb = 0;
+    struct CellB { std::vector<int32_t> B; int64_t off; };
+    std::vector<CellB> cellB;
+    for (int c = 0; c < ncell; ++c) {
+      const int nI = rd.i32(), nB = rd.i32();
+      HIF_REQUIRE(nI > 0 && nB >= 0, HIF_ERR_ARG, "bad cell sizes");
+      rd.i32s(I, nI);
+      rd.i32s(B, nB);
+      check_ids(I);
+      check_ids(B);
+      rd.f64s(Lm, (size_t)nI * nI);
+      rd.f64s(Gm, (size_t)nI * nB);
+      const std::vector<double> Li = tri_inverse(Lm, nI);
+      std::vector<int> keep;
+      for (int b = 0; b < nB; ++b) {
+        bool nz = false;
+        for (int i = 0; i < nI && !nz; ++i) nz = Gm[(size_t)i * nB + b] != 0.0;
+        if (nz) keep.push_back(b);
+      }
+      CellDesc d{};
+      d.nI = nI;
+      d.nB = (int)keep.size();
+      d.offI = (int32_t)fh.idx.size();
+      fh.idx.insert(fh.idx.end(), I.begin(), I.end());
+      d.offB = (int32_t)fh.idx.size();
+      std::vector<int32_t> Bk;
+      for (int b : keep) Bk.push_back(B[b]);
+      fh.idx.insert(fh.idx.end(), Bk.begin(), Bk.end());
+      d.offV = (int32_t)fh.vals.size();
+      push_packed(fh.vals, Li, nI);
+      for (int j = 0; j < nI; ++j)      // H[b][j] = sum_i G[i][b] Linv[i][j], column-major
+        for (int b : keep) {
+          double s = 0;
+          for (int i = j; i < nI; ++i) s += Gm[(size_t)i * nB + b] * Li[(size_t)i * nI + j];
+          fh.vals.push_back(s);
+        }
+      d.offCB = (int32_t)cb;
+      cellB.push_back({Bk, cb});
+      cb += d.nB;
+      lh.maxI = std::max(lh.maxI, nI);
+      lh.maxB = std::max(lh.maxB, d.nB);
+      lh.cells.push_back(d);
+    }
+    fh.cbmax = std::max(fh.cbmax, cb);
+    // ---- groups
+    const int ngroup = rd.i32();
+    HIF_REQUIRE(ngroup >= 0, HIF_ERR_ARG, "bad group count");
+    struct G { std::vector<int32_t> ids; std::vector<double> Linv; };
+    std::vector<G> groups(ngroup);
+    std::unordered_map<int32_t, std::pair<int, int>> where;  // dof -> (group, position)
+    for (int g = 0; g < ngroup; ++g) {
+      const int gn = rd.i32();
+      HIF_REQUIRE(gn > 0, HIF_ERR_ARG, "bad group size");
+      rd.i32s(groups[g].ids, gn);
+      check_ids(groups[g].ids);
+      rd.f64s(Lm, (size_t)gn * gn);
+      groups[g].Linv = tri_inverse(Lm, gn);
+      for (int i = 0; i < gn; ++i) where[groups[g].ids[i]] = {g, i};
+    }
+    // ---- skeletonized edges
+    const int nskel = rd.i32();
+    struct Sk { int nr = 0, k = 0; std::vector<int32_t> perm; std::vector<double> T, Lsinv; };
+    std::vector<Sk> sk(ngroup);
+    for (int e = 0; e < nskel; ++e) {
+      const int nr = rd.i32(), k = rd.i32();
+      HIF_REQUIRE(nr >= 0 && k >= 0 && nr + k > 0, HIF_ERR_ARG, "bad edge sizes");
+      rd.i32s(red, nr);
+      rd.i32s(skel, k);
+      rd.f64s(Tm, (size_t)k * nr);
+      rd.f64s(Lm, (size_t)nr * nr);
+      const int32_t any = nr ? red[0] : skel[0];
+      auto it = where.find(any);
+      HIF_REQUIRE(it != where.end(), HIF_ERR_ARG, "skeletonized edge is not a group");
+      const int g = it->second.first;
+      HIF_REQUIRE((int)groups[g].ids.size() == nr + k, HIF_ERR_ARG, "edge/group size mismatch");
+      Sk s;
+      s.nr = nr;
+      s.k = k;
+      for (int32_t d : red) {
+        auto w = where.find(d);
+        HIF_REQUIRE(w != where.end() && w->second.first == g, HIF_ERR_ARG, "edge DOF mismatch");
+        s.perm.push_back(w->second.second);
+      }
+      for (int32_t d : skel) {
+        auto w = where.find(d);
+        HIF_REQUIRE(w != where.end() && w->second.first == g, HIF_ERR_ARG, "edge DOF mismatch");
+        s.perm.push_back(w->second.second);
+      }
+      s.T.resize((size_t)k * nr);
+      for (int j = 0; j < nr; ++j)
+        for (int r = 0; r < k; ++r) s.T[(size_t)j * k + r] = Tm[(size_t)r * nr + j];
+      if (nr) s.Lsinv = tri_inverse(Lm, nr);
+      sk[g] = std::move(s);
+    }
+    // gather map: contributions aimed at every group DOF, in cell order
+    std::vector<std::vector<std::vector<int32_t>>> slots(ngroup);
+    for (int g = 0; g < ngroup; ++g) slots[g].resize(groups[g].ids.size());
+    for (const CellB& c : cellB)
+      for (size_t b = 0; b < c.B.size(); ++b) {
+        auto w = where.find(c.B[b]);
+        HIF_REQUIRE(w != where.end(), HIF_ERR_ARG, "cell boundary DOF is not in a group");
+        slots[w->second.first][w->second.second].push_back((int32_t)(c.off + b));
+      }
+    for (int g = 0; g < ngroup; ++g) {
+      const int gn = (int)groups[g].ids.size();
+      GroupDesc d{};
+      d.n = gn;
+      d.nr = sk[g].nr;
+      d.offIdx = (int32_t)fh.idx.size();
+      fh.idx.insert(fh.idx.end(), groups[g].ids.begin(), groups[g].ids.end());
+      d.offPerm = (int32_t)fh.idx.size();
+      if (d.nr) {
+        fh.idx.insert(fh.idx.end(), sk[g].perm.begin(), sk[g].perm.end());
+      }
+      d.offGP = (int32_t)fh.idx.size();
+      int32_t acc = 0;
+      fh.idx.push_back(0);
+      for (int i = 0; i < gn; ++i) {
+        acc += (int32_t)slots[g][i].size();
+        fh.idx.push_back(acc);
+      }
+      for (int i = 0; i < gn; ++i)
+        fh.idx.insert(fh.idx.end(), slots[g][i].begin(), slots[g][i].end());
+      d.offV = (int32_t)fh.vals.size();
+      push_packed(fh.vals, groups[g].Linv, gn);
+      if (d.nr) {
+        fh.vals.insert(fh.vals.end(), sk[g].T.begin(), sk[g].T.end());
+        push_packed(fh.vals, sk[g].Lsinv, d.nr);
+      }
+      lh.maxG = std::max(lh.maxG, gn);
+      lh.maxR = std::max(lh.maxR, d.nr);
+      lh.maxK = std::max(lh.maxK, gn - d.nr);
+      lh.groups.push_back(d);
+    }
+    fh.lv.push_back(std::move(lh));
+  }
+  const int nroot = rd.i32();
+  HIF_REQUIRE(nroot >= 0, HIF_ERR_ARG, "bad root size");
+  rd.i32s(ids, nroot);
+  check_ids(ids);
+  rd.f64s(Lm, (size_t)nroot * nroot);
+  fh.nroot = nroot;
+  fh.offRootIdx = (int32_t)fh.idx.size();
+  fh.idx.insert(fh.idx.end(), ids.begin(), ids.end());
+  fh.offRootV = (int64_t)fh.vals.size();
+  if (nroot) push_packed(fh.vals, tri_inverse(Lm, nroot), nroot);
+  HIF_REQUIRE(rd.pos == rd.n, HIF_ERR_ARG, "trailing bytes in HIFB blob");
+  HIF_REQUIRE(fh.vals.size() < (size_t)INT32_MAX && fh.idx.size() < (size_t)INT32_MAX,
+              HIF_ERR_ARG, "factor too large for 32-bit offsets");
+  return fh;
+}
+
+void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipStream_t s) {
+  fd.store = store;
+  fd.lv.clear();
+  fd.lv.resize(fh.lv.size());
+  for (size_t l = 0; l < fh.lv.size(); ++l) {
+    const LevelHost& lh = fh.lv[l];
+    LevelDev& ld = fd.lv[l];
+    ld.ncell = (int)lh.cells.size();
+    ld.ngroup = (int)lh.groups.size();
+    ld.maxI = lh.maxI;
+    ld.maxB = lh.maxB;
+    ld.maxG = lh.maxG;
+    ld.maxK = lh.maxK;
+    ld.maxR = lh.maxR;
+    ld.cells.upload(lh.cells, s);
+    ld.groups.upload(lh.groups, s);
+  }
+  fd.idx.upload(fh.idx, s);
+  fd.nvals = (int64_t)fh.vals.size();
+  const size_t eb = store_elem_bytes(store);
+  std::vector<unsigned char> raw(fh.vals.size() * eb);
+  for (size_t i = 0; i < fh.vals.size(); ++i) {
+    if (store == HIF_STORE_F64) {
+      std::memcpy(&raw[i * 8], &fh.vals[i], 8);
+    } else if (store == HIF_STORE_F32) {
+      const float f = (float)fh.vals[i];
+      std::memcpy(&raw[i * 4], &f, 4);
+    } else {
+      const uint16_t b = f32_to_bf16_bits((float)fh.vals[i]);
+      std::memcpy(&raw[i * 2], &b, 2);
+    }
+  }
+  fd.vals.upload(raw, s);
+  fd.nroot = fh.nroot;
+  fd.offRootIdx = fh.offRootIdx;
+  fd.offRootV = fh.offRootV;
+  fd.cb.alloc(std::max<int64_t>(1, fh.cbmax));
+  size_t worst = 0;
+  apply_smem_need(fd, &worst);
+  fd.smem_max = worst;
+  HIF_REQUIRE(worst <= 160 * 1024, HIF_ERR_ARG, "factor blocks too large for the LDS-staged apply");
+  if (worst > 64 * 1024) set_apply_smem_limits(worst);
+  HIF_CHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace hifcn

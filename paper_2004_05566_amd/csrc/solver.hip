@@ -1,0 +1,347 @@
+// Stencil operator and preconditioned CG kernels (Sec. 2, Sec. 2.1, Algorithm 1).
+//
+// A = I - dt/2 M with M the five/seven-point variable-coefficient stencil: with link weights
+// w = dt/(2 h^2) a_link, (A p)_j = p_j + sum_links w (p_j - p_nbr) and (I + dt/2 M) u =
+// u - sum_links w (u_j - u_nbr) (Dirichlet: p = 0 beyond the boundary).
+//
+// PCG keeps every scalar on the device (CgState), so a whole iteration is queued without a
+// host round trip: the direction update p = z + beta p is fused into the SpMV (each lane
+// rebuilds the new direction at its stencil points from z and the previous direction, written
+// to a second buffer), p.q, r.z and ||r||^2 are fused reductions with a deterministic two-level
+// sum (per-block partials, last block adds them in a fixed order), and the convergence test
+// ||r|| <= rtol ||g|| sets a device flag that makes every later kernel of the step return.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace hifcn {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Deterministic grid-wide sum.  Returns true in the last block to finish, where *total holds
+// the sum (valid in every thread of that block).
+__device__ bool grid_sum(double v, double* partials, uint32_t* counter, double* total) {
+  __shared__ double red[kThreads / 64];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    partials[blockIdx.x] = s;
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double acc = 0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads)
+    acc += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  acc = wave_sum(acc);
+  __syncthreads();
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    red[0] = s;
+    *counter = 0;
+  }
+  __syncthreads();
+  *total = red[0];
+  return true;
+}
+
+// Sum over links of w (p_j - p_nbr) at node i.  P(k) returns the value at node k.
+template <int DIM, typename P>
+__device__ __forceinline__ double link_sum(int64_t i, int n, const double* __restrict__ w,
+                                           double pi, P pv) {
+  const int64_t n1 = n + 1;
+  const int64_t nn = (int64_t)n * n;
+  int ix = (int)(i % n);
+  int64_t rest = i / n;
+  int iy = (int)(rest % n);
+  int iz = DIM == 3 ? (int)(rest / n) : 0;
+  double acc = 0;
+  // x links: array (.., n+1) with link k between nodes k-1 and k
+  {
+    const int64_t row = DIM == 3 ? ((int64_t)iz * n + iy) : iy;
+    const double* wx = w + row * n1;
+    const double wl = wx[ix], wr = wx[ix + 1];
+    const double pl = ix > 0 ? pv(i - 1) : 0.0;
+    const double pr = ix < n - 1 ? pv(i + 1) : 0.0;
+    acc += wl * (pi - pl) + wr * (pi - pr);
+  }
+  {
+    const int64_t lx = (DIM == 3 ? nn : (int64_t)n) * n1;  // size of the x-link array
+    const double* wy = w + lx;
+    const int64_t b = DIM == 3 ? ((int64_t)iz * n1 + iy) * n + ix : (int64_t)iy * n + ix;
+    const double wl = wy[b], wr = wy[b + n];
+    const double pl = iy > 0 ? pv(i - n) : 0.0;
+    const double pr = iy < n - 1 ? pv(i + n) : 0.0;
+    acc += wl * (pi - pl) + wr * (pi - pr);
+  }
+  if (DIM == 3) {
+    const int64_t lx = nn * n1;
+    const double* wz = w + 2 * lx;
+    const int64_t b = ((int64_t)iz * n + iy) * n + ix;
+    const double wl = wz[b], wr = wz[b + nn];
+    const double pl = iz > 0 ? pv(i - nn) : 0.0;
+    const double pr = iz < n - 1 ? pv(i + nn) : 0.0;
+    acc += wl * (pi - pl) + wr * (pi - pr);
+  }
+  return acc;
+}
+
+// ---- link weights from cell values: mean of the 2 (2D) / 4 (3D) cells sharing the link ------
+__global__ void k_links2d(const double* __restrict__ a, int n, double scale, double* __restrict__ w) {
+  const int64_t n1 = n + 1;
+  const int64_t per = (int64_t)n * n1;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 2 * per;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (t < per) {  // x link k at node row iy: cells (cy in {iy, iy+1}, cx = k)
+      const int64_t iy = t / n1, k = t % n1;
+      w[t] = scale * 0.5 * (a[iy * n1 + k] + a[(iy + 1) * n1 + k]);
+    } else {        // y link k at node column ix: cells (cy = k, cx in {ix, ix+1})
+      const int64_t u = t - per, k = u / n, ix = u % n;
+      w[t] = scale * 0.5 * (a[k * n1 + ix] + a[k * n1 + ix + 1]);
+    }
+  }
+}
+
+__global__ void k_links3d(const double* __restrict__ a, int n, double scale, double* __restrict__ w) {
+  const int64_t n1 = n + 1;
+  const int64_t per = (int64_t)n * n * n1;
+  auto A = [&](int64_t cz, int64_t cy, int64_t cx) { return a[(cz * n1 + cy) * n1 + cx]; };
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * per;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int axis = (int)(t / per);
+    const int64_t u = t - axis * per;
+    double s;
+    if (axis == 0) {         // (iz, iy, k)
+      const int64_t k = u % n1, r = u / n1, iy = r % n, iz = r / n;
+      s = A(iz, iy, k) + A(iz, iy + 1, k) + A(iz + 1, iy, k) + A(iz + 1, iy + 1, k);
+    } else if (axis == 1) {  // (iz, k, ix)
+      const int64_t ix = u % n, r = u / n, k = r % n1, iz = r / n1;
+      s = A(iz, k, ix) + A(iz, k, ix + 1) + A(iz + 1, k, ix) + A(iz + 1, k, ix + 1);
+    } else {                 // (k, iy, ix)
+      const int64_t ix = u % n, r = u / n, iy = r % n, k = r / n;
+      s = A(k, iy, ix) + A(k, iy, ix + 1) + A(k, iy + 1, ix) + A(k, iy + 1, ix + 1);
+    }
+    w[t] = scale * 0.25 * s;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_spmv(int n, int64_t N, const double* __restrict__ w,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double xi = x[i];
+    y[i] = xi + link_sum<DIM>(i, n, w, xi, [&](int64_t k) { return x[k]; });
+  }
+}
+
+__device__ __forceinline__ double react(double u, int kind, double k1, double k2) {
+  return kind == 1 ? k1 * u * (1.0 - u / k2) : 0.0;
+}
+
+// g = (I + dt/2 M) u + dt r(u) -> r; x = 0; ||g||^2 and the PCG scalars are reset.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const double* __restrict__ w,
+                                                     const double* __restrict__ u,
+                                                     double* __restrict__ r, double* __restrict__ x,
+                                                     int kind, double k1, double k2, double dt,
+                                                     double rtol, int maxit, CgState* st,
+                                                     double* partials, uint32_t* counter) {
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double ui = u[i];
+    const double g = ui - link_sum<DIM>(i, n, w, ui, [&](int64_t k) { return u[k]; }) +
+                     dt * react(ui, kind, k1, k2);
+    r[i] = g;
+    x[i] = 0.0;
+    acc += g * g;
+  }
+  double tot;
+  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) {
+    st->gg = tot;
+    st->tol2 = rtol * rtol * tot;
+    st->rr = tot;
+    st->rz = 0;
+    st->rz_new = 0;
+    st->pq = 0;
+    st->iters = 0;
+    st->status = 0;
+    st->maxit = maxit;
+    st->done = (tot == 0.0) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_if(int64_t N, const double* __restrict__ src,
+                                                      double* __restrict__ dst,
+                                                      const CgState* st) {
+  if (st->done) return;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_dot_rz(int64_t N, const double* __restrict__ r,
+                                                        const double* __restrict__ z, CgState* st,
+                                                        double* partials, uint32_t* counter) {
+  if (st->done) return;
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads)
+    acc += r[i] * z[i];
+  double tot;
+  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) st->rz_new = tot;
+}
+
+// p_out = z + beta p_in (beta = 0 on the first iteration), q = A p_out, p_out.q.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N,
+                                                          const double* __restrict__ w,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ pin,
+                                                          double* __restrict__ pout,
+                                                          double* __restrict__ q, CgState* st,
+                                                          double* partials, uint32_t* counter) {
+  if (st->done) return;
+  const bool first = st->iters == 0;
+  const double beta = first ? 0.0 : st->rz_new / st->rz;
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    auto pv = [&](int64_t k) { return first ? z[k] : z[k] + beta * pin[k]; };
+    const double pi = pv(i);
+    const double qi = pi + link_sum<DIM>(i, n, w, pi, pv);
+    pout[i] = pi;
+    q[i] = qi;
+    acc += pi * qi;
+  }
+  double tot;
+  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) {
+    st->pq = tot;
+    st->rz = st->rz_new;
+  }
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; ||r||^2; convergence / failure flags.
+__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, const double* __restrict__ p,
+                                                        const double* __restrict__ q,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ r, CgState* st,
+                                                        double* partials, uint32_t* counter) {
+  if (st->done) return;
+  const double alpha = st->rz / st->pq;
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  double tot;
+  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) {
+    st->rr = tot;
+    st->iters += 1;
+    if (!(tot == tot) || tot > 1.7e308) {
+      st->status = HIF_ERR_NO_CONV;
+      st->done = 1;
+    } else if (tot <= st->tol2) {
+      st->done = 1;
+    } else if (st->iters >= st->maxit) {
+      st->status = HIF_ERR_NO_CONV;
+      st->done = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_finish(int64_t N, const double* __restrict__ x,
+                                                        double* __restrict__ u, const CgState* st,
+                                                        int32_t* iters, double* relres, int step) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads)
+    u[i] = x[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    iters[step] = st->iters;
+    relres[step] = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
+  }
+}
+
+}  // namespace
+
+int vec_blocks(int64_t N) {
+  int64_t b = (N + kThreads - 1) / kThreads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+}
+
+void launch_links(const double* a_cells, int dim, int n, double scale, double* links,
+                  hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_links2d, dim3(1024), dim3(kThreads), 0, s, a_cells, n, scale, links);
+  else
+    hipLaunchKernelGGL(k_links3d, dim3(1024), dim3(kThreads), 0, s, a_cells, n, scale, links);
+  HIF_CHECK(hipGetLastError());
+}
+
+void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
+  if (h.dim == 2)
+    hipLaunchKernelGGL(k_spmv<2>, dim3(vec_blocks(h.N)), dim3(kThreads), 0, s, h.n, h.N,
+                       h.links.p, x, y);
+  else
+    hipLaunchKernelGGL(k_spmv<3>, dim3(vec_blocks(h.N)), dim3(kThreads), 0, s, h.n, h.N,
+                       h.links.p, x, y);
+  HIF_CHECK(hipGetLastError());
+}
+
+void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, double rtol,
+                   int maxit, hipStream_t s) {
+  auto k = h.dim == 2 ? k_cg_rhs<2> : k_cg_rhs<3>;
+  hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, u, h.r.p, h.x.p,
+                     kind, k1, k2, h.dt, rtol, maxit, h.st.p, h.partials.p, h.counter.p);
+  HIF_CHECK(hipGetLastError());
+}
+
+void launch_cg_copy_rz(Handle& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_if, dim3(h.nblk), dim3(kThreads), 0, s, h.N, h.r.p, h.z.p, h.st.p);
+}
+
+void launch_cg_dot_rz(Handle& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dot_rz, dim3(h.nblk), dim3(kThreads), 0, s, h.N, h.r.p, h.z.p, h.st.p,
+                     h.partials.p, h.counter.p);
+}
+
+void launch_cg_dir_spmv(Handle& h, const double* pin, double* pout, hipStream_t s) {
+  auto k = h.dim == 2 ? k_cg_dir_spmv<2> : k_cg_dir_spmv<3>;
+  hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, h.z.p, pin, pout,
+                     h.q.p, h.st.p, h.partials.p, h.counter.p);
+}
+
+void launch_cg_update(Handle& h, const double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, p, h.q.p, h.x.p, h.r.p,
+                     h.st.p, h.partials.p, h.counter.p);
+}
+
+void launch_cg_finish(Handle& h, double* u, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_finish, dim3(h.nblk), dim3(kThreads), 0, s, h.N, h.x.p, u, h.st.p,
+                     h.step_iters.p, h.step_relres.p, step);
+  HIF_CHECK(hipGetLastError());
+}
+
+}  // namespace hifcn

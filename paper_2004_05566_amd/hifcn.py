@@ -1,0 +1,200 @@
+"""ctypes binding of libhifcn (include/hifcn.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  Tensors must be CUDA (HIP) FP64 and
+C-contiguous; calls are ordered on torch's current stream.  Importing this module raises if
+the library has not been built, so no caller can fall back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhifcn.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                      "`python -m paper_2004_05566_amd.build` (hipcc, gfx950)")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+STORE = {"f64": 0, "f32": 1, "bf16": 2}
+HIF_OK, HIF_ERR_ARG, HIF_ERR_OOM, HIF_ERR_NOT_SPD, HIF_ERR_NO_CONV, HIF_ERR_HIP = range(6)
+
+
+class HifError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[status {status}] {msg}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("leaf", ctypes.c_int32)]
+
+
+class _Reaction(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k1", ctypes.c_double), ("k2", ctypes.c_double)]
+
+
+class _CgOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("root", ctypes.c_int32), ("entries", ctypes.c_int64),
+                ("N", ctypes.c_int64), ("store", ctypes.c_int32), ("dim", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_lib.hif_factor.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), ctypes.c_double,
+                            ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.hif_import.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), _vp, ctypes.c_size_t,
+                            ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.hif_apply.argtypes = [_vp, _vp, _vp, _vp]
+_lib.hif_spmv.argtypes = [_vp, _vp, _vp, _vp]
+_lib.cn_step.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts), _vp,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), _vp]
+_lib.cn_solve.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts), _vp,
+                          ctypes.c_int32, _vp, _vp, _vp]
+_lib.hif_factor_bytes.argtypes = [_vp]
+_lib.hif_factor_bytes.restype = ctypes.c_size_t
+_lib.hif_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
+_lib.hif_destroy.argtypes = [_vp]
+_lib.hif_destroy.restype = None
+_lib.hif_last_error.restype = ctypes.c_char_p
+for _f in ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
+           "hif_get_info"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTS = ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
+           "hif_factor_bytes", "hif_get_info", "hif_destroy", "hif_last_error")
+
+
+def _check(status: int):
+    if status != HIF_OK:
+        raise HifError(status, _lib.hif_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _grid(n: int, dim: int, leaf: int) -> _Grid:
+    g = _Grid()
+    g.dim = dim
+    g.n[0] = g.n[1] = n
+    g.n[2] = n if dim == 3 else 0
+    g.leaf = leaf
+    return g
+
+
+class Handle:
+    """A built (or imported) PHIF factor of A = I - dt/2 M plus its PCG workspace."""
+
+    def __init__(self, ptr: ctypes.c_void_p, n: int, dim: int):
+        self._h = ptr
+        self.n, self.dim = n, dim
+        self.N = n ** dim
+
+    def _p(self):
+        if not self._h:
+            raise HifError(HIF_ERR_ARG, "handle is closed")
+        return self._h
+
+    def apply(self, x, out=None, stream=None):
+        """out = F^-1 x."""
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(_lib.hif_apply(self._p(), _dev_f64(x, "x"), _dev_f64(out, "out"), _stream(stream)))
+        return out
+
+    def spmv(self, x, out=None, stream=None):
+        """out = (I - dt/2 M) x."""
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(_lib.hif_spmv(self._p(), _dev_f64(x, "x"), _dev_f64(out, "out"), _stream(stream)))
+        return out
+
+    def cn_solve(self, u, nsteps: int, rtol: float = 1e-8, maxit: int = 500,
+                 reaction=(0, 0.0, 1.0), stream=None):
+        """Advance u (in place) by nsteps Crank-Nicolson steps; returns (iters, relres)."""
+        r = _Reaction(int(reaction[0]), float(reaction[1]), float(reaction[2]))
+        o = _CgOpts(float(rtol), int(maxit), 0)
+        its = np.zeros(max(1, nsteps), np.int32)
+        rel = np.zeros(max(1, nsteps), np.float64)
+        st = _lib.cn_solve(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u"),
+                           int(nsteps), its.ctypes.data_as(_vp), rel.ctypes.data_as(_vp),
+                           _stream(stream))
+        if st == HIF_ERR_NO_CONV:
+            raise HifError(st, _lib.hif_last_error().decode())
+        _check(st)
+        return its[:nsteps].copy(), rel[:nsteps].copy()
+
+    def cn_step(self, u, rtol: float = 1e-8, maxit: int = 500, reaction=(0, 0.0, 1.0),
+                stream=None):
+        r = _Reaction(int(reaction[0]), float(reaction[1]), float(reaction[2]))
+        o = _CgOpts(float(rtol), int(maxit), 0)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check(_lib.cn_step(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u"),
+                            ctypes.byref(it), ctypes.byref(rel), _stream(stream)))
+        return it.value, rel.value
+
+    def factor_bytes(self) -> int:
+        return int(_lib.hif_factor_bytes(self._p()))
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(_lib.hif_get_info(self._p(), ctypes.byref(i)))
+        return {"levels": i.levels, "root": i.root, "entries": i.entries, "N": i.N,
+                "store": i.store, "dim": i.dim}
+
+    def close(self):
+        if self._h:
+            _lib.hif_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def factor(a_cells, dt: float, n: int, dim: int, eps: float, store: str = "f32",
+           leaf: int = 8, stream=None) -> Handle:
+    """hif_factor: build the PHIF factor on the GPU."""
+    h = ctypes.c_void_p()
+    g = _grid(n, dim, leaf)
+    _check(_lib.hif_factor(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g), float(eps),
+                           STORE[store], _stream(stream), ctypes.byref(h)))
+    return Handle(h, n, dim)
+
+
+def import_factor(a_cells, dt: float, n: int, dim: int, blob: bytes, store: str = "f64",
+                  leaf: int = 8, stream=None) -> Handle:
+    """hif_import: load a factor from an HIFB blob (test fixture)."""
+    h = ctypes.c_void_p()
+    g = _grid(n, dim, leaf)
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(_lib.hif_import(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g), buf,
+                           len(blob), STORE[store], _stream(stream), ctypes.byref(h)))
+    return Handle(h, n, dim)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def raw_library():
+    return _lib
