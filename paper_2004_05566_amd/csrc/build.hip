@@ -1,8 +1,935 @@
-// placeholder, replaced by the GPU factor build
+// PHIF factor build on the GPU, FP64 (Sec. 2.2).
+//
+// The active matrix of a level is held as a table of dense blocks A_gh between the level's
+// groups (cell interiors, edges/faces, corners, 3D edges) for every pair of groups that share a
+// cell closure.  Per level l = 0..L-1 (every stage is one batched launch over independent
+// blocks):
+//   (1) k_build_cells  : per cell, L = chol(A_II), L^-1, G = L^-1 A_IB, Schur S = G^T G, and the
+//                        apply blocks L^-1 and H = G^T L^-1 (eq2_3).
+//       k_schur_add    : per separator block, A_gh -= sum of the S pieces of the cells sharing
+//                        it, in a fixed cell order (deterministic, no atomics) (eq3_1).
+//   (2) k_jacobi_chol  : per separator group, L_g = chol(A_gg), L_g^-1, A_gg <- I.
+//       k_jacobi_scale : per separator block, A_gh <- L_g^-1 A_gh L_h^-T (jacobi-precond, eq3_2).
+//   (3) k_id           : per edge (3D face), column-pivoted Householder QR of the coupling to all
+//                        other active DOFs, rank k at relative precision eps, T = R11^-1 R12,
+//                        L_s = chol(I + T^T T), X = I - T (I + T^T T)^-1 T^T (eq2_5, eq_T, eq2_9).
+//       k_regroup      : blocks of level l+1 gathered from the surviving rows/columns (eq3_3).
+// Root: chol of the last remaining block (eq3_4).  The host plans the index structure between
+// launches; only ranks and pivot orders come back from the device once per level.
+#include <algorithm>
+#include <cmath>
+
 #include "kernels.hpp"
+#include "plan.hpp"
+
 namespace hifcn {
-void gpu_build(Handle& h, const double* a_cells, hif_store_t store, hipStream_t s) {
-  (void)h; (void)a_cells; (void)store; (void)s;
-  throw HifError(HIF_ERR_ARG, "GPU factor build not available yet");
+
+namespace {
+
+constexpr int kBT = 256;  // threads per build workgroup
+
+struct SubBlk { int64_t off; int32_t width, pad; };
+struct CellTask { int32_t nI, nB, nsub, offSub; int64_t offAII, offW, offS, offV; };
+struct Contrib { int64_t offS; int32_t ld, r0, c0, pad; };
+struct SchurTask { int64_t dst; int32_t rows, cols, ncontrib, offC; };
+struct GroupTask { int32_t n, pad; int64_t offBlk, offW, offLD, offV; };
+struct ScaleTask { int64_t offBlk, offTmp, offLg, offLh; int32_t rows, cols; };
+struct IdTask { int32_t n, m, nrs, offRS; int64_t offW, offV, offX; int32_t offPerm, kslot; };
+struct SrcEnt { int64_t off; int32_t ld, g; };
+struct RegroupTask { int64_t dst; int32_t nG, nH, offRowsG, offRowsH, nsubH, offSrc; };
+struct FillTask { int64_t off; int32_t rows, cols, offRowIds, offColIds; };
+
+// ------------------------------------------------------------- workgroup dense FP64 helpers --
+// In-place Cholesky (lower) of the n x n row-major matrix W (leading dimension ld).  A
+// non-positive or non-finite pivot raises *err and is replaced by 1 so the kernel completes.
+__device__ void wg_potrf(double* W, int n, int ld, int* err) {
+  __shared__ double piv;
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = W[(int64_t)j * ld + j];
+      if (!(d > 0.0) || !(d < 1.0e300)) {
+        atomicOr(err, 1);
+        d = 1.0;
+      }
+      piv = sqrt(d);
+      W[(int64_t)j * ld + j] = piv;
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) W[(int64_t)i * ld + j] /= p;
+    __syncthreads();
+    const int m = n - j - 1;
+    const int64_t tot = (int64_t)m * m;
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+      const int r = (int)(t / m), c = (int)(t - (int64_t)r * m);
+      if (c <= r) {
+        const int i = j + 1 + r, k = j + 1 + c;
+        W[(int64_t)i * ld + k] -= W[(int64_t)i * ld + j] * W[(int64_t)k * ld + j];
+      }
+    }
+    __syncthreads();
+  }
 }
+
+// B <- L^-1 B by right-looking forward substitution; L lower n x n (ld_l), B n x nc (ld_b).
+// tri: B is lower triangular (the identity), so step k only touches columns <= k.
+__device__ void wg_trsm_lower(const double* L, int n, int ldl, double* B, int nc, int ldb,
+                              bool tri) {
+  for (int k = 0; k < n; ++k) {
+    const double d = L[(int64_t)k * ldl + k];
+    const int cols = tri ? k + 1 : nc;
+    for (int c = threadIdx.x; c < cols; c += blockDim.x) B[(int64_t)k * ldb + c] /= d;
+    __syncthreads();
+    const int rows = n - k - 1;
+    const int64_t tot = (int64_t)rows * cols;
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+      const int r = (int)(t / cols), c = (int)(t - (int64_t)r * cols);
+      const int i = k + 1 + r;
+      B[(int64_t)i * ldb + c] -= L[(int64_t)i * ldl + k] * B[(int64_t)k * ldb + c];
+    }
+    __syncthreads();
+  }
 }
+
+__device__ void wg_identity(double* X, int n, int ld) {
+  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+    const int i = (int)(t / n), j = (int)(t - (int64_t)i * n);
+    X[(int64_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// packed column-major lower triangle of the row-major lower matrix X
+__device__ void wg_store_packed(double* dst, const double* X, int n, int ld) {
+  const int64_t tot = (int64_t)n * n;
+  for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int j = (int)(t / n), i = (int)(t - (int64_t)j * n);
+    if (i >= j) dst[colstart(j, n) + (i - j)] = X[(int64_t)i * ld + j];
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return __shfl(v, 0, 64);
+}
+
+// ---------------------------------------------------------------------------- stencil fill --
+// Entry (i, j) of A = I - dt/2 M from the scaled link weights (see solver.hip for the layout).
+__device__ double a_entry(int n, int dim, const double* w, int32_t i, int32_t j) {
+  const int64_t n1 = n + 1, nn = (int64_t)n * n;
+  const int ix = i % n, iy = (i / n) % n, iz = dim == 3 ? i / (int)nn : 0;
+  const int64_t lx = (dim == 3 ? nn : (int64_t)n) * n1;
+  const int64_t xrow = dim == 3 ? ((int64_t)iz * n + iy) * n1 : (int64_t)iy * n1;
+  const int64_t yb = dim == 3 ? ((int64_t)iz * n1 + iy) * n + ix : (int64_t)iy * n + ix;
+  const int64_t zb = ((int64_t)iz * n + iy) * n + ix;
+  if (i == j) {
+    double d = 1.0 + w[xrow + ix] + w[xrow + ix + 1] + w[lx + yb] + w[lx + yb + n];
+    if (dim == 3) d += w[2 * lx + zb] + w[2 * lx + zb + nn];
+    return d;
+  }
+  const int jx = j % n, jy = (j / n) % n, jz = dim == 3 ? j / (int)nn : 0;
+  const int dx = jx - ix, dy = jy - iy, dz = jz - iz;
+  if (dy == 0 && dz == 0) {
+    if (dx == 1) return -w[xrow + ix + 1];
+    if (dx == -1) return -w[xrow + ix];
+  } else if (dx == 0 && dz == 0) {
+    if (dy == 1) return -w[lx + yb + n];
+    if (dy == -1) return -w[lx + yb];
+  } else if (dim == 3 && dx == 0 && dy == 0) {
+    if (dz == 1) return -w[2 * lx + zb + nn];
+    if (dz == -1) return -w[2 * lx + zb];
+  }
+  return 0.0;
+}
+
+__global__ __launch_bounds__(kBT) void k_fill(const FillTask* __restrict__ tasks,
+                                              const int32_t* __restrict__ ids, int n, int dim,
+                                              const double* __restrict__ w, double* __restrict__ A) {
+  const FillTask t = tasks[blockIdx.x];
+  const int64_t tot = (int64_t)t.rows * t.cols;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int r = (int)(e / t.cols), c = (int)(e - (int64_t)r * t.cols);
+    A[t.off + e] = a_entry(n, dim, w, ids[t.offRowIds + r], ids[t.offColIds + c]);
+  }
+}
+
+// ------------------------------------------------------------------- (1) cell elimination --
+__global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict__ tasks,
+                                                     const SubBlk* __restrict__ subs,
+                                                     const double* __restrict__ A,
+                                                     double* __restrict__ work,
+                                                     double* __restrict__ schur,
+                                                     double* __restrict__ fv, int* err) {
+  const CellTask t = tasks[blockIdx.x];
+  const int nI = t.nI, nB = t.nB;
+  double* W = work + t.offW;                    // nI x nI : A_II -> L
+  double* X = W + (int64_t)nI * nI;             // nI x nI : L^-1
+  double* G = X + (int64_t)nI * nI;             // nI x nB : A_IB -> G
+  for (int64_t e = threadIdx.x; e < (int64_t)nI * nI; e += blockDim.x) W[e] = A[t.offAII + e];
+  int c0 = 0;
+  for (int s = 0; s < t.nsub; ++s) {
+    const SubBlk sb = subs[t.offSub + s];
+    for (int64_t e = threadIdx.x; e < (int64_t)nI * sb.width; e += blockDim.x) {
+      const int i = (int)(e / sb.width), j = (int)(e - (int64_t)i * sb.width);
+      G[(int64_t)i * nB + c0 + j] = A[sb.off + e];
+    }
+    c0 += sb.width;
+  }
+  wg_identity(X, nI, nI);
+  __syncthreads();
+  wg_potrf(W, nI, nI, err);
+  wg_trsm_lower(W, nI, nI, X, nI, nI, true);
+  if (nB) wg_trsm_lower(W, nI, nI, G, nB, nB, false);
+  __syncthreads();
+  // Schur contribution S = G^T G
+  for (int64_t e = threadIdx.x; e < (int64_t)nB * nB; e += blockDim.x) {
+    const int a = (int)(e / nB), b = (int)(e - (int64_t)a * nB);
+    double acc = 0;
+    for (int i = 0; i < nI; ++i) acc += G[(int64_t)i * nB + a] * G[(int64_t)i * nB + b];
+    schur[t.offS + e] = acc;
+  }
+  // apply blocks: packed L^-1, then H = G^T L^-1 column-major (H[j*nB + b])
+  double* V = fv + t.offV;
+  wg_store_packed(V, X, nI, nI);
+  double* H = V + tri_count(nI);
+  for (int64_t e = threadIdx.x; e < (int64_t)nB * nI; e += blockDim.x) {
+    const int j = (int)(e / nB), b = (int)(e - (int64_t)j * nB);
+    double acc = 0;
+    for (int i = j; i < nI; ++i) acc += G[(int64_t)i * nB + b] * X[(int64_t)i * nI + j];
+    H[e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kBT) void k_schur_add(const SchurTask* __restrict__ tasks,
+                                                   const Contrib* __restrict__ con,
+                                                   const double* __restrict__ schur,
+                                                   double* __restrict__ A) {
+  const SchurTask t = tasks[blockIdx.x];
+  const int64_t tot = (int64_t)t.rows * t.cols;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int i = (int)(e / t.cols), j = (int)(e - (int64_t)i * t.cols);
+    double acc = A[t.dst + e];
+    for (int c = 0; c < t.ncontrib; ++c) {
+      const Contrib q = con[t.offC + c];
+      acc -= schur[q.offS + (int64_t)(q.r0 + i) * q.ld + q.c0 + j];
+    }
+    A[t.dst + e] = acc;
+  }
+}
+
+// --------------------------------------------------------------------- (2) block Jacobi --
+__global__ __launch_bounds__(kBT) void k_jacobi_chol(const GroupTask* __restrict__ tasks,
+                                                     double* __restrict__ A,
+                                                     double* __restrict__ work,
+                                                     double* __restrict__ LD,
+                                                     double* __restrict__ fv, int* err) {
+  const GroupTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  double* W = work + t.offW;
+  double* X = LD + t.offLD;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) W[e] = A[t.offBlk + e];
+  wg_identity(X, n, n);
+  __syncthreads();
+  wg_potrf(W, n, n, err);
+  wg_trsm_lower(W, n, n, X, n, n, true);
+  __syncthreads();
+  wg_store_packed(fv + t.offV, X, n, n);
+  wg_identity(A + t.offBlk, n, n);  // the rescaled diagonal block is the identity
+}
+
+// A_gh <- L_g^-1 A_gh L_h^-T via Y = A L_h^-T (scratch), then A = L_g^-1 Y.
+__global__ __launch_bounds__(kBT) void k_jacobi_scale(const ScaleTask* __restrict__ tasks,
+                                                      double* __restrict__ A,
+                                                      double* __restrict__ tmp,
+                                                      const double* __restrict__ LD) {
+  const ScaleTask t = tasks[blockIdx.x];
+  const int R = t.rows, C = t.cols;
+  double* Ab = A + t.offBlk;
+  double* Y = tmp + t.offTmp;
+  const double* Lg = LD + t.offLg;
+  const double* Lh = LD + t.offLh;
+  const int64_t tot = (int64_t)R * C;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int i = (int)(e / C), j = (int)(e - (int64_t)i * C);
+    double acc = 0;
+    for (int q = 0; q <= j; ++q) acc += Ab[(int64_t)i * C + q] * Lh[(int64_t)j * C + q];
+    Y[e] = acc;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int i = (int)(e / C), j = (int)(e - (int64_t)i * C);
+    double acc = 0;
+    for (int p = 0; p <= i; ++p) acc += Lg[(int64_t)i * R + p] * Y[(int64_t)p * C + j];
+    Ab[e] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ (3) skeletonization --
+// Work layout: M (m x n column-major), norms (n), v (m), T (k x nr col-major), S/Ls (nr x nr),
+// Ls^-1 (nr x nr), Wm (k x nr).
+__global__ __launch_bounds__(kBT) void k_id(const IdTask* __restrict__ tasks,
+                                            const SubBlk* __restrict__ rs,
+                                            const double* __restrict__ A,
+                                            double* __restrict__ work, double* __restrict__ fv,
+                                            double* __restrict__ Xbuf, int32_t* __restrict__ permout,
+                                            int32_t* __restrict__ kout, double eps, int* err) {
+  const IdTask t = tasks[blockIdx.x];
+  const int n = t.n, m = t.m;
+  double* M = work + t.offW;
+  double* nrm = M + (int64_t)m * n;
+  double* v = nrm + n;
+  __shared__ int perm_s[1024];
+  __shared__ int piv_s, kstop_s;
+  __shared__ double r00_s, pnorm_s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // gather M: rows = the coupling blocks (h, g) of every other group h, stacked
+  {
+    int r0 = 0;
+    for (int s = 0; s < t.nrs; ++s) {
+      const SubBlk sb = rs[t.offRS + s];  // block (h, g): width = |h| rows, n columns
+      for (int64_t e = threadIdx.x; e < (int64_t)sb.width * n; e += blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        M[(int64_t)j * m + r0 + i] = A[sb.off + e];
+      }
+      r0 += sb.width;
+    }
+  }
+  for (int j = threadIdx.x; j < n; j += blockDim.x) perm_s[j] = j;
+  if (threadIdx.x == 0) { kstop_s = -1; r00_s = 0; }
+  __syncthreads();
+  const int kk = min(m, n);
+  int k = kk;
+  for (int st = 0; st < kk; ++st) {
+    for (int j = st + wid; j < n; j += nw) {   // squared norms of the remaining columns
+      double acc = 0;
+      for (int i = st + lane; i < m; i += 64) acc += M[(int64_t)j * m + i] * M[(int64_t)j * m + i];
+      acc = wave_sum(acc);
+      if (lane == 0) nrm[j] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int p = st;
+      double best = nrm[st];
+      for (int j = st + 1; j < n; ++j)
+        if (nrm[j] > best) { best = nrm[j]; p = j; }   // ties: lowest position
+      const double pn = sqrt(best);
+      if (st == 0) r00_s = pn;
+      kstop_s = (pn <= eps * r00_s || pn == 0.0) ? st : -1;
+      piv_s = p;
+      pnorm_s = pn;
+      if (kstop_s < 0 && p != st) {
+        const int tmpi = perm_s[st];
+        perm_s[st] = perm_s[p];
+        perm_s[p] = tmpi;
+      }
+    }
+    __syncthreads();
+    if (kstop_s >= 0) { k = st; break; }
+    const int p = piv_s;
+    if (p != st)
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double a = M[(int64_t)st * m + i];
+        M[(int64_t)st * m + i] = M[(int64_t)p * m + i];
+        M[(int64_t)p * m + i] = a;
+      }
+    __syncthreads();
+    // Householder reflector for column st, rows st..m-1
+    const double pn = pnorm_s;
+    const double x0 = M[(int64_t)st * m + st];
+    const double alpha = x0 >= 0 ? -pn : pn;
+    const double v0 = x0 - alpha;
+    const double vtv = pn * pn - x0 * x0 + v0 * v0;
+    for (int i = st + threadIdx.x; i < m; i += blockDim.x) v[i] = (i == st) ? v0 : M[(int64_t)st * m + i];
+    __syncthreads();
+    if (threadIdx.x == 0) M[(int64_t)st * m + st] = alpha;
+    if (vtv > 0) {
+      const double tau = 2.0 / vtv;
+      for (int j = st + 1 + wid; j < n; j += nw) {
+        double acc = 0;
+        for (int i = st + lane; i < m; i += 64) acc += v[i] * M[(int64_t)j * m + i];
+        acc = wave_sum(acc) * tau;
+        for (int i = st + lane; i < m; i += 64) M[(int64_t)j * m + i] -= acc * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  const int nr = n - k;
+  double* T = v + m;                     // k x nr, column-major
+  double* S = T + (int64_t)k * nr;       // nr x nr -> L_s
+  double* Li = S + (int64_t)nr * nr;     // nr x nr -> L_s^-1
+  double* Wm = Li + (int64_t)nr * nr;    // k x nr row-major: T L_s^-T
+  // T = R11^-1 R12 by back substitution, one column per thread
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    double* tc = T + (int64_t)j * k;
+    for (int s = k - 1; s >= 0; --s) {
+      double acc = M[(int64_t)(k + j) * m + s];
+      for (int q = s + 1; q < k; ++q) acc -= M[(int64_t)q * m + s] * tc[q];
+      tc[s] = acc / M[(int64_t)s * m + s];
+    }
+  }
+  __syncthreads();
+  // S = I + T^T T
+  for (int64_t e = threadIdx.x; e < (int64_t)nr * nr; e += blockDim.x) {
+    const int a = (int)(e / nr), b = (int)(e - (int64_t)a * nr);
+    double acc = (a == b) ? 1.0 : 0.0;
+    for (int s = 0; s < k; ++s) acc += T[(int64_t)a * k + s] * T[(int64_t)b * k + s];
+    S[e] = acc;
+  }
+  wg_identity(Li, nr, nr);
+  __syncthreads();
+  wg_potrf(S, nr, nr, err);
+  wg_trsm_lower(S, nr, nr, Li, nr, nr, true);
+  __syncthreads();
+  // factor values: T (column-major k x nr) and packed L_s^-1 after the group's packed L_g^-1
+  double* V = fv + t.offV + tri_count(n);
+  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) V[e] = T[e];
+  wg_store_packed(V + (int64_t)k * nr, Li, nr, nr);
+  // Wm = T L_s^-T,  X = I - Wm Wm^T (k x k)
+  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) {
+    const int s = (int)(e / nr), i = (int)(e - (int64_t)s * nr);
+    double acc = 0;
+    for (int j = 0; j <= i; ++j) acc += T[(int64_t)j * k + s] * Li[(int64_t)i * nr + j];
+    Wm[e] = acc;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+    const int a = (int)(e / k), b = (int)(e - (int64_t)a * k);
+    double acc = (a == b) ? 1.0 : 0.0;
+    for (int i = 0; i < nr; ++i) acc -= Wm[(int64_t)a * nr + i] * Wm[(int64_t)b * nr + i];
+    Xbuf[t.offX + e] = acc;
+  }
+  // pivot order: redundant first, then skeletons
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    permout[t.offPerm + i] = (i < nr) ? perm_s[k + i] : perm_s[i - nr];
+  if (threadIdx.x == 0) kout[t.kslot] = k;
+}
+
+// ------------------------------------------------------------------------------- regroup --
+__global__ __launch_bounds__(kBT) void k_regroup(const RegroupTask* __restrict__ tasks,
+                                                 const RowSrc* __restrict__ rows,
+                                                 const SrcEnt* __restrict__ src,
+                                                 const double* __restrict__ Aold,
+                                                 const double* __restrict__ Xbuf,
+                                                 const int64_t* __restrict__ xoff,
+                                                 const int32_t* __restrict__ gk,
+                                                 double* __restrict__ Anew) {
+  const RegroupTask t = tasks[blockIdx.x];
+  const int64_t tot = (int64_t)t.nG * t.nH;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int i = (int)(e / t.nH), j = (int)(e - (int64_t)i * t.nH);
+    const RowSrc ri = rows[t.offRowsG + i], rj = rows[t.offRowsH + j];
+    const SrcEnt s = src[t.offSrc + (int64_t)ri.sub * t.nsubH + rj.sub];
+    double v = 0.0;
+    if (s.off >= 0) {
+      v = Aold[s.off + (int64_t)ri.pos * s.ld + rj.pos];
+    } else if (s.off == -2) {  // the same previous group: X (skeletonized) or the identity
+      const int64_t xo = xoff[s.g];
+      v = xo >= 0 ? Xbuf[xo + (int64_t)ri.spos * gk[s.g] + rj.spos] : (ri.pos == rj.pos ? 1.0 : 0.0);
+    }
+    Anew[t.dst + e] = v;
+  }
+}
+
+__global__ void k_to_store_f64(const double* src, double* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_to_store_f32(const double* src, float* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+__global__ void k_to_store_bf16(const double* src, bf16_t* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i].bits = f32_to_bf16_bits((float)src[i]);
+}
+
+template <typename T>
+void upload(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
+  d.alloc(std::max<size_t>(1, h.size()));
+  if (!h.empty())
+    HIF_CHECK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
+
+}  // namespace
+
+// Build the factor of the handle's operator on the device and lay it out for the apply.
+void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t s) {
+  (void)a_cells;  // the link weights were already derived from it
+  const Geometry geo{hd.dim, hd.n, hd.leaf, hd.L};
+  DevBuf<int> err(1);
+  HIF_CHECK(hipMemsetAsync(err.p, 0, sizeof(int), s));
+  auto check_err = [&](const char* where) {
+    int e = 0;
+    HIF_CHECK(hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIF_CHECK(hipStreamSynchronize(s));
+    HIF_REQUIRE(e == 0, HIF_ERR_NOT_SPD,
+                std::string("non-positive Cholesky pivot during ") + where);
+  };
+
+  LevelPlan P = plan_level0(geo);
+  DevBuf<double> A(std::max<int64_t>(1, P.nvals));
+  {  // level-0 blocks straight from the stencil
+    std::vector<int32_t> ids;
+    std::vector<int32_t> goff(P.groups.size());
+    for (size_t g = 0; g < P.groups.size(); ++g) {
+      goff[g] = (int32_t)ids.size();
+      ids.insert(ids.end(), P.groups[g].dofs.begin(), P.groups[g].dofs.end());
+    }
+    std::vector<FillTask> ft(P.blocks.size());
+    for (size_t b = 0; b < P.blocks.size(); ++b) {
+      const int g = P.blocks[b].first, h = P.blocks[b].second;
+      ft[b] = {P.block_off[b], (int32_t)P.groups[g].dofs.size(), (int32_t)P.groups[h].dofs.size(),
+               goff[g], goff[h]};
+    }
+    DevBuf<int32_t> dids;
+    DevBuf<FillTask> dft;
+    upload(dids, ids, s);
+    upload(dft, ft, s);
+    hipLaunchKernelGGL(k_fill, dim3(ft.size()), dim3(kBT), 0, s, dft.p, dids.p, hd.n, hd.dim,
+                       hd.links.p, A.p);
+    HIF_CHECK(hipGetLastError());
+    HIF_CHECK(hipStreamSynchronize(s));
+  }
+
+  // Host record of the factor layout (offsets relative to each level's value chunk).
+  struct LevelOut {
+    std::vector<CellDesc> cells;
+    std::vector<std::vector<int32_t>> cellI, cellB;
+    std::vector<GroupDesc> groups;
+    std::vector<std::vector<int32_t>> gids, gperm, gslots_ptr, gslots;
+    int64_t base = 0;
+    int maxI = 0, maxB = 0, maxG = 0, maxK = 0, maxR = 0;
+    int64_t cbn = 0;
+  };
+  std::vector<LevelOut> outs;
+  std::vector<DevBuf<double>> chunks;
+  int64_t nvals_actual = 0;
+  int64_t total_chunk = 0;
+
+  for (int lev = 0; lev < hd.L; ++lev) {
+    LevelOut lo;
+    const int G = (int)P.groups.size();
+    auto gsz = [&](int g) { return (int)P.groups[g].dofs.size(); };
+    // ---- value chunk layout: cells then separator groups
+    int64_t voff = 0;
+    std::vector<int64_t> cell_voff(P.cells.size()), grp_voff(G, -1);
+    std::vector<int> cell_nB(P.cells.size());
+    for (size_t ci = 0; ci < P.cells.size(); ++ci) {
+      int nB = 0;
+      for (int b : P.cellB[ci]) nB += gsz(b);
+      cell_nB[ci] = nB;
+      cell_voff[ci] = voff;
+      const int nI = gsz(P.cells[ci]);
+      voff += tri64(nI) + (int64_t)nB * nI;
+    }
+    for (int g : P.seps) {
+      grp_voff[g] = voff;
+      voff += tri64(gsz(g)) * (P.groups[g].kind == 1 ? 2 : 1);
+    }
+    DevBuf<double> fv(std::max<int64_t>(1, voff));
+
+    // ---- (1) cell elimination
+    std::vector<CellTask> ct(P.cells.size());
+    std::vector<SubBlk> subs;
+    int64_t woff = 0, soff = 0;
+    std::vector<int64_t> cell_soff(P.cells.size());
+    for (size_t ci = 0; ci < P.cells.size(); ++ci) {
+      const int c = P.cells[ci];
+      const int nI = gsz(c), nB = cell_nB[ci];
+      CellTask& t = ct[ci];
+      t.nI = nI;
+      t.nB = nB;
+      t.nsub = (int)P.cellB[ci].size();
+      t.offSub = (int32_t)subs.size();
+      for (int b : P.cellB[ci]) {
+        const int blk = P.find_block(c, b);
+        HIF_REQUIRE(blk >= 0, HIF_ERR_ARG, "internal: missing cell-boundary block");
+        subs.push_back({P.block_off[blk], gsz(b), 0});
+      }
+      t.offAII = P.block_off[P.find_block(c, c)];
+      t.offW = woff;
+      woff += 2 * (int64_t)nI * nI + (int64_t)nI * nB;
+      t.offS = soff;
+      cell_soff[ci] = soff;
+      soff += (int64_t)nB * nB;
+      t.offV = cell_voff[ci];
+    }
+    {
+      DevBuf<CellTask> dct;
+      DevBuf<SubBlk> dsub;
+      DevBuf<double> work(std::max<int64_t>(1, woff));
+      DevBuf<double> schur(std::max<int64_t>(1, soff));
+      upload(dct, ct, s);
+      upload(dsub, subs, s);
+      if (!ct.empty())
+        hipLaunchKernelGGL(k_build_cells, dim3(ct.size()), dim3(kBT), 0, s, dct.p, dsub.p, A.p,
+                           work.p, schur.p, fv.p, err.p);
+      HIF_CHECK(hipGetLastError());
+      // Schur assembly into every separator block touched by some cell
+      std::vector<std::vector<Contrib>> per_block(P.blocks.size());
+      for (size_t ci = 0; ci < P.cells.size(); ++ci) {
+        const std::vector<int>& B = P.cellB[ci];
+        std::vector<int> boff(B.size());
+        int acc = 0;
+        for (size_t q = 0; q < B.size(); ++q) { boff[q] = acc; acc += gsz(B[q]); }
+        for (size_t a = 0; a < B.size(); ++a)
+          for (size_t b = 0; b < B.size(); ++b) {
+            const int blk = P.find_block(B[a], B[b]);
+            HIF_REQUIRE(blk >= 0, HIF_ERR_ARG, "internal: missing separator block");
+            per_block[blk].push_back({cell_soff[ci], cell_nB[ci], boff[a], boff[b], 0});
+          }
+      }
+      std::vector<SchurTask> stk;
+      std::vector<Contrib> con;
+      for (size_t b = 0; b < P.blocks.size(); ++b) {
+        if (per_block[b].empty()) continue;
+        const int g = P.blocks[b].first, h = P.blocks[b].second;
+        stk.push_back({P.block_off[b], gsz(g), gsz(h), (int32_t)per_block[b].size(),
+                       (int32_t)con.size()});
+        con.insert(con.end(), per_block[b].begin(), per_block[b].end());
+      }
+      DevBuf<SchurTask> dst;
+      DevBuf<Contrib> dcon;
+      upload(dst, stk, s);
+      upload(dcon, con, s);
+      if (!stk.empty())
+        hipLaunchKernelGGL(k_schur_add, dim3(stk.size()), dim3(kBT), 0, s, dst.p, dcon.p, schur.p,
+                           A.p);
+      HIF_CHECK(hipGetLastError());
+      check_err("cell elimination");
+    }
+
+    // ---- (2) block Jacobi on every separator group
+    std::vector<int64_t> ld_off(G, -1);
+    {
+      std::vector<GroupTask> gt;
+      int64_t wo = 0, lo2 = 0;
+      for (int g : P.seps) {
+        const int n = gsz(g);
+        ld_off[g] = lo2;
+        gt.push_back({n, 0, P.block_off[P.find_block(g, g)], wo, lo2, grp_voff[g]});
+        wo += (int64_t)n * n;
+        lo2 += (int64_t)n * n;
+      }
+      DevBuf<GroupTask> dgt;
+      DevBuf<double> work(std::max<int64_t>(1, wo));
+      DevBuf<double> LD(std::max<int64_t>(1, lo2));
+      upload(dgt, gt, s);
+      if (!gt.empty())
+        hipLaunchKernelGGL(k_jacobi_chol, dim3(gt.size()), dim3(kBT), 0, s, dgt.p, A.p, work.p,
+                           LD.p, fv.p, err.p);
+      HIF_CHECK(hipGetLastError());
+      std::vector<ScaleTask> sc;
+      int64_t to = 0;
+      for (size_t b = 0; b < P.blocks.size(); ++b) {
+        const int g = P.blocks[b].first, h = P.blocks[b].second;
+        if (g == h || P.groups[g].kind == 0 || P.groups[h].kind == 0) continue;
+        sc.push_back({P.block_off[b], to, ld_off[g], ld_off[h], gsz(g), gsz(h)});
+        to += (int64_t)gsz(g) * gsz(h);
+      }
+      DevBuf<ScaleTask> dsc;
+      DevBuf<double> tmp(std::max<int64_t>(1, to));
+      upload(dsc, sc, s);
+      if (!sc.empty())
+        hipLaunchKernelGGL(k_jacobi_scale, dim3(sc.size()), dim3(kBT), 0, s, dsc.p, A.p, tmp.p,
+                           LD.p);
+      HIF_CHECK(hipGetLastError());
+      check_err("block Jacobi");
+    }
+
+    // ---- (3) skeletonization of every edge (3D: face)
+    std::vector<int32_t> kval(P.skel.size());
+    std::vector<int32_t> permv;
+    std::vector<int32_t> perm_off(G, -1);
+    DevBuf<double> Xbuf;
+    std::vector<int64_t> xoff(G, -1);
+    {
+      std::vector<IdTask> it;
+      std::vector<SubBlk> rs;
+      int64_t wo = 0, xo = 0;
+      int32_t po = 0;
+      for (size_t q = 0; q < P.skel.size(); ++q) {
+        const int g = P.skel[q];
+        const int n = gsz(g);
+        HIF_REQUIRE(n <= 1024, HIF_ERR_ARG, "edge/face group larger than 1024 DOFs");
+        IdTask t{};
+        t.n = n;
+        t.offRS = (int32_t)rs.size();
+        int m = 0;
+        for (int h : P.seps) {   // every other active group coupled to g
+          if (h == g) continue;
+          const int blk = P.find_block(h, g);
+          if (blk < 0) continue;
+          rs.push_back({P.block_off[blk], gsz(h), 0});
+          m += gsz(h);
+        }
+        t.m = m;
+        t.nrs = (int32_t)(rs.size() - t.offRS);
+        t.offW = wo;
+        wo += (int64_t)m * n + n + m + (int64_t)n * n * 3 + 16;
+        t.offV = grp_voff[g];
+        t.offX = xo;
+        xoff[g] = xo;
+        xo += (int64_t)n * n;
+        t.offPerm = po;
+        perm_off[g] = po;
+        po += n;
+        t.kslot = (int32_t)q;
+        it.push_back(t);
+      }
+      DevBuf<IdTask> dit;
+      DevBuf<SubBlk> drs;
+      DevBuf<double> work(std::max<int64_t>(1, wo));
+      Xbuf.alloc(std::max<int64_t>(1, xo));
+      DevBuf<int32_t> dperm(std::max<int32_t>(1, po));
+      DevBuf<int32_t> dk(std::max<size_t>(1, P.skel.size()));
+      upload(dit, it, s);
+      upload(drs, rs, s);
+      if (!it.empty())
+        hipLaunchKernelGGL(k_id, dim3(it.size()), dim3(kBT), 0, s, dit.p, drs.p, A.p, work.p, fv.p,
+                           Xbuf.p, dperm.p, dk.p, hd.eps, err.p);
+      HIF_CHECK(hipGetLastError());
+      permv.resize(po);
+      if (po)
+        HIF_CHECK(hipMemcpyAsync(permv.data(), dperm.p, po * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+      if (!kval.empty())
+        HIF_CHECK(hipMemcpyAsync(kval.data(), dk.p, kval.size() * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+      check_err("skeletonization");
+    }
+
+    // ---- record this level's apply layout
+    std::vector<int> gk(G, -1);
+    for (size_t q = 0; q < P.skel.size(); ++q) gk[P.skel[q]] = kval[q];
+    int64_t cbn = 0;
+    std::vector<int64_t> cell_cb(P.cells.size());
+    for (size_t ci = 0; ci < P.cells.size(); ++ci) {
+      const int c = P.cells[ci];
+      CellDesc d{};
+      d.nI = gsz(c);
+      d.nB = cell_nB[ci];
+      d.offV = (int32_t)cell_voff[ci];  // chunk-relative for now
+      d.offCB = (int32_t)cbn;
+      cell_cb[ci] = cbn;
+      cbn += d.nB;
+      lo.cells.push_back(d);
+      lo.cellI.push_back(P.groups[c].dofs);
+      std::vector<int32_t> B;
+      for (int b : P.cellB[ci]) B.insert(B.end(), P.groups[b].dofs.begin(), P.groups[b].dofs.end());
+      lo.cellB.push_back(std::move(B));
+      lo.maxI = std::max(lo.maxI, d.nI);
+      lo.maxB = std::max(lo.maxB, d.nB);
+      nvals_actual += tri64(d.nI) + (int64_t)d.nI * d.nB;
+    }
+    lo.cbn = cbn;
+    // gather map of boundary contributions, in cell order
+    std::vector<int> sep_index(G, -1);
+    for (size_t q = 0; q < P.seps.size(); ++q) sep_index[P.seps[q]] = (int)q;
+    std::vector<std::vector<std::vector<int32_t>>> slots(P.seps.size());
+    for (size_t q = 0; q < P.seps.size(); ++q) slots[q].resize(gsz(P.seps[q]));
+    for (size_t ci = 0; ci < P.cells.size(); ++ci) {
+      int64_t o = cell_cb[ci];
+      for (int b : P.cellB[ci]) {
+        const int q = sep_index[b];
+        for (int p = 0; p < gsz(b); ++p) slots[q][p].push_back((int32_t)(o + p));
+        o += gsz(b);
+      }
+    }
+    std::vector<std::vector<int32_t>> surv(G);
+    for (size_t q = 0; q < P.seps.size(); ++q) {
+      const int g = P.seps[q];
+      const int n = gsz(g);
+      GroupDesc d{};
+      d.n = n;
+      d.nr = gk[g] >= 0 ? n - gk[g] : 0;
+      d.offV = (int32_t)grp_voff[g];
+      lo.gids.push_back(P.groups[g].dofs);
+      std::vector<int32_t> pm;
+      if (gk[g] >= 0) {
+        pm.assign(permv.begin() + perm_off[g], permv.begin() + perm_off[g] + n);
+        surv[g].assign(pm.begin() + d.nr, pm.end());
+      } else {
+        surv[g].resize(n);
+        for (int i = 0; i < n; ++i) surv[g][i] = i;
+      }
+      lo.gperm.push_back(pm);
+      std::vector<int32_t> ptr{0};
+      std::vector<int32_t> sl;
+      for (int p = 0; p < n; ++p) {
+        sl.insert(sl.end(), slots[q][p].begin(), slots[q][p].end());
+        ptr.push_back((int32_t)sl.size());
+      }
+      lo.gslots_ptr.push_back(std::move(ptr));
+      lo.gslots.push_back(std::move(sl));
+      lo.groups.push_back(d);
+      lo.maxG = std::max(lo.maxG, n);
+      lo.maxR = std::max(lo.maxR, d.nr);
+      lo.maxK = std::max(lo.maxK, n - d.nr);
+      const int64_t kk = n - d.nr;
+      nvals_actual += tri64(n) + (d.nr ? kk * d.nr + tri64(d.nr) : 0);
+    }
+    lo.base = total_chunk;
+    total_chunk += voff;
+    outs.push_back(std::move(lo));
+    chunks.push_back(std::move(fv));
+
+    // ---- regroup into level l+1
+    LevelPlan Pn = plan_next(geo, P, surv);
+    DevBuf<double> An(std::max<int64_t>(1, Pn.nvals));
+    {
+      std::vector<RegroupTask> rt;
+      std::vector<RowSrc> rows;
+      std::vector<SrcEnt> src;
+      std::vector<int32_t> rows_off(Pn.groups.size());
+      for (size_t g = 0; g < Pn.groups.size(); ++g) {
+        rows_off[g] = (int32_t)rows.size();
+        rows.insert(rows.end(), Pn.rows[g].begin(), Pn.rows[g].end());
+      }
+      for (size_t b = 0; b < Pn.blocks.size(); ++b) {
+        const int Gi = Pn.blocks[b].first, Hi = Pn.blocks[b].second;
+        const std::vector<int>& sg = Pn.subs[Gi];
+        const std::vector<int>& sh = Pn.subs[Hi];
+        RegroupTask t{};
+        t.dst = Pn.block_off[b];
+        t.nG = (int32_t)Pn.groups[Gi].dofs.size();
+        t.nH = (int32_t)Pn.groups[Hi].dofs.size();
+        t.offRowsG = rows_off[Gi];
+        t.offRowsH = rows_off[Hi];
+        t.nsubH = (int32_t)sh.size();
+        t.offSrc = (int32_t)src.size();
+        for (int ga : sg)
+          for (int hb : sh) {
+            if (ga == hb) {
+              src.push_back({-2, 0, ga});
+            } else {
+              const int blk = P.find_block(ga, hb);
+              src.push_back(blk >= 0 ? SrcEnt{P.block_off[blk], gsz(hb), 0} : SrcEnt{-1, 0, 0});
+            }
+          }
+        rt.push_back(t);
+      }
+      std::vector<int32_t> gkv(G, 0);
+      for (int g = 0; g < G; ++g) gkv[g] = gk[g] >= 0 ? gk[g] : 0;
+      DevBuf<RegroupTask> drt;
+      DevBuf<RowSrc> drows;
+      DevBuf<SrcEnt> dsrc;
+      DevBuf<int64_t> dxoff;
+      DevBuf<int32_t> dgk;
+      upload(drt, rt, s);
+      upload(drows, rows, s);
+      upload(dsrc, src, s);
+      upload(dxoff, xoff, s);
+      upload(dgk, gkv, s);
+      if (!rt.empty())
+        hipLaunchKernelGGL(k_regroup, dim3(rt.size()), dim3(kBT), 0, s, drt.p, drows.p, dsrc.p,
+                           A.p, Xbuf.p, dxoff.p, dgk.p, An.p);
+      HIF_CHECK(hipGetLastError());
+      HIF_CHECK(hipStreamSynchronize(s));
+    }
+    A = std::move(An);
+    P = std::move(Pn);
+  }
+
+  // ---- root: the single group left at level L
+  HIF_REQUIRE(P.cells.size() == 1 && P.seps.empty(), HIF_ERR_ARG, "internal: root is not one cell");
+  const int rg = P.cells[0];
+  const int nroot = (int)P.groups[rg].dofs.size();
+  DevBuf<double> rchunk(std::max<int64_t>(1, tri64(nroot)));
+  {
+    std::vector<CellTask> ct(1);
+    ct[0] = {nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, 0, 0};
+    DevBuf<CellTask> dct;
+    DevBuf<SubBlk> dsub(1);
+    DevBuf<double> work(std::max<int64_t>(1, 2 * (int64_t)nroot * nroot));
+    DevBuf<double> schur(1);
+    upload(dct, ct, s);
+    hipLaunchKernelGGL(k_build_cells, dim3(1), dim3(kBT), 0, s, dct.p, dsub.p, A.p, work.p,
+                       schur.p, rchunk.p, err.p);
+    HIF_CHECK(hipGetLastError());
+    check_err("root factorization");
+  }
+  nvals_actual += tri64(nroot);
+  const int64_t root_base = total_chunk;
+  total_chunk += tri64(nroot);
+
+  // ---- final layout: descriptors and indices on the host, values converted on the device
+  FactorDev& f = hd.f;
+  f.store = store;
+  f.lv.clear();
+  f.lv.resize(outs.size());
+  std::vector<int32_t> idx;
+  int64_t cbmax = 0;
+  for (size_t l = 0; l < outs.size(); ++l) {
+    LevelOut& lo = outs[l];
+    LevelDev& ld = f.lv[l];
+    for (size_t c = 0; c < lo.cells.size(); ++c) {
+      CellDesc& d = lo.cells[c];
+      d.offV = (int32_t)(lo.base + d.offV);
+      d.offI = (int32_t)idx.size();
+      idx.insert(idx.end(), lo.cellI[c].begin(), lo.cellI[c].end());
+      d.offB = (int32_t)idx.size();
+      idx.insert(idx.end(), lo.cellB[c].begin(), lo.cellB[c].end());
+    }
+    for (size_t q = 0; q < lo.groups.size(); ++q) {
+      GroupDesc& d = lo.groups[q];
+      d.offV = (int32_t)(lo.base + d.offV);
+      d.offIdx = (int32_t)idx.size();
+      idx.insert(idx.end(), lo.gids[q].begin(), lo.gids[q].end());
+      d.offPerm = (int32_t)idx.size();
+      idx.insert(idx.end(), lo.gperm[q].begin(), lo.gperm[q].end());
+      d.offGP = (int32_t)idx.size();
+      idx.insert(idx.end(), lo.gslots_ptr[q].begin(), lo.gslots_ptr[q].end());
+      idx.insert(idx.end(), lo.gslots[q].begin(), lo.gslots[q].end());
+    }
+    ld.ncell = (int)lo.cells.size();
+    ld.ngroup = (int)lo.groups.size();
+    ld.maxI = lo.maxI;
+    ld.maxB = lo.maxB;
+    ld.maxG = lo.maxG;
+    ld.maxK = lo.maxK;
+    ld.maxR = lo.maxR;
+    ld.cells.upload(lo.cells, s);
+    ld.groups.upload(lo.groups, s);
+    cbmax = std::max(cbmax, lo.cbn);
+  }
+  f.nroot = nroot;
+  f.offRootIdx = (int32_t)idx.size();
+  idx.insert(idx.end(), P.groups[rg].dofs.begin(), P.groups[rg].dofs.end());
+  f.offRootV = root_base;
+  HIF_REQUIRE(total_chunk < (int64_t)INT32_MAX && idx.size() < (size_t)INT32_MAX, HIF_ERR_ARG,
+              "factor too large for 32-bit offsets");
+  f.idx.upload(idx, s);
+  f.nvals = nvals_actual;
+  const size_t eb = store_elem_bytes(store);
+  f.vals.alloc(std::max<int64_t>(1, total_chunk) * eb);
+  auto convert = [&](const double* src, int64_t base, int64_t n) {
+    if (n == 0) return;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    if (store == HIF_STORE_F64)
+      hipLaunchKernelGGL(k_to_store_f64, dim3(blocks), dim3(256), 0, s, src,
+                         reinterpret_cast<double*>(f.vals.p) + base, n);
+    else if (store == HIF_STORE_F32)
+      hipLaunchKernelGGL(k_to_store_f32, dim3(blocks), dim3(256), 0, s, src,
+                         reinterpret_cast<float*>(f.vals.p) + base, n);
+    else
+      hipLaunchKernelGGL(k_to_store_bf16, dim3(blocks), dim3(256), 0, s, src,
+                         reinterpret_cast<bf16_t*>(f.vals.p) + base, n);
+  };
+  for (size_t l = 0; l < outs.size(); ++l) {
+    const int64_t n = (l + 1 < outs.size() ? outs[l + 1].base : root_base) - outs[l].base;
+    convert(chunks[l].p, outs[l].base, n);
+  }
+  convert(rchunk.p, root_base, tri64(nroot));
+  HIF_CHECK(hipGetLastError());
+  f.cb.alloc(std::max<int64_t>(1, cbmax));
+  size_t worst = 0;
+  apply_smem_need(f, &worst);
+  f.smem_max = worst;
+  HIF_REQUIRE(worst <= 160 * 1024, HIF_ERR_ARG, "factor blocks too large for the apply kernels");
+  if (worst > 64 * 1024) set_apply_smem_limits(worst);
+  HIF_CHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace hifcn

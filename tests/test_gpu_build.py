@@ -1,0 +1,113 @@
+"""GPU factor build (hif_factor) against the oracle.
+
+eps = 0 makes the method exact (no compression: F = A), so the GPU apply must reproduce A^-1
+and PCG must converge in one iteration.  For eps > 0 the skeleton choice of each ID is one of
+several valid results; the build is compared through what is unique: u after CN steps solved
+to rtol 1e-12 (1e-10 relative), the iteration counts (+-1), the symmetry of F^-1, and the
+preconditioner quality relative to the oracle's own factor.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import cn, fd, phif
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+TINY = [("2d-n15-m4", 15, 2, 4), ("2d-n32-m8", 32, 2, 8), ("2d-n40-m4", 40, 2, 4),
+        ("3d-n8-m4", 8, 3, 4), ("3d-n12-m4", 12, 3, 4), ("2d-n10-root", 10, 2, 8)]
+
+
+def _factor(a, dt, n, dim, leaf, eps, store="f64"):
+    import torch
+    from paper_2004_05566_amd import hifcn
+    a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
+    return hifcn.factor(a_dev, dt, n, dim, eps, store=store, leaf=leaf)
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_eps_zero_gpu_factor_is_exact_inverse(case, gpu_lib):
+    import torch
+    name, n, dim, leaf = case
+    print(f"[case] {name}", flush=True)
+    a = gen.iid_loguniform_cells(n, dim, 3)
+    dt = 0.05
+    A, B = fd.cn_matrices(a, dt)
+    h = _factor(a, dt, n, dim, leaf, 0.0)
+    rng = np.random.default_rng(4)
+    r = rng.normal(size=A.shape[0])
+    z = h.apply(torch.tensor(r, device="cuda")).cpu().numpy()
+    exact = spla.spsolve(A.tocsc(), r)
+    assert np.linalg.norm(z - exact) <= 1e-10 * np.linalg.norm(exact)
+    u = torch.tensor(rng.normal(size=A.shape[0]), device="cuda")
+    its, _ = h.cn_solve(u, 2, rtol=1e-12)
+    assert list(its) == [1, 1]
+
+
+@pytest.mark.parametrize("case", TINY[:5], ids=[c[0] for c in TINY[:5]])
+@pytest.mark.parametrize("eps", [1e-6, 1e-3])
+def test_gpu_factor_cn_matches_oracle(case, eps, gpu_lib):
+    import torch
+    name, n, dim, leaf = case
+    print(f"[case] {name} eps={eps}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.15, 11)
+    dt = 0.05
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, dim, leaf, eps)
+    u0 = gen.bumps(n, dim, 3, 12)
+    react = (1, 1.0, 1.0)
+    us, its, _ = cn.cn_solve(A, B, u0, dt, 3, lambda r: phif.phif_apply(F, r), 1e-12, react)
+    h = _factor(a, dt, n, dim, leaf, eps)
+    u = torch.tensor(u0.ravel(), device="cuda")
+    gits, grel = h.cn_solve(u, 3, rtol=1e-12, reaction=react)
+    assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])
+    assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)
+    # F^-1 symmetric: x.F^-1 y = y.F^-1 x
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=A.shape[0])
+    y = rng.normal(size=A.shape[0])
+    Fx = h.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    Fy = h.apply(torch.tensor(y, device="cuda")).cpu().numpy()
+    assert abs(y @ Fx - x @ Fy) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(Fy)
+    # preconditioner quality comparable to the oracle's factor: ||r - A F^-1 r|| / ||r||
+    g_err = np.linalg.norm(x - A @ Fx) / np.linalg.norm(x)
+    o_err = np.linalg.norm(x - A @ phif.phif_apply(F, x)) / np.linalg.norm(x)
+    assert g_err <= 10 * o_err + 1e-12, (g_err, o_err)
+    info = h.info()
+    assert info["levels"] == len(F.levels)
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_reduced_storage_cn(store, gpu_lib):
+    import torch
+    n, dim, leaf, eps, dt = 64, 2, 8, 1e-4, 0.01
+    a = gen.grf_coefficient(n, dim, 0.1, 21)
+    u0 = gen.bumps(n, dim, 5, 22)
+    react = (1, 1.0, 1.0)
+    A, B = fd.cn_matrices(a, dt)
+    lu = spla.splu(A.tocsc())
+    ref = u0.ravel().copy()
+    for _ in range(3):
+        ref = lu.solve(cn.cn_rhs(B, ref, dt, react))
+    h64 = _factor(a, dt, n, dim, leaf, eps, "f64")
+    u64 = torch.tensor(u0.ravel(), device="cuda")
+    it64, _ = h64.cn_solve(u64, 3, rtol=1e-12, reaction=react)
+    h = _factor(a, dt, n, dim, leaf, eps, store)
+    u = torch.tensor(u0.ravel(), device="cuda")
+    its, _ = h.cn_solve(u, 3, rtol=1e-12, reaction=react)
+    err = np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-10
+    if store == "f32":
+        assert max(its) <= max(it64) + 1
+    assert h.factor_bytes() * (2 if store == "f32" else 4) == h64.factor_bytes()
+
+
+def test_not_spd_is_reported(gpu_lib):
+    import torch
+    from paper_2004_05566_amd import hifcn
+    n = 16
+    a = -np.ones((n + 1, n + 1))          # a < 0 with a large dt makes A indefinite
+    with pytest.raises(hifcn.HifError) as ei:
+        _factor(a, 10.0, n, 2, 4, 1e-6)
+    assert ei.value.status == hifcn.HIF_ERR_NOT_SPD
