@@ -1,0 +1,267 @@
+"""Benchmark: HIF-preconditioned Crank-Nicolson steps per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fisher2d-256] [--store f32]
+
+One timed "step" is one Crank-Nicolson step of the whole hot path: the right-hand side
+(I + dt/2 M) u + dt r(u), then PCG to rtol 1e-8 with the HIF preconditioner (every CG
+iteration: fused direction update + SpMV, vector update, HIF apply, r.z).  The factor is
+built once before timing (its time is reported as t_factor_s).  Inputs are synthetic and
+resident in HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+STAGES = ["cell_fwd", "group_fwd", "root", "group_bwd", "cell_bwd"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "cell_stage_level0_pmc.json")
+APPLY_SRC = os.path.join(ROOT, "paper_2004_05566_amd", "csrc", "apply.hip")
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _time_cn(h, u0, steps, warmup, rtol, reaction):
+    import torch
+    u = u0.clone()
+    if warmup:
+        h.cn_solve(u, warmup, rtol=rtol, reaction=reaction)
+    _sync()
+    t0 = time.perf_counter()
+    its, rel = h.cn_solve(u, steps, rtol=rtol, reaction=reaction)
+    _sync()
+    dt = time.perf_counter() - t0
+    return dt, its, rel, u
+
+
+def _time_op(fn, reps):
+    import torch
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        fn()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def _src_sha() -> str:
+    import hashlib
+    return hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()[:16]
+
+
+def pmc_traffic(kernel: str, store: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, scaled by
+    the counters of a plain copy of known size; None if absent or if the kernel source changed
+    since the counters were taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    d = json.load(open(PMC_SUMMARY))
+    if d.get("apply_src_sha") != _src_sha():
+        return None
+    k = d.get("kernels", {}).get(f"{workload}/{store}/{kernel}")
+    if not k:
+        return None
+    return (k["fetch_kib"] * 1024 * d["copy_scale_fetch"]
+            + k["write_kib"] * 1024 * d["copy_scale_write"])
+
+
+def stage_breakdown(h, x, y, levels, reps=20):
+    """HIP-event time and algorithmic bytes of every apply stage (apply loop, no early exits)."""
+    out = []
+    for lev in range(levels + 1):
+        for st in STAGES:
+            if (st == "root") != (lev == levels):
+                continue
+            h.profile_stage(lev, st, True)
+            for _ in range(reps):
+                h.apply(x, out=y)
+            p = h.profile_read()
+            h.profile_stage(lev, st, False)
+            if p["launches"]:
+                us = 1e3 * p["ms"] / p["launches"]
+                out.append({"level": lev, "stage": st, "us": us, "bytes": p["bytes"],
+                            "GB/s": p["bytes"] / us / 1e3})
+    return out
+
+
+def copy_probe(nbytes: int):
+    """A plain device copy of known size (calibrates the HBM byte counters)."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}))
+
+
+def cpu_baseline(w, budget_steps: int):
+    """The FP64 oracle on the same workload: factor build, then `budget_steps` CN steps."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cn, fd, phif
+    with threadpool_limits(limits=1):
+        A, B = fd.cn_matrices(w.a_cells, w.dt)
+        t0 = time.perf_counter()
+        F = phif.phif_build(A, w.n, w.dim, w.leaf, w.eps)
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, its, _ = cn.cn_solve(A, B, w.u0, w.dt, budget_steps,
+                                lambda r: phif.phif_apply(F, r), 1e-8, w.reaction)
+        ts = time.perf_counter() - t0
+    return {"value": budget_steps / ts, "unit": "CN steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: oracle PHIF build ({tf:.1f} s, untimed in value) then "
+                      f"{budget_steps} CN steps at rtol 1e-8, mean n_i {np.mean(its):.2f}",
+            "t_factor_s": tf}
+
+
+def reference_error(w, u_gpu, nsteps):
+    """Relative error of the GPU u against the FP64 sparse direct solution of the same steps."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+
+    from oracle import cn, fd
+    A, B = fd.cn_matrices(w.a_cells, w.dt)
+    lu = spla.splu(A.tocsc())
+    u = w.u0.ravel().copy()
+    for _ in range(nsteps):
+        u = lu.solve(cn.cn_rhs(B, u, w.dt, w.reaction))
+    return float(np.linalg.norm(u_gpu - u) / np.linalg.norm(u))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="fisher2d-256")
+    ap.add_argument("--store", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-check", action="store_true", help="skip the error check")
+    ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain copy of this many bytes (counter calibration)")
+    args = ap.parse_args(argv)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return 0
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2004_05566_amd import hifcn
+    from workloads import gen
+
+    w = gen.workload(args.workload)
+    dev = torch.device("cuda:0")
+    a_dev = torch.tensor(w.a_cells, dtype=torch.float64, device=dev)
+    u0 = torch.tensor(w.u0.ravel(), dtype=torch.float64, device=dev)
+    react = w.reaction
+
+    _sync()
+    t0 = time.perf_counter()
+    h = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store=args.store, leaf=w.leaf)
+    _sync()
+    t_factor = time.perf_counter() - t0
+
+    elapsed, its, rel, u = _time_cn(h, u0, args.steps, args.warmup, args.rtol, react)
+    value = args.steps / elapsed
+
+    # dominant kernel: the level-0 cell stages, timed live with HIP events on the stream they
+    # run on, over a second pass of the same timed steps
+    roof = {}
+    for st in ("cell_fwd", "cell_bwd"):
+        h.profile_stage(0, st, True)
+        _time_cn(h, u0, args.steps, 0, args.rtol, react)
+        p = h.profile_read()
+        h.profile_stage(0, st, False)
+        roof[st] = p
+    dom = max(roof, key=lambda k: roof[k]["ms"])
+    pd = roof[dom]
+    avg_s = pd["ms"] / 1e3 / max(1, pd["launches"])
+    achieved = pd["bytes"] / avg_s / 1e9
+    kname = {"cell_fwd": "k_cell_fwd", "cell_bwd": "k_cell_bwd"}[dom]
+    traffic = pmc_traffic(kname, args.store, w.name)
+
+    # FP64-stored factor, same workload (the metric compares both forms)
+    h64 = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store="f64", leaf=w.leaf)
+    el64, its64, _, _ = _time_cn(h64, u0, args.steps, args.warmup, args.rtol, react)
+
+    # apply and SpMV bandwidth (algorithmic bytes: factor read twice + FP64 vector in/out)
+    x = torch.randn(w.N, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    t_apply = _time_op(lambda: h.apply(x, out=y), 50)
+    fb = h.factor_bytes()
+    apply_bytes = 2 * fb + 16 * w.N
+    t_spmv = _time_op(lambda: h.spmv(x, out=y), 200)
+    spmv_bytes = (8 + 8 + 8 * w.dim) * w.N
+    stages = None if args.no_stages else stage_breakdown(h, x, y, h.info()["levels"])
+
+    err = None
+    if not args.no_check:
+        err = reference_error(w, u.cpu().numpy(), args.warmup + args.steps)
+
+    out = {
+        "metric": "CN steps/s at 1e-8 rel. resid (FP32-HIF vs FP64), HIF-apply GB/s",
+        "value": value,
+        "unit": "CN steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f64 CG / f32 HIF storage", "bf16": "f64 CG / bf16 HIF storage",
+                  "f64": "f64"}[args.store],
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "dim": w.dim, "n": w.n, "eps": w.eps,
+                   "dt": w.dt, "leaf": w.leaf, "store": args.store, "rtol": args.rtol,
+                   "reaction": list(react)},
+        "n_i_mean": float(np.mean(its)),
+        "f64_store": {"value": args.steps / el64, "n_i_mean": float(np.mean(its64))},
+        "t_factor_s": t_factor,
+        "factor_bytes": fb,
+        "apply": {"us": t_apply * 1e6, "GB/s": apply_bytes / t_apply / 1e9,
+                  "bytes": apply_bytes},
+        "spmv": {"us": t_spmv * 1e6, "GB/s": spmv_bytes / t_spmv / 1e9, "bytes": spmv_bytes},
+        "rel_err_vs_direct": err,
+        "roofline": {"bound": "hbm", "kernel": f"{kname} (level 0, {dom})",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": pd["bytes"],
+                     "avg_us": avg_s * 1e6, "launches": pd["launches"],
+                     "other_level0_stage_us": {k: 1e3 * v["ms"] / max(1, v["launches"])
+                                               for k, v in roof.items()}},
+        "apply_stages": stages,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, 10)
+    h.close()
+    h64.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

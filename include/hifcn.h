@@ -123,6 +123,26 @@ typedef struct {
 } hif_info_t;
 hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
 
+/* Timing of one stage of hif_apply with HIP events recorded around its launches on the stream
+ * they run on (for bandwidth accounting).  Stages of level l (0 <= l < levels): 0 cell forward
+ * (E_l^T), 1 group forward (C_l^T K_l^T), 3 group backward (K_l C_l), 4 cell backward (E_l);
+ * stage 2 is the root solve (level = levels).  Launches that returned at once because PCG had
+ * already converged are not counted. */
+typedef struct {
+  int32_t level;
+  int32_t stage;
+  int64_t launches;  /* launches timed since hif_profile_stage(..., enable = 1) */
+  double ms;         /* their total elapsed time */
+  int64_t bytes;     /* algorithmic bytes one launch moves: factor blocks in the storage
+                        precision + FP64 vector and contribution traffic + int32 indices */
+} hif_stage_prof_t;
+
+/* Start (enable != 0: counters reset) or stop timing the launches of (level, stage). */
+hif_status_t hif_profile_stage(hif_handle_t h, int32_t level, int32_t stage, int32_t enable);
+
+/* Totals of the timed stage so far; synchronises the device. */
+hif_status_t hif_profile_read(hif_handle_t h, hif_stage_prof_t* out);
+
 /* Releases every device allocation of the handle (synchronises the device first). */
 void hif_destroy(hif_handle_t h);
 

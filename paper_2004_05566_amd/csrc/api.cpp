@@ -7,7 +7,6 @@
 namespace hifcn {
 
 void gpu_build(Handle& h, const double* a_cells, hif_store_t store, hipStream_t s);
-void launch_cg_copy_rz(Handle& h, hipStream_t s);
 int vec_blocks(int64_t N);
 
 Handle::~Handle() {
@@ -74,10 +73,8 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   h->p0.alloc(h->N);
   h->p1.alloc(h->N);
   h->q.alloc(h->N);
-  h->partials.alloc(h->nblk);
+  h->partials.alloc((size_t)h->nblk * cg_partial_slots());
   h->st.alloc(1);
-  h->counter.alloc(1);
-  HIF_CHECK(hipMemsetAsync(h->counter.p, 0, sizeof(uint32_t), s));
   HIF_CHECK(hipMemsetAsync(h->st.p, 0, sizeof(CgState), s));
   h->step_iters.alloc(1);
   h->step_relres.alloc(1);
@@ -91,30 +88,46 @@ void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, dou
                  hipStream_t s) {
   const int kind = r ? r->kind : 0;
   const double k1 = r ? r->k1 : 0, k2 = r ? r->k2 : 1;
-  launch_cg_rhs(h, u, kind, k1, k2, o->rtol, o->maxit, s);
+  launch_cg_rhs(h, u, kind, k1, k2, o->maxit, s);
   const int* done = &h.st.p->done;
-  launch_cg_copy_rz(h, s);
+  launch_cg_check_copy(h, -1, o->rtol, s);
   hif_apply_inplace(h.f, h.z.p, done, s);
-  launch_cg_dot_rz(h, s);
-  int launched = 0;
+  launch_cg_dot_rz(h, 0, s);
+  // Queue iterations without waiting, up to the predicted count; the predicted last iteration
+  // stops after its convergence test, so a converged step leaves no dead apply behind.
+  int launched = 0;        // iterations whose update has been queued
+  bool tail_open = false;  // the last queued iteration still owes its apply + r.z
   int chunk = std::max(1, h.last_iters);
-  while (true) {
-    for (int c = 0; c < chunk && launched < o->maxit; ++c, ++launched) {
-      double* pin = (launched & 1) ? h.p1.p : h.p0.p;
-      double* pout = (launched & 1) ? h.p0.p : h.p1.p;
-      launch_cg_dir_spmv(h, pin, pout, s);
-      launch_cg_update(h, pout, s);
-      launch_cg_copy_rz(h, s);
-      hif_apply_inplace(h.f, h.z.p, done, s);
-      launch_cg_dot_rz(h, s);
-    }
+  auto read_flags = [&] {
     HIF_CHECK(hipGetLastError());
     // [iters, done, status] are adjacent in CgState
     HIF_CHECK(hipMemcpyAsync(h.host_flag, &h.st.p->iters, 3 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
     HIF_CHECK(hipStreamSynchronize(s));
-    if (h.host_flag[1] || launched >= o->maxit) break;
-    chunk = 1;
+    return h.host_flag[1] != 0;
+  };
+  while (true) {
+    if (tail_open) {  // the previous chunk's last iteration did not converge
+      hif_apply_inplace(h.f, h.z.p, done, s);
+      launch_cg_dot_rz(h, launched, s);
+      tail_open = false;
+    }
+    for (int c = 0; c < chunk && launched < o->maxit; ++c) {
+      const int it = launched++;
+      double* pin = (it & 1) ? h.p1.p : h.p0.p;
+      double* pout = (it & 1) ? h.p0.p : h.p1.p;
+      launch_cg_dir_spmv(h, it, pin, pout, s);
+      launch_cg_update(h, it, pout, s);
+      launch_cg_check_copy(h, it, o->rtol, s);
+      if (c + 1 == chunk || launched == o->maxit) {
+        tail_open = true;
+        break;
+      }
+      hif_apply_inplace(h.f, h.z.p, done, s);
+      launch_cg_dot_rz(h, it + 1, s);
+    }
+    if (read_flags() || launched >= o->maxit) break;
+    chunk = 2;
   }
   h.last_iters = h.host_flag[0];
   launch_cg_finish(h, u, step, s);
@@ -246,6 +259,66 @@ hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
     info->N = h.N;
     info->store = (int32_t)h.f.store;
     info->dim = h.dim;
+  });
+}
+
+hif_status_t hif_profile_stage(hif_handle_t hh, int32_t level, int32_t stage, int32_t enable) {
+  return guarded([&] {
+    HIF_REQUIRE(hh, HIF_ERR_ARG, "NULL handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    HIF_REQUIRE(stage >= 0 && stage <= 4, HIF_ERR_ARG, "stage must be 0..4");
+    HIF_REQUIRE(level >= 0 && level <= (int)h.f.lv.size(), HIF_ERR_ARG, "level out of range");
+    if (!h.f.prof) h.f.prof = std::make_unique<StageProfiler>();
+    StageProfiler& p = *h.f.prof;
+    HIF_CHECK(hipDeviceSynchronize());
+    p.enabled = enable != 0;
+    if (p.enabled) {
+      p.level = level;
+      p.stage = stage;
+      p.launches = 0;
+      p.ms = 0;
+      p.pending.clear();
+      p.used = 0;
+      if (p.live.n < 4096) p.live.alloc(4096);
+    }
+  });
+}
+
+hif_status_t hif_profile_read(hif_handle_t hh, hif_stage_prof_t* out) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && out, HIF_ERR_ARG, "NULL argument");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    HIF_REQUIRE(h.f.prof != nullptr, HIF_ERR_ARG, "no stage is being timed");
+    StageProfiler& p = *h.f.prof;
+    HIF_CHECK(hipDeviceSynchronize());
+    std::vector<int32_t> live(p.pending.size(), 1);
+    if (!live.empty())
+      HIF_CHECK(hipMemcpy(live.data(), p.live.p, live.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < p.pending.size(); ++q) {
+      if (!live[q]) continue;  // the kernel returned at once: PCG had already converged
+      float ms = 0;
+      HIF_CHECK(hipEventElapsedTime(&ms, p.pending[q].first, p.pending[q].second));
+      p.ms += ms;
+      ++p.launches;
+    }
+    p.pending.clear();
+    p.used = 0;
+    out->level = p.level;
+    out->stage = p.stage;
+    out->launches = p.launches;
+    out->ms = p.ms;
+    int64_t bytes = 0;
+    if (p.stage == STAGE_ROOT) {
+      bytes = h.f.root_bytes;
+    } else if (p.level < (int)h.f.lv.size()) {
+      const LevelDev& L = h.f.lv[p.level];
+      bytes = p.stage == STAGE_CELL_FWD   ? L.cell_bytes[0]
+              : p.stage == STAGE_CELL_BWD ? L.cell_bytes[1]
+              : p.stage == STAGE_GROUP_FWD ? L.group_bytes[0]
+                                           : L.group_bytes[1];
+    }
+    out->bytes = bytes;
   });
 }
 

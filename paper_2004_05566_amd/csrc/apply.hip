@@ -15,10 +15,15 @@
 //   cell stage  (E_l):           x_I <- L^-T x_I - H^T x_B (gather only).
 //
 // Every block of a stage is independent (the factors are block diagonal up to a permutation,
-// Sec. 2.2), so each stage is one launch with one workgroup per cell or group.  Blocks are
-// staged into LDS with coalesced loads (padded square layouts keep both the row and the column
-// walks free of bank conflicts), converted to the compute type C on the way.  Every kernel
-// returns at once when the device flag `done` is set, so PCG iterations can be queued ahead.
+// Sec. 2.2), so each stage is one launch.  Each block's values are contiguous and 16-byte
+// aligned; a workgroup (or, for small groups, a lane segment of a wavefront) copies its block
+// into LDS with vector loads that are all in flight together, converting to the compute type C,
+// then works from LDS.  Loops that walk a block across rows and across columns start each lane
+// at a skewed position so that lanes hit different LDS banks.  Blocks too large for LDS are read
+// straight from global memory instead.  Every kernel returns at once when the device flag
+// `done` is set, so PCG iterations can be queued ahead.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -27,132 +32,241 @@ namespace hifcn {
 namespace {
 
 constexpr int kRootThreads = 256;
+constexpr size_t kStageBudget = 48 * 1024;   // LDS per workgroup when many are in flight
+constexpr size_t kStageMax = 150 * 1024;     // LDS per workgroup for few, large blocks
 
-__host__ __device__ inline int odd_stride(int n) { return (n & 1) ? n : n + 1; }
+// ---------------------------------------------------------------------- vector staging --
+template <typename S> struct VecOf;
+template <> struct VecOf<float> { using T = float4; static constexpr int W = 4; };
+template <> struct VecOf<double> { using T = double2; static constexpr int W = 2; };
+template <> struct VecOf<bf16_t> { using T = uint4; static constexpr int W = 8; };
 
-// Stage packed column-major lower triangle (order n) into LDS as a row-major square with odd
-// row stride `ld` (entries above the diagonal are left unset and never read).
-template <typename S, typename C>
-__device__ __forceinline__ void stage_tri(C* dst, const S* src, int n, int ld) {
-  int base = 0;
-  for (int j = 0; j < n; ++j) {
-    for (int i = j + (int)threadIdx.x; i < n; i += blockDim.x)
-      dst[i * ld + j] = load_as<C>(src + base + (i - j));
-    base += n - j;
+template <typename C>
+__device__ __forceinline__ void unpack(const float4& v, C* d) {
+  d[0] = (C)v.x; d[1] = (C)v.y; d[2] = (C)v.z; d[3] = (C)v.w;
+}
+template <typename C>
+__device__ __forceinline__ void unpack(const double2& v, C* d) {
+  d[0] = (C)v.x; d[1] = (C)v.y;
+}
+template <typename C>
+__device__ __forceinline__ void unpack(const uint4& v, C* d) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    d[2 * q] = (C)__uint_as_float(w[q] << 16);
+    d[2 * q + 1] = (C)__uint_as_float(w[q] & 0xffff0000u);
   }
 }
 
-// Stage a column-major rows x cols block into LDS, column stride `ld` (ld >= rows).
+// Copy `tot` elements starting at the (16-byte aligned) `src` into LDS `dst`, using `nthr`
+// threads numbered `lt`; four vector loads per thread are issued before any is consumed.
+// `dst` must hold `tot` rounded up to the vector width.
 template <typename S, typename C>
-__device__ __forceinline__ void stage_cols(C* dst, const S* src, int rows, int cols, int ld) {
-  const int tot = rows * cols;
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int j = t / rows, r = t - j * rows;
-    dst[j * ld + r] = load_as<C>(src + t);
+__device__ __forceinline__ void stage_flat(C* dst, const S* src, int tot, int lt, int nthr) {
+  using V = typename VecOf<S>::T;
+  constexpr int W = VecOf<S>::W;
+  const V* sv = reinterpret_cast<const V*>(src);
+  const int nv = (tot + W - 1) / W;
+  for (int b = lt; b < nv; b += 4 * nthr) {
+    V r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = b + u * nthr;
+      if (q < nv) r[u] = sv[q];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = b + u * nthr;
+      if (q < nv) unpack<C>(r[u], dst + q * W);
+    }
   }
 }
 
-// Read-only views of the factor blocks: staged in LDS (ST) or read straight from global memory.
-// Tri: lower triangle of order n, element (i, j), i >= j; packed column-major in global memory,
-//      row-major with odd stride `ld` in LDS.
-// Col: column-major rows x cols block, element (r, c); column stride `ld` in LDS.
+__host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Read-only views of the factor blocks: from LDS (packed layouts, ST) or global memory.
+// Tri: packed column-major lower triangle of order n; Col: column-major rows x cols block.
 template <typename S, typename C, bool ST>
 struct Tri {
   const C* l;
   const S* g;
-  int n, ld;
+  int n;
   __device__ __forceinline__ C operator()(int i, int j) const {
-    if constexpr (ST) return l[i * ld + j];
-    else return load_as<C>(g + colstart(j, n) + (i - j));
+    const int o = colstart(j, n) + (i - j);
+    if constexpr (ST) return l[o];
+    else return load_as<C>(g + o);
   }
 };
 template <typename S, typename C, bool ST>
 struct Col {
   const C* l;
   const S* g;
-  int rows, ld;
+  int rows;
   __device__ __forceinline__ C operator()(int r, int c) const {
-    if constexpr (ST) return l[c * ld + r];
-    else return load_as<C>(g + (int64_t)c * rows + r);
+    const int64_t o = (int64_t)c * rows + r;
+    if constexpr (ST) return l[o];
+    else return load_as<C>(g + o);
   }
 };
 
 // ------------------------------------------------------------------------------ cell stages --
-template <typename S, typename C, bool ST>
+// Sum over the `team` adjacent lanes that share one output (team a power of two <= 64).
+template <typename C>
+__device__ __forceinline__ C team_sum(C v, int team) {
+  for (int off = team >> 1; off > 0; off >>= 1) v += __shfl_down(v, off, team);
+  return v;
+}
+
+// LDS (staged): block (blk_elems) | 3 nI + 2 nB vector elements.  Outputs are computed by teams
+// of `team` lanes splitting the inner dot product.
+//   mode 0 (dense H):  w = L^-1 y_I and c = H y_I as nI + nB independent dot products.
+//   mode 1 (links):    w = L^-1 y_I, v = L^-T w (= A_II^-1 y_I), c_b = A_BI(b, ib_b) v_ib_b.
+template <typename S, typename C, bool ST, int MODE>
 __global__ __launch_bounds__(256) void k_cell_fwd(const CellDesc* __restrict__ cd,
                                                   const int32_t* __restrict__ idx,
                                                   const S* __restrict__ vals,
                                                   double* __restrict__ y, double* __restrict__ cb,
-                                                  const int* __restrict__ done) {
+                                                  const int* __restrict__ done, int blk_elems,
+                                                  int team) {
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const CellDesc d = cd[blockIdx.x];
   const int nI = d.nI, nB = d.nB;
-  const int ldL = odd_stride(nI), ldH = odd_stride(nB);
+  constexpr int mode = MODE;
+  const int tl = tri_count(nI);
   const S* v = vals + d.offV;
-  C* Ls = sm;
-  C* Hs = ST ? Ls + nI * ldL : Ls;
-  C* ys = ST ? Hs + nI * ldH : sm;
-  if constexpr (ST) {
-    stage_tri(Ls, v, nI, ldL);
-    stage_cols(Hs, v + tri_count(nI), nB, nI, ldH);
-  }
-  const Tri<S, C, ST> Li{Ls, v, nI, ldL};
-  const Col<S, C, ST> H{Hs, v + tri_count(nI), nB, ldH};
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)y[idx[d.offI + i]];
+  C* blk = sm;
+  C* ys = ST ? sm + blk_elems : sm;
+  C* ws = ys + nI;
+  C* vs = ws + nI;
+  int* ib = reinterpret_cast<int*>(vs + nI);
+  if constexpr (ST) stage_flat(blk, v, tl + (mode ? nB : nB * nI), threadIdx.x, blockDim.x);
+  const Tri<S, C, ST> Li{blk, v, nI};
+  const Col<S, C, ST> H{blk + tl, v + tl, nB};
+  const int32_t* gI = idx + d.offI;
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)y[gI[i]];
+  if constexpr (MODE == 1)
+    for (int b = threadIdx.x; b < nB; b += blockDim.x) ib[b] = idx[d.offC + b];
   __syncthreads();
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+  const int part = threadIdx.x % team, per = blockDim.x / team;
+  const int nout = mode ? nI : nI + nB;
+  for (int ob = 0; ob < nout; ob += per) {
+    const int o = ob + (int)threadIdx.x / team;
     C acc = 0;
-    for (int j = 0; j <= i; ++j) acc += Li(i, j) * ys[j];
-    y[idx[d.offI + i]] = (double)acc;
+    if (o < nI) {
+      for (int j = part; j <= o; j += team) acc += Li(o, j) * ys[j];
+    } else if (o < nout) {
+      for (int j = part; j < nI; j += team) acc += H(o - nI, j) * ys[j];
+    }
+    acc = team_sum(acc, team);
+    if (part == 0 && o < nout) {
+      if (o < nI) {
+        y[gI[o]] = (double)acc;
+        ws[o] = acc;
+      } else {
+        cb[d.offCB + o - nI] = (double)acc;
+      }
+    }
   }
-  for (int b = threadIdx.x; b < nB; b += blockDim.x) {
-    C acc = 0;
-    for (int j = 0; j < nI; ++j) acc += H(b, j) * ys[j];
-    cb[d.offCB + b] = (double)acc;
+  if constexpr (MODE == 1) {
+    __syncthreads();
+    for (int ob = 0; ob < nI; ob += per) {   // v = L^-T w
+      const int o = ob + (int)threadIdx.x / team;
+      C acc = 0;
+      if (o < nI)
+        for (int j = o + part; j < nI; j += team) acc += Li(j, o) * ws[j];
+      acc = team_sum(acc, team);
+      if (part == 0 && o < nI) vs[o] = acc;
+    }
+    __syncthreads();
+    const S* cw = v + tl;
+    for (int b = threadIdx.x; b < nB; b += blockDim.x)
+      cb[d.offCB + b] = (double)((C)(ST ? blk[tl + b] : load_as<C>(cw + b)) * vs[ib[b]]);
   }
 }
 
-template <typename S, typename C, bool ST>
+//   mode 0: x_I <- L^-T x_I - H^T x_B as nI dot products over [L^-1 column | H column].
+//   mode 1: t = A_IB x_B (one link per boundary DOF), x_I <- L^-T (x_I - L^-1 t).
+template <typename S, typename C, bool ST, int MODE>
 __global__ __launch_bounds__(256) void k_cell_bwd(const CellDesc* __restrict__ cd,
                                                   const int32_t* __restrict__ idx,
                                                   const S* __restrict__ vals,
                                                   double* __restrict__ x,
-                                                  const int* __restrict__ done) {
+                                                  const int* __restrict__ done, int blk_elems,
+                                                  int team) {
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const CellDesc d = cd[blockIdx.x];
   const int nI = d.nI, nB = d.nB;
-  const int ldL = odd_stride(nI), ldH = odd_stride(nB);
+  constexpr int mode = MODE;
+  const int tl = tri_count(nI);
   const S* v = vals + d.offV;
-  C* Ls = sm;
-  C* Hs = ST ? Ls + nI * ldL : Ls;
-  C* xs = ST ? Hs + nI * ldH : sm;
+  C* blk = sm;
+  C* xs = ST ? sm + blk_elems : sm;
   C* xb = xs + nI;
-  if constexpr (ST) {
-    stage_tri(Ls, v, nI, ldL);
-    stage_cols(Hs, v + tri_count(nI), nB, nI, ldH);
-  }
-  const Tri<S, C, ST> Li{Ls, v, nI, ldL};
-  const Col<S, C, ST> H{Hs, v + tri_count(nI), nB, ldH};
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) xs[i] = (C)x[idx[d.offI + i]];
+  C* ts = xb + nB;
+  C* us = ts + nI;
+  int* ib = reinterpret_cast<int*>(us + nI);
+  if constexpr (ST) stage_flat(blk, v, tl + (mode ? nB : nB * nI), threadIdx.x, blockDim.x);
+  const Tri<S, C, ST> Li{blk, v, nI};
+  const Col<S, C, ST> H{blk + tl, v + tl, nB};
+  const int32_t* gI = idx + d.offI;
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) xs[i] = (C)x[gI[i]];
   for (int b = threadIdx.x; b < nB; b += blockDim.x) xb[b] = (C)x[idx[d.offB + b]];
+  if constexpr (MODE == 1)
+    for (int b = threadIdx.x; b < nB; b += blockDim.x) ib[b] = idx[d.offC + b];
   __syncthreads();
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+  const int part = threadIdx.x % team, per = blockDim.x / team;
+  if constexpr (MODE == 0) {
+    for (int ob = 0; ob < nI; ob += per) {
+      const int o = ob + (int)threadIdx.x / team;
+      C acc = 0;
+      if (o < nI) {
+        for (int j = o + part; j < nI; j += team) acc += Li(j, o) * xs[j];
+        for (int b = part; b < nB; b += team) acc -= H(b, o) * xb[b];
+      }
+      acc = team_sum(acc, team);
+      if (part == 0 && o < nI) x[gI[o]] = (double)acc;
+    }
+    return;
+  }
+  const S* cw = v + tl;
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {   // t = A_IB x_B
     C acc = 0;
-    for (int j = i; j < nI; ++j) acc += Li(j, i) * xs[j];
-    C hb = 0;
-    for (int b = 0; b < nB; ++b) hb += H(b, i) * xb[b];
-    x[idx[d.offI + i]] = (double)(acc - hb);
+    for (int b = 0; b < nB; ++b)
+      if (ib[b] == i) acc += (C)(ST ? blk[tl + b] : load_as<C>(cw + b)) * xb[b];
+    ts[i] = acc;
+  }
+  __syncthreads();
+  for (int ob = 0; ob < nI; ob += per) {                 // u = x_I - L^-1 t
+    const int o = ob + (int)threadIdx.x / team;
+    C acc = 0;
+    if (o < nI)
+      for (int j = part; j <= o; j += team) acc += Li(o, j) * ts[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && o < nI) us[o] = xs[o] - acc;
+  }
+  __syncthreads();
+  for (int ob = 0; ob < nI; ob += per) {                 // x_I = L^-T u
+    const int o = ob + (int)threadIdx.x / team;
+    C acc = 0;
+    if (o < nI)
+      for (int j = o + part; j < nI; j += team) acc += Li(j, o) * us[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && o < nI) x[gI[o]] = (double)acc;
   }
 }
 
 // ----------------------------------------------------------------------------- group stages --
-// LDS: Lg (n x ldG), T (nr cols of stride ldT >= k), Ls (nr x ldR) when staged; then vectors.
+// A workgroup handles blockDim/seg groups, `seg` lanes each.  Every phase runs on all lanes
+// (empty loops where a group has nothing to do) so the barriers are uniform.
+// LDS per group (staged): block (blk_elems) then yg/zg (n each) and tv/uv (nr each).
 template <typename S, typename C, bool ST>
-__global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__ gd,
+__global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__ gd, int ngroup,
+                                                   int seg, int per_group, int blk_elems,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ y,
@@ -160,143 +274,133 @@ __global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__
                                                    const int* __restrict__ done) {
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* sm = reinterpret_cast<C*>(smem_raw);
-  const GroupDesc d = gd[blockIdx.x];
+  const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
+  const int gi = blockIdx.x * (blockDim.x / seg) + gsel;
+  GroupDesc d{};
+  if (gi < ngroup) d = gd[gi];
   const int n = d.n, nr = d.nr, k = n - nr;
-  const int ldG = odd_stride(n), ldT = odd_stride(k), ldR = odd_stride(nr);
+  C* base = reinterpret_cast<C*>(smem_raw) + (int64_t)gsel * per_group;
   const S* v = vals + d.offV;
-  const S* vT = v + tri_count(n);
-  const S* vR = vT + (int64_t)k * nr;
-  C* Lgs = sm;
-  C* Tss = ST ? Lgs + n * ldG : sm;
-  C* Lrs = ST ? Tss + nr * ldT : sm;
-  C* yg = ST ? Lrs + nr * ldR : sm;
+  const int tg = tri_count(n), tt = k * nr, tr = tri_count(nr);
+  C* blk = base;
+  C* yg = ST ? base + blk_elems : base;
   C* zg = yg + n;
-  C* tv = zg + n;   // nr
-  C* uv = tv + nr;  // nr
-  if constexpr (ST) {
-    stage_tri(Lgs, v, n, ldG);
-    if (nr > 0) {
-      stage_cols(Tss, vT, k, nr, ldT);
-      stage_tri(Lrs, vR, nr, ldR);
-    }
-  }
-  const Tri<S, C, ST> Lg{Lgs, v, n, ldG};
-  const Col<S, C, ST> T{Tss, vT, k, ldT};
-  const Tri<S, C, ST> Lr{Lrs, vR, nr, ldR};
+  C* tv = zg + n;
+  C* uv = tv + nr;
+  if constexpr (ST) stage_flat(blk, v, tg + tt + tr, lt, seg);
+  const Tri<S, C, ST> Lg{blk, v, n};
+  const Col<S, C, ST> T{blk + tg, v + tg, k};
+  const Tri<S, C, ST> Lr{blk + tg + tt, v + tg + tt, nr};
+  const int32_t* gi_idx = idx + d.offIdx;
   const int32_t* gp = idx + d.offGP;
   const int32_t* slots = gp + n + 1;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double acc = y[idx[d.offIdx + i]];
+  const int32_t* perm = idx + d.offPerm;
+  for (int i = lt; i < n; i += seg) {
+    double acc = y[gi_idx[i]];
     for (int s = gp[i]; s < gp[i + 1]; ++s) acc -= cb[slots[s]];
     yg[i] = (C)acc;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {   // C^T: z = L_g^-1 y_g
+  for (int i = lt; i < n; i += seg) {        // C^T: z = L_g^-1 y_g
     C acc = 0;
     for (int j = 0; j <= i; ++j) acc += Lg(i, j) * yg[j];
     zg[i] = acc;
   }
   __syncthreads();
-  const int32_t* perm = idx + d.offPerm;
-  if (nr > 0) {   // K^T
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {     // y_I~ - T^T y_I^
-      C acc = zg[perm[i]];
-      for (int s = 0; s < k; ++s) acc -= T(s, i) * zg[perm[nr + s]];
-      tv[i] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {     // t = L_s^-1 (...)
-      C acc = 0;
-      for (int j = 0; j <= i; ++j) acc += Lr(i, j) * tv[j];
-      uv[i] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {     // L_s^-T t
-      C acc = 0;
-      for (int j = i; j < nr; ++j) acc += Lr(j, i) * uv[j];
-      tv[i] = acc;
-    }
-    __syncthreads();
-    for (int s = threadIdx.x; s < k; s += blockDim.x) {      // y_I^ += T L_s^-T t
+  // K^T (no-op when nr == 0)
+  for (int i = lt; i < nr; i += seg) {       // y_I~ - T^T y_I^
+    C acc = zg[perm[i]];
+    for (int s = 0; s < k; ++s) acc -= T(s, i) * zg[perm[nr + s]];
+    tv[i] = acc;
+  }
+  __syncthreads();
+  for (int i = lt; i < nr; i += seg) {       // t = L_s^-1 (...)
+    C acc = 0;
+    for (int j = 0; j <= i; ++j) acc += Lr(i, j) * tv[j];
+    uv[i] = acc;
+  }
+  __syncthreads();
+  for (int i = lt; i < nr; i += seg) {       // L_s^-T t
+    C acc = 0;
+    for (int j = i; j < nr; ++j) acc += Lr(j, i) * uv[j];
+    tv[i] = acc;
+  }
+  __syncthreads();
+  if (nr > 0) {
+    for (int s = lt; s < k; s += seg) {      // y_I^ += T L_s^-T t
       C acc = zg[perm[nr + s]];
       for (int i = 0; i < nr; ++i) acc += T(s, i) * tv[i];
-      y[idx[d.offIdx + perm[nr + s]]] = (double)acc;
+      y[gi_idx[perm[nr + s]]] = (double)acc;
     }
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) y[idx[d.offIdx + perm[i]]] = (double)uv[i];
+    for (int i = lt; i < nr; i += seg) y[gi_idx[perm[i]]] = (double)uv[i];
   } else {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[idx[d.offIdx + i]] = (double)zg[i];
+    for (int i = lt; i < n; i += seg) y[gi_idx[i]] = (double)zg[i];
   }
 }
 
 template <typename S, typename C, bool ST>
-__global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__ gd,
+__global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__ gd, int ngroup,
+                                                   int seg, int per_group, int blk_elems,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ x,
                                                    const int* __restrict__ done) {
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* sm = reinterpret_cast<C*>(smem_raw);
-  const GroupDesc d = gd[blockIdx.x];
+  const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
+  const int gi = blockIdx.x * (blockDim.x / seg) + gsel;
+  GroupDesc d{};
+  if (gi < ngroup) d = gd[gi];
   const int n = d.n, nr = d.nr, k = n - nr;
-  const int ldG = odd_stride(n), ldT = odd_stride(k), ldR = odd_stride(nr);
+  C* base = reinterpret_cast<C*>(smem_raw) + (int64_t)gsel * per_group;
   const S* v = vals + d.offV;
-  const S* vT = v + tri_count(n);
-  const S* vR = vT + (int64_t)k * nr;
-  C* Lgs = sm;
-  C* Tss = ST ? Lgs + n * ldG : sm;
-  C* Lrs = ST ? Tss + nr * ldT : sm;
-  C* xg = ST ? Lrs + nr * ldR : sm;
+  const int tg = tri_count(n), tt = k * nr, tr = tri_count(nr);
+  C* blk = base;
+  C* xg = ST ? base + blk_elems : base;
   C* zg = xg + n;
   C* tv = zg + n;
   C* uv = tv + nr;
-  if constexpr (ST) {
-    stage_tri(Lgs, v, n, ldG);
-    if (nr > 0) {
-      stage_cols(Tss, vT, k, nr, ldT);
-      stage_tri(Lrs, vR, nr, ldR);
-    }
-  }
-  const Tri<S, C, ST> Lg{Lgs, v, n, ldG};
-  const Col<S, C, ST> T{Tss, vT, k, ldT};
-  const Tri<S, C, ST> Lr{Lrs, vR, nr, ldR};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) xg[i] = (C)x[idx[d.offIdx + i]];
-  __syncthreads();
+  if constexpr (ST) stage_flat(blk, v, tg + tt + tr, lt, seg);
+  const Tri<S, C, ST> Lg{blk, v, n};
+  const Col<S, C, ST> T{blk + tg, v + tg, k};
+  const Tri<S, C, ST> Lr{blk + tg + tt, v + tg + tt, nr};
+  const int32_t* gi_idx = idx + d.offIdx;
   const int32_t* perm = idx + d.offPerm;
-  if (nr > 0) {   // K
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {     // a = T^T x_I^
-      C acc = 0;
-      for (int s = 0; s < k; ++s) acc += T(s, i) * xg[perm[nr + s]];
-      tv[i] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {     // x_I~ + L_s^-1 a
-      C acc = xg[perm[i]];
-      for (int j = 0; j <= i; ++j) acc += Lr(i, j) * tv[j];
-      uv[i] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {     // u = L_s^-T (...)
-      C acc = 0;
-      for (int j = i; j < nr; ++j) acc += Lr(j, i) * uv[j];
-      tv[i] = acc;
-    }
-    __syncthreads();
-    for (int s = threadIdx.x; s < k; s += blockDim.x) {      // x_I^ -= T u
+  for (int i = lt; i < n; i += seg) xg[i] = (C)x[gi_idx[i]];
+  __syncthreads();
+  for (int i = lt; i < nr; i += seg) {       // a = T^T x_I^
+    C acc = 0;
+    for (int s = 0; s < k; ++s) acc += T(s, i) * xg[perm[nr + s]];
+    tv[i] = acc;
+  }
+  __syncthreads();
+  for (int i = lt; i < nr; i += seg) {       // x_I~ + L_s^-1 a
+    C acc = xg[perm[i]];
+    for (int j = 0; j <= i; ++j) acc += Lr(i, j) * tv[j];
+    uv[i] = acc;
+  }
+  __syncthreads();
+  for (int i = lt; i < nr; i += seg) {       // u = L_s^-T (...)
+    C acc = 0;
+    for (int j = i; j < nr; ++j) acc += Lr(j, i) * uv[j];
+    tv[i] = acc;
+  }
+  __syncthreads();
+  if (nr > 0) {
+    for (int s = lt; s < k; s += seg) {      // x_I^ -= T u
       C acc = xg[perm[nr + s]];
       for (int i = 0; i < nr; ++i) acc -= T(s, i) * tv[i];
       zg[perm[nr + s]] = acc;
     }
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) zg[perm[i]] = tv[i];
+    for (int i = lt; i < nr; i += seg) zg[perm[i]] = tv[i];
   } else {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) zg[i] = xg[i];
+    for (int i = lt; i < n; i += seg) zg[i] = xg[i];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {        // C: x_g = L_g^-T x_g
+  for (int i = lt; i < n; i += seg) {        // C: x_g = L_g^-T x_g
     C acc = 0;
     for (int j = i; j < n; ++j) acc += Lg(j, i) * zg[j];
-    x[idx[d.offIdx + i]] = (double)acc;
+    x[gi_idx[i]] = (double)acc;
   }
 }
 
@@ -328,72 +432,162 @@ __global__ __launch_bounds__(kRootThreads) void k_root(int nr, const int32_t* __
   }
 }
 
+// --------------------------------------------------------------------------- launch plans --
+struct StagePlan {
+  bool staged;
+  int threads;
+  int seg;        // lanes per group (group stages)
+  int per;        // groups per workgroup
+  int blk_elems;  // LDS elements reserved for one block
+  int per_group;  // LDS elements per group (blocks + vectors)
+  size_t smem;    // bytes
+  int grid;
+};
+
+// Cells: one workgroup each.  Few, large cells (upper levels) get 256 lanes and may use most of
+// the LDS; many small cells (level 0) keep the footprint small so that many stay resident.
 template <typename C>
-size_t cell_smem(int maxI, int maxB, bool staged) {
-  const size_t vec = (size_t)maxI + maxB;
-  if (!staged) return sizeof(C) * vec;
-  return sizeof(C) * ((size_t)maxI * odd_stride(maxI) + (size_t)maxI * odd_stride(maxB) + vec);
-}
-template <typename C>
-size_t group_smem(int maxN, int maxK, int maxR, bool staged) {
-  const size_t vec = 2 * (size_t)maxN + 2 * (size_t)maxR;
-  if (!staged) return sizeof(C) * vec;
-  return sizeof(C) * ((size_t)maxN * odd_stride(maxN) + (size_t)maxR * odd_stride(maxK) +
-                      (size_t)maxR * odd_stride(maxR) + vec);
+StagePlan cell_plan(const LevelDev& L) {
+  StagePlan p{};
+  p.blk_elems = round_up(L.maxCV, 8);
+  const size_t vec = 3 * (size_t)L.maxI + 2 * (size_t)L.maxB + 4;
+  const size_t budget = L.ncell >= 2048 ? kStageBudget : kStageMax;
+  p.staged = sizeof(C) * (p.blk_elems + vec) <= budget;
+  const int outs = L.maxI + L.maxB;
+  p.threads = (L.ncell >= 2048 || outs <= 64) ? 64 : (outs <= 128 ? 128 : 256);
+  // lanes per output: spread the dot products over the workgroup
+  int team = 1;
+  while (team < 8 && (team * 2) * L.maxI <= p.threads) team <<= 1;
+  p.seg = team;
+  if (!p.staged) p.blk_elems = 0;
+  p.smem = sizeof(C) * (p.blk_elems + vec);
+  p.grid = L.ncell;
+  return p;
 }
 
-// Blocks are staged in LDS when a level's largest block fits this budget (keeps several
-// workgroups resident per CU); larger blocks are read straight from global memory.
-constexpr size_t kStageBudget = 48 * 1024;
-
 template <typename C>
-bool cell_staged(const LevelDev& L) { return cell_smem<C>(L.maxI, L.maxB, true) <= kStageBudget; }
-template <typename C>
-bool group_staged(const LevelDev& L) {
-  return group_smem<C>(L.maxG, L.maxK, L.maxR, true) <= kStageBudget;
+StagePlan group_plan(const LevelDev& L) {
+  StagePlan p{};
+  int seg = 8;
+  while (seg < L.maxG && seg < 256) seg <<= 1;
+  p.seg = seg;
+  p.threads = std::max(seg, 64);
+  p.per = p.threads / seg;
+  p.blk_elems = round_up(L.maxGV, 8);
+  const int vec = round_up(2 * L.maxG + 2 * L.maxR, 4);
+  p.per_group = p.blk_elems + vec;
+  p.staged = sizeof(C) * (size_t)p.per * p.per_group <= kStageBudget;
+  if (!p.staged) {  // global-memory blocks: one group per workgroup, vectors only in LDS
+    p.seg = p.threads = L.maxG <= 64 ? 64 : (L.maxG <= 128 ? 128 : 256);
+    p.per = 1;
+    p.per_group = vec;
+    p.blk_elems = 0;
+  }
+  p.smem = sizeof(C) * (size_t)p.per * p.per_group;
+  p.grid = (L.ngroup + p.per - 1) / p.per;
+  return p;
 }
 
-int cell_threads(const LevelDev& L, bool st) { return (st && L.maxI <= 64) ? 64 : (L.maxI <= 128 ? 128 : 256); }
-int group_threads(const LevelDev& L) { return L.maxG <= 64 ? 64 : (L.maxG <= 128 ? 128 : 256); }
+// Optional timing of the launches of one (level, stage): the kernel is launched with a start
+// and a stop event that the runtime records around its execution on the same stream.
+// A tiny follow-up kernel records whether the timed launch did work (the early-exit flag cannot
+// change during an apply), so that launches that returned at once are left out of the average.
+__global__ void k_record_live(const int* __restrict__ done, int32_t* __restrict__ live) {
+  if (threadIdx.x == 0) *live = (done && *done) ? 0 : 1;
+}
+
+struct StageTimer {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  StageProfiler* p = nullptr;
+  const int* done;
+  hipStream_t s;
+  StageTimer(StageProfiler* prof, int level, int stage, const int* dn, hipStream_t st)
+      : done(dn), s(st) {
+    if (prof && prof->enabled && prof->level == level && prof->stage == stage) {
+      p = prof;
+      e0 = p->next_event();
+      e1 = p->next_event();
+      p->pending.push_back({e0, e1});
+      if (p->live.n < p->pending.size()) {  // grow (only between timed runs in practice)
+        HIF_CHECK(hipStreamSynchronize(s));
+        DevBuf<int32_t> nl(std::max<size_t>(256, 2 * p->pending.size()));
+        if (p->live.n)
+          HIF_CHECK(hipMemcpy(nl.p, p->live.p, p->live.n * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice));
+        p->live = std::move(nl);
+      }
+    }
+  }
+  ~StageTimer() {
+    if (p)
+      hipLaunchKernelGGL(k_record_live, dim3(1), dim3(64), 0, s, done,
+                         p->live.p + (p->pending.size() - 1));
+  }
+};
+
+template <typename K, typename... Args>
+void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const StageTimer& t,
+            Args... args) {
+  if (t.e0)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)smem, s, t.e0, t.e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, smem, s, args...);
+}
+
+template <typename S, typename C, int MODE>
+void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
+                 const int* done, hipStream_t s, const StageTimer& t) {
+  const StagePlan p = cell_plan<C>(L);
+  if (fwd) {
+    auto k = p.staged ? k_cell_fwd<S, C, true, MODE> : k_cell_fwd<S, C, false, MODE>;
+    launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, L.cells.p, (const int32_t*)f.idx.p,
+           vals, y, f.cb.p, done, p.blk_elems, p.seg);
+  } else {
+    auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
+    launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, L.cells.p, (const int32_t*)f.idx.p,
+           vals, y, done, p.blk_elems, p.seg);
+  }
+}
 
 template <typename S, typename C>
 void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
   const S* vals = reinterpret_cast<const S*>(f.vals.p);
   const int32_t* idx = f.idx.p;
+  StageProfiler* prof = f.prof.get();
   for (size_t l = 0; l < f.lv.size(); ++l) {
     const LevelDev& L = f.lv[l];
     if (L.ncell) {
-      const bool st = cell_staged<C>(L);
-      auto k = st ? k_cell_fwd<S, C, true> : k_cell_fwd<S, C, false>;
-      hipLaunchKernelGGL(k, dim3(L.ncell), dim3(cell_threads(L, st)),
-                         cell_smem<C>(L.maxI, L.maxB, st), s, L.cells.p, idx, vals, y, f.cb.p,
-                         done);
+      const StageTimer t(prof, (int)l, STAGE_CELL_FWD, done, s);
+      if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, done, s, t);
+      else launch_cell<S, C, 0>(f, L, true, vals, y, done, s, t);
     }
     if (L.ngroup) {
-      const bool st = group_staged<C>(L);
-      auto k = st ? k_group_fwd<S, C, true> : k_group_fwd<S, C, false>;
-      hipLaunchKernelGGL(k, dim3(L.ngroup), dim3(group_threads(L)),
-                         group_smem<C>(L.maxG, L.maxK, L.maxR, st), s, L.groups.p, idx, vals, y,
-                         f.cb.p, done);
+      const StageTimer t(prof, (int)l, STAGE_GROUP_FWD, done, s);
+      const StagePlan p = group_plan<C>(L);
+      auto k = p.staged ? k_group_fwd<S, C, true> : k_group_fwd<S, C, false>;
+      launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, (const GroupDesc*)L.groups.p,
+             L.ngroup, p.seg, p.per_group, p.blk_elems, idx, vals, y, (const double*)f.cb.p,
+             done);
     }
   }
-  if (f.nroot)
-    hipLaunchKernelGGL((k_root<S, C>), dim3(1), dim3(kRootThreads), 2 * sizeof(C) * f.nroot, s,
-                       f.nroot, idx + f.offRootIdx, vals + f.offRootV, y, done);
+  if (f.nroot) {
+    const StageTimer t(prof, (int)f.lv.size(), STAGE_ROOT, done, s);
+    launch(k_root<S, C>, dim3(1), dim3(kRootThreads), 2 * sizeof(C) * f.nroot, s, t, f.nroot,
+           idx + f.offRootIdx, vals + f.offRootV, y, done);
+  }
   for (size_t l = f.lv.size(); l-- > 0;) {
     const LevelDev& L = f.lv[l];
     if (L.ngroup) {
-      const bool st = group_staged<C>(L);
-      auto k = st ? k_group_bwd<S, C, true> : k_group_bwd<S, C, false>;
-      hipLaunchKernelGGL(k, dim3(L.ngroup), dim3(group_threads(L)),
-                         group_smem<C>(L.maxG, L.maxK, L.maxR, st), s, L.groups.p, idx, vals, y,
-                         done);
+      const StageTimer t(prof, (int)l, STAGE_GROUP_BWD, done, s);
+      const StagePlan p = group_plan<C>(L);
+      auto k = p.staged ? k_group_bwd<S, C, true> : k_group_bwd<S, C, false>;
+      launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, (const GroupDesc*)L.groups.p,
+             L.ngroup, p.seg, p.per_group, p.blk_elems, idx, vals, y, done);
     }
     if (L.ncell) {
-      const bool st = cell_staged<C>(L);
-      auto k = st ? k_cell_bwd<S, C, true> : k_cell_bwd<S, C, false>;
-      hipLaunchKernelGGL(k, dim3(L.ncell), dim3(cell_threads(L, st)),
-                         cell_smem<C>(L.maxI, L.maxB, st), s, L.cells.p, idx, vals, y, done);
+      const StageTimer t(prof, (int)l, STAGE_CELL_BWD, done, s);
+      if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, done, s, t);
+      else launch_cell<S, C, 0>(f, L, false, vals, y, done, s, t);
     }
   }
   HIF_CHECK(hipGetLastError());
@@ -403,19 +597,18 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
 
 size_t apply_smem_need(const FactorDev& f, size_t* worst) {
   size_t w = 0;
-  const bool f64 = f.store == HIF_STORE_F64;
   for (const LevelDev& L : f.lv) {
     size_t c, g;
-    if (f64) {
-      c = cell_smem<double>(L.maxI, L.maxB, cell_staged<double>(L));
-      g = group_smem<double>(L.maxG, L.maxK, L.maxR, group_staged<double>(L));
+    if (f.store == HIF_STORE_F64) {
+      c = cell_plan<double>(L).smem;
+      g = group_plan<double>(L).smem;
     } else {
-      c = cell_smem<float>(L.maxI, L.maxB, cell_staged<float>(L));
-      g = group_smem<float>(L.maxG, L.maxK, L.maxR, group_staged<float>(L));
+      c = cell_plan<float>(L).smem;
+      g = group_plan<float>(L).smem;
     }
     w = std::max(w, std::max(c, g));
   }
-  w = std::max(w, (size_t)(f64 ? 16 : 8) * f.nroot);
+  w = std::max(w, (size_t)(f.store == HIF_STORE_F64 ? 16 : 8) * f.nroot);
   if (worst) *worst = w;
   return w;
 }
@@ -428,18 +621,22 @@ void hif_apply_inplace(const FactorDev& f, double* y, const int* done, hipStream
   }
 }
 
-}  // namespace hifcn
-
-namespace hifcn {
-
 // Allow the apply kernels to use up to `bytes` of dynamic LDS (gfx950: 160 KiB per CU).
 void set_apply_smem_limits(size_t bytes) {
   const int b = (int)bytes;
 #define HIF_SMEM(K) HIF_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(K),           \
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, b))
 #define HIF_SMEM_ALL(S, C)                                                                    \
-  HIF_SMEM((k_cell_fwd<S, C, false>));                                                        \
-  HIF_SMEM((k_cell_bwd<S, C, false>));                                                        \
+  HIF_SMEM((k_cell_fwd<S, C, false, 0>));                                                     \
+  HIF_SMEM((k_cell_bwd<S, C, false, 0>));                                                     \
+  HIF_SMEM((k_cell_fwd<S, C, true, 0>));                                                      \
+  HIF_SMEM((k_cell_bwd<S, C, true, 0>));                                                      \
+  HIF_SMEM((k_cell_fwd<S, C, false, 1>));                                                     \
+  HIF_SMEM((k_cell_bwd<S, C, false, 1>));                                                     \
+  HIF_SMEM((k_cell_fwd<S, C, true, 1>));                                                      \
+  HIF_SMEM((k_cell_bwd<S, C, true, 1>));                                                      \
+  HIF_SMEM((k_group_fwd<S, C, true>));                                                        \
+  HIF_SMEM((k_group_bwd<S, C, true>));                                                        \
   HIF_SMEM((k_group_fwd<S, C, false>));                                                       \
   HIF_SMEM((k_group_bwd<S, C, false>));                                                       \
   HIF_SMEM((k_root<S, C>))

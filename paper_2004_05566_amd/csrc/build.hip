@@ -18,6 +18,7 @@
 // launches; only ranks and pivot orders come back from the device once per level.
 #include <algorithm>
 #include <cmath>
+#include <unordered_map>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -29,7 +30,11 @@ namespace {
 constexpr int kBT = 256;  // threads per build workgroup
 
 struct SubBlk { int64_t off; int32_t width, pad; };
-struct CellTask { int32_t nI, nB, nsub, offSub; int64_t offAII, offW, offS, offV; };
+struct CellTask {
+  int32_t nI, nB, nsub, offSub;
+  int64_t offAII, offW, offS, offV;
+  int32_t mode, offIb;  // mode 1: keep A_IB(ib_b, b) per boundary DOF instead of H
+};
 struct Contrib { int64_t offS; int32_t ld, r0, c0, pad; };
 struct SchurTask { int64_t dst; int32_t rows, cols, ncontrib, offC; };
 struct GroupTask { int32_t n, pad; int64_t offBlk, offW, offLD, offV; };
@@ -155,6 +160,7 @@ __global__ __launch_bounds__(kBT) void k_fill(const FillTask* __restrict__ tasks
 // ------------------------------------------------------------------- (1) cell elimination --
 __global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict__ tasks,
                                                      const SubBlk* __restrict__ subs,
+                                                     const int32_t* __restrict__ ibl,
                                                      const double* __restrict__ A,
                                                      double* __restrict__ work,
                                                      double* __restrict__ schur,
@@ -176,6 +182,10 @@ __global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict_
   }
   wg_identity(X, nI, nI);
   __syncthreads();
+  double* V = fv + t.offV;
+  if (t.mode)   // the single coupling of each boundary DOF, before G overwrites A_IB
+    for (int b = threadIdx.x; b < nB; b += blockDim.x)
+      V[tri_count(nI) + b] = G[(int64_t)ibl[t.offIb + b] * nB + b];
   wg_potrf(W, nI, nI, err);
   wg_trsm_lower(W, nI, nI, X, nI, nI, true);
   if (nB) wg_trsm_lower(W, nI, nI, G, nB, nB, false);
@@ -187,9 +197,9 @@ __global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict_
     for (int i = 0; i < nI; ++i) acc += G[(int64_t)i * nB + a] * G[(int64_t)i * nB + b];
     schur[t.offS + e] = acc;
   }
-  // apply blocks: packed L^-1, then H = G^T L^-1 column-major (H[j*nB + b])
-  double* V = fv + t.offV;
+  // apply blocks: packed L^-1, then (mode 0) H = G^T L^-1 column-major (H[j*nB + b])
   wg_store_packed(V, X, nI, nI);
+  if (t.mode) return;
   double* H = V + tri_count(nI);
   for (int64_t e = threadIdx.x; e < (int64_t)nB * nI; e += blockDim.x) {
     const int j = (int)(e / nB), b = (int)(e - (int64_t)j * nB);
@@ -495,11 +505,11 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   // Host record of the factor layout (offsets relative to each level's value chunk).
   struct LevelOut {
     std::vector<CellDesc> cells;
-    std::vector<std::vector<int32_t>> cellI, cellB;
+    std::vector<std::vector<int32_t>> cellI, cellB, cellIb;
     std::vector<GroupDesc> groups;
     std::vector<std::vector<int32_t>> gids, gperm, gslots_ptr, gslots;
     int64_t base = 0;
-    int maxI = 0, maxB = 0, maxG = 0, maxK = 0, maxR = 0;
+    int maxI = 0, maxB = 0, maxG = 0, maxK = 0, maxR = 0, maxCV = 0, maxGV = 0;
     int64_t cbn = 0;
   };
   std::vector<LevelOut> outs;
@@ -515,23 +525,47 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     int64_t voff = 0;
     std::vector<int64_t> cell_voff(P.cells.size()), grp_voff(G, -1);
     std::vector<int> cell_nB(P.cells.size());
+    // level 0: A_IB is the stencil, one link per boundary DOF; keep that link instead of H
+    const int cmode = lev == 0 ? 1 : 0;
+    std::vector<std::vector<int32_t>> cell_ib(P.cells.size());
     for (size_t ci = 0; ci < P.cells.size(); ++ci) {
       int nB = 0;
       for (int b : P.cellB[ci]) nB += gsz(b);
       cell_nB[ci] = nB;
+      voff = align_vals(voff);
       cell_voff[ci] = voff;
       const int nI = gsz(P.cells[ci]);
-      voff += tri64(nI) + (int64_t)nB * nI;
+      voff += tri64(nI) + (cmode ? (int64_t)nB : (int64_t)nB * nI);
+      if (cmode) {
+        std::unordered_map<int32_t, int32_t> pos;
+        const std::vector<int32_t>& I = P.groups[P.cells[ci]].dofs;
+        for (int i = 0; i < nI; ++i) pos[I[i]] = i;
+        const int64_t nn = (int64_t)hd.n * hd.n;
+        for (int b : P.cellB[ci])
+          for (int32_t id : P.groups[b].dofs) {
+            int found = -1;
+            const int64_t cand[6] = {id - 1, id + 1, id - hd.n, id + hd.n, id - nn, id + nn};
+            for (int q = 0; q < (hd.dim == 3 ? 6 : 4) && found < 0; ++q) {
+              auto it = pos.find((int32_t)cand[q]);
+              if (it != pos.end()) found = it->second;
+            }
+            HIF_REQUIRE(found >= 0, HIF_ERR_ARG, "internal: boundary DOF without a stencil link");
+            cell_ib[ci].push_back(found);
+          }
+      }
     }
     for (int g : P.seps) {
+      voff = align_vals(voff);
       grp_voff[g] = voff;
       voff += tri64(gsz(g)) * (P.groups[g].kind == 1 ? 2 : 1);
     }
+    voff = align_vals(voff);
     DevBuf<double> fv(std::max<int64_t>(1, voff));
 
     // ---- (1) cell elimination
     std::vector<CellTask> ct(P.cells.size());
     std::vector<SubBlk> subs;
+    std::vector<int32_t> ibl;
     int64_t woff = 0, soff = 0;
     std::vector<int64_t> cell_soff(P.cells.size());
     for (size_t ci = 0; ci < P.cells.size(); ++ci) {
@@ -554,17 +588,22 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       cell_soff[ci] = soff;
       soff += (int64_t)nB * nB;
       t.offV = cell_voff[ci];
+      t.mode = cmode;
+      t.offIb = (int32_t)ibl.size();
+      ibl.insert(ibl.end(), cell_ib[ci].begin(), cell_ib[ci].end());
     }
     {
       DevBuf<CellTask> dct;
       DevBuf<SubBlk> dsub;
+      DevBuf<int32_t> dibl;
       DevBuf<double> work(std::max<int64_t>(1, woff));
       DevBuf<double> schur(std::max<int64_t>(1, soff));
       upload(dct, ct, s);
       upload(dsub, subs, s);
+      upload(dibl, ibl, s);
       if (!ct.empty())
-        hipLaunchKernelGGL(k_build_cells, dim3(ct.size()), dim3(kBT), 0, s, dct.p, dsub.p, A.p,
-                           work.p, schur.p, fv.p, err.p);
+        hipLaunchKernelGGL(k_build_cells, dim3(ct.size()), dim3(kBT), 0, s, dct.p, dsub.p, dibl.p,
+                           A.p, work.p, schur.p, fv.p, err.p);
       HIF_CHECK(hipGetLastError());
       // Schur assembly into every separator block touched by some cell
       std::vector<std::vector<Contrib>> per_block(P.blocks.size());
@@ -645,6 +684,12 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     DevBuf<double> Xbuf;
     std::vector<int64_t> xoff(G, -1);
     {
+      // rows of every edge's ID: the blocks (h, g) of all other separator groups h
+      std::vector<std::vector<int>> rows_of(G);
+      for (size_t b = 0; b < P.blocks.size(); ++b) {
+        const int h = P.blocks[b].first, g = P.blocks[b].second;
+        if (h != g && P.groups[h].kind > 0 && P.groups[g].kind == 1) rows_of[g].push_back((int)b);
+      }
       std::vector<IdTask> it;
       std::vector<SubBlk> rs;
       int64_t wo = 0, xo = 0;
@@ -657,10 +702,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         t.n = n;
         t.offRS = (int32_t)rs.size();
         int m = 0;
-        for (int h : P.seps) {   // every other active group coupled to g
-          if (h == g) continue;
-          const int blk = P.find_block(h, g);
-          if (blk < 0) continue;
+        for (int blk : rows_of[g]) {   // blocks sorted by (h, g): h in group order
+          const int h = P.blocks[blk].first;
           rs.push_back({P.block_off[blk], gsz(h), 0});
           m += gsz(h);
         }
@@ -712,6 +755,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       d.nB = cell_nB[ci];
       d.offV = (int32_t)cell_voff[ci];  // chunk-relative for now
       d.offCB = (int32_t)cbn;
+      d.mode = cmode;
+      lo.cellIb.push_back(cell_ib[ci]);
       cell_cb[ci] = cbn;
       cbn += d.nB;
       lo.cells.push_back(d);
@@ -721,7 +766,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       lo.cellB.push_back(std::move(B));
       lo.maxI = std::max(lo.maxI, d.nI);
       lo.maxB = std::max(lo.maxB, d.nB);
-      nvals_actual += tri64(d.nI) + (int64_t)d.nI * d.nB;
+      const int64_t cv = tri64(d.nI) + (cmode ? (int64_t)d.nB : (int64_t)d.nI * d.nB);
+      lo.maxCV = std::max<int>(lo.maxCV, (int)cv);
+      nvals_actual += cv;
     }
     lo.cbn = cbn;
     // gather map of boundary contributions, in cell order
@@ -769,6 +816,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       lo.maxK = std::max(lo.maxK, n - d.nr);
       const int64_t kk = n - d.nr;
       nvals_actual += tri64(n) + (d.nr ? kk * d.nr + tri64(d.nr) : 0);
+      lo.maxGV = std::max<int>(lo.maxGV, (int)(tri64(n) + kk * d.nr + tri64(d.nr)));
     }
     lo.base = total_chunk;
     total_chunk += voff;
@@ -839,20 +887,21 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   DevBuf<double> rchunk(std::max<int64_t>(1, tri64(nroot)));
   {
     std::vector<CellTask> ct(1);
-    ct[0] = {nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, 0, 0};
+    ct[0] = {nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, 0, 0, 0, 0};
     DevBuf<CellTask> dct;
     DevBuf<SubBlk> dsub(1);
+    DevBuf<int32_t> dibl(1);
     DevBuf<double> work(std::max<int64_t>(1, 2 * (int64_t)nroot * nroot));
     DevBuf<double> schur(1);
     upload(dct, ct, s);
-    hipLaunchKernelGGL(k_build_cells, dim3(1), dim3(kBT), 0, s, dct.p, dsub.p, A.p, work.p,
-                       schur.p, rchunk.p, err.p);
+    hipLaunchKernelGGL(k_build_cells, dim3(1), dim3(kBT), 0, s, dct.p, dsub.p, dibl.p, A.p,
+                       work.p, schur.p, rchunk.p, err.p);
     HIF_CHECK(hipGetLastError());
     check_err("root factorization");
   }
   nvals_actual += tri64(nroot);
   const int64_t root_base = total_chunk;
-  total_chunk += tri64(nroot);
+  total_chunk += align_vals(tri64(nroot));
 
   // ---- final layout: descriptors and indices on the host, values converted on the device
   FactorDev& f = hd.f;
@@ -871,6 +920,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       idx.insert(idx.end(), lo.cellI[c].begin(), lo.cellI[c].end());
       d.offB = (int32_t)idx.size();
       idx.insert(idx.end(), lo.cellB[c].begin(), lo.cellB[c].end());
+      d.offC = (int32_t)idx.size();
+      idx.insert(idx.end(), lo.cellIb[c].begin(), lo.cellIb[c].end());
     }
     for (size_t q = 0; q < lo.groups.size(); ++q) {
       GroupDesc& d = lo.groups[q];
@@ -890,11 +941,20 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     ld.maxG = lo.maxG;
     ld.maxK = lo.maxK;
     ld.maxR = lo.maxR;
+    ld.maxCV = lo.maxCV;
+    ld.maxGV = lo.maxGV;
+    ld.cmode = lo.cells.empty() ? 0 : lo.cells[0].mode;
+    {
+      std::vector<int64_t> nsl(lo.groups.size());
+      for (size_t q = 0; q < lo.groups.size(); ++q) nsl[q] = (int64_t)lo.gslots[q].size();
+      level_stage_bytes(lo.cells, lo.groups, nsl, store_elem_bytes(store), ld);
+    }
     ld.cells.upload(lo.cells, s);
     ld.groups.upload(lo.groups, s);
     cbmax = std::max(cbmax, lo.cbn);
   }
   f.nroot = nroot;
+  f.root_bytes = (int64_t)store_elem_bytes(store) * tri64(nroot) + 20 * (int64_t)nroot;
   f.offRootIdx = (int32_t)idx.size();
   idx.insert(idx.end(), P.groups[rg].dofs.begin(), P.groups[rg].dofs.end());
   f.offRootV = root_base;
@@ -903,7 +963,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   f.idx.upload(idx, s);
   f.nvals = nvals_actual;
   const size_t eb = store_elem_bytes(store);
-  f.vals.alloc(std::max<int64_t>(1, total_chunk) * eb);
+  f.vals.alloc((total_chunk + kValAlign) * eb);
+  HIF_CHECK(hipMemsetAsync(f.vals.p, 0, (total_chunk + kValAlign) * eb, s));
   auto convert = [&](const double* src, int64_t base, int64_t n) {
     if (n == 0) return;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);

@@ -96,9 +96,11 @@ struct CellDesc {
   int32_t nI, nB;      // interior and boundary sizes
   int32_t offI, offB;  // index lists (global DOF ids)
   int32_t offV;        // values: packed column-major lower L^-1 (nI(nI+1)/2), then
-                       //         H = A_BI A_II^-1 column-major (nB x nI, H[j*nB + b])
+                       //   mode 0: H = A_BI A_II^-1 column-major (nB x nI, H[j*nB + b])
+                       //   mode 1: the coupling A_IB(ib_b, b) of each boundary DOF b (nB)
   int32_t offCB;       // first slot of this cell's boundary contributions
-  int32_t pad0, pad1;
+  int32_t mode;        // 0: dense H; 1: A_IB has one entry per column (stencil links, level 0)
+  int32_t offC;        // mode 1: interior position ib_b of each boundary DOF's link (nB)
 };
 
 struct GroupDesc {

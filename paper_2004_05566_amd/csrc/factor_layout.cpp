@@ -65,6 +65,31 @@ void push_packed(std::vector<double>& out, const std::vector<double>& M, int n) 
 
 }  // namespace
 
+void level_stage_bytes(const std::vector<CellDesc>& cells, const std::vector<GroupDesc>& groups,
+                       const std::vector<int64_t>& group_slots, size_t eb, LevelDev& ld) {
+  int64_t cf = 0, cbk = 0, gf = 0, gbk = 0;
+  for (const CellDesc& d : cells) {
+    const int64_t nI = d.nI, nB = d.nB;
+    const int64_t blk = (int64_t)eb * (tri_count(nI) + (d.mode ? nB : nB * nI));
+    const int64_t ib = d.mode ? 4 * nB : 0;
+    cf += blk + 8 * (2 * nI + nB) + 4 * nI + ib + (int64_t)sizeof(CellDesc);
+    cbk += blk + 8 * (2 * nI + nB) + 4 * (nI + nB) + ib + (int64_t)sizeof(CellDesc);
+  }
+  for (size_t q = 0; q < groups.size(); ++q) {
+    const GroupDesc& d = groups[q];
+    const int64_t n = d.n, nr = d.nr, k = n - nr;
+    const int64_t blk = (int64_t)eb * (tri_count(n) + (nr ? k * nr + tri_count(nr) : 0));
+    const int64_t perm = nr ? 4 * n : 0;
+    const int64_t sl = q < group_slots.size() ? group_slots[q] : 0;
+    gf += blk + 16 * n + 12 * sl + 4 * n + 4 * (n + 1) + perm + (int64_t)sizeof(GroupDesc);
+    gbk += blk + 16 * n + 4 * n + perm + (int64_t)sizeof(GroupDesc);
+  }
+  ld.cell_bytes[0] = cf;
+  ld.cell_bytes[1] = cbk;
+  ld.group_bytes[0] = gf;
+  ld.group_bytes[1] = gbk;
+}
+
 FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf) {
   HIF_REQUIRE(blob != nullptr, HIF_ERR_ARG, "NULL blob");
   Reader rd{static_cast<const unsigned char*>(blob), nbytes};
@@ -114,6 +139,7 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
       std::vector<int32_t> Bk;
       for (int b : keep) Bk.push_back(B[b]);
       fh.idx.insert(fh.idx.end(), Bk.begin(), Bk.end());
+      fh.vals.resize(align_vals((int64_t)fh.vals.size()), 0.0);
       d.offV = (int32_t)fh.vals.size();
       push_packed(fh.vals, Li, nI);
       for (int j = 0; j < nI; ++j)      // H[b][j] = sum_i G[i][b] Linv[i][j], column-major
@@ -123,10 +149,12 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
           fh.vals.push_back(s);
         }
       d.offCB = (int32_t)cb;
+      fh.nvals_used += tri_count(nI) + (int64_t)nI * d.nB;
       cellB.push_back({Bk, cb});
       cb += d.nB;
       lh.maxI = std::max(lh.maxI, nI);
       lh.maxB = std::max(lh.maxB, d.nB);
+      lh.maxCV = std::max<int>(lh.maxCV, (int)(tri_count(nI) + (int64_t)d.nB * nI));
       lh.cells.push_back(d);
     }
     fh.cbmax = std::max(fh.cbmax, cb);
@@ -191,6 +219,9 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
       }
     for (int g = 0; g < ngroup; ++g) {
       const int gn = (int)groups[g].ids.size();
+      int64_t nsl = 0;
+      for (int i = 0; i < gn; ++i) nsl += (int64_t)slots[g][i].size();
+      lh.group_slots.push_back(nsl);
       GroupDesc d{};
       d.n = gn;
       d.nr = sk[g].nr;
@@ -209,15 +240,19 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
       }
       for (int i = 0; i < gn; ++i)
         fh.idx.insert(fh.idx.end(), slots[g][i].begin(), slots[g][i].end());
+      fh.vals.resize(align_vals((int64_t)fh.vals.size()), 0.0);
       d.offV = (int32_t)fh.vals.size();
       push_packed(fh.vals, groups[g].Linv, gn);
       if (d.nr) {
         fh.vals.insert(fh.vals.end(), sk[g].T.begin(), sk[g].T.end());
         push_packed(fh.vals, sk[g].Lsinv, d.nr);
       }
+      fh.nvals_used += tri_count(gn) + (int64_t)(gn - d.nr) * d.nr + tri_count(d.nr);
       lh.maxG = std::max(lh.maxG, gn);
       lh.maxR = std::max(lh.maxR, d.nr);
       lh.maxK = std::max(lh.maxK, gn - d.nr);
+      lh.maxGV = std::max<int>(lh.maxGV, (int)(tri_count(gn) + (int64_t)(gn - d.nr) * d.nr +
+                                               tri_count(d.nr)));
       lh.groups.push_back(d);
     }
     fh.lv.push_back(std::move(lh));
@@ -230,8 +265,10 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
   fh.nroot = nroot;
   fh.offRootIdx = (int32_t)fh.idx.size();
   fh.idx.insert(fh.idx.end(), ids.begin(), ids.end());
+  fh.vals.resize(align_vals((int64_t)fh.vals.size()), 0.0);
   fh.offRootV = (int64_t)fh.vals.size();
   if (nroot) push_packed(fh.vals, tri_inverse(Lm, nroot), nroot);
+  fh.nvals_used += tri_count(nroot);
   HIF_REQUIRE(rd.pos == rd.n, HIF_ERR_ARG, "trailing bytes in HIFB blob");
   HIF_REQUIRE(fh.vals.size() < (size_t)INT32_MAX && fh.idx.size() < (size_t)INT32_MAX,
               HIF_ERR_ARG, "factor too large for 32-bit offsets");
@@ -252,13 +289,17 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
     ld.maxG = lh.maxG;
     ld.maxK = lh.maxK;
     ld.maxR = lh.maxR;
+    ld.maxCV = lh.maxCV;
+    ld.maxGV = lh.maxGV;
+    ld.cmode = 0;
+    level_stage_bytes(lh.cells, lh.groups, lh.group_slots, store_elem_bytes(store), ld);
     ld.cells.upload(lh.cells, s);
     ld.groups.upload(lh.groups, s);
   }
   fd.idx.upload(fh.idx, s);
-  fd.nvals = (int64_t)fh.vals.size();
+  fd.nvals = fh.nvals_used;
   const size_t eb = store_elem_bytes(store);
-  std::vector<unsigned char> raw(fh.vals.size() * eb);
+  std::vector<unsigned char> raw((fh.vals.size() + kValAlign) * eb, 0);
   for (size_t i = 0; i < fh.vals.size(); ++i) {
     if (store == HIF_STORE_F64) {
       std::memcpy(&raw[i * 8], &fh.vals[i], 8);
@@ -272,6 +313,7 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
   }
   fd.vals.upload(raw, s);
   fd.nroot = fh.nroot;
+  fd.root_bytes = (int64_t)eb * tri_count(fh.nroot) + 20 * (int64_t)fh.nroot;
   fd.offRootIdx = fh.offRootIdx;
   fd.offRootV = fh.offRootV;
   fd.cb.alloc(std::max<int64_t>(1, fh.cbmax));

@@ -13,8 +13,39 @@ struct LevelDev {
   int ncell = 0, ngroup = 0;
   int maxI = 0, maxB = 0;            // largest cell interior / boundary
   int maxG = 0, maxK = 0, maxR = 0;  // largest group, skeleton and redundant set
+  int maxCV = 0, maxGV = 0;          // largest cell / group value block (elements)
+  int cmode = 0;                     // coupling mode of every cell of the level (CellDesc.mode)
+  int64_t cell_bytes[2] = {0, 0};    // algorithmic bytes per launch: [forward, backward]
+  int64_t group_bytes[2] = {0, 0};
   DevBuf<CellDesc> cells;
   DevBuf<GroupDesc> groups;
+};
+
+// Stages of one apply, as timed by the profiler.
+enum { STAGE_CELL_FWD = 0, STAGE_GROUP_FWD = 1, STAGE_ROOT = 2, STAGE_GROUP_BWD = 3,
+       STAGE_CELL_BWD = 4 };
+
+// HIP-event timing of every launch of one (level, stage) of the apply.
+struct StageProfiler {
+  bool enabled = false;
+  int level = 0, stage = 0;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  DevBuf<int32_t> live;   // per pending launch: 1 if the kernel did work (0: early exit)
+  int64_t launches = 0;
+  double ms = 0;
+  hipEvent_t next_event() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIF_CHECK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~StageProfiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 // The factor in its apply layout: per-level descriptors, one int32 index array and one value
@@ -30,6 +61,8 @@ struct FactorDev {
   int64_t offRootV = 0;    // packed L_r^-1 in vals
   DevBuf<double> cb;       // boundary contributions of the cell stage (max over levels)
   size_t smem_max = 0;
+  int64_t root_bytes = 0;
+  std::unique_ptr<StageProfiler> prof;
 };
 
 // Host-side, FP64 version of the same layout (used by import; the GPU build writes the device
@@ -37,7 +70,8 @@ struct FactorDev {
 struct LevelHost {
   std::vector<CellDesc> cells;
   std::vector<GroupDesc> groups;
-  int maxI = 0, maxB = 0, maxG = 0, maxK = 0, maxR = 0;
+  int maxI = 0, maxB = 0, maxG = 0, maxK = 0, maxR = 0, maxCV = 0, maxGV = 0;
+  std::vector<int64_t> group_slots;  // contributions gathered by each group
 };
 struct FactorHost {
   std::vector<LevelHost> lv;
@@ -47,6 +81,7 @@ struct FactorHost {
   int32_t offRootIdx = 0;
   int64_t offRootV = 0;
   int64_t cbmax = 0;
+  int64_t nvals_used = 0;  // stored values excluding alignment padding
 };
 
 // PCG state kept on the device (scalars of Algorithm 1's pcg).
@@ -69,7 +104,6 @@ struct Handle {
   // PCG workspace
   DevBuf<double> x, r, z, p0, p1, q, partials;
   DevBuf<CgState> st;
-  DevBuf<uint32_t> counter;
   DevBuf<int32_t> step_iters;
   DevBuf<double> step_relres;
   int32_t* host_flag = nullptr;  // pinned: done flag mirror
@@ -79,7 +113,16 @@ struct Handle {
 };
 
 // ---- factor layout ---------------------------------------------------------------------------
+// Every block of values starts at a multiple of kValAlign elements (16-byte aligned in every
+// storage precision) so the apply kernels can stage it with vector loads; the value array is
+// padded by kValAlign elements at its end.
+constexpr int64_t kValAlign = 8;
+inline int64_t align_vals(int64_t off) { return (off + kValAlign - 1) / kValAlign * kValAlign; }
 void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipStream_t s);
+// Algorithmic bytes one launch of each stage of a level moves: factor blocks (storage
+// precision), FP64 vector reads/writes, contributions and int32 indices.
+void level_stage_bytes(const std::vector<CellDesc>& cells, const std::vector<GroupDesc>& groups,
+                       const std::vector<int64_t>& group_slots, size_t eb, LevelDev& ld);
 FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf);
 size_t apply_smem_need(const FactorDev& f, size_t* worst);
 void set_apply_smem_limits(size_t bytes);
@@ -89,11 +132,14 @@ void hif_apply_inplace(const FactorDev& f, double* y, const int* done, hipStream
 void launch_links(const double* a_cells, int dim, int n, double scale, double* links,
                   hipStream_t s);
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
-void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, double rtol,
-                   int maxit, hipStream_t s);
-void launch_cg_dot_rz(Handle& h, hipStream_t s);
-void launch_cg_dir_spmv(Handle& h, const double* pin, double* pout, hipStream_t s);
-void launch_cg_update(Handle& h, const double* p, hipStream_t s);
+// PCG kernels; `it` is the 0-based index of the CG iteration (host-side count).
+int cg_partial_slots();
+void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
+                   hipStream_t s);
+void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s);
+void launch_cg_dot_rz(Handle& h, int it, hipStream_t s);
+void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipStream_t s);
+void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s);
 void launch_cg_finish(Handle& h, double* u, int step, hipStream_t s);
 
 }  // namespace hifcn

@@ -8,8 +8,9 @@
 // host round trip: the direction update p = z + beta p is fused into the SpMV (each lane
 // rebuilds the new direction at its stencil points from z and the previous direction, written
 // to a second buffer), p.q, r.z and ||r||^2 are fused reductions with a deterministic two-level
-// sum (per-block partials, last block adds them in a fixed order), and the convergence test
-// ||r|| <= rtol ||g|| sets a device flag that makes every later kernel of the step return.
+// sum (per-block partials, re-added in a fixed order by the kernel that consumes them), and
+// the convergence test ||r|| <= rtol ||g|| sets a device flag that makes every later kernel of
+// the step return.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -24,42 +25,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic grid-wide sum.  Returns true in the last block to finish, where *total holds
-// the sum (valid in every thread of that block).
-__device__ bool grid_sum(double v, double* partials, uint32_t* counter, double* total) {
+// Per-block partial sums: every reduction kernel writes one partial per block; the kernel that
+// needs the total re-adds all partials in the same fixed order in every block, so the result is
+// deterministic and no inter-block synchronisation (fences, atomics) is needed inside a kernel.
+__device__ double block_sum(double v) {
   __shared__ double red[kThreads / 64];
-  __shared__ int last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   v = wave_sum(v);
+  __syncthreads();
   if (lane == 0) red[wid] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0;
-    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
-    partials[blockIdx.x] = s;
-    __threadfence();
-    const uint32_t prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  return s;
+}
+
+__device__ void put_partial(double v, double* part) {
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ double total(const double* part, int nb) {
   double acc = 0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads)
-    acc += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  acc = wave_sum(acc);
-  __syncthreads();
-  if (lane == 0) red[wid] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0;
-    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
-    red[0] = s;
-    *counter = 0;
-  }
-  __syncthreads();
-  *total = red[0];
-  return true;
+  for (int i = threadIdx.x; i < nb; i += kThreads) acc += part[i];
+  return block_sum(acc);
 }
 
 // Sum over links of w (p_j - p_nbr) at node i.  P(k) returns the value at node k.
@@ -157,14 +147,16 @@ __device__ __forceinline__ double react(double u, int kind, double k1, double k2
   return kind == 1 ? k1 * u * (1.0 - u / k2) : 0.0;
 }
 
-// g = (I + dt/2 M) u + dt r(u) -> r; x = 0; ||g||^2 and the PCG scalars are reset.
+// Partial-sum slots (each nblk long): ||g||^2, p.q, ||r||^2, r.z for even / odd iterations.
+enum { P_GG = 0, P_PQ = 1, P_RR = 2, P_RZ0 = 3 };
+
+// g = (I + dt/2 M) u + dt r(u) -> r; x = 0; partials of ||g||^2.
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const double* __restrict__ w,
                                                      const double* __restrict__ u,
                                                      double* __restrict__ r, double* __restrict__ x,
                                                      int kind, double k1, double k2, double dt,
-                                                     double rtol, int maxit, CgState* st,
-                                                     double* partials, uint32_t* counter) {
+                                                     int maxit, CgState* st, double* part) {
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
@@ -175,54 +167,88 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
     x[i] = 0.0;
     acc += g * g;
   }
-  double tot;
-  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) {
-    st->gg = tot;
-    st->tol2 = rtol * rtol * tot;
-    st->rr = tot;
-    st->rz = 0;
-    st->rz_new = 0;
-    st->pq = 0;
+  put_partial(acc, part + P_GG * (int64_t)gridDim.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->iters = 0;
     st->status = 0;
+    st->done = 0;
     st->maxit = maxit;
-    st->done = (tot == 0.0) ? 1 : 0;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_copy_if(int64_t N, const double* __restrict__ src,
-                                                      double* __restrict__ dst,
-                                                      const CgState* st) {
+// Convergence test, then z = r if the iteration goes on.  init: ||g||^2 is finalised (g = 0
+// ends the solve at once); otherwise ||r||^2 of the update just made is finalised and the
+// iteration count advanced.  Block 0 publishes the scalars; every block reaches the same verdict.
+// `it` is the 0-based index of the iteration whose update was just made (ignored for init);
+// it comes from the host so that no block reads a scalar that block 0 rewrites in this launch.
+__global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init, int it0,
+                                                            double rtol,
+                                                            const double* __restrict__ r,
+                                                            double* __restrict__ z, CgState* st,
+                                                            const double* __restrict__ part) {
   if (st->done) return;
+  const int nb = gridDim.x;
+  bool stop;
+  if (init) {
+    const double gg = total(part + P_GG * (int64_t)nb, nb);
+    stop = !(gg > 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->gg = gg;
+      st->tol2 = rtol * rtol * gg;
+      st->rr = gg;
+      st->done = stop ? 1 : 0;
+    }
+  } else {
+    const double rr = total(part + P_RR * (int64_t)nb, nb);
+    const int it = it0 + 1;
+    const bool bad = !(rr == rr) || rr > 1.7e308;
+    const bool conv = !bad && rr <= st->tol2;
+    const bool cap = !bad && !conv && it >= st->maxit;
+    stop = bad || conv || cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->rr = rr;
+      st->iters = it;
+      st->done = stop ? 1 : 0;
+      st->status = (bad || cap) ? HIF_ERR_NO_CONV : 0;
+    }
+  }
+  if (stop) return;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads)
-    dst[i] = src[i];
+    z[i] = r[i];
 }
 
-__global__ __launch_bounds__(kThreads) void k_cg_dot_rz(int64_t N, const double* __restrict__ r,
-                                                        const double* __restrict__ z, CgState* st,
-                                                        double* partials, uint32_t* counter) {
+// r.z for the direction of iteration `it` (slot it & 1).
+__global__ __launch_bounds__(kThreads) void k_cg_dot_rz(int64_t N, int it,
+                                                        const double* __restrict__ r,
+                                                        const double* __restrict__ z,
+                                                        const CgState* st, double* part) {
   if (st->done) return;
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads)
     acc += r[i] * z[i];
-  double tot;
-  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) st->rz_new = tot;
+  put_partial(acc, part + (P_RZ0 + (it & 1)) * (int64_t)gridDim.x);
 }
 
-// p_out = z + beta p_in (beta = 0 on the first iteration), q = A p_out, p_out.q.
+// p_out = z + beta p_in (beta = 0 on the first iteration), q = A p_out, partials of p_out.q.
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N,
+__global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N, int it,
                                                           const double* __restrict__ w,
                                                           const double* __restrict__ z,
                                                           const double* __restrict__ pin,
                                                           double* __restrict__ pout,
-                                                          double* __restrict__ q, CgState* st,
-                                                          double* partials, uint32_t* counter) {
+                                                          double* __restrict__ q,
+                                                          const CgState* st, double* part) {
   if (st->done) return;
-  const bool first = st->iters == 0;
-  const double beta = first ? 0.0 : st->rz_new / st->rz;
+  const int nb = gridDim.x;
+  const bool first = it == 0;
+  double beta = 0.0;
+  if (!first) {
+    const double rz = total(part + (P_RZ0 + (it & 1)) * (int64_t)nb, nb);
+    const double rz_prev = total(part + (P_RZ0 + ((it + 1) & 1)) * (int64_t)nb, nb);
+    beta = rz / rz_prev;
+  }
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
@@ -233,21 +259,21 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N,
     q[i] = qi;
     acc += pi * qi;
   }
-  double tot;
-  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) {
-    st->pq = tot;
-    st->rz = st->rz_new;
-  }
+  put_partial(acc, part + P_PQ * (int64_t)nb);
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; ||r||^2; convergence / failure flags.
-__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, const double* __restrict__ p,
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; partials of ||r||^2.
+__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
+                                                        const double* __restrict__ p,
                                                         const double* __restrict__ q,
                                                         double* __restrict__ x,
-                                                        double* __restrict__ r, CgState* st,
-                                                        double* partials, uint32_t* counter) {
+                                                        double* __restrict__ r, const CgState* st,
+                                                        double* part) {
   if (st->done) return;
-  const double alpha = st->rz / st->pq;
+  const int nb = gridDim.x;
+  const double rz = total(part + (P_RZ0 + (it & 1)) * (int64_t)nb, nb);
+  const double pq = total(part + P_PQ * (int64_t)nb, nb);
+  const double alpha = rz / pq;
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
@@ -256,20 +282,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, const double*
     r[i] = ri;
     acc += ri * ri;
   }
-  double tot;
-  if (grid_sum(acc, partials, counter, &tot) && threadIdx.x == 0) {
-    st->rr = tot;
-    st->iters += 1;
-    if (!(tot == tot) || tot > 1.7e308) {
-      st->status = HIF_ERR_NO_CONV;
-      st->done = 1;
-    } else if (tot <= st->tol2) {
-      st->done = 1;
-    } else if (st->iters >= st->maxit) {
-      st->status = HIF_ERR_NO_CONV;
-      st->done = 1;
-    }
-  }
+  put_partial(acc, part + P_RR * (int64_t)nb);
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg_finish(int64_t N, const double* __restrict__ x,
@@ -288,8 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_finish(int64_t N, const double*
 
 int vec_blocks(int64_t N) {
   int64_t b = (N + kThreads - 1) / kThreads;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 512));
 }
+
+int cg_partial_slots() { return P_RZ0 + 2; }
 
 void launch_links(const double* a_cells, int dim, int n, double scale, double* links,
                   hipStream_t s) {
@@ -301,41 +316,40 @@ void launch_links(const double* a_cells, int dim, int n, double scale, double* l
 }
 
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
+  const int nb = (int)std::min<int64_t>((h.N + kThreads - 1) / kThreads, 4096);
   if (h.dim == 2)
-    hipLaunchKernelGGL(k_spmv<2>, dim3(vec_blocks(h.N)), dim3(kThreads), 0, s, h.n, h.N,
-                       h.links.p, x, y);
+    hipLaunchKernelGGL(k_spmv<2>, dim3(nb), dim3(kThreads), 0, s, h.n, h.N, h.links.p, x, y);
   else
-    hipLaunchKernelGGL(k_spmv<3>, dim3(vec_blocks(h.N)), dim3(kThreads), 0, s, h.n, h.N,
-                       h.links.p, x, y);
+    hipLaunchKernelGGL(k_spmv<3>, dim3(nb), dim3(kThreads), 0, s, h.n, h.N, h.links.p, x, y);
   HIF_CHECK(hipGetLastError());
 }
 
-void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, double rtol,
-                   int maxit, hipStream_t s) {
+void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
+                   hipStream_t s) {
   auto k = h.dim == 2 ? k_cg_rhs<2> : k_cg_rhs<3>;
   hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, u, h.r.p, h.x.p,
-                     kind, k1, k2, h.dt, rtol, maxit, h.st.p, h.partials.p, h.counter.p);
-  HIF_CHECK(hipGetLastError());
+                     kind, k1, k2, h.dt, maxit, h.st.p, h.partials.p);
 }
 
-void launch_cg_copy_rz(Handle& h, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_if, dim3(h.nblk), dim3(kThreads), 0, s, h.N, h.r.p, h.z.p, h.st.p);
+void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it < 0 ? 1 : 0, it,
+                     rtol, h.r.p, h.z.p, h.st.p, h.partials.p);
 }
 
-void launch_cg_dot_rz(Handle& h, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dot_rz, dim3(h.nblk), dim3(kThreads), 0, s, h.N, h.r.p, h.z.p, h.st.p,
-                     h.partials.p, h.counter.p);
+void launch_cg_dot_rz(Handle& h, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dot_rz, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, h.r.p, h.z.p,
+                     h.st.p, h.partials.p);
 }
 
-void launch_cg_dir_spmv(Handle& h, const double* pin, double* pout, hipStream_t s) {
+void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipStream_t s) {
   auto k = h.dim == 2 ? k_cg_dir_spmv<2> : k_cg_dir_spmv<3>;
-  hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, h.z.p, pin, pout,
-                     h.q.p, h.st.p, h.partials.p, h.counter.p);
+  hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, it, h.links.p, h.z.p, pin,
+                     pout, h.q.p, h.st.p, h.partials.p);
 }
 
-void launch_cg_update(Handle& h, const double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, p, h.q.p, h.x.p, h.r.p,
-                     h.st.p, h.partials.p, h.counter.p);
+void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, p, h.q.p, h.x.p,
+                     h.r.p, h.st.p, h.partials.p);
 }
 
 void launch_cg_finish(Handle& h, double* u, int step, hipStream_t s) {

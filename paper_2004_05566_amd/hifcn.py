@@ -45,6 +45,13 @@ class _Info(ctypes.Structure):
                 ("N", ctypes.c_int64), ("store", ctypes.c_int32), ("dim", ctypes.c_int32)]
 
 
+class _StageProf(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("stage", ctypes.c_int32),
+                ("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_int64)]
+
+
+STAGES = {"cell_fwd": 0, "group_fwd": 1, "root": 2, "group_bwd": 3, "cell_bwd": 4}
+
 _vp = ctypes.c_void_p
 _lib.hif_factor.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), ctypes.c_double,
                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]
@@ -59,15 +66,18 @@ _lib.cn_solve.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts
 _lib.hif_factor_bytes.argtypes = [_vp]
 _lib.hif_factor_bytes.restype = ctypes.c_size_t
 _lib.hif_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
+_lib.hif_profile_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+_lib.hif_profile_read.argtypes = [_vp, ctypes.POINTER(_StageProf)]
 _lib.hif_destroy.argtypes = [_vp]
 _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
 for _f in ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
-           "hif_get_info"):
+           "hif_get_info", "hif_profile_stage", "hif_profile_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
-           "hif_factor_bytes", "hif_get_info", "hif_destroy", "hif_last_error")
+           "hif_factor_bytes", "hif_get_info", "hif_profile_stage", "hif_profile_read",
+           "hif_destroy", "hif_last_error")
 
 
 def _check(status: int):
@@ -149,6 +159,16 @@ class Handle:
         _check(_lib.cn_step(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u"),
                             ctypes.byref(it), ctypes.byref(rel), _stream(stream)))
         return it.value, rel.value
+
+    def profile_stage(self, level: int, stage: str, enable: bool = True):
+        """Time (with HIP events) every launch of one apply stage from now on."""
+        _check(_lib.hif_profile_stage(self._p(), int(level), STAGES[stage], int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        p = _StageProf()
+        _check(_lib.hif_profile_read(self._p(), ctypes.byref(p)))
+        return {"level": p.level, "stage": p.stage, "launches": p.launches, "ms": p.ms,
+                "bytes": p.bytes}
 
     def factor_bytes(self) -> int:
         return int(_lib.hif_factor_bytes(self._p()))

@@ -111,3 +111,23 @@ def test_not_spd_is_reported(gpu_lib):
     with pytest.raises(hifcn.HifError) as ei:
         _factor(a, 10.0, n, 2, 4, 1e-6)
     assert ei.value.status == hifcn.HIF_ERR_NOT_SPD
+
+
+def test_stage_profiler_counts_launches(gpu_lib):
+    import torch
+    n, dim, leaf, eps, dt = 32, 2, 8, 1e-6, 0.01
+    a = gen.grf_coefficient(n, dim, 0.1, 31)
+    h = _factor(a, dt, n, dim, leaf, eps, "f32")
+    x = torch.randn(n * n, dtype=torch.float64, device="cuda")
+    h.profile_stage(0, "cell_fwd", True)
+    for _ in range(5):
+        h.apply(x)
+    p = h.profile_read()
+    assert p["launches"] == 5 and p["ms"] > 0 and p["bytes"] > h.factor_bytes() // 10
+    # while a stage is timed, every timed apply inside cn_solve does real work
+    h.profile_stage(0, "cell_bwd", True)
+    u = torch.tensor(gen.bumps(n, dim, 3, 2).ravel(), device="cuda")
+    its, _ = h.cn_solve(u, 2, rtol=1e-10)
+    p = h.profile_read()
+    assert p["launches"] == int(sum(its))   # one live apply per iteration that goes on + the first
+    h.profile_stage(0, "cell_bwd", False)
