@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const CellDesc* __restrict__ c
 // LDS per group (staged): block (blk_elems) then yg/zg (n each) and tv/uv (nr each).
 template <typename S, typename C, bool ST>
 __global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__ gd, int ngroup,
-                                                   int seg, int per_group, int blk_elems,
+                                                   int seg, int per_group, int blk_elems, int team,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ y,
@@ -307,11 +307,15 @@ __global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__
     zg[i] = acc;
   }
   __syncthreads();
-  // K^T (no-op when nr == 0)
-  for (int i = lt; i < nr; i += seg) {       // y_I~ - T^T y_I^
-    C acc = zg[perm[i]];
-    for (int s = 0; s < k; ++s) acc -= T(s, i) * zg[perm[nr + s]];
-    tv[i] = acc;
+  // K^T (no-op when nr == 0).  Column walks (T(., i), L(., i)) are split over `team` lanes.
+  const int part = lt % team, per_t = seg / team;
+  for (int ob = 0; ob < nr; ob += per_t) {   // y_I~ - T^T y_I^
+    const int i = ob + lt / team;
+    C acc = 0;
+    if (i < nr)
+      for (int s = part; s < k; s += team) acc += T(s, i) * zg[perm[nr + s]];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < nr) tv[i] = zg[perm[i]] - acc;
   }
   __syncthreads();
   for (int i = lt; i < nr; i += seg) {       // t = L_s^-1 (...)
@@ -320,10 +324,13 @@ __global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__
     uv[i] = acc;
   }
   __syncthreads();
-  for (int i = lt; i < nr; i += seg) {       // L_s^-T t
+  for (int ob = 0; ob < nr; ob += per_t) {   // L_s^-T t
+    const int i = ob + lt / team;
     C acc = 0;
-    for (int j = i; j < nr; ++j) acc += Lr(j, i) * uv[j];
-    tv[i] = acc;
+    if (i < nr)
+      for (int j = i + part; j < nr; j += team) acc += Lr(j, i) * uv[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < nr) tv[i] = acc;
   }
   __syncthreads();
   if (nr > 0) {
@@ -340,7 +347,7 @@ __global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__
 
 template <typename S, typename C, bool ST>
 __global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__ gd, int ngroup,
-                                                   int seg, int per_group, int blk_elems,
+                                                   int seg, int per_group, int blk_elems, int team,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ x,
@@ -368,10 +375,14 @@ __global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__
   const int32_t* perm = idx + d.offPerm;
   for (int i = lt; i < n; i += seg) xg[i] = (C)x[gi_idx[i]];
   __syncthreads();
-  for (int i = lt; i < nr; i += seg) {       // a = T^T x_I^
+  const int part = lt % team, per_t = seg / team;
+  for (int ob = 0; ob < nr; ob += per_t) {   // a = T^T x_I^
+    const int i = ob + lt / team;
     C acc = 0;
-    for (int s = 0; s < k; ++s) acc += T(s, i) * xg[perm[nr + s]];
-    tv[i] = acc;
+    if (i < nr)
+      for (int s = part; s < k; s += team) acc += T(s, i) * xg[perm[nr + s]];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < nr) tv[i] = acc;
   }
   __syncthreads();
   for (int i = lt; i < nr; i += seg) {       // x_I~ + L_s^-1 a
@@ -380,10 +391,13 @@ __global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__
     uv[i] = acc;
   }
   __syncthreads();
-  for (int i = lt; i < nr; i += seg) {       // u = L_s^-T (...)
+  for (int ob = 0; ob < nr; ob += per_t) {   // u = L_s^-T (...)
+    const int i = ob + lt / team;
     C acc = 0;
-    for (int j = i; j < nr; ++j) acc += Lr(j, i) * uv[j];
-    tv[i] = acc;
+    if (i < nr)
+      for (int j = i + part; j < nr; j += team) acc += Lr(j, i) * uv[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < nr) tv[i] = acc;
   }
   __syncthreads();
   if (nr > 0) {
@@ -397,10 +411,13 @@ __global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__
     for (int i = lt; i < n; i += seg) zg[i] = xg[i];
   }
   __syncthreads();
-  for (int i = lt; i < n; i += seg) {        // C: x_g = L_g^-T x_g
+  for (int ob = 0; ob < n; ob += per_t) {    // C: x_g = L_g^-T x_g
+    const int i = ob + lt / team;
     C acc = 0;
-    for (int j = i; j < n; ++j) acc += Lg(j, i) * zg[j];
-    x[gi_idx[i]] = (double)acc;
+    if (i < n)
+      for (int j = i + part; j < n; j += team) acc += Lg(j, i) * zg[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < n) x[gi_idx[i]] = (double)acc;
   }
 }
 
@@ -432,6 +449,170 @@ __global__ __launch_bounds__(kRootThreads) void k_root(int nr, const int32_t* __
   }
 }
 
+// -------------------------------------------------------------------------- tiled cells --
+// Cells whose blocks do not fit one workgroup's LDS are spread over many workgroups.  The
+// forward sweep writes the new interior values into a scratch vector (not into y), so that
+// every tile of a cell still reads the old y_I; the backward sweep reads them back from there
+// and writes the final interior values into y.
+//   row tiles:    64 consecutive rows of [L^-1; H] (packed columns are contiguous over rows,
+//                 so each load of a wavefront is coalesced); the four wavefronts of the
+//                 workgroup take every fourth column and add up through LDS.
+//   column tiles: 16 consecutive columns; each wavefront reduces whole columns (contiguous in
+//                 memory) for four outputs.
+constexpr int kRowTile = 64;
+constexpr int kColTile = 16;
+
+template <typename S, typename C, int MODE>
+__global__ __launch_bounds__(256) void k_tfwd_rows(const CellDesc* __restrict__ cd,
+                                                   const int4* __restrict__ tiles,
+                                                   const int32_t* __restrict__ idx,
+                                                   const S* __restrict__ vals,
+                                                   const double* __restrict__ y,
+                                                   double* __restrict__ wsc,
+                                                   double* __restrict__ cb,
+                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* ys = reinterpret_cast<C*>(smem_raw);
+  __shared__ C red[4][kRowTile];
+  const int4 t = tiles[blockIdx.x];
+  const CellDesc d = cd[t.x];
+  const int nI = d.nI, nB = d.nB;
+  const int nrows = MODE ? nI : nI + nB;
+  const int r0 = t.y;
+  const int rmax = min(nrows, r0 + kRowTile);
+  const int jmax = min(nI, rmax);  // columns needed by these rows
+  const int32_t* gI = idx + d.offI;
+  for (int j = threadIdx.x; j < (MODE ? jmax : nI); j += blockDim.x) ys[j] = (C)y[gI[j]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = r0 + lane;
+  const S* v = vals + d.offV;
+  const int tl = tri_count(nI);
+  C acc = 0;
+  if (r < nI) {
+    for (int j = wave; j <= r; j += 4) acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ys[j];
+  } else if (r < nrows) {
+    const S* H = v + tl + (r - nI);
+    for (int j = wave; j < nI; j += 4) acc += load_as<C>(H + (int64_t)j * nB) * ys[j];
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && r < nrows) {
+    const C tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    if (r < nI) wsc[t.z + r] = (double)tot;
+    else cb[d.offCB + r - nI] = (double)tot;
+  }
+}
+
+__device__ __forceinline__ double wave_reduce(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_reduce(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Column tiles.  KIND 0 (backward, dense H): x_i = L^-T w - H^T x_B -> y.
+//                KIND 1 (backward, links):   x_i = L^-T u -> y.
+//                KIND 2 (forward, links):    v_i = L^-T w;  c_b = A_BI(b, ib_b) v_ib_b -> cb.
+template <typename S, typename C, int KIND>
+__global__ __launch_bounds__(256) void k_tcols(const CellDesc* __restrict__ cd,
+                                               const int4* __restrict__ tiles,
+                                               const int32_t* __restrict__ idx,
+                                               const S* __restrict__ vals,
+                                               double* __restrict__ y,
+                                               const double* __restrict__ wsc,
+                                               double* __restrict__ cb,
+                                               const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* xs = reinterpret_cast<C*>(smem_raw);
+  __shared__ C vt[kColTile];
+  const int4 t = tiles[blockIdx.x];
+  const CellDesc d = cd[t.x];
+  const int nI = d.nI, nB = KIND == 0 ? d.nB : 0;
+  C* xb = xs + nI;
+  const int c0 = t.y;
+  for (int j = c0 + (int)threadIdx.x; j < nI; j += blockDim.x) xs[j] = (C)wsc[t.z + j];
+  for (int b = threadIdx.x; b < nB; b += blockDim.x) xb[b] = (C)y[idx[d.offB + b]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const S* v = vals + d.offV;
+  const int tl = tri_count(nI);
+  for (int q = wave; q < kColTile; q += 4) {
+    const int i = c0 + q;
+    if (i >= nI) break;
+    const S* col = v + colstart(i, nI);
+    C acc = 0;
+    for (int j = i + lane; j < nI; j += 64) acc += load_as<C>(col + (j - i)) * xs[j];
+    if constexpr (KIND == 0) {
+      const S* hc = v + tl + (int64_t)i * d.nB;
+      for (int b = lane; b < nB; b += 64) acc -= load_as<C>(hc + b) * xb[b];
+    }
+    acc = wave_reduce(acc);
+    if (lane == 0) {
+      if constexpr (KIND == 2) vt[q] = acc;
+      else y[idx[d.offI + i]] = (double)acc;
+    }
+  }
+  if constexpr (KIND == 2) {
+    __syncthreads();
+    const int32_t* ib = idx + d.offC;
+    const S* cw = v + tl;
+    for (int b = threadIdx.x; b < d.nB; b += blockDim.x) {
+      const int i = ib[b];
+      if (i >= c0 && i < c0 + kColTile) cb[d.offCB + b] = (double)(load_as<C>(cw + b) * vt[i - c0]);
+    }
+  }
+}
+
+// Backward, links: t = A_IB x_B (per interior DOF, its links in a fixed order), then
+// u_r = w_r - (L^-1 t)_r over a row tile, in place in the scratch vector.
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_tbwd_rows1(const CellDesc* __restrict__ cd,
+                                                    const int4* __restrict__ tiles,
+                                                    const int32_t* __restrict__ idx,
+                                                    const S* __restrict__ vals,
+                                                    const double* __restrict__ y,
+                                                    double* __restrict__ wsc,
+                                                    const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* ts = reinterpret_cast<C*>(smem_raw);
+  __shared__ C red[4][kRowTile];
+  const int4 t = tiles[blockIdx.x];
+  const CellDesc d = cd[t.x];
+  const int nI = d.nI, nB = d.nB;
+  const int r0 = t.y;
+  const int rmax = min(nI, r0 + kRowTile);
+  const S* v = vals + d.offV;
+  const int tl = tri_count(nI);
+  // idx layout after offC: ib[nB], rowptr[nI + 1], blist[nB] (links grouped by interior DOF)
+  const int32_t* rp = idx + d.offC + nB;
+  const int32_t* bl = rp + nI + 1;
+  const int32_t* gB = idx + d.offB;
+  for (int j = threadIdx.x; j < rmax; j += blockDim.x) {
+    C acc = 0;
+    for (int q = rp[j]; q < rp[j + 1]; ++q) {
+      const int b = bl[q];
+      acc += load_as<C>(v + tl + b) * (C)y[gB[b]];
+    }
+    ts[j] = acc;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = r0 + lane;
+  C acc = 0;
+  if (r < nI)
+    for (int j = wave; j <= r; j += 4) acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ts[j];
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && r < nI)
+    wsc[t.z + r] -= (double)(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
+}
+
 // --------------------------------------------------------------------------- launch plans --
 struct StagePlan {
   bool staged;
@@ -442,6 +623,7 @@ struct StagePlan {
   int per_group;  // LDS elements per group (blocks + vectors)
   size_t smem;    // bytes
   int grid;
+  int team;       // lanes sharing one column walk (group stages)
 };
 
 // Cells: one workgroup each.  Few, large cells (upper levels) get 256 lanes and may use most of
@@ -485,6 +667,8 @@ StagePlan group_plan(const LevelDev& L) {
   }
   p.smem = sizeof(C) * (size_t)p.per * p.per_group;
   p.grid = (L.ngroup + p.per - 1) / p.per;
+  // column walks: lanes of one group read a column together when it is in global memory
+  p.team = p.staged ? 1 : 64;
   return p;
 }
 
@@ -501,6 +685,7 @@ struct StageTimer {
   StageProfiler* p = nullptr;
   const int* done;
   hipStream_t s;
+  StageTimer() : done(nullptr), s(nullptr) {}
   StageTimer(StageProfiler* prof, int level, int stage, const int* dn, hipStream_t st)
       : done(dn), s(st) {
     if (prof && prof->enabled && prof->level == level && prof->stage == stage) {
@@ -550,6 +735,41 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
 }
 
 template <typename S, typename C>
+void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
+                  const int* done, hipStream_t s, const StageTimer& t) {
+  const int32_t* idx = f.idx.p;
+  const size_t rows_smem = sizeof(C) * (size_t)std::max(1, L.maxI);
+  const size_t cols_smem = sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB);
+  if (fwd) {
+    if (L.cmode) {
+      launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(256), rows_smem, s, t,
+             (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
+             f.wsc.p, f.cb.p, done);
+      launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(256), cols_smem, s, StageTimer(),
+             (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
+             (const double*)f.wsc.p, f.cb.p, done);
+    } else {
+      launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(256), rows_smem, s, t,
+             (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
+             f.wsc.p, f.cb.p, done);
+    }
+  } else {
+    if (L.cmode) {
+      launch(k_tbwd_rows1<S, C>, dim3(L.nrt), dim3(256), rows_smem, s, t,
+             (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
+             f.wsc.p, done);
+      launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(256), cols_smem, s, StageTimer(),
+             (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
+             (const double*)f.wsc.p, f.cb.p, done);
+    } else {
+      launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(256), cols_smem, s, t,
+             (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
+             (const double*)f.wsc.p, f.cb.p, done);
+    }
+  }
+}
+
+template <typename S, typename C>
 void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
   const S* vals = reinterpret_cast<const S*>(f.vals.p);
   const int32_t* idx = f.idx.p;
@@ -558,7 +778,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     const LevelDev& L = f.lv[l];
     if (L.ncell) {
       const StageTimer t(prof, (int)l, STAGE_CELL_FWD, done, s);
-      if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, done, s, t);
+      if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, done, s, t);
+      else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, done, s, t);
       else launch_cell<S, C, 0>(f, L, true, vals, y, done, s, t);
     }
     if (L.ngroup) {
@@ -566,14 +787,19 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       const StagePlan p = group_plan<C>(L);
       auto k = p.staged ? k_group_fwd<S, C, true> : k_group_fwd<S, C, false>;
       launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, (const GroupDesc*)L.groups.p,
-             L.ngroup, p.seg, p.per_group, p.blk_elems, idx, vals, y, (const double*)f.cb.p,
-             done);
+             L.ngroup, p.seg, p.per_group, p.blk_elems, p.team, idx, vals, y,
+             (const double*)f.cb.p, done);
     }
   }
   if (f.nroot) {
     const StageTimer t(prof, (int)f.lv.size(), STAGE_ROOT, done, s);
-    launch(k_root<S, C>, dim3(1), dim3(kRootThreads), 2 * sizeof(C) * f.nroot, s, t, f.nroot,
-           idx + f.offRootIdx, vals + f.offRootV, y, done);
+    if (f.root_tiled) {  // y_r = L^-T (L^-1 y_r) as a row pass then a column pass
+      launch_tiled<S, C>(f, f.rootlv, true, vals, y, done, s, t);
+      launch_tiled<S, C>(f, f.rootlv, false, vals, y, done, s, StageTimer());
+    } else {
+      launch(k_root<S, C>, dim3(1), dim3(kRootThreads), 2 * sizeof(C) * f.nroot, s, t, f.nroot,
+             idx + f.offRootIdx, vals + f.offRootV, y, done);
+    }
   }
   for (size_t l = f.lv.size(); l-- > 0;) {
     const LevelDev& L = f.lv[l];
@@ -582,11 +808,12 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       const StagePlan p = group_plan<C>(L);
       auto k = p.staged ? k_group_bwd<S, C, true> : k_group_bwd<S, C, false>;
       launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, (const GroupDesc*)L.groups.p,
-             L.ngroup, p.seg, p.per_group, p.blk_elems, idx, vals, y, done);
+             L.ngroup, p.seg, p.per_group, p.blk_elems, p.team, idx, vals, y, done);
     }
     if (L.ncell) {
       const StageTimer t(prof, (int)l, STAGE_CELL_BWD, done, s);
-      if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, done, s, t);
+      if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, done, s, t);
+      else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, done, s, t);
       else launch_cell<S, C, 0>(f, L, false, vals, y, done, s, t);
     }
   }
@@ -597,6 +824,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
 
 size_t apply_smem_need(const FactorDev& f, size_t* worst) {
   size_t w = 0;
+  const size_t cs = f.store == HIF_STORE_F64 ? 8 : 4;
   for (const LevelDev& L : f.lv) {
     size_t c, g;
     if (f.store == HIF_STORE_F64) {
@@ -606,9 +834,10 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst) {
       c = cell_plan<float>(L).smem;
       g = group_plan<float>(L).smem;
     }
+    if (L.tiled) c = cs * (size_t)(L.maxI + L.maxB);
     w = std::max(w, std::max(c, g));
   }
-  w = std::max(w, (size_t)(f.store == HIF_STORE_F64 ? 16 : 8) * f.nroot);
+  w = std::max(w, f.root_tiled ? cs * (size_t)f.nroot : 2 * cs * (size_t)f.nroot);
   if (worst) *worst = w;
   return w;
 }
@@ -639,12 +868,71 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM((k_group_bwd<S, C, true>));                                                        \
   HIF_SMEM((k_group_fwd<S, C, false>));                                                       \
   HIF_SMEM((k_group_bwd<S, C, false>));                                                       \
+  HIF_SMEM((k_tfwd_rows<S, C, 0>));                                                           \
+  HIF_SMEM((k_tfwd_rows<S, C, 1>));                                                           \
+  HIF_SMEM((k_tbwd_rows1<S, C>));                                                             \
+  HIF_SMEM((k_tcols<S, C, 0>));                                                               \
+  HIF_SMEM((k_tcols<S, C, 1>));                                                               \
+  HIF_SMEM((k_tcols<S, C, 2>));                                                               \
   HIF_SMEM((k_root<S, C>))
   HIF_SMEM_ALL(double, double);
   HIF_SMEM_ALL(float, float);
   HIF_SMEM_ALL(bf16_t, float);
 #undef HIF_SMEM_ALL
 #undef HIF_SMEM
+}
+
+
+namespace {
+// Tiles of one level; its cells' interiors take scratch [*base, *base + sum nI): every level
+// keeps its own region because all forward stages run before any backward stage.
+void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, hipStream_t s) {
+  std::vector<int4> rt, ct;
+  int64_t woff = *base;
+  for (size_t c = 0; c < cells.size(); ++c) {
+    const CellDesc& d = cells[c];
+    const int nrows = d.mode ? d.nI : d.nI + d.nB;
+    for (int r0 = 0; r0 < nrows; r0 += kRowTile) rt.push_back({(int)c, r0, (int)woff, 0});
+    for (int c0 = 0; c0 < d.nI; c0 += kColTile) ct.push_back({(int)c, c0, (int)woff, 0});
+    woff += d.nI;
+  }
+  L.nrt = (int)rt.size();
+  L.nct = (int)ct.size();
+  L.rtiles.upload(rt, s);
+  L.ctiles.upload(ct, s);
+  HIF_REQUIRE(woff < (int64_t)INT32_MAX, HIF_ERR_ARG, "tiled scratch too large");
+  *base = woff;
+}
+}  // namespace
+
+void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells, hipStream_t s) {
+  const bool f64 = f.store == HIF_STORE_F64;
+  int64_t wtot = 0;
+  for (size_t l = 0; l < f.lv.size(); ++l) {
+    LevelDev& L = f.lv[l];
+    L.tiled = L.ncell > 0 && !(f64 ? cell_plan<double>(L).staged : cell_plan<float>(L).staged);
+    if (L.tiled) tile_level(L, cells[l], &wtot, s);
+  }
+  // a root of more than 256 KiB of factor is spread over many workgroups
+  const size_t eb = store_elem_bytes(f.store);
+  f.root_tiled = (size_t)tri_count(f.nroot) * eb > 256 * 1024;
+  if (f.root_tiled) {
+    CellDesc d{};
+    d.nI = f.nroot;
+    d.nB = 0;
+    d.offI = f.offRootIdx;
+    d.offV = (int32_t)f.offRootV;
+    d.mode = 0;
+    LevelDev& R = f.rootlv;
+    R.ncell = 1;
+    R.maxI = f.nroot;
+    R.maxB = 0;
+    R.cmode = 0;
+    R.tiled = true;
+    R.cells.upload(std::vector<CellDesc>{d}, s);
+    tile_level(R, {d}, &wtot, s);
+  }
+  f.wsc.alloc(std::max<int64_t>(1, wtot));
 }
 
 }  // namespace hifcn

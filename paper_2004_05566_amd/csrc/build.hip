@@ -922,6 +922,16 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       idx.insert(idx.end(), lo.cellB[c].begin(), lo.cellB[c].end());
       d.offC = (int32_t)idx.size();
       idx.insert(idx.end(), lo.cellIb[c].begin(), lo.cellIb[c].end());
+      if (d.mode == 1) {  // links grouped by interior DOF: rowptr[nI + 1], blist[nB]
+        const std::vector<int32_t>& ib = lo.cellIb[c];
+        std::vector<int32_t> rp(d.nI + 1, 0), bl(ib.size());
+        for (int32_t i : ib) ++rp[i + 1];
+        for (int i = 0; i < d.nI; ++i) rp[i + 1] += rp[i];
+        std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+        for (size_t b = 0; b < ib.size(); ++b) bl[fill[ib[b]]++] = (int32_t)b;
+        idx.insert(idx.end(), rp.begin(), rp.end());
+        idx.insert(idx.end(), bl.begin(), bl.end());
+      }
     }
     for (size_t q = 0; q < lo.groups.size(); ++q) {
       GroupDesc& d = lo.groups[q];
@@ -985,6 +995,11 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   convert(rchunk.p, root_base, tri64(nroot));
   HIF_CHECK(hipGetLastError());
   f.cb.alloc(std::max<int64_t>(1, cbmax));
+  {
+    std::vector<std::vector<CellDesc>> cells;
+    for (const LevelOut& lo : outs) cells.push_back(lo.cells);
+    setup_tiling(f, cells, s);
+  }
   size_t worst = 0;
   apply_smem_need(f, &worst);
   f.smem_max = worst;

@@ -43,17 +43,22 @@ struct Reader {
   }
 };
 
-// Inverse of a row-major lower-triangular matrix (host, FP64, forward substitution).
+// Inverse of a row-major lower-triangular matrix (host, FP64, forward substitution by rows:
+// row i of X = (e_i - sum_{k<i} L_ik X_k) / L_ii, with contiguous row operations).
 std::vector<double> tri_inverse(const std::vector<double>& L, int n) {
   std::vector<double> X((size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    HIF_REQUIRE(L[(size_t)j * n + j] > 0.0, HIF_ERR_NOT_SPD, "non-positive Cholesky pivot in blob");
-    X[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      double s = 0;
-      for (int k = j; k < i; ++k) s += L[(size_t)i * n + k] * X[(size_t)k * n + j];
-      X[(size_t)i * n + j] = -s / L[(size_t)i * n + i];
+  for (int i = 0; i < n; ++i) {
+    const double d = L[(size_t)i * n + i];
+    HIF_REQUIRE(d > 0.0, HIF_ERR_NOT_SPD, "non-positive Cholesky pivot in blob");
+    double* xi = &X[(size_t)i * n];
+    xi[i] = 1.0;
+    for (int k = 0; k < i; ++k) {
+      const double l = L[(size_t)i * n + k];
+      if (l == 0.0) continue;
+      const double* xk = &X[(size_t)k * n];
+      for (int j = 0; j <= k; ++j) xi[j] -= l * xk[j];
     }
+    for (int j = 0; j <= i; ++j) xi[j] /= d;
   }
   return X;
 }
@@ -142,12 +147,21 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
       fh.vals.resize(align_vals((int64_t)fh.vals.size()), 0.0);
       d.offV = (int32_t)fh.vals.size();
       push_packed(fh.vals, Li, nI);
-      for (int j = 0; j < nI; ++j)      // H[b][j] = sum_i G[i][b] Linv[i][j], column-major
-        for (int b : keep) {
-          double s = 0;
-          for (int i = j; i < nI; ++i) s += Gm[(size_t)i * nB + b] * Li[(size_t)i * nI + j];
-          fh.vals.push_back(s);
+      {  // H[q][j] = sum_i G[i][keep_q] Linv[i][j] (row operations), stored column-major
+        const int nk = (int)keep.size();
+        std::vector<double> H((size_t)nk * nI, 0.0);
+        for (int i = 0; i < nI; ++i) {
+          const double* li = &Li[(size_t)i * nI];
+          for (int q = 0; q < nk; ++q) {
+            const double g = Gm[(size_t)i * nB + keep[q]];
+            if (g == 0.0) continue;
+            double* hq = &H[(size_t)q * nI];
+            for (int j = 0; j <= i; ++j) hq[j] += g * li[j];
+          }
         }
+        for (int j = 0; j < nI; ++j)
+          for (int q = 0; q < nk; ++q) fh.vals.push_back(H[(size_t)q * nI + j]);
+      }
       d.offCB = (int32_t)cb;
       fh.nvals_used += tri_count(nI) + (int64_t)nI * d.nB;
       cellB.push_back({Bk, cb});
@@ -317,6 +331,11 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
   fd.offRootIdx = fh.offRootIdx;
   fd.offRootV = fh.offRootV;
   fd.cb.alloc(std::max<int64_t>(1, fh.cbmax));
+  {
+    std::vector<std::vector<CellDesc>> cells;
+    for (const LevelHost& lh : fh.lv) cells.push_back(lh.cells);
+    setup_tiling(fd, cells, s);
+  }
   size_t worst = 0;
   apply_smem_need(fd, &worst);
   fd.smem_max = worst;

@@ -19,6 +19,11 @@ struct LevelDev {
   int64_t group_bytes[2] = {0, 0};
   DevBuf<CellDesc> cells;
   DevBuf<GroupDesc> groups;
+  // Cells too large for one workgroup are tiled: row tiles and column tiles of 64 / 16
+  // (cell, first row or column, scratch offset of the cell's interior, unused).
+  bool tiled = false;
+  int nrt = 0, nct = 0;
+  DevBuf<int4> rtiles, ctiles;
 };
 
 // Stages of one apply, as timed by the profiler.
@@ -63,6 +68,9 @@ struct FactorDev {
   size_t smem_max = 0;
   int64_t root_bytes = 0;
   std::unique_ptr<StageProfiler> prof;
+  DevBuf<double> wsc;   // interiors of tiled cells between the forward and backward sweep
+  LevelDev rootlv;      // the root as a one-cell level, used when it is tiled
+  bool root_tiled = false;
 };
 
 // Host-side, FP64 version of the same layout (used by import; the GPU build writes the device
@@ -125,6 +133,9 @@ void level_stage_bytes(const std::vector<CellDesc>& cells, const std::vector<Gro
                        const std::vector<int64_t>& group_slots, size_t eb, LevelDev& ld);
 FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf);
 size_t apply_smem_need(const FactorDev& f, size_t* worst);
+// Decide per level whether cells are tiled across workgroups and upload the tile lists;
+// `cells` are the host copies of every level's descriptors.
+void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells, hipStream_t s);
 void set_apply_smem_limits(size_t bytes);
 
 // ---- kernels --------------------------------------------------------------------------------

@@ -131,3 +131,20 @@ def test_stage_profiler_counts_launches(gpu_lib):
     p = h.profile_read()
     assert p["launches"] == int(sum(its))   # one live apply per iteration that goes on + the first
     h.profile_stage(0, "cell_bwd", False)
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_tiled_3d_factor_cn_matches_oracle(store, gpu_lib):
+    """Leaf cells of 8^3 DOFs (link mode, tiled over workgroups) and a tiled root."""
+    import torch
+    n, dim, leaf, eps, dt = 16, 3, 8, 1e-4, 0.02
+    a = gen.grf_coefficient(n, dim, 0.15, 41)
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, dim, leaf, eps)
+    u0 = gen.bumps(n, dim, 3, 42)
+    us, its, _ = cn.cn_solve(A, B, u0, dt, 2, lambda r: phif.phif_apply(F, r), 1e-12)
+    h = _factor(a, dt, n, dim, leaf, eps, store)
+    u = torch.tensor(u0.ravel(), device="cuda")
+    gits, _ = h.cn_solve(u, 2, rtol=1e-12)
+    assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])
+    assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)

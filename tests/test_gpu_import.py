@@ -126,3 +126,16 @@ def test_zero_rhs_and_no_convergence(gpu_lib):
     with pytest.raises(hifcn.HifError) as ei:
         h.cn_solve(u, 1, rtol=1e-30, maxit=1)
     assert ei.value.status == hifcn.HIF_ERR_NO_CONV
+
+
+def test_apply_tiled_cells_and_root_match_oracle(gpu_lib):
+    """3D cells of 8^3 DOFs and a root of ~2000 DOFs exceed one workgroup's LDS: the apply
+    spreads them over row and column tiles (dense-H mode for imported factors)."""
+    import torch
+    case = ("3d-n16-m8-tiled", 16, 3, 8, 1e-3, 0.05, "grf")
+    a, A, B, F, h = _setup(case)
+    assert len(F.root_idx) > 300
+    r = np.random.default_rng(9).normal(size=A.shape[0])
+    z = h.apply(torch.tensor(r, device="cuda")).cpu().numpy()
+    ref = phif.phif_apply(F, r)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
