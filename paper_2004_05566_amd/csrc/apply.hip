@@ -455,15 +455,17 @@ __global__ __launch_bounds__(kRootThreads) void k_root(int nr, const int32_t* __
 // every tile of a cell still reads the old y_I; the backward sweep reads them back from there
 // and writes the final interior values into y.
 //   row tiles:    64 consecutive rows of [L^-1; H] (packed columns are contiguous over rows,
-//                 so each load of a wavefront is coalesced); the four wavefronts of the
-//                 workgroup take every fourth column and add up through LDS.
-//   column tiles: 16 consecutive columns; each wavefront reduces whole columns (contiguous in
-//                 memory) for four outputs.
+//                 so each load of a wavefront is coalesced); the 16 wavefronts of the
+//                 workgroup take every 16th column and add up through LDS.
+//   column tiles: 32 consecutive columns; each wavefront reduces whole columns (contiguous in
+//                 memory) for two outputs.
 constexpr int kRowTile = 64;
-constexpr int kColTile = 16;
+constexpr int kColTile = 32;
+constexpr int kTileThreads = 1024;   // 16 wavefronts per tile
+constexpr int kTileWaves = kTileThreads / 64;
 
 template <typename S, typename C, int MODE>
-__global__ __launch_bounds__(256) void k_tfwd_rows(const CellDesc* __restrict__ cd,
+__global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __restrict__ cd,
                                                    const int4* __restrict__ tiles,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(256) void k_tfwd_rows(const CellDesc* __restrict__ 
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* ys = reinterpret_cast<C*>(smem_raw);
-  __shared__ C red[4][kRowTile];
+  __shared__ C red[kTileWaves][kRowTile];
   const int4 t = tiles[blockIdx.x];
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
@@ -491,15 +493,18 @@ __global__ __launch_bounds__(256) void k_tfwd_rows(const CellDesc* __restrict__ 
   const int tl = tri_count(nI);
   C acc = 0;
   if (r < nI) {
-    for (int j = wave; j <= r; j += 4) acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ys[j];
+    for (int j = wave; j <= r; j += kTileWaves)
+      acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ys[j];
   } else if (r < nrows) {
     const S* H = v + tl + (r - nI);
-    for (int j = wave; j < nI; j += 4) acc += load_as<C>(H + (int64_t)j * nB) * ys[j];
+    for (int j = wave; j < nI; j += kTileWaves) acc += load_as<C>(H + (int64_t)j * nB) * ys[j];
   }
   red[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && r < nrows) {
-    const C tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    C tot = 0;
+#pragma unroll
+    for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
     if (r < nI) wsc[t.z + r] = (double)tot;
     else cb[d.offCB + r - nI] = (double)tot;
   }
@@ -518,7 +523,7 @@ __device__ __forceinline__ float wave_reduce(float v) {
 //                KIND 1 (backward, links):   x_i = L^-T u -> y.
 //                KIND 2 (forward, links):    v_i = L^-T w;  c_b = A_BI(b, ib_b) v_ib_b -> cb.
 template <typename S, typename C, int KIND>
-__global__ __launch_bounds__(256) void k_tcols(const CellDesc* __restrict__ cd,
+__global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restrict__ cd,
                                                const int4* __restrict__ tiles,
                                                const int32_t* __restrict__ idx,
                                                const S* __restrict__ vals,
@@ -541,7 +546,7 @@ __global__ __launch_bounds__(256) void k_tcols(const CellDesc* __restrict__ cd,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const S* v = vals + d.offV;
   const int tl = tri_count(nI);
-  for (int q = wave; q < kColTile; q += 4) {
+  for (int q = wave; q < kColTile; q += kTileWaves) {
     const int i = c0 + q;
     if (i >= nI) break;
     const S* col = v + colstart(i, nI);
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(256) void k_tcols(const CellDesc* __restrict__ cd,
 // Backward, links: t = A_IB x_B (per interior DOF, its links in a fixed order), then
 // u_r = w_r - (L^-1 t)_r over a row tile, in place in the scratch vector.
 template <typename S, typename C>
-__global__ __launch_bounds__(256) void k_tbwd_rows1(const CellDesc* __restrict__ cd,
+__global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __restrict__ cd,
                                                     const int4* __restrict__ tiles,
                                                     const int32_t* __restrict__ idx,
                                                     const S* __restrict__ vals,
@@ -581,7 +586,7 @@ __global__ __launch_bounds__(256) void k_tbwd_rows1(const CellDesc* __restrict__
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* ts = reinterpret_cast<C*>(smem_raw);
-  __shared__ C red[4][kRowTile];
+  __shared__ C red[kTileWaves][kRowTile];
   const int4 t = tiles[blockIdx.x];
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
@@ -606,11 +611,168 @@ __global__ __launch_bounds__(256) void k_tbwd_rows1(const CellDesc* __restrict__
   const int r = r0 + lane;
   C acc = 0;
   if (r < nI)
-    for (int j = wave; j <= r; j += 4) acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ts[j];
+    for (int j = wave; j <= r; j += kTileWaves)
+      acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ts[j];
   red[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && r < nI)
-    wsc[t.z + r] -= (double)(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
+  if (wave == 0 && r < nI) {
+    C tot = 0;
+#pragma unroll
+    for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
+    wsc[t.z + r] -= (double)tot;
+  }
+}
+
+// --------------------------------------------------------------------------- large groups --
+// One workgroup of 16 wavefronts per group, blocks read from global memory:
+//   row walks (out_r = sum_j A(r, j) x_j with A column-major): lanes take 64 consecutive rows
+//     (coalesced), wavefronts split the columns, partial sums meet in LDS;
+//   column walks (out_c = sum_j A(j, c) x_j): one wavefront per output reads the contiguous
+//     column.
+template <typename C, typename A, typename LO, typename HI, typename OUT>
+__device__ void rows_walk(int nrows, A a, LO lo, HI hi, const C* x, OUT out,
+                          C (*red)[kRowTile]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < nrows; r0 += kRowTile) {
+    const int r = r0 + lane;
+    C acc = 0;
+    if (r < nrows)
+      for (int j = lo(r) + wave; j < hi(r); j += kTileWaves) acc += a(r, j) * x[j];
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && r < nrows) {
+      C tot = 0;
+#pragma unroll
+      for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
+      out(r, tot);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename C, typename A, typename LO, typename HI, typename OUT>
+__device__ void cols_walk(int ncols, A a, LO lo, HI hi, const C* x, OUT out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < ncols; c += kTileWaves) {
+    C acc = 0;
+    for (int j = lo(c) + lane; j < hi(c); j += 64) acc += a(j, c) * x[j];
+    acc = wave_reduce(acc);
+    if (lane == 0) out(c, acc);
+  }
+  __syncthreads();
+}
+
+// LDS: vg (n) | zg (n) | xs (k) | tv (nr) | uv (nr)
+template <typename S, typename C>
+__global__ __launch_bounds__(kTileThreads) void k_group_big_fwd(const GroupDesc* __restrict__ gd,
+                                                                const int32_t* __restrict__ idx,
+                                                                const S* __restrict__ vals,
+                                                                double* __restrict__ y,
+                                                                const double* __restrict__ cb,
+                                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ C red[kTileWaves][kRowTile];
+  const GroupDesc d = gd[blockIdx.x];
+  const int n = d.n, nr = d.nr, k = n - nr;
+  C* yg = reinterpret_cast<C*>(smem_raw);
+  C* zg = yg + n;
+  C* xs = zg + n;
+  C* tv = xs + k;
+  C* uv = tv + nr;
+  const S* Lg = vals + d.offV;
+  const S* T = Lg + tri_count(n);
+  const S* Lr = T + (int64_t)k * nr;
+  const int32_t* gi = idx + d.offIdx;
+  const int32_t* gp = idx + d.offGP;
+  const int32_t* slots = gp + n + 1;
+  const int32_t* perm = idx + d.offPerm;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc = y[gi[i]];
+    for (int q = gp[i]; q < gp[i + 1]; ++q) acc -= cb[slots[q]];
+    yg[i] = (C)acc;
+  }
+  __syncthreads();
+  // C^T: z = L_g^-1 y_g
+  rows_walk<C>(n, [&](int r, int j) { return load_as<C>(Lg + colstart(j, n) + (r - j)); },
+               [](int) { return 0; }, [](int r) { return r + 1; }, yg,
+               [&](int r, C v) { zg[r] = v; }, red);
+  if (nr == 0) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) y[gi[i]] = (double)zg[i];
+    return;
+  }
+  for (int q = threadIdx.x; q < k; q += blockDim.x) xs[q] = zg[perm[nr + q]];
+  __syncthreads();
+  // y_I~ - T^T y_I^  (column i of T is contiguous over the skeleton index)
+  cols_walk<C>(nr, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
+               [](int) { return 0; }, [&](int) { return k; }, xs,
+               [&](int i, C v) { tv[i] = zg[perm[i]] - v; });
+  // t = L_s^-1 (...)
+  rows_walk<C>(nr, [&](int r, int j) { return load_as<C>(Lr + colstart(j, nr) + (r - j)); },
+               [](int) { return 0; }, [](int r) { return r + 1; }, tv,
+               [&](int r, C v) { uv[r] = v; }, red);
+  // L_s^-T t
+  cols_walk<C>(nr, [&](int j, int i) { return load_as<C>(Lr + colstart(i, nr) + (j - i)); },
+               [](int i) { return i; }, [&](int) { return nr; }, uv,
+               [&](int i, C v) { tv[i] = v; });
+  // y_I^ += T L_s^-T t  (row s of T: lanes over s are contiguous for each i)
+  rows_walk<C>(k, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
+               [](int) { return 0; }, [&](int) { return nr; }, tv,
+               [&](int q, C v) { y[gi[perm[nr + q]]] = (double)(xs[q] + v); }, red);
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) y[gi[perm[i]]] = (double)uv[i];
+}
+
+template <typename S, typename C>
+__global__ __launch_bounds__(kTileThreads) void k_group_big_bwd(const GroupDesc* __restrict__ gd,
+                                                                const int32_t* __restrict__ idx,
+                                                                const S* __restrict__ vals,
+                                                                double* __restrict__ x,
+                                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ C red[kTileWaves][kRowTile];
+  const GroupDesc d = gd[blockIdx.x];
+  const int n = d.n, nr = d.nr, k = n - nr;
+  C* xg = reinterpret_cast<C*>(smem_raw);
+  C* zg = xg + n;
+  C* xs = zg + n;
+  C* tv = xs + k;
+  C* uv = tv + nr;
+  const S* Lg = vals + d.offV;
+  const S* T = Lg + tri_count(n);
+  const S* Lr = T + (int64_t)k * nr;
+  const int32_t* gi = idx + d.offIdx;
+  const int32_t* perm = idx + d.offPerm;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) xg[i] = (C)x[gi[i]];
+  __syncthreads();
+  if (nr > 0) {
+    for (int q = threadIdx.x; q < k; q += blockDim.x) xs[q] = xg[perm[nr + q]];
+    __syncthreads();
+    // a = T^T x_I^
+    cols_walk<C>(nr, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
+                 [](int) { return 0; }, [&](int) { return k; }, xs,
+                 [&](int i, C v) { tv[i] = v; });
+    // x_I~ + L_s^-1 a
+    rows_walk<C>(nr, [&](int r, int j) { return load_as<C>(Lr + colstart(j, nr) + (r - j)); },
+                 [](int) { return 0; }, [](int r) { return r + 1; }, tv,
+                 [&](int r, C v) { uv[r] = xg[perm[r]] + v; }, red);
+    // u = L_s^-T (...)
+    cols_walk<C>(nr, [&](int j, int i) { return load_as<C>(Lr + colstart(i, nr) + (j - i)); },
+                 [](int i) { return i; }, [&](int) { return nr; }, uv,
+                 [&](int i, C v) { tv[i] = v; });
+    // x_I^ -= T u
+    rows_walk<C>(k, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
+                 [](int) { return 0; }, [&](int) { return nr; }, tv,
+                 [&](int q, C v) { zg[perm[nr + q]] = xs[q] - v; }, red);
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) zg[perm[i]] = tv[i];
+  } else {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) zg[i] = xg[i];
+  }
+  __syncthreads();
+  // C: x_g = L_g^-T x_g
+  cols_walk<C>(n, [&](int j, int i) { return load_as<C>(Lg + colstart(i, n) + (j - i)); },
+               [](int i) { return i; }, [&](int) { return n; }, zg,
+               [&](int i, C v) { x[gi[i]] = (double)v; });
 }
 
 // --------------------------------------------------------------------------- launch plans --
@@ -734,6 +896,11 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
   }
 }
 
+template <typename C>
+size_t big_group_smem(const LevelDev& L) {
+  return sizeof(C) * (2 * (size_t)L.maxG + (size_t)L.maxK + 2 * (size_t)L.maxR + 4);
+}
+
 template <typename S, typename C>
 void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
                   const int* done, hipStream_t s, const StageTimer& t) {
@@ -742,27 +909,27 @@ void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals
   const size_t cols_smem = sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB);
   if (fwd) {
     if (L.cmode) {
-      launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(256), rows_smem, s, t,
+      launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, f.cb.p, done);
-      launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(256), cols_smem, s, StageTimer(),
+      launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, StageTimer(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, f.cb.p, done);
     } else {
-      launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(256), rows_smem, s, t,
+      launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, f.cb.p, done);
     }
   } else {
     if (L.cmode) {
-      launch(k_tbwd_rows1<S, C>, dim3(L.nrt), dim3(256), rows_smem, s, t,
+      launch(k_tbwd_rows1<S, C>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, done);
-      launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(256), cols_smem, s, StageTimer(),
+      launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, StageTimer(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, f.cb.p, done);
     } else {
-      launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(256), cols_smem, s, t,
+      launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, f.cb.p, done);
     }
@@ -782,7 +949,11 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, done, s, t);
       else launch_cell<S, C, 0>(f, L, true, vals, y, done, s, t);
     }
-    if (L.ngroup) {
+    if (L.ngroup && !group_plan<C>(L).staged) {
+      const StageTimer t(prof, (int)l, STAGE_GROUP_FWD, done, s);
+      launch(k_group_big_fwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L), s,
+             t, (const GroupDesc*)L.groups.p, idx, vals, y, (const double*)f.cb.p, done);
+    } else if (L.ngroup) {
       const StageTimer t(prof, (int)l, STAGE_GROUP_FWD, done, s);
       const StagePlan p = group_plan<C>(L);
       auto k = p.staged ? k_group_fwd<S, C, true> : k_group_fwd<S, C, false>;
@@ -803,7 +974,11 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
   }
   for (size_t l = f.lv.size(); l-- > 0;) {
     const LevelDev& L = f.lv[l];
-    if (L.ngroup) {
+    if (L.ngroup && !group_plan<C>(L).staged) {
+      const StageTimer t(prof, (int)l, STAGE_GROUP_BWD, done, s);
+      launch(k_group_big_bwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L), s,
+             t, (const GroupDesc*)L.groups.p, idx, vals, y, done);
+    } else if (L.ngroup) {
       const StageTimer t(prof, (int)l, STAGE_GROUP_BWD, done, s);
       const StagePlan p = group_plan<C>(L);
       auto k = p.staged ? k_group_bwd<S, C, true> : k_group_bwd<S, C, false>;
@@ -835,6 +1010,8 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst) {
       g = group_plan<float>(L).smem;
     }
     if (L.tiled) c = cs * (size_t)(L.maxI + L.maxB);
+    if (!(f.store == HIF_STORE_F64 ? group_plan<double>(L).staged : group_plan<float>(L).staged))
+      g = cs * (2 * (size_t)L.maxG + (size_t)L.maxK + 2 * (size_t)L.maxR + 4);
     w = std::max(w, std::max(c, g));
   }
   w = std::max(w, f.root_tiled ? cs * (size_t)f.nroot : 2 * cs * (size_t)f.nroot);
@@ -874,6 +1051,8 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM((k_tcols<S, C, 0>));                                                               \
   HIF_SMEM((k_tcols<S, C, 1>));                                                               \
   HIF_SMEM((k_tcols<S, C, 2>));                                                               \
+  HIF_SMEM((k_group_big_fwd<S, C>));                                                          \
+  HIF_SMEM((k_group_big_bwd<S, C>));                                                          \
   HIF_SMEM((k_root<S, C>))
   HIF_SMEM_ALL(double, double);
   HIF_SMEM_ALL(float, float);

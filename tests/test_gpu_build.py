@@ -148,3 +148,21 @@ def test_tiled_3d_factor_cn_matches_oracle(store, gpu_lib):
     gits, _ = h.cn_solve(u, 2, rtol=1e-12)
     assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])
     assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)
+
+
+def test_3d_two_levels_large_groups_match_oracle(gpu_lib):
+    """32^3 grid, two levels: the level-1 faces (up to ~230 DOFs) exceed the per-group LDS
+    budget and go through the one-group-per-workgroup global-memory kernels; the root is
+    tiled."""
+    import torch
+    n, dim, leaf, eps, dt = 32, 3, 8, 1e-4, 0.02
+    a = gen.grf_coefficient(n, dim, 0.15, 51)
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, dim, leaf, eps)
+    u0 = gen.bumps(n, dim, 4, 52)
+    us, its, _ = cn.cn_solve(A, B, u0, dt, 2, lambda r: phif.phif_apply(F, r), 1e-12)
+    h = _factor(a, dt, n, dim, leaf, eps, "f32")
+    u = torch.tensor(u0.ravel(), device="cuda")
+    gits, _ = h.cn_solve(u, 2, rtol=1e-12)
+    assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])
+    assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)
