@@ -110,6 +110,65 @@ def copy_probe(nbytes: int):
     print(json.dumps({"copy_probe_bytes": nbytes}))
 
 
+def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
+                  seed_base: int = 5000) -> dict:
+    """The serving workload: `count` independent 2D Fisher-KPP solves of mixed size, dt and
+    coefficient (50 CN steps each), arriving as a Poisson process of `rate` requests/s (rate 0:
+    all at once), served by continuous batching.  Inputs are drawn before the clock starts."""
+    import numpy as np
+
+    from paper_2004_05566_amd.serve import Request, Server, percentiles
+    from workloads import gen
+
+    def req(w):
+        return Request(w.n, w.a_cells, w.u0, w.dt, w.steps, eps=w.eps, reaction=w.reaction,
+                       rtol=w.rtol, store="f32", tag=w.name)
+
+    reqs = [req(gen.serving_request(i, seed_base)) for i in range(count)]
+    # first-use costs (kernel loading, LDS attributes) outside the clock: one of each size
+    warm = Server(budget_bytes, max_slots)
+    for f in [warm.submit(req(gen.serving_request(10_000 + i, seed_base, sizes=(n,))))
+              for i, n in enumerate((64, 128, 256, 512))]:
+        f.result()
+    warm.close()
+    arrivals = (gen.poisson_arrivals(count, rate, seed_base + 7) if rate > 0
+                else np.zeros(count))
+    srv = Server(budget_bytes, max_slots)
+    finished = [0]
+
+    def progress(_f):
+        finished[0] += 1
+        if finished[0] % 32 == 0:
+            print(f"serving: {finished[0]}/{count} done", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter() + 0.01
+    futs = []
+    for r, ta in zip(reqs, arrivals):
+        delay = t0 + ta - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        futs.append(srv.submit(r, t_arrival=t0 + ta))
+        futs[-1].add_done_callback(progress)
+    res = [f.result() for f in futs]
+    srv.close()
+    t_end = max(r.t_done for r in res)
+    lat = [r.latency for r in res]
+    steps = sum(len(r.iters) for r in res)
+    st = srv.stats()
+    out = {"requests": count, "arrival_rate_per_s": rate or None,
+           "arrivals": "poisson" if rate > 0 else "all at t=0",
+           **{k + "_latency_s": v for k, v in percentiles(lat).items()},
+           "mean_latency_s": float(np.mean(lat)),
+           "makespan_s": t_end - t0, "requests_per_s": count / (t_end - t0),
+           "cn_steps_per_s": steps / (t_end - t0),
+           "mean_build_s": float(np.mean([r.t_ready - r.t_admit for r in res])),
+           "mean_queue_s": float(np.mean([r.t_admit - r.t_arrival for r in res])),
+           "n_i_mean": float(np.mean(np.concatenate([r.iters for r in res]))),
+           "sizes": sorted({int(r.u.shape[0]) for r in res}),
+           **st}
+    return out
+
+
 def cpu_baseline(w, budget_steps: int):
     """The FP64 oracle on the same workload: factor build, then `budget_steps` CN steps."""
     import numpy as np
@@ -156,6 +215,13 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the error check")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
+    ap.add_argument("--serving", type=int, default=256,
+                    help="requests of the serving workload (0: skip)")
+    ap.add_argument("--serving-rate", type=float, default=40.0,
+                    help="Poisson arrival rate of serving requests per second (0: all at once)")
+    ap.add_argument("--serving-slots", type=int, default=32)
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration)")
     args = ap.parse_args(argv)
@@ -171,6 +237,14 @@ def main(argv=None):
 
     from paper_2004_05566_amd import hifcn
     from workloads import gen
+
+    def serving():
+        return serving_bench(args.serving, args.serving_rate, args.serving_slots,
+                             int(args.serving_budget_gb * (1 << 30)))
+
+    if args.serving_only:
+        print(json.dumps({"serving": serving()}))
+        return 0
 
     w = gen.workload(args.workload)
     dev = torch.device("cuda:0")
@@ -255,10 +329,12 @@ def main(argv=None):
                                                for k, v in roof.items()}},
         "apply_stages": stages,
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, 10)
     h.close()
     h64.close()
+    if args.serving:
+        out["serving"] = serving()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, 10)
     print(json.dumps(out))
     return 0
 

@@ -108,11 +108,27 @@ hif_status_t cn_solve(hif_handle_t h, const hif_reaction_t* r, const hif_cg_opts
                       double* u_dev, int32_t nsteps, int32_t* iters_host, double* relres_host,
                       void* hip_stream);
 
+/* Continuous batching: one Crank-Nicolson step (as cn_step) for each of `count` independent
+ * solves, handle h[i] with state u_dev[i] (device, N_i FP64), reaction r[i] (array, may be
+ * NULL: none) and options opts[i], each queued on its own stream hip_streams[i] (array, may be
+ * NULL: the null stream).  The PCG iterations of all solves are queued in lockstep with one
+ * convergence read-back per round for the whole batch, so the kernels of different solves
+ * overlap on the device, and each solve's result is exactly what cn_step gives for it alone.
+ * iters_host[i], relres_host[i], status_host[i] (host arrays, each may be NULL) receive the
+ * statistics and each solve's own status (HIF_OK or HIF_ERR_NO_CONV).  A handle may appear at
+ * most once.  Synchronises every stream.  Returns HIF_ERR_NO_CONV if any solve failed to
+ * converge; every other solve still completes its step. */
+hif_status_t cn_batch_step(hif_handle_t* h, const hif_reaction_t* r, const hif_cg_opts_t* opts,
+                           double** u_dev, int32_t count, int32_t* iters_host,
+                           double* relres_host, int32_t* status_host, void** hip_streams);
+
 /* Stored factor bytes (unpadded, in the storage precision): the algorithmic bytes one sweep of
  * hif_apply reads; one apply reads them twice. */
 size_t hif_factor_bytes(hif_handle_t h);
 
-/* Structure summary: number of levels, root size and stored factor entries. */
+/* Structure summary: number of levels, root size, stored factor entries, and every byte of
+ * device memory the handle holds (factor, descriptors and PCG workspace; what a server admitting
+ * solves by HBM footprint accounts for). */
 typedef struct {
   int32_t levels;
   int32_t root;
@@ -120,6 +136,7 @@ typedef struct {
   int64_t N;
   int32_t store;
   int32_t dim;
+  int64_t device_bytes;
 } hif_info_t;
 hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
 

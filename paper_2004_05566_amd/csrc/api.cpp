@@ -78,59 +78,97 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   HIF_CHECK(hipMemsetAsync(h->st.p, 0, sizeof(CgState), s));
   h->step_iters.alloc(1);
   h->step_relres.alloc(1);
-  HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 4 * sizeof(int32_t),
+  // [0..2] iters, done, status of the running step; [4..5] the last step's relres (FP64)
+  HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 8 * sizeof(int32_t),
                           hipHostMallocDefault));
   return h;
 }
 
-// One Crank-Nicolson step on the device; the host waits only to test convergence.
-void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u, int step,
-                 hipStream_t s) {
-  const int kind = r ? r->kind : 0;
-  const double k1 = r ? r->k1 : 0, k2 = r ? r->k2 : 1;
-  launch_cg_rhs(h, u, kind, k1, k2, o->maxit, s);
-  const int* done = &h.st.p->done;
-  launch_cg_check_copy(h, -1, o->rtol, s);
-  hif_apply_inplace(h.f, h.z.p, done, s);
-  launch_cg_dot_rz(h, 0, s);
-  // Queue iterations without waiting, up to the predicted count; the predicted last iteration
-  // stops after its convergence test, so a converged step leaves no dead apply behind.
+// One Crank-Nicolson step of one solve, as a small state machine so that several solves can be
+// advanced in lockstep (continuous batching).  Iterations are queued without waiting, up to
+// the predicted count; the predicted last iteration stops after its convergence test, so a
+// converged step leaves no dead preconditioner apply behind.
+struct StepState {
+  Handle* h = nullptr;
+  hipStream_t s = nullptr;
+  const hif_reaction_t* r = nullptr;
+  const hif_cg_opts_t* o = nullptr;
+  double* u = nullptr;
+  int step = 0;
   int launched = 0;        // iterations whose update has been queued
   bool tail_open = false;  // the last queued iteration still owes its apply + r.z
-  int chunk = std::max(1, h.last_iters);
-  auto read_flags = [&] {
-    HIF_CHECK(hipGetLastError());
-    // [iters, done, status] are adjacent in CgState
-    HIF_CHECK(hipMemcpyAsync(h.host_flag, &h.st.p->iters, 3 * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
-    HIF_CHECK(hipStreamSynchronize(s));
-    return h.host_flag[1] != 0;
-  };
-  while (true) {
-    if (tail_open) {  // the previous chunk's last iteration did not converge
-      hif_apply_inplace(h.f, h.z.p, done, s);
-      launch_cg_dot_rz(h, launched, s);
-      tail_open = false;
-    }
-    for (int c = 0; c < chunk && launched < o->maxit; ++c) {
-      const int it = launched++;
-      double* pin = (it & 1) ? h.p1.p : h.p0.p;
-      double* pout = (it & 1) ? h.p0.p : h.p1.p;
-      launch_cg_dir_spmv(h, it, pin, pout, s);
-      launch_cg_update(h, it, pout, s);
-      launch_cg_check_copy(h, it, o->rtol, s);
-      if (c + 1 == chunk || launched == o->maxit) {
-        tail_open = true;
-        break;
-      }
-      hif_apply_inplace(h.f, h.z.p, done, s);
-      launch_cg_dot_rz(h, it + 1, s);
-    }
-    if (read_flags() || launched >= o->maxit) break;
-    chunk = 2;
+  int chunk = 1;
+  bool finished = false;
+  int status = 0;
+};
+
+void step_begin(StepState& st) {
+  Handle& h = *st.h;
+  const int kind = st.r ? st.r->kind : 0;
+  const double k1 = st.r ? st.r->k1 : 0, k2 = st.r ? st.r->k2 : 1;
+  launch_cg_rhs(h, st.u, kind, k1, k2, st.o->maxit, st.s);
+  launch_cg_check_copy(h, -1, st.o->rtol, st.s);
+  hif_apply_inplace(h.f, h.z.p, &h.st.p->done, st.s);
+  launch_cg_dot_rz(h, 0, st.s);
+  st.chunk = std::max(1, h.last_iters);
+}
+
+// Queue the next chunk of iterations and the read-back of [iters, done, status].
+void step_queue(StepState& st) {
+  Handle& h = *st.h;
+  const int* done = &h.st.p->done;
+  if (st.tail_open) {  // the previous chunk's last iteration did not converge
+    hif_apply_inplace(h.f, h.z.p, done, st.s);
+    launch_cg_dot_rz(h, st.launched, st.s);
+    st.tail_open = false;
   }
-  h.last_iters = h.host_flag[0];
-  launch_cg_finish(h, u, step, s);
+  for (int c = 0; c < st.chunk && st.launched < st.o->maxit; ++c) {
+    const int it = st.launched++;
+    double* pin = (it & 1) ? h.p1.p : h.p0.p;
+    double* pout = (it & 1) ? h.p0.p : h.p1.p;
+    launch_cg_dir_spmv(h, it, pin, pout, st.s);
+    launch_cg_update(h, it, pout, st.s);
+    launch_cg_check_copy(h, it, st.o->rtol, st.s);
+    if (c + 1 == st.chunk || st.launched == st.o->maxit) {
+      st.tail_open = true;
+      break;
+    }
+    hif_apply_inplace(h.f, h.z.p, done, st.s);
+    launch_cg_dot_rz(h, it + 1, st.s);
+  }
+  HIF_CHECK(hipGetLastError());
+  HIF_CHECK(hipMemcpyAsync(h.host_flag, &h.st.p->iters, 3 * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st.s));
+}
+
+// After the stream has been synchronised: finish the step if PCG stopped.
+void step_after_sync(StepState& st) {
+  Handle& h = *st.h;
+  if (h.host_flag[1] || st.launched >= st.o->maxit) {
+    h.last_iters = h.host_flag[0];
+    st.status = h.host_flag[2];
+    launch_cg_finish(h, st.u, st.step, st.s);
+    st.finished = true;
+  } else {
+    st.chunk = 2;
+  }
+}
+
+void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u, int step,
+                 hipStream_t s) {
+  StepState st;
+  st.h = &h;
+  st.s = s;
+  st.r = r;
+  st.o = o;
+  st.u = u;
+  st.step = step;
+  step_begin(st);
+  while (!st.finished) {
+    step_queue(st);
+    HIF_CHECK(hipStreamSynchronize(s));
+    step_after_sync(st);
+  }
 }
 
 void check_opts(const hif_cg_opts_t* o) {
@@ -143,6 +181,22 @@ void check_reaction(const hif_reaction_t* r) {
   if (!r) return;
   HIF_REQUIRE(r->kind == 0 || r->kind == 1, HIF_ERR_ARG, "unknown reaction kind");
   HIF_REQUIRE(r->kind == 0 || r->k2 != 0.0, HIF_ERR_ARG, "k2 must be non-zero");
+}
+
+// Every byte of device memory the handle holds (factor, descriptors, PCG workspace).
+int64_t handle_device_bytes(const Handle& h) {
+  int64_t b = 0;
+  auto add = [&](const auto& buf) { b += (int64_t)(buf.n * sizeof(*buf.p)); };
+  add(h.links); add(h.x); add(h.r); add(h.z); add(h.p0); add(h.p1); add(h.q); add(h.partials);
+  add(h.st); add(h.step_iters); add(h.step_relres);
+  const FactorDev& f = h.f;
+  add(f.idx); add(f.vals); add(f.cb); add(f.wsc);
+  auto add_level = [&](const LevelDev& l) {
+    add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles);
+  };
+  for (const LevelDev& l : f.lv) add_level(l);
+  add_level(f.rootlv);
+  return b;
 }
 
 }  // namespace
@@ -217,7 +271,7 @@ hif_status_t cn_solve(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opt
     int failed_step = -1;
     for (int k = 0; k < nsteps; ++k) {
       cn_step_dev(h, r, o, u, k, s);
-      if (h.host_flag[2] != 0) { failed_step = k; break; }
+      if (h.host_flag[2] != 0) { failed_step = k; break; }  // status of the step just made
     }
     const int done_steps = failed_step >= 0 ? failed_step + 1 : nsteps;
     std::vector<int32_t> it(std::max(1, done_steps));
@@ -243,6 +297,61 @@ hif_status_t cn_step(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opts
   return cn_solve(hh, r, o, u, 1, iters, relres, hip_stream);
 }
 
+hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif_cg_opts_t* os,
+                           double** us, int32_t count, int32_t* iters, double* relres,
+                           int32_t* status, void** streams) {
+  return guarded([&] {
+    HIF_REQUIRE(count >= 0, HIF_ERR_ARG, "count must be >= 0");
+    HIF_REQUIRE(count == 0 || (hs && os && us), HIF_ERR_ARG, "NULL argument");
+    std::vector<StepState> st(count);
+    for (int i = 0; i < count; ++i) {
+      HIF_REQUIRE(hs[i] && us[i], HIF_ERR_ARG, "NULL handle or state");
+      check_opts(&os[i]);
+      if (rs) check_reaction(&rs[i]);
+      for (int j = 0; j < i; ++j)
+        HIF_REQUIRE(hs[j] != hs[i], HIF_ERR_ARG, "a handle appears twice in one batch");
+      st[i].h = reinterpret_cast<Handle*>(hs[i]);
+      st[i].s = streams ? static_cast<hipStream_t>(streams[i]) : nullptr;
+      st[i].r = rs ? &rs[i] : nullptr;
+      st[i].o = &os[i];
+      st[i].u = us[i];
+      st[i].step = 0;
+    }
+    for (auto& x : st) step_begin(x);
+    int open = count;
+    while (open > 0) {
+      for (auto& x : st)
+        if (!x.finished) step_queue(x);
+      for (auto& x : st)
+        if (!x.finished) HIF_CHECK(hipStreamSynchronize(x.s));
+      for (auto& x : st)
+        if (!x.finished) {
+          step_after_sync(x);
+          if (x.finished) --open;
+        }
+    }
+    int failed = -1;
+    for (auto& x : st)  // the finish kernel's statistics, into pinned memory
+      HIF_CHECK(hipMemcpyAsync(x.h->host_flag, x.h->step_iters.p, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, x.s));
+    for (auto& x : st)
+      HIF_CHECK(hipMemcpyAsync(x.h->host_flag + 4, x.h->step_relres.p, sizeof(double),
+                               hipMemcpyDeviceToHost, x.s));
+    for (auto& x : st) HIF_CHECK(hipStreamSynchronize(x.s));
+    for (int i = 0; i < count; ++i) {
+      const Handle& h = *st[i].h;
+      double rr;
+      std::memcpy(&rr, h.host_flag + 4, sizeof(double));
+      if (iters) iters[i] = h.host_flag[0];
+      if (relres) relres[i] = rr;
+      if (status) status[i] = st[i].status ? HIF_ERR_NO_CONV : HIF_OK;
+      if (st[i].status != 0 && failed < 0) failed = i;
+    }
+    HIF_REQUIRE(failed < 0, HIF_ERR_NO_CONV,
+                "PCG did not converge for batch entry " + std::to_string(failed));
+  });
+}
+
 size_t hif_factor_bytes(hif_handle_t hh) {
   if (!hh) return 0;
   const Handle& h = *reinterpret_cast<const Handle*>(hh);
@@ -259,6 +368,7 @@ hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
     info->N = h.N;
     info->store = (int32_t)h.f.store;
     info->dim = h.dim;
+    info->device_bytes = handle_device_bytes(h);
   });
 }
 

@@ -24,6 +24,8 @@
 // `done` is set, so PCG iterations can be queued ahead.
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -1027,8 +1029,14 @@ void hif_apply_inplace(const FactorDev& f, double* y, const int* done, hipStream
   }
 }
 
-// Allow the apply kernels to use up to `bytes` of dynamic LDS (gfx950: 160 KiB per CU).
+// Allow the apply kernels to use up to `bytes` of dynamic LDS (gfx950: 160 KiB per CU).  The
+// attribute is shared by every handle, so it only ever grows (a smaller factor built later must
+// not take LDS away from a larger one), under a lock since factors may be built concurrently.
 void set_apply_smem_limits(size_t bytes) {
+  static std::mutex mu;
+  static size_t granted = 64 * 1024;
+  std::lock_guard<std::mutex> lock(mu);
+  if (bytes <= granted) return;
   const int b = (int)bytes;
 #define HIF_SMEM(K) HIF_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(K),           \
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, b))
@@ -1059,6 +1067,7 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM_ALL(bf16_t, float);
 #undef HIF_SMEM_ALL
 #undef HIF_SMEM
+  granted = bytes;
 }
 
 

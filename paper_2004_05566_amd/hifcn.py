@@ -42,7 +42,8 @@ class _CgOpts(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("root", ctypes.c_int32), ("entries", ctypes.c_int64),
-                ("N", ctypes.c_int64), ("store", ctypes.c_int32), ("dim", ctypes.c_int32)]
+                ("N", ctypes.c_int64), ("store", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
 
 
 class _StageProf(ctypes.Structure):
@@ -63,6 +64,7 @@ _lib.cn_step.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts)
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), _vp]
 _lib.cn_solve.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts), _vp,
                           ctypes.c_int32, _vp, _vp, _vp]
+_lib.cn_batch_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
 _lib.hif_factor_bytes.argtypes = [_vp]
 _lib.hif_factor_bytes.restype = ctypes.c_size_t
 _lib.hif_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
@@ -72,11 +74,11 @@ _lib.hif_destroy.argtypes = [_vp]
 _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
 for _f in ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
-           "hif_get_info", "hif_profile_stage", "hif_profile_read"):
+           "cn_batch_step", "hif_get_info", "hif_profile_stage", "hif_profile_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
-           "hif_factor_bytes", "hif_get_info", "hif_profile_stage", "hif_profile_read",
+           "cn_batch_step", "hif_factor_bytes", "hif_get_info", "hif_profile_stage", "hif_profile_read",
            "hif_destroy", "hif_last_error")
 
 
@@ -177,7 +179,7 @@ class Handle:
         i = _Info()
         _check(_lib.hif_get_info(self._p(), ctypes.byref(i)))
         return {"levels": i.levels, "root": i.root, "entries": i.entries, "N": i.N,
-                "store": i.store, "dim": i.dim}
+                "store": i.store, "dim": i.dim, "device_bytes": i.device_bytes}
 
     def close(self):
         if self._h:
@@ -189,6 +191,28 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+def cn_batch_step(handles, states, reactions, rtols, maxits, streams):
+    """cn_batch_step: one Crank-Nicolson step for each (handle, state) pair, in lockstep, each on
+    its own stream.  Returns (iters, relres, status) arrays; a solve that did not converge has
+    status HIF_ERR_NO_CONV (the others are still advanced); any other failure raises."""
+    count = len(handles)
+    hs = (_vp * max(1, count))(*[h._p() for h in handles])
+    us = (_vp * max(1, count))(*[_dev_f64(u, "u") for u in states])
+    rs = (_Reaction * max(1, count))(*[_Reaction(int(r[0]), float(r[1]), float(r[2]))
+                                      for r in reactions])
+    os_ = (_CgOpts * max(1, count))(*[_CgOpts(float(t), int(m), 0)
+                                      for t, m in zip(rtols, maxits)])
+    ss = (_vp * max(1, count))(*[s.cuda_stream for s in streams])
+    its = np.zeros(max(1, count), np.int32)
+    rel = np.zeros(max(1, count), np.float64)
+    sts = np.zeros(max(1, count), np.int32)
+    st = _lib.cn_batch_step(hs, rs, os_, us, count, its.ctypes.data_as(_vp),
+                            rel.ctypes.data_as(_vp), sts.ctypes.data_as(_vp), ss)
+    if st != HIF_ERR_NO_CONV:
+        _check(st)
+    return its[:count].copy(), rel[:count].copy(), sts[:count].copy()
 
 
 def factor(a_cells, dt: float, n: int, dim: int, eps: float, store: str = "f32",

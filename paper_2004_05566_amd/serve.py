@@ -1,0 +1,314 @@
+"""Continuous-batching server for independent Crank-Nicolson solves on one GPU.
+
+Each request is a whole parabolic solve (its own grid, coefficient a, dt, reaction, step count;
+eq1 and eq_CN, Sec. 2.1) preconditioned by its own HIF factor (Sec. 2.2).  The server
+
+  * admits a request when a slot is free and its estimated HBM footprint fits the budget
+    (a request that could never fit is rejected at once, one that does not fit now waits),
+  * builds its factor on a builder thread, on a stream of its own, while the batch runs,
+  * advances every resident solve by one Crank-Nicolson step per round with one call of the
+    library's batched entry point (each solve on its own stream, PCG iterations queued in
+    lockstep, one convergence read-back per round for the whole batch), so the kernels of
+    different solves overlap on the device and newly built solves join at the next round,
+  * copies a finished solve's state to the host, resolves its future and frees its memory.
+
+A solve's arithmetic does not depend on the other solves in the batch (every kernel touches only
+its own handle's buffers and every reduction has a fixed order), so its result is bitwise the
+same alone and in any mix.  This module only schedules: every step of every solve runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future, ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hifcn
+
+
+@dataclass
+class Request:
+    """One independent solve: n^dim interior nodes, a on the (n+1)^dim cells, u0 on the nodes."""
+
+    n: int
+    a_cells: np.ndarray
+    u0: np.ndarray
+    dt: float
+    nsteps: int
+    eps: float = 1e-4
+    reaction: tuple = (0, 0.0, 1.0)
+    dim: int = 2
+    rtol: float = 1e-8
+    maxit: int = 500
+    store: str = "f32"
+    leaf: int = 8
+    tag: object = None
+
+
+@dataclass
+class Result:
+    u: np.ndarray            # final state, shape n^dim (FP64)
+    iters: np.ndarray        # PCG iterations of every step
+    relres: np.ndarray       # final relative residual of every step
+    t_arrival: float         # perf_counter times
+    t_admit: float
+    t_ready: float
+    t_done: float
+    device_bytes: int        # HBM the solve held while resident
+    tag: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+def estimate_bytes(n: int, dim: int, store: str) -> int:
+    """Upper estimate of the device memory one solve needs while its factor is built.
+
+    The build keeps the factor's blocks in FP64 (up to about 48 entries per DOF for the 2D
+    workloads at eps = 1e-4 and 3x that in 3D) besides their stored copy, plus the PCG
+    workspace and coefficients (about 12 FP64 vectors)."""
+    N = n ** dim
+    entries = 48 if dim == 2 else 144
+    eb = {"f64": 8, "f32": 4, "bf16": 2}[store]
+    return int(N * (entries * (8 + eb) + 12 * 8) + (8 << 20))
+
+
+@dataclass
+class _Job:
+    req: Request
+    fut: Future
+    t_arrival: float
+    est: int
+    held: int = 0
+    t_admit: float = 0.0
+    t_ready: float = 0.0
+    handle: object = None
+    u: object = None
+    stream: object = None
+    step: int = 0
+    iters: list = field(default_factory=list)
+    relres: list = field(default_factory=list)
+
+
+class Server:
+    """Serve Request objects with at most `max_slots` resident solves within `hbm_budget_bytes`.
+
+    submit() returns a concurrent.futures.Future resolved with a Result (or the error)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 32, builders: int = 2,
+                 device: int = 0, paused: bool = False):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.budget = int(hbm_budget_bytes)
+        self.max_slots = int(max_slots)
+        self._cv = threading.Condition()
+        self._waiting: collections.deque[_Job] = collections.deque()
+        self._ready: list[_Job] = []
+        self._active: list[_Job] = []
+        self._held = 0       # bytes reserved by admitted solves
+        self._slots = 0      # admitted solves (building, ready or active)
+        self._streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
+        self._free_streams = list(range(self.max_slots))
+        self._builders = ThreadPoolExecutor(max_workers=max(1, builders),
+                                            thread_name_prefix="hif-build")
+        self._tls = threading.local()
+        self._closing = False
+        self._paused = bool(paused)  # admit and build, but run no rounds until resume()
+        self.rounds = 0
+        self.batch_sizes: list[int] = []
+        self.peak_held = 0
+        self._error: BaseException | None = None
+        self._thread = threading.Thread(target=self._run, name="hif-serve", daemon=True)
+        self._thread.start()
+
+    # -- client side -------------------------------------------------------------------------
+    def submit(self, req: Request, t_arrival: float | None = None) -> Future:
+        fut: Future = Future()
+        if req.dim not in (2, 3) or req.n < 1 or req.nsteps < 1:
+            fut.set_exception(ValueError("bad request: need dim in {2,3}, n >= 1, nsteps >= 1"))
+            return fut
+        if req.a_cells.shape != (req.n + 1,) * req.dim or req.u0.size != req.n ** req.dim:
+            fut.set_exception(ValueError("a_cells must have (n+1)^dim and u0 n^dim values"))
+            return fut
+        est = estimate_bytes(req.n, req.dim, req.store)
+        if est > self.budget:
+            fut.set_exception(MemoryError(
+                f"request needs about {est} bytes of HBM, more than the budget {self.budget}"))
+            return fut
+        job = _Job(req, fut, time.perf_counter() if t_arrival is None else t_arrival, est)
+        with self._cv:
+            if self._closing:
+                raise RuntimeError("server is closed")
+            self._waiting.append(job)
+            self._cv.notify_all()
+        return fut
+
+    def resume(self):
+        """Start the batch rounds of a server created with paused=True."""
+        with self._cv:
+            self._paused = False
+            self._cv.notify_all()
+
+    def ready_count(self) -> int:
+        """Solves whose factor is built and that wait for their first round."""
+        with self._cv:
+            return len(self._ready)
+
+    def close(self, wait: bool = True):
+        """Stop accepting requests; finish (wait=True) every admitted and waiting request."""
+        with self._cv:
+            self._closing = True
+            self._paused = False
+            self._cv.notify_all()
+        if wait:
+            self._thread.join()
+        self._builders.shutdown(wait=wait)
+        if self._error is not None:
+            raise self._error
+
+    def stats(self) -> dict:
+        b = np.array(self.batch_sizes or [0])
+        return {"rounds": self.rounds, "mean_batch": float(b.mean()), "max_batch": int(b.max()),
+                "peak_held_bytes": int(self.peak_held), "budget_bytes": self.budget,
+                "max_slots": self.max_slots}
+
+    # -- builder threads ---------------------------------------------------------------------
+    def _build_stream(self):
+        import torch
+        s = getattr(self._tls, "stream", None)
+        if s is None:
+            s = self._tls.stream = torch.cuda.Stream(device=self.device)
+        return s
+
+    def _build(self, job: _Job):
+        import torch
+        r = job.req
+        s = self._build_stream()
+        with torch.cuda.stream(s):
+            a = torch.as_tensor(np.ascontiguousarray(r.a_cells, dtype=np.float64)).to(
+                self.device, non_blocking=False)
+            u = torch.as_tensor(np.ascontiguousarray(r.u0, dtype=np.float64).ravel()).to(
+                self.device, non_blocking=False)
+            h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf, stream=s)
+            s.synchronize()  # u is ready for the slot's stream, a may be released
+            del a
+        return h, u
+
+    def _destroy(self, handle):
+        handle.close()
+
+    # -- scheduler ---------------------------------------------------------------------------
+    def _admit_locked(self):
+        while self._waiting and self._slots < self.max_slots:
+            job = self._waiting[0]
+            if self._held + job.est > self.budget:
+                break  # first come, first served: later requests wait behind this one
+            self._waiting.popleft()
+            self._slots += 1
+            self._held += job.est
+            job.held = job.est
+            self.peak_held = max(self.peak_held, self._held)
+            job.t_admit = time.perf_counter()
+            job.stream = self._streams[self._free_streams.pop()]
+            f = self._builders.submit(self._build, job)
+            f.add_done_callback(lambda f, job=job: self._built(job, f))
+
+    def _built(self, job: _Job, f):
+        with self._cv:
+            try:
+                job.handle, job.u = f.result()
+            except BaseException as e:  # factor failed: report it and give the slot back
+                self._release_locked(job)
+                job.fut.set_exception(e)
+                self._cv.notify_all()
+                return
+            actual = int(job.handle.info()["device_bytes"])
+            self._held += actual - job.held
+            job.held = actual
+            self.peak_held = max(self.peak_held, self._held)
+            job.t_ready = time.perf_counter()
+            self._ready.append(job)
+            self._cv.notify_all()
+
+    def _release_locked(self, job: _Job):
+        self._slots -= 1
+        self._held -= job.held
+        job.held = 0
+        self._free_streams.append(self._streams.index(job.stream))
+
+    def _finish(self, job: _Job, status: int):
+        r = job.req
+        if status == hifcn.HIF_OK:
+            u = job.u.cpu().numpy().reshape((r.n,) * r.dim)
+            res = Result(u, np.array(job.iters, np.int32), np.array(job.relres), job.t_arrival,
+                         job.t_admit, job.t_ready, time.perf_counter(), job.held, r.tag)
+        h, job.handle, job.u = job.handle, None, None
+        # hipFree waits for the whole device: release on a builder thread, off the batch loop
+        done = self._builders.submit(self._destroy, h)
+        done.add_done_callback(lambda _f, job=job: self._freed(job))
+        if status == hifcn.HIF_OK:
+            job.fut.set_result(res)
+        else:
+            job.fut.set_exception(hifcn.HifError(status, f"PCG did not converge at step "
+                                                         f"{job.step} of {r.nsteps}"))
+
+    def _freed(self, job: _Job):
+        with self._cv:
+            self._release_locked(job)
+            self._cv.notify_all()
+
+    def _run(self):
+        try:
+            while True:
+                with self._cv:
+                    self._admit_locked()
+                    if not self._paused:
+                        self._active.extend(self._ready)
+                        self._ready.clear()
+                    if not self._active:
+                        if self._closing and not self._waiting and self._slots == 0:
+                            return
+                        self._cv.wait(timeout=0.05)
+                        continue
+                    batch = list(self._active)
+                its, rel, sts = hifcn.cn_batch_step(
+                    [j.handle for j in batch], [j.u for j in batch],
+                    [j.req.reaction for j in batch], [j.req.rtol for j in batch],
+                    [j.req.maxit for j in batch], [j.stream for j in batch])
+                self.rounds += 1
+                self.batch_sizes.append(len(batch))
+                finished = []
+                for j, it, rr, st in zip(batch, its, rel, sts):
+                    j.step += 1
+                    j.iters.append(int(it))
+                    j.relres.append(float(rr))
+                    if st != hifcn.HIF_OK or j.step == j.req.nsteps:
+                        finished.append((j, int(st)))
+                if finished:
+                    with self._cv:
+                        for j, _ in finished:
+                            self._active.remove(j)
+                    for j, st in finished:
+                        self._finish(j, st)
+        except BaseException as e:  # fail every outstanding request rather than hang them
+            self._error = e
+            with self._cv:
+                for j in list(self._waiting) + self._ready + self._active:
+                    if not j.fut.done():
+                        j.fut.set_exception(e)
+                self._waiting.clear()
+
+
+def percentiles(latencies, qs=(50, 99)) -> dict:
+    """p50/p99 (nearest-rank) of a list of latencies in seconds."""
+    x = np.sort(np.asarray(latencies, dtype=np.float64))
+    out = {}
+    for q in qs:
+        k = max(0, int(np.ceil(q / 100.0 * x.size)) - 1)
+        out[f"p{q}"] = float(x[k]) if x.size else None
+    return out

@@ -41,3 +41,22 @@ def test_error_path_without_gpu_work():
     assert b"NULL" in lib.hif_last_error() or b"dim" in lib.hif_last_error()
     assert lib.hif_factor_bytes(None) == 0
     lib.hif_destroy(None)
+
+
+def test_batch_step_argument_errors_without_gpu_work():
+    from paper_2004_05566_amd import hifcn
+    lib = hifcn.raw_library()
+    assert lib.cn_batch_step(None, None, None, None, -1, None, None, None, None) == \
+        hifcn.HIF_ERR_ARG
+    assert lib.cn_batch_step(None, None, None, None, 0, None, None, None, None) == hifcn.HIF_OK
+    assert lib.cn_batch_step(None, None, None, None, 2, None, None, None, None) == \
+        hifcn.HIF_ERR_ARG
+    assert b"NULL" in lib.hif_last_error()
+
+
+def test_info_struct_layout():
+    """hif_info_t: 2 x i32, 2 x i64, 2 x i32, i64 (no padding surprises)."""
+    import ctypes
+    from paper_2004_05566_amd import hifcn
+    assert ctypes.sizeof(hifcn._Info) == 40
+    assert hifcn._Info.device_bytes.offset == 32

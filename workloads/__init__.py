@@ -12,7 +12,10 @@ from .gen import (  # noqa: F401
     iid_loguniform_cells,
     iid_uniform_nodes,
     node_coords,
+    poisson_arrivals,
+    serving_request,
     serving_requests,
+    spectral_grf_coefficient,
     sine_mode,
     workload,
     WORKLOADS,

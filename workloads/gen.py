@@ -60,6 +60,32 @@ def grf_coefficient(n: int, dim: int, length: float, seed: int, lo: float = 0.1,
     return a.reshape((n + 1,) * dim)
 
 
+def spectral_grf_coefficient(n: int, dim: int, length: float, seed: int, lo: float = 0.1,
+                             hi: float = 10.0) -> np.ndarray:
+    """Lognormal field a = exp(g) on the cells, mapped to [lo, hi], drawn by FFT filtering.
+
+    g is white noise on a grid twice the cell grid per axis (so the periodic wrap-around of the
+    FFT does not correlate opposite sides of the unit domain), filtered by the square root of
+    the spectral density exp(-(2 pi f length)^2 / 2) of the squared-exponential covariance of
+    length ``length``, and cropped to the (n+1)^dim cells.  Same distribution family as
+    grf_coefficient at O(P log P) cost, for the many mid-size requests of the serving workload.
+    """
+    rng = _rng(seed)
+    m = 2 * (n + 1)
+    noise = rng.normal(size=(m,) * dim)
+    f = np.fft.fftfreq(m, d=1.0 / (n + 1))  # cycles per unit length
+    f2 = sum(np.meshgrid(*([f ** 2] * dim), indexing="ij"))
+    g = np.fft.ifftn(np.fft.fftn(noise) * np.exp(-((2 * np.pi * length) ** 2) * f2 / 4)).real
+    g = g[(slice(0, n + 1),) * dim]
+    t = (g - g.min()) / (g.max() - g.min())
+    return np.exp(np.log(lo) + (np.log(hi) - np.log(lo)) * t)
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (s, from 0) of a Poisson process of `rate` requests per second."""
+    return np.cumsum(_rng(seed).exponential(1.0 / rate, size=count))
+
+
 def iid_loguniform_cells(n: int, dim: int, seed: int, lo_exp: float = -2.0,
                          hi_exp: float = 2.0) -> np.ndarray:
     """Per-cell iid 10^U(lo_exp, hi_exp) on the (n+1)^dim cells."""
@@ -143,17 +169,21 @@ def _heat3d_64() -> Workload:
                     1e-4, 1e-8)
 
 
-def serving_requests(count: int = 256, seed_base: int = 5000) -> list[Workload]:
-    """Independent 2D Fisher-KPP solves of mixed size for the serving workload."""
-    out = []
-    for i in range(count):
-        rng = _rng(seed_base + 10 * i)
-        n = int(rng.choice([64, 128, 256, 512]))
-        dt = float(rng.choice([1e-3, 1e-2, 1e-1]))
-        a = grf_coefficient(n, 2, 0.1, seed_base + 10 * i + 1)
-        u0 = bumps(n, 2, 10, seed_base + 10 * i + 2)
-        out.append(Workload(f"req{i}", 2, n, a, u0, dt, 50, 1e-4, 1e-8, reaction=(1, 1.0, 1.0)))
-    return out
+def serving_request(i: int, seed_base: int = 5000, sizes=(64, 128, 256, 512)) -> Workload:
+    """Request i of the serving workload: an independent 2D Fisher-KPP solve (r = u(1-u)) with
+    its own lognormal coefficient, n drawn from `sizes`, dt from {1e-3, 1e-2, 1e-1}, 50 steps."""
+    rng = _rng(seed_base + 10 * i)
+    n = int(rng.choice(list(sizes)))
+    dt = float(rng.choice([1e-3, 1e-2, 1e-1]))
+    a = spectral_grf_coefficient(n, 2, 0.1, seed_base + 10 * i + 1)
+    u0 = bumps(n, 2, 10, seed_base + 10 * i + 2)
+    return Workload(f"req{i}", 2, n, a, u0, dt, 50, 1e-4, 1e-8, reaction=(1, 1.0, 1.0))
+
+
+def serving_requests(count: int = 256, seed_base: int = 5000, sizes=(64, 128, 256, 512)
+                     ) -> list[Workload]:
+    """The serving workload: `count` independent requests (see serving_request)."""
+    return [serving_request(i, seed_base, sizes) for i in range(count)]
 
 
 WORKLOADS = {
