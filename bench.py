@@ -111,7 +111,7 @@ def copy_probe(nbytes: int):
 
 
 def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
-                  seed_base: int = 5000) -> dict:
+                  builders: int = 8, seed_base: int = 5000) -> dict:
     """The serving workload: `count` independent 2D Fisher-KPP solves of mixed size, dt and
     coefficient (50 CN steps each), arriving as a Poisson process of `rate` requests/s (rate 0:
     all at once), served by continuous batching.  Inputs are drawn before the clock starts."""
@@ -126,14 +126,14 @@ def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
 
     reqs = [req(gen.serving_request(i, seed_base)) for i in range(count)]
     # first-use costs (kernel loading, LDS attributes) outside the clock: one of each size
-    warm = Server(budget_bytes, max_slots)
+    warm = Server(budget_bytes, max_slots, builders)
     for f in [warm.submit(req(gen.serving_request(10_000 + i, seed_base, sizes=(n,))))
               for i, n in enumerate((64, 128, 256, 512))]:
         f.result()
     warm.close()
     arrivals = (gen.poisson_arrivals(count, rate, seed_base + 7) if rate > 0
                 else np.zeros(count))
-    srv = Server(budget_bytes, max_slots)
+    srv = Server(budget_bytes, max_slots, builders)
     finished = [0]
 
     def progress(_f):
@@ -164,7 +164,7 @@ def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
            "mean_build_s": float(np.mean([r.t_ready - r.t_admit for r in res])),
            "mean_queue_s": float(np.mean([r.t_admit - r.t_arrival for r in res])),
            "n_i_mean": float(np.mean(np.concatenate([r.iters for r in res]))),
-           "sizes": sorted({int(r.u.shape[0]) for r in res}),
+           "sizes": sorted({int(r.u.shape[0]) for r in res}), "builders": builders,
            **st}
     return out
 
@@ -220,6 +220,8 @@ def main(argv=None):
     ap.add_argument("--serving-rate", type=float, default=40.0,
                     help="Poisson arrival rate of serving requests per second (0: all at once)")
     ap.add_argument("--serving-slots", type=int, default=32)
+    ap.add_argument("--serving-builders", type=int, default=8,
+                    help="threads (each with its own stream) building factors concurrently")
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -240,7 +242,7 @@ def main(argv=None):
 
     def serving():
         return serving_bench(args.serving, args.serving_rate, args.serving_slots,
-                             int(args.serving_budget_gb * (1 << 30)))
+                             int(args.serving_budget_gb * (1 << 30)), args.serving_builders)
 
     if args.serving_only:
         print(json.dumps({"serving": serving()}))

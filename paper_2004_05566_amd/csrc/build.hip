@@ -18,8 +18,10 @@
 // launches; only ranks and pivot orders come back from the device once per level.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <unordered_map>
 
+#include "front.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -469,6 +471,10 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   const Geometry geo{hd.dim, hd.n, hd.leaf, hd.L};
   DevBuf<int> err(1);
   HIF_CHECK(hipMemsetAsync(err.p, 0, sizeof(int), s));
+  // cells with at least this many interior DOFs (and the root) use the blocked front path;
+  // HIFCN_FRONT_MIN overrides it (tests force either path on small grids)
+  int front_min = 128;
+  if (const char* e = std::getenv("HIFCN_FRONT_MIN")) front_min = std::max(1, std::atoi(e));
   auto check_err = [&](const char* where) {
     int e = 0;
     HIF_CHECK(hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -592,19 +598,37 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       t.offIb = (int32_t)ibl.size();
       ibl.insert(ibl.end(), cell_ib[ci].begin(), cell_ib[ci].end());
     }
+    // large cells (dense H) go through the blocked front elimination on the matrix cores
+    std::vector<CellTask> small;
+    std::vector<FrontTask> fronts;
+    std::vector<FrontSub> fsubs;
+    woff = 0;
+    for (CellTask t : ct) {
+      if (t.mode == 0 && t.nI >= front_min) {
+        fronts.push_back({t.nI, t.nB, t.nsub, (int32_t)fsubs.size(), t.offAII, t.offV, t.offS,
+                          0, 0});
+        for (int q = 0; q < t.nsub; ++q) fsubs.push_back({subs[t.offSub + q].off,
+                                                          subs[t.offSub + q].width, 0});
+      } else {
+        t.offW = woff;
+        woff += 2 * (int64_t)t.nI * t.nI + (int64_t)t.nI * t.nB;
+        small.push_back(t);
+      }
+    }
     {
       DevBuf<CellTask> dct;
       DevBuf<SubBlk> dsub;
       DevBuf<int32_t> dibl;
       DevBuf<double> work(std::max<int64_t>(1, woff));
       DevBuf<double> schur(std::max<int64_t>(1, soff));
-      upload(dct, ct, s);
+      upload(dct, small, s);
       upload(dsub, subs, s);
       upload(dibl, ibl, s);
-      if (!ct.empty())
-        hipLaunchKernelGGL(k_build_cells, dim3(ct.size()), dim3(kBT), 0, s, dct.p, dsub.p, dibl.p,
-                           A.p, work.p, schur.p, fv.p, err.p);
+      if (!small.empty())
+        hipLaunchKernelGGL(k_build_cells, dim3(small.size()), dim3(kBT), 0, s, dct.p, dsub.p,
+                           dibl.p, A.p, work.p, schur.p, fv.p, err.p);
       HIF_CHECK(hipGetLastError());
+      build_fronts(fronts, fsubs, A.p, schur.p, fv.p, err.p, s);
       // Schur assembly into every separator block touched by some cell
       std::vector<std::vector<Contrib>> per_block(P.blocks.size());
       for (size_t ci = 0; ci < P.cells.size(); ++ci) {
@@ -885,7 +909,11 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   const int rg = P.cells[0];
   const int nroot = (int)P.groups[rg].dofs.size();
   DevBuf<double> rchunk(std::max<int64_t>(1, tri64(nroot)));
-  {
+  if (nroot >= front_min) {
+    build_fronts({FrontTask{nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, -1, 0, 0}}, {},
+                 A.p, nullptr, rchunk.p, err.p, s);
+    check_err("root factorization");
+  } else {
     std::vector<CellTask> ct(1);
     ct[0] = {nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, 0, 0, 0, 0};
     DevBuf<CellTask> dct;

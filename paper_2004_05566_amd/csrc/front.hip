@@ -1,0 +1,361 @@
+// Dense FP64 elimination of large cells and of the root on the matrix cores (Sec. 2.2: the cell
+// elimination of eq2_3 and the root Cholesky of eq3_4).
+//
+// A cell with interior I and boundary B is eliminated through the augmented front
+//
+//          [ A_II  A_IB ]      rows I (nI), B (nB), E (nI); columns I, B; only the lower
+//     F =  [ A_BI   0   ]      triangle is used (F is symmetric)
+//          [  I         ]
+//
+// by a blocked right-looking Cholesky over the nI interior columns.  Afterwards its lower
+// triangle holds
+//     I rows : L = chol(A_II)
+//     B rows : A_BI L^-T = G^T              with G = L^-1 A_IB
+//     E rows : L^-T                         (row j of E is column j of L^-1)
+//     B x B  : -G^T G = -S                  (minus the Schur complement)
+// so one pass yields every block the apply and the next level need; H = G^T L^-1 is one more
+// product.  Per panel of 64 columns: the diagonal block is factored and inverted by one
+// workgroup, the panel rows are multiplied by that inverse, and the trailing update runs as
+// 64 x 64 tiles of v_mfma_f64_16x16x4f64.  The update is restricted to what the results above
+// read: E rows only against interior columns, and only the E rows that are nonzero so far
+// (L^-T is upper triangular, so E row j is zero left of column j).
+#include <algorithm>
+
+#include "front.hpp"
+
+namespace hifcn {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 64;         // output tile and panel width
+constexpr int kKc = 32;        // K chunk staged in LDS
+constexpr int kLd = kKc + 1;   // LDS row stride of a staged chunk (doubles)
+constexpr int kThreads = 256;  // 4 wavefronts; wave w owns the 32 x 32 quadrant (w / 2, w % 2)
+
+__device__ __forceinline__ int64_t front_ld(const FrontTask& t) { return t.nI + t.nB; }
+
+// Stage rows [0, rows) x columns [0, kv) of src (leading dimension ld) into S (64 x kKc,
+// stride kLd), zero elsewhere.
+__device__ __forceinline__ void stage(double* S, const double* src, int64_t ld, int rows, int kv) {
+  for (int e = threadIdx.x; e < kT * kKc; e += kThreads) {
+    const int r = e / kKc, c = e - r * kKc;
+    S[r * kLd + c] = (r < rows && c < kv) ? src[(int64_t)r * ld + c] : 0.0;
+  }
+}
+
+// acc += As (64 x kKc) * Bs (64 x kKc)^T.  MFMA 16x16x4 FP64 operands: lane l holds A[l%16][l/16]
+// and B^T[l%16][l/16]; accumulator element r of lane l is row 4r + l/16, column l%16 (the FP64
+// form interleaves the rows, unlike the 4(l/16) + r of the FP16/BF16 forms).
+__device__ __forceinline__ void mfma_chunk(const double* As, const double* Bs, d4 acc[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int ra = 32 * (w >> 1), cb = 32 * (w & 1);
+#pragma unroll
+  for (int k0 = 0; k0 < kKc; k0 += 4) {
+    const double a0 = As[(ra + i) * kLd + k0 + kk];
+    const double a1 = As[(ra + 16 + i) * kLd + k0 + kk];
+    const double b0 = Bs[(cb + i) * kLd + k0 + kk];
+    const double b1 = Bs[(cb + 16 + i) * kLd + k0 + kk];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// Tile position of accumulator element (a, b, r) of this lane.
+__device__ __forceinline__ void acc_pos(int a, int b, int r, int* row, int* col) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  *row = 32 * (w >> 1) + 16 * a + 4 * r + (lane >> 4);
+  *col = 32 * (w & 1) + 16 * b + (lane & 15);
+}
+
+// acc = A (rows x K) * B (cols x K)^T over k in [k_begin, k_end), both row-major with ld.
+__device__ void tile_nt(const double* A, const double* B, int64_t ld, int rows, int cols,
+                        int k_begin, int k_end, d4 acc[2][2]) {
+  __shared__ double As[kT * kLd], Bs[kT * kLd];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = k_begin; k0 < k_end; k0 += kKc) {
+    const int kv = min(kKc, k_end - k0);
+    stage(As, A + k0, ld, rows, kv);
+    stage(Bs, B + k0, ld, cols, kv);
+    __syncthreads();
+    mfma_chunk(As, Bs, acc);
+    __syncthreads();
+  }
+}
+
+// Row segments of a panel step at column k (width w): interior rows below the panel, all
+// boundary rows, and the E rows that are nonzero so far.  Block index -> (first row, rows).
+__device__ bool panel_rows(const FrontTask& t, int k, int w, int blk, int* r0, int* rows,
+                           int* seg) {
+  const int s1 = t.nI - k - w, s2 = t.nB, s3 = min(k + w, t.nI);
+  const int b1 = (s1 + kT - 1) / kT, b2 = (s2 + kT - 1) / kT, b3 = (s3 + kT - 1) / kT;
+  if (blk < b1) {
+    *seg = 0;
+    *r0 = k + w + blk * kT;
+    *rows = min(kT, t.nI - *r0);
+  } else if (blk < b1 + b2) {
+    *seg = 1;
+    *r0 = t.nI + (blk - b1) * kT;
+    *rows = min(kT, t.nI + t.nB - *r0);
+  } else if (blk < b1 + b2 + b3) {
+    *seg = 2;
+    const int j0 = (blk - b1 - b2) * kT;
+    *r0 = t.nI + t.nB + j0;
+    *rows = min(kT, s3 - j0);
+  } else {
+    return false;
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kThreads) void k_front_init(const FrontTask* __restrict__ tasks,
+                                                         const FrontSub* __restrict__ subs,
+                                                         const double* __restrict__ A,
+                                                         double* __restrict__ F) {
+  const FrontTask t = tasks[blockIdx.y];
+  const int64_t ld = front_ld(t);
+  const int R = 2 * t.nI + t.nB;
+  for (int r = blockIdx.x * 4; r < min(R, (int)blockIdx.x * 4 + 4); ++r) {
+    double* row = F + t.offF + (int64_t)r * ld;
+    if (r < t.nI) {
+      for (int c = threadIdx.x; c < ld; c += kThreads)
+        row[c] = c < t.nI ? A[t.offAII + (int64_t)r * t.nI + c] : 0.0;
+    } else if (r < t.nI + t.nB) {
+      // boundary DOF b lies in column block q at local column b - c0
+      const int b = r - t.nI;
+      int q = 0, c0 = 0;
+      while (q + 1 < t.nsub && b >= c0 + subs[t.offSub + q].width) c0 += subs[t.offSub + q++].width;
+      const FrontSub sb = subs[t.offSub + q];
+      for (int c = threadIdx.x; c < ld; c += kThreads)
+        row[c] = c < t.nI ? A[sb.off + (int64_t)c * sb.width + (b - c0)] : 0.0;
+    } else {
+      const int j = r - t.nI - t.nB;
+      for (int c = threadIdx.x; c < ld; c += kThreads) row[c] = (c == j) ? 1.0 : 0.0;
+    }
+  }
+}
+
+// Factor the diagonal block of the panel at column k in LDS, write L11 back and L11^-1 to D.
+__global__ __launch_bounds__(kThreads) void k_front_diag(const FrontTask* __restrict__ tasks,
+                                                         int k, double* __restrict__ F,
+                                                         double* __restrict__ D, int* err) {
+  __shared__ double Ls[kT * (kT + 1)], Ys[kT * (kT + 1)];
+  constexpr int ls = kT + 1;
+  const FrontTask t = tasks[blockIdx.x];
+  const int w = min(kT, t.nI - k);
+  if (w <= 0) return;
+  const int64_t ld = front_ld(t);
+  double* Fk = F + t.offF + (int64_t)k * ld + k;
+  for (int e = threadIdx.x; e < kT * kT; e += kThreads) {
+    const int i = e / kT, j = e - i * kT;
+    Ls[i * ls + j] = (i < w && j <= i) ? Fk[(int64_t)i * ld + j] : 0.0;
+    Ys[i * ls + j] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    if (threadIdx.x == 0) {
+      double d = Ls[j * ls + j];
+      if (!(d > 0.0) || !(d < 1.0e300)) {
+        *err = 1;
+        d = 1.0;
+      }
+      Ls[j * ls + j] = sqrt(d);
+    }
+    __syncthreads();
+    const double p = Ls[j * ls + j];
+    for (int i = j + 1 + threadIdx.x; i < w; i += kThreads) Ls[i * ls + j] /= p;
+    __syncthreads();
+    const int m = w - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += kThreads) {
+      const int r = e / m, c = e - r * m;
+      if (c <= r) Ls[(j + 1 + r) * ls + j + 1 + c] -= Ls[(j + 1 + r) * ls + j] * Ls[(j + 1 + c) * ls + j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < w * w; e += kThreads) {
+    const int i = e / w, j = e - i * w;
+    if (j <= i) Fk[(int64_t)i * ld + j] = Ls[i * ls + j];
+  }
+  // column c of L11^-1 by forward substitution, one thread per column
+  if (threadIdx.x < w) {
+    const int c = threadIdx.x;
+    Ys[c * ls + c] = 1.0 / Ls[c * ls + c];
+    for (int i = c + 1; i < w; ++i) {
+      double acc = 0.0;
+      for (int q = c; q < i; ++q) acc += Ls[i * ls + q] * Ys[q * ls + c];
+      Ys[i * ls + c] = -acc / Ls[i * ls + i];
+    }
+  }
+  __syncthreads();
+  double* Dt = D + t.offD;
+  for (int e = threadIdx.x; e < kT * kT; e += kThreads) {
+    const int i = e / kT, j = e - i * kT;
+    Dt[e] = Ys[i * ls + j];
+  }
+}
+
+// Panel rows times L11^-T: X[r][:] = F[r][k:k+w] L11^-T.
+__global__ __launch_bounds__(kThreads) void k_front_panel(const FrontTask* __restrict__ tasks,
+                                                          int k, double* __restrict__ F,
+                                                          const double* __restrict__ D) {
+  const FrontTask t = tasks[blockIdx.y];
+  const int w = min(kT, t.nI - k);
+  if (w <= 0) return;
+  int r0, rows, seg;
+  if (!panel_rows(t, k, w, blockIdx.x, &r0, &rows, &seg)) return;
+  const int64_t ld = front_ld(t);
+  double* Fr = F + t.offF + (int64_t)r0 * ld + k;
+  d4 acc[2][2];
+  // B operand: D (64 x 64, ld 64) staged in the same chunks
+  __shared__ double As[kT * kLd], Bs[kT * kLd];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < w; k0 += kKc) {
+    const int kv = min(kKc, w - k0);
+    stage(As, Fr + k0, ld, rows, kv);
+    stage(Bs, D + t.offD + k0, kT, kT, kv);
+    __syncthreads();
+    mfma_chunk(As, Bs, acc);
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(a, b, r, &row, &col);
+        if (row < rows && col < w) Fr[(int64_t)row * ld + col] = acc[a][b][r];
+      }
+}
+
+// Trailing update F[r][c] -= sum_t X[r][t] X[c][t] over the columns right of the panel.
+__global__ __launch_bounds__(kThreads) void k_front_update(const FrontTask* __restrict__ tasks,
+                                                           int k, double* __restrict__ F) {
+  const FrontTask t = tasks[blockIdx.z];
+  const int w = min(kT, t.nI - k);
+  if (w <= 0) return;
+  int r0, rows, seg;
+  if (!panel_rows(t, k, w, blockIdx.y, &r0, &rows, &seg)) return;
+  const int c0 = k + w + blockIdx.x * kT;
+  const int cmax = seg == 2 ? t.nI - 1 : r0 + rows - 1;  // E rows: interior columns only
+  if (c0 > cmax) return;
+  const int cols = min(kT, cmax - c0 + 1);
+  const int64_t ld = front_ld(t);
+  double* base = F + t.offF;
+  d4 acc[2][2];
+  tile_nt(base + (int64_t)r0 * ld + k, base + (int64_t)c0 * ld + k, ld, rows, cols, 0, w, acc);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(a, b, r, &row, &col);
+        if (row < rows && col < cols && (seg == 2 || c0 + col <= r0 + row))
+          base[(int64_t)(r0 + row) * ld + c0 + col] -= acc[a][b][r];
+      }
+}
+
+// Packed column-major L^-1 from the E rows and S = -(B x B block), symmetric, row-major.
+__global__ __launch_bounds__(kThreads) void k_front_out(const FrontTask* __restrict__ tasks,
+                                                        const double* __restrict__ F,
+                                                        double* __restrict__ fv,
+                                                        double* __restrict__ schur) {
+  const FrontTask t = tasks[blockIdx.y];
+  const int64_t ld = front_ld(t);
+  const int j = blockIdx.x;
+  const double* Fb = F + t.offF;
+  if (j < t.nI) {
+    const double* e = Fb + (int64_t)(t.nI + t.nB + j) * ld;
+    double* v = fv + t.offV + colstart(j, t.nI) - j;
+    for (int i = j + threadIdx.x; i < t.nI; i += kThreads) v[i] = e[i];
+  }
+  if (j < t.nB && t.offS >= 0) {
+    double* srow = schur + t.offS + (int64_t)j * t.nB;
+    for (int b = threadIdx.x; b < t.nB; b += kThreads) {
+      const int hi = max(j, b), lo = min(j, b);
+      srow[b] = -Fb[(int64_t)(t.nI + hi) * ld + t.nI + lo];
+    }
+  }
+}
+
+// H = G^T L^-1 (nB x nI, stored column-major): H[b][j] = sum_{i >= j} G^T[b][i] E[j][i].
+__global__ __launch_bounds__(kThreads) void k_front_h(const FrontTask* __restrict__ tasks,
+                                                      const double* __restrict__ F,
+                                                      double* __restrict__ fv) {
+  const FrontTask t = tasks[blockIdx.z];
+  const int b0 = blockIdx.y * kT, j0 = blockIdx.x * kT;
+  if (b0 >= t.nB || j0 >= t.nI) return;
+  const int64_t ld = front_ld(t);
+  const double* Fb = F + t.offF;
+  const int rows = min(kT, t.nB - b0), cols = min(kT, t.nI - j0);
+  d4 acc[2][2];
+  tile_nt(Fb + (int64_t)(t.nI + b0) * ld, Fb + (int64_t)(t.nI + t.nB + j0) * ld, ld, rows, cols,
+          j0, t.nI, acc);
+  double* H = fv + t.offV + tri_count(t.nI);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(a, b, r, &row, &col);
+        if (row < rows && col < cols) H[(int64_t)(j0 + col) * t.nB + b0 + row] = acc[a][b][r];
+      }
+}
+
+int cdiv(int64_t a, int b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
+                  const double* A, double* schur, double* fv, int* err, hipStream_t s) {
+  if (tasks.empty()) return;
+  int64_t foff = 0;
+  int maxR = 0, maxI = 0, maxB = 0, maxLd = 0;
+  for (size_t q = 0; q < tasks.size(); ++q) {
+    FrontTask& t = tasks[q];
+    t.offF = foff;
+    t.offD = (int64_t)q * kT * kT;
+    foff += (int64_t)(2 * t.nI + t.nB) * (t.nI + t.nB);
+    maxR = std::max(maxR, 2 * t.nI + t.nB);
+    maxI = std::max(maxI, t.nI);
+    maxB = std::max(maxB, t.nB);
+    maxLd = std::max(maxLd, t.nI + t.nB);
+  }
+  const int nt = (int)tasks.size();
+  DevBuf<double> F(foff), D((size_t)nt * kT * kT);
+  DevBuf<FrontTask> dt;
+  DevBuf<FrontSub> ds;
+  dt.upload(tasks, s);
+  std::vector<FrontSub> sv = subs.empty() ? std::vector<FrontSub>(1) : subs;
+  ds.upload(sv, s);
+  hipLaunchKernelGGL(k_front_init, dim3(cdiv(maxR, 4), nt), dim3(kThreads), 0, s, dt.p, ds.p, A,
+                     F.p);
+  for (int k = 0; k < maxI; k += kT) {
+    // grid extents: the largest task at this panel (smaller ones exit at once)
+    int prow = 0, pcol = 0;
+    for (const FrontTask& t : tasks) {
+      const int w = std::min(kT, t.nI - k);
+      if (w <= 0) continue;
+      prow = std::max(prow, cdiv(t.nI - k - w, kT) + cdiv(t.nB, kT) +
+                                cdiv(std::min(k + w, t.nI), kT));
+      pcol = std::max(pcol, cdiv(t.nI + t.nB - k - w, kT));
+    }
+    hipLaunchKernelGGL(k_front_diag, dim3(nt), dim3(kThreads), 0, s, dt.p, k, F.p, D.p, err);
+    hipLaunchKernelGGL(k_front_panel, dim3(prow, nt), dim3(kThreads), 0, s, dt.p, k, F.p, D.p);
+    if (pcol > 0)
+      hipLaunchKernelGGL(k_front_update, dim3(pcol, prow, nt), dim3(kThreads), 0, s, dt.p, k,
+                         F.p);
+  }
+  hipLaunchKernelGGL(k_front_out, dim3(std::max(maxI, maxB), nt), dim3(kThreads), 0, s, dt.p,
+                     F.p, fv, schur);
+  if (maxB > 0)
+    hipLaunchKernelGGL(k_front_h, dim3(cdiv(maxI, kT), cdiv(maxB, kT), nt), dim3(kThreads), 0, s,
+                       dt.p, F.p, fv);
+  HIF_CHECK(hipGetLastError());
+  // F and D are released when this returns: the caller's next check synchronises the stream,
+  // and hipFree waits for the kernels that use them.
+}
+
+}  // namespace hifcn

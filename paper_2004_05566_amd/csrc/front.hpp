@@ -1,0 +1,30 @@
+// Dense FP64 elimination of large cells and of the root on the matrix cores (Sec. 2.2, eq2_3,
+// eq3_4).  Used by the factor build for cells too large for one workgroup.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace hifcn {
+
+// One cell to eliminate.  Inputs live in the build's block table A (row-major blocks): A_II
+// (nI x nI at offAII) and A_IB as nsub column blocks (nI x width at FrontSub.off).  Outputs:
+// packed column-major L^-1 (nI(nI+1)/2) at fv + offV followed, if nB > 0, by H = A_BI A_II^-1
+// column-major (nB x nI), and the Schur complement S = A_BI A_II^-1 A_IB (nB x nB row-major) at
+// schur + offS.
+struct FrontTask {
+  int32_t nI, nB, nsub, offSub;
+  int64_t offAII, offV, offS;
+  int64_t offF, offD;  // internal: the front and the diagonal-block inverse (set by the driver)
+};
+struct FrontSub {
+  int64_t off;
+  int32_t width, pad;
+};
+
+// Factor every task (batched: each kernel covers all tasks).  A non-positive pivot raises *err.
+void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
+                  const double* A, double* schur, double* fv, int* err, hipStream_t s);
+
+}  // namespace hifcn
