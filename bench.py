@@ -21,6 +21,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix, published
 STAGES = ["cell_fwd", "group_fwd", "root", "group_bwd", "cell_bwd"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "cell_stage_level0_pmc.json")
 APPLY_SRC = os.path.join(ROOT, "paper_2004_05566_amd", "csrc", "apply.hip")
@@ -57,6 +58,15 @@ def _time_op(fn, reps):
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def _build_mfma(info: dict) -> dict:
+    """The factor build's matrix-core work (large cells and root): algorithmic FP64 flops over the
+    summed duration of those kernels, against the FP64 matrix peak."""
+    fl, ms = info["build_mfma_flops"], info["build_mfma_ms"]
+    tf = fl / (ms * 1e9) if ms > 0 else None
+    return {"flops": fl, "ms": ms, "TFLOP/s": tf, "peak": FP64_MFMA_PEAK_TFLOPS,
+            "frac": tf / FP64_MFMA_PEAK_TFLOPS if tf else None}
 
 
 def _src_sha() -> str:
@@ -317,6 +327,7 @@ def main(argv=None):
         "n_i_mean": float(np.mean(its)),
         "f64_store": {"value": args.steps / el64, "n_i_mean": float(np.mean(its64))},
         "t_factor_s": t_factor,
+        "build_mfma": _build_mfma(h.info()),
         "factor_bytes": fb,
         "apply": {"us": t_apply * 1e6, "GB/s": apply_bytes / t_apply / 1e9,
                   "bytes": apply_bytes},

@@ -126,9 +126,11 @@ hif_status_t cn_batch_step(hif_handle_t* h, const hif_reaction_t* r, const hif_c
  * hif_apply reads; one apply reads them twice. */
 size_t hif_factor_bytes(hif_handle_t h);
 
-/* Structure summary: number of levels, root size, stored factor entries, and every byte of
- * device memory the handle holds (factor, descriptors and PCG workspace; what a server admitting
- * solves by HBM footprint accounts for). */
+/* Structure summary: number of levels, root size, stored factor entries, every byte of device
+ * memory the handle holds (factor, descriptors and PCG workspace; what a server admitting solves
+ * by HBM footprint accounts for), and the part of the build that ran on the FP64 matrix cores
+ * (large cells and the root, Sec. 2.2): its algorithmic flops and the summed duration of those
+ * kernels (0 for imported factors). */
 typedef struct {
   int32_t levels;
   int32_t root;
@@ -137,6 +139,8 @@ typedef struct {
   int32_t store;
   int32_t dim;
   int64_t device_bytes;
+  int64_t build_mfma_flops;
+  double build_mfma_ms;
 } hif_info_t;
 hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
 

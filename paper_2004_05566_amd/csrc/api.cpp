@@ -369,6 +369,8 @@ hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
     info->store = (int32_t)h.f.store;
     info->dim = h.dim;
     info->device_bytes = handle_device_bytes(h);
+    info->build_mfma_flops = h.f.mfma_flops;
+    info->build_mfma_ms = h.f.mfma_ms;
   });
 }
 

@@ -475,6 +475,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   // HIFCN_FRONT_MIN overrides it (tests force either path on small grids)
   int front_min = 128;
   if (const char* e = std::getenv("HIFCN_FRONT_MIN")) front_min = std::max(1, std::atoi(e));
+  FrontStats fstats;
   auto check_err = [&](const char* where) {
     int e = 0;
     HIF_CHECK(hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -628,7 +629,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         hipLaunchKernelGGL(k_build_cells, dim3(small.size()), dim3(kBT), 0, s, dct.p, dsub.p,
                            dibl.p, A.p, work.p, schur.p, fv.p, err.p);
       HIF_CHECK(hipGetLastError());
-      build_fronts(fronts, fsubs, A.p, schur.p, fv.p, err.p, s);
+      build_fronts(fronts, fsubs, A.p, schur.p, fv.p, err.p, s, &fstats);
       // Schur assembly into every separator block touched by some cell
       std::vector<std::vector<Contrib>> per_block(P.blocks.size());
       for (size_t ci = 0; ci < P.cells.size(); ++ci) {
@@ -911,7 +912,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   DevBuf<double> rchunk(std::max<int64_t>(1, tri64(nroot)));
   if (nroot >= front_min) {
     build_fronts({FrontTask{nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, -1, 0, 0}}, {},
-                 A.p, nullptr, rchunk.p, err.p, s);
+                 A.p, nullptr, rchunk.p, err.p, s, &fstats);
     check_err("root factorization");
   } else {
     std::vector<CellTask> ct(1);
@@ -992,6 +993,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     cbmax = std::max(cbmax, lo.cbn);
   }
   f.nroot = nroot;
+  f.mfma_flops = fstats.flops;
+  f.mfma_ms = fstats.ms;
   f.root_bytes = (int64_t)store_elem_bytes(store) * tri64(nroot) + 20 * (int64_t)nroot;
   f.offRootIdx = (int32_t)idx.size();
   idx.insert(idx.end(), P.groups[rg].dofs.begin(), P.groups[rg].dofs.end());

@@ -19,6 +19,8 @@
 // 64 x 64 tiles of v_mfma_f64_16x16x4f64.  The update is restricted to what the results above
 // read: E rows only against interior columns, and only the E rows that are nonzero so far
 // (L^-T is upper triangular, so E row j is zero left of column j).
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "front.hpp"
@@ -309,8 +311,23 @@ int cdiv(int64_t a, int b) { return (int)((a + b - 1) / b); }
 }  // namespace
 
 void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
-                  const double* A, double* schur, double* fv, int* err, hipStream_t s) {
+                  const double* A, double* schur, double* fv, int* err, hipStream_t s,
+                  FrontStats* stats) {
   if (tasks.empty()) return;
+  // event pairs around every matrix-core launch (only when statistics are wanted)
+  std::vector<hipEvent_t> ev;
+  auto timed = [&](auto kernel, dim3 grid, auto... args) {
+    if (!stats) {
+      hipLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, s, args...);
+      return;
+    }
+    hipEvent_t e0, e1;
+    HIF_CHECK(hipEventCreate(&e0));
+    HIF_CHECK(hipEventCreate(&e1));
+    ev.push_back(e0);
+    ev.push_back(e1);
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, s, e0, e1, 0, args...);
+  };
   int64_t foff = 0;
   int maxR = 0, maxI = 0, maxB = 0, maxLd = 0;
   for (size_t q = 0; q < tasks.size(); ++q) {
@@ -343,17 +360,36 @@ void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& sub
       pcol = std::max(pcol, cdiv(t.nI + t.nB - k - w, kT));
     }
     hipLaunchKernelGGL(k_front_diag, dim3(nt), dim3(kThreads), 0, s, dt.p, k, F.p, D.p, err);
-    hipLaunchKernelGGL(k_front_panel, dim3(prow, nt), dim3(kThreads), 0, s, dt.p, k, F.p, D.p);
-    if (pcol > 0)
-      hipLaunchKernelGGL(k_front_update, dim3(pcol, prow, nt), dim3(kThreads), 0, s, dt.p, k,
-                         F.p);
+    timed(k_front_panel, dim3(prow, nt), (const FrontTask*)dt.p, k, F.p, (const double*)D.p);
+    if (pcol > 0) timed(k_front_update, dim3(pcol, prow, nt), (const FrontTask*)dt.p, k, F.p);
   }
   hipLaunchKernelGGL(k_front_out, dim3(std::max(maxI, maxB), nt), dim3(kThreads), 0, s, dt.p,
                      F.p, fv, schur);
   if (maxB > 0)
-    hipLaunchKernelGGL(k_front_h, dim3(cdiv(maxI, kT), cdiv(maxB, kT), nt), dim3(kThreads), 0, s,
-                       dt.p, F.p, fv);
+    timed(k_front_h, dim3(cdiv(maxI, kT), cdiv(maxB, kT), nt), (const FrontTask*)dt.p,
+          (const double*)F.p, fv);
   HIF_CHECK(hipGetLastError());
+  if (stats) {
+    // algorithmic flops: panel X = F L11^-T (w(w+1) per row), the trailing update over the
+    // rows and columns the results read (2w per entry), H = G^T L^-1 (triangular)
+    for (const FrontTask& t : tasks) {
+      for (int k = 0; k < t.nI; k += kT) {
+        const int64_t w = std::min(kT, t.nI - k), m = t.nI - k - w, e = std::min<int64_t>(k + w, t.nI);
+        stats->flops += w * (w + 1) * (m + t.nB + e);
+        stats->flops += 2 * w * (m * (m + 1) / 2 + (int64_t)t.nB * m +
+                                 (int64_t)t.nB * (t.nB + 1) / 2 + e * m);
+      }
+      stats->flops += (int64_t)t.nB * t.nI * (t.nI + 1);
+    }
+    HIF_CHECK(hipStreamSynchronize(s));
+    for (size_t q = 0; q < ev.size(); q += 2) {
+      float ms = 0;
+      HIF_CHECK(hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+      stats->ms += ms;
+      ++stats->launches;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
   // F and D are released when this returns: the caller's next check synchronises the stream,
   // and hipFree waits for the kernels that use them.
 }

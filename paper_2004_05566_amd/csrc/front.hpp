@@ -23,8 +23,18 @@ struct FrontSub {
   int32_t width, pad;
 };
 
+// Work done on the matrix cores: algorithmic FP64 flops of the panel, trailing-update and H
+// products, and the summed durations of those kernels (HIP events around each launch).
+struct FrontStats {
+  int64_t flops = 0;
+  double ms = 0;
+  int64_t launches = 0;
+};
+
 // Factor every task (batched: each kernel covers all tasks).  A non-positive pivot raises *err.
+// Synchronises the stream when `stats` is given (to read the kernel timings).
 void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
-                  const double* A, double* schur, double* fv, int* err, hipStream_t s);
+                  const double* A, double* schur, double* fv, int* err, hipStream_t s,
+                  FrontStats* stats = nullptr);
 
 }  // namespace hifcn

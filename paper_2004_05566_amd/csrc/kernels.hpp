@@ -71,6 +71,9 @@ struct FactorDev {
   DevBuf<double> wsc;   // interiors of tiled cells between the forward and backward sweep
   LevelDev rootlv;      // the root as a one-cell level, used when it is tiled
   bool root_tiled = false;
+  // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
+  int64_t mfma_flops = 0;
+  double mfma_ms = 0;
 };
 
 // Host-side, FP64 version of the same layout (used by import; the GPU build writes the device

@@ -55,8 +55,9 @@ def test_batch_step_argument_errors_without_gpu_work():
 
 
 def test_info_struct_layout():
-    """hif_info_t: 2 x i32, 2 x i64, 2 x i32, i64 (no padding surprises)."""
+    """hif_info_t: 2 x i32, 2 x i64, 2 x i32, 2 x i64, f64 (no padding surprises)."""
     import ctypes
     from paper_2004_05566_amd import hifcn
-    assert ctypes.sizeof(hifcn._Info) == 40
+    assert ctypes.sizeof(hifcn._Info) == 56
     assert hifcn._Info.device_bytes.offset == 32
+    assert hifcn._Info.build_mfma_ms.offset == 48
