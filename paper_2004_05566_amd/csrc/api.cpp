@@ -192,7 +192,7 @@ int64_t handle_device_bytes(const Handle& h) {
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc);
   auto add_level = [&](const LevelDev& l) {
-    add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles);
+    add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.owned);
   };
   for (const LevelDev& l : f.lv) add_level(l);
   add_level(f.rootlv);
@@ -420,15 +420,20 @@ hif_status_t hif_profile_read(hif_handle_t hh, hif_stage_prof_t* out) {
     out->stage = p.stage;
     out->launches = p.launches;
     out->ms = p.ms;
+    // a fused launch carries the bytes of every stage it runs
     int64_t bytes = 0;
+    const int nlev = (int)h.f.lv.size();
     if (p.stage == STAGE_ROOT) {
       bytes = h.f.root_bytes;
-    } else if (p.level < (int)h.f.lv.size()) {
+      if (h.f.root_fused)
+        bytes += h.f.lv[nlev - 1].group_bytes[0] + h.f.lv[nlev - 1].group_bytes[1];
+    } else if (p.level < nlev) {
       const LevelDev& L = h.f.lv[p.level];
       bytes = p.stage == STAGE_CELL_FWD   ? L.cell_bytes[0]
               : p.stage == STAGE_CELL_BWD ? L.cell_bytes[1]
               : p.stage == STAGE_GROUP_FWD ? L.group_bytes[0]
                                            : L.group_bytes[1];
+      if (p.stage == STAGE_GROUP_FWD && L.fuse) bytes += h.f.lv[p.level + 1].cell_bytes[0];
     }
     out->bytes = bytes;
   });

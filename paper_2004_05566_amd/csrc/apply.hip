@@ -24,7 +24,10 @@
 // `done` is set, so PCG iterations can be queued ahead.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <mutex>
+#include <queue>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -125,16 +128,12 @@ __device__ __forceinline__ C team_sum(C v, int team) {
 //   mode 0 (dense H):  w = L^-1 y_I and c = H y_I as nI + nB independent dot products.
 //   mode 1 (links):    w = L^-1 y_I, v = L^-T w (= A_II^-1 y_I), c_b = A_BI(b, ib_b) v_ib_b.
 template <typename S, typename C, bool ST, int MODE>
-__global__ __launch_bounds__(256) void k_cell_fwd(const CellDesc* __restrict__ cd,
-                                                  const int32_t* __restrict__ idx,
-                                                  const S* __restrict__ vals,
-                                                  double* __restrict__ y, double* __restrict__ cb,
-                                                  const int* __restrict__ done, int blk_elems,
-                                                  int team) {
-  if (done && *done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+// prestaged: the block is already in LDS (a fused launch loads it while its groups run).
+__device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* __restrict__ idx,
+                                              const S* __restrict__ vals, double* __restrict__ y,
+                                              double* __restrict__ cb, int blk_elems, int team,
+                                              bool prestaged, unsigned char* smem_raw) {
   C* sm = reinterpret_cast<C*>(smem_raw);
-  const CellDesc d = cd[blockIdx.x];
   const int nI = d.nI, nB = d.nB;
   constexpr int mode = MODE;
   const int tl = tri_count(nI);
@@ -144,7 +143,8 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const CellDesc* __restrict__ c
   C* ws = ys + nI;
   C* vs = ws + nI;
   int* ib = reinterpret_cast<int*>(vs + nI);
-  if constexpr (ST) stage_flat(blk, v, tl + (mode ? nB : nB * nI), threadIdx.x, blockDim.x);
+  if constexpr (ST)
+    if (!prestaged) stage_flat(blk, v, tl + (mode ? nB : nB * nI), threadIdx.x, blockDim.x);
   const Tri<S, C, ST> Li{blk, v, nI};
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
   const int32_t* gI = idx + d.offI;
@@ -189,19 +189,26 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const CellDesc* __restrict__ c
   }
 }
 
+template <typename S, typename C, bool ST, int MODE>
+__global__ __launch_bounds__(256) void k_cell_fwd(const CellDesc* __restrict__ cd,
+                                                  const int32_t* __restrict__ idx,
+                                                  const S* __restrict__ vals,
+                                                  double* __restrict__ y, double* __restrict__ cb,
+                                                  const int* __restrict__ done, int blk_elems,
+                                                  int team) {
+  const CellDesc d = cd[blockIdx.x];
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cell_fwd_body<S, C, ST, MODE>(d, idx, vals, y, cb, blk_elems, team, false, smem_raw);
+}
+
 //   mode 0: x_I <- L^-T x_I - H^T x_B as nI dot products over [L^-1 column | H column].
 //   mode 1: t = A_IB x_B (one link per boundary DOF), x_I <- L^-T (x_I - L^-1 t).
 template <typename S, typename C, bool ST, int MODE>
-__global__ __launch_bounds__(256) void k_cell_bwd(const CellDesc* __restrict__ cd,
-                                                  const int32_t* __restrict__ idx,
-                                                  const S* __restrict__ vals,
-                                                  double* __restrict__ x,
-                                                  const int* __restrict__ done, int blk_elems,
-                                                  int team) {
-  if (done && *done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* __restrict__ idx,
+                                              const S* __restrict__ vals, double* __restrict__ x,
+                                              int blk_elems, int team, unsigned char* smem_raw) {
   C* sm = reinterpret_cast<C*>(smem_raw);
-  const CellDesc d = cd[blockIdx.x];
   const int nI = d.nI, nB = d.nB;
   constexpr int mode = MODE;
   const int tl = tri_count(nI);
@@ -262,24 +269,34 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const CellDesc* __restrict__ c
   }
 }
 
+template <typename S, typename C, bool ST, int MODE>
+__global__ __launch_bounds__(256) void k_cell_bwd(const CellDesc* __restrict__ cd,
+                                                  const int32_t* __restrict__ idx,
+                                                  const S* __restrict__ vals,
+                                                  double* __restrict__ x,
+                                                  const int* __restrict__ done, int blk_elems,
+                                                  int team) {
+  const CellDesc d = cd[blockIdx.x];
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cell_bwd_body<S, C, ST, MODE>(d, idx, vals, x, blk_elems, team, smem_raw);
+}
+
 // ----------------------------------------------------------------------------- group stages --
 // A workgroup handles blockDim/seg groups, `seg` lanes each.  Every phase runs on all lanes
 // (empty loops where a group has nothing to do) so the barriers are uniform.
 // LDS per group (staged): block (blk_elems) then yg/zg (n each) and tv/uv (nr each).
+// A lane segment without a group gets an empty descriptor (n = 0) and still takes part in every
+// barrier.
 template <typename S, typename C, bool ST>
-__global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__ gd, int ngroup,
-                                                   int seg, int per_group, int blk_elems, int team,
-                                                   const int32_t* __restrict__ idx,
-                                                   const S* __restrict__ vals,
-                                                   double* __restrict__ y,
-                                                   const double* __restrict__ cb,
-                                                   const int* __restrict__ done) {
-  if (done && *done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int per_group,
+                                               int blk_elems, int team,
+                                               const int32_t* __restrict__ idx,
+                                               const S* __restrict__ vals,
+                                               double* __restrict__ y,
+                                               const double* __restrict__ cb,
+                                               unsigned char* smem_raw) {
   const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
-  const int gi = blockIdx.x * (blockDim.x / seg) + gsel;
-  GroupDesc d{};
-  if (gi < ngroup) d = gd[gi];
   const int n = d.n, nr = d.nr, k = n - nr;
   C* base = reinterpret_cast<C*>(smem_raw) + (int64_t)gsel * per_group;
   const S* v = vals + d.offV;
@@ -348,18 +365,28 @@ __global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__
 }
 
 template <typename S, typename C, bool ST>
-__global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__ gd, int ngroup,
+__global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__ gd, int ngroup,
                                                    int seg, int per_group, int blk_elems, int team,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
-                                                   double* __restrict__ x,
+                                                   double* __restrict__ y,
+                                                   const double* __restrict__ cb,
                                                    const int* __restrict__ done) {
-  if (done && *done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
-  const int gi = blockIdx.x * (blockDim.x / seg) + gsel;
+  const int gi = blockIdx.x * (blockDim.x / seg) + threadIdx.x / seg;
   GroupDesc d{};
   if (gi < ngroup) d = gd[gi];
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  group_fwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, idx, vals, y, cb, smem_raw);
+}
+
+template <typename S, typename C, bool ST>
+__device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int per_group,
+                                               int blk_elems, int team,
+                                               const int32_t* __restrict__ idx,
+                                               const S* __restrict__ vals,
+                                               double* __restrict__ x, unsigned char* smem_raw) {
+  const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
   const int n = d.n, nr = d.nr, k = n - nr;
   C* base = reinterpret_cast<C*>(smem_raw) + (int64_t)gsel * per_group;
   const S* v = vals + d.offV;
@@ -423,31 +450,151 @@ __global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__
   }
 }
 
+template <typename S, typename C, bool ST>
+__global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__ gd, int ngroup,
+                                                   int seg, int per_group, int blk_elems, int team,
+                                                   const int32_t* __restrict__ idx,
+                                                   const S* __restrict__ vals,
+                                                   double* __restrict__ x,
+                                                   const int* __restrict__ done) {
+  const int gi = blockIdx.x * (blockDim.x / seg) + threadIdx.x / seg;
+  GroupDesc d{};
+  if (gi < ngroup) d = gd[gi];
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  group_bwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, idx, vals, x, smem_raw);
+}
+
 // ------------------------------------------------------------------------------------ root --
 // y_r <- L_r^-T (L_r^-1 y_r), L_r^-1 packed column-major, read straight from global memory.
+template <typename S, typename C>
+__device__ __forceinline__ void root_body(int nr, const int32_t* __restrict__ ridx,
+                                          const S* __restrict__ Lv, double* __restrict__ y,
+                                          bool staged, unsigned char* smem_raw) {
+  // staged: packed L^-1 copied into LDS first (tri(nr) rounded up to the vector width)
+  C* Ls = reinterpret_cast<C*>(smem_raw);
+  C* ys = Ls + (staged ? round_up((int)tri_count(nr), 8) : 0);
+  C* ws = ys + nr;
+  if (staged) stage_flat(Ls, Lv, (int)tri_count(nr), threadIdx.x, blockDim.x);
+  auto Lr = [&](int i, int j) -> C {
+    const int o = colstart(j, nr) + (i - j);
+    return staged ? Ls[o] : load_as<C>(Lv + o);
+  };
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) ys[i] = (C)y[ridx[i]];
+  __syncthreads();
+  // `team` lanes share each output's dot product
+  int team = 1;
+  while (team < 16 && team * 2 * nr <= (int)blockDim.x) team <<= 1;
+  const int part = threadIdx.x % team, per = blockDim.x / team;
+  for (int ob = 0; ob < nr; ob += per) {   // w = L^-1 y
+    const int o = ob + (int)threadIdx.x / team;
+    C acc = 0;
+    if (o < nr)
+      for (int j = part; j <= o; j += team) acc += Lr(o, j) * ys[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && o < nr) ws[o] = acc;
+  }
+  __syncthreads();
+  for (int ob = 0; ob < nr; ob += per) {   // y = L^-T w (column o is contiguous)
+    const int o = ob + (int)threadIdx.x / team;
+    C acc = 0;
+    if (o < nr)
+      for (int j = o + part; j < nr; j += team) acc += Lr(j, o) * ws[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && o < nr) y[ridx[o]] = (double)acc;
+  }
+}
+
+// LDS of the root stage: staged when the packed block fits next to the two vectors.
+template <typename C>
+size_t root_smem(int nr, bool* staged) {
+  const size_t st = sizeof(C) * ((size_t)round_up((int)tri_count(nr), 8) + 2 * (size_t)nr);
+  *staged = st <= kStageMax;
+  return *staged ? st : 2 * sizeof(C) * (size_t)nr;
+}
+
 template <typename S, typename C>
 __global__ __launch_bounds__(kRootThreads) void k_root(int nr, const int32_t* __restrict__ ridx,
                                                        const S* __restrict__ Lv,
                                                        double* __restrict__ y,
+                                                       int staged,
                                                        const int* __restrict__ done) {
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* ys = reinterpret_cast<C*>(smem_raw);
-  C* ws = ys + nr;
-  for (int i = threadIdx.x; i < nr; i += blockDim.x) ys[i] = (C)y[ridx[i]];
+  root_body<S, C>(nr, ridx, Lv, y, staged != 0, smem_raw);
+}
+
+// --------------------------------------------------------------------------- fused stages --
+// The group stage of level l and the forward cell stage of level l+1 in one launch.  Workgroup
+// p runs the level-l groups it owns (every group with a DOF in the interior of the level l+1
+// cell p, plus a share of the groups on level l+1 cell boundaries) at once, `seg` lanes each,
+// then the cell stage of cell p.  Cell p reads only its own interior, which only its own groups
+// write; groups read only their own DOFs and the contributions of the level-l cells (the
+// previous launch); so no workgroup needs another one's result.  The contributions of
+// consecutive levels live in the two halves of the contribution buffer (cb_in: level l,
+// cb_out: level l+1).  The owned groups' descriptors are stored padded to `maxown` per cell, so
+// one load finds them.  With `prestage`, the cell's block is loaded into LDS (below `goff`)
+// while the groups run.
+template <typename S, typename C, bool CST>
+__global__ __launch_bounds__(1024) void k_fuse_fwd(const GroupDesc* __restrict__ owned,
+                                                   int maxown, int seg, int per_group, int blk_g,
+                                                   int goff, const CellDesc* __restrict__ cd,
+                                                   int blk_c, int team_c, int prestage,
+                                                   const int32_t* __restrict__ idx,
+                                                   const S* __restrict__ vals,
+                                                   double* __restrict__ y,
+                                                   const double* __restrict__ cb_in,
+                                                   double* __restrict__ cb_out,
+                                                   const int* __restrict__ done) {
+  const int p = blockIdx.x;
+  const int gsel = threadIdx.x / seg;
+  GroupDesc g{};
+  if (gsel < maxown) g = owned[(int64_t)p * maxown + gsel];
+  const CellDesc d = cd[p];
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if constexpr (CST)
+    if (prestage)
+      stage_flat(reinterpret_cast<C*>(smem_raw), vals + d.offV, tri_count(d.nI) + d.nB * d.nI,
+                 threadIdx.x, blockDim.x);
+  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, 1, idx, vals, y, cb_in, smem_raw + goff);
   __syncthreads();
-  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-    C acc = 0;
-    int base = 0;
-    for (int j = 0; j <= i; ++j) { acc += load_as<C>(Lv + base + (i - j)) * ys[j]; base += nr - j; }
-    ws[i] = acc;
+  cell_fwd_body<S, C, CST, 0>(d, idx, vals, y, cb_out, blk_c, team_c, prestage != 0, smem_raw);
+}
+
+// The last level's groups (forward), the root, and the same groups (backward) in one
+// workgroup: the root is the only cell above them, so barriers order everything.  Groups run
+// `per` at a time.
+template <typename S, typename C>
+__global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict__ gd, int ngroup,
+                                                    int seg, int per, int per_group, int blk_g,
+                                                    int nr, const int32_t* __restrict__ ridx,
+                                                    const S* __restrict__ Lv,
+                                                    const int32_t* __restrict__ idx,
+                                                    const S* __restrict__ vals,
+                                                    double* __restrict__ y,
+                                                    const double* __restrict__ cb_in,
+                                                    int rstaged, const int* __restrict__ done) {
+  const int gsel = threadIdx.x / seg;
+  GroupDesc g{};
+  if (gsel < per && gsel < ngroup) g = gd[gsel];
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  for (int b = 0; b < ngroup; b += per) {
+    if (b > 0) {
+      g = GroupDesc{};
+      if (gsel < per && b + gsel < ngroup) g = gd[b + gsel];
+    }
+    group_fwd_body<S, C, true>(g, seg, per_group, blk_g, 1, idx, vals, y, cb_in, smem_raw);
+    __syncthreads();
   }
+  root_body<S, C>(nr, ridx, Lv, y, rstaged != 0, smem_raw);
   __syncthreads();
-  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-    C acc = 0;
-    const int base = colstart(i, nr);
-    for (int j = i; j < nr; ++j) acc += load_as<C>(Lv + base + (j - i)) * ws[j];
-    y[ridx[i]] = (double)acc;
+  for (int b = 0; b < ngroup; b += per) {
+    g = GroupDesc{};
+    if (gsel < per && b + gsel < ngroup) g = gd[b + gsel];
+    group_bwd_body<S, C, true>(g, seg, per_group, blk_g, 1, idx, vals, y, smem_raw);
+    __syncthreads();
   }
 }
 
@@ -475,11 +622,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __re
                                                    double* __restrict__ wsc,
                                                    double* __restrict__ cb,
                                                    const int* __restrict__ done) {
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* ys = reinterpret_cast<C*>(smem_raw);
   __shared__ C red[kTileWaves][kRowTile];
   const int4 t = tiles[blockIdx.x];
+  if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
   const int nrows = MODE ? nI : nI + nB;
@@ -533,11 +680,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restri
                                                const double* __restrict__ wsc,
                                                double* __restrict__ cb,
                                                const int* __restrict__ done) {
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* xs = reinterpret_cast<C*>(smem_raw);
   __shared__ C vt[kColTile];
   const int4 t = tiles[blockIdx.x];
+  if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = KIND == 0 ? d.nB : 0;
   C* xb = xs + nI;
@@ -585,11 +732,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __r
                                                     const double* __restrict__ y,
                                                     double* __restrict__ wsc,
                                                     const int* __restrict__ done) {
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* ts = reinterpret_cast<C*>(smem_raw);
   __shared__ C red[kTileWaves][kRowTile];
   const int4 t = tiles[blockIdx.x];
+  if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
   const int r0 = t.y;
@@ -672,10 +819,10 @@ __global__ __launch_bounds__(kTileThreads) void k_group_big_fwd(const GroupDesc*
                                                                 double* __restrict__ y,
                                                                 const double* __restrict__ cb,
                                                                 const int* __restrict__ done) {
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ C red[kTileWaves][kRowTile];
   const GroupDesc d = gd[blockIdx.x];
+  if (done && *done) return;
   const int n = d.n, nr = d.nr, k = n - nr;
   C* yg = reinterpret_cast<C*>(smem_raw);
   C* zg = yg + n;
@@ -730,10 +877,10 @@ __global__ __launch_bounds__(kTileThreads) void k_group_big_bwd(const GroupDesc*
                                                                 const S* __restrict__ vals,
                                                                 double* __restrict__ x,
                                                                 const int* __restrict__ done) {
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ C red[kTileWaves][kRowTile];
   const GroupDesc d = gd[blockIdx.x];
+  if (done && *done) return;
   const int n = d.n, nr = d.nr, k = n - nr;
   C* xg = reinterpret_cast<C*>(smem_raw);
   C* zg = xg + n;
@@ -836,6 +983,54 @@ StagePlan group_plan(const LevelDev& L) {
   return p;
 }
 
+// Fused launches: the owned groups all run at once (the block size is the smallest of 256, 512
+// and 1024 lanes that holds them; a level whose cells own more is not fused), then the cell
+// (team re-derived for that block size); or, for the root, groups `per` at a time.
+struct FusePlan {
+  bool ok = false;
+  int threads = 256, per = 0, team_c = 1, goff = 0;
+  bool cst = false, prestage = false;
+  int blk_c = 0;
+  size_t smem = 0;
+  StagePlan g{};
+};
+
+template <typename C>
+FusePlan fuse_plan(const LevelDev& G, const LevelDev* Cl, int nroot) {
+  FusePlan f;
+  if (!G.ngroup) return f;
+  f.g = group_plan<C>(G);
+  if (!f.g.staged) return f;
+  const size_t pg = sizeof(C) * (size_t)f.g.per_group;
+  if (Cl) {
+    if (!Cl->ncell || Cl->tiled || Cl->cmode != 0 || G.maxown < 1) return f;
+    f.threads = 256;
+    while (f.threads < 1024 && f.threads / f.g.seg < G.maxown) f.threads *= 2;
+    if (f.threads / f.g.seg < G.maxown) return f;
+    f.per = G.maxown;
+    const size_t gsm = (size_t)f.per * pg;
+    const StagePlan cp = cell_plan<C>(*Cl);
+    int team = 1;
+    while (team < 8 && (team * 2) * Cl->maxI <= f.threads) team <<= 1;
+    f.team_c = team;
+    f.cst = cp.staged;
+    f.blk_c = cp.blk_elems;
+    const size_t csm = (cp.smem + 15) / 16 * 16;
+    f.prestage = f.cst && csm + gsm <= kStageMax;
+    f.goff = f.prestage ? (int)csm : 0;
+    f.smem = f.prestage ? csm + gsm : std::max(gsm, cp.smem);
+  } else {
+    f.threads = 1024;
+    f.per = (int)std::min<size_t>(f.threads / f.g.seg, std::max<size_t>(1, kStageMax / pg));
+    bool rs;
+    const size_t rsm = root_smem<C>(nroot, &rs);
+    f.prestage = rs;  // the root block is staged in LDS
+    f.smem = std::max((size_t)f.per * pg, rsm);
+  }
+  f.ok = f.smem <= kStageMax;
+  return f;
+}
+
 // Optional timing of the launches of one (level, stage): the kernel is launched with a start
 // and a stop event that the runtime records around its execution on the same stream.
 // A tiny follow-up kernel records whether the timed launch did work (the early-exit flag cannot
@@ -885,12 +1080,12 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const S
 
 template <typename S, typename C, int MODE>
 void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
-                 const int* done, hipStream_t s, const StageTimer& t) {
+                 double* cb, const int* done, hipStream_t s, const StageTimer& t) {
   const StagePlan p = cell_plan<C>(L);
   if (fwd) {
     auto k = p.staged ? k_cell_fwd<S, C, true, MODE> : k_cell_fwd<S, C, false, MODE>;
     launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, L.cells.p, (const int32_t*)f.idx.p,
-           vals, y, f.cb.p, done, p.blk_elems, p.seg);
+           vals, y, cb, done, p.blk_elems, p.seg);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, L.cells.p, (const int32_t*)f.idx.p,
@@ -905,7 +1100,7 @@ size_t big_group_smem(const LevelDev& L) {
 
 template <typename S, typename C>
 void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
-                  const int* done, hipStream_t s, const StageTimer& t) {
+                  double* cb, const int* done, hipStream_t s, const StageTimer& t) {
   const int32_t* idx = f.idx.p;
   const size_t rows_smem = sizeof(C) * (size_t)std::max(1, L.maxI);
   const size_t cols_smem = sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB);
@@ -913,14 +1108,14 @@ void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals
     if (L.cmode) {
       launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
-             f.wsc.p, f.cb.p, done);
+             f.wsc.p, cb, done);
       launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, StageTimer(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
-             (const double*)f.wsc.p, f.cb.p, done);
+             (const double*)f.wsc.p, cb, done);
     } else {
       launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
-             f.wsc.p, f.cb.p, done);
+             f.wsc.p, cb, done);
     }
   } else {
     if (L.cmode) {
@@ -929,11 +1124,11 @@ void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals
              f.wsc.p, done);
       launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, StageTimer(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
-             (const double*)f.wsc.p, f.cb.p, done);
+             (const double*)f.wsc.p, cb, done);
     } else {
       launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t,
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
-             (const double*)f.wsc.p, f.cb.p, done);
+             (const double*)f.wsc.p, cb, done);
     }
   }
 }
@@ -943,55 +1138,76 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
   const S* vals = reinterpret_cast<const S*>(f.vals.p);
   const int32_t* idx = f.idx.p;
   StageProfiler* prof = f.prof.get();
-  for (size_t l = 0; l < f.lv.size(); ++l) {
+  const int nlev = (int)f.lv.size();
+  auto cbl = [&](int l) { return f.cb.p + (int64_t)(l & 1) * f.cbstride; };
+  for (int l = 0; l < nlev; ++l) {
     const LevelDev& L = f.lv[l];
-    if (L.ncell) {
-      const StageTimer t(prof, (int)l, STAGE_CELL_FWD, done, s);
-      if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, done, s, t);
-      else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, done, s, t);
-      else launch_cell<S, C, 0>(f, L, true, vals, y, done, s, t);
+    if (L.ncell && !(l > 0 && f.lv[l - 1].fuse)) {
+      const StageTimer t(prof, l, STAGE_CELL_FWD, done, s);
+      if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
+      else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t);
+      else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t);
     }
-    if (L.ngroup && !group_plan<C>(L).staged) {
-      const StageTimer t(prof, (int)l, STAGE_GROUP_FWD, done, s);
+    if (!L.ngroup) continue;
+    if (L.fuse) {  // + the cell stage of level l+1
+      const LevelDev& P = f.lv[l + 1];
+      const FusePlan fp = fuse_plan<C>(L, &P, 0);
+      const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
+      auto k = fp.cst ? k_fuse_fwd<S, C, true> : k_fuse_fwd<S, C, false>;
+      launch(k, dim3(P.ncell), dim3(fp.threads), fp.smem, s, t, (const GroupDesc*)L.owned.p,
+             L.maxown, fp.g.seg, fp.g.per_group, fp.g.blk_elems, fp.goff,
+             (const CellDesc*)P.cells.p, fp.blk_c, fp.team_c, (int)fp.prestage, idx, vals, y,
+             (const double*)cbl(l), cbl(l + 1), done);
+    } else if (l == nlev - 1 && f.root_fused) {  // + root + this level's backward groups
+      const FusePlan fp = fuse_plan<C>(L, nullptr, f.nroot);
+      const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
+      launch(k_fuse_root<S, C>, dim3(1), dim3(fp.threads), fp.smem, s, t,
+             (const GroupDesc*)L.groups.p, L.ngroup, fp.g.seg, fp.per, fp.g.per_group,
+             fp.g.blk_elems, f.nroot, idx + f.offRootIdx, vals + f.offRootV, idx, vals, y,
+             (const double*)cbl(l), (int)fp.prestage, done);
+    } else if (!group_plan<C>(L).staged) {
+      const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       launch(k_group_big_fwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L), s,
-             t, (const GroupDesc*)L.groups.p, idx, vals, y, (const double*)f.cb.p, done);
-    } else if (L.ngroup) {
-      const StageTimer t(prof, (int)l, STAGE_GROUP_FWD, done, s);
-      const StagePlan p = group_plan<C>(L);
-      auto k = p.staged ? k_group_fwd<S, C, true> : k_group_fwd<S, C, false>;
-      launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, (const GroupDesc*)L.groups.p,
-             L.ngroup, p.seg, p.per_group, p.blk_elems, p.team, idx, vals, y,
-             (const double*)f.cb.p, done);
-    }
-  }
-  if (f.nroot) {
-    const StageTimer t(prof, (int)f.lv.size(), STAGE_ROOT, done, s);
-    if (f.root_tiled) {  // y_r = L^-T (L^-1 y_r) as a row pass then a column pass
-      launch_tiled<S, C>(f, f.rootlv, true, vals, y, done, s, t);
-      launch_tiled<S, C>(f, f.rootlv, false, vals, y, done, s, StageTimer());
+             t, (const GroupDesc*)L.groups.p, idx, vals, y, (const double*)cbl(l), done);
     } else {
-      launch(k_root<S, C>, dim3(1), dim3(kRootThreads), 2 * sizeof(C) * f.nroot, s, t, f.nroot,
-             idx + f.offRootIdx, vals + f.offRootV, y, done);
+      const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
+      const StagePlan p = group_plan<C>(L);
+      launch(k_group_fwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.smem, s, t,
+             (const GroupDesc*)L.groups.p, L.ngroup, p.seg, p.per_group, p.blk_elems, p.team, idx,
+             vals, y, (const double*)cbl(l), done);
     }
   }
-  for (size_t l = f.lv.size(); l-- > 0;) {
+  if (f.nroot && !f.root_fused) {
+    const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
+    if (f.root_tiled) {  // y_r = L^-T (L^-1 y_r) as a row pass then a column pass
+      launch_tiled<S, C>(f, f.rootlv, true, vals, y, cbl(nlev), done, s, t);
+      launch_tiled<S, C>(f, f.rootlv, false, vals, y, cbl(nlev), done, s, StageTimer());
+    } else {
+      bool rs;
+      const size_t rsm = root_smem<C>(f.nroot, &rs);
+      launch(k_root<S, C>, dim3(1), dim3(kRootThreads), rsm, s, t, f.nroot, idx + f.offRootIdx,
+             vals + f.offRootV, y, (int)rs, done);
+    }
+  }
+  for (int l = nlev - 1; l >= 0; --l) {
     const LevelDev& L = f.lv[l];
-    if (L.ngroup && !group_plan<C>(L).staged) {
-      const StageTimer t(prof, (int)l, STAGE_GROUP_BWD, done, s);
-      launch(k_group_big_bwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L), s,
-             t, (const GroupDesc*)L.groups.p, idx, vals, y, done);
-    } else if (L.ngroup) {
-      const StageTimer t(prof, (int)l, STAGE_GROUP_BWD, done, s);
-      const StagePlan p = group_plan<C>(L);
-      auto k = p.staged ? k_group_bwd<S, C, true> : k_group_bwd<S, C, false>;
-      launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, (const GroupDesc*)L.groups.p,
-             L.ngroup, p.seg, p.per_group, p.blk_elems, p.team, idx, vals, y, done);
+    if (L.ngroup && !(l == nlev - 1 && f.root_fused)) {
+      const StageTimer t(prof, l, STAGE_GROUP_BWD, done, s);
+      if (!group_plan<C>(L).staged) {
+        launch(k_group_big_bwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L),
+               s, t, (const GroupDesc*)L.groups.p, idx, vals, y, done);
+      } else {
+        const StagePlan p = group_plan<C>(L);
+        launch(k_group_bwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.smem, s, t,
+               (const GroupDesc*)L.groups.p, L.ngroup, p.seg, p.per_group, p.blk_elems, p.team,
+               idx, vals, y, done);
+      }
     }
     if (L.ncell) {
-      const StageTimer t(prof, (int)l, STAGE_CELL_BWD, done, s);
-      if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, done, s, t);
-      else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, done, s, t);
-      else launch_cell<S, C, 0>(f, L, false, vals, y, done, s, t);
+      const StageTimer t(prof, l, STAGE_CELL_BWD, done, s);
+      if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
+      else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, cbl(l), done, s, t);
+      else launch_cell<S, C, 0>(f, L, false, vals, y, cbl(l), done, s, t);
     }
   }
   HIF_CHECK(hipGetLastError());
@@ -1016,7 +1232,17 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst) {
       g = cs * (2 * (size_t)L.maxG + (size_t)L.maxK + 2 * (size_t)L.maxR + 4);
     w = std::max(w, std::max(c, g));
   }
-  w = std::max(w, f.root_tiled ? cs * (size_t)f.nroot : 2 * cs * (size_t)f.nroot);
+  bool rs;
+  w = std::max(w, f.root_tiled ? cs * (size_t)f.nroot
+                               : (f.store == HIF_STORE_F64 ? root_smem<double>(f.nroot, &rs)
+                                                           : root_smem<float>(f.nroot, &rs)));
+  const int nlev = (int)f.lv.size();
+  for (int l = 0; l < nlev; ++l) {
+    const LevelDev* P = l + 1 < nlev ? &f.lv[l + 1] : nullptr;
+    if (!(f.lv[l].fuse || (!P && f.root_fused))) continue;
+    w = std::max(w, f.store == HIF_STORE_F64 ? fuse_plan<double>(f.lv[l], P, f.nroot).smem
+                                             : fuse_plan<float>(f.lv[l], P, f.nroot).smem);
+  }
   if (worst) *worst = w;
   return w;
 }
@@ -1061,7 +1287,10 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM((k_tcols<S, C, 2>));                                                               \
   HIF_SMEM((k_group_big_fwd<S, C>));                                                          \
   HIF_SMEM((k_group_big_bwd<S, C>));                                                          \
-  HIF_SMEM((k_root<S, C>))
+  HIF_SMEM((k_root<S, C>));                                                                   \
+  HIF_SMEM((k_fuse_fwd<S, C, true>));                                                         \
+  HIF_SMEM((k_fuse_fwd<S, C, false>));                                                        \
+  HIF_SMEM((k_fuse_root<S, C>))
   HIF_SMEM_ALL(double, double);
   HIF_SMEM_ALL(float, float);
   HIF_SMEM_ALL(bf16_t, float);
@@ -1092,6 +1321,65 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
   *base = woff;
 }
 }  // namespace
+
+void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                  const std::vector<std::vector<GroupDesc>>& groups,
+                  const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
+  const bool f64 = f.store == HIF_STORE_F64;
+  const int nlev = (int)f.lv.size();
+  const bool off = std::getenv("HIFCN_NO_FUSE") != nullptr;
+  std::vector<int32_t> parent(N, -1);
+  for (int l = 0; l + 1 < nlev; ++l) {
+    LevelDev& L = f.lv[l];
+    const LevelDev& P = f.lv[l + 1];
+    L.fuse = false;
+    if (off || !L.ngroup || !P.ncell || P.tiled || P.cmode != 0) continue;
+    // owner of each level-l group: the level l+1 cell holding one of its DOFs in its interior
+    const std::vector<CellDesc>& pc = cells[l + 1];
+    for (size_t p = 0; p < pc.size(); ++p)
+      for (int i = 0; i < pc[p].nI; ++i) parent[idx[pc[p].offI + i]] = (int32_t)p;
+    const std::vector<GroupDesc>& gs = groups[l];
+    std::vector<int32_t> owner(gs.size(), -1);
+    bool split = false;
+    for (size_t g = 0; g < gs.size() && !split; ++g)
+      for (int i = 0; i < gs[g].n; ++i) {
+        const int32_t q = parent[idx[gs[g].offIdx + i]];
+        if (q < 0) continue;
+        if (owner[g] < 0) owner[g] = q;
+        else if (owner[g] != q) { split = true; break; }
+      }
+    for (size_t p = 0; p < pc.size(); ++p)
+      for (int i = 0; i < pc[p].nI; ++i) parent[idx[pc[p].offI + i]] = -1;
+    if (split) continue;
+    // groups on level l+1 cell boundaries go to the least loaded cell
+    std::vector<int32_t> load(pc.size(), 0);
+    for (int32_t o : owner) if (o >= 0) ++load[o];
+    std::priority_queue<std::pair<int32_t, int32_t>, std::vector<std::pair<int32_t, int32_t>>,
+                        std::greater<>> least;  // (load, cell)
+    for (size_t p = 0; p < pc.size(); ++p) least.push({load[p], (int32_t)p});
+    for (int32_t& o : owner)
+      if (o < 0) {
+        const auto top = least.top();
+        least.pop();
+        o = top.second;
+        least.push({++load[o], o});
+      }
+    int maxown = 0;
+    for (int32_t c : load) maxown = std::max(maxown, c);
+    L.maxown = maxown;
+    if (!(f64 ? fuse_plan<double>(L, &P, 0).ok : fuse_plan<float>(L, &P, 0).ok)) continue;
+    std::vector<GroupDesc> owned((size_t)pc.size() * maxown, GroupDesc{});
+    std::vector<int32_t> fill(pc.size(), 0);
+    for (size_t g = 0; g < gs.size(); ++g)
+      owned[(size_t)owner[g] * maxown + fill[owner[g]]++] = gs[g];
+    L.owned.upload(owned, s);
+    L.fuse = true;
+  }
+  f.root_fused = false;
+  if (!off && nlev > 0 && f.nroot && !f.root_tiled && f.lv[nlev - 1].ngroup)
+    f.root_fused = f64 ? fuse_plan<double>(f.lv[nlev - 1], nullptr, f.nroot).ok
+                       : fuse_plan<float>(f.lv[nlev - 1], nullptr, f.nroot).ok;
+}
 
 void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells, hipStream_t s) {
   const bool f64 = f.store == HIF_STORE_F64;

@@ -1025,11 +1025,17 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   }
   convert(rchunk.p, root_base, tri64(nroot));
   HIF_CHECK(hipGetLastError());
-  f.cb.alloc(std::max<int64_t>(1, cbmax));
+  f.cbstride = std::max<int64_t>(1, cbmax);
+  f.cb.alloc(2 * f.cbstride);
   {
     std::vector<std::vector<CellDesc>> cells;
-    for (const LevelOut& lo : outs) cells.push_back(lo.cells);
+    std::vector<std::vector<GroupDesc>> groups;
+    for (const LevelOut& lo : outs) {
+      cells.push_back(lo.cells);
+      groups.push_back(lo.groups);
+    }
     setup_tiling(f, cells, s);
+    setup_fusion(f, cells, groups, idx, hd.N, s);
   }
   size_t worst = 0;
   apply_smem_need(f, &worst);

@@ -330,11 +330,24 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
   fd.root_bytes = (int64_t)eb * tri_count(fh.nroot) + 20 * (int64_t)fh.nroot;
   fd.offRootIdx = fh.offRootIdx;
   fd.offRootV = fh.offRootV;
-  fd.cb.alloc(std::max<int64_t>(1, fh.cbmax));
+  fd.cbstride = std::max<int64_t>(1, fh.cbmax);
+  fd.cb.alloc(2 * fd.cbstride);
   {
     std::vector<std::vector<CellDesc>> cells;
-    for (const LevelHost& lh : fh.lv) cells.push_back(lh.cells);
+    std::vector<std::vector<GroupDesc>> groups;
+    int64_t N = 0;  // one past the largest DOF id
+    for (const LevelHost& lh : fh.lv) {
+      cells.push_back(lh.cells);
+      groups.push_back(lh.groups);
+      for (const CellDesc& c : lh.cells)
+        for (int i = 0; i < c.nI + c.nB; ++i)
+          N = std::max<int64_t>(N, fh.idx[(i < c.nI ? c.offI + i : c.offB + i - c.nI)] + 1);
+      for (const GroupDesc& g : lh.groups)
+        for (int i = 0; i < g.n; ++i) N = std::max<int64_t>(N, fh.idx[g.offIdx + i] + 1);
+    }
+    for (int i = 0; i < fh.nroot; ++i) N = std::max<int64_t>(N, fh.idx[fh.offRootIdx + i] + 1);
     setup_tiling(fd, cells, s);
+    setup_fusion(fd, cells, groups, fh.idx, N, s);
   }
   size_t worst = 0;
   apply_smem_need(fd, &worst);

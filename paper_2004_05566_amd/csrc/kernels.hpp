@@ -24,6 +24,12 @@ struct LevelDev {
   bool tiled = false;
   int nrt = 0, nct = 0;
   DevBuf<int4> rtiles, ctiles;
+  // The group stage of this level runs in one launch with the cell stage of the next level:
+  // owned = the descriptors of the groups each next-level cell runs, maxown per cell (padded
+  // with empty descriptors).
+  bool fuse = false;
+  int maxown = 0;
+  DevBuf<GroupDesc> owned;
 };
 
 // Stages of one apply, as timed by the profiler.
@@ -64,7 +70,9 @@ struct FactorDev {
   int nroot = 0;
   int32_t offRootIdx = 0;  // root DOF ids in idx
   int64_t offRootV = 0;    // packed L_r^-1 in vals
-  DevBuf<double> cb;       // boundary contributions of the cell stage (max over levels)
+  DevBuf<double> cb;       // boundary contributions of the cell stage: two halves of cbstride,
+  int64_t cbstride = 0;    //   level l uses half l % 2 (consecutive levels may run together)
+  bool root_fused = false; // last level's groups, root and backward groups in one launch
   size_t smem_max = 0;
   int64_t root_bytes = 0;
   std::unique_ptr<StageProfiler> prof;
@@ -139,6 +147,11 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst);
 // Decide per level whether cells are tiled across workgroups and upload the tile lists;
 // `cells` are the host copies of every level's descriptors.
 void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells, hipStream_t s);
+// Decide which group stages run together with the next level's cell stage (and the last level
+// with the root) and upload the ownership lists; call after setup_tiling.
+void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                  const std::vector<std::vector<GroupDesc>>& groups,
+                  const std::vector<int32_t>& idx, int64_t N, hipStream_t s);
 void set_apply_smem_limits(size_t bytes);
 
 // ---- kernels --------------------------------------------------------------------------------
