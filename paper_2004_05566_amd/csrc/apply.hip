@@ -65,23 +65,26 @@ __device__ __forceinline__ void unpack(const uint4& v, C* d) {
 }
 
 // Copy `tot` elements starting at the (16-byte aligned) `src` into LDS `dst`, using `nthr`
-// threads numbered `lt`; four vector loads per thread are issued before any is consumed.
+// threads numbered `lt`; kStageUnroll vector loads per thread are issued before any is consumed
+// (few lanes staging a large block need many loads in flight to cover the memory latency).
 // `dst` must hold `tot` rounded up to the vector width.
+constexpr int kStageUnroll = 8;
 template <typename S, typename C>
 __device__ __forceinline__ void stage_flat(C* dst, const S* src, int tot, int lt, int nthr) {
   using V = typename VecOf<S>::T;
   constexpr int W = VecOf<S>::W;
+  constexpr int U = kStageUnroll;
   const V* sv = reinterpret_cast<const V*>(src);
   const int nv = (tot + W - 1) / W;
-  for (int b = lt; b < nv; b += 4 * nthr) {
-    V r[4];
+  for (int b = lt; b < nv; b += U * nthr) {
+    V r[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int q = b + u * nthr;
       if (q < nv) r[u] = sv[q];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int q = b + u * nthr;
       if (q < nv) unpack<C>(r[u], dst + q * W);
     }
