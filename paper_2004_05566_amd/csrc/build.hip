@@ -18,6 +18,7 @@
 // launches; only ranks and pivot orders come back from the device once per level.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <unordered_map>
 
@@ -276,8 +277,67 @@ __global__ __launch_bounds__(kBT) void k_jacobi_scale(const ScaleTask* __restric
 }
 
 // ------------------------------------------------------------------ (3) skeletonization --
-// Work layout: M (m x n column-major), norms (n), v (m), T (k x nr col-major), S/Ls (nr x nr),
-// Ls^-1 (nr x nr), Wm (k x nr).
+// T = R11^-1 R12, L_s, X and the outputs of one ID, once the first k steps of the pivoted QR are
+// in M (R in its upper triangle) and perm holds the column order.  Work layout after M: norms
+// (n), v (m), T (k x nr col-major), S/Ls (nr x nr), Ls^-1 (nr x nr), Wm (k x nr).
+__device__ void id_finish(const IdTask& t, double* M, int k, const int* perm,
+                          double* __restrict__ fv, double* __restrict__ Xbuf,
+                          int32_t* __restrict__ permout, int32_t* __restrict__ kout, int* err) {
+  const int n = t.n, m = t.m;
+  double* v = M + (int64_t)m * n + n;
+  const int nr = n - k;
+  double* T = v + m;                     // k x nr, column-major
+  double* S = T + (int64_t)k * nr;       // nr x nr -> L_s
+  double* Li = S + (int64_t)nr * nr;     // nr x nr -> L_s^-1
+  double* Wm = Li + (int64_t)nr * nr;    // k x nr row-major: T L_s^-T
+  // T = R11^-1 R12 by back substitution, one column per thread
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    double* tc = T + (int64_t)j * k;
+    for (int s = k - 1; s >= 0; --s) {
+      double acc = M[(int64_t)(k + j) * m + s];
+      for (int q = s + 1; q < k; ++q) acc -= M[(int64_t)q * m + s] * tc[q];
+      tc[s] = acc / M[(int64_t)s * m + s];
+    }
+  }
+  __syncthreads();
+  // S = I + T^T T
+  for (int64_t e = threadIdx.x; e < (int64_t)nr * nr; e += blockDim.x) {
+    const int a = (int)(e / nr), b = (int)(e - (int64_t)a * nr);
+    double acc = (a == b) ? 1.0 : 0.0;
+    for (int s = 0; s < k; ++s) acc += T[(int64_t)a * k + s] * T[(int64_t)b * k + s];
+    S[e] = acc;
+  }
+  wg_identity(Li, nr, nr);
+  __syncthreads();
+  wg_potrf(S, nr, nr, err);
+  wg_trsm_lower(S, nr, nr, Li, nr, nr, true);
+  __syncthreads();
+  // factor values: T (column-major k x nr) and packed L_s^-1 after the group's packed L_g^-1
+  double* V = fv + t.offV + tri_count(n);
+  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) V[e] = T[e];
+  wg_store_packed(V + (int64_t)k * nr, Li, nr, nr);
+  // Wm = T L_s^-T,  X = I - Wm Wm^T (k x k)
+  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) {
+    const int s = (int)(e / nr), i = (int)(e - (int64_t)s * nr);
+    double acc = 0;
+    for (int j = 0; j <= i; ++j) acc += T[(int64_t)j * k + s] * Li[(int64_t)i * nr + j];
+    Wm[e] = acc;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+    const int a = (int)(e / k), b = (int)(e - (int64_t)a * k);
+    double acc = (a == b) ? 1.0 : 0.0;
+    for (int i = 0; i < nr; ++i) acc -= Wm[(int64_t)a * nr + i] * Wm[(int64_t)b * nr + i];
+    Xbuf[t.offX + e] = acc;
+  }
+  // pivot order: redundant first, then skeletons
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    permout[t.offPerm + i] = (i < nr) ? perm[k + i] : perm[i - nr];
+  if (threadIdx.x == 0) kout[t.kslot] = k;
+}
+
+// One ID per workgroup (small edges): gather M (m x n column-major), column-pivoted Householder
+// QR until the rank test stops it, then id_finish.
 __global__ __launch_bounds__(kBT) void k_id(const IdTask* __restrict__ tasks,
                                             const SubBlk* __restrict__ rs,
                                             const double* __restrict__ A,
@@ -364,55 +424,174 @@ __global__ __launch_bounds__(kBT) void k_id(const IdTask* __restrict__ tasks,
     }
     __syncthreads();
   }
-  const int nr = n - k;
-  double* T = v + m;                     // k x nr, column-major
-  double* S = T + (int64_t)k * nr;       // nr x nr -> L_s
-  double* Li = S + (int64_t)nr * nr;     // nr x nr -> L_s^-1
-  double* Wm = Li + (int64_t)nr * nr;    // k x nr row-major: T L_s^-T
-  // T = R11^-1 R12 by back substitution, one column per thread
-  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
-    double* tc = T + (int64_t)j * k;
-    for (int s = k - 1; s >= 0; --s) {
-      double acc = M[(int64_t)(k + j) * m + s];
-      for (int q = s + 1; q < k; ++q) acc -= M[(int64_t)q * m + s] * tc[q];
-      tc[s] = acc / M[(int64_t)s * m + s];
+  id_finish(t, M, k, perm_s, fv, Xbuf, permout, kout, err);
+}
+
+// Large IDs (3D faces): the same pivoted QR, one launch pair per step over all of a level's
+// large IDs, so each step's reflector is applied by many workgroups (one wavefront per column)
+// instead of one.  Per step: k_qr_pivot (one workgroup per ID) picks the column of largest
+// remaining norm (ties: lowest position), applies the rank test, swaps it into place and forms
+// the reflector; k_qr_apply updates every later column and recomputes its norm over the rows
+// below the step.  The arithmetic and the order of the steps are those of k_id.
+struct QrState {
+  int32_t k, stopped;
+  double r00, tau, v0;
+};
+
+__global__ __launch_bounds__(kBT) void k_qr_init(const IdTask* __restrict__ tasks,
+                                                 const SubBlk* __restrict__ rs,
+                                                 const double* __restrict__ A,
+                                                 double* __restrict__ work,
+                                                 int32_t* __restrict__ perm,
+                                                 QrState* __restrict__ qs) {
+  const IdTask t = tasks[blockIdx.x];
+  const int n = t.n, m = t.m;
+  double* M = work + t.offW;
+  double* nrm = M + (int64_t)m * n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int r0 = 0;
+  for (int q = 0; q < t.nrs; ++q) {
+    const SubBlk sb = rs[t.offRS + q];
+    for (int64_t e = threadIdx.x; e < (int64_t)sb.width * n; e += blockDim.x) {
+      const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+      M[(int64_t)j * m + r0 + i] = A[sb.off + e];
+    }
+    r0 += sb.width;
+  }
+  for (int j = threadIdx.x; j < n; j += blockDim.x) perm[t.offPerm + j] = j;
+  __syncthreads();
+  for (int j = wid; j < n; j += nw) {
+    double acc = 0;
+    for (int i = lane; i < m; i += 64) acc += M[(int64_t)j * m + i] * M[(int64_t)j * m + i];
+    acc = wave_sum(acc);
+    if (lane == 0) nrm[j] = acc;
+  }
+  if (threadIdx.x == 0) qs[blockIdx.x] = QrState{-1, 0, 0.0, 0.0, 0.0};
+}
+
+__global__ __launch_bounds__(kBT) void k_qr_pivot(const IdTask* __restrict__ tasks, int st,
+                                                  double* __restrict__ work,
+                                                  int32_t* __restrict__ perm,
+                                                  QrState* __restrict__ qs, double eps) {
+  __shared__ double bv[kBT];
+  __shared__ int bi[kBT];
+  __shared__ int stop_s;
+  QrState q = qs[blockIdx.x];
+  if (q.stopped) return;
+  const IdTask t = tasks[blockIdx.x];
+  const int n = t.n, m = t.m;
+  double* M = work + t.offW;
+  double* nrm = M + (int64_t)m * n;
+  if (st >= min(m, n)) {
+    if (threadIdx.x == 0) {
+      q.k = st;
+      q.stopped = 1;
+      qs[blockIdx.x] = q;
+    }
+    return;
+  }
+  double best = -1.0;
+  int p = n;
+  for (int j = st + threadIdx.x; j < n; j += blockDim.x)
+    if (nrm[j] > best) { best = nrm[j]; p = j; }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = p;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double ob = bv[threadIdx.x + w];
+      const int oi = bi[threadIdx.x + w];
+      if (ob > bv[threadIdx.x] || (ob == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = ob;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  p = bi[0];
+  double pb = bv[0];
+  if (p >= n) {  // no comparable norm (NaN): keep the column in place, as the one-workgroup QR
+    p = st;
+    pb = nrm[st];
+  }
+  const double pn = sqrt(pb);
+  const double r00 = st == 0 ? pn : q.r00;
+  if (threadIdx.x == 0) stop_s = (pn <= eps * r00 || pn == 0.0) ? 1 : 0;
+  __syncthreads();
+  if (stop_s) {
+    if (threadIdx.x == 0) {
+      q.k = st;
+      q.stopped = 1;
+      q.r00 = r00;
+      qs[blockIdx.x] = q;
+    }
+    return;
+  }
+  if (p != st) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      const double a = M[(int64_t)st * m + i];
+      M[(int64_t)st * m + i] = M[(int64_t)p * m + i];
+      M[(int64_t)p * m + i] = a;
+    }
+    if (threadIdx.x == 0) {
+      const int32_t a = perm[t.offPerm + st];
+      perm[t.offPerm + st] = perm[t.offPerm + p];
+      perm[t.offPerm + p] = a;
+      nrm[p] = nrm[st];
     }
   }
   __syncthreads();
-  // S = I + T^T T
-  for (int64_t e = threadIdx.x; e < (int64_t)nr * nr; e += blockDim.x) {
-    const int a = (int)(e / nr), b = (int)(e - (int64_t)a * nr);
-    double acc = (a == b) ? 1.0 : 0.0;
-    for (int s = 0; s < k; ++s) acc += T[(int64_t)a * k + s] * T[(int64_t)b * k + s];
-    S[e] = acc;
+  const double x0 = M[(int64_t)st * m + st];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double alpha = x0 >= 0 ? -pn : pn;
+    const double v0 = x0 - alpha;
+    const double vtv = pn * pn - x0 * x0 + v0 * v0;
+    M[(int64_t)st * m + st] = alpha;
+    q.r00 = r00;
+    q.v0 = v0;
+    q.tau = vtv > 0 ? 2.0 / vtv : 0.0;
+    qs[blockIdx.x] = q;
   }
-  wg_identity(Li, nr, nr);
-  __syncthreads();
-  wg_potrf(S, nr, nr, err);
-  wg_trsm_lower(S, nr, nr, Li, nr, nr, true);
-  __syncthreads();
-  // factor values: T (column-major k x nr) and packed L_s^-1 after the group's packed L_g^-1
-  double* V = fv + t.offV + tri_count(n);
-  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) V[e] = T[e];
-  wg_store_packed(V + (int64_t)k * nr, Li, nr, nr);
-  // Wm = T L_s^-T,  X = I - Wm Wm^T (k x k)
-  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) {
-    const int s = (int)(e / nr), i = (int)(e - (int64_t)s * nr);
+}
+
+// One wavefront per column j > st: apply the step's reflector, then the squared norm over the
+// rows below st (the next step's pivot test).
+__global__ __launch_bounds__(kBT) void k_qr_apply(const IdTask* __restrict__ tasks, int st,
+                                                  double* __restrict__ work,
+                                                  const QrState* __restrict__ qs) {
+  const QrState q = qs[blockIdx.y];
+  if (q.stopped) return;
+  const IdTask t = tasks[blockIdx.y];
+  const int n = t.n, m = t.m;
+  const int lane = threadIdx.x & 63;
+  const int j = st + 1 + (int)blockIdx.x * (kBT / 64) + ((int)threadIdx.x >> 6);
+  if (j >= n) return;
+  double* M = work + t.offW;
+  const double* vc = M + (int64_t)st * m;  // the reflector below the diagonal
+  double* c = M + (int64_t)j * m;
+  if (q.tau > 0) {  // same lane split as k_id, so both give identical results
     double acc = 0;
-    for (int j = 0; j <= i; ++j) acc += T[(int64_t)j * k + s] * Li[(int64_t)i * nr + j];
-    Wm[e] = acc;
+    for (int i = st + lane; i < m; i += 64) acc += (i == st ? q.v0 : vc[i]) * c[i];
+    const double d = wave_sum(acc) * q.tau;
+    for (int i = st + lane; i < m; i += 64) c[i] -= d * (i == st ? q.v0 : vc[i]);
   }
-  __syncthreads();
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
-    const int a = (int)(e / k), b = (int)(e - (int64_t)a * k);
-    double acc = (a == b) ? 1.0 : 0.0;
-    for (int i = 0; i < nr; ++i) acc -= Wm[(int64_t)a * nr + i] * Wm[(int64_t)b * nr + i];
-    Xbuf[t.offX + e] = acc;
-  }
-  // pivot order: redundant first, then skeletons
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    permout[t.offPerm + i] = (i < nr) ? perm_s[k + i] : perm_s[i - nr];
-  if (threadIdx.x == 0) kout[t.kslot] = k;
+  double nn = 0;
+  for (int i = st + 1 + lane; i < m; i += 64) nn += c[i] * c[i];
+  nn = wave_sum(nn);
+  if (lane == 0) M[(int64_t)m * n + j] = nn;
+}
+
+__global__ __launch_bounds__(kBT) void k_qr_finish(const IdTask* __restrict__ tasks,
+                                                   double* __restrict__ work,
+                                                   const int32_t* __restrict__ perm,
+                                                   const QrState* __restrict__ qs,
+                                                   double* __restrict__ fv,
+                                                   double* __restrict__ Xbuf,
+                                                   int32_t* __restrict__ permout,
+                                                   int32_t* __restrict__ kout, int* err) {
+  const IdTask t = tasks[blockIdx.x];
+  id_finish(t, work + t.offW, qs[blockIdx.x].k, perm + t.offPerm, fv, Xbuf, permout, kout, err);
 }
 
 // ------------------------------------------------------------------------------- regroup --
@@ -476,6 +655,11 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   int front_min = 128;
   if (const char* e = std::getenv("HIFCN_FRONT_MIN")) front_min = std::max(1, std::atoi(e));
   FrontStats fstats;
+  const bool build_log = std::getenv("HIFCN_BUILD_LOG") != nullptr;
+  // IDs with at least this many columns use the multi-workgroup QR; HIFCN_QR_MULTI_MIN
+  // overrides it (tests force either path on small grids)
+  int qr_multi = 96;
+  if (const char* e = std::getenv("HIFCN_QR_MULTI_MIN")) qr_multi = std::max(1, std::atoi(e));
   auto check_err = [&](const char* where) {
     int e = 0;
     HIF_CHECK(hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -746,17 +930,66 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         t.kslot = (int32_t)q;
         it.push_back(t);
       }
-      DevBuf<IdTask> dit;
+      if (build_log) {
+        int mx_n = 0, mx_m = 0;
+        double mn = 0;
+        for (const IdTask& t : it) {
+          mx_n = std::max(mx_n, t.n);
+          mx_m = std::max(mx_m, t.m);
+          mn += (double)t.m * t.n;
+        }
+        int mx_i = 0, mx_b = 0, mx_g = 0;
+        for (const CellTask& t : ct) { mx_i = std::max(mx_i, t.nI); mx_b = std::max(mx_b, t.nB); }
+        for (int g : P.seps) mx_g = std::max(mx_g, gsz(g));
+        std::fprintf(stderr,
+                     "[hifcn build] level %d: %zu cells (max nI %d, nB %d), %zu separator groups "
+                     "(max %d), %zu IDs (max n %d, max m %d, sum m*n %.3g)\n",
+                     lev, ct.size(), mx_i, mx_b, P.seps.size(), mx_g, it.size(), mx_n, mx_m, mn);
+      }
+      // IDs of at least qr_multi columns take the multi-workgroup QR
+      std::vector<IdTask> small, big;
+      int big_steps = 0, big_cols = 0;
+      for (const IdTask& t : it) {
+        if (t.n >= qr_multi) {
+          big.push_back(t);
+          big_steps = std::max(big_steps, std::min(t.m, t.n));
+          big_cols = std::max(big_cols, t.n);
+        } else {
+          small.push_back(t);
+        }
+      }
+      DevBuf<IdTask> dit, dbig;
       DevBuf<SubBlk> drs;
       DevBuf<double> work(std::max<int64_t>(1, wo));
       Xbuf.alloc(std::max<int64_t>(1, xo));
       DevBuf<int32_t> dperm(std::max<int32_t>(1, po));
       DevBuf<int32_t> dk(std::max<size_t>(1, P.skel.size()));
-      upload(dit, it, s);
+      upload(dit, small, s);
+      upload(dbig, big, s);
       upload(drs, rs, s);
-      if (!it.empty())
-        hipLaunchKernelGGL(k_id, dim3(it.size()), dim3(kBT), 0, s, dit.p, drs.p, A.p, work.p, fv.p,
-                           Xbuf.p, dperm.p, dk.p, hd.eps, err.p);
+      if (!small.empty())
+        hipLaunchKernelGGL(k_id, dim3(small.size()), dim3(kBT), 0, s, dit.p, drs.p, A.p, work.p,
+                           fv.p, Xbuf.p, dperm.p, dk.p, hd.eps, err.p);
+      if (!big.empty()) {
+        const int nb = (int)big.size();
+        DevBuf<int32_t> pw(std::max<int32_t>(1, po));
+        DevBuf<QrState> qs(nb);
+        hipLaunchKernelGGL(k_qr_init, dim3(nb), dim3(kBT), 0, s, dbig.p, drs.p, A.p, work.p, pw.p,
+                           qs.p);
+        for (int st = 0; st <= big_steps; ++st) {
+          hipLaunchKernelGGL(k_qr_pivot, dim3(nb), dim3(kBT), 0, s, dbig.p, st, work.p, pw.p,
+                             qs.p, hd.eps);
+          const int cols = big_cols - st - 1;
+          if (st < big_steps && cols > 0)
+            hipLaunchKernelGGL(k_qr_apply, dim3((cols + kBT / 64 - 1) / (kBT / 64), nb),
+                               dim3(kBT), 0, s, dbig.p, st, work.p, (const QrState*)qs.p);
+        }
+        hipLaunchKernelGGL(k_qr_finish, dim3(nb), dim3(kBT), 0, s, dbig.p, work.p,
+                           (const int32_t*)pw.p, (const QrState*)qs.p, fv.p, Xbuf.p, dperm.p,
+                           dk.p, err.p);
+        HIF_CHECK(hipGetLastError());
+        check_err("skeletonization");  // synchronises: pw and qs are released after their use
+      }
       HIF_CHECK(hipGetLastError());
       permv.resize(po);
       if (po)
