@@ -276,6 +276,25 @@ __global__ __launch_bounds__(kBT) void k_jacobi_scale(const ScaleTask* __restric
   }
 }
 
+// Large groups after their Cholesky on the matrix cores: dense L_g^-1 (row-major, for the
+// rescaling) from the packed copy, and A_gg <- I.
+__global__ __launch_bounds__(kBT) void k_jacobi_unpack(const GroupTask* __restrict__ tasks,
+                                                       double* __restrict__ A,
+                                                       double* __restrict__ LD,
+                                                       const double* __restrict__ fv) {
+  const GroupTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  const double* pk = fv + t.offV;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    LD[t.offLD + e] = j <= i ? pk[colstart(j, n) + (i - j)] : 0.0;
+    A[t.offBlk + e] = i == j ? 1.0 : 0.0;
+  }
+}
+
+// blocks with both sides at least this large are rescaled by products on the matrix cores
+constexpr int kScaleMfma = 48;
+
 // ------------------------------------------------------------------ (3) skeletonization --
 // T = R11^-1 R12, L_s, X and the outputs of one ID, once the first k steps of the pivoted QR are
 // in M (R in its upper triangle) and perm holds the column order.  Work layout after M: norms
@@ -655,6 +674,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   int front_min = 128;
   if (const char* e = std::getenv("HIFCN_FRONT_MIN")) front_min = std::max(1, std::atoi(e));
   FrontStats fstats;
+  const int scale_min = std::min(kScaleMfma, front_min);  // forcing the front path forces this too
   const bool build_log = std::getenv("HIFCN_BUILD_LOG") != nullptr;
   // IDs with at least this many columns use the multi-workgroup QR; HIFCN_QR_MULTI_MIN
   // overrides it (tests force either path on small grids)
@@ -851,34 +871,64 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     // ---- (2) block Jacobi on every separator group
     std::vector<int64_t> ld_off(G, -1);
     {
-      std::vector<GroupTask> gt;
+      // large groups: Cholesky and inverse as fronts without boundary on the matrix cores
+      std::vector<GroupTask> gt, gbig;
+      std::vector<FrontTask> gf;
       int64_t wo = 0, lo2 = 0;
       for (int g : P.seps) {
         const int n = gsz(g);
         ld_off[g] = lo2;
-        gt.push_back({n, 0, P.block_off[P.find_block(g, g)], wo, lo2, grp_voff[g]});
-        wo += (int64_t)n * n;
+        const GroupTask t{n, 0, P.block_off[P.find_block(g, g)], wo, lo2, grp_voff[g]};
+        if (n >= front_min) {
+          gbig.push_back(t);
+          gf.push_back({n, 0, 0, 0, t.offBlk, t.offV, -1, 0, 0});
+        } else {
+          gt.push_back(t);
+          wo += (int64_t)n * n;
+        }
         lo2 += (int64_t)n * n;
       }
-      DevBuf<GroupTask> dgt;
+      DevBuf<GroupTask> dgt, dgb;
       DevBuf<double> work(std::max<int64_t>(1, wo));
       DevBuf<double> LD(std::max<int64_t>(1, lo2));
       upload(dgt, gt, s);
+      upload(dgb, gbig, s);
       if (!gt.empty())
         hipLaunchKernelGGL(k_jacobi_chol, dim3(gt.size()), dim3(kBT), 0, s, dgt.p, A.p, work.p,
                            LD.p, fv.p, err.p);
+      if (!gf.empty()) {
+        build_fronts(gf, {}, A.p, nullptr, fv.p, err.p, s, &fstats);
+        hipLaunchKernelGGL(k_jacobi_unpack, dim3(gbig.size()), dim3(kBT), 0, s, dgb.p, A.p, LD.p,
+                           (const double*)fv.p);
+      }
       HIF_CHECK(hipGetLastError());
-      std::vector<ScaleTask> sc;
+      std::vector<ScaleTask> sc, scb;
       int64_t to = 0;
       for (size_t b = 0; b < P.blocks.size(); ++b) {
         const int g = P.blocks[b].first, h = P.blocks[b].second;
         if (g == h || P.groups[g].kind == 0 || P.groups[h].kind == 0) continue;
-        sc.push_back({P.block_off[b], to, ld_off[g], ld_off[h], gsz(g), gsz(h)});
+        const ScaleTask t{P.block_off[b], to, ld_off[g], ld_off[h], gsz(g), gsz(h)};
+        // large blocks: two batched products on the matrix cores
+        (gsz(g) >= scale_min && gsz(h) >= scale_min ? scb : sc).push_back(t);
         to += (int64_t)gsz(g) * gsz(h);
       }
       DevBuf<ScaleTask> dsc;
       DevBuf<double> tmp(std::max<int64_t>(1, to));
       upload(dsc, sc, s);
+      if (!scb.empty()) {
+        std::vector<GemmTask> y_of, a_of;
+        for (const ScaleTask& t : scb) {
+          double* Ab = A.p + t.offBlk;
+          double* Y = tmp.p + t.offTmp;
+          // Y = A_gh L_h^-T, then A_gh = L_g^-1 Y
+          y_of.push_back({Ab, LD.p + t.offLh, Y, t.cols, t.cols, t.cols, t.rows, t.cols, t.cols,
+                          1, 1, 0});
+          a_of.push_back({LD.p + t.offLg, Y, Ab, t.rows, t.cols, t.cols, t.rows, t.cols, t.rows,
+                          0, 2, 0});
+        }
+        gemm_batched(y_of, s, &fstats);
+        gemm_batched(a_of, s, &fstats);
+      }
       if (!sc.empty())
         hipLaunchKernelGGL(k_jacobi_scale, dim3(sc.size()), dim3(kBT), 0, s, dsc.p, A.p, tmp.p,
                            LD.p);

@@ -1,5 +1,5 @@
-// Dense FP64 elimination of large cells and of the root on the matrix cores (Sec. 2.2: the cell
-// elimination of eq2_3 and the root Cholesky of eq3_4).
+// Dense FP64 work of the factor build on the matrix cores (Sec. 2.2): the elimination of large
+// cells and of the root (eq2_3, eq3_4), and batched products (the block-Jacobi rescaling).
 //
 // A cell with interior I and boundary B is eliminated through the augmented front
 //
@@ -306,9 +306,91 @@ __global__ __launch_bounds__(kThreads) void k_front_h(const FrontTask* __restric
       }
 }
 
+// Stage rows [0, kv) x columns [0, cols) of src (row-major, ld) transposed: S[j][k] = src[k][j].
+__device__ __forceinline__ void stage_t(double* S, const double* src, int64_t ld, int kv,
+                                        int cols) {
+  for (int e = threadIdx.x; e < kT * kKc; e += kThreads) {
+    const int k = e / kT, j = e - k * kT;
+    S[j * kLd + k] = (k < kv && j < cols) ? src[(int64_t)k * ld + j] : 0.0;
+  }
+}
+
+// One 64 x 64 tile (task, first row, first column) of a batched product.
+__global__ __launch_bounds__(kThreads) void k_gemm_tiles(const GemmTask* __restrict__ tasks,
+                                                         const int4* __restrict__ tiles) {
+  __shared__ double As[kT * kLd], Bs[kT * kLd];
+  const int4 tl = tiles[blockIdx.x];
+  const GemmTask t = tasks[tl.x];
+  const int r0 = tl.y, c0 = tl.z;
+  const int rows = min(kT, t.m - r0), cols = min(kT, t.n - c0);
+  int kend = t.k;
+  if (t.tri == 1) kend = min(kend, c0 + cols);
+  if (t.tri == 2) kend = min(kend, r0 + rows);
+  d4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kend; k0 += kKc) {
+    const int kv = min(kKc, kend - k0);
+    stage(As, t.A + (int64_t)r0 * t.lda + k0, t.lda, rows, kv);
+    if (t.nt) stage(Bs, t.B + (int64_t)c0 * t.ldb + k0, t.ldb, cols, kv);
+    else stage_t(Bs, t.B + (int64_t)k0 * t.ldb + c0, t.ldb, kv, cols);
+    __syncthreads();
+    mfma_chunk(As, Bs, acc);
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(a, b, r, &row, &col);
+        if (row < rows && col < cols) t.C[(int64_t)(r0 + row) * t.ldc + c0 + col] = acc[a][b][r];
+      }
+}
+
 int cdiv(int64_t a, int b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
+
+void gemm_batched(const std::vector<GemmTask>& tasks, hipStream_t s, FrontStats* stats) {
+  if (tasks.empty()) return;
+  std::vector<int4> tiles;
+  for (size_t q = 0; q < tasks.size(); ++q) {
+    const GemmTask& t = tasks[q];
+    for (int r0 = 0; r0 < t.m; r0 += kT)
+      for (int c0 = 0; c0 < t.n; c0 += kT) tiles.push_back({(int)q, r0, c0, 0});
+    if (stats) {  // algorithmic flops (triangular operands count their nonzero part)
+      if (t.tri == 1) stats->flops += (int64_t)t.m * t.n * (t.n + 1);
+      else if (t.tri == 2) stats->flops += (int64_t)t.n * t.m * (t.m + 1);
+      else stats->flops += 2 * (int64_t)t.m * t.n * t.k;
+    }
+  }
+  if (tiles.empty()) return;
+  DevBuf<GemmTask> dt;
+  DevBuf<int4> dtl;
+  dt.upload(tasks, s);
+  dtl.upload(tiles, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIF_CHECK(hipEventCreate(&e0));
+    HIF_CHECK(hipEventCreate(&e1));
+    hipExtLaunchKernelGGL(k_gemm_tiles, dim3(tiles.size()), dim3(kThreads), 0, s, e0, e1, 0,
+                          (const GemmTask*)dt.p, (const int4*)dtl.p);
+  } else {
+    hipLaunchKernelGGL(k_gemm_tiles, dim3(tiles.size()), dim3(kThreads), 0, s,
+                       (const GemmTask*)dt.p, (const int4*)dtl.p);
+  }
+  HIF_CHECK(hipGetLastError());
+  if (stats) {
+    HIF_CHECK(hipStreamSynchronize(s));
+    float ms = 0;
+    HIF_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    stats->ms += ms;
+    ++stats->launches;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  // the task and tile lists are released when this returns; hipFree waits for the kernel
+}
 
 void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
                   const double* A, double* schur, double* fv, int* err, hipStream_t s,

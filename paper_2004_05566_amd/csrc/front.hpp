@@ -31,6 +31,21 @@ struct FrontStats {
   int64_t launches = 0;
 };
 
+// One product C = A B^T (nt = 1) or C = A B (nt = 0) of row-major FP64 matrices (m x n result,
+// inner dimension k).  tri = 1: B is lower triangular in the sense that column j of the result
+// needs only k <= j (C = A L^T with L lower); tri = 2: A is lower triangular (C = L B).
+struct GemmTask {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int32_t m, n, k, nt, tri, pad;
+};
+
+// Run every product (batched: one launch over the 64 x 64 tiles of all of them).  C must not
+// overlap A or B.
+void gemm_batched(const std::vector<GemmTask>& tasks, hipStream_t s, FrontStats* stats = nullptr);
+
 // Factor every task (batched: each kernel covers all tasks).  A non-positive pivot raises *err.
 // Synchronises the stream when `stats` is given (to read the kernel timings).
 void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
