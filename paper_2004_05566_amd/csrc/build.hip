@@ -624,7 +624,9 @@ __global__ __launch_bounds__(kBT) void k_regroup(const RegroupTask* __restrict__
                                                  double* __restrict__ Anew) {
   const RegroupTask t = tasks[blockIdx.x];
   const int64_t tot = (int64_t)t.nG * t.nH;
-  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+  // gridDim.y workgroups share a block (large blocks would otherwise run on one CU)
+  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.y * blockDim.x) {
     const int i = (int)(e / t.nH), j = (int)(e - (int64_t)i * t.nH);
     const RowSrc ri = rows[t.offRowsG + i], rj = rows[t.offRowsH + j];
     const SrcEnt s = src[t.offSrc + (int64_t)ri.sub * t.nsubH + rj.sub];
@@ -809,9 +811,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     std::vector<FrontSub> fsubs;
     woff = 0;
     for (CellTask t : ct) {
-      if (t.mode == 0 && t.nI >= front_min) {
+      if (t.nI >= front_min) {
         fronts.push_back({t.nI, t.nB, t.nsub, (int32_t)fsubs.size(), t.offAII, t.offV, t.offS,
-                          0, 0});
+                          0, 0, t.mode, t.offIb});
         for (int q = 0; q < t.nsub; ++q) fsubs.push_back({subs[t.offSub + q].off,
                                                           subs[t.offSub + q].width, 0});
       } else {
@@ -833,7 +835,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         hipLaunchKernelGGL(k_build_cells, dim3(small.size()), dim3(kBT), 0, s, dct.p, dsub.p,
                            dibl.p, A.p, work.p, schur.p, fv.p, err.p);
       HIF_CHECK(hipGetLastError());
-      build_fronts(fronts, fsubs, A.p, schur.p, fv.p, err.p, s, &fstats);
+      build_fronts(fronts, fsubs, A.p, schur.p, fv.p, err.p, s, &fstats, dibl.p);
       // Schur assembly into every separator block touched by some cell
       std::vector<std::vector<Contrib>> per_block(P.blocks.size());
       for (size_t ci = 0; ci < P.cells.size(); ++ci) {
@@ -1178,9 +1180,12 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       upload(dsrc, src, s);
       upload(dxoff, xoff, s);
       upload(dgk, gkv, s);
+      int64_t maxtot = 0;
+      for (const RegroupTask& t : rt) maxtot = std::max<int64_t>(maxtot, (int64_t)t.nG * t.nH);
+      const int slices = (int)std::min<int64_t>(64, std::max<int64_t>(1, maxtot / (1 << 16)));
       if (!rt.empty())
-        hipLaunchKernelGGL(k_regroup, dim3(rt.size()), dim3(kBT), 0, s, drt.p, drows.p, dsrc.p,
-                           A.p, Xbuf.p, dxoff.p, dgk.p, An.p);
+        hipLaunchKernelGGL(k_regroup, dim3(rt.size(), slices), dim3(kBT), 0, s, drt.p, drows.p,
+                           dsrc.p, A.p, Xbuf.p, dxoff.p, dgk.p, An.p);
       HIF_CHECK(hipGetLastError());
       HIF_CHECK(hipStreamSynchronize(s));
     }

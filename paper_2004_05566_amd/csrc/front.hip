@@ -118,7 +118,9 @@ __device__ bool panel_rows(const FrontTask& t, int k, int w, int blk, int* r0, i
 __global__ __launch_bounds__(kThreads) void k_front_init(const FrontTask* __restrict__ tasks,
                                                          const FrontSub* __restrict__ subs,
                                                          const double* __restrict__ A,
-                                                         double* __restrict__ F) {
+                                                         double* __restrict__ F,
+                                                         const int32_t* __restrict__ ibl,
+                                                         double* __restrict__ fv) {
   const FrontTask t = tasks[blockIdx.y];
   const int64_t ld = front_ld(t);
   const int R = 2 * t.nI + t.nB;
@@ -135,6 +137,8 @@ __global__ __launch_bounds__(kThreads) void k_front_init(const FrontTask* __rest
       const FrontSub sb = subs[t.offSub + q];
       for (int c = threadIdx.x; c < ld; c += kThreads)
         row[c] = c < t.nI ? A[sb.off + (int64_t)c * sb.width + (b - c0)] : 0.0;
+      if (t.mode == 1 && threadIdx.x == 0)  // the boundary DOF's one coupling, kept for the apply
+        fv[t.offV + tri_count(t.nI) + b] = A[sb.off + (int64_t)ibl[t.offIb + b] * sb.width + (b - c0)];
     } else {
       const int j = r - t.nI - t.nB;
       for (int c = threadIdx.x; c < ld; c += kThreads) row[c] = (c == j) ? 1.0 : 0.0;
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_front_h(const FrontTask* __restric
                                                       double* __restrict__ fv) {
   const FrontTask t = tasks[blockIdx.z];
   const int b0 = blockIdx.y * kT, j0 = blockIdx.x * kT;
-  if (b0 >= t.nB || j0 >= t.nI) return;
+  if (t.mode == 1 || b0 >= t.nB || j0 >= t.nI) return;
   const int64_t ld = front_ld(t);
   const double* Fb = F + t.offF;
   const int rows = min(kT, t.nB - b0), cols = min(kT, t.nI - j0);
@@ -394,8 +398,31 @@ void gemm_batched(const std::vector<GemmTask>& tasks, hipStream_t s, FrontStats*
 
 void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
                   const double* A, double* schur, double* fv, int* err, hipStream_t s,
-                  FrontStats* stats) {
+                  FrontStats* stats, const int32_t* ibl) {
   if (tasks.empty()) return;
+  // batches of at most kFrontBatch doubles of front storage
+  constexpr int64_t kFrontBatch = int64_t(1) << 28;
+  {
+    size_t b0 = 0;
+    int64_t acc = 0;
+    bool split = false;
+    for (size_t q = 0; q < tasks.size(); ++q) {
+      const int64_t f = (int64_t)(2 * tasks[q].nI + tasks[q].nB) * (tasks[q].nI + tasks[q].nB);
+      if (q > b0 && acc + f > kFrontBatch) {
+        build_fronts(std::vector<FrontTask>(tasks.begin() + b0, tasks.begin() + q), subs, A,
+                     schur, fv, err, s, stats, ibl);
+        b0 = q;
+        acc = 0;
+        split = true;
+      }
+      acc += f;
+    }
+    if (split) {
+      build_fronts(std::vector<FrontTask>(tasks.begin() + b0, tasks.end()), subs, A, schur, fv,
+                   err, s, stats, ibl);
+      return;
+    }
+  }
   // event pairs around every matrix-core launch (only when statistics are wanted)
   std::vector<hipEvent_t> ev;
   auto timed = [&](auto kernel, dim3 grid, auto... args) {
@@ -430,7 +457,7 @@ void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& sub
   std::vector<FrontSub> sv = subs.empty() ? std::vector<FrontSub>(1) : subs;
   ds.upload(sv, s);
   hipLaunchKernelGGL(k_front_init, dim3(cdiv(maxR, 4), nt), dim3(kThreads), 0, s, dt.p, ds.p, A,
-                     F.p);
+                     F.p, ibl, fv);
   for (int k = 0; k < maxI; k += kT) {
     // grid extents: the largest task at this panel (smaller ones exit at once)
     int prow = 0, pcol = 0;
@@ -461,7 +488,7 @@ void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& sub
         stats->flops += 2 * w * (m * (m + 1) / 2 + (int64_t)t.nB * m +
                                  (int64_t)t.nB * (t.nB + 1) / 2 + e * m);
       }
-      stats->flops += (int64_t)t.nB * t.nI * (t.nI + 1);
+      if (t.mode == 0) stats->flops += (int64_t)t.nB * t.nI * (t.nI + 1);
     }
     HIF_CHECK(hipStreamSynchronize(s));
     for (size_t q = 0; q < ev.size(); q += 2) {

@@ -17,6 +17,9 @@ struct FrontTask {
   int32_t nI, nB, nsub, offSub;
   int64_t offAII, offV, offS;
   int64_t offF, offD;  // internal: the front and the diagonal-block inverse (set by the driver)
+  // mode 1 (stencil links): instead of H, store the single coupling A_IB(ib_b, b) of each
+  // boundary DOF b, with ib_b = ibl[offIb + b]
+  int32_t mode = 0, offIb = 0;
 };
 struct FrontSub {
   int64_t off;
@@ -48,8 +51,10 @@ void gemm_batched(const std::vector<GemmTask>& tasks, hipStream_t s, FrontStats*
 
 // Factor every task (batched: each kernel covers all tasks).  A non-positive pivot raises *err.
 // Synchronises the stream when `stats` is given (to read the kernel timings).
+// Fronts are processed in batches of at most about 2 GiB of front storage.  ibl: device copy
+// of the interior positions of mode-1 tasks (may be NULL when there are none).
 void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& subs,
                   const double* A, double* schur, double* fv, int* err, hipStream_t s,
-                  FrontStats* stats = nullptr);
+                  FrontStats* stats = nullptr, const int32_t* ibl = nullptr);
 
 }  // namespace hifcn
