@@ -601,16 +601,47 @@ __global__ __launch_bounds__(kBT) void k_qr_apply(const IdTask* __restrict__ tas
   if (lane == 0) M[(int64_t)m * n + j] = nn;
 }
 
-__global__ __launch_bounds__(kBT) void k_qr_finish(const IdTask* __restrict__ tasks,
-                                                   double* __restrict__ work,
-                                                   const int32_t* __restrict__ perm,
-                                                   const QrState* __restrict__ qs,
-                                                   double* __restrict__ fv,
-                                                   double* __restrict__ Xbuf,
-                                                   int32_t* __restrict__ permout,
-                                                   int32_t* __restrict__ kout, int* err) {
+// Large IDs after the QR, the first part of id_finish: T = R11^-1 R12 (one column per lane),
+// its copy into the factor values, the pivot order and the rank.  The products that follow
+// (S = I + T^T T, X = I - Wm Wm^T with Wm = T L_s^-T) and chol(S) run on the matrix cores.
+__global__ __launch_bounds__(kBT) void k_qr_t(const IdTask* __restrict__ tasks,
+                                              double* __restrict__ work,
+                                              const int32_t* __restrict__ perm,
+                                              const QrState* __restrict__ qs,
+                                              double* __restrict__ fv,
+                                              int32_t* __restrict__ permout,
+                                              int32_t* __restrict__ kout) {
   const IdTask t = tasks[blockIdx.x];
-  id_finish(t, work + t.offW, qs[blockIdx.x].k, perm + t.offPerm, fv, Xbuf, permout, kout, err);
+  const int n = t.n, m = t.m, k = qs[blockIdx.x].k, nr = n - k;
+  const double* M = work + t.offW;
+  double* T = work + t.offW + (int64_t)m * n + n + m;
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    double* tc = T + (int64_t)j * k;
+    for (int s = k - 1; s >= 0; --s) {
+      double acc = M[(int64_t)(k + j) * m + s];
+      for (int q = s + 1; q < k; ++q) acc -= M[(int64_t)q * m + s] * tc[q];
+      tc[s] = acc / M[(int64_t)s * m + s];
+    }
+  }
+  __syncthreads();
+  double* V = fv + t.offV + tri_count(n);
+  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += blockDim.x) V[e] = T[e];
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    permout[t.offPerm + i] = (i < nr) ? perm[t.offPerm + k + i] : perm[t.offPerm + i - nr];
+  if (threadIdx.x == 0) kout[t.kslot] = k;
+}
+
+// Dense row-major copy (zeros above the diagonal) of packed column-major lower triangles.
+struct UnpackTask { int64_t src, dst; int32_t n, pad; };
+__global__ __launch_bounds__(kBT) void k_unpack_tri(const UnpackTask* __restrict__ tasks,
+                                                    const double* __restrict__ src,
+                                                    double* __restrict__ dst) {
+  const UnpackTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    dst[t.dst + e] = j <= i ? src[t.src + colstart(j, n) + (i - j)] : 0.0;
+  }
 }
 
 // ------------------------------------------------------------------------------- regroup --
@@ -924,9 +955,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
           double* Y = tmp.p + t.offTmp;
           // Y = A_gh L_h^-T, then A_gh = L_g^-1 Y
           y_of.push_back({Ab, LD.p + t.offLh, Y, t.cols, t.cols, t.cols, t.rows, t.cols, t.cols,
-                          1, 1, 0});
+                          1, 1, 0, 1.0, 0, 0});
           a_of.push_back({LD.p + t.offLg, Y, Ab, t.rows, t.cols, t.cols, t.rows, t.cols, t.rows,
-                          0, 2, 0});
+                          0, 2, 0, 1.0, 0, 0});
         }
         gemm_batched(y_of, s, &fstats);
         gemm_batched(a_of, s, &fstats);
@@ -1036,9 +1067,42 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
             hipLaunchKernelGGL(k_qr_apply, dim3((cols + kBT / 64 - 1) / (kBT / 64), nb),
                                dim3(kBT), 0, s, dbig.p, st, work.p, (const QrState*)qs.p);
         }
-        hipLaunchKernelGGL(k_qr_finish, dim3(nb), dim3(kBT), 0, s, dbig.p, work.p,
-                           (const int32_t*)pw.p, (const QrState*)qs.p, fv.p, Xbuf.p, dperm.p,
-                           dk.p, err.p);
+        // ranks back to the host: the rest is sized by them
+        std::vector<QrState> qh(nb);
+        HIF_CHECK(hipMemcpyAsync(qh.data(), qs.p, nb * sizeof(QrState), hipMemcpyDeviceToHost,
+                                 s));
+        HIF_CHECK(hipStreamSynchronize(s));
+        hipLaunchKernelGGL(k_qr_t, dim3(nb), dim3(kBT), 0, s, dbig.p, work.p,
+                           (const int32_t*)pw.p, (const QrState*)qs.p, fv.p, dperm.p, dk.p);
+        std::vector<GemmTask> g_s, g_w, g_x;
+        std::vector<FrontTask> f_s;
+        std::vector<UnpackTask> u_s;
+        for (int q = 0; q < nb; ++q) {
+          const IdTask& t = big[q];
+          const int n = t.n, m = t.m, k = qh[q].k, nr = n - k;
+          double* T = work.p + t.offW + (int64_t)m * n + n + m;  // k x nr col-major
+          double* S = T + (int64_t)k * nr;
+          double* Li = S + (int64_t)nr * nr;
+          double* Wm = Li + (int64_t)nr * nr;
+          // X = I - Wm Wm^T (k x k); with nothing redundant (nr = 0) that is the identity
+          g_x.push_back({Wm, Wm, Xbuf.p + t.offX, nr, nr, k, k, k, nr, 1, 0, 0, -1.0, 1, 0});
+          if (nr == 0) continue;
+          g_s.push_back({T, T, S, k, k, nr, nr, nr, k, 1, 0, 0, 1.0, 1, 0});
+          f_s.push_back({nr, 0, 0, 0, S - work.p, t.offV + tri64(n) + (int64_t)k * nr, -1, 0, 0});
+          u_s.push_back({t.offV + tri64(n) + (int64_t)k * nr, Li - work.p, nr, 0});
+          g_w.push_back({T, Li, Wm, k, nr, nr, k, nr, nr, 1, 1, 1, 1.0, 0, 0});
+        }
+        gemm_batched(g_s, s, &fstats);                                    // S = I + T^T T
+        build_fronts(f_s, {}, work.p, nullptr, fv.p, err.p, s, &fstats);  // packed L_s^-1
+        if (!u_s.empty()) {
+          DevBuf<UnpackTask> du;
+          upload(du, u_s, s);
+          hipLaunchKernelGGL(k_unpack_tri, dim3(u_s.size()), dim3(kBT), 0, s,
+                             (const UnpackTask*)du.p, (const double*)fv.p, work.p);
+          HIF_CHECK(hipGetLastError());
+          gemm_batched(g_w, s, &fstats);  // Wm = T L_s^-T (also synchronises before du goes)
+        }
+        gemm_batched(g_x, s, &fstats);    // X = I - Wm Wm^T
         HIF_CHECK(hipGetLastError());
         check_err("skeletonization");  // synchronises: pw and qs are released after their use
       }

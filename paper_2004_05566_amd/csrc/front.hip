@@ -335,7 +335,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tiles(const GemmTask* __restr
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < kend; k0 += kKc) {
     const int kv = min(kKc, kend - k0);
-    stage(As, t.A + (int64_t)r0 * t.lda + k0, t.lda, rows, kv);
+    if (t.ta) stage_t(As, t.A + (int64_t)k0 * t.lda + r0, t.lda, kv, rows);
+    else stage(As, t.A + (int64_t)r0 * t.lda + k0, t.lda, rows, kv);
     if (t.nt) stage(Bs, t.B + (int64_t)c0 * t.ldb + k0, t.ldb, cols, kv);
     else stage_t(Bs, t.B + (int64_t)k0 * t.ldb + c0, t.ldb, kv, cols);
     __syncthreads();
@@ -347,7 +348,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tiles(const GemmTask* __restr
       for (int r = 0; r < 4; ++r) {
         int row, col;
         acc_pos(a, b, r, &row, &col);
-        if (row < rows && col < cols) t.C[(int64_t)(r0 + row) * t.ldc + c0 + col] = acc[a][b][r];
+        if (row < rows && col < cols)
+          t.C[(int64_t)(r0 + row) * t.ldc + c0 + col] =
+              t.alpha * acc[a][b][r] + ((t.addI && r0 + row == c0 + col) ? 1.0 : 0.0);
       }
 }
 

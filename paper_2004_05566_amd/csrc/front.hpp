@@ -34,15 +34,18 @@ struct FrontStats {
   int64_t launches = 0;
 };
 
-// One product C = A B^T (nt = 1) or C = A B (nt = 0) of row-major FP64 matrices (m x n result,
-// inner dimension k).  tri = 1: B is lower triangular in the sense that column j of the result
-// needs only k <= j (C = A L^T with L lower); tri = 2: A is lower triangular (C = L B).
+// One product C = alpha op(A) op(B) (+ I if addI) of row-major FP64 matrices (m x n result,
+// inner dimension k): op(B) = B^T if nt = 1, else B; op(A) = A, or with ta = 1 A is given as
+// its transpose (k x m).  tri = 1: column j of the result needs only inner indices <= j (op(B)
+// = L^T with L lower); tri = 2: row i needs only inner indices <= i (op(A) lower triangular).
 struct GemmTask {
   const double* A;
   const double* B;
   double* C;
   int64_t lda, ldb, ldc;
-  int32_t m, n, k, nt, tri, pad;
+  int32_t m, n, k, nt, tri, ta;
+  double alpha;
+  int32_t addI, pad;
 };
 
 // Run every product (batched: one launch over the 64 x 64 tiles of all of them).  C must not

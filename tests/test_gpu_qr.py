@@ -1,7 +1,9 @@
 """The multi-workgroup pivoted QR of large IDs against the one-workgroup QR and the oracle.
 
 HIFCN_QR_MULTI_MIN=1 sends every ID through the per-step launches; both paths take the same
-pivots with the same lane split of every reduction, so the factors are identical.
+pivots with the same lane split of every reduction, so the ranks and skeletons are identical;
+the products after the QR run on the matrix cores in the multi-workgroup path, so the factors
+agree to rounding.
 """
 import os
 
@@ -43,7 +45,8 @@ def test_multi_workgroup_qr_matches_one_workgroup_qr(case, eps, gpu_lib):
     h0 = _factor(a, 0.05, n, dim, leaf, eps, 1 << 30)
     assert h1.info()["entries"] == h0.info()["entries"]
     x = torch.tensor(np.random.default_rng(5).normal(size=n ** dim), device="cuda")
-    assert torch.equal(h1.apply(x), h0.apply(x))
+    y1, y0 = h1.apply(x), h0.apply(x)
+    assert torch.linalg.norm(y1 - y0) <= 1e-12 * torch.linalg.norm(y0)
     h1.close()
     h0.close()
 
