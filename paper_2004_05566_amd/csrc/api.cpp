@@ -1,6 +1,9 @@
 // C-ABI entry points of libhifcn (declared in include/hifcn.h).
 #include <cmath>
+#include <cstdlib>
+#include <exception>
 #include <string>
+#include <thread>
 
 #include "kernels.hpp"
 
@@ -82,6 +85,15 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 8 * sizeof(int32_t),
                           hipHostMallocDefault));
   return h;
+}
+
+// Host threads that share the launches of one batched step (HIFCN_BATCH_THREADS, default 8).
+int batch_threads() {
+  static const int n = [] {
+    const char* e = std::getenv("HIFCN_BATCH_THREADS");
+    return e ? std::max(1, std::atoi(e)) : 8;
+  }();
+  return n;
 }
 
 // One Crank-Nicolson step of one solve, as a small state machine so that several solves can be
@@ -317,27 +329,55 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
       st[i].u = us[i];
       st[i].step = 0;
     }
-    for (auto& x : st) step_begin(x);
-    int open = count;
-    while (open > 0) {
-      for (auto& x : st)
-        if (!x.finished) step_queue(x);
-      for (auto& x : st)
-        if (!x.finished) HIF_CHECK(hipStreamSynchronize(x.s));
-      for (auto& x : st)
-        if (!x.finished) {
-          step_after_sync(x);
-          if (x.finished) --open;
-        }
+    // Solves are split over host threads (launching is host-bound when many solves run), each
+    // thread advancing its share in lockstep with one read-back per round.
+    auto run = [&](int w, int W, int dev) {
+      HIF_CHECK(hipSetDevice(dev));
+      std::vector<StepState*> mine;
+      for (int i = w; i < count; i += W) mine.push_back(&st[i]);
+      for (StepState* x : mine) step_begin(*x);
+      size_t open = mine.size();
+      while (open > 0) {
+        for (StepState* x : mine)
+          if (!x->finished) step_queue(*x);
+        for (StepState* x : mine)
+          if (!x->finished) HIF_CHECK(hipStreamSynchronize(x->s));
+        for (StepState* x : mine)
+          if (!x->finished) {
+            step_after_sync(*x);
+            if (x->finished) --open;
+          }
+      }
+      for (StepState* x : mine) {  // the finish kernel's statistics, into pinned memory
+        HIF_CHECK(hipMemcpyAsync(x->h->host_flag, x->h->step_iters.p, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, x->s));
+        HIF_CHECK(hipMemcpyAsync(x->h->host_flag + 4, x->h->step_relres.p, sizeof(double),
+                                 hipMemcpyDeviceToHost, x->s));
+      }
+      for (StepState* x : mine) HIF_CHECK(hipStreamSynchronize(x->s));
+    };
+    if (count == 0) return;
+    int dev = 0;
+    HIF_CHECK(hipGetDevice(&dev));
+    const int W = std::min(count, batch_threads());
+    if (W <= 1) {
+      run(0, 1, dev);
+    } else {
+      std::vector<std::thread> pool;
+      std::vector<std::exception_ptr> errs(W);
+      for (int w = 0; w < W; ++w)
+        pool.emplace_back([&, w] {
+          try {
+            run(w, W, dev);
+          } catch (...) {
+            errs[w] = std::current_exception();
+          }
+        });
+      for (std::thread& t : pool) t.join();
+      for (std::exception_ptr& e : errs)
+        if (e) std::rethrow_exception(e);
     }
     int failed = -1;
-    for (auto& x : st)  // the finish kernel's statistics, into pinned memory
-      HIF_CHECK(hipMemcpyAsync(x.h->host_flag, x.h->step_iters.p, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, x.s));
-    for (auto& x : st)
-      HIF_CHECK(hipMemcpyAsync(x.h->host_flag + 4, x.h->step_relres.p, sizeof(double),
-                               hipMemcpyDeviceToHost, x.s));
-    for (auto& x : st) HIF_CHECK(hipStreamSynchronize(x.s));
     for (int i = 0; i < count; ++i) {
       const Handle& h = *st[i].h;
       double rr;

@@ -17,6 +17,7 @@
 // Root: chol of the last remaining block (eq3_4).  The host plans the index structure between
 // launches; only ranks and pivot orders come back from the device once per level.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -687,7 +688,7 @@ __global__ void k_to_store_bf16(const double* src, bf16_t* dst, int64_t n) {
 
 template <typename T>
 void upload(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
-  d.alloc(std::max<size_t>(1, h.size()));
+  d.alloc_on(std::max<size_t>(1, h.size()), s);
   if (!h.empty())
     HIF_CHECK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
@@ -700,7 +701,7 @@ int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t s) {
   (void)a_cells;  // the link weights were already derived from it
   const Geometry geo{hd.dim, hd.n, hd.leaf, hd.L};
-  DevBuf<int> err(1);
+  DevBuf<int> err(1, s);
   HIF_CHECK(hipMemsetAsync(err.p, 0, sizeof(int), s));
   // cells with at least this many interior DOFs (and the root) use the blocked front path;
   // HIFCN_FRONT_MIN overrides it (tests force either path on small grids)
@@ -709,6 +710,16 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   FrontStats fstats;
   const int scale_min = std::min(kScaleMfma, front_min);  // forcing the front path forces this too
   const bool build_log = std::getenv("HIFCN_BUILD_LOG") != nullptr;
+  // with the log on, each phase's wall time (the stream is synchronised at every mark)
+  auto t_last = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what, int lev) {
+    if (!build_log) return;
+    HIF_CHECK(hipStreamSynchronize(s));
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[hifcn build] level %d %-14s %8.3f ms\n", lev, what,
+                 std::chrono::duration<double, std::milli>(now - t_last).count());
+    t_last = now;
+  };
   // IDs with at least this many columns use the multi-workgroup QR; HIFCN_QR_MULTI_MIN
   // overrides it (tests force either path on small grids)
   int qr_multi = 96;
@@ -722,7 +733,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   };
 
   LevelPlan P = plan_level0(geo);
-  DevBuf<double> A(std::max<int64_t>(1, P.nvals));
+  mark("plan", 0);
+  DevBuf<double> A(std::max<int64_t>(1, P.nvals), s);
   {  // level-0 blocks straight from the stencil
     std::vector<int32_t> ids;
     std::vector<int32_t> goff(P.groups.size());
@@ -804,7 +816,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       voff += tri64(gsz(g)) * (P.groups[g].kind == 1 ? 2 : 1);
     }
     voff = align_vals(voff);
-    DevBuf<double> fv(std::max<int64_t>(1, voff));
+    DevBuf<double> fv(std::max<int64_t>(1, voff), s);
 
     // ---- (1) cell elimination
     std::vector<CellTask> ct(P.cells.size());
@@ -857,8 +869,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       DevBuf<CellTask> dct;
       DevBuf<SubBlk> dsub;
       DevBuf<int32_t> dibl;
-      DevBuf<double> work(std::max<int64_t>(1, woff));
-      DevBuf<double> schur(std::max<int64_t>(1, soff));
+      DevBuf<double> work(std::max<int64_t>(1, woff), s);
+      DevBuf<double> schur(std::max<int64_t>(1, soff), s);
       upload(dct, small, s);
       upload(dsub, subs, s);
       upload(dibl, ibl, s);
@@ -901,6 +913,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       check_err("cell elimination");
     }
 
+    mark("cells", lev);
     // ---- (2) block Jacobi on every separator group
     std::vector<int64_t> ld_off(G, -1);
     {
@@ -922,8 +935,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         lo2 += (int64_t)n * n;
       }
       DevBuf<GroupTask> dgt, dgb;
-      DevBuf<double> work(std::max<int64_t>(1, wo));
-      DevBuf<double> LD(std::max<int64_t>(1, lo2));
+      DevBuf<double> work(std::max<int64_t>(1, wo), s);
+      DevBuf<double> LD(std::max<int64_t>(1, lo2), s);
       upload(dgt, gt, s);
       upload(dgb, gbig, s);
       if (!gt.empty())
@@ -946,7 +959,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         to += (int64_t)gsz(g) * gsz(h);
       }
       DevBuf<ScaleTask> dsc;
-      DevBuf<double> tmp(std::max<int64_t>(1, to));
+      DevBuf<double> tmp(std::max<int64_t>(1, to), s);
       upload(dsc, sc, s);
       if (!scb.empty()) {
         std::vector<GemmTask> y_of, a_of;
@@ -969,6 +982,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       check_err("block Jacobi");
     }
 
+    mark("jacobi", lev);
     // ---- (3) skeletonization of every edge (3D: face)
     std::vector<int32_t> kval(P.skel.size());
     std::vector<int32_t> permv;
@@ -1043,10 +1057,10 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       }
       DevBuf<IdTask> dit, dbig;
       DevBuf<SubBlk> drs;
-      DevBuf<double> work(std::max<int64_t>(1, wo));
-      Xbuf.alloc(std::max<int64_t>(1, xo));
-      DevBuf<int32_t> dperm(std::max<int32_t>(1, po));
-      DevBuf<int32_t> dk(std::max<size_t>(1, P.skel.size()));
+      DevBuf<double> work(std::max<int64_t>(1, wo), s);
+      Xbuf.alloc_on(std::max<int64_t>(1, xo), s);
+      DevBuf<int32_t> dperm(std::max<int32_t>(1, po), s);
+      DevBuf<int32_t> dk(std::max<size_t>(1, P.skel.size()), s);
       upload(dit, small, s);
       upload(dbig, big, s);
       upload(drs, rs, s);
@@ -1055,8 +1069,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
                            fv.p, Xbuf.p, dperm.p, dk.p, hd.eps, err.p);
       if (!big.empty()) {
         const int nb = (int)big.size();
-        DevBuf<int32_t> pw(std::max<int32_t>(1, po));
-        DevBuf<QrState> qs(nb);
+        DevBuf<int32_t> pw(std::max<int32_t>(1, po), s);
+        DevBuf<QrState> qs(nb, s);
         hipLaunchKernelGGL(k_qr_init, dim3(nb), dim3(kBT), 0, s, dbig.p, drs.p, A.p, work.p, pw.p,
                            qs.p);
         for (int st = 0; st <= big_steps; ++st) {
@@ -1117,6 +1131,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       check_err("skeletonization");
     }
 
+    mark("skeletons", lev);
     // ---- record this level's apply layout
     std::vector<int> gk(G, -1);
     for (size_t q = 0; q < P.skel.size(); ++q) gk[P.skel[q]] = kval[q];
@@ -1198,8 +1213,10 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     chunks.push_back(std::move(fv));
 
     // ---- regroup into level l+1
+    mark("layout", lev);
     LevelPlan Pn = plan_next(geo, P, surv);
-    DevBuf<double> An(std::max<int64_t>(1, Pn.nvals));
+    mark("plan next", lev);
+    DevBuf<double> An(std::max<int64_t>(1, Pn.nvals), s);
     {
       std::vector<RegroupTask> rt;
       std::vector<RowSrc> rows;
@@ -1255,13 +1272,15 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     }
     A = std::move(An);
     P = std::move(Pn);
+    mark("regroup", lev);
   }
 
   // ---- root: the single group left at level L
+  mark("(levels done)", hd.L);
   HIF_REQUIRE(P.cells.size() == 1 && P.seps.empty(), HIF_ERR_ARG, "internal: root is not one cell");
   const int rg = P.cells[0];
   const int nroot = (int)P.groups[rg].dofs.size();
-  DevBuf<double> rchunk(std::max<int64_t>(1, tri64(nroot)));
+  DevBuf<double> rchunk(std::max<int64_t>(1, tri64(nroot)), s);
   if (nroot >= front_min) {
     build_fronts({FrontTask{nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, -1, 0, 0}}, {},
                  A.p, nullptr, rchunk.p, err.p, s, &fstats);
@@ -1270,10 +1289,10 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     std::vector<CellTask> ct(1);
     ct[0] = {nroot, 0, 0, 0, P.block_off[P.find_block(rg, rg)], 0, 0, 0, 0, 0};
     DevBuf<CellTask> dct;
-    DevBuf<SubBlk> dsub(1);
-    DevBuf<int32_t> dibl(1);
-    DevBuf<double> work(std::max<int64_t>(1, 2 * (int64_t)nroot * nroot));
-    DevBuf<double> schur(1);
+    DevBuf<SubBlk> dsub(1, s);
+    DevBuf<int32_t> dibl(1, s);
+    DevBuf<double> work(std::max<int64_t>(1, 2 * (int64_t)nroot * nroot), s);
+    DevBuf<double> schur(1, s);
     upload(dct, ct, s);
     hipLaunchKernelGGL(k_build_cells, dim3(1), dim3(kBT), 0, s, dct.p, dsub.p, dibl.p, A.p,
                        work.p, schur.p, rchunk.p, err.p);
@@ -1375,8 +1394,10 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     const int64_t n = (l + 1 < outs.size() ? outs[l + 1].base : root_base) - outs[l].base;
     convert(chunks[l].p, outs[l].base, n);
   }
+  mark("root", hd.L);
   convert(rchunk.p, root_base, tri64(nroot));
   HIF_CHECK(hipGetLastError());
+  mark("store", hd.L);
   f.cbstride = std::max<int64_t>(1, cbmax);
   f.cb.alloc(2 * f.cbstride);
   {
@@ -1395,6 +1416,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   HIF_REQUIRE(worst <= 160 * 1024, HIF_ERR_ARG, "factor blocks too large for the apply kernels");
   if (worst > 64 * 1024) set_apply_smem_limits(worst);
   HIF_CHECK(hipStreamSynchronize(s));
+  mark("apply setup", hd.L);
 }
 
 }  // namespace hifcn

@@ -34,18 +34,31 @@ struct HifError : std::runtime_error {
   } while (0)
 
 // ---------------------------------------------------------------------------------------------
-// Owning device buffer.
+// Owning device buffer.  alloc() uses hipMalloc (long-lived buffers); alloc_on() uses the
+// stream-ordered allocator, so that the many short-lived buffers of a factor build neither take
+// a device-wide lock nor wait for other streams when they are freed (hipFree synchronises the
+// device; hipFreeAsync only orders the release on the buffer's stream).
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  hipStream_t so = nullptr;  // stream-ordered: the stream it was allocated on
+  bool ordered = false;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(size_t count, hipStream_t s) { alloc_on(count, s); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), so(o.so), ordered(o.ordered) {
+    o.p = nullptr;
+    o.n = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; so = o.so; ordered = o.ordered;
+      o.p = nullptr; o.n = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -54,10 +67,22 @@ struct DevBuf {
     n = count;
     if (count) HIF_CHECK(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
   }
+  void alloc_on(size_t count, hipStream_t s) {
+    release();
+    n = count;
+    so = s;
+    ordered = true;
+    if (count) HIF_CHECK(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), s));
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (ordered) (void)hipFreeAsync(p, so);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
+    ordered = false;
+    so = nullptr;
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     if (h.size() != n) alloc(h.size());

@@ -372,8 +372,8 @@ void gemm_batched(const std::vector<GemmTask>& tasks, hipStream_t s, FrontStats*
     }
   }
   if (tiles.empty()) return;
-  DevBuf<GemmTask> dt;
-  DevBuf<int4> dtl;
+  DevBuf<GemmTask> dt(tasks.size(), s);
+  DevBuf<int4> dtl(tiles.size(), s);
   dt.upload(tasks, s);
   dtl.upload(tiles, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -453,11 +453,11 @@ void build_fronts(std::vector<FrontTask> tasks, const std::vector<FrontSub>& sub
     maxLd = std::max(maxLd, t.nI + t.nB);
   }
   const int nt = (int)tasks.size();
-  DevBuf<double> F(foff), D((size_t)nt * kT * kT);
-  DevBuf<FrontTask> dt;
-  DevBuf<FrontSub> ds;
-  dt.upload(tasks, s);
+  DevBuf<double> F(foff, s), D((size_t)nt * kT * kT, s);
+  DevBuf<FrontTask> dt(tasks.size(), s);
   std::vector<FrontSub> sv = subs.empty() ? std::vector<FrontSub>(1) : subs;
+  DevBuf<FrontSub> ds(sv.size(), s);
+  dt.upload(tasks, s);
   ds.upload(sv, s);
   hipLaunchKernelGGL(k_front_init, dim3(cdiv(maxR, 4), nt), dim3(kThreads), 0, s, dt.p, ds.p, A,
                      F.p, ibl, fv);

@@ -31,6 +31,25 @@ uint64_t Geometry::key(int32_t id, int lev, int* kind) const {
   return k;
 }
 
+int64_t Geometry::slot(uint64_t key, int lev) const {
+  const int st = step(lev), ns = nsep(lev), R = 2 * ns + 1;
+  int64_t sl = 0, mul = 1;
+  for (int a = 0; a < dim; ++a) {
+    const uint64_t v = (key >> (21 * a)) & ((1ull << 21) - 1);
+    const int on = (int)(v >> 20), val = (int)(v & ((1ull << 20) - 1));
+    sl += mul * (on ? ns + val / st : val);
+    mul *= R;
+  }
+  return sl;
+}
+
+int64_t Geometry::nslots(int lev) const {
+  const int64_t R = 2 * nsep(lev) + 1;
+  int64_t t = 1;
+  for (int a = 0; a < dim; ++a) t *= R;
+  return t;
+}
+
 namespace {
 
 void decode(uint64_t key, int dim, int on[3], int val[3]) {
@@ -77,9 +96,8 @@ void finish_plan(const Geometry& geo, LevelPlan& P) {
       P.rows = std::move(r2);
     }
   }
-  std::unordered_map<uint64_t, int> gid;
-  gid.reserve(G * 2);
-  for (int i = 0; i < G; ++i) gid[P.groups[i].key] = i;
+  std::vector<int> gid(geo.nslots(P.level), -1);  // slot -> group
+  for (int i = 0; i < G; ++i) gid[geo.slot(P.groups[i].key, P.level)] = i;
   P.cells.clear();
   P.seps.clear();
   P.skel.clear();
@@ -90,7 +108,8 @@ void finish_plan(const Geometry& geo, LevelPlan& P) {
   }
   const int st = geo.step(P.level), ns = geo.nsep(P.level);
   P.cellB.assign(P.cells.size(), {});
-  std::vector<uint64_t> pairs;
+  // partners of each group: every group sharing a cell closure with it
+  std::vector<std::vector<int>> nbr(G);
   for (size_t ci = 0; ci < P.cells.size(); ++ci) {
     const int c = P.cells[ci];
     int on[3], val[3];
@@ -120,12 +139,12 @@ void finish_plan(const Geometry& geo, LevelPlan& P) {
         kd += o[a];
       }
       if (kd > 0) {
-        auto it = gid.find(encode(geo.dim, o, v));
-        if (it != gid.end()) {
-          closure.push_back(it->second);
+        const int h = gid[geo.slot(encode(geo.dim, o, v), P.level)];
+        if (h >= 0) {
+          closure.push_back(h);
           // at level 0 a cell interior couples (through the stencil) only to faces/edges with a
           // single separator coordinate
-          if (P.level > 0 || kd == 1) P.cellB[ci].push_back(it->second);
+          if (P.level > 0 || kd == 1) P.cellB[ci].push_back(h);
         }
       }
       int a = 0;
@@ -133,23 +152,26 @@ void finish_plan(const Geometry& geo, LevelPlan& P) {
       if (a == geo.dim) break;
     }
     std::sort(P.cellB[ci].begin(), P.cellB[ci].end());
-    for (int g : closure)
-      for (int h : closure) pairs.push_back(((uint64_t)(uint32_t)g << 32) | (uint32_t)h);
+    for (int g : closure) nbr[g].insert(nbr[g].end(), closure.begin(), closure.end());
   }
-  std::sort(pairs.begin(), pairs.end());
-  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  // blocks in (g, h) order: per g its partners sorted and unique
+  std::vector<uint64_t> pairs;
+  for (int g = 0; g < G; ++g) {
+    std::vector<int>& v = nbr[g];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    for (int h : v) pairs.push_back(((uint64_t)(uint32_t)g << 32) | (uint32_t)h);
+  }
   P.blocks.resize(pairs.size());
   P.block_off.resize(pairs.size());
-  P.block_of.clear();
-  P.block_of.reserve(pairs.size() * 2);
   int64_t off = 0;
   for (size_t b = 0; b < pairs.size(); ++b) {
     const int g = (int)(pairs[b] >> 32), h = (int)(pairs[b] & 0xffffffffu);
     P.blocks[b] = {g, h};
-    P.block_of[pairs[b]] = (int)b;
     P.block_off[b] = off;
     off += (int64_t)P.groups[g].dofs.size() * (int64_t)P.groups[h].dofs.size();
   }
+  P.block_keys = std::move(pairs);
   P.nvals = off;
 }
 
@@ -160,18 +182,14 @@ LevelPlan plan_level0(const Geometry& geo) {
   P.level = 0;
   int64_t N = 1;
   for (int d = 0; d < geo.dim; ++d) N *= geo.n;
-  std::unordered_map<uint64_t, int> gid;
+  std::vector<int> gid(geo.nslots(0), -1);  // slot -> group
   for (int64_t id = 0; id < N; ++id) {
     int kind;
     const uint64_t k = geo.key((int32_t)id, 0, &kind);
-    auto it = gid.find(k);
-    int g;
-    if (it == gid.end()) {
+    int& g = gid[geo.slot(k, 0)];
+    if (g < 0) {
       g = (int)P.groups.size();
-      gid[k] = g;
       P.groups.push_back({k, kind, {}});
-    } else {
-      g = it->second;
     }
     P.groups[g].dofs.push_back((int32_t)id);
   }
@@ -183,7 +201,7 @@ LevelPlan plan_next(const Geometry& geo, const LevelPlan& prev,
                     const std::vector<std::vector<int32_t>>& surv) {
   LevelPlan P;
   P.level = prev.level + 1;
-  std::unordered_map<uint64_t, int> gid;
+  std::vector<int> gid(geo.nslots(P.level), -1);  // slot -> group
   for (int g : prev.seps) {
     const PGroup& pg = prev.groups[g];
     const std::vector<int32_t>& sv = surv[g];
@@ -192,16 +210,12 @@ LevelPlan plan_next(const Geometry& geo, const LevelPlan& prev,
       const int32_t dof = pg.dofs[sv[s]];
       int kind;
       const uint64_t k = geo.key(dof, P.level, &kind);
-      auto it = gid.find(k);
-      int G;
-      if (it == gid.end()) {
+      int& G = gid[geo.slot(k, P.level)];
+      if (G < 0) {
         G = (int)P.groups.size();
-        gid[k] = G;
         P.groups.push_back({k, kind, {}});
         P.subs.emplace_back();
         P.rows.emplace_back();
-      } else {
-        G = it->second;
       }
       HIF_REQUIRE(target < 0 || target == G, HIF_ERR_ARG,
                   "internal: a group split across two groups of the next level");

@@ -10,7 +10,7 @@
 #pragma once
 
 #include <cstdint>
-#include <unordered_map>
+#include <algorithm>
 #include <vector>
 
 namespace hifcn {
@@ -37,7 +37,7 @@ struct LevelPlan {
   std::vector<std::vector<int>> cellB;        // per cell: boundary groups coupled to it
   // dense blocks (g, h) that may be non-zero: every ordered pair inside a cell closure
   std::vector<std::pair<int, int>> blocks;
-  std::unordered_map<uint64_t, int> block_of;  // (g << 32 | h) -> block index
+  std::vector<uint64_t> block_keys;           // (g << 32 | h) of each block, ascending
   std::vector<int64_t> block_off;             // value offsets (row-major |g| x |h|)
   int64_t nvals = 0;
   // provenance of each group's DOFs from the previous level (empty at level 0)
@@ -45,8 +45,9 @@ struct LevelPlan {
   std::vector<std::vector<RowSrc>> rows;      // per group: one entry per DOF
 
   int find_block(int g, int h) const {
-    auto it = block_of.find(((uint64_t)(uint32_t)g << 32) | (uint32_t)h);
-    return it == block_of.end() ? -1 : it->second;
+    const uint64_t k = ((uint64_t)(uint32_t)g << 32) | (uint32_t)h;
+    auto it = std::lower_bound(block_keys.begin(), block_keys.end(), k);
+    return (it == block_keys.end() || *it != k) ? -1 : (int)(it - block_keys.begin());
   }
 };
 
@@ -60,6 +61,11 @@ struct Geometry {
     c[2] = dim == 3 ? id / (n * n) + 1 : 0;
   }
   uint64_t key(int32_t id, int lev, int* kind) const;
+  // Dense index of a group key at level lev: per axis the rank of the coordinate class (the
+  // 2 nsep + 1 classes interval 0..nsep, then separator 1..nsep), slowest axis most
+  // significant, so that slots ascend with keys.
+  int64_t slot(uint64_t key, int lev) const;
+  int64_t nslots(int lev) const;
 };
 
 // Level-0 plan: every DOF is active, groups ordered by key, DOFs by id.
