@@ -91,6 +91,55 @@ __device__ __forceinline__ void stage_flat(C* dst, const S* src, int tot, int lt
   }
 }
 
+// stage_flat of a block together with the gather of up to two index lists from an FP64 vector
+// (list a: na values into da, list b: nb values into db).  The index loads are issued first,
+// then the block's first round of vector loads, then the value loads, which wait only for the
+// indices; the block reaches LDS after that.  So the dependent index -> value loads overlap the
+// block copy instead of following it.
+template <typename S, typename C>
+__device__ __forceinline__ void stage_gather(C* dst, const S* src, int tot,
+                                             const double* __restrict__ vec,
+                                             const int32_t* __restrict__ ia, int na, C* da,
+                                             const int32_t* __restrict__ ibx, int nb, C* db,
+                                             int lt, int nthr) {
+  using V = typename VecOf<S>::T;
+  constexpr int W = VecOf<S>::W;
+  constexpr int U = kStageUnroll;
+  const int ga = lt < na ? ia[lt] : -1;
+  const int gb = lt < nb ? ibx[lt] : -1;
+  const V* sv = reinterpret_cast<const V*>(src);
+  const int nv = (tot + W - 1) / W;
+  V r[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = lt + u * nthr;
+    if (q < nv) r[u] = sv[q];
+  }
+  const double va = ga >= 0 ? vec[ga] : 0.0;
+  const double vb = gb >= 0 ? vec[gb] : 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = lt + u * nthr;
+    if (q < nv) unpack<C>(r[u], dst + q * W);
+  }
+  for (int b = lt + U * nthr; b < nv; b += U * nthr) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = b + u * nthr;
+      if (q < nv) r[u] = sv[q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = b + u * nthr;
+      if (q < nv) unpack<C>(r[u], dst + q * W);
+    }
+  }
+  if (ga >= 0) da[lt] = (C)va;
+  if (gb >= 0) db[lt] = (C)vb;
+  for (int i = lt + nthr; i < na; i += nthr) da[i] = (C)vec[ia[i]];
+  for (int i = lt + nthr; i < nb; i += nthr) db[i] = (C)vec[ibx[i]];
+}
+
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Read-only views of the factor blocks: from LDS (packed layouts, ST) or global memory.
@@ -146,12 +195,15 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   C* ws = ys + nI;
   C* vs = ws + nI;
   int* ib = reinterpret_cast<int*>(vs + nI);
-  if constexpr (ST)
-    if (!prestaged) stage_flat(blk, v, tl + (mode ? nB : nB * nI), threadIdx.x, blockDim.x);
+  const int32_t* gI = idx + d.offI;
+  if (ST && !prestaged) {
+    stage_gather(blk, v, tl + (mode ? nB : nB * nI), y, gI, nI, ys, gI, 0, ys, threadIdx.x,
+                 blockDim.x);
+  } else {
+    for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)y[gI[i]];
+  }
   const Tri<S, C, ST> Li{blk, v, nI};
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
-  const int32_t* gI = idx + d.offI;
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)y[gI[i]];
   if constexpr (MODE == 1)
     for (int b = threadIdx.x; b < nB; b += blockDim.x) ib[b] = idx[d.offC + b];
   __syncthreads();
@@ -222,12 +274,16 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
   C* ts = xb + nB;
   C* us = ts + nI;
   int* ib = reinterpret_cast<int*>(us + nI);
-  if constexpr (ST) stage_flat(blk, v, tl + (mode ? nB : nB * nI), threadIdx.x, blockDim.x);
+  const int32_t* gI = idx + d.offI;
+  if constexpr (ST) {
+    stage_gather(blk, v, tl + (mode ? nB : nB * nI), x, gI, nI, xs, idx + d.offB, nB, xb,
+                 threadIdx.x, blockDim.x);
+  } else {
+    for (int i = threadIdx.x; i < nI; i += blockDim.x) xs[i] = (C)x[gI[i]];
+    for (int b = threadIdx.x; b < nB; b += blockDim.x) xb[b] = (C)x[idx[d.offB + b]];
+  }
   const Tri<S, C, ST> Li{blk, v, nI};
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
-  const int32_t* gI = idx + d.offI;
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) xs[i] = (C)x[gI[i]];
-  for (int b = threadIdx.x; b < nB; b += blockDim.x) xb[b] = (C)x[idx[d.offB + b]];
   if constexpr (MODE == 1)
     for (int b = threadIdx.x; b < nB; b += blockDim.x) ib[b] = idx[d.offC + b];
   __syncthreads();
