@@ -194,10 +194,19 @@ def cpu_baseline(w, budget_steps: int):
         _, its, _ = cn.cn_solve(A, B, w.u0, w.dt, budget_steps,
                                 lambda r: phif.phif_apply(F, r), 1e-8, w.reaction)
         ts = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": budget_steps / ts, "unit": "CN steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name}: oracle PHIF build ({tf:.1f} s, untimed in value) then "
-                      f"{budget_steps} CN steps at rtol 1e-8, mean n_i {np.mean(its):.2f}",
-            "t_factor_s": tf}
+                      f"{budget_steps} CN steps at rtol 1e-8, mean n_i {np.mean(its):.2f}, "
+                      f"one thread",
+            "t_factor_s": tf, "host_cpu": model, "host_nproc": os.cpu_count()}
 
 
 def reference_error(w, u_gpu, nsteps):
@@ -227,8 +236,9 @@ def main(argv=None):
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving workload (0: skip)")
-    ap.add_argument("--serving-rate", type=float, default=40.0,
-                    help="Poisson arrival rate of serving requests per second (0: all at once)")
+    ap.add_argument("--serving-rate", type=float, default=-1.0,
+                    help="Poisson arrival rate of serving requests per second; -1: 0.7 x the "
+                         "saturated throughput measured first; 0: only the saturated run")
     ap.add_argument("--serving-slots", type=int, default=32)
     ap.add_argument("--serving-builders", type=int, default=8,
                     help="threads (each with its own stream) building factors concurrently")
@@ -251,8 +261,19 @@ def main(argv=None):
     from workloads import gen
 
     def serving():
-        return serving_bench(args.serving, args.serving_rate, args.serving_slots,
-                             int(args.serving_budget_gb * (1 << 30)), args.serving_builders)
+        """Saturated run (all requests at t = 0) to measure the throughput mu, then Poisson
+        arrivals at the stated rate (default 0.7 mu)."""
+        budget = int(args.serving_budget_gb * (1 << 30))
+        sat = serving_bench(args.serving, 0.0, args.serving_slots, budget, args.serving_builders)
+        out = {"saturated": sat}
+        rate = args.serving_rate
+        if rate < 0:
+            rate = round(0.7 * sat["requests_per_s"], 1)
+            out["rate_rule"] = "0.7 x saturated requests/s"
+        if rate > 0:
+            out["poisson"] = serving_bench(args.serving, rate, args.serving_slots, budget,
+                                           args.serving_builders)
+        return out
 
     if args.serving_only:
         print(json.dumps({"serving": serving()}))
@@ -308,7 +329,7 @@ def main(argv=None):
         err = reference_error(w, u.cpu().numpy(), args.warmup + args.steps)
 
     out = {
-        "metric": "CN steps/s at 1e-8 rel. resid (FP32-HIF vs FP64), HIF-apply GB/s",
+        "metric": "CN steps/s at 1e-8 rel. resid (FP32-HIF vs FP64), HIF-apply GB/s; p99 latency",
         "value": value,
         "unit": "CN steps/s",
         "n_gpus": 1,

@@ -9,7 +9,8 @@ eq1 and eq_CN, Sec. 2.1) preconditioned by its own HIF factor (Sec. 2.2).  The s
   * advances every resident solve by one Crank-Nicolson step per round with one call of the
     library's batched entry point (each solve on its own stream, PCG iterations queued in
     lockstep, one convergence read-back per round for the whole batch), so the kernels of
-    different solves overlap on the device and newly built solves join at the next round,
+    different solves overlap on the device and newly built solves join at the next round;
+    solves of similar size share one of several scheduler lanes, which run concurrently,
   * copies a finished solve's state to the host, resolves its future and frees its memory.
 
 A solve's arithmetic does not depend on the other solves in the batch (every kernel touches only
@@ -98,10 +99,12 @@ class _Job:
 class Server:
     """Serve Request objects with at most `max_slots` resident solves within `hbm_budget_bytes`.
 
+    `lanes` scheduler threads each advance their own batch of resident solves (solves of similar
+    size share a lane) with the batched step entry point, concurrently with each other.
     submit() returns a concurrent.futures.Future resolved with a Result (or the error)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 32, builders: int = 2,
-                 device: int = 0, paused: bool = False):
+                 device: int = 0, paused: bool = False, lanes: int = 4):
         import torch
         self.device = torch.device("cuda", device)
         self.budget = int(hbm_budget_bytes)
@@ -109,7 +112,6 @@ class Server:
         self._cv = threading.Condition()
         self._waiting: collections.deque[_Job] = collections.deque()
         self._ready: list[_Job] = []
-        self._active: list[_Job] = []
         self._held = 0       # bytes reserved by admitted solves
         self._slots = 0      # admitted solves (building, ready or active)
         self._streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
@@ -123,8 +125,12 @@ class Server:
         self.batch_sizes: list[int] = []
         self.peak_held = 0
         self._error: BaseException | None = None
-        self._thread = threading.Thread(target=self._run, name="hif-serve", daemon=True)
-        self._thread.start()
+        self.lanes = max(1, int(lanes))
+        self._threads = [threading.Thread(target=self._run_lane, args=(k,),
+                                          name=f"hif-serve-{k}", daemon=True)
+                         for k in range(self.lanes)]
+        for t in self._threads:
+            t.start()
 
     # -- client side -------------------------------------------------------------------------
     def submit(self, req: Request, t_arrival: float | None = None) -> Future:
@@ -166,7 +172,8 @@ class Server:
             self._paused = False
             self._cv.notify_all()
         if wait:
-            self._thread.join()
+            for t in self._threads:
+                t.join()
         self._builders.shutdown(wait=wait)
         if self._error is not None:
             raise self._error
@@ -262,26 +269,40 @@ class Server:
             self._release_locked(job)
             self._cv.notify_all()
 
-    def _run(self):
+    @staticmethod
+    def _lane_of(job: "_Job", lanes: int) -> int:
+        """Solves of similar size share a lane (rounds in lockstep wait for their slowest
+        member, so mixing a 64^2 and a 512^2 solve would hold the small one back)."""
+        N = job.req.n ** job.req.dim
+        return (N.bit_length() // 2) % lanes
+
+    def _run_lane(self, lane: int):
+        active: list[_Job] = []
         try:
             while True:
                 with self._cv:
+                    if self._error is not None:
+                        return
                     self._admit_locked()
                     if not self._paused:
-                        self._active.extend(self._ready)
-                        self._ready.clear()
-                    if not self._active:
+                        mine = [j for j in self._ready if self._lane_of(j, self.lanes) == lane]
+                        for j in mine:
+                            self._ready.remove(j)
+                        active.extend(mine)
+                    if not active:
                         if self._closing and not self._waiting and self._slots == 0:
+                            self._cv.notify_all()
                             return
-                        self._cv.wait(timeout=0.05)
+                        self._cv.wait(timeout=0.02)
                         continue
-                    batch = list(self._active)
+                    batch = list(active)
                 its, rel, sts = hifcn.cn_batch_step(
                     [j.handle for j in batch], [j.u for j in batch],
                     [j.req.reaction for j in batch], [j.req.rtol for j in batch],
                     [j.req.maxit for j in batch], [j.stream for j in batch])
-                self.rounds += 1
-                self.batch_sizes.append(len(batch))
+                with self._cv:
+                    self.rounds += 1
+                    self.batch_sizes.append(len(batch))
                 finished = []
                 for j, it, rr, st in zip(batch, its, rel, sts):
                     j.step += 1
@@ -289,20 +310,18 @@ class Server:
                     j.relres.append(float(rr))
                     if st != hifcn.HIF_OK or j.step == j.req.nsteps:
                         finished.append((j, int(st)))
-                if finished:
-                    with self._cv:
-                        for j, _ in finished:
-                            self._active.remove(j)
-                    for j, st in finished:
-                        self._finish(j, st)
+                for j, st in finished:
+                    active.remove(j)
+                    self._finish(j, st)
         except BaseException as e:  # fail every outstanding request rather than hang them
-            self._error = e
             with self._cv:
-                for j in list(self._waiting) + self._ready + self._active:
+                if self._error is None:
+                    self._error = e
+                for j in list(self._waiting) + self._ready + active:
                     if not j.fut.done():
                         j.fut.set_exception(e)
                 self._waiting.clear()
-
+                self._cv.notify_all()
 
 def percentiles(latencies, qs=(50, 99)) -> dict:
     """p50/p99 (nearest-rank) of a list of latencies in seconds."""

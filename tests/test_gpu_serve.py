@@ -106,7 +106,7 @@ def test_server_mix_equals_alone(gpu_lib):
     reqs = [_req(n, dt, 200 + 10 * i, k, reaction=((1, 1.0, 1.0) if i % 2 else (0, 0.0, 1.0)),
                  store=("f32", "f64", "bf16")[i % 3])
             for i, (n, dt, k) in enumerate(specs)]
-    srv = Server(hbm_budget_bytes=1 << 30, max_slots=3, builders=2, paused=True)
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=3, builders=2, paused=True, lanes=1)
     futs = [srv.submit(r) for r in reqs[:5]]
     t_end = time.time() + 60
     while srv.ready_count() < 3 and time.time() < t_end:  # the first three slots are built
@@ -168,3 +168,18 @@ def test_server_admission_by_memory(gpu_lib):
     assert all(b[0] >= a[1] for a, b in zip(spans, spans[1:])), spans
     u, its, _ = _alone(small)
     assert np.array_equal(res[0].u, u) and np.array_equal(res[0].iters, its)
+
+
+def test_server_lanes_mix_equals_alone(gpu_lib):
+    """Several scheduler lanes (solves grouped by size) running concurrently: same results."""
+    from paper_2004_05566_amd.serve import Server
+    specs = [(32, 1e-2, 3), (64, 1e-1, 4), (128, 1e-3, 2), (32, 1e-1, 5), (64, 1e-2, 3),
+             (128, 1e-2, 2)]
+    reqs = [_req(n, dt, 500 + 10 * i, k) for i, (n, dt, k) in enumerate(specs)]
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=6, builders=3, lanes=3)
+    futs = [srv.submit(r) for r in reqs]
+    res = [f.result(timeout=120) for f in futs]
+    srv.close()
+    for r, x in zip(reqs, res):
+        u, its, _ = _alone(r)
+        assert np.array_equal(x.u, u) and np.array_equal(x.iters, its)
