@@ -1,0 +1,79 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+fisher2d-256 is small enough for the oracle: the FP64-stored factor must give the oracle's u to
+1e-10 (both solved to rtol 1e-12) with iteration counts within 1, and the FP32-stored factor at
+the benchmark's rtol 1e-8 must stay within 1e-7 of a sparse direct solve with at most one extra
+iteration.  heat2d-1024 and heat3d-64 are checked through a property that holds at any size:
+every GPU step's u^{k+1} solves the step's system (eq_CN) to the requested tolerance, with the
+residual recomputed in FP64 on the CPU from the stencil matrices of the oracle module.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import cn, fd, phif
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _factor(w, store):
+    import torch
+    from paper_2004_05566_amd import hifcn
+    a = torch.tensor(w.a_cells, dtype=torch.float64, device="cuda")
+    return hifcn.factor(a, w.dt, w.n, w.dim, w.eps, store=store, leaf=w.leaf)
+
+
+def test_fisher2d_256_fp64_matches_oracle(gpu_lib):
+    import torch
+    w = gen.workload("fisher2d-256")
+    A, B = fd.cn_matrices(w.a_cells, w.dt)
+    F = phif.phif_build(A, w.n, w.dim, w.leaf, w.eps)
+    us, its, _ = cn.cn_solve(A, B, w.u0, w.dt, 3, lambda r: phif.phif_apply(F, r), 1e-12,
+                             w.reaction)
+    h = _factor(w, "f64")
+    u = torch.tensor(w.u0.ravel(), device="cuda")
+    gits, _ = h.cn_solve(u, 3, rtol=1e-12, reaction=w.reaction)
+    assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])
+    assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)
+    h.close()
+
+
+def test_fisher2d_256_fp32_store_against_direct_solve(gpu_lib):
+    import torch
+    w = gen.workload("fisher2d-256")
+    A, B = fd.cn_matrices(w.a_cells, w.dt)
+    lu = spla.splu(A.tocsc())
+    steps = 5
+    h32, h64 = _factor(w, "f32"), _factor(w, "f64")
+    u32 = torch.tensor(w.u0.ravel(), device="cuda")
+    u64 = u32.clone()
+    it32, _ = h32.cn_solve(u32, steps, rtol=1e-8, reaction=w.reaction)
+    it64, _ = h64.cn_solve(u64, steps, rtol=1e-8, reaction=w.reaction)
+    u = w.u0.ravel().copy()
+    for _ in range(steps):
+        u = lu.solve(cn.cn_rhs(B, u, w.dt, w.reaction))
+    assert np.linalg.norm(u32.cpu().numpy() - u) <= 1e-7 * np.linalg.norm(u)
+    assert all(int(a) <= int(b) + 1 for a, b in zip(it32, it64)), (list(it32), list(it64))
+    h32.close()
+    h64.close()
+
+
+@pytest.mark.parametrize("name,steps", [("heat2d-1024", 2), ("heat3d-64", 2)])
+def test_full_size_steps_solve_their_systems(name, steps, gpu_lib):
+    import torch
+    w = gen.workload(name)
+    print(f"[case] {name}", flush=True)
+    A, B = fd.cn_matrices(w.a_cells, w.dt)
+    h = _factor(w, "f32")
+    u = torch.tensor(w.u0.ravel(), device="cuda")
+    prev = w.u0.ravel().copy()
+    for k in range(steps):
+        it, rel = h.cn_step(u, rtol=w.rtol, reaction=w.reaction)
+        cur = u.cpu().numpy()
+        g = cn.cn_rhs(B, prev, w.dt, w.reaction)
+        res = np.linalg.norm(A @ cur - g) / np.linalg.norm(g)
+        assert rel <= w.rtol and res <= 10 * w.rtol, (k, it, rel, res)
+        assert 1 <= it <= 20, it
+        prev = cur
+    h.close()
