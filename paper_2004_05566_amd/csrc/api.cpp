@@ -204,7 +204,7 @@ int64_t handle_device_bytes(const Handle& h) {
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc);
   auto add_level = [&](const LevelDev& l) {
-    add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.owned);
+    add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.crec); add(l.grec); add(l.frec);
   };
   for (const LevelDev& l : f.lv) add_level(l);
   add_level(f.rootlv);

@@ -142,6 +142,17 @@ __device__ __forceinline__ void stage_gather(C* dst, const S* src, int tot,
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Per-block records: a block's descriptor followed by its index lists, with the descriptor's
+// offsets relative to the record, so that one coalesced copy into LDS brings everything a
+// stage needs before any of its data loads (instead of a descriptor load, then index loads,
+// then data loads).  `n` int32 (a multiple of 4), 16-byte aligned on both sides.
+__device__ __forceinline__ void load_record(int32_t* dst, const int32_t* __restrict__ src, int n,
+                                            int lt, int nthr) {
+  const int4* s4 = reinterpret_cast<const int4*>(src);
+  int4* d4 = reinterpret_cast<int4*>(dst);
+  for (int q = lt; q < n / 4; q += nthr) d4[q] = s4[q];
+}
+
 // Read-only views of the factor blocks: from LDS (packed layouts, ST) or global memory.
 // Tri: packed column-major lower triangle of order n; Col: column-major rows x cols block.
 template <typename S, typename C, bool ST>
@@ -245,16 +256,21 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
 }
 
 template <typename S, typename C, bool ST, int MODE>
-__global__ __launch_bounds__(256) void k_cell_fwd(const CellDesc* __restrict__ cd,
-                                                  const int32_t* __restrict__ idx,
+// One workgroup per cell; its record (stride int32) goes to the front of LDS.
+__global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ recs, int stride,
                                                   const S* __restrict__ vals,
                                                   double* __restrict__ y, double* __restrict__ cb,
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team) {
-  const CellDesc d = cd[blockIdx.x];
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cell_fwd_body<S, C, ST, MODE>(d, idx, vals, y, cb, blk_elems, team, false, smem_raw);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
+  const int dn = done ? *done : 0;
+  __syncthreads();
+  if (dn) return;
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
+                                smem_raw + 4 * stride);
 }
 
 //   mode 0: x_I <- L^-T x_I - H^T x_B as nI dot products over [L^-1 column | H column].
@@ -329,16 +345,19 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
 }
 
 template <typename S, typename C, bool ST, int MODE>
-__global__ __launch_bounds__(256) void k_cell_bwd(const CellDesc* __restrict__ cd,
-                                                  const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ recs, int stride,
                                                   const S* __restrict__ vals,
                                                   double* __restrict__ x,
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team) {
-  const CellDesc d = cd[blockIdx.x];
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cell_bwd_body<S, C, ST, MODE>(d, idx, vals, x, blk_elems, team, smem_raw);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
+  const int dn = done ? *done : 0;
+  __syncthreads();
+  if (dn) return;
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride);
 }
 
 // ----------------------------------------------------------------------------- group stages --
@@ -424,19 +443,27 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
 }
 
 template <typename S, typename C, bool ST>
-__global__ __launch_bounds__(256) void k_group_fwd(const GroupDesc* __restrict__ gd, int ngroup,
-                                                   int seg, int per_group, int blk_elems, int team,
-                                                   const int32_t* __restrict__ idx,
+// blockDim/seg groups per workgroup, consecutive, so their records are one contiguous copy.
+__global__ __launch_bounds__(256) void k_group_fwd(const int32_t* __restrict__ recs, int stride,
+                                                   int ngroup, int seg, int per_group,
+                                                   int blk_elems, int team,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ y,
                                                    const double* __restrict__ cb,
                                                    const int* __restrict__ done) {
-  const int gi = blockIdx.x * (blockDim.x / seg) + threadIdx.x / seg;
-  GroupDesc d{};
-  if (gi < ngroup) d = gd[gi];
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  group_fwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, idx, vals, y, cb, smem_raw);
+  const int per = blockDim.x / seg, g0 = blockIdx.x * per, cnt = min(per, ngroup - g0);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, recs + (int64_t)g0 * stride, cnt * stride, threadIdx.x, blockDim.x);
+  const int dn = done ? *done : 0;
+  __syncthreads();
+  if (dn) return;
+  const int gsel = threadIdx.x / seg;
+  const int32_t* rb = rec + gsel * stride;
+  GroupDesc d{};
+  if (gsel < cnt) d = *reinterpret_cast<const GroupDesc*>(rb);
+  group_fwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, rb, vals, y, cb,
+                           smem_raw + 4 * per * stride);
 }
 
 template <typename S, typename C, bool ST>
@@ -510,18 +537,25 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
 }
 
 template <typename S, typename C, bool ST>
-__global__ __launch_bounds__(256) void k_group_bwd(const GroupDesc* __restrict__ gd, int ngroup,
-                                                   int seg, int per_group, int blk_elems, int team,
-                                                   const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(256) void k_group_bwd(const int32_t* __restrict__ recs, int stride,
+                                                   int ngroup, int seg, int per_group,
+                                                   int blk_elems, int team,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ x,
                                                    const int* __restrict__ done) {
-  const int gi = blockIdx.x * (blockDim.x / seg) + threadIdx.x / seg;
-  GroupDesc d{};
-  if (gi < ngroup) d = gd[gi];
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  group_bwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, idx, vals, x, smem_raw);
+  const int per = blockDim.x / seg, g0 = blockIdx.x * per, cnt = min(per, ngroup - g0);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, recs + (int64_t)g0 * stride, cnt * stride, threadIdx.x, blockDim.x);
+  const int dn = done ? *done : 0;
+  __syncthreads();
+  if (dn) return;
+  const int gsel = threadIdx.x / seg;
+  const int32_t* rb = rec + gsel * stride;
+  GroupDesc d{};
+  if (gsel < cnt) d = *reinterpret_cast<const GroupDesc*>(rb);
+  group_bwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, rb, vals, x,
+                           smem_raw + 4 * per * stride);
 }
 
 // ------------------------------------------------------------------------------------ root --
@@ -595,30 +629,35 @@ __global__ __launch_bounds__(kRootThreads) void k_root(int nr, const int32_t* __
 // one load finds them.  With `prestage`, the cell's block is loaded into LDS (below `goff`)
 // while the groups run.
 template <typename S, typename C, bool CST>
-__global__ __launch_bounds__(1024) void k_fuse_fwd(const GroupDesc* __restrict__ owned,
-                                                   int maxown, int seg, int per_group, int blk_g,
-                                                   int goff, const CellDesc* __restrict__ cd,
-                                                   int blk_c, int team_c, int prestage,
-                                                   const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(1024) void k_fuse_fwd(const int32_t* __restrict__ frec, int fstride,
+                                                   int cstride, int gstride, int maxown, int seg,
+                                                   int per_group, int blk_g, int goff, int blk_c,
+                                                   int team_c, int prestage,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ y,
                                                    const double* __restrict__ cb_in,
                                                    double* __restrict__ cb_out,
                                                    const int* __restrict__ done) {
-  const int p = blockIdx.x;
-  const int gsel = threadIdx.x / seg;
-  GroupDesc g{};
-  if (gsel < maxown) g = owned[(int64_t)p * maxown + gsel];
-  const CellDesc d = cd[p];
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // the record of cell p, then those of the groups it owns (padded to maxown)
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, frec + (int64_t)blockIdx.x * fstride, fstride, threadIdx.x, blockDim.x);
+  const int dn = done ? *done : 0;
+  __syncthreads();
+  if (dn) return;
+  unsigned char* work = smem_raw + 4 * fstride;
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  const int gsel = threadIdx.x / seg;
+  const int32_t* rb = rec + cstride + gsel * gstride;
+  GroupDesc g{};
+  if (gsel < maxown) g = *reinterpret_cast<const GroupDesc*>(rb);
   if constexpr (CST)
     if (prestage)
-      stage_flat(reinterpret_cast<C*>(smem_raw), vals + d.offV, tri_count(d.nI) + d.nB * d.nI,
+      stage_flat(reinterpret_cast<C*>(work), vals + d.offV, tri_count(d.nI) + d.nB * d.nI,
                  threadIdx.x, blockDim.x);
-  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, 1, idx, vals, y, cb_in, smem_raw + goff);
+  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, 1, rb, vals, y, cb_in, work + goff);
   __syncthreads();
-  cell_fwd_body<S, C, CST, 0>(d, idx, vals, y, cb_out, blk_c, team_c, prestage != 0, smem_raw);
+  cell_fwd_body<S, C, CST, 0>(d, rec, vals, y, cb_out, blk_c, team_c, prestage != 0, work);
 }
 
 // The last level's groups (forward), the root, and the same groups (backward) in one
@@ -986,6 +1025,7 @@ __global__ __launch_bounds__(kTileThreads) void k_group_big_bwd(const GroupDesc*
 // --------------------------------------------------------------------------- launch plans --
 struct StagePlan {
   bool staged;
+  size_t rec;     // bytes of the block records at the front of LDS
   int threads;
   int seg;        // lanes per group (group stages)
   int per;        // groups per workgroup
@@ -1012,6 +1052,7 @@ StagePlan cell_plan(const LevelDev& L) {
   while (team < 8 && (team * 2) * L.maxI <= p.threads) team <<= 1;
   p.seg = team;
   if (!p.staged) p.blk_elems = 0;
+  p.rec = 4 * (size_t)L.cstride;
   p.smem = sizeof(C) * (p.blk_elems + vec);
   p.grid = L.ncell;
   return p;
@@ -1035,6 +1076,7 @@ StagePlan group_plan(const LevelDev& L) {
     p.per_group = vec;
     p.blk_elems = 0;
   }
+  p.rec = 4 * (size_t)p.per * L.gstride;
   p.smem = sizeof(C) * (size_t)p.per * p.per_group;
   p.grid = (L.ngroup + p.per - 1) / p.per;
   // column walks: lanes of one group read a column together when it is in global memory
@@ -1047,6 +1089,7 @@ StagePlan group_plan(const LevelDev& L) {
 // (team re-derived for that block size); or, for the root, groups `per` at a time.
 struct FusePlan {
   bool ok = false;
+  size_t rec = 0;  // bytes of the record (cell + owned groups) at the front of LDS
   int threads = 256, per = 0, team_c = 1, goff = 0;
   bool cst = false, prestage = false;
   int blk_c = 0;
@@ -1075,7 +1118,8 @@ FusePlan fuse_plan(const LevelDev& G, const LevelDev* Cl, int nroot) {
     f.cst = cp.staged;
     f.blk_c = cp.blk_elems;
     const size_t csm = (cp.smem + 15) / 16 * 16;
-    f.prestage = f.cst && csm + gsm <= kStageMax;
+    f.rec = 4 * (size_t)G.fstride;
+    f.prestage = f.cst && f.rec + csm + gsm <= kStageMax;
     f.goff = f.prestage ? (int)csm : 0;
     f.smem = f.prestage ? csm + gsm : std::max(gsm, cp.smem);
   } else {
@@ -1086,7 +1130,7 @@ FusePlan fuse_plan(const LevelDev& G, const LevelDev* Cl, int nroot) {
     f.prestage = rs;  // the root block is staged in LDS
     f.smem = std::max((size_t)f.per * pg, rsm);
   }
-  f.ok = f.smem <= kStageMax;
+  f.ok = f.rec + f.smem <= kStageMax;
   return f;
 }
 
@@ -1143,12 +1187,12 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
   const StagePlan p = cell_plan<C>(L);
   if (fwd) {
     auto k = p.staged ? k_cell_fwd<S, C, true, MODE> : k_cell_fwd<S, C, false, MODE>;
-    launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, L.cells.p, (const int32_t*)f.idx.p,
-           vals, y, cb, done, p.blk_elems, p.seg);
+    launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
+           L.cstride, vals, y, cb, done, p.blk_elems, p.seg);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
-    launch(k, dim3(p.grid), dim3(p.threads), p.smem, s, t, L.cells.p, (const int32_t*)f.idx.p,
-           vals, y, done, p.blk_elems, p.seg);
+    launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
+           L.cstride, vals, y, done, p.blk_elems, p.seg);
   }
 }
 
@@ -1213,10 +1257,10 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       const FusePlan fp = fuse_plan<C>(L, &P, 0);
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       auto k = fp.cst ? k_fuse_fwd<S, C, true> : k_fuse_fwd<S, C, false>;
-      launch(k, dim3(P.ncell), dim3(fp.threads), fp.smem, s, t, (const GroupDesc*)L.owned.p,
-             L.maxown, fp.g.seg, fp.g.per_group, fp.g.blk_elems, fp.goff,
-             (const CellDesc*)P.cells.p, fp.blk_c, fp.team_c, (int)fp.prestage, idx, vals, y,
-             (const double*)cbl(l), cbl(l + 1), done);
+      launch(k, dim3(P.ncell), dim3(fp.threads), fp.rec + fp.smem, s, t,
+             (const int32_t*)L.frec.p, L.fstride, P.cstride, L.gstride, L.maxown, fp.g.seg,
+             fp.g.per_group, fp.g.blk_elems, fp.goff, fp.blk_c, fp.team_c, (int)fp.prestage,
+             vals, y, (const double*)cbl(l), cbl(l + 1), done);
     } else if (l == nlev - 1 && f.root_fused) {  // + root + this level's backward groups
       const FusePlan fp = fuse_plan<C>(L, nullptr, f.nroot);
       const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
@@ -1231,9 +1275,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     } else {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       const StagePlan p = group_plan<C>(L);
-      launch(k_group_fwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.smem, s, t,
-             (const GroupDesc*)L.groups.p, L.ngroup, p.seg, p.per_group, p.blk_elems, p.team, idx,
-             vals, y, (const double*)cbl(l), done);
+      launch(k_group_fwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t,
+             (const int32_t*)L.grec.p, L.gstride, L.ngroup, p.seg, p.per_group, p.blk_elems,
+             p.team, vals, y, (const double*)cbl(l), done);
     }
   }
   if (f.nroot && !f.root_fused) {
@@ -1257,9 +1301,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
                s, t, (const GroupDesc*)L.groups.p, idx, vals, y, done);
       } else {
         const StagePlan p = group_plan<C>(L);
-        launch(k_group_bwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.smem, s, t,
-               (const GroupDesc*)L.groups.p, L.ngroup, p.seg, p.per_group, p.blk_elems, p.team,
-               idx, vals, y, done);
+        launch(k_group_bwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t,
+               (const int32_t*)L.grec.p, L.gstride, L.ngroup, p.seg, p.per_group, p.blk_elems,
+               p.team, vals, y, done);
       }
     }
     if (L.ncell) {
@@ -1280,11 +1324,11 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst) {
   for (const LevelDev& L : f.lv) {
     size_t c, g;
     if (f.store == HIF_STORE_F64) {
-      c = cell_plan<double>(L).smem;
-      g = group_plan<double>(L).smem;
+      c = cell_plan<double>(L).rec + cell_plan<double>(L).smem;
+      g = group_plan<double>(L).rec + group_plan<double>(L).smem;
     } else {
-      c = cell_plan<float>(L).smem;
-      g = group_plan<float>(L).smem;
+      c = cell_plan<float>(L).rec + cell_plan<float>(L).smem;
+      g = group_plan<float>(L).rec + group_plan<float>(L).smem;
     }
     if (L.tiled) c = cs * (size_t)(L.maxI + L.maxB);
     if (!(f.store == HIF_STORE_F64 ? group_plan<double>(L).staged : group_plan<float>(L).staged))
@@ -1299,8 +1343,9 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst) {
   for (int l = 0; l < nlev; ++l) {
     const LevelDev* P = l + 1 < nlev ? &f.lv[l + 1] : nullptr;
     if (!(f.lv[l].fuse || (!P && f.root_fused))) continue;
-    w = std::max(w, f.store == HIF_STORE_F64 ? fuse_plan<double>(f.lv[l], P, f.nroot).smem
-                                             : fuse_plan<float>(f.lv[l], P, f.nroot).smem);
+    const FusePlan fp = f.store == HIF_STORE_F64 ? fuse_plan<double>(f.lv[l], P, f.nroot)
+                                                 : fuse_plan<float>(f.lv[l], P, f.nroot);
+    w = std::max(w, fp.rec + fp.smem);
   }
   if (worst) *worst = w;
   return w;
@@ -1381,12 +1426,61 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
 }
 }  // namespace
 
+namespace {
+// Record of one cell: the descriptor with record-relative index offsets, then I, B and (link
+// mode) the interior positions of the couplings.
+int cell_record_len(const CellDesc& d) { return round_up(8 + d.nI + d.nB + (d.mode ? d.nB : 0), 4); }
+void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& idx) {
+  CellDesc e = d;
+  e.offI = 8;
+  e.offB = 8 + d.nI;
+  e.offC = d.mode ? 8 + d.nI + d.nB : 0;
+  std::memcpy(r, &e, sizeof(CellDesc));
+  for (int i = 0; i < d.nI; ++i) r[8 + i] = idx[d.offI + i];
+  for (int b = 0; b < d.nB; ++b) r[8 + d.nI + b] = idx[d.offB + b];
+  if (d.mode)
+    for (int b = 0; b < d.nB; ++b) r[8 + d.nI + d.nB + b] = idx[d.offC + b];
+}
+// Record of one group: the descriptor, then DOF ids, pivot order, gather pointers and slots.
+int group_record_len(const GroupDesc& g, const std::vector<int32_t>& idx) {
+  return round_up(8 + 2 * g.n + g.n + 1 + idx[g.offGP + g.n], 4);
+}
+void put_group_record(int32_t* r, const GroupDesc& g, const std::vector<int32_t>& idx) {
+  const int n = g.n, ns = idx[g.offGP + n];
+  GroupDesc e = g;
+  e.offIdx = 8;
+  e.offPerm = 8 + n;
+  e.offGP = 8 + 2 * n;
+  std::memcpy(r, &e, sizeof(GroupDesc));
+  for (int i = 0; i < n; ++i) r[8 + i] = idx[g.offIdx + i];
+  for (int i = 0; i < n; ++i)
+    r[8 + n + i] = g.offPerm + i < (int64_t)idx.size() ? idx[g.offPerm + i] : i;
+  for (int i = 0; i < n + 1 + ns; ++i) r[8 + 2 * n + i] = idx[g.offGP + i];
+}
+}  // namespace
+
 void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                   const std::vector<std::vector<GroupDesc>>& groups,
                   const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
   const bool f64 = f.store == HIF_STORE_F64;
   const int nlev = (int)f.lv.size();
   const bool off = std::getenv("HIFCN_NO_FUSE") != nullptr;
+  // block records of every level
+  for (int l = 0; l < nlev; ++l) {
+    LevelDev& L = f.lv[l];
+    L.cstride = 4;
+    for (const CellDesc& d : cells[l]) L.cstride = std::max(L.cstride, cell_record_len(d));
+    std::vector<int32_t> cr((size_t)cells[l].size() * L.cstride, 0);
+    for (size_t c = 0; c < cells[l].size(); ++c)
+      put_cell_record(cr.data() + c * L.cstride, cells[l][c], idx);
+    L.crec.upload(cr, s);
+    L.gstride = 8;
+    for (const GroupDesc& g : groups[l]) L.gstride = std::max(L.gstride, group_record_len(g, idx));
+    std::vector<int32_t> gr((size_t)groups[l].size() * L.gstride, 0);
+    for (size_t g = 0; g < groups[l].size(); ++g)
+      put_group_record(gr.data() + g * L.gstride, groups[l][g], idx);
+    L.grec.upload(gr, s);
+  }
   std::vector<int32_t> parent(N, -1);
   for (int l = 0; l + 1 < nlev; ++l) {
     LevelDev& L = f.lv[l];
@@ -1426,12 +1520,18 @@ void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
     int maxown = 0;
     for (int32_t c : load) maxown = std::max(maxown, c);
     L.maxown = maxown;
+    L.fstride = P.cstride + maxown * L.gstride;
     if (!(f64 ? fuse_plan<double>(L, &P, 0).ok : fuse_plan<float>(L, &P, 0).ok)) continue;
-    std::vector<GroupDesc> owned((size_t)pc.size() * maxown, GroupDesc{});
+    // per next-level cell: its record, then the records of the groups it owns
+    std::vector<int32_t> fr((size_t)pc.size() * L.fstride, 0);
+    for (size_t p = 0; p < pc.size(); ++p) put_cell_record(fr.data() + p * L.fstride, pc[p], idx);
     std::vector<int32_t> fill(pc.size(), 0);
-    for (size_t g = 0; g < gs.size(); ++g)
-      owned[(size_t)owner[g] * maxown + fill[owner[g]]++] = gs[g];
-    L.owned.upload(owned, s);
+    for (size_t g = 0; g < gs.size(); ++g) {
+      const int32_t o = owner[g];
+      put_group_record(fr.data() + (size_t)o * L.fstride + P.cstride +
+                           (size_t)fill[o]++ * L.gstride, gs[g], idx);
+    }
+    L.frec.upload(fr, s);
     L.fuse = true;
   }
   f.root_fused = false;

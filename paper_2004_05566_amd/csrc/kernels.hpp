@@ -29,7 +29,11 @@ struct LevelDev {
   // with empty descriptors).
   bool fuse = false;
   int maxown = 0;
-  DevBuf<GroupDesc> owned;
+  // Block records (descriptor with record-relative offsets, then its index lists), fixed
+  // stride in int32 per block: cells, groups, and (fused levels) each next-level cell's record
+  // followed by those of the groups it owns.
+  DevBuf<int32_t> crec, grec, frec;
+  int cstride = 0, gstride = 0, fstride = 0;
 };
 
 // Stages of one apply, as timed by the profiler.
