@@ -398,14 +398,18 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
     yg[i] = (C)acc;
   }
   __syncthreads();
-  for (int i = lt; i < n; i += seg) {        // C^T: z = L_g^-1 y_g
+  // Every product is split over `team` adjacent lanes per output.
+  const int part = lt % team, per_t = seg / team;
+  for (int ob = 0; ob < n; ob += per_t) {    // C^T: z = L_g^-1 y_g
+    const int i = ob + lt / team;
     C acc = 0;
-    for (int j = 0; j <= i; ++j) acc += Lg(i, j) * yg[j];
-    zg[i] = acc;
+    if (i < n)
+      for (int j = part; j <= i; j += team) acc += Lg(i, j) * yg[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < n) zg[i] = acc;
   }
   __syncthreads();
-  // K^T (no-op when nr == 0).  Column walks (T(., i), L(., i)) are split over `team` lanes.
-  const int part = lt % team, per_t = seg / team;
+  // K^T (no-op when nr == 0)
   for (int ob = 0; ob < nr; ob += per_t) {   // y_I~ - T^T y_I^
     const int i = ob + lt / team;
     C acc = 0;
@@ -415,10 +419,13 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
     if (part == 0 && i < nr) tv[i] = zg[perm[i]] - acc;
   }
   __syncthreads();
-  for (int i = lt; i < nr; i += seg) {       // t = L_s^-1 (...)
+  for (int ob = 0; ob < nr; ob += per_t) {   // t = L_s^-1 (...)
+    const int i = ob + lt / team;
     C acc = 0;
-    for (int j = 0; j <= i; ++j) acc += Lr(i, j) * tv[j];
-    uv[i] = acc;
+    if (i < nr)
+      for (int j = part; j <= i; j += team) acc += Lr(i, j) * tv[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < nr) uv[i] = acc;
   }
   __syncthreads();
   for (int ob = 0; ob < nr; ob += per_t) {   // L_s^-T t
@@ -431,10 +438,13 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
   }
   __syncthreads();
   if (nr > 0) {
-    for (int s = lt; s < k; s += seg) {      // y_I^ += T L_s^-T t
-      C acc = zg[perm[nr + s]];
-      for (int i = 0; i < nr; ++i) acc += T(s, i) * tv[i];
-      y[gi_idx[perm[nr + s]]] = (double)acc;
+    for (int ob = 0; ob < k; ob += per_t) {  // y_I^ += T L_s^-T t
+      const int s = ob + lt / team;
+      C acc = 0;
+      if (s < k)
+        for (int i = part; i < nr; i += team) acc += T(s, i) * tv[i];
+      acc = team_sum(acc, team);
+      if (part == 0 && s < k) y[gi_idx[perm[nr + s]]] = (double)(zg[perm[nr + s]] + acc);
     }
     for (int i = lt; i < nr; i += seg) y[gi_idx[perm[i]]] = (double)uv[i];
   } else {
@@ -500,10 +510,13 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
     if (part == 0 && i < nr) tv[i] = acc;
   }
   __syncthreads();
-  for (int i = lt; i < nr; i += seg) {       // x_I~ + L_s^-1 a
-    C acc = xg[perm[i]];
-    for (int j = 0; j <= i; ++j) acc += Lr(i, j) * tv[j];
-    uv[i] = acc;
+  for (int ob = 0; ob < nr; ob += per_t) {   // x_I~ + L_s^-1 a
+    const int i = ob + lt / team;
+    C acc = 0;
+    if (i < nr)
+      for (int j = part; j <= i; j += team) acc += Lr(i, j) * tv[j];
+    acc = team_sum(acc, team);
+    if (part == 0 && i < nr) uv[i] = xg[perm[i]] + acc;
   }
   __syncthreads();
   for (int ob = 0; ob < nr; ob += per_t) {   // u = L_s^-T (...)
@@ -516,10 +529,13 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
   }
   __syncthreads();
   if (nr > 0) {
-    for (int s = lt; s < k; s += seg) {      // x_I^ -= T u
-      C acc = xg[perm[nr + s]];
-      for (int i = 0; i < nr; ++i) acc -= T(s, i) * tv[i];
-      zg[perm[nr + s]] = acc;
+    for (int ob = 0; ob < k; ob += per_t) {  // x_I^ -= T u
+      const int s = ob + lt / team;
+      C acc = 0;
+      if (s < k)
+        for (int i = part; i < nr; i += team) acc += T(s, i) * tv[i];
+      acc = team_sum(acc, team);
+      if (part == 0 && s < k) zg[perm[nr + s]] = xg[perm[nr + s]] - acc;
     }
     for (int i = lt; i < nr; i += seg) zg[perm[i]] = tv[i];
   } else {
@@ -631,8 +647,8 @@ __global__ __launch_bounds__(kRootThreads) void k_root(int nr, const int32_t* __
 template <typename S, typename C, bool CST>
 __global__ __launch_bounds__(1024) void k_fuse_fwd(const int32_t* __restrict__ frec, int fstride,
                                                    int cstride, int gstride, int maxown, int seg,
-                                                   int per_group, int blk_g, int goff, int blk_c,
-                                                   int team_c, int prestage,
+                                                   int team_g, int per_group, int blk_g, int goff,
+                                                   int blk_c, int team_c, int prestage,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ y,
                                                    const double* __restrict__ cb_in,
@@ -655,7 +671,7 @@ __global__ __launch_bounds__(1024) void k_fuse_fwd(const int32_t* __restrict__ f
     if (prestage)
       stage_flat(reinterpret_cast<C*>(work), vals + d.offV, tri_count(d.nI) + d.nB * d.nI,
                  threadIdx.x, blockDim.x);
-  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, 1, rb, vals, y, cb_in, work + goff);
+  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, team_g, rb, vals, y, cb_in, work + goff);
   __syncthreads();
   cell_fwd_body<S, C, CST, 0>(d, rec, vals, y, cb_out, blk_c, team_c, prestage != 0, work);
 }
@@ -665,7 +681,8 @@ __global__ __launch_bounds__(1024) void k_fuse_fwd(const int32_t* __restrict__ f
 // `per` at a time.
 template <typename S, typename C>
 __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict__ gd, int ngroup,
-                                                    int seg, int per, int per_group, int blk_g,
+                                                    int seg, int team, int per, int per_group,
+                                                    int blk_g,
                                                     int nr, const int32_t* __restrict__ ridx,
                                                     const S* __restrict__ Lv,
                                                     const int32_t* __restrict__ idx,
@@ -683,7 +700,7 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
       g = GroupDesc{};
       if (gsel < per && b + gsel < ngroup) g = gd[b + gsel];
     }
-    group_fwd_body<S, C, true>(g, seg, per_group, blk_g, 1, idx, vals, y, cb_in, smem_raw);
+    group_fwd_body<S, C, true>(g, seg, per_group, blk_g, team, idx, vals, y, cb_in, smem_raw);
     __syncthreads();
   }
   root_body<S, C>(nr, ridx, Lv, y, rstaged != 0, smem_raw);
@@ -691,7 +708,7 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
   for (int b = 0; b < ngroup; b += per) {
     g = GroupDesc{};
     if (gsel < per && b + gsel < ngroup) g = gd[b + gsel];
-    group_bwd_body<S, C, true>(g, seg, per_group, blk_g, 1, idx, vals, y, smem_raw);
+    group_bwd_body<S, C, true>(g, seg, per_group, blk_g, team, idx, vals, y, smem_raw);
     __syncthreads();
   }
 }
@@ -1089,6 +1106,7 @@ StagePlan group_plan(const LevelDev& L) {
 // (team re-derived for that block size); or, for the root, groups `per` at a time.
 struct FusePlan {
   bool ok = false;
+  int team_g = 1;  // lanes per output in the group stage (segments of g.seg x team_g lanes)
   size_t rec = 0;  // bytes of the record (cell + owned groups) at the front of LDS
   int threads = 256, per = 0, team_c = 1, goff = 0;
   bool cst = false, prestage = false;
@@ -1109,7 +1127,7 @@ FusePlan fuse_plan(const LevelDev& G, const LevelDev* Cl, int nroot) {
     f.threads = 256;
     while (f.threads < 1024 && f.threads / f.g.seg < G.maxown) f.threads *= 2;
     if (f.threads / f.g.seg < G.maxown) return f;
-    f.per = G.maxown;
+    f.per = G.maxown;  // one lane per output (measured: splitting helps only the root launch)
     const size_t gsm = (size_t)f.per * pg;
     const StagePlan cp = cell_plan<C>(*Cl);
     int team = 1;
@@ -1125,6 +1143,10 @@ FusePlan fuse_plan(const LevelDev& G, const LevelDev* Cl, int nroot) {
   } else {
     f.threads = 1024;
     f.per = (int)std::min<size_t>(f.threads / f.g.seg, std::max<size_t>(1, kStageMax / pg));
+    f.per = std::min(f.per, G.ngroup);
+    // spare lanes share each group's products: `team_g` lanes per output
+    while (f.team_g < 8 && (size_t)f.per * f.g.seg * f.team_g * 2 <= (size_t)f.threads)
+      f.team_g *= 2;
     bool rs;
     const size_t rsm = root_smem<C>(nroot, &rs);
     f.prestage = rs;  // the root block is staged in LDS
@@ -1258,14 +1280,15 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       auto k = fp.cst ? k_fuse_fwd<S, C, true> : k_fuse_fwd<S, C, false>;
       launch(k, dim3(P.ncell), dim3(fp.threads), fp.rec + fp.smem, s, t,
-             (const int32_t*)L.frec.p, L.fstride, P.cstride, L.gstride, L.maxown, fp.g.seg,
-             fp.g.per_group, fp.g.blk_elems, fp.goff, fp.blk_c, fp.team_c, (int)fp.prestage,
-             vals, y, (const double*)cbl(l), cbl(l + 1), done);
+             (const int32_t*)L.frec.p, L.fstride, P.cstride, L.gstride, L.maxown,
+             fp.g.seg * fp.team_g, fp.team_g, fp.g.per_group, fp.g.blk_elems, fp.goff, fp.blk_c,
+             fp.team_c, (int)fp.prestage, vals, y, (const double*)cbl(l), cbl(l + 1), done);
     } else if (l == nlev - 1 && f.root_fused) {  // + root + this level's backward groups
       const FusePlan fp = fuse_plan<C>(L, nullptr, f.nroot);
       const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
       launch(k_fuse_root<S, C>, dim3(1), dim3(fp.threads), fp.smem, s, t,
-             (const GroupDesc*)L.groups.p, L.ngroup, fp.g.seg, fp.per, fp.g.per_group,
+             (const GroupDesc*)L.groups.p, L.ngroup, fp.g.seg * fp.team_g, fp.team_g, fp.per,
+             fp.g.per_group,
              fp.g.blk_elems, f.nroot, idx + f.offRootIdx, vals + f.offRootV, idx, vals, y,
              (const double*)cbl(l), (int)fp.prestage, done);
     } else if (!group_plan<C>(L).staged) {
