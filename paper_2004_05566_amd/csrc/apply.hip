@@ -887,156 +887,175 @@ __global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __r
   }
 }
 
-// --------------------------------------------------------------------------- large groups --
-// One workgroup of 16 wavefronts per group, blocks read from global memory:
-//   row walks (out_r = sum_j A(r, j) x_j with A column-major): lanes take 64 consecutive rows
-//     (coalesced), wavefronts split the columns, partial sums meet in LDS;
-//   column walks (out_c = sum_j A(j, c) x_j): one wavefront per output reads the contiguous
-//     column.
-template <typename C, typename A, typename LO, typename HI, typename OUT>
-__device__ void rows_walk(int nrows, A a, LO lo, HI hi, const C* x, OUT out,
-                          C (*red)[kRowTile]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r0 = 0; r0 < nrows; r0 += kRowTile) {
-    const int r = r0 + lane;
-    C acc = 0;
-    if (r < nrows)
-      for (int j = lo(r) + wave; j < hi(r); j += kTileWaves) acc += a(r, j) * x[j];
-    red[wave][lane] = acc;
-    __syncthreads();
-    if (wave == 0 && r < nrows) {
-      C tot = 0;
-#pragma unroll
-      for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
-      out(r, tot);
+// ------------------------------------------------------------------------- tiled groups --
+// Large groups with few per level (upper levels of 3D problems) leave most of the chip idle
+// with one workgroup each.  Their stage runs instead as five launches, one per product of the
+// group step, each spread over row tiles (64 rows) or column tiles (32 columns) of all groups,
+// with the group's intermediate vectors in the scratch vector at the tile's offset:
+// z (n) | t (nr) | u (nr) | v (nr).  In the group order, with s = skeleton and r = redundant
+// positions (Sec. 2.2, skeletonization and the apply of eqAinv):
+//   forward:  z = L_g^-1 y_g;  t = z_r - T^T z_s;  u = L_s^-1 t -> y_r;  v = L_s^-T u;
+//             y_s = z_s + T v
+//   backward: t = T^T x_s;  u = x_r + L_s^-1 t;  v = L_s^-T u -> z_r;  z_s = x_s - T v;
+//             x_g = L_g^-T z
+// y is written only by launches after the last one that reads it for the same group.  A group
+// with nr = 0 has no tiles in the middle launches; its last forward launch copies z to y and its
+// fourth backward launch copies x to z.
+enum { GR_F_LG = 0, GR_F_LS, GR_F_T, GR_B_LS, GR_B_T };  // row launches
+enum { GC_F_T = 0, GC_F_LS, GC_B_T, GC_B_LS, GC_B_LG };  // column launches
+// tile lists, by the dimension they cover
+enum { GT_ROWS_N = 0, GT_ROWS_NR, GT_ROWS_K, GT_COLS_NR, GT_COLS_N, GT_KINDS };
+
+template <typename S>
+struct GroupBlocks {
+  const S *Lg, *T, *Ls;
+  __device__ GroupBlocks(const GroupDesc& d, const S* vals) {
+    Lg = vals + d.offV;
+    T = Lg + tri_count(d.n);
+    Ls = T + (int64_t)(d.n - d.nr) * d.nr;
+  }
+};
+
+template <typename S, typename C, int STEP>
+__global__ __launch_bounds__(kTileThreads) void k_gt_rows(const GroupDesc* __restrict__ gd,
+                                                          const int4* __restrict__ tiles,
+                                                          const int32_t* __restrict__ idx,
+                                                          const S* __restrict__ vals,
+                                                          double* __restrict__ y,
+                                                          const double* __restrict__ cb,
+                                                          double* __restrict__ wsc,
+                                                          const int* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* xs = reinterpret_cast<C*>(smem_raw);
+  __shared__ C red[kTileWaves][kRowTile];
+  const int4 t = tiles[blockIdx.x];
+  if (done && *done) return;
+  const GroupDesc d = gd[t.x];
+  const int n = d.n, nr = d.nr, k = n - nr;
+  double* z = wsc + t.z;
+  double* tv = z + n;
+  double* u = tv + nr;
+  double* v = u + nr;
+  const int32_t* gi = idx + d.offIdx;
+  const int32_t* perm = idx + d.offPerm;
+  const GroupBlocks<S> b(d, vals);
+  constexpr bool tri = STEP != GR_F_T && STEP != GR_B_T;
+  const int nrows = STEP == GR_F_LG ? n : (tri ? nr : k);
+  const int r0 = t.y;
+  const int rmax = min(nrows, r0 + kRowTile);
+  const int nin = tri ? rmax : nr;  // inputs these rows need
+  if constexpr (STEP == GR_F_LG) {  // y_g less the contributions of the level's cells
+    const int32_t* gp = idx + d.offGP;
+    const int32_t* slots = gp + n + 1;
+    for (int j = threadIdx.x; j < nin; j += blockDim.x) {
+      double acc = y[gi[j]];
+      for (int q = gp[j]; q < gp[j + 1]; ++q) acc -= cb[slots[q]];
+      xs[j] = (C)acc;
     }
-    __syncthreads();
-  }
-}
-
-template <typename C, typename A, typename LO, typename HI, typename OUT>
-__device__ void cols_walk(int ncols, A a, LO lo, HI hi, const C* x, OUT out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < ncols; c += kTileWaves) {
-    C acc = 0;
-    for (int j = lo(c) + lane; j < hi(c); j += 64) acc += a(j, c) * x[j];
-    acc = wave_reduce(acc);
-    if (lane == 0) out(c, acc);
-  }
-  __syncthreads();
-}
-
-// LDS: vg (n) | zg (n) | xs (k) | tv (nr) | uv (nr)
-template <typename S, typename C>
-__global__ __launch_bounds__(kTileThreads) void k_group_big_fwd(const GroupDesc* __restrict__ gd,
-                                                                const int32_t* __restrict__ idx,
-                                                                const S* __restrict__ vals,
-                                                                double* __restrict__ y,
-                                                                const double* __restrict__ cb,
-                                                                const int* __restrict__ done) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ C red[kTileWaves][kRowTile];
-  const GroupDesc d = gd[blockIdx.x];
-  if (done && *done) return;
-  const int n = d.n, nr = d.nr, k = n - nr;
-  C* yg = reinterpret_cast<C*>(smem_raw);
-  C* zg = yg + n;
-  C* xs = zg + n;
-  C* tv = xs + k;
-  C* uv = tv + nr;
-  const S* Lg = vals + d.offV;
-  const S* T = Lg + tri_count(n);
-  const S* Lr = T + (int64_t)k * nr;
-  const int32_t* gi = idx + d.offIdx;
-  const int32_t* gp = idx + d.offGP;
-  const int32_t* slots = gp + n + 1;
-  const int32_t* perm = idx + d.offPerm;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double acc = y[gi[i]];
-    for (int q = gp[i]; q < gp[i + 1]; ++q) acc -= cb[slots[q]];
-    yg[i] = (C)acc;
-  }
-  __syncthreads();
-  // C^T: z = L_g^-1 y_g
-  rows_walk<C>(n, [&](int r, int j) { return load_as<C>(Lg + colstart(j, n) + (r - j)); },
-               [](int) { return 0; }, [](int r) { return r + 1; }, yg,
-               [&](int r, C v) { zg[r] = v; }, red);
-  if (nr == 0) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[gi[i]] = (double)zg[i];
-    return;
-  }
-  for (int q = threadIdx.x; q < k; q += blockDim.x) xs[q] = zg[perm[nr + q]];
-  __syncthreads();
-  // y_I~ - T^T y_I^  (column i of T is contiguous over the skeleton index)
-  cols_walk<C>(nr, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
-               [](int) { return 0; }, [&](int) { return k; }, xs,
-               [&](int i, C v) { tv[i] = zg[perm[i]] - v; });
-  // t = L_s^-1 (...)
-  rows_walk<C>(nr, [&](int r, int j) { return load_as<C>(Lr + colstart(j, nr) + (r - j)); },
-               [](int) { return 0; }, [](int r) { return r + 1; }, tv,
-               [&](int r, C v) { uv[r] = v; }, red);
-  // L_s^-T t
-  cols_walk<C>(nr, [&](int j, int i) { return load_as<C>(Lr + colstart(i, nr) + (j - i)); },
-               [](int i) { return i; }, [&](int) { return nr; }, uv,
-               [&](int i, C v) { tv[i] = v; });
-  // y_I^ += T L_s^-T t  (row s of T: lanes over s are contiguous for each i)
-  rows_walk<C>(k, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
-               [](int) { return 0; }, [&](int) { return nr; }, tv,
-               [&](int q, C v) { y[gi[perm[nr + q]]] = (double)(xs[q] + v); }, red);
-  for (int i = threadIdx.x; i < nr; i += blockDim.x) y[gi[perm[i]]] = (double)uv[i];
-}
-
-template <typename S, typename C>
-__global__ __launch_bounds__(kTileThreads) void k_group_big_bwd(const GroupDesc* __restrict__ gd,
-                                                                const int32_t* __restrict__ idx,
-                                                                const S* __restrict__ vals,
-                                                                double* __restrict__ x,
-                                                                const int* __restrict__ done) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ C red[kTileWaves][kRowTile];
-  const GroupDesc d = gd[blockIdx.x];
-  if (done && *done) return;
-  const int n = d.n, nr = d.nr, k = n - nr;
-  C* xg = reinterpret_cast<C*>(smem_raw);
-  C* zg = xg + n;
-  C* xs = zg + n;
-  C* tv = xs + k;
-  C* uv = tv + nr;
-  const S* Lg = vals + d.offV;
-  const S* T = Lg + tri_count(n);
-  const S* Lr = T + (int64_t)k * nr;
-  const int32_t* gi = idx + d.offIdx;
-  const int32_t* perm = idx + d.offPerm;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) xg[i] = (C)x[gi[i]];
-  __syncthreads();
-  if (nr > 0) {
-    for (int q = threadIdx.x; q < k; q += blockDim.x) xs[q] = xg[perm[nr + q]];
-    __syncthreads();
-    // a = T^T x_I^
-    cols_walk<C>(nr, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
-                 [](int) { return 0; }, [&](int) { return k; }, xs,
-                 [&](int i, C v) { tv[i] = v; });
-    // x_I~ + L_s^-1 a
-    rows_walk<C>(nr, [&](int r, int j) { return load_as<C>(Lr + colstart(j, nr) + (r - j)); },
-                 [](int) { return 0; }, [](int r) { return r + 1; }, tv,
-                 [&](int r, C v) { uv[r] = xg[perm[r]] + v; }, red);
-    // u = L_s^-T (...)
-    cols_walk<C>(nr, [&](int j, int i) { return load_as<C>(Lr + colstart(i, nr) + (j - i)); },
-                 [](int i) { return i; }, [&](int) { return nr; }, uv,
-                 [&](int i, C v) { tv[i] = v; });
-    // x_I^ -= T u
-    rows_walk<C>(k, [&](int q, int i) { return load_as<C>(T + (int64_t)i * k + q); },
-                 [](int) { return 0; }, [&](int) { return nr; }, tv,
-                 [&](int q, C v) { zg[perm[nr + q]] = xs[q] - v; }, red);
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) zg[perm[i]] = tv[i];
   } else {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) zg[i] = xg[i];
+    const double* src = tri ? tv : v;
+    for (int j = threadIdx.x; j < nin; j += blockDim.x) xs[j] = (C)src[j];
   }
   __syncthreads();
-  // C: x_g = L_g^-T x_g
-  cols_walk<C>(n, [&](int j, int i) { return load_as<C>(Lg + colstart(i, n) + (j - i)); },
-               [](int i) { return i; }, [&](int) { return n; }, zg,
-               [&](int i, C v) { x[gi[i]] = (double)v; });
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = r0 + lane;
+  C acc = 0;
+  if (r < nrows) {
+    if constexpr (tri) {
+      const S* A = STEP == GR_F_LG ? b.Lg : b.Ls;
+      const int m = STEP == GR_F_LG ? n : nr;
+      for (int j = wave; j <= r; j += kTileWaves)
+        acc += load_as<C>(A + colstart(j, m) + (r - j)) * xs[j];
+    } else {
+      for (int i = wave; i < nr; i += kTileWaves)
+        acc += load_as<C>(b.T + (int64_t)i * k + r) * xs[i];
+    }
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && r < nrows) {
+    C tot = 0;
+#pragma unroll
+    for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
+    if constexpr (STEP == GR_F_LG) {
+      z[r] = (double)tot;
+    } else if constexpr (STEP == GR_F_LS) {
+      u[r] = (double)tot;
+      y[gi[perm[r]]] = (double)tot;
+    } else if constexpr (STEP == GR_F_T) {
+      const int p = nr ? perm[nr + r] : r;
+      y[gi[p]] = (double)((C)z[p] + tot);
+    } else if constexpr (STEP == GR_B_LS) {
+      u[r] = (double)((C)y[gi[perm[r]]] + tot);
+    } else {
+      const int p = nr ? perm[nr + r] : r;
+      z[p] = (double)((C)y[gi[p]] - tot);
+    }
+  }
+}
+
+template <typename S, typename C, int STEP>
+__global__ __launch_bounds__(kTileThreads) void k_gt_cols(const GroupDesc* __restrict__ gd,
+                                                          const int4* __restrict__ tiles,
+                                                          const int32_t* __restrict__ idx,
+                                                          const S* __restrict__ vals,
+                                                          double* __restrict__ y,
+                                                          double* __restrict__ wsc,
+                                                          const int* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* xs = reinterpret_cast<C*>(smem_raw);
+  const int4 t = tiles[blockIdx.x];
+  if (done && *done) return;
+  const GroupDesc d = gd[t.x];
+  const int n = d.n, nr = d.nr, k = n - nr;
+  double* z = wsc + t.z;
+  double* tv = z + n;
+  double* u = tv + nr;
+  double* v = u + nr;
+  const int32_t* gi = idx + d.offIdx;
+  const int32_t* perm = idx + d.offPerm;
+  const GroupBlocks<S> b(d, vals);
+  constexpr bool isT = STEP == GC_F_T || STEP == GC_B_T;
+  const int m = STEP == GC_B_LG ? n : nr;  // columns (and rows of the triangle)
+  const int c0 = t.y;
+  if constexpr (isT) {  // x_s (all of it): z_s forward, x_s backward
+    for (int q = threadIdx.x; q < k; q += blockDim.x) {
+      const int p = perm[nr + q];
+      xs[q] = STEP == GC_F_T ? (C)z[p] : (C)y[gi[p]];
+    }
+  } else {  // the rows j >= c0 of the triangle's columns
+    const double* src = STEP == GC_B_LG ? z : u;
+    for (int j = c0 + (int)threadIdx.x; j < m; j += blockDim.x) xs[j - c0] = (C)src[j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < kColTile; q += kTileWaves) {
+    const int i = c0 + q;
+    if (i >= m) break;
+    C acc = 0;
+    if constexpr (isT) {
+      const S* col = b.T + (int64_t)i * k;
+      for (int j = lane; j < k; j += 64) acc += load_as<C>(col + j) * xs[j];
+    } else {
+      const S* col = (STEP == GC_B_LG ? b.Lg : b.Ls) + colstart(i, m);
+      for (int j = i + lane; j < m; j += 64) acc += load_as<C>(col + (j - i)) * xs[j - c0];
+    }
+    acc = wave_reduce(acc);
+    if (lane == 0) {
+      if constexpr (STEP == GC_F_T) {
+        tv[i] = (double)((C)z[perm[i]] - acc);
+      } else if constexpr (STEP == GC_F_LS) {
+        v[i] = (double)acc;
+      } else if constexpr (STEP == GC_B_T) {
+        tv[i] = (double)acc;
+      } else if constexpr (STEP == GC_B_LS) {
+        v[i] = (double)acc;
+        z[perm[i]] = (double)acc;
+      } else {
+        y[gi[i]] = (double)acc;
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------------------------- launch plans --
@@ -1194,10 +1213,25 @@ struct StageTimer {
   }
 };
 
+// A stage of several launches: its start event goes with the first, its stop event with the
+// last.
+struct TimedSeq {
+  const StageTimer& t;
+  int n, i = 0;
+  TimedSeq(const StageTimer& st, int count) : t(st), n(count) {}
+  StageTimer next() {
+    StageTimer x;
+    if (i == 0) x.e0 = t.e0;
+    if (i == n - 1) x.e1 = t.e1;
+    ++i;
+    return x;
+  }
+};
+
 template <typename K, typename... Args>
 void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const StageTimer& t,
             Args... args) {
-  if (t.e0)
+  if (t.e0 || t.e1)
     hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)smem, s, t.e0, t.e1, 0, args...);
   else
     hipLaunchKernelGGL(kernel, grid, block, smem, s, args...);
@@ -1218,43 +1252,77 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
   }
 }
 
-template <typename C>
-size_t big_group_smem(const LevelDev& L) {
-  return sizeof(C) * (2 * (size_t)L.maxG + (size_t)L.maxK + 2 * (size_t)L.maxR + 4);
-}
+// launches of one tiled cell sweep
+int tiled_launches(const LevelDev& L) { return L.cmode ? 2 : 1; }
 
 template <typename S, typename C>
 void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
-                  double* cb, const int* done, hipStream_t s, const StageTimer& t) {
+                  double* cb, const int* done, hipStream_t s, TimedSeq& t) {
   const int32_t* idx = f.idx.p;
   const size_t rows_smem = sizeof(C) * (size_t)std::max(1, L.maxI);
   const size_t cols_smem = sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB);
   if (fwd) {
     if (L.cmode) {
-      launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
+      launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, cb, done);
-      launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, StageTimer(),
+      launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, cb, done);
     } else {
-      launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
+      launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, cb, done);
     }
   } else {
     if (L.cmode) {
-      launch(k_tbwd_rows1<S, C>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t,
+      launch(k_tbwd_rows1<S, C>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, done);
-      launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, StageTimer(),
+      launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, cb, done);
     } else {
-      launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t,
+      launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, cb, done);
     }
+  }
+}
+
+template <typename S, typename C>
+void launch_group_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
+                        double* y, const double* cb, const int* done, hipStream_t s,
+                        const StageTimer& t) {
+  const int32_t* idx = f.idx.p;
+  const GroupDesc* gd = (const GroupDesc*)L.groups.p;
+  const size_t sm = sizeof(C) * (size_t)std::max(1, L.maxG);
+  double* w = f.wsc.p;
+  // the lists each launch runs over, in launch order (an empty list skips its launch)
+  static const int fk[5] = {GT_ROWS_N, GT_COLS_NR, GT_ROWS_NR, GT_COLS_NR, GT_ROWS_K};
+  static const int bk[5] = {GT_COLS_NR, GT_ROWS_NR, GT_COLS_NR, GT_ROWS_K, GT_COLS_N};
+  const int* kinds = fwd ? fk : bk;
+  int count = 0;
+  for (int i = 0; i < 5; ++i) count += L.gtn[kinds[i]] > 0;
+  TimedSeq ts(t, count);
+  auto go = [&](int i, auto kernel, auto... args) {
+    const int kind = kinds[i];
+    if (!L.gtn[kind]) return;
+    launch(kernel, dim3(L.gtn[kind]), dim3(kTileThreads), sm, s, ts.next(), gd,
+           (const int4*)L.gtiles.p + L.gto[kind], idx, vals, y, args..., w, done);
+  };
+  if (fwd) {
+    go(0, k_gt_rows<S, C, GR_F_LG>, cb);
+    go(1, k_gt_cols<S, C, GC_F_T>);
+    go(2, k_gt_rows<S, C, GR_F_LS>, cb);
+    go(3, k_gt_cols<S, C, GC_F_LS>);
+    go(4, k_gt_rows<S, C, GR_F_T>, cb);
+  } else {
+    go(0, k_gt_cols<S, C, GC_B_T>);
+    go(1, k_gt_rows<S, C, GR_B_LS>, cb);
+    go(2, k_gt_cols<S, C, GC_B_LS>);
+    go(3, k_gt_rows<S, C, GR_B_T>, cb);
+    go(4, k_gt_cols<S, C, GC_B_LG>);
   }
 }
 
@@ -1269,7 +1337,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     const LevelDev& L = f.lv[l];
     if (L.ncell && !(l > 0 && f.lv[l - 1].fuse)) {
       const StageTimer t(prof, l, STAGE_CELL_FWD, done, s);
-      if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
+      TimedSeq ts(t, tiled_launches(L));
+      if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, ts);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t);
     }
@@ -1291,10 +1360,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
              fp.g.per_group,
              fp.g.blk_elems, f.nroot, idx + f.offRootIdx, vals + f.offRootV, idx, vals, y,
              (const double*)cbl(l), (int)fp.prestage, done);
-    } else if (!group_plan<C>(L).staged) {
+    } else if (L.gtiled) {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
-      launch(k_group_big_fwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L), s,
-             t, (const GroupDesc*)L.groups.p, idx, vals, y, (const double*)cbl(l), done);
+      launch_group_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
     } else {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       const StagePlan p = group_plan<C>(L);
@@ -1306,8 +1374,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
   if (f.nroot && !f.root_fused) {
     const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
     if (f.root_tiled) {  // y_r = L^-T (L^-1 y_r) as a row pass then a column pass
-      launch_tiled<S, C>(f, f.rootlv, true, vals, y, cbl(nlev), done, s, t);
-      launch_tiled<S, C>(f, f.rootlv, false, vals, y, cbl(nlev), done, s, StageTimer());
+      TimedSeq ts(t, 2 * tiled_launches(f.rootlv));
+      launch_tiled<S, C>(f, f.rootlv, true, vals, y, cbl(nlev), done, s, ts);
+      launch_tiled<S, C>(f, f.rootlv, false, vals, y, cbl(nlev), done, s, ts);
     } else {
       bool rs;
       const size_t rsm = root_smem<C>(f.nroot, &rs);
@@ -1319,9 +1388,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     const LevelDev& L = f.lv[l];
     if (L.ngroup && !(l == nlev - 1 && f.root_fused)) {
       const StageTimer t(prof, l, STAGE_GROUP_BWD, done, s);
-      if (!group_plan<C>(L).staged) {
-        launch(k_group_big_bwd<S, C>, dim3(L.ngroup), dim3(kTileThreads), big_group_smem<C>(L),
-               s, t, (const GroupDesc*)L.groups.p, idx, vals, y, done);
+      if (L.gtiled) {
+        launch_group_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
       } else {
         const StagePlan p = group_plan<C>(L);
         launch(k_group_bwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t,
@@ -1331,7 +1399,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     }
     if (L.ncell) {
       const StageTimer t(prof, l, STAGE_CELL_BWD, done, s);
-      if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
+      TimedSeq ts(t, tiled_launches(L));
+      if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, ts);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, false, vals, y, cbl(l), done, s, t);
     }
@@ -1354,8 +1423,7 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst) {
       g = group_plan<float>(L).rec + group_plan<float>(L).smem;
     }
     if (L.tiled) c = cs * (size_t)(L.maxI + L.maxB);
-    if (!(f.store == HIF_STORE_F64 ? group_plan<double>(L).staged : group_plan<float>(L).staged))
-      g = cs * (2 * (size_t)L.maxG + (size_t)L.maxK + 2 * (size_t)L.maxR + 4);
+    if (L.gtiled) g = cs * (size_t)std::max(1, L.maxG);
     w = std::max(w, std::max(c, g));
   }
   bool rs;
@@ -1412,8 +1480,16 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM((k_tcols<S, C, 0>));                                                               \
   HIF_SMEM((k_tcols<S, C, 1>));                                                               \
   HIF_SMEM((k_tcols<S, C, 2>));                                                               \
-  HIF_SMEM((k_group_big_fwd<S, C>));                                                          \
-  HIF_SMEM((k_group_big_bwd<S, C>));                                                          \
+  HIF_SMEM((k_gt_rows<S, C, GR_F_LG>));                                                       \
+  HIF_SMEM((k_gt_rows<S, C, GR_F_LS>));                                                       \
+  HIF_SMEM((k_gt_rows<S, C, GR_F_T>));                                                        \
+  HIF_SMEM((k_gt_rows<S, C, GR_B_LS>));                                                       \
+  HIF_SMEM((k_gt_rows<S, C, GR_B_T>));                                                        \
+  HIF_SMEM((k_gt_cols<S, C, GC_F_T>));                                                        \
+  HIF_SMEM((k_gt_cols<S, C, GC_F_LS>));                                                       \
+  HIF_SMEM((k_gt_cols<S, C, GC_B_T>));                                                        \
+  HIF_SMEM((k_gt_cols<S, C, GC_B_LS>));                                                       \
+  HIF_SMEM((k_gt_cols<S, C, GC_B_LG>));                                                       \
   HIF_SMEM((k_root<S, C>));                                                                   \
   HIF_SMEM((k_fuse_fwd<S, C, true>));                                                         \
   HIF_SMEM((k_fuse_fwd<S, C, false>));                                                        \
@@ -1446,6 +1522,40 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
   L.ctiles.upload(ct, s);
   HIF_REQUIRE(woff < (int64_t)INT32_MAX, HIF_ERR_ARG, "tiled scratch too large");
   *base = woff;
+}
+
+// Tiles of a level's groups; the group vectors take scratch from `base` on (every group stage
+// finishes before the next starts, so all levels share the region).  Each list runs its heavier
+// tiles first (rows far down a triangle, columns near its left edge).  Returns the scratch used.
+int64_t tile_groups(LevelDev& L, const std::vector<GroupDesc>& gs, int64_t base, hipStream_t s) {
+  struct T { int64_t work; int4 t; };
+  std::vector<T> lists[GT_KINDS];
+  int64_t off = base;
+  for (size_t g = 0; g < gs.size(); ++g) {
+    const int n = gs[g].n, nr = gs[g].nr, k = n - nr;
+    auto add = [&](int kind, int m, int step, bool tri_rows, bool tri_cols, int len) {
+      for (int a0 = 0; a0 < m; a0 += step) {
+        const int64_t w = tri_rows ? std::min(m, a0 + step) : tri_cols ? m - a0 : len;
+        lists[kind].push_back({w, {(int)g, a0, (int)off, 0}});
+      }
+    };
+    add(GT_ROWS_N, n, kRowTile, true, false, 0);
+    add(GT_ROWS_NR, nr, kRowTile, true, false, 0);
+    add(GT_ROWS_K, k, kRowTile, false, false, nr);
+    add(GT_COLS_NR, nr, kColTile, false, false, k + nr);
+    add(GT_COLS_N, n, kColTile, false, true, 0);
+    off += n + 3 * (int64_t)nr;
+  }
+  std::vector<int4> all;
+  for (int i = 0; i < GT_KINDS; ++i) {
+    std::stable_sort(lists[i].begin(), lists[i].end(),
+                     [](const T& x, const T& y) { return x.work > y.work; });
+    L.gto[i] = (int)all.size();
+    L.gtn[i] = (int)lists[i].size();
+    for (const T& t : lists[i]) all.push_back(t.t);
+  }
+  L.gtiles.upload(all, s);
+  return off - base;
 }
 }  // namespace
 
@@ -1509,7 +1619,7 @@ void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
     LevelDev& L = f.lv[l];
     const LevelDev& P = f.lv[l + 1];
     L.fuse = false;
-    if (off || !L.ngroup || !P.ncell || P.tiled || P.cmode != 0) continue;
+    if (off || !L.ngroup || L.gtiled || !P.ncell || P.tiled || P.cmode != 0) continue;
     // owner of each level-l group: the level l+1 cell holding one of its DOFs in its interior
     const std::vector<CellDesc>& pc = cells[l + 1];
     for (size_t p = 0; p < pc.size(); ++p)
@@ -1558,18 +1668,30 @@ void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
     L.fuse = true;
   }
   f.root_fused = false;
-  if (!off && nlev > 0 && f.nroot && !f.root_tiled && f.lv[nlev - 1].ngroup)
+  if (!off && nlev > 0 && f.nroot && !f.root_tiled && f.lv[nlev - 1].ngroup &&
+      !f.lv[nlev - 1].gtiled)
     f.root_fused = f64 ? fuse_plan<double>(f.lv[nlev - 1], nullptr, f.nroot).ok
                        : fuse_plan<float>(f.lv[nlev - 1], nullptr, f.nroot).ok;
 }
 
-void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells, hipStream_t s) {
+void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                  const std::vector<std::vector<GroupDesc>>& groups, hipStream_t s) {
   const bool f64 = f.store == HIF_STORE_F64;
   int64_t wtot = 0;
   for (size_t l = 0; l < f.lv.size(); ++l) {
     LevelDev& L = f.lv[l];
     L.tiled = L.ncell > 0 && !(f64 ? cell_plan<double>(L).staged : cell_plan<float>(L).staged);
     if (L.tiled) tile_level(L, cells[l], &wtot, s);
+  }
+  // groups that do not fit one workgroup (HIFCN_GROUP_TILES=1: every level's groups, for tests)
+  const char* ge = std::getenv("HIFCN_GROUP_TILES");
+  const bool all_groups = ge && std::atoi(ge) != 0;
+  int64_t gneed = 0;
+  for (size_t l = 0; l < f.lv.size(); ++l) {
+    LevelDev& L = f.lv[l];
+    L.gtiled = L.ngroup > 0 && (all_groups || !(f64 ? group_plan<double>(L).staged
+                                                     : group_plan<float>(L).staged));
+    if (L.gtiled) gneed = std::max(gneed, tile_groups(L, groups[l], wtot, s));
   }
   // a root of more than 256 KiB of factor is spread over many workgroups
   const size_t eb = store_elem_bytes(f.store);
@@ -1590,7 +1712,8 @@ void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
     R.cells.upload(std::vector<CellDesc>{d}, s);
     tile_level(R, {d}, &wtot, s);
   }
-  f.wsc.alloc(std::max<int64_t>(1, wtot));
+  HIF_REQUIRE(wtot + gneed < (int64_t)INT32_MAX, HIF_ERR_ARG, "tiled scratch too large");
+  f.wsc.alloc(std::max<int64_t>(1, wtot + gneed));
 }
 
 }  // namespace hifcn

@@ -24,6 +24,12 @@ struct LevelDev {
   bool tiled = false;
   int nrt = 0, nct = 0;
   DevBuf<int4> rtiles, ctiles;
+  // Groups too large for one workgroup's LDS run one launch per product over tiles of all the
+  // level's groups (group, first row or column, scratch offset of the group's vectors, unused):
+  // five lists (rows over n, nr, k; columns over nr, n) at gto[i] in gtiles, gtn[i] tiles each.
+  bool gtiled = false;
+  int gto[5] = {0, 0, 0, 0, 0}, gtn[5] = {0, 0, 0, 0, 0};
+  DevBuf<int4> gtiles;
   // The group stage of this level runs in one launch with the cell stage of the next level:
   // owned = the descriptors of the groups each next-level cell runs, maxown per cell (padded
   // with empty descriptors).
@@ -80,7 +86,8 @@ struct FactorDev {
   size_t smem_max = 0;
   int64_t root_bytes = 0;
   std::unique_ptr<StageProfiler> prof;
-  DevBuf<double> wsc;   // interiors of tiled cells between the forward and backward sweep
+  DevBuf<double> wsc;   // interiors of tiled cells between the forward and backward sweep,
+                        // then the vectors of tiled groups within one stage
   LevelDev rootlv;      // the root as a one-cell level, used when it is tiled
   bool root_tiled = false;
   // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
@@ -150,7 +157,8 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
 size_t apply_smem_need(const FactorDev& f, size_t* worst);
 // Decide per level whether cells are tiled across workgroups and upload the tile lists;
 // `cells` are the host copies of every level's descriptors.
-void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells, hipStream_t s);
+void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                  const std::vector<std::vector<GroupDesc>>& groups, hipStream_t s);
 // Decide which group stages run together with the next level's cell stage (and the last level
 // with the root) and upload the ownership lists; call after setup_tiling.
 void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,

@@ -152,8 +152,8 @@ def test_tiled_3d_factor_cn_matches_oracle(store, gpu_lib):
 
 def test_3d_two_levels_large_groups_match_oracle(gpu_lib):
     """32^3 grid, two levels: the level-1 faces (up to ~230 DOFs) exceed the per-group LDS
-    budget and go through the one-group-per-workgroup global-memory kernels; the root is
-    tiled."""
+    budget and run as tiled group stages (one launch per product over tiles of all groups);
+    the root is tiled."""
     import torch
     n, dim, leaf, eps, dt = 32, 3, 8, 1e-4, 0.02
     a = gen.grf_coefficient(n, dim, 0.15, 51)
