@@ -725,8 +725,32 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
 //                 memory) for two outputs.
 constexpr int kRowTile = 64;
 constexpr int kColTile = 32;
-constexpr int kTileThreads = 1024;   // 16 wavefronts per tile
+#ifndef HIFCN_TILE_THREADS
+#define HIFCN_TILE_THREADS 1024
+#endif
+#ifndef HIFCN_DOT_UNROLL
+#define HIFCN_DOT_UNROLL 8
+#endif
+constexpr int kTileThreads = HIFCN_TILE_THREADS;
 constexpr int kTileWaves = kTileThreads / 64;
+constexpr int kDotUnroll = HIFCN_DOT_UNROLL;
+
+// sum of elem(j) x_j over j = j0, j0 + step, ... < j1, in that order, with up to U loads of
+// the matrix in flight (the loads of U terms are issued before their products are added)
+template <int U, typename C, typename F>
+__device__ __forceinline__ C strided_dot(int j0, int j1, int step, F elem, const C* x) {
+  C acc = 0;
+  int j = j0;
+  for (; j + (U - 1) * step < j1; j += U * step) {
+    C e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) e[u] = elem(j + u * step);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += e[u] * x[j + u * step];
+  }
+  for (; j < j1; j += step) acc += elem(j) * x[j];
+  return acc;
+}
 
 template <typename S, typename C, int MODE>
 __global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __restrict__ cd,
@@ -757,11 +781,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __re
   const int tl = tri_count(nI);
   C acc = 0;
   if (r < nI) {
-    for (int j = wave; j <= r; j += kTileWaves)
-      acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ys[j];
+    acc = strided_dot<kDotUnroll>(
+        wave, r + 1, kTileWaves, [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
+        ys);
   } else if (r < nrows) {
     const S* H = v + tl + (r - nI);
-    for (int j = wave; j < nI; j += kTileWaves) acc += load_as<C>(H + (int64_t)j * nB) * ys[j];
+    acc = strided_dot<kDotUnroll>(
+        wave, nI, kTileWaves, [&](int j) { return load_as<C>(H + (int64_t)j * nB); }, ys);
   }
   red[wave][lane] = acc;
   __syncthreads();
@@ -814,11 +840,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restri
     const int i = c0 + q;
     if (i >= nI) break;
     const S* col = v + colstart(i, nI);
-    C acc = 0;
-    for (int j = i + lane; j < nI; j += 64) acc += load_as<C>(col + (j - i)) * xs[j];
+    C acc = strided_dot<kDotUnroll>(
+        i + lane, nI, 64, [&](int j) { return load_as<C>(col + (j - i)); }, xs);
     if constexpr (KIND == 0) {
       const S* hc = v + tl + (int64_t)i * d.nB;
-      for (int b = lane; b < nB; b += 64) acc -= load_as<C>(hc + b) * xb[b];
+      acc -= strided_dot<kDotUnroll>(lane, nB, 64, [&](int b) { return load_as<C>(hc + b); }, xb);
     }
     acc = wave_reduce(acc);
     if (lane == 0) {
@@ -875,8 +901,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __r
   const int r = r0 + lane;
   C acc = 0;
   if (r < nI)
-    for (int j = wave; j <= r; j += kTileWaves)
-      acc += load_as<C>(v + colstart(j, nI) + (r - j)) * ts[j];
+    acc = strided_dot<kDotUnroll>(
+        wave, r + 1, kTileWaves, [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
+        ts);
   red[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && r < nI) {
@@ -964,11 +991,12 @@ __global__ __launch_bounds__(kTileThreads) void k_gt_rows(const GroupDesc* __res
     if constexpr (tri) {
       const S* A = STEP == GR_F_LG ? b.Lg : b.Ls;
       const int m = STEP == GR_F_LG ? n : nr;
-      for (int j = wave; j <= r; j += kTileWaves)
-        acc += load_as<C>(A + colstart(j, m) + (r - j)) * xs[j];
+      acc = strided_dot<kDotUnroll>(
+          wave, r + 1, kTileWaves, [&](int j) { return load_as<C>(A + colstart(j, m) + (r - j)); },
+          xs);
     } else {
-      for (int i = wave; i < nr; i += kTileWaves)
-        acc += load_as<C>(b.T + (int64_t)i * k + r) * xs[i];
+      acc = strided_dot<kDotUnroll>(
+          wave, nr, kTileWaves, [&](int i) { return load_as<C>(b.T + (int64_t)i * k + r); }, xs);
     }
   }
   red[wave][lane] = acc;
@@ -1032,13 +1060,14 @@ __global__ __launch_bounds__(kTileThreads) void k_gt_cols(const GroupDesc* __res
   for (int q = wave; q < kColTile; q += kTileWaves) {
     const int i = c0 + q;
     if (i >= m) break;
-    C acc = 0;
+    C acc;
     if constexpr (isT) {
       const S* col = b.T + (int64_t)i * k;
-      for (int j = lane; j < k; j += 64) acc += load_as<C>(col + j) * xs[j];
+      acc = strided_dot<kDotUnroll>(lane, k, 64, [&](int j) { return load_as<C>(col + j); }, xs);
     } else {
       const S* col = (STEP == GC_B_LG ? b.Lg : b.Ls) + colstart(i, m);
-      for (int j = i + lane; j < m; j += 64) acc += load_as<C>(col + (j - i)) * xs[j - c0];
+      acc = strided_dot<kDotUnroll>(
+          i - c0 + lane, m - c0, 64, [&](int j) { return load_as<C>(col + (j - (i - c0))); }, xs);
     }
     acc = wave_reduce(acc);
     if (lane == 0) {
