@@ -202,12 +202,12 @@ int64_t handle_device_bytes(const Handle& h) {
   add(h.links); add(h.x); add(h.r); add(h.z); add(h.p0); add(h.p1); add(h.q); add(h.partials);
   add(h.st); add(h.step_iters); add(h.step_relres);
   const FactorDev& f = h.f;
-  add(f.idx); add(f.vals); add(f.cb); add(f.wsc);
-  auto add_level = [&](const LevelDev& l) {
+  add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);
+  add(f.rddoff); add(f.rdtiles); add(f.rscat);
+  for (const LevelDev& l : f.lv) {
     add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.crec); add(l.grec); add(l.frec);
-  };
-  for (const LevelDev& l : f.lv) add_level(l);
-  add_level(f.rootlv);
+    add(l.cdtiles); add(l.grtiles); add(l.gctiles); add(l.gscat); add(l.cddoff); add(l.gddoff);
+  }
   return b;
 }
 

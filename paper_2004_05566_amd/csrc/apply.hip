@@ -731,9 +731,24 @@ constexpr int kColTile = 32;
 #ifndef HIFCN_DOT_UNROLL
 #define HIFCN_DOT_UNROLL 8
 #endif
+#ifndef HIFCN_XCD_REMAP
+#define HIFCN_XCD_REMAP 1
+#endif
 constexpr int kTileThreads = HIFCN_TILE_THREADS;
 constexpr int kTileWaves = kTileThreads / 64;
 constexpr int kDotUnroll = HIFCN_DOT_UNROLL;
+
+// Workgroup b of a launch runs on XCD b % 8, and each XCD has its own L2.  Tile b' = xcd_tile(b)
+// gives every XCD one contiguous run of the tile list, so neighbouring tiles of one block, which
+// share the cache lines at their edges, are fetched into the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int g) {
+#if HIFCN_XCD_REMAP
+  const int q = g >> 3, rem = g & 7, x = b & 7;
+  return x * q + min(x, rem) + (b >> 3);
+#else
+  return b;
+#endif
+}
 
 // sum of elem(j) x_j over j = j0, j0 + step, ... < j1, in that order, with up to U loads of
 // the matrix in flight (the loads of U terms are issued before their products are added)
@@ -752,8 +767,8 @@ __device__ __forceinline__ C strided_dot(int j0, int j1, int step, F elem, const
   return acc;
 }
 
-template <typename S, typename C, int MODE>
-__global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __restrict__ cd,
+template <typename S, typename C, int MODE, int TT>
+__global__ __launch_bounds__(TT) void k_tfwd_rows(const CellDesc* __restrict__ cd,
                                                    const int4* __restrict__ tiles,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
@@ -763,8 +778,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __re
                                                    const int* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* ys = reinterpret_cast<C*>(smem_raw);
-  __shared__ C red[kTileWaves][kRowTile];
-  const int4 t = tiles[blockIdx.x];
+  __shared__ C red[(TT / 64)][kRowTile];
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
@@ -782,19 +797,19 @@ __global__ __launch_bounds__(kTileThreads) void k_tfwd_rows(const CellDesc* __re
   C acc = 0;
   if (r < nI) {
     acc = strided_dot<kDotUnroll>(
-        wave, r + 1, kTileWaves, [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
+        wave, r + 1, (TT / 64), [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
         ys);
   } else if (r < nrows) {
     const S* H = v + tl + (r - nI);
     acc = strided_dot<kDotUnroll>(
-        wave, nI, kTileWaves, [&](int j) { return load_as<C>(H + (int64_t)j * nB); }, ys);
+        wave, nI, (TT / 64), [&](int j) { return load_as<C>(H + (int64_t)j * nB); }, ys);
   }
   red[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && r < nrows) {
     C tot = 0;
 #pragma unroll
-    for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
+    for (int w = 0; w < (TT / 64); ++w) tot += red[w][lane];
     if (r < nI) wsc[t.z + r] = (double)tot;
     else cb[d.offCB + r - nI] = (double)tot;
   }
@@ -812,8 +827,8 @@ __device__ __forceinline__ float wave_reduce(float v) {
 // Column tiles.  KIND 0 (backward, dense H): x_i = L^-T w - H^T x_B -> y.
 //                KIND 1 (backward, links):   x_i = L^-T u -> y.
 //                KIND 2 (forward, links):    v_i = L^-T w;  c_b = A_BI(b, ib_b) v_ib_b -> cb.
-template <typename S, typename C, int KIND>
-__global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restrict__ cd,
+template <typename S, typename C, int KIND, int TT>
+__global__ __launch_bounds__(TT) void k_tcols(const CellDesc* __restrict__ cd,
                                                const int4* __restrict__ tiles,
                                                const int32_t* __restrict__ idx,
                                                const S* __restrict__ vals,
@@ -824,7 +839,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restri
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* xs = reinterpret_cast<C*>(smem_raw);
   __shared__ C vt[kColTile];
-  const int4 t = tiles[blockIdx.x];
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = KIND == 0 ? d.nB : 0;
@@ -836,7 +851,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restri
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const S* v = vals + d.offV;
   const int tl = tri_count(nI);
-  for (int q = wave; q < kColTile; q += kTileWaves) {
+  for (int q = wave; q < kColTile; q += (TT / 64)) {
     const int i = c0 + q;
     if (i >= nI) break;
     const S* col = v + colstart(i, nI);
@@ -865,8 +880,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tcols(const CellDesc* __restri
 
 // Backward, links: t = A_IB x_B (per interior DOF, its links in a fixed order), then
 // u_r = w_r - (L^-1 t)_r over a row tile, in place in the scratch vector.
-template <typename S, typename C>
-__global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __restrict__ cd,
+template <typename S, typename C, int TT>
+__global__ __launch_bounds__(TT) void k_tbwd_rows1(const CellDesc* __restrict__ cd,
                                                     const int4* __restrict__ tiles,
                                                     const int32_t* __restrict__ idx,
                                                     const S* __restrict__ vals,
@@ -875,8 +890,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __r
                                                     const int* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* ts = reinterpret_cast<C*>(smem_raw);
-  __shared__ C red[kTileWaves][kRowTile];
-  const int4 t = tiles[blockIdx.x];
+  __shared__ C red[(TT / 64)][kRowTile];
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
@@ -902,188 +917,186 @@ __global__ __launch_bounds__(kTileThreads) void k_tbwd_rows1(const CellDesc* __r
   C acc = 0;
   if (r < nI)
     acc = strided_dot<kDotUnroll>(
-        wave, r + 1, kTileWaves, [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
+        wave, r + 1, (TT / 64), [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
         ts);
   red[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && r < nI) {
     C tot = 0;
 #pragma unroll
-    for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
+    for (int w = 0; w < (TT / 64); ++w) tot += red[w][lane];
     wsc[t.z + r] -= (double)tot;
   }
 }
 
-// ------------------------------------------------------------------------- tiled groups --
-// Large groups with few per level (upper levels of 3D problems) leave most of the chip idle
-// with one workgroup each.  Their stage runs instead as five launches, one per product of the
-// group step, each spread over row tiles (64 rows) or column tiles (32 columns) of all groups,
-// with the group's intermediate vectors in the scratch vector at the tile's offset:
-// z (n) | t (nr) | u (nr) | v (nr).  In the group order, with s = skeleton and r = redundant
-// positions (Sec. 2.2, skeletonization and the apply of eqAinv):
-//   forward:  z = L_g^-1 y_g;  t = z_r - T^T z_s;  u = L_s^-1 t -> y_r;  v = L_s^-T u;
-//             y_s = z_s + T v
-//   backward: t = T^T x_s;  u = x_r + L_s^-1 t;  v = L_s^-T u -> z_r;  z_s = x_s - T v;
-//             x_g = L_g^-T z
-// y is written only by launches after the last one that reads it for the same group.  A group
-// with nr = 0 has no tiles in the middle launches; its last forward launch copies z to y and its
-// fourth backward launch copies x to z.
-enum { GR_F_LG = 0, GR_F_LS, GR_F_T, GR_B_LS, GR_B_T };  // row launches
-enum { GC_F_T = 0, GC_F_LS, GC_B_T, GC_B_LS, GC_B_LG };  // column launches
-// tile lists, by the dimension they cover
-enum { GT_ROWS_N = 0, GT_ROWS_NR, GT_ROWS_K, GT_COLS_NR, GT_COLS_N, GT_KINDS };
+// --------------------------------------------------------------------------- dense forms --
+// Blocks in dense form (column-major, leading dimension ld = n rounded up to 32 elements) are
+// applied in one pass over many workgroups:
+//   row tiles:    64 rows; the wavefronts split the columns of the tile's column range
+//                 [c0, c0 + span) and add up through LDS.  Every 64-row segment of a column is
+//                 whole, aligned cache lines.
+//   column tiles: consecutive columns, each reduced by one wavefront over its whole length.
+// Tile: (block, first row or column, first column of the range, scratch offset).
+//   DR_CELL_FWD   cell interior in link mode: v = A_II^-1 y_I; the couplings of the tile's rows
+//                 go to cb, y_I is kept in the scratch vector for the backward sweep (the
+//                 level's interiors are not touched in between)
+//   DR_CELL_BWD   x_I = A_II^-1 (y_I - A_IB x_B) -> y
+//   DR_GROUP_FWD  the group step G (y_g less the cell contributions) -> scratch
+//   DR_ROOT       partial sums of A_r^-1 y_r over one column range -> scratch
+//   column tiles: the backward group step G^T x_g -> scratch
+// Dense group and root results go back to y by a scatter list once every tile has read its
+// inputs.
+enum { DR_CELL_FWD = 0, DR_CELL_BWD, DR_GROUP_FWD, DR_ROOT };
+constexpr int kDenseColsPerTile = 32;
 
-template <typename S>
-struct GroupBlocks {
-  const S *Lg, *T, *Ls;
-  __device__ GroupBlocks(const GroupDesc& d, const S* vals) {
-    Lg = vals + d.offV;
-    T = Lg + tri_count(d.n);
-    Ls = T + (int64_t)(d.n - d.nr) * d.nr;
-  }
-};
+__host__ __device__ inline int dense_ld(int n) { return (n + 31) & ~31; }
 
-template <typename S, typename C, int STEP>
-__global__ __launch_bounds__(kTileThreads) void k_gt_rows(const GroupDesc* __restrict__ gd,
-                                                          const int4* __restrict__ tiles,
-                                                          const int32_t* __restrict__ idx,
-                                                          const S* __restrict__ vals,
-                                                          double* __restrict__ y,
-                                                          const double* __restrict__ cb,
-                                                          double* __restrict__ wsc,
-                                                          const int* __restrict__ done) {
+template <typename S, typename C, int KIND, int TT>
+__global__ __launch_bounds__(TT) void k_dense_rows(const CellDesc* __restrict__ cd,
+                                                   const GroupDesc* __restrict__ gd,
+                                                   const int64_t* __restrict__ ddoff,
+                                                   const int4* __restrict__ tiles, int span,
+                                                   int nroot, const int32_t* __restrict__ ridx,
+                                                   const int32_t* __restrict__ idx,
+                                                   const S* __restrict__ vals,
+                                                   const S* __restrict__ dv,
+                                                   double* __restrict__ y,
+                                                   double* __restrict__ cb,
+                                                   double* __restrict__ wsc,
+                                                   const int* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* xs = reinterpret_cast<C*>(smem_raw);
-  __shared__ C red[kTileWaves][kRowTile];
-  const int4 t = tiles[blockIdx.x];
+  __shared__ C red[TT / 64][kRowTile];
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   if (done && *done) return;
-  const GroupDesc d = gd[t.x];
-  const int n = d.n, nr = d.nr, k = n - nr;
-  double* z = wsc + t.z;
-  double* tv = z + n;
-  double* u = tv + nr;
-  double* v = u + nr;
-  const int32_t* gi = idx + d.offIdx;
-  const int32_t* perm = idx + d.offPerm;
-  const GroupBlocks<S> b(d, vals);
-  constexpr bool tri = STEP != GR_F_T && STEP != GR_B_T;
-  const int nrows = STEP == GR_F_LG ? n : (tri ? nr : k);
-  const int r0 = t.y;
-  const int rmax = min(nrows, r0 + kRowTile);
-  const int nin = tri ? rmax : nr;  // inputs these rows need
-  if constexpr (STEP == GR_F_LG) {  // y_g less the contributions of the level's cells
-    const int32_t* gp = idx + d.offGP;
+  int n;
+  CellDesc c{};
+  GroupDesc g{};
+  if constexpr (KIND == DR_CELL_FWD || KIND == DR_CELL_BWD) {
+    c = cd[t.x];
+    n = c.nI;
+  } else if constexpr (KIND == DR_GROUP_FWD) {
+    g = gd[t.x];
+    n = g.n;
+  } else {
+    n = nroot;
+  }
+  const int r0 = t.y, c0 = t.z;
+  const int c1 = min(n, c0 + span);
+  const S* M = dv + ddoff[t.x];
+  const int ld = dense_ld(n);
+  double* w = wsc + t.w;
+  // the inputs of the tile's column range
+  if constexpr (KIND == DR_CELL_FWD) {
+    const int32_t* gI = idx + c.offI;
+    for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) xs[j - c0] = (C)y[gI[j]];
+  } else if constexpr (KIND == DR_CELL_BWD) {
+    // idx layout after offC: ib[nB], rowptr[nI + 1], blist[nB] (links grouped by interior DOF)
+    const int32_t* rp = idx + c.offC + c.nB;
+    const int32_t* bl = rp + n + 1;
+    const int32_t* gB = idx + c.offB;
+    const S* cw = vals + c.offV + tri_count(n);
+    for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) {
+      C tj = 0;
+      for (int q = rp[j]; q < rp[j + 1]; ++q) {
+        const int b = bl[q];
+        tj += load_as<C>(cw + b) * (C)y[gB[b]];
+      }
+      xs[j - c0] = (C)w[j] - tj;
+    }
+  } else if constexpr (KIND == DR_GROUP_FWD) {
+    const int32_t* gi = idx + g.offIdx;
+    const int32_t* gp = idx + g.offGP;
     const int32_t* slots = gp + n + 1;
-    for (int j = threadIdx.x; j < nin; j += blockDim.x) {
-      double acc = y[gi[j]];
-      for (int q = gp[j]; q < gp[j + 1]; ++q) acc -= cb[slots[q]];
-      xs[j] = (C)acc;
+    for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) {
+      double a = y[gi[j]];
+      for (int q = gp[j]; q < gp[j + 1]; ++q) a -= cb[slots[q]];
+      xs[j - c0] = (C)a;
     }
   } else {
-    const double* src = tri ? tv : v;
-    for (int j = threadIdx.x; j < nin; j += blockDim.x) xs[j] = (C)src[j];
+    for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) xs[j - c0] = (C)y[ridx[j]];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = r0 + lane;
   C acc = 0;
-  if (r < nrows) {
-    if constexpr (tri) {
-      const S* A = STEP == GR_F_LG ? b.Lg : b.Ls;
-      const int m = STEP == GR_F_LG ? n : nr;
-      acc = strided_dot<kDotUnroll>(
-          wave, r + 1, kTileWaves, [&](int j) { return load_as<C>(A + colstart(j, m) + (r - j)); },
-          xs);
-    } else {
-      acc = strided_dot<kDotUnroll>(
-          wave, nr, kTileWaves, [&](int i) { return load_as<C>(b.T + (int64_t)i * k + r); }, xs);
-    }
+  if (r < n) {
+    const S* col = M + r;
+    acc = strided_dot<kDotUnroll>(
+        wave, c1 - c0, TT / 64, [&](int j) { return load_as<C>(col + (int64_t)(c0 + j) * ld); },
+        xs);
   }
   red[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && r < nrows) {
-    C tot = 0;
+  if constexpr (KIND == DR_CELL_FWD) {
+    __shared__ C vt[kRowTile];
+    if (wave == 0 && r < n) {
+      C tot = 0;
 #pragma unroll
-    for (int w = 0; w < kTileWaves; ++w) tot += red[w][lane];
-    if constexpr (STEP == GR_F_LG) {
-      z[r] = (double)tot;
-    } else if constexpr (STEP == GR_F_LS) {
-      u[r] = (double)tot;
-      y[gi[perm[r]]] = (double)tot;
-    } else if constexpr (STEP == GR_F_T) {
-      const int p = nr ? perm[nr + r] : r;
-      y[gi[p]] = (double)((C)z[p] + tot);
-    } else if constexpr (STEP == GR_B_LS) {
-      u[r] = (double)((C)y[gi[perm[r]]] + tot);
-    } else {
-      const int p = nr ? perm[nr + r] : r;
-      z[p] = (double)((C)y[gi[p]] - tot);
+      for (int q = 0; q < TT / 64; ++q) tot += red[q][lane];
+      vt[lane] = tot;
+      w[r] = y[idx[c.offI + r]];
+    }
+    __syncthreads();
+    const int32_t* ib = idx + c.offC;
+    const S* cw = vals + c.offV + tri_count(n);
+    for (int b = threadIdx.x; b < c.nB; b += TT) {
+      const int i = ib[b];
+      if (i >= r0 && i < r0 + kRowTile) cb[c.offCB + b] = (double)(load_as<C>(cw + b) * vt[i - r0]);
+    }
+  } else {
+    if (wave == 0 && r < n) {
+      C tot = 0;
+#pragma unroll
+      for (int q = 0; q < TT / 64; ++q) tot += red[q][lane];
+      if constexpr (KIND == DR_CELL_BWD) y[idx[c.offI + r]] = (double)tot;
+      else w[r] = (double)tot;
     }
   }
 }
 
-template <typename S, typename C, int STEP>
-__global__ __launch_bounds__(kTileThreads) void k_gt_cols(const GroupDesc* __restrict__ gd,
-                                                          const int4* __restrict__ tiles,
-                                                          const int32_t* __restrict__ idx,
-                                                          const S* __restrict__ vals,
-                                                          double* __restrict__ y,
-                                                          double* __restrict__ wsc,
-                                                          const int* __restrict__ done) {
+// Backward group step: x_g <- G^T x_g, column c of G (contiguous) by one wavefront.
+template <typename S, typename C, int TT>
+__global__ __launch_bounds__(TT) void k_dense_gcols(const GroupDesc* __restrict__ gd,
+                                                    const int64_t* __restrict__ ddoff,
+                                                    const int4* __restrict__ tiles,
+                                                    const int32_t* __restrict__ idx,
+                                                    const S* __restrict__ dv,
+                                                    const double* __restrict__ y,
+                                                    double* __restrict__ wsc,
+                                                    const int* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* xs = reinterpret_cast<C*>(smem_raw);
-  const int4 t = tiles[blockIdx.x];
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   if (done && *done) return;
-  const GroupDesc d = gd[t.x];
-  const int n = d.n, nr = d.nr, k = n - nr;
-  double* z = wsc + t.z;
-  double* tv = z + n;
-  double* u = tv + nr;
-  double* v = u + nr;
-  const int32_t* gi = idx + d.offIdx;
-  const int32_t* perm = idx + d.offPerm;
-  const GroupBlocks<S> b(d, vals);
-  constexpr bool isT = STEP == GC_F_T || STEP == GC_B_T;
-  const int m = STEP == GC_B_LG ? n : nr;  // columns (and rows of the triangle)
-  const int c0 = t.y;
-  if constexpr (isT) {  // x_s (all of it): z_s forward, x_s backward
-    for (int q = threadIdx.x; q < k; q += blockDim.x) {
-      const int p = perm[nr + q];
-      xs[q] = STEP == GC_F_T ? (C)z[p] : (C)y[gi[p]];
-    }
-  } else {  // the rows j >= c0 of the triangle's columns
-    const double* src = STEP == GC_B_LG ? z : u;
-    for (int j = c0 + (int)threadIdx.x; j < m; j += blockDim.x) xs[j - c0] = (C)src[j];
-  }
+  const GroupDesc g = gd[t.x];
+  const int n = g.n, ld = dense_ld(n);
+  const int32_t* gi = idx + g.offIdx;
+  for (int j = threadIdx.x; j < n; j += TT) xs[j] = (C)y[gi[j]];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = wave; q < kColTile; q += kTileWaves) {
-    const int i = c0 + q;
-    if (i >= m) break;
-    C acc;
-    if constexpr (isT) {
-      const S* col = b.T + (int64_t)i * k;
-      acc = strided_dot<kDotUnroll>(lane, k, 64, [&](int j) { return load_as<C>(col + j); }, xs);
-    } else {
-      const S* col = (STEP == GC_B_LG ? b.Lg : b.Ls) + colstart(i, m);
-      acc = strided_dot<kDotUnroll>(
-          i - c0 + lane, m - c0, 64, [&](int j) { return load_as<C>(col + (j - (i - c0))); }, xs);
-    }
+  const S* M = dv + ddoff[t.x];
+  for (int q = wave; q < kDenseColsPerTile; q += TT / 64) {
+    const int i = t.y + q;
+    if (i >= n) break;
+    const S* col = M + (int64_t)i * ld;
+    C acc = strided_dot<kDotUnroll>(lane, n, 64, [&](int j) { return load_as<C>(col + j); }, xs);
     acc = wave_reduce(acc);
-    if (lane == 0) {
-      if constexpr (STEP == GC_F_T) {
-        tv[i] = (double)((C)z[perm[i]] - acc);
-      } else if constexpr (STEP == GC_F_LS) {
-        v[i] = (double)acc;
-      } else if constexpr (STEP == GC_B_T) {
-        tv[i] = (double)acc;
-      } else if constexpr (STEP == GC_B_LS) {
-        v[i] = (double)acc;
-        z[perm[i]] = (double)acc;
-      } else {
-        y[gi[i]] = (double)acc;
-      }
-    }
+    if (lane == 0) wsc[t.w + i] = (double)acc;
+  }
+}
+
+// y[id] = sum over p < parts of wsc[src + p * stride], entries (id, src, parts, stride).
+__global__ __launch_bounds__(256) void k_dense_scatter(const int4* __restrict__ e, int count,
+                                                       const double* __restrict__ wsc,
+                                                       double* __restrict__ y,
+                                                       const int* __restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const int4 q = e[i];
+    double a = 0;
+    for (int p = 0; p < q.z; ++p) a += wsc[q.y + (int64_t)p * q.w];
+    y[q.x] = a;
   }
 }
 
@@ -1284,35 +1297,35 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
 // launches of one tiled cell sweep
 int tiled_launches(const LevelDev& L) { return L.cmode ? 2 : 1; }
 
-template <typename S, typename C>
-void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
+template <typename S, typename C, int TT>
+void launch_tiled_tt(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
                   double* cb, const int* done, hipStream_t s, TimedSeq& t) {
   const int32_t* idx = f.idx.p;
   const size_t rows_smem = sizeof(C) * (size_t)std::max(1, L.maxI);
   const size_t cols_smem = sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB);
   if (fwd) {
     if (L.cmode) {
-      launch(k_tfwd_rows<S, C, 1>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t.next(),
+      launch(k_tfwd_rows<S, C, 1, TT>, dim3(L.nrt), dim3(TT), rows_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, cb, done);
-      launch(k_tcols<S, C, 2>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t.next(),
+      launch(k_tcols<S, C, 2, TT>, dim3(L.nct), dim3(TT), cols_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, cb, done);
     } else {
-      launch(k_tfwd_rows<S, C, 0>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t.next(),
+      launch(k_tfwd_rows<S, C, 0, TT>, dim3(L.nrt), dim3(TT), rows_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, cb, done);
     }
   } else {
     if (L.cmode) {
-      launch(k_tbwd_rows1<S, C>, dim3(L.nrt), dim3(kTileThreads), rows_smem, s, t.next(),
+      launch(k_tbwd_rows1<S, C, TT>, dim3(L.nrt), dim3(TT), rows_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
              f.wsc.p, done);
-      launch(k_tcols<S, C, 1>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t.next(),
+      launch(k_tcols<S, C, 1, TT>, dim3(L.nct), dim3(TT), cols_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, cb, done);
     } else {
-      launch(k_tcols<S, C, 0>, dim3(L.nct), dim3(kTileThreads), cols_smem, s, t.next(),
+      launch(k_tcols<S, C, 0, TT>, dim3(L.nct), dim3(TT), cols_smem, s, t.next(),
              (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
              (const double*)f.wsc.p, cb, done);
     }
@@ -1320,39 +1333,80 @@ void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals
 }
 
 template <typename S, typename C>
-void launch_group_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
-                        double* y, const double* cb, const int* done, hipStream_t s,
-                        const StageTimer& t) {
-  const int32_t* idx = f.idx.p;
-  const GroupDesc* gd = (const GroupDesc*)L.groups.p;
-  const size_t sm = sizeof(C) * (size_t)std::max(1, L.maxG);
-  double* w = f.wsc.p;
-  // the lists each launch runs over, in launch order (an empty list skips its launch)
-  static const int fk[5] = {GT_ROWS_N, GT_COLS_NR, GT_ROWS_NR, GT_COLS_NR, GT_ROWS_K};
-  static const int bk[5] = {GT_COLS_NR, GT_ROWS_NR, GT_COLS_NR, GT_ROWS_K, GT_COLS_N};
-  const int* kinds = fwd ? fk : bk;
-  int count = 0;
-  for (int i = 0; i < 5; ++i) count += L.gtn[kinds[i]] > 0;
-  TimedSeq ts(t, count);
-  auto go = [&](int i, auto kernel, auto... args) {
-    const int kind = kinds[i];
-    if (!L.gtn[kind]) return;
-    launch(kernel, dim3(L.gtn[kind]), dim3(kTileThreads), sm, s, ts.next(), gd,
-           (const int4*)L.gtiles.p + L.gto[kind], idx, vals, y, args..., w, done);
-  };
-  if (fwd) {
-    go(0, k_gt_rows<S, C, GR_F_LG>, cb);
-    go(1, k_gt_cols<S, C, GC_F_T>);
-    go(2, k_gt_rows<S, C, GR_F_LS>, cb);
-    go(3, k_gt_cols<S, C, GC_F_LS>);
-    go(4, k_gt_rows<S, C, GR_F_T>, cb);
-  } else {
-    go(0, k_gt_cols<S, C, GC_B_T>);
-    go(1, k_gt_rows<S, C, GR_B_LS>, cb);
-    go(2, k_gt_cols<S, C, GC_B_LS>);
-    go(3, k_gt_rows<S, C, GR_B_T>, cb);
-    go(4, k_gt_cols<S, C, GC_B_LG>);
+void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
+                  double* cb, const int* done, hipStream_t s, TimedSeq& t) {
+  switch (L.tthreads) {
+    case 256: launch_tiled_tt<S, C, 256>(f, L, fwd, vals, y, cb, done, s, t); break;
+    case 512: launch_tiled_tt<S, C, 512>(f, L, fwd, vals, y, cb, done, s, t); break;
+    default: launch_tiled_tt<S, C, 1024>(f, L, fwd, vals, y, cb, done, s, t); break;
   }
+}
+
+constexpr int kDenseSpanAll = 1 << 30;   // row tiles over all columns of their block
+
+template <typename S, typename C, int TT>
+void launch_dense_cells_tt(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
+                           double* y, double* cb, const int* done, hipStream_t s,
+                           const StageTimer& t) {
+  const size_t sm = sizeof(C) * (size_t)std::max(1, L.maxI);
+  auto k = fwd ? k_dense_rows<S, C, DR_CELL_FWD, TT> : k_dense_rows<S, C, DR_CELL_BWD, TT>;
+  launch(k, dim3(L.ncdt), dim3(TT), sm, s, t, (const CellDesc*)L.cells.p,
+         (const GroupDesc*)nullptr, (const int64_t*)L.cddoff.p, (const int4*)L.cdtiles.p,
+         kDenseSpanAll, 0, (const int32_t*)nullptr, (const int32_t*)f.idx.p, vals,
+         reinterpret_cast<const S*>(f.dvals.p), y, cb, f.wsc.p, done);
+}
+
+template <typename S, typename C>
+void launch_dense_cells(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
+                        double* y, double* cb, const int* done, hipStream_t s,
+                        const StageTimer& t) {
+  switch (L.tthreads) {
+    case 256: launch_dense_cells_tt<S, C, 256>(f, L, fwd, vals, y, cb, done, s, t); break;
+    case 512: launch_dense_cells_tt<S, C, 512>(f, L, fwd, vals, y, cb, done, s, t); break;
+    default: launch_dense_cells_tt<S, C, 1024>(f, L, fwd, vals, y, cb, done, s, t); break;
+  }
+}
+
+constexpr int kDenseThreads = 512;
+
+void launch_scatter(const DevBuf<int4>& e, int count, const FactorDev& f, double* y,
+                    const int* done, hipStream_t s, const StageTimer& t) {
+  const int grid = std::max(1, std::min(1024, (count + 255) / 256));
+  launch(k_dense_scatter, dim3(grid), dim3(256), 0, s, t, (const int4*)e.p, count,
+         (const double*)f.wsc.p, y, done);
+}
+
+template <typename S, typename C>
+void launch_dense_groups(const FactorDev& f, const LevelDev& L, bool fwd, double* y,
+                         const double* cb, const int* done, hipStream_t s, const StageTimer& t) {
+  TimedSeq ts(t, 2);
+  const size_t sm = sizeof(C) * (size_t)std::max(1, L.maxG);
+  const S* dv = reinterpret_cast<const S*>(f.dvals.p);
+  if (fwd)
+    launch(k_dense_rows<S, C, DR_GROUP_FWD, kDenseThreads>, dim3(L.ngrt), dim3(kDenseThreads),
+           sm, s, ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)L.groups.p,
+           (const int64_t*)L.gddoff.p, (const int4*)L.grtiles.p, kDenseSpanAll, 0,
+           (const int32_t*)nullptr, (const int32_t*)f.idx.p, (const S*)nullptr, dv, y,
+           const_cast<double*>(cb), f.wsc.p, done);
+  else
+    launch(k_dense_gcols<S, C, kDenseThreads>, dim3(L.ngct), dim3(kDenseThreads), sm, s,
+           ts.next(), (const GroupDesc*)L.groups.p, (const int64_t*)L.gddoff.p,
+           (const int4*)L.gctiles.p, (const int32_t*)f.idx.p, dv, (const double*)y, f.wsc.p,
+           done);
+  launch_scatter(L.gscat, L.ngsc, f, y, done, s, ts.next());
+}
+
+template <typename S, typename C>
+void launch_dense_root(const FactorDev& f, double* y, const int* done, hipStream_t s,
+                       const StageTimer& t) {
+  TimedSeq ts(t, 2);
+  const size_t sm = sizeof(C) * (size_t)std::max(1, std::min(f.nroot, f.rspan));
+  launch(k_dense_rows<S, C, DR_ROOT, kDenseThreads>, dim3(f.nrdt), dim3(kDenseThreads), sm, s,
+         ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)nullptr,
+         (const int64_t*)f.rddoff.p, (const int4*)f.rdtiles.p, f.rspan, f.nroot,
+         (const int32_t*)f.idx.p + f.offRootIdx, (const int32_t*)f.idx.p, (const S*)nullptr,
+         reinterpret_cast<const S*>(f.dvals.p), y, (double*)nullptr, f.wsc.p, done);
+  launch_scatter(f.rscat, f.nrsc, f, y, done, s, ts.next());
 }
 
 template <typename S, typename C>
@@ -1367,7 +1421,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     if (L.ncell && !(l > 0 && f.lv[l - 1].fuse)) {
       const StageTimer t(prof, l, STAGE_CELL_FWD, done, s);
       TimedSeq ts(t, tiled_launches(L));
-      if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, ts);
+      if (L.cdense) launch_dense_cells<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
+      else if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, ts);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t);
     }
@@ -1391,7 +1446,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
              (const double*)cbl(l), (int)fp.prestage, done);
     } else if (L.gtiled) {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
-      launch_group_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
+      launch_dense_groups<S, C>(f, L, true, y, cbl(l), done, s, t);
     } else {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       const StagePlan p = group_plan<C>(L);
@@ -1402,10 +1457,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
   }
   if (f.nroot && !f.root_fused) {
     const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
-    if (f.root_tiled) {  // y_r = L^-T (L^-1 y_r) as a row pass then a column pass
-      TimedSeq ts(t, 2 * tiled_launches(f.rootlv));
-      launch_tiled<S, C>(f, f.rootlv, true, vals, y, cbl(nlev), done, s, ts);
-      launch_tiled<S, C>(f, f.rootlv, false, vals, y, cbl(nlev), done, s, ts);
+    if (f.root_tiled) {
+      launch_dense_root<S, C>(f, y, done, s, t);
     } else {
       bool rs;
       const size_t rsm = root_smem<C>(f.nroot, &rs);
@@ -1418,7 +1471,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     if (L.ngroup && !(l == nlev - 1 && f.root_fused)) {
       const StageTimer t(prof, l, STAGE_GROUP_BWD, done, s);
       if (L.gtiled) {
-        launch_group_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
+        launch_dense_groups<S, C>(f, L, false, y, cbl(l), done, s, t);
       } else {
         const StagePlan p = group_plan<C>(L);
         launch(k_group_bwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t,
@@ -1429,7 +1482,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     if (L.ncell) {
       const StageTimer t(prof, l, STAGE_CELL_BWD, done, s);
       TimedSeq ts(t, tiled_launches(L));
-      if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, ts);
+      if (L.cdense) launch_dense_cells<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
+      else if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, ts);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, false, vals, y, cbl(l), done, s, t);
     }
@@ -1490,6 +1544,13 @@ void set_apply_smem_limits(size_t bytes) {
   const int b = (int)bytes;
 #define HIF_SMEM(K) HIF_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(K),           \
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, b))
+#define HIF_SMEM_TILES(S, C, TT)                                                              \
+  HIF_SMEM((k_tfwd_rows<S, C, 0, TT>));                                                       \
+  HIF_SMEM((k_tfwd_rows<S, C, 1, TT>));                                                       \
+  HIF_SMEM((k_tbwd_rows1<S, C, TT>));                                                         \
+  HIF_SMEM((k_tcols<S, C, 0, TT>));                                                           \
+  HIF_SMEM((k_tcols<S, C, 1, TT>));                                                           \
+  HIF_SMEM((k_tcols<S, C, 2, TT>))
 #define HIF_SMEM_ALL(S, C)                                                                    \
   HIF_SMEM((k_cell_fwd<S, C, false, 0>));                                                     \
   HIF_SMEM((k_cell_bwd<S, C, false, 0>));                                                     \
@@ -1503,22 +1564,9 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM((k_group_bwd<S, C, true>));                                                        \
   HIF_SMEM((k_group_fwd<S, C, false>));                                                       \
   HIF_SMEM((k_group_bwd<S, C, false>));                                                       \
-  HIF_SMEM((k_tfwd_rows<S, C, 0>));                                                           \
-  HIF_SMEM((k_tfwd_rows<S, C, 1>));                                                           \
-  HIF_SMEM((k_tbwd_rows1<S, C>));                                                             \
-  HIF_SMEM((k_tcols<S, C, 0>));                                                               \
-  HIF_SMEM((k_tcols<S, C, 1>));                                                               \
-  HIF_SMEM((k_tcols<S, C, 2>));                                                               \
-  HIF_SMEM((k_gt_rows<S, C, GR_F_LG>));                                                       \
-  HIF_SMEM((k_gt_rows<S, C, GR_F_LS>));                                                       \
-  HIF_SMEM((k_gt_rows<S, C, GR_F_T>));                                                        \
-  HIF_SMEM((k_gt_rows<S, C, GR_B_LS>));                                                       \
-  HIF_SMEM((k_gt_rows<S, C, GR_B_T>));                                                        \
-  HIF_SMEM((k_gt_cols<S, C, GC_F_T>));                                                        \
-  HIF_SMEM((k_gt_cols<S, C, GC_F_LS>));                                                       \
-  HIF_SMEM((k_gt_cols<S, C, GC_B_T>));                                                        \
-  HIF_SMEM((k_gt_cols<S, C, GC_B_LS>));                                                       \
-  HIF_SMEM((k_gt_cols<S, C, GC_B_LG>));                                                       \
+  HIF_SMEM_TILES(S, C, 256);                                                                  \
+  HIF_SMEM_TILES(S, C, 512);                                                                  \
+  HIF_SMEM_TILES(S, C, 1024);                                                                 \
   HIF_SMEM((k_root<S, C>));                                                                   \
   HIF_SMEM((k_fuse_fwd<S, C, true>));                                                         \
   HIF_SMEM((k_fuse_fwd<S, C, false>));                                                        \
@@ -1527,6 +1575,7 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM_ALL(float, float);
   HIF_SMEM_ALL(bf16_t, float);
 #undef HIF_SMEM_ALL
+#undef HIF_SMEM_TILES
 #undef HIF_SMEM
   granted = bytes;
 }
@@ -1553,39 +1602,6 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
   *base = woff;
 }
 
-// Tiles of a level's groups; the group vectors take scratch from `base` on (every group stage
-// finishes before the next starts, so all levels share the region).  Each list runs its heavier
-// tiles first (rows far down a triangle, columns near its left edge).  Returns the scratch used.
-int64_t tile_groups(LevelDev& L, const std::vector<GroupDesc>& gs, int64_t base, hipStream_t s) {
-  struct T { int64_t work; int4 t; };
-  std::vector<T> lists[GT_KINDS];
-  int64_t off = base;
-  for (size_t g = 0; g < gs.size(); ++g) {
-    const int n = gs[g].n, nr = gs[g].nr, k = n - nr;
-    auto add = [&](int kind, int m, int step, bool tri_rows, bool tri_cols, int len) {
-      for (int a0 = 0; a0 < m; a0 += step) {
-        const int64_t w = tri_rows ? std::min(m, a0 + step) : tri_cols ? m - a0 : len;
-        lists[kind].push_back({w, {(int)g, a0, (int)off, 0}});
-      }
-    };
-    add(GT_ROWS_N, n, kRowTile, true, false, 0);
-    add(GT_ROWS_NR, nr, kRowTile, true, false, 0);
-    add(GT_ROWS_K, k, kRowTile, false, false, nr);
-    add(GT_COLS_NR, nr, kColTile, false, false, k + nr);
-    add(GT_COLS_N, n, kColTile, false, true, 0);
-    off += n + 3 * (int64_t)nr;
-  }
-  std::vector<int4> all;
-  for (int i = 0; i < GT_KINDS; ++i) {
-    std::stable_sort(lists[i].begin(), lists[i].end(),
-                     [](const T& x, const T& y) { return x.work > y.work; });
-    L.gto[i] = (int)all.size();
-    L.gtn[i] = (int)lists[i].size();
-    for (const T& t : lists[i]) all.push_back(t.t);
-  }
-  L.gtiles.upload(all, s);
-  return off - base;
-}
 }  // namespace
 
 namespace {
@@ -1703,46 +1719,128 @@ void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                        : fuse_plan<float>(f.lv[nlev - 1], nullptr, f.nroot).ok;
 }
 
+namespace {
+// Workgroup size of a tiled level: small cells (few columns per row tile) run more, smaller
+// workgroups per CU.  HIFCN_TILE_SMALL_THREADS / HIFCN_TILE_SMALL_MAX override the choice.
+int tile_threads(int maxI) {
+  int small_threads = 512, small_max = 512;
+  if (const char* e = std::getenv("HIFCN_TILE_SMALL_THREADS")) small_threads = std::atoi(e);
+  if (const char* e = std::getenv("HIFCN_TILE_SMALL_MAX")) small_max = std::atoi(e);
+  if (small_threads != 256 && small_threads != 512) small_threads = 1024;
+  return maxI <= small_max ? small_threads : 1024;
+}
+}  // namespace
+
 void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
-                  const std::vector<std::vector<GroupDesc>>& groups, hipStream_t s) {
+                  const std::vector<std::vector<GroupDesc>>& groups,
+                  const std::vector<int32_t>& idx, hipStream_t s) {
   const bool f64 = f.store == HIF_STORE_F64;
+  const int64_t eb = (int64_t)store_elem_bytes(f.store);
+  std::vector<DenseJob> jobs;
+  int64_t dtot = 0;
+  auto dense_job = [&](int kind, int n, int nr, int64_t src, int32_t perm) {
+    const DenseJob j{kind, n, nr, dense_ld(n), src, dtot, perm, 0};
+    jobs.push_back(j);
+    dtot += (int64_t)n * dense_ld(n);
+    return j.dst;
+  };
+  // cells: link-mode blocks too large for one workgroup in dense form; the scratch keeps the
+  // interiors of tiled cells from the forward to the backward sweep ([0, wtot))
   int64_t wtot = 0;
   for (size_t l = 0; l < f.lv.size(); ++l) {
     LevelDev& L = f.lv[l];
     L.tiled = L.ncell > 0 && !(f64 ? cell_plan<double>(L).staged : cell_plan<float>(L).staged);
-    if (L.tiled) tile_level(L, cells[l], &wtot, s);
+    L.cdense = L.tiled && L.cmode == 1;
+    if (!L.tiled) continue;
+    L.tthreads = tile_threads(L.maxI);
+    if (!L.cdense) {
+      tile_level(L, cells[l], &wtot, s);
+      continue;
+    }
+    std::vector<int4> tl;
+    std::vector<int64_t> off;
+    int64_t fb = 0, bb = 0;
+    for (size_t c = 0; c < cells[l].size(); ++c) {
+      const CellDesc& d = cells[l][c];
+      off.push_back(dense_job(0, d.nI, 0, d.offV, 0));
+      for (int r0 = 0; r0 < d.nI; r0 += kRowTile) tl.push_back({(int)c, r0, 0, (int)wtot});
+      wtot += d.nI;
+      const int64_t nI = d.nI, nB = d.nB;
+      fb += eb * (nI * nI + nB) + 8 * (3 * nI + nB) + 4 * (nI + 2 * nB) + (int64_t)sizeof(CellDesc);
+      bb += eb * (nI * nI + nB) + 8 * (2 * nI + nB) + 4 * (2 * nI + 1 + 3 * nB) +
+            (int64_t)sizeof(CellDesc);
+    }
+    L.ncdt = (int)tl.size();
+    L.cdtiles.upload(tl, s);
+    L.cddoff.upload(off, s);
+    L.cell_bytes[0] = fb;
+    L.cell_bytes[1] = bb;
   }
   // groups that do not fit one workgroup (HIFCN_GROUP_TILES=1: every level's groups, for tests)
+  // in dense form; their results, and the root's partial sums, take the scratch from wtot on
+  // (one stage at a time)
   const char* ge = std::getenv("HIFCN_GROUP_TILES");
   const bool all_groups = ge && std::atoi(ge) != 0;
-  int64_t gneed = 0;
+  int64_t dneed = 0;
   for (size_t l = 0; l < f.lv.size(); ++l) {
     LevelDev& L = f.lv[l];
     L.gtiled = L.ngroup > 0 && (all_groups || !(f64 ? group_plan<double>(L).staged
                                                      : group_plan<float>(L).staged));
-    if (L.gtiled) gneed = std::max(gneed, tile_groups(L, groups[l], wtot, s));
+    if (!L.gtiled) continue;
+    std::vector<int4> rt, ct, sc;
+    std::vector<int64_t> off;
+    int64_t zo = wtot, fb = 0, bb = 0;
+    for (size_t g = 0; g < groups[l].size(); ++g) {
+      const GroupDesc& d = groups[l][g];
+      const int n = d.n;
+      off.push_back(dense_job(1, n, d.nr, d.offV, d.offPerm));
+      for (int r0 = 0; r0 < n; r0 += kRowTile) rt.push_back({(int)g, r0, 0, (int)zo});
+      for (int c0 = 0; c0 < n; c0 += kDenseColsPerTile) ct.push_back({(int)g, c0, 0, (int)zo});
+      for (int r = 0; r < n; ++r) sc.push_back({idx[d.offIdx + r], (int)(zo + r), 1, 0});
+      zo += n;
+      const int64_t ns = idx[d.offGP + n];
+      fb += eb * (int64_t)n * n + 8 * (4 * (int64_t)n + ns) + 4 * (3 * (int64_t)n + 1 + ns) +
+            (int64_t)sizeof(GroupDesc);
+      bb += eb * (int64_t)n * n + 8 * 4 * (int64_t)n + 4 * 2 * (int64_t)n +
+            (int64_t)sizeof(GroupDesc);
+    }
+    dneed = std::max(dneed, zo - wtot);
+    L.ngrt = (int)rt.size();
+    L.ngct = (int)ct.size();
+    L.ngsc = (int)sc.size();
+    L.grtiles.upload(rt, s);
+    L.gctiles.upload(ct, s);
+    L.gscat.upload(sc, s);
+    L.gddoff.upload(off, s);
+    L.group_bytes[0] = fb;
+    L.group_bytes[1] = bb;
   }
-  // a root of more than 256 KiB of factor is spread over many workgroups
-  const size_t eb = store_elem_bytes(f.store);
-  f.root_tiled = (size_t)tri_count(f.nroot) * eb > 256 * 1024;
+  // a root of more than 256 KiB of factor: dense A_r^-1, row tiles over column ranges
+  f.root_tiled = tri_count(f.nroot) * eb > 256 * 1024;
   if (f.root_tiled) {
-    CellDesc d{};
-    d.nI = f.nroot;
-    d.nB = 0;
-    d.offI = f.offRootIdx;
-    d.offV = (int32_t)f.offRootV;
-    d.mode = 0;
-    LevelDev& R = f.rootlv;
-    R.ncell = 1;
-    R.maxI = f.nroot;
-    R.maxB = 0;
-    R.cmode = 0;
-    R.tiled = true;
-    R.cells.upload(std::vector<CellDesc>{d}, s);
-    tile_level(R, {d}, &wtot, s);
+    const int n = f.nroot;
+    f.rspan = 512;
+    const int nch = (n + f.rspan - 1) / f.rspan;
+    f.rddoff.upload(std::vector<int64_t>{dense_job(0, n, 0, f.offRootV, 0)}, s);
+    std::vector<int4> rt, sc;
+    for (int c = 0; c < nch; ++c)
+      for (int r0 = 0; r0 < n; r0 += kRowTile)
+        rt.push_back({0, r0, c * f.rspan, (int)(wtot + (int64_t)c * n)});
+    for (int r = 0; r < n; ++r) sc.push_back({idx[f.offRootIdx + r], (int)(wtot + r), nch, n});
+    f.nrdt = (int)rt.size();
+    f.nrsc = (int)sc.size();
+    f.rdtiles.upload(rt, s);
+    f.rscat.upload(sc, s);
+    dneed = std::max(dneed, (int64_t)nch * n);
+    f.root_bytes = eb * (int64_t)n * n + 8 * (2 * (int64_t)n + 2 * (int64_t)nch * n) +
+                   4 * 2 * (int64_t)n;
   }
-  HIF_REQUIRE(wtot + gneed < (int64_t)INT32_MAX, HIF_ERR_ARG, "tiled scratch too large");
-  f.wsc.alloc(std::max<int64_t>(1, wtot + gneed));
+  HIF_REQUIRE(wtot + dneed < (int64_t)INT32_MAX, HIF_ERR_ARG, "tiled scratch too large");
+  f.wsc.alloc(std::max<int64_t>(1, wtot + dneed));
+  f.ndvals = dtot;
+  f.dvals.alloc((size_t)std::max<int64_t>(1, dtot) * eb);
+  if (dtot) HIF_CHECK(hipMemsetAsync(f.dvals.p, 0, (size_t)dtot * eb, s));
+  build_dense_forms(f, jobs, s);
 }
 
 }  // namespace hifcn

@@ -1407,7 +1407,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       cells.push_back(lo.cells);
       groups.push_back(lo.groups);
     }
-    setup_tiling(f, cells, groups, s);
+    setup_tiling(f, cells, groups, idx, s);
     setup_fusion(f, cells, groups, idx, hd.N, s);
   }
   size_t worst = 0;

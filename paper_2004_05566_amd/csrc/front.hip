@@ -327,13 +327,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tiles(const GemmTask* __restr
   const GemmTask t = tasks[tl.x];
   const int r0 = tl.y, c0 = tl.z;
   const int rows = min(kT, t.m - r0), cols = min(kT, t.n - c0);
-  int kend = t.k;
+  int kend = t.k, kbeg = 0;
   if (t.tri == 1) kend = min(kend, c0 + cols);
   if (t.tri == 2) kend = min(kend, r0 + rows);
+  if (t.tri == 3) kbeg = max(r0, c0);
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < kend; k0 += kKc) {
+  for (int k0 = kbeg; k0 < kend; k0 += kKc) {
     const int kv = min(kKc, kend - k0);
     if (t.ta) stage_t(As, t.A + (int64_t)k0 * t.lda + r0, t.lda, kv, rows);
     else stage(As, t.A + (int64_t)r0 * t.lda + k0, t.lda, rows, kv);
@@ -368,6 +369,9 @@ void gemm_batched(const std::vector<GemmTask>& tasks, hipStream_t s, FrontStats*
     if (stats) {  // algorithmic flops (triangular operands count their nonzero part)
       if (t.tri == 1) stats->flops += (int64_t)t.m * t.n * (t.n + 1);
       else if (t.tri == 2) stats->flops += (int64_t)t.n * t.m * (t.m + 1);
+      else if (t.tri == 3)  // entries (i, j) with max(i, j) = d: 2d + 1 of them, k - d terms
+        for (int64_t d = 0; d < std::min<int64_t>(std::min(t.m, t.n), t.k); ++d)
+          stats->flops += 2 * (2 * d + 1) * (t.k - d);
       else stats->flops += 2 * (int64_t)t.m * t.n * t.k;
     }
   }

@@ -37,7 +37,8 @@ struct FrontStats {
 // One product C = alpha op(A) op(B) (+ I if addI) of row-major FP64 matrices (m x n result,
 // inner dimension k): op(B) = B^T if nt = 1, else B; op(A) = A, or with ta = 1 A is given as
 // its transpose (k x m).  tri = 1: column j of the result needs only inner indices <= j (op(B)
-// = L^T with L lower); tri = 2: row i needs only inner indices <= i (op(A) lower triangular).
+// = L^T with L lower); tri = 2: row i needs only inner indices <= i (op(A) lower triangular);
+// tri = 3: entry (i, j) needs only inner indices >= max(i, j) (op(A) = L^T, op(B) = L, square).
 struct GemmTask {
   const double* A;
   const double* B;

@@ -22,14 +22,18 @@ struct LevelDev {
   // Cells too large for one workgroup are tiled: row tiles and column tiles of 64 / 16
   // (cell, first row or column, scratch offset of the cell's interior, unused).
   bool tiled = false;
+  int tthreads = 1024;               // workgroup size of the tiles (256, 512 or 1024)
   int nrt = 0, nct = 0;
   DevBuf<int4> rtiles, ctiles;
-  // Groups too large for one workgroup's LDS run one launch per product over tiles of all the
-  // level's groups (group, first row or column, scratch offset of the group's vectors, unused):
-  // five lists (rows over n, nr, k; columns over nr, n) at gto[i] in gtiles, gtn[i] tiles each.
-  bool gtiled = false;
-  int gto[5] = {0, 0, 0, 0, 0}, gtn[5] = {0, 0, 0, 0, 0};
-  DevBuf<int4> gtiles;
+  // Blocks that one workgroup cannot hold are applied in dense form (FactorDev::dvals), spread
+  // over many workgroups: link-mode cells of tiled levels (cdense: A_II^-1, row tiles) and the
+  // groups of gtiled levels (the whole group step G: row tiles forward, column tiles backward,
+  // results written back from the scratch vector by a scatter list).  Tiles: (block, first row
+  // or column, first column of the tile's range, scratch offset); ddoff: dvals offset per block.
+  bool cdense = false, gtiled = false;
+  int ncdt = 0, ngrt = 0, ngct = 0, ngsc = 0;
+  DevBuf<int4> cdtiles, grtiles, gctiles, gscat;
+  DevBuf<int64_t> cddoff, gddoff;
   // The group stage of this level runs in one launch with the cell stage of the next level:
   // owned = the descriptors of the groups each next-level cell runs, maxown per cell (padded
   // with empty descriptors).
@@ -87,9 +91,16 @@ struct FactorDev {
   int64_t root_bytes = 0;
   std::unique_ptr<StageProfiler> prof;
   DevBuf<double> wsc;   // interiors of tiled cells between the forward and backward sweep,
-                        // then the vectors of tiled groups within one stage
-  LevelDev rootlv;      // the root as a one-cell level, used when it is tiled
+                        // then the results of dense group and root stages within one stage
+  // Dense forms (column-major, leading dimension a multiple of 32, storage precision).
+  DevBuf<unsigned char> dvals;
+  int64_t ndvals = 0;
+  // A root of more than 256 KiB is applied as M = L_r^-T L_r^-1 in dense form: row tiles over
+  // column ranges of rspan, partial sums added up by the scatter list.
   bool root_tiled = false;
+  int rspan = 0, nrdt = 0, nrsc = 0;
+  DevBuf<int64_t> rddoff;
+  DevBuf<int4> rdtiles, rscat;
   // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
   int64_t mfma_flops = 0;
   double mfma_ms = 0;
@@ -158,7 +169,20 @@ size_t apply_smem_need(const FactorDev& f, size_t* worst);
 // Decide per level whether cells are tiled across workgroups and upload the tile lists;
 // `cells` are the host copies of every level's descriptors.
 void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
-                  const std::vector<std::vector<GroupDesc>>& groups, hipStream_t s);
+                  const std::vector<std::vector<GroupDesc>>& groups,
+                  const std::vector<int32_t>& idx, hipStream_t s);
+
+// One block put in dense form (column-major n x n, leading dimension ld, at dst in dvals).
+struct DenseJob {
+  int32_t kind;      // 0: M = L^-T L^-1 from a packed L^-1 at src; 1: the step of a group whose
+                     //    value block starts at src
+  int32_t n, nr, ld;
+  int64_t src, dst;
+  int32_t offPerm, pad;  // kind 1: pivot order in idx
+};
+// Form the dense blocks (FP64 on the matrix cores, stored in the factor's precision); dvals
+// must be allocated and vals final.
+void build_dense_forms(FactorDev& f, const std::vector<DenseJob>& jobs, hipStream_t s);
 // Decide which group stages run together with the next level's cell stage (and the last level
 // with the root) and upload the ownership lists; call after setup_tiling.
 void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,

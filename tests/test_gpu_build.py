@@ -135,7 +135,8 @@ def test_stage_profiler_counts_launches(gpu_lib):
 
 @pytest.mark.parametrize("store", ["f64", "f32"])
 def test_tiled_3d_factor_cn_matches_oracle(store, gpu_lib):
-    """Leaf cells of 8^3 DOFs (link mode, tiled over workgroups) and a tiled root."""
+    """Leaf cells of 8^3 DOFs (link mode, too large for one workgroup: dense A_II^-1 over
+    row tiles) and a dense root."""
     import torch
     n, dim, leaf, eps, dt = 16, 3, 8, 1e-4, 0.02
     a = gen.grf_coefficient(n, dim, 0.15, 41)
@@ -152,8 +153,8 @@ def test_tiled_3d_factor_cn_matches_oracle(store, gpu_lib):
 
 def test_3d_two_levels_large_groups_match_oracle(gpu_lib):
     """32^3 grid, two levels: the level-1 faces (up to ~230 DOFs) exceed the per-group LDS
-    budget and run as tiled group stages (one launch per product over tiles of all groups);
-    the root is tiled."""
+    budget and run in dense form (one matrix per group step, tiled over many workgroups); the
+    root is dense too."""
     import torch
     n, dim, leaf, eps, dt = 32, 3, 8, 1e-4, 0.02
     a = gen.grf_coefficient(n, dim, 0.15, 51)

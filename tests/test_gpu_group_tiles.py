@@ -1,9 +1,10 @@
-"""Tiled group stages: each product of the group step as its own launch over row and column
-tiles of all the level's groups (used for groups too large for one workgroup's LDS).
+"""Dense group stages: the whole step of each group as one dense matrix G (forward) and G^T
+(backward), formed at factor time from the group's blocks and applied over row and column tiles
+of all the level's groups (used for groups too large for one workgroup's LDS).
 
-HIFCN_GROUP_TILES=1 at factor time tiles the groups of every level, so small problems exercise
-the path against the staged kernels and the oracle.  Both do the same arithmetic with different
-splits of the dot products, so they agree to rounding.
+HIFCN_GROUP_TILES=1 at factor time puts the groups of every level in dense form, so small
+problems exercise the path against the staged kernels and the oracle.  Both apply the same
+operator, multiplied out in a different order, so they agree to rounding.
 """
 import os
 
@@ -75,7 +76,8 @@ def test_group_tiles_cn_matches_oracle(case, gpu_lib):
 
 def test_multi_launch_stage_timing(gpu_lib):
     """A stage of several launches is timed from the start of its first launch to the end of
-    its last: the tiled group stages and the tiled root of a 32^3 grid."""
+    its last: the dense group stages and the dense root of a 32^3 grid (product, then the
+    write-back of the results)."""
     import torch
     n, dim, leaf = 32, 3, 8
     a = gen.grf_coefficient(n, dim, 0.15, 74)
