@@ -314,12 +314,12 @@ def main(argv=None):
     h64 = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store="f64", leaf=w.leaf)
     el64, its64, _, _ = _time_cn(h64, u0, args.steps, args.warmup, args.rtol, react)
 
-    # apply and SpMV bandwidth (algorithmic bytes: factor read twice + FP64 vector in/out)
+    # apply and SpMV bandwidth (algorithmic bytes: the sum over the apply's stages of the factor
+    # blocks in the form they are read, their index lists and the FP64 vectors they move)
     x = torch.randn(w.N, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
     t_apply = _time_op(lambda: h.apply(x, out=y), 50)
-    fb = h.factor_bytes()
-    apply_bytes = 2 * fb + 16 * w.N
+    apply_bytes = h.info()["apply_bytes"]
     t_spmv = _time_op(lambda: h.spmv(x, out=y), 200)
     spmv_bytes = (8 + 8 + 8 * w.dim) * w.N
     stages = None if args.no_stages else stage_breakdown(h, x, y, h.info()["levels"])
@@ -349,7 +349,8 @@ def main(argv=None):
         "f64_store": {"value": args.steps / el64, "n_i_mean": float(np.mean(its64))},
         "t_factor_s": t_factor,
         "build_mfma": _build_mfma(h.info()),
-        "factor_bytes": fb,
+        "factor_bytes": h.factor_bytes(),
+        "device_bytes": h.info()["device_bytes"],
         "apply": {"us": t_apply * 1e6, "GB/s": apply_bytes / t_apply / 1e9,
                   "bytes": apply_bytes},
         "spmv": {"us": t_spmv * 1e6, "GB/s": spmv_bytes / t_spmv / 1e9, "bytes": spmv_bytes},

@@ -122,15 +122,17 @@ hif_status_t cn_batch_step(hif_handle_t* h, const hif_reaction_t* r, const hif_c
                            double** u_dev, int32_t count, int32_t* iters_host,
                            double* relres_host, int32_t* status_host, void** hip_streams);
 
-/* Stored factor bytes (unpadded, in the storage precision): the algorithmic bytes one sweep of
- * hif_apply reads; one apply reads them twice. */
+/* Stored factor bytes (unpadded, in the storage precision; without the dense forms that
+ * hif_get_info's device_bytes includes). */
 size_t hif_factor_bytes(hif_handle_t h);
 
 /* Structure summary: number of levels, root size, stored factor entries, every byte of device
  * memory the handle holds (factor, descriptors and PCG workspace; what a server admitting solves
- * by HBM footprint accounts for), and the part of the build that ran on the FP64 matrix cores
- * (large cells and the root, Sec. 2.2): its algorithmic flops and the summed duration of those
- * kernels (0 for imported factors). */
+ * by HBM footprint accounts for), the part of the build that ran on the FP64 matrix cores
+ * (large cells, the root and the dense forms of blocks too large for one workgroup, Sec. 2.2):
+ * its algorithmic flops and the summed duration of those kernels (0 for imported factors), and
+ * the algorithmic bytes of one hif_apply (the sum over its stages, as hif_profile_read reports
+ * them: factor blocks in the form the apply reads them, index lists and FP64 vectors). */
 typedef struct {
   int32_t levels;
   int32_t root;
@@ -141,6 +143,7 @@ typedef struct {
   int64_t device_bytes;
   int64_t build_mfma_flops;
   double build_mfma_ms;
+  int64_t apply_bytes;
 } hif_info_t;
 hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
 

@@ -411,6 +411,10 @@ hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
     info->device_bytes = handle_device_bytes(h);
     info->build_mfma_flops = h.f.mfma_flops;
     info->build_mfma_ms = h.f.mfma_ms;
+    int64_t ab = h.f.nroot ? h.f.root_bytes : 0;
+    for (const LevelDev& l : h.f.lv)
+      ab += l.cell_bytes[0] + l.cell_bytes[1] + l.group_bytes[0] + l.group_bytes[1];
+    info->apply_bytes = ab;
   });
 }
 

@@ -714,40 +714,26 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
 }
 
 // -------------------------------------------------------------------------- tiled cells --
-// Cells whose blocks do not fit one workgroup's LDS are spread over many workgroups.  The
-// forward sweep writes the new interior values into a scratch vector (not into y), so that
-// every tile of a cell still reads the old y_I; the backward sweep reads them back from there
-// and writes the final interior values into y.
+// Cells with a dense coupling H = A_BI A_II^-1 whose blocks do not fit one workgroup's LDS
+// are spread over many workgroups (link-mode cells of that size use the dense form below).
+// The forward sweep writes the new interior values into a scratch vector (not into y), so
+// that every tile of a cell still reads the old y_I; the backward sweep reads them back from
+// there and writes the final interior values into y.
 //   row tiles:    64 consecutive rows of [L^-1; H] (packed columns are contiguous over rows,
-//                 so each load of a wavefront is coalesced); the 16 wavefronts of the
-//                 workgroup take every 16th column and add up through LDS.
+//                 so each load of a wavefront is coalesced); the wavefronts of the workgroup
+//                 split the columns and add up through LDS.
 //   column tiles: 32 consecutive columns; each wavefront reduces whole columns (contiguous in
-//                 memory) for two outputs.
+//                 memory).
 constexpr int kRowTile = 64;
 constexpr int kColTile = 32;
-#ifndef HIFCN_TILE_THREADS
-#define HIFCN_TILE_THREADS 1024
-#endif
-#ifndef HIFCN_DOT_UNROLL
-#define HIFCN_DOT_UNROLL 8
-#endif
-#ifndef HIFCN_XCD_REMAP
-#define HIFCN_XCD_REMAP 1
-#endif
-constexpr int kTileThreads = HIFCN_TILE_THREADS;
-constexpr int kTileWaves = kTileThreads / 64;
-constexpr int kDotUnroll = HIFCN_DOT_UNROLL;
+constexpr int kDotUnroll = 8;   // matrix loads in flight per lane in the dot products
 
 // Workgroup b of a launch runs on XCD b % 8, and each XCD has its own L2.  Tile b' = xcd_tile(b)
 // gives every XCD one contiguous run of the tile list, so neighbouring tiles of one block, which
 // share the cache lines at their edges, are fetched into the same L2.
 __device__ __forceinline__ int xcd_tile(int b, int g) {
-#if HIFCN_XCD_REMAP
   const int q = g >> 3, rem = g & 7, x = b & 7;
   return x * q + min(x, rem) + (b >> 3);
-#else
-  return b;
-#endif
 }
 
 // sum of elem(j) x_j over j = j0, j0 + step, ... < j1, in that order, with up to U loads of
@@ -767,7 +753,8 @@ __device__ __forceinline__ C strided_dot(int j0, int j1, int step, F elem, const
   return acc;
 }
 
-template <typename S, typename C, int MODE, int TT>
+// Forward: w = L^-1 y_I -> scratch, c_B = H w -> cb.
+template <typename S, typename C, int TT>
 __global__ __launch_bounds__(TT) void k_tfwd_rows(const CellDesc* __restrict__ cd,
                                                    const int4* __restrict__ tiles,
                                                    const int32_t* __restrict__ idx,
@@ -783,12 +770,10 @@ __global__ __launch_bounds__(TT) void k_tfwd_rows(const CellDesc* __restrict__ c
   if (done && *done) return;
   const CellDesc d = cd[t.x];
   const int nI = d.nI, nB = d.nB;
-  const int nrows = MODE ? nI : nI + nB;
+  const int nrows = nI + nB;
   const int r0 = t.y;
-  const int rmax = min(nrows, r0 + kRowTile);
-  const int jmax = min(nI, rmax);  // columns needed by these rows
   const int32_t* gI = idx + d.offI;
-  for (int j = threadIdx.x; j < (MODE ? jmax : nI); j += blockDim.x) ys[j] = (C)y[gI[j]];
+  for (int j = threadIdx.x; j < nI; j += blockDim.x) ys[j] = (C)y[gI[j]];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = r0 + lane;
@@ -824,25 +809,21 @@ __device__ __forceinline__ float wave_reduce(float v) {
   return v;
 }
 
-// Column tiles.  KIND 0 (backward, dense H): x_i = L^-T w - H^T x_B -> y.
-//                KIND 1 (backward, links):   x_i = L^-T u -> y.
-//                KIND 2 (forward, links):    v_i = L^-T w;  c_b = A_BI(b, ib_b) v_ib_b -> cb.
-template <typename S, typename C, int KIND, int TT>
+// Backward: x_I = L^-T w - H^T x_B -> y, with w from the scratch vector.
+template <typename S, typename C, int TT>
 __global__ __launch_bounds__(TT) void k_tcols(const CellDesc* __restrict__ cd,
                                                const int4* __restrict__ tiles,
                                                const int32_t* __restrict__ idx,
                                                const S* __restrict__ vals,
                                                double* __restrict__ y,
                                                const double* __restrict__ wsc,
-                                               double* __restrict__ cb,
                                                const int* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* xs = reinterpret_cast<C*>(smem_raw);
-  __shared__ C vt[kColTile];
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   if (done && *done) return;
   const CellDesc d = cd[t.x];
-  const int nI = d.nI, nB = KIND == 0 ? d.nB : 0;
+  const int nI = d.nI, nB = d.nB;
   C* xb = xs + nI;
   const int c0 = t.y;
   for (int j = c0 + (int)threadIdx.x; j < nI; j += blockDim.x) xs[j] = (C)wsc[t.z + j];
@@ -857,75 +838,10 @@ __global__ __launch_bounds__(TT) void k_tcols(const CellDesc* __restrict__ cd,
     const S* col = v + colstart(i, nI);
     C acc = strided_dot<kDotUnroll>(
         i + lane, nI, 64, [&](int j) { return load_as<C>(col + (j - i)); }, xs);
-    if constexpr (KIND == 0) {
-      const S* hc = v + tl + (int64_t)i * d.nB;
-      acc -= strided_dot<kDotUnroll>(lane, nB, 64, [&](int b) { return load_as<C>(hc + b); }, xb);
-    }
+    const S* hc = v + tl + (int64_t)i * nB;
+    acc -= strided_dot<kDotUnroll>(lane, nB, 64, [&](int b) { return load_as<C>(hc + b); }, xb);
     acc = wave_reduce(acc);
-    if (lane == 0) {
-      if constexpr (KIND == 2) vt[q] = acc;
-      else y[idx[d.offI + i]] = (double)acc;
-    }
-  }
-  if constexpr (KIND == 2) {
-    __syncthreads();
-    const int32_t* ib = idx + d.offC;
-    const S* cw = v + tl;
-    for (int b = threadIdx.x; b < d.nB; b += blockDim.x) {
-      const int i = ib[b];
-      if (i >= c0 && i < c0 + kColTile) cb[d.offCB + b] = (double)(load_as<C>(cw + b) * vt[i - c0]);
-    }
-  }
-}
-
-// Backward, links: t = A_IB x_B (per interior DOF, its links in a fixed order), then
-// u_r = w_r - (L^-1 t)_r over a row tile, in place in the scratch vector.
-template <typename S, typename C, int TT>
-__global__ __launch_bounds__(TT) void k_tbwd_rows1(const CellDesc* __restrict__ cd,
-                                                    const int4* __restrict__ tiles,
-                                                    const int32_t* __restrict__ idx,
-                                                    const S* __restrict__ vals,
-                                                    const double* __restrict__ y,
-                                                    double* __restrict__ wsc,
-                                                    const int* __restrict__ done) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* ts = reinterpret_cast<C*>(smem_raw);
-  __shared__ C red[(TT / 64)][kRowTile];
-  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-  if (done && *done) return;
-  const CellDesc d = cd[t.x];
-  const int nI = d.nI, nB = d.nB;
-  const int r0 = t.y;
-  const int rmax = min(nI, r0 + kRowTile);
-  const S* v = vals + d.offV;
-  const int tl = tri_count(nI);
-  // idx layout after offC: ib[nB], rowptr[nI + 1], blist[nB] (links grouped by interior DOF)
-  const int32_t* rp = idx + d.offC + nB;
-  const int32_t* bl = rp + nI + 1;
-  const int32_t* gB = idx + d.offB;
-  for (int j = threadIdx.x; j < rmax; j += blockDim.x) {
-    C acc = 0;
-    for (int q = rp[j]; q < rp[j + 1]; ++q) {
-      const int b = bl[q];
-      acc += load_as<C>(v + tl + b) * (C)y[gB[b]];
-    }
-    ts[j] = acc;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = r0 + lane;
-  C acc = 0;
-  if (r < nI)
-    acc = strided_dot<kDotUnroll>(
-        wave, r + 1, (TT / 64), [&](int j) { return load_as<C>(v + colstart(j, nI) + (r - j)); },
-        ts);
-  red[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0 && r < nI) {
-    C tot = 0;
-#pragma unroll
-    for (int w = 0; w < (TT / 64); ++w) tot += red[w][lane];
-    wsc[t.z + r] -= (double)tot;
+    if (lane == 0) y[idx[d.offI + i]] = (double)acc;
   }
 }
 
@@ -1294,47 +1210,24 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
   }
 }
 
-// launches of one tiled cell sweep
-int tiled_launches(const LevelDev& L) { return L.cmode ? 2 : 1; }
-
+// One sweep of a tiled level (dense H): row tiles forward, column tiles backward.
 template <typename S, typename C, int TT>
 void launch_tiled_tt(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
-                  double* cb, const int* done, hipStream_t s, TimedSeq& t) {
+                     double* cb, const int* done, hipStream_t s, const StageTimer& t) {
   const int32_t* idx = f.idx.p;
-  const size_t rows_smem = sizeof(C) * (size_t)std::max(1, L.maxI);
-  const size_t cols_smem = sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB);
-  if (fwd) {
-    if (L.cmode) {
-      launch(k_tfwd_rows<S, C, 1, TT>, dim3(L.nrt), dim3(TT), rows_smem, s, t.next(),
-             (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
-             f.wsc.p, cb, done);
-      launch(k_tcols<S, C, 2, TT>, dim3(L.nct), dim3(TT), cols_smem, s, t.next(),
-             (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
-             (const double*)f.wsc.p, cb, done);
-    } else {
-      launch(k_tfwd_rows<S, C, 0, TT>, dim3(L.nrt), dim3(TT), rows_smem, s, t.next(),
-             (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
-             f.wsc.p, cb, done);
-    }
-  } else {
-    if (L.cmode) {
-      launch(k_tbwd_rows1<S, C, TT>, dim3(L.nrt), dim3(TT), rows_smem, s, t.next(),
-             (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals, (const double*)y,
-             f.wsc.p, done);
-      launch(k_tcols<S, C, 1, TT>, dim3(L.nct), dim3(TT), cols_smem, s, t.next(),
-             (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
-             (const double*)f.wsc.p, cb, done);
-    } else {
-      launch(k_tcols<S, C, 0, TT>, dim3(L.nct), dim3(TT), cols_smem, s, t.next(),
-             (const CellDesc*)L.cells.p, (const int4*)L.ctiles.p, idx, vals, y,
-             (const double*)f.wsc.p, cb, done);
-    }
-  }
+  if (fwd)
+    launch(k_tfwd_rows<S, C, TT>, dim3(L.nrt), dim3(TT), sizeof(C) * (size_t)std::max(1, L.maxI),
+           s, t, (const CellDesc*)L.cells.p, (const int4*)L.rtiles.p, idx, vals,
+           (const double*)y, f.wsc.p, cb, done);
+  else
+    launch(k_tcols<S, C, TT>, dim3(L.nct), dim3(TT),
+           sizeof(C) * (size_t)std::max(1, L.maxI + L.maxB), s, t, (const CellDesc*)L.cells.p,
+           (const int4*)L.ctiles.p, idx, vals, y, (const double*)f.wsc.p, done);
 }
 
 template <typename S, typename C>
 void launch_tiled(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
-                  double* cb, const int* done, hipStream_t s, TimedSeq& t) {
+                  double* cb, const int* done, hipStream_t s, const StageTimer& t) {
   switch (L.tthreads) {
     case 256: launch_tiled_tt<S, C, 256>(f, L, fwd, vals, y, cb, done, s, t); break;
     case 512: launch_tiled_tt<S, C, 512>(f, L, fwd, vals, y, cb, done, s, t); break;
@@ -1420,9 +1313,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     const LevelDev& L = f.lv[l];
     if (L.ncell && !(l > 0 && f.lv[l - 1].fuse)) {
       const StageTimer t(prof, l, STAGE_CELL_FWD, done, s);
-      TimedSeq ts(t, tiled_launches(L));
       if (L.cdense) launch_dense_cells<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
-      else if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, ts);
+      else if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t);
     }
@@ -1481,9 +1373,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
     }
     if (L.ncell) {
       const StageTimer t(prof, l, STAGE_CELL_BWD, done, s);
-      TimedSeq ts(t, tiled_launches(L));
       if (L.cdense) launch_dense_cells<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
-      else if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, ts);
+      else if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, false, vals, y, cbl(l), done, s, t);
     }
@@ -1545,12 +1436,8 @@ void set_apply_smem_limits(size_t bytes) {
 #define HIF_SMEM(K) HIF_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(K),           \
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, b))
 #define HIF_SMEM_TILES(S, C, TT)                                                              \
-  HIF_SMEM((k_tfwd_rows<S, C, 0, TT>));                                                       \
-  HIF_SMEM((k_tfwd_rows<S, C, 1, TT>));                                                       \
-  HIF_SMEM((k_tbwd_rows1<S, C, TT>));                                                         \
-  HIF_SMEM((k_tcols<S, C, 0, TT>));                                                           \
-  HIF_SMEM((k_tcols<S, C, 1, TT>));                                                           \
-  HIF_SMEM((k_tcols<S, C, 2, TT>))
+  HIF_SMEM((k_tfwd_rows<S, C, TT>));                                                          \
+  HIF_SMEM((k_tcols<S, C, TT>))
 #define HIF_SMEM_ALL(S, C)                                                                    \
   HIF_SMEM((k_cell_fwd<S, C, false, 0>));                                                     \
   HIF_SMEM((k_cell_bwd<S, C, false, 0>));                                                     \

@@ -104,3 +104,26 @@ def test_multi_launch_stage_timing(gpu_lib):
     torch.cuda.synchronize()
     assert sum(total.values()) < t0.elapsed_time(t1) / 10, total
     h.close()
+
+
+@pytest.mark.parametrize("n,dim,leaf", [(64, 2, 8), (32, 3, 8)])
+def test_apply_bytes_sum_of_stages(n, dim, leaf, gpu_lib):
+    """hif_get_info's apply_bytes is the sum of the bytes every stage reports (fused launches
+    count the stages they run; dense forms count the dense matrices)."""
+    import torch
+    a = gen.grf_coefficient(n, dim, 0.15, 75)
+    h = _factor(a, 0.02, n, dim, leaf, 1e-4, "f32", False)
+    levels = h.info()["levels"]
+    x = torch.tensor(np.random.default_rng(7).normal(size=n ** dim), device="cuda")
+    tot = 0
+    for lev in range(levels + 1):
+        for st in ("cell_fwd", "group_fwd", "root", "group_bwd", "cell_bwd"):
+            if (st == "root") != (lev == levels):
+                continue
+            h.profile_stage(lev, st, True)
+            h.apply(x)
+            p = h.profile_read()
+            h.profile_stage(lev, st, False)
+            tot += p["bytes"] if p["launches"] else 0
+    assert tot == h.info()["apply_bytes"] > 0
+    h.close()
