@@ -153,6 +153,36 @@ __device__ __forceinline__ void load_record(int32_t* dst, const int32_t* __restr
   for (int q = lt; q < n / 4; q += nthr) d4[q] = s4[q];
 }
 
+// Dot products along a line of a factor block: sum over j = j0, j0 + step, ... < j1 of
+// e(o_j) x(j), where the element offsets advance by d, d + dd, d + 2 dd, ... (a packed triangle's
+// rows advance quadratically, everything else linearly), so no term needs a multiply.  Up to U
+// elements and inputs are loaded before their products are added; the additions keep the order
+// of a plain loop.
+template <int U, typename C, typename E, typename X>
+__device__ __forceinline__ C dot_walk(E e, int o, int d, int dd, int j0, int j1, int step, X x) {
+  C acc = 0;
+  int j = j0;
+  for (; j + (U - 1) * step < j1; j += U * step) {
+    C ev[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ev[u] = e(o);
+      xv[u] = x(j + u * step);
+      o += d;
+      d += dd;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += ev[u] * xv[u];
+  }
+  for (; j < j1; j += step) {
+    acc += e(o) * x(j);
+    o += d;
+    d += dd;
+  }
+  return acc;
+}
+constexpr int kLineUnroll = 4;
+
 // Read-only views of the factor blocks: from LDS (packed layouts, ST) or global memory.
 // Tri: packed column-major lower triangle of order n; Col: column-major rows x cols block.
 template <typename S, typename C, bool ST>
@@ -160,10 +190,23 @@ struct Tri {
   const C* l;
   const S* g;
   int n;
-  __device__ __forceinline__ C operator()(int i, int j) const {
-    const int o = colstart(j, n) + (i - j);
+  __device__ __forceinline__ C at(int o) const {
     if constexpr (ST) return l[o];
     else return load_as<C>(g + o);
+  }
+  __device__ __forceinline__ C operator()(int i, int j) const { return at(colstart(j, n) + (i - j)); }
+  // sum over j = j0, j0 + step, ... <= i of (i, j) x(j)
+  template <typename X>
+  __device__ __forceinline__ C row_dot(int i, int j0, int step, X x) const {
+    return dot_walk<kLineUnroll, C>([&](int o) { return at(o); }, colstart(j0, n) + (i - j0),
+                                    step * (n - 1 - j0) - step * (step - 1) / 2, -step * step,
+                                    j0, i + 1, step, x);
+  }
+  // sum over j = j0, j0 + step, ... < n of (j, c) x(j), j0 >= c (column c is contiguous)
+  template <typename X>
+  __device__ __forceinline__ C col_dot(int c, int j0, int step, X x) const {
+    return dot_walk<kLineUnroll, C>([&](int o) { return at(o); }, colstart(c, n) + (j0 - c),
+                                    step, 0, j0, n, step, x);
   }
 };
 template <typename S, typename C, bool ST>
@@ -171,10 +214,22 @@ struct Col {
   const C* l;
   const S* g;
   int rows;
-  __device__ __forceinline__ C operator()(int r, int c) const {
-    const int64_t o = (int64_t)c * rows + r;
+  __device__ __forceinline__ C at(int o) const {
     if constexpr (ST) return l[o];
     else return load_as<C>(g + o);
+  }
+  __device__ __forceinline__ C operator()(int r, int c) const { return at(c * rows + r); }
+  // sum over r = r0, r0 + step, ... < r1 of (r, c) x(r)
+  template <typename X>
+  __device__ __forceinline__ C col_dot(int c, int r0, int r1, int step, X x) const {
+    return dot_walk<kLineUnroll, C>([&](int o) { return at(o); }, c * rows + r0, step, 0, r0, r1,
+                                    step, x);
+  }
+  // sum over c = c0, c0 + step, ... < c1 of (r, c) x(c)
+  template <typename X>
+  __device__ __forceinline__ C row_dot(int r, int c0, int c1, int step, X x) const {
+    return dot_walk<kLineUnroll, C>([&](int o) { return at(o); }, c0 * rows + r, step * rows, 0,
+                                    c0, c1, step, x);
   }
 };
 
@@ -224,9 +279,9 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
     const int o = ob + (int)threadIdx.x / team;
     C acc = 0;
     if (o < nI) {
-      for (int j = part; j <= o; j += team) acc += Li(o, j) * ys[j];
+      acc = Li.row_dot(o, part, team, [&](int j) { return ys[j]; });
     } else if (o < nout) {
-      for (int j = part; j < nI; j += team) acc += H(o - nI, j) * ys[j];
+      acc = H.row_dot(o - nI, part, nI, team, [&](int j) { return ys[j]; });
     }
     acc = team_sum(acc, team);
     if (part == 0 && o < nout) {
@@ -244,7 +299,7 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
       const int o = ob + (int)threadIdx.x / team;
       C acc = 0;
       if (o < nI)
-        for (int j = o + part; j < nI; j += team) acc += Li(j, o) * ws[j];
+        acc = Li.col_dot(o, o + part, team, [&](int j) { return ws[j]; });
       acc = team_sum(acc, team);
       if (part == 0 && o < nI) vs[o] = acc;
     }
@@ -309,8 +364,8 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
       const int o = ob + (int)threadIdx.x / team;
       C acc = 0;
       if (o < nI) {
-        for (int j = o + part; j < nI; j += team) acc += Li(j, o) * xs[j];
-        for (int b = part; b < nB; b += team) acc -= H(b, o) * xb[b];
+        acc = Li.col_dot(o, o + part, team, [&](int j) { return xs[j]; });
+        acc -= H.col_dot(o, part, nB, team, [&](int b) { return xb[b]; });
       }
       acc = team_sum(acc, team);
       if (part == 0 && o < nI) x[gI[o]] = (double)acc;
@@ -318,10 +373,15 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
     return;
   }
   const S* cw = v + tl;
+  // the links of each interior DOF: rowptr (nI + 1) and boundary positions (nB) after ib
+  const int32_t* rp = idx + d.offC + nB;
+  const int32_t* bl = rp + nI + 1;
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {   // t = A_IB x_B
     C acc = 0;
-    for (int b = 0; b < nB; ++b)
-      if (ib[b] == i) acc += (C)(ST ? blk[tl + b] : load_as<C>(cw + b)) * xb[b];
+    for (int q = rp[i]; q < rp[i + 1]; ++q) {
+      const int b = bl[q];
+      acc += (C)(ST ? blk[tl + b] : load_as<C>(cw + b)) * xb[b];
+    }
     ts[i] = acc;
   }
   __syncthreads();
@@ -329,7 +389,7 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
     const int o = ob + (int)threadIdx.x / team;
     C acc = 0;
     if (o < nI)
-      for (int j = part; j <= o; j += team) acc += Li(o, j) * ts[j];
+      acc = Li.row_dot(o, part, team, [&](int j) { return ts[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && o < nI) us[o] = xs[o] - acc;
   }
@@ -338,7 +398,7 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
     const int o = ob + (int)threadIdx.x / team;
     C acc = 0;
     if (o < nI)
-      for (int j = o + part; j < nI; j += team) acc += Li(j, o) * us[j];
+      acc = Li.col_dot(o, o + part, team, [&](int j) { return us[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && o < nI) x[gI[o]] = (double)acc;
   }
@@ -392,9 +452,16 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
   const int32_t* gp = idx + d.offGP;
   const int32_t* slots = gp + n + 1;
   const int32_t* perm = idx + d.offPerm;
-  for (int i = lt; i < n; i += seg) {
+  for (int i = lt; i < n; i += seg) {  // contributions loaded two at a time
     double acc = y[gi_idx[i]];
-    for (int s = gp[i]; s < gp[i + 1]; ++s) acc -= cb[slots[s]];
+    int s = gp[i];
+    const int s1 = gp[i + 1];
+    for (; s + 1 < s1; s += 2) {
+      const double c0 = cb[slots[s]], c1 = cb[slots[s + 1]];
+      acc -= c0;
+      acc -= c1;
+    }
+    if (s < s1) acc -= cb[slots[s]];
     yg[i] = (C)acc;
   }
   __syncthreads();
@@ -404,7 +471,7 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < n)
-      for (int j = part; j <= i; j += team) acc += Lg(i, j) * yg[j];
+      acc = Lg.row_dot(i, part, team, [&](int j) { return yg[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < n) zg[i] = acc;
   }
@@ -414,7 +481,7 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < nr)
-      for (int s = part; s < k; s += team) acc += T(s, i) * zg[perm[nr + s]];
+      acc = T.col_dot(i, part, k, team, [&](int s) { return zg[perm[nr + s]]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < nr) tv[i] = zg[perm[i]] - acc;
   }
@@ -423,7 +490,7 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < nr)
-      for (int j = part; j <= i; j += team) acc += Lr(i, j) * tv[j];
+      acc = Lr.row_dot(i, part, team, [&](int j) { return tv[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < nr) uv[i] = acc;
   }
@@ -432,7 +499,7 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < nr)
-      for (int j = i + part; j < nr; j += team) acc += Lr(j, i) * uv[j];
+      acc = Lr.col_dot(i, i + part, team, [&](int j) { return uv[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < nr) tv[i] = acc;
   }
@@ -442,7 +509,7 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
       const int s = ob + lt / team;
       C acc = 0;
       if (s < k)
-        for (int i = part; i < nr; i += team) acc += T(s, i) * tv[i];
+        acc = T.row_dot(s, part, nr, team, [&](int i) { return tv[i]; });
       acc = team_sum(acc, team);
       if (part == 0 && s < k) y[gi_idx[perm[nr + s]]] = (double)(zg[perm[nr + s]] + acc);
     }
@@ -505,7 +572,7 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < nr)
-      for (int s = part; s < k; s += team) acc += T(s, i) * xg[perm[nr + s]];
+      acc = T.col_dot(i, part, k, team, [&](int s) { return xg[perm[nr + s]]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < nr) tv[i] = acc;
   }
@@ -514,7 +581,7 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < nr)
-      for (int j = part; j <= i; j += team) acc += Lr(i, j) * tv[j];
+      acc = Lr.row_dot(i, part, team, [&](int j) { return tv[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < nr) uv[i] = xg[perm[i]] + acc;
   }
@@ -523,7 +590,7 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < nr)
-      for (int j = i + part; j < nr; j += team) acc += Lr(j, i) * uv[j];
+      acc = Lr.col_dot(i, i + part, team, [&](int j) { return uv[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < nr) tv[i] = acc;
   }
@@ -533,7 +600,7 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
       const int s = ob + lt / team;
       C acc = 0;
       if (s < k)
-        for (int i = part; i < nr; i += team) acc += T(s, i) * tv[i];
+        acc = T.row_dot(s, part, nr, team, [&](int i) { return tv[i]; });
       acc = team_sum(acc, team);
       if (part == 0 && s < k) zg[perm[nr + s]] = xg[perm[nr + s]] - acc;
     }
@@ -546,7 +613,7 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
     const int i = ob + lt / team;
     C acc = 0;
     if (i < n)
-      for (int j = i + part; j < n; j += team) acc += Lg(j, i) * zg[j];
+      acc = Lg.col_dot(i, i + part, team, [&](int j) { return zg[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && i < n) x[gi_idx[i]] = (double)acc;
   }
@@ -585,10 +652,8 @@ __device__ __forceinline__ void root_body(int nr, const int32_t* __restrict__ ri
   C* ys = Ls + (staged ? round_up((int)tri_count(nr), 8) : 0);
   C* ws = ys + nr;
   if (staged) stage_flat(Ls, Lv, (int)tri_count(nr), threadIdx.x, blockDim.x);
-  auto Lr = [&](int i, int j) -> C {
-    const int o = colstart(j, nr) + (i - j);
-    return staged ? Ls[o] : load_as<C>(Lv + o);
-  };
+  const Tri<S, C, true> Lst{Ls, Lv, nr};
+  const Tri<S, C, false> Lgl{Ls, Lv, nr};
   for (int i = threadIdx.x; i < nr; i += blockDim.x) ys[i] = (C)y[ridx[i]];
   __syncthreads();
   // `team` lanes share each output's dot product
@@ -599,7 +664,8 @@ __device__ __forceinline__ void root_body(int nr, const int32_t* __restrict__ ri
     const int o = ob + (int)threadIdx.x / team;
     C acc = 0;
     if (o < nr)
-      for (int j = part; j <= o; j += team) acc += Lr(o, j) * ys[j];
+      acc = staged ? Lst.row_dot(o, part, team, [&](int j) { return ys[j]; })
+                   : Lgl.row_dot(o, part, team, [&](int j) { return ys[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && o < nr) ws[o] = acc;
   }
@@ -608,7 +674,8 @@ __device__ __forceinline__ void root_body(int nr, const int32_t* __restrict__ ri
     const int o = ob + (int)threadIdx.x / team;
     C acc = 0;
     if (o < nr)
-      for (int j = o + part; j < nr; j += team) acc += Lr(j, o) * ws[j];
+      acc = staged ? Lst.col_dot(o, o + part, team, [&](int j) { return ws[j]; })
+                   : Lgl.col_dot(o, o + part, team, [&](int j) { return ws[j]; });
     acc = team_sum(acc, team);
     if (part == 0 && o < nr) y[ridx[o]] = (double)acc;
   }
@@ -1494,7 +1561,9 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
 namespace {
 // Record of one cell: the descriptor with record-relative index offsets, then I, B and (link
 // mode) the interior positions of the couplings.
-int cell_record_len(const CellDesc& d) { return round_up(8 + d.nI + d.nB + (d.mode ? d.nB : 0), 4); }
+int cell_record_len(const CellDesc& d) {
+  return round_up(8 + d.nI + d.nB + (d.mode ? 2 * d.nB + d.nI + 1 : 0), 4);
+}
 void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& idx) {
   CellDesc e = d;
   e.offI = 8;
@@ -1503,8 +1572,8 @@ void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& 
   std::memcpy(r, &e, sizeof(CellDesc));
   for (int i = 0; i < d.nI; ++i) r[8 + i] = idx[d.offI + i];
   for (int b = 0; b < d.nB; ++b) r[8 + d.nI + b] = idx[d.offB + b];
-  if (d.mode)
-    for (int b = 0; b < d.nB; ++b) r[8 + d.nI + d.nB + b] = idx[d.offC + b];
+  if (d.mode)  // ib[nB], then the links grouped by interior DOF: rowptr[nI + 1], blist[nB]
+    for (int q = 0; q < 2 * d.nB + d.nI + 1; ++q) r[8 + d.nI + d.nB + q] = idx[d.offC + q];
 }
 // Record of one group: the descriptor, then DOF ids, pivot order, gather pointers and slots.
 int group_record_len(const GroupDesc& g, const std::vector<int32_t>& idx) {
