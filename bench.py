@@ -231,6 +231,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="fisher2d-256")
     ap.add_argument("--store", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--leaf", type=int, default=0, help="leaf box size (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the error check")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
@@ -280,6 +281,8 @@ def main(argv=None):
         return 0
 
     w = gen.workload(args.workload)
+    if args.leaf:
+        w.leaf = args.leaf
     dev = torch.device("cuda:0")
     a_dev = torch.tensor(w.a_cells, dtype=torch.float64, device=dev)
     u0 = torch.tensor(w.u0.ravel(), dtype=torch.float64, device=dev)

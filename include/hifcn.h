@@ -132,7 +132,9 @@ size_t hif_factor_bytes(hif_handle_t h);
  * (large cells, the root and the dense forms of blocks too large for one workgroup, Sec. 2.2):
  * its algorithmic flops and the summed duration of those kernels (0 for imported factors), and
  * the algorithmic bytes of one hif_apply (the sum over its stages, as hif_profile_read reports
- * them: factor blocks in the form the apply reads them, index lists and FP64 vectors). */
+ * them: factor blocks in the form the apply reads them, index lists and FP64 vectors), and the
+ * level from which the apply runs as one dense matrix (the group steps of that level and every
+ * stage above it, the root included; reported as the root stage), or -1. */
 typedef struct {
   int32_t levels;
   int32_t root;
@@ -144,6 +146,8 @@ typedef struct {
   int64_t build_mfma_flops;
   double build_mfma_ms;
   int64_t apply_bytes;
+  int32_t top_level;
+  int32_t reserved;
 } hif_info_t;
 hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
 

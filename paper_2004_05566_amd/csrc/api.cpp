@@ -203,6 +203,8 @@ int64_t handle_device_bytes(const Handle& h) {
   add(h.st); add(h.step_iters); add(h.step_relres);
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);
+  add(f.tvals); add(f.tgid); add(f.tgptr); add(f.tgslot); add(f.tdtiles); add(f.tscat);
+  add(f.tddoff); add(f.twsc);
   add(f.rddoff); add(f.rdtiles); add(f.rscat);
   for (const LevelDev& l : f.lv) {
     add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.crec); add(l.grec); add(l.frec);
@@ -411,10 +413,18 @@ hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
     info->device_bytes = handle_device_bytes(h);
     info->build_mfma_flops = h.f.mfma_flops;
     info->build_mfma_ms = h.f.mfma_ms;
-    int64_t ab = h.f.nroot ? h.f.root_bytes : 0;
-    for (const LevelDev& l : h.f.lv)
-      ab += l.cell_bytes[0] + l.cell_bytes[1] + l.group_bytes[0] + l.group_bytes[1];
+    // with a dense top, the levels above it and its groups run inside the dense matrix
+    const FactorDev& f = h.f;
+    const int last = f.top >= 0 ? f.top : (int)f.lv.size() - 1;
+    int64_t ab = f.top >= 0 ? f.top_bytes : (f.nroot ? f.root_bytes : 0);
+    for (int l = 0; l <= last; ++l) {
+      const LevelDev& L = f.lv[l];
+      ab += L.cell_bytes[0] + L.cell_bytes[1];
+      if (l < f.top || f.top < 0) ab += L.group_bytes[0] + L.group_bytes[1];
+    }
     info->apply_bytes = ab;
+    info->top_level = f.top;
+    info->reserved = 0;
   });
 }
 
@@ -467,7 +477,9 @@ hif_status_t hif_profile_read(hif_handle_t hh, hif_stage_prof_t* out) {
     // a fused launch carries the bytes of every stage it runs
     int64_t bytes = 0;
     const int nlev = (int)h.f.lv.size();
-    if (p.stage == STAGE_ROOT) {
+    if (p.stage == STAGE_ROOT && h.f.top >= 0) {
+      bytes = h.f.top_bytes;
+    } else if (p.stage == STAGE_ROOT) {
       bytes = h.f.root_bytes;
       if (h.f.root_fused)
         bytes += h.f.lv[nlev - 1].group_bytes[0] + h.f.lv[nlev - 1].group_bytes[1];

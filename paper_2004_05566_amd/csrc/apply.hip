@@ -926,10 +926,12 @@ __global__ __launch_bounds__(TT) void k_tcols(const CellDesc* __restrict__ cd,
 //   DR_CELL_BWD   x_I = A_II^-1 (y_I - A_IB x_B) -> y
 //   DR_GROUP_FWD  the group step G (y_g less the cell contributions) -> scratch
 //   DR_ROOT       partial sums of A_r^-1 y_r over one column range -> scratch
+//   DR_TOP        partial sums of the dense top M_k (y_k less the contributions of level k's
+//                 cells) over one column range -> scratch
 //   column tiles: the backward group step G^T x_g -> scratch
 // Dense group and root results go back to y by a scatter list once every tile has read its
 // inputs.
-enum { DR_CELL_FWD = 0, DR_CELL_BWD, DR_GROUP_FWD, DR_ROOT };
+enum { DR_CELL_FWD = 0, DR_CELL_BWD, DR_GROUP_FWD, DR_ROOT, DR_TOP };
 constexpr int kDenseColsPerTile = 32;
 
 __host__ __device__ inline int dense_ld(int n) { return (n + 31) & ~31; }
@@ -940,6 +942,8 @@ __global__ __launch_bounds__(TT) void k_dense_rows(const CellDesc* __restrict__ 
                                                    const int64_t* __restrict__ ddoff,
                                                    const int4* __restrict__ tiles, int span,
                                                    int nroot, const int32_t* __restrict__ ridx,
+                                                   const int32_t* __restrict__ gptr,
+                                                   const int32_t* __restrict__ gslot,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
                                                    const S* __restrict__ dv,
@@ -994,6 +998,12 @@ __global__ __launch_bounds__(TT) void k_dense_rows(const CellDesc* __restrict__ 
     for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) {
       double a = y[gi[j]];
       for (int q = gp[j]; q < gp[j + 1]; ++q) a -= cb[slots[q]];
+      xs[j - c0] = (C)a;
+    }
+  } else if constexpr (KIND == DR_TOP) {
+    for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) {
+      double a = y[ridx[j]];
+      for (int q = gptr[j]; q < gptr[j + 1]; ++q) a -= cb[gslot[q]];
       xs[j - c0] = (C)a;
     }
   } else {
@@ -1312,7 +1322,8 @@ void launch_dense_cells_tt(const FactorDev& f, const LevelDev& L, bool fwd, cons
   auto k = fwd ? k_dense_rows<S, C, DR_CELL_FWD, TT> : k_dense_rows<S, C, DR_CELL_BWD, TT>;
   launch(k, dim3(L.ncdt), dim3(TT), sm, s, t, (const CellDesc*)L.cells.p,
          (const GroupDesc*)nullptr, (const int64_t*)L.cddoff.p, (const int4*)L.cdtiles.p,
-         kDenseSpanAll, 0, (const int32_t*)nullptr, (const int32_t*)f.idx.p, vals,
+         kDenseSpanAll, 0, (const int32_t*)nullptr, (const int32_t*)nullptr,
+         (const int32_t*)nullptr, (const int32_t*)f.idx.p, vals,
          reinterpret_cast<const S*>(f.dvals.p), y, cb, f.wsc.p, done);
 }
 
@@ -1346,7 +1357,8 @@ void launch_dense_groups(const FactorDev& f, const LevelDev& L, bool fwd, double
     launch(k_dense_rows<S, C, DR_GROUP_FWD, kDenseThreads>, dim3(L.ngrt), dim3(kDenseThreads),
            sm, s, ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)L.groups.p,
            (const int64_t*)L.gddoff.p, (const int4*)L.grtiles.p, kDenseSpanAll, 0,
-           (const int32_t*)nullptr, (const int32_t*)f.idx.p, (const S*)nullptr, dv, y,
+           (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
+           (const int32_t*)f.idx.p, (const S*)nullptr, dv, y,
            const_cast<double*>(cb), f.wsc.p, done);
   else
     launch(k_dense_gcols<S, C, kDenseThreads>, dim3(L.ngct), dim3(kDenseThreads), sm, s,
@@ -1364,9 +1376,26 @@ void launch_dense_root(const FactorDev& f, double* y, const int* done, hipStream
   launch(k_dense_rows<S, C, DR_ROOT, kDenseThreads>, dim3(f.nrdt), dim3(kDenseThreads), sm, s,
          ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)nullptr,
          (const int64_t*)f.rddoff.p, (const int4*)f.rdtiles.p, f.rspan, f.nroot,
-         (const int32_t*)f.idx.p + f.offRootIdx, (const int32_t*)f.idx.p, (const S*)nullptr,
+         (const int32_t*)f.idx.p + f.offRootIdx, (const int32_t*)nullptr, (const int32_t*)nullptr,
+         (const int32_t*)f.idx.p, (const S*)nullptr,
          reinterpret_cast<const S*>(f.dvals.p), y, (double*)nullptr, f.wsc.p, done);
   launch_scatter(f.rscat, f.nrsc, f, y, done, s, ts.next());
+}
+
+template <typename S, typename C>
+void launch_dense_top(const FactorDev& f, double* y, const double* cb, const int* done,
+                      hipStream_t s, const StageTimer& t) {
+  TimedSeq ts(t, 2);
+  const size_t sm = sizeof(C) * (size_t)std::max(1, std::min(f.ntop, f.tspan));
+  launch(k_dense_rows<S, C, DR_TOP, kDenseThreads>, dim3(f.ntdt), dim3(kDenseThreads), sm, s,
+         ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)nullptr,
+         (const int64_t*)f.tddoff.p, (const int4*)f.tdtiles.p, f.tspan, f.ntop,
+         (const int32_t*)f.tgid.p, (const int32_t*)f.tgptr.p, (const int32_t*)f.tgslot.p,
+         (const int32_t*)f.idx.p, (const S*)nullptr, reinterpret_cast<const S*>(f.tvals.p), y,
+         const_cast<double*>(cb), f.twsc.p, done);
+  const int grid = std::max(1, std::min(1024, (f.ntsc + 255) / 256));
+  launch(k_dense_scatter, dim3(grid), dim3(256), 0, s, ts.next(), (const int4*)f.tscat.p, f.ntsc,
+         (const double*)f.twsc.p, y, done);
 }
 
 template <typename S, typename C>
@@ -1386,6 +1415,11 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t);
     }
     if (!L.ngroup) continue;
+    if (l == f.top) {  // this level's groups, every level above and the root: one matrix
+      const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
+      launch_dense_top<S, C>(f, y, cbl(l), done, s, t);
+      break;
+    }
     if (L.fuse) {  // + the cell stage of level l+1
       const LevelDev& P = f.lv[l + 1];
       const FusePlan fp = fuse_plan<C>(L, &P, 0);
@@ -1414,7 +1448,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
              p.team, vals, y, (const double*)cbl(l), done);
     }
   }
-  if (f.nroot && !f.root_fused) {
+  if (f.nroot && !f.root_fused && f.top < 0) {
     const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
     if (f.root_tiled) {
       launch_dense_root<S, C>(f, y, done, s, t);
@@ -1425,9 +1459,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
              vals + f.offRootV, y, (int)rs, done);
     }
   }
-  for (int l = nlev - 1; l >= 0; --l) {
+  for (int l = f.top >= 0 ? f.top : nlev - 1; l >= 0; --l) {
     const LevelDev& L = f.lv[l];
-    if (L.ngroup && !(l == nlev - 1 && f.root_fused)) {
+    if (L.ngroup && l != f.top && !(l == nlev - 1 && f.root_fused)) {
       const StageTimer t(prof, l, STAGE_GROUP_BWD, done, s);
       if (L.gtiled) {
         launch_dense_groups<S, C>(f, L, false, y, cbl(l), done, s, t);

@@ -106,9 +106,10 @@ int64_t job_scratch(const DenseJob& j) {
   return 3 * n * n + 2 * nr * n + nr * nr + nr * k + nr * n;  // Zp, K, G'; X1, V; L_s^-1; T^T
 }
 
-template <typename S>
+// S: storage type of the stored blocks; O: type of the dense forms written to `out`.
+template <typename S, typename O>
 void run_batch(FactorDev& f, const std::vector<DenseJob>& jobs, size_t b0, size_t b1,
-               int64_t wtot, hipStream_t s, FrontStats* st) {
+               int64_t wtot, O* out, hipStream_t s, FrontStats* st) {
   DevBuf<double> w(std::max<int64_t>(1, wtot), s);
   std::vector<Prep> prep;
   std::vector<Store> store;
@@ -171,15 +172,14 @@ void run_batch(FactorDev& f, const std::vector<DenseJob>& jobs, size_t b0, size_
   gemm_batched(g2, s, st);
   gemm_batched(g3, s, st);
   gemm_batched(g4, s, st);
-  hipLaunchKernelGGL(k_dense_store<S>, dim3(gx, store.size()), dim3(kB), 0, s,
-                     (const Store*)ds.p, (const int32_t*)f.idx.p, (const double*)w.p,
-                     reinterpret_cast<S*>(f.dvals.p));
+  hipLaunchKernelGGL(k_dense_store<O>, dim3(gx, store.size()), dim3(kB), 0, s,
+                     (const Store*)ds.p, (const int32_t*)f.idx.p, (const double*)w.p, out);
   HIF_CHECK(hipGetLastError());
   HIF_CHECK(hipStreamSynchronize(s));  // the job lists go out of scope
 }
 
-template <typename S>
-void build_dense_t(FactorDev& f, const std::vector<DenseJob>& jobs, hipStream_t s) {
+template <typename S, typename O>
+void build_dense_t(FactorDev& f, const std::vector<DenseJob>& jobs, O* out, hipStream_t s) {
   constexpr int64_t kBatch = int64_t(1) << 28;  // FP64 scratch per batch (2 GiB)
   FrontStats st;
   size_t b0 = 0;
@@ -187,13 +187,13 @@ void build_dense_t(FactorDev& f, const std::vector<DenseJob>& jobs, hipStream_t 
   for (size_t q = 0; q < jobs.size(); ++q) {
     const int64_t need = job_scratch(jobs[q]);
     if (q > b0 && (acc + need > kBatch || q - b0 == 65535)) {  // grid.y counts the jobs
-      run_batch<S>(f, jobs, b0, q, acc, s, &st);
+      run_batch<S, O>(f, jobs, b0, q, acc, out, s, &st);
       b0 = q;
       acc = 0;
     }
     acc += need;
   }
-  if (b0 < jobs.size()) run_batch<S>(f, jobs, b0, jobs.size(), acc, s, &st);
+  if (b0 < jobs.size()) run_batch<S, O>(f, jobs, b0, jobs.size(), acc, out, s, &st);
   f.mfma_flops += st.flops;
   f.mfma_ms += st.ms;
 }
@@ -203,9 +203,25 @@ void build_dense_t(FactorDev& f, const std::vector<DenseJob>& jobs, hipStream_t 
 void build_dense_forms(FactorDev& f, const std::vector<DenseJob>& jobs, hipStream_t s) {
   if (jobs.empty()) return;
   switch (f.store) {
-    case HIF_STORE_F64: build_dense_t<double>(f, jobs, s); break;
-    case HIF_STORE_F32: build_dense_t<float>(f, jobs, s); break;
-    case HIF_STORE_BF16: build_dense_t<bf16_t>(f, jobs, s); break;
+    case HIF_STORE_F64:
+      build_dense_t<double>(f, jobs, reinterpret_cast<double*>(f.dvals.p), s);
+      break;
+    case HIF_STORE_F32:
+      build_dense_t<float>(f, jobs, reinterpret_cast<float*>(f.dvals.p), s);
+      break;
+    case HIF_STORE_BF16:
+      build_dense_t<bf16_t>(f, jobs, reinterpret_cast<bf16_t*>(f.dvals.p), s);
+      break;
+  }
+}
+
+void build_dense_forms_f64(FactorDev& f, const std::vector<DenseJob>& jobs, double* out,
+                           hipStream_t s) {
+  if (jobs.empty()) return;
+  switch (f.store) {
+    case HIF_STORE_F64: build_dense_t<double>(f, jobs, out, s); break;
+    case HIF_STORE_F32: build_dense_t<float>(f, jobs, out, s); break;
+    case HIF_STORE_BF16: build_dense_t<bf16_t>(f, jobs, out, s); break;
   }
 }
 

@@ -348,6 +348,7 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
     for (int i = 0; i < fh.nroot; ++i) N = std::max<int64_t>(N, fh.idx[fh.offRootIdx + i] + 1);
     setup_tiling(fd, cells, groups, fh.idx, s);
     setup_fusion(fd, cells, groups, fh.idx, N, s);
+    setup_dense_top(fd, cells, groups, fh.idx, N, s);
   }
   size_t worst = 0;
   apply_smem_need(fd, &worst);

@@ -101,6 +101,18 @@ struct FactorDev {
   int rspan = 0, nrdt = 0, nrsc = 0;
   DevBuf<int64_t> rddoff;
   DevBuf<int4> rdtiles, rscat;
+  // Dense top: the stages from the group step of level `top` up to the root and back, applied
+  // as one symmetric matrix on that level's group DOFs (tvals, column-major, leading dimension
+  // ntop rounded up to 32); -1: none.  Inputs: DOF ids (tgid) less the contributions in the
+  // slots tgslot[tgptr[i] .. tgptr[i + 1]); row tiles over column ranges of tspan, partial sums
+  // in twsc added up by the write-back list tscat.
+  int top = -1, ntop = 0, tspan = 0, ntdt = 0, ntsc = 0;
+  int64_t top_bytes = 0;
+  DevBuf<unsigned char> tvals;
+  DevBuf<int32_t> tgid, tgptr, tgslot;
+  DevBuf<int4> tdtiles, tscat;
+  DevBuf<int64_t> tddoff;
+  DevBuf<double> twsc;
   // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
   int64_t mfma_flops = 0;
   double mfma_ms = 0;
@@ -172,6 +184,14 @@ void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                   const std::vector<std::vector<GroupDesc>>& groups,
                   const std::vector<int32_t>& idx, hipStream_t s);
 
+// Choose the level from which the rest of the apply runs as one dense matrix, form it and lay
+// it out (no dense top when no level's matrix stays within the element budget
+// HIFCN_DENSE_TOP, default 6M; 0 disables).  Call after setup_fusion (it turns the fused root
+// off when it takes over the root).
+void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                     const std::vector<std::vector<GroupDesc>>& groups,
+                     const std::vector<int32_t>& idx, int64_t N, hipStream_t s);
+
 // One block put in dense form (column-major n x n, leading dimension ld, at dst in dvals).
 struct DenseJob {
   int32_t kind;      // 0: M = L^-T L^-1 from a packed L^-1 at src; 1: the step of a group whose
@@ -183,6 +203,9 @@ struct DenseJob {
 // Form the dense blocks (FP64 on the matrix cores, stored in the factor's precision); dvals
 // must be allocated and vals final.
 void build_dense_forms(FactorDev& f, const std::vector<DenseJob>& jobs, hipStream_t s);
+// The same products in FP64, written column-major to out + dst (leading dimension ld).
+void build_dense_forms_f64(FactorDev& f, const std::vector<DenseJob>& jobs, double* out,
+                           hipStream_t s);
 // Decide which group stages run together with the next level's cell stage (and the last level
 // with the root) and upload the ownership lists; call after setup_tiling.
 void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,

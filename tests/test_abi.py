@@ -58,7 +58,8 @@ def test_info_struct_layout():
     """hif_info_t: 2 x i32, 2 x i64, 2 x i32, 2 x i64, f64 (no padding surprises)."""
     import ctypes
     from paper_2004_05566_amd import hifcn
-    assert ctypes.sizeof(hifcn._Info) == 64
+    assert ctypes.sizeof(hifcn._Info) == 72
     assert hifcn._Info.apply_bytes.offset == 56
+    assert hifcn._Info.top_level.offset == 64
     assert hifcn._Info.device_bytes.offset == 32
     assert hifcn._Info.build_mfma_ms.offset == 48

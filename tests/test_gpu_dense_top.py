@@ -1,0 +1,93 @@
+"""Dense top: the stages from some level's group step up to the root and back, applied as one
+symmetric matrix formed at factor time.
+
+The same factor with HIFCN_DENSE_TOP=0 runs every stage; both apply the same operator, multiplied
+out differently, so they agree to rounding.  The CN tests against the oracle elsewhere run with
+the dense top on (the default).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cn, fd, phif
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("2d-n32-m8", 32, 2, 8), ("2d-n64-m8", 64, 2, 8), ("2d-n127-m8", 127, 2, 8),
+         ("2d-n40-m4", 40, 2, 4), ("3d-n12-m4", 12, 3, 4), ("3d-n16-m4", 16, 3, 4)]
+
+
+def _factor(a, dt, n, dim, leaf, eps, store, top):
+    import torch
+    from paper_2004_05566_amd import hifcn
+    a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
+    old = os.environ.pop("HIFCN_DENSE_TOP", None)
+    if top is not None:
+        os.environ["HIFCN_DENSE_TOP"] = str(top)
+    try:
+        return hifcn.factor(a_dev, dt, n, dim, eps, store=store, leaf=leaf)
+    finally:
+        os.environ.pop("HIFCN_DENSE_TOP", None)
+        if old is not None:
+            os.environ["HIFCN_DENSE_TOP"] = old
+
+
+def _top(h):
+    return h.info()["top_level"]
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_dense_top_matches_stagewise(case, store, gpu_lib):
+    import torch
+    name, n, dim, leaf = case
+    print(f"[case] {name} {store}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.1, 81)
+    h1 = _factor(a, 0.05, n, dim, leaf, 1e-4, store, None)
+    h0 = _factor(a, 0.05, n, dim, leaf, 1e-4, store, 0)
+    assert _top(h1) >= 0 and _top(h0) == -1
+    rng = np.random.default_rng(8)
+    for _ in range(2):
+        x = torch.tensor(rng.normal(size=n ** dim), device="cuda")
+        y1, y0 = h1.apply(x), h0.apply(x)
+        tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}[store]
+        assert torch.linalg.norm(y1 - y0) <= tol * torch.linalg.norm(y0)
+    h1.close()
+    h0.close()
+
+
+@pytest.mark.parametrize("top", [1 << 15, 1 << 18, 1 << 21])
+def test_dense_top_budgets_cn_matches_oracle(top, gpu_lib):
+    """Budgets that put the dense top at different levels (down to level 0 on a 64^2 grid)."""
+    import torch
+    n, dim, leaf, eps, dt = 64, 2, 8, 1e-6, 0.05
+    a = gen.grf_coefficient(n, dim, 0.15, 82)
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, dim, leaf, eps)
+    u0 = gen.bumps(n, dim, 3, 83)
+    react = (1, 1.0, 1.0)
+    us, its, _ = cn.cn_solve(A, B, u0, dt, 2, lambda r: phif.phif_apply(F, r), 1e-12, react)
+    h = _factor(a, dt, n, dim, leaf, eps, "f64", top)
+    print("top level", h.info()["top_level"], flush=True)
+    u = torch.tensor(u0.ravel(), device="cuda")
+    gits, _ = h.cn_solve(u, 2, rtol=1e-12, reaction=react)
+    assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])
+    assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)
+    h.close()
+
+
+def test_dense_top_level_follows_budget(gpu_lib):
+    """A larger element budget moves the dense top down (never up); on a 64^2 grid the budgets
+    cover at least two levels."""
+    n, dim, leaf = 64, 2, 8
+    a = gen.grf_coefficient(n, dim, 0.15, 84)
+    levels = []
+    for top in (1 << 10, 1 << 14, 1 << 17, 1 << 20, 1 << 23):
+        h = _factor(a, 0.05, n, dim, leaf, 1e-6, "f64", top)
+        levels.append(h.info()["top_level"])
+        h.close()
+    key = [lv if lv >= 0 else 99 for lv in levels]
+    assert key == sorted(key, reverse=True), levels
+    assert len({lv for lv in levels if lv >= 0}) >= 2, levels

@@ -2,7 +2,8 @@
 groups with the root) against the unfused launch sequence and the oracle.
 
 HIFCN_NO_FUSE=1 at factor time keeps one launch per stage.  Both sequences do the same
-arithmetic with different lane splits of the dot products, so they agree to rounding.
+arithmetic with different lane splits of the dot products, so they agree to rounding.  The dense
+top (HIFCN_DENSE_TOP) is off here so that every level's stages run.
 """
 import os
 
@@ -22,15 +23,17 @@ def _factor(a, dt, n, dim, leaf, eps, store, fuse):
     import torch
     from paper_2004_05566_amd import hifcn
     a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
-    old = os.environ.pop("HIFCN_NO_FUSE", None)
+    old = {k: os.environ.pop(k, None) for k in ("HIFCN_NO_FUSE", "HIFCN_DENSE_TOP")}
     if not fuse:
         os.environ["HIFCN_NO_FUSE"] = "1"
+    os.environ["HIFCN_DENSE_TOP"] = "0"  # every level's stages run (the fusions are tested)
     try:
         return hifcn.factor(a_dev, dt, n, dim, eps, store=store, leaf=leaf)
     finally:
-        os.environ.pop("HIFCN_NO_FUSE", None)
-        if old is not None:
-            os.environ["HIFCN_NO_FUSE"] = old
+        for k, v in old.items():
+            os.environ.pop(k, None)
+            if v is not None:
+                os.environ[k] = v
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
