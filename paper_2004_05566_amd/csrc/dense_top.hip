@@ -43,18 +43,15 @@ template <> __device__ __forceinline__ void st_v<bf16_t>(bf16_t* p, double v) {
   p->bits = f32_to_bf16_bits((float)v);
 }
 
-// Gc[cls(base + r)][base + c] = G_g(r, c) for every group (G_g column-major, order n).
-struct GScatter { int64_t src; int32_t n, base; };
-__global__ __launch_bounds__(kB) void k_top_scatter_g(const GScatter* __restrict__ t,
-                                                      const int32_t* __restrict__ cls,
-                                                      const double* __restrict__ gf, int nl,
-                                                      double* __restrict__ Gc) {
-  const GScatter g = t[blockIdx.y];
+// Cn[p][q] = C[cls(p)][cls(q)]: from the order (first, S, R) back to the natural one.
+__global__ __launch_bounds__(kB) void k_top_to_natural(int nl, const int32_t* __restrict__ cls,
+                                                       const double* __restrict__ C,
+                                                       double* __restrict__ Cn) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)g.n * g.n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)nl * nl;
        e += step) {
-    const int c = (int)(e / g.n), r = (int)(e - (int64_t)c * g.n);
-    Gc[(int64_t)cls[g.base + r] * nl + g.base + c] = gf[g.src + e];
+    const int p = (int)(e / nl), q = (int)(e - (int64_t)p * nl);
+    Cn[e] = C[(int64_t)cls[p] * nl + cls[q]];
   }
 }
 
@@ -304,32 +301,37 @@ DevBuf<double> build_top(FactorDev& f, const std::vector<std::vector<CellDesc>>&
     } else {
       assemble_c<S>(f, cells[l + 1], idx, sp, Mnext.p, where, C.p, s, &st);
     }
-    // G_l (dense group forms), rows in the order of C: Gc[cls(p)][q] = G[p][q]
+    // C back in the natural order, then M_l = G^T Cn G one group block at a time (G is
+    // block diagonal: group q's block sits at rows and columns gbase[q] ..)
+    DevBuf<int32_t> dcls;
+    upload_vec(dcls, sp.cls, s);
+    DevBuf<double> Cn((size_t)nl * nl, s);
+    hipLaunchKernelGGL(k_top_to_natural, dim3(grid_for((int64_t)nl * nl)), dim3(kB), 0, s, nl,
+                       (const int32_t*)dcls.p, (const double*)C.p, Cn.p);
+    HIF_CHECK(hipGetLastError());
     const std::vector<GroupDesc>& gs = groups[l];
     std::vector<DenseJob> gj;
-    std::vector<GScatter> gsc;
-    int64_t go = 0, maxg = 1;
+    std::vector<GemmTask> tw, tm;
+    int64_t go = 0;
     for (size_t q = 0; q < gs.size(); ++q) {
       gj.push_back({1, gs[q].n, gs[q].nr, gs[q].n, (int64_t)gs[q].offV, go, gs[q].offPerm, 0});
-      gsc.push_back({go, gs[q].n, sp.gbase[q]});
       go += (int64_t)gs[q].n * gs[q].n;
-      maxg = std::max<int64_t>(maxg, (int64_t)gs[q].n * gs[q].n);
     }
     DevBuf<double> gf((size_t)std::max<int64_t>(1, go), s);
-    build_dense_forms_f64(f, gj, gf.p, s);
-    DevBuf<int32_t> dcls;
-    DevBuf<GScatter> dgs;
-    upload_vec(dcls, sp.cls, s);
-    upload_vec(dgs, gsc, s);
-    DevBuf<double> Gc((size_t)nl * nl, s);
-    HIF_CHECK(hipMemsetAsync(Gc.p, 0, sizeof(double) * (size_t)nl * nl, s));
-    hipLaunchKernelGGL(k_top_scatter_g, dim3(grid_for(maxg), gsc.size()), dim3(kB), 0, s,
-                       (const GScatter*)dgs.p, (const int32_t*)dcls.p, (const double*)gf.p, nl,
-                       Gc.p);
-    HIF_CHECK(hipGetLastError());
+    build_dense_forms_f64(f, gj, gf.p, s);  // column-major G_g = row-major G_g^T
     DevBuf<double> W((size_t)nl * nl, s), Ml((size_t)nl * nl, s);
-    gemm_batched({{C.p, Gc.p, W.p, nl, nl, nl, nl, nl, nl, 0, 0, 0, 1.0, 0, 0}}, s, &st);
-    gemm_batched({{Gc.p, W.p, Ml.p, nl, nl, nl, nl, nl, nl, 0, 0, 1, 1.0, 0, 0}}, s, &st);
+    go = 0;
+    for (size_t q = 0; q < gs.size(); ++q) {
+      const int ng = gs[q].n, b = sp.gbase[q];
+      // W[:, g] = Cn[:, g] G_g  (op(B) = (G_g^T)^T)
+      tw.push_back({Cn.p + b, gf.p + go, W.p + b, nl, ng, nl, nl, ng, ng, 1, 0, 0, 1.0, 0, 0});
+      // M[g, :] = G_g^T W[g, :]
+      tm.push_back({gf.p + go, W.p + (int64_t)b * nl, Ml.p + (int64_t)b * nl, ng, nl, nl, ng, nl,
+                    ng, 0, 0, 0, 1.0, 0, 0});
+      go += (int64_t)ng * ng;
+    }
+    gemm_batched(tw, s, &st);
+    gemm_batched(tm, s, &st);
     HIF_CHECK(hipStreamSynchronize(s));
     Mnext = std::move(Ml);
   }
@@ -345,7 +347,9 @@ void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cel
                      const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
   f.top = -1;
   const int nlev = (int)f.lv.size();
-  int64_t budget = 6 << 20;  // elements of M_k
+  // entries of M_k: one pass over 40M FP32 entries (160 MiB) costs about what the three
+  // latency-bound launches of one more level do (measured on the 1024^2 grid)
+  int64_t budget = int64_t(40) << 20;
   if (const char* e = std::getenv("HIFCN_DENSE_TOP")) budget = std::atoll(e);
   if (budget <= 0 || nlev == 0 || f.nroot == 0) return;
   // the lowest level whose M_k fits, with every level from it up to the top eligible

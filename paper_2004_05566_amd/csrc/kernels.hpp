@@ -186,8 +186,8 @@ void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
 
 // Choose the level from which the rest of the apply runs as one dense matrix, form it and lay
 // it out (no dense top when no level's matrix stays within the element budget
-// HIFCN_DENSE_TOP, default 6M; 0 disables).  Call after setup_fusion (it turns the fused root
-// off when it takes over the root).
+// HIFCN_DENSE_TOP, default 40M entries; 0 disables).  Call after setup_fusion (it
+// turns the fused root off when it takes over the root).
 void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                      const std::vector<std::vector<GroupDesc>>& groups,
                      const std::vector<int32_t>& idx, int64_t N, hipStream_t s);

@@ -72,11 +72,14 @@ def estimate_bytes(n: int, dim: int, store: str) -> int:
 
     The build keeps the factor's blocks in FP64 (up to about 48 entries per DOF for the 2D
     workloads at eps = 1e-4 and 3x that in 3D) besides their stored copy, plus the PCG
-    workspace and coefficients (about 12 FP64 vectors)."""
+    workspace and coefficients (about 12 FP64 vectors).  The dense top of the apply holds at
+    most 40M entries, and fewer than (N/4)^2 (N/4 bounds the separator DOFs of the levels it
+    covers), formed through about six FP64 matrices of its size."""
     N = n ** dim
     entries = 48 if dim == 2 else 144
     eb = {"f64": 8, "f32": 4, "bf16": 2}[store]
-    return int(N * (entries * (8 + eb) + 12 * 8) + (8 << 20))
+    top = min(40 << 20, (N // 4) ** 2)
+    return int(N * (entries * (8 + eb) + 12 * 8) + top * (eb + 48) + (8 << 20))
 
 
 @dataclass

@@ -151,10 +151,12 @@ def test_tiled_3d_factor_cn_matches_oracle(store, gpu_lib):
     assert max(abs(int(x) - int(y)) for x, y in zip(gits, its)) <= 1, (list(gits), its)
 
 
-def test_3d_two_levels_large_groups_match_oracle(gpu_lib):
+@pytest.mark.parametrize("top", ["0", None], ids=["stagewise", "dense-top"])
+def test_3d_two_levels_large_groups_match_oracle(top, gpu_lib):
     """32^3 grid, two levels: the level-1 faces (up to ~230 DOFs) exceed the per-group LDS
     budget and run in dense form (one matrix per group step, tiled over many workgroups); the
-    root is dense too."""
+    root is dense too.  With the default budget the dense top takes over from level 1."""
+    import os
     import torch
     n, dim, leaf, eps, dt = 32, 3, 8, 1e-4, 0.02
     a = gen.grf_coefficient(n, dim, 0.15, 51)
@@ -162,7 +164,16 @@ def test_3d_two_levels_large_groups_match_oracle(gpu_lib):
     F = phif.phif_build(A, n, dim, leaf, eps)
     u0 = gen.bumps(n, dim, 4, 52)
     us, its, _ = cn.cn_solve(A, B, u0, dt, 2, lambda r: phif.phif_apply(F, r), 1e-12)
-    h = _factor(a, dt, n, dim, leaf, eps, "f32")
+    old = os.environ.pop("HIFCN_DENSE_TOP", None)
+    if top is not None:
+        os.environ["HIFCN_DENSE_TOP"] = top
+    try:
+        h = _factor(a, dt, n, dim, leaf, eps, "f32")
+    finally:
+        os.environ.pop("HIFCN_DENSE_TOP", None)
+        if old is not None:
+            os.environ["HIFCN_DENSE_TOP"] = old
+    assert (h.info()["top_level"] >= 0) == (top is None)
     u = torch.tensor(u0.ravel(), device="cuda")
     gits, _ = h.cn_solve(u, 2, rtol=1e-12)
     assert np.linalg.norm(u.cpu().numpy() - us[-1]) <= 1e-10 * np.linalg.norm(us[-1])

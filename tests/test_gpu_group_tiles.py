@@ -20,19 +20,24 @@ CASES = [("2d-n32-m8", 32, 2, 8), ("2d-n127-m8", 127, 2, 8), ("2d-n40-m4", 40, 2
          ("3d-n12-m4", 12, 3, 4), ("3d-n16-m4", 16, 3, 4)]
 
 
-def _factor(a, dt, n, dim, leaf, eps, store, tiles):
+def _factor(a, dt, n, dim, leaf, eps, store, tiles, top="0"):
+    """top: HIFCN_DENSE_TOP (off by default here, so that every level's group stages run;
+    None keeps the library's default)."""
     import torch
     from paper_2004_05566_amd import hifcn
     a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
-    old = os.environ.pop("HIFCN_GROUP_TILES", None)
+    old = {k: os.environ.pop(k, None) for k in ("HIFCN_GROUP_TILES", "HIFCN_DENSE_TOP")}
     if tiles:
         os.environ["HIFCN_GROUP_TILES"] = "1"
+    if top is not None:
+        os.environ["HIFCN_DENSE_TOP"] = top
     try:
         return hifcn.factor(a_dev, dt, n, dim, eps, store=store, leaf=leaf)
     finally:
-        os.environ.pop("HIFCN_GROUP_TILES", None)
-        if old is not None:
-            os.environ["HIFCN_GROUP_TILES"] = old
+        for k, v in old.items():
+            os.environ.pop(k, None)
+            if v is not None:
+                os.environ[k] = v
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
@@ -106,13 +111,14 @@ def test_multi_launch_stage_timing(gpu_lib):
     h.close()
 
 
+@pytest.mark.parametrize("top", [None, "0"], ids=["top", "notop"])
 @pytest.mark.parametrize("n,dim,leaf", [(64, 2, 8), (32, 3, 8)])
-def test_apply_bytes_sum_of_stages(n, dim, leaf, gpu_lib):
+def test_apply_bytes_sum_of_stages(n, dim, leaf, top, gpu_lib):
     """hif_get_info's apply_bytes is the sum of the bytes every stage reports (fused launches
     count the stages they run; dense forms count the dense matrices)."""
     import torch
     a = gen.grf_coefficient(n, dim, 0.15, 75)
-    h = _factor(a, 0.02, n, dim, leaf, 1e-4, "f32", False)
+    h = _factor(a, 0.02, n, dim, leaf, 1e-4, "f32", False, top)
     levels = h.info()["levels"]
     x = torch.tensor(np.random.default_rng(7).normal(size=n ** dim), device="cuda")
     tot = 0

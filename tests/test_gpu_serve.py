@@ -152,13 +152,13 @@ def test_server_admission_by_memory(gpu_lib):
     from paper_2004_05566_amd.serve import Server, estimate_bytes
     small = _req(32, 1e-2, 401, 2)
     big = _req(128, 1e-2, 411, 2)
-    budget = estimate_bytes(64, 2, "f32")
+    one = estimate_bytes(32, 2, "f32")
+    budget = (3 * one) // 2
+    assert estimate_bytes(128, 2, "f32") > budget
     srv = Server(hbm_budget_bytes=budget, max_slots=4)
     f_big = srv.submit(big)
     with pytest.raises(MemoryError):
         f_big.result(timeout=10)
-    one = estimate_bytes(32, 2, "f32")
-    assert 2 * one > budget >= one
     futs = [srv.submit(small)] + [srv.submit(_req(32, 1e-2, 421 + 10 * i, 2)) for i in range(3)]
     res = [f.result(timeout=60) for f in futs]
     srv.close()
