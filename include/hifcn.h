@@ -69,6 +69,19 @@ typedef struct { double rtol; int32_t maxit; int32_t warm_start; } hif_cg_opts_t
 hif_status_t hif_factor(const double* a_cells_dev, double dt, const hif_grid_t* grid,
                         double eps, hif_store_t store, void* hip_stream, hif_handle_t* out);
 
+/* Build options.  dense_top: the largest number of entries the dense top of the apply may hold
+ * (the stages from some level's group step up to the root and back, formed at build time as
+ * one symmetric matrix; see hif_get_info's top_level): < 0 the library's default (or the
+ * HIFCN_DENSE_TOP environment variable), 0 none.  Forming it costs build time that a solve of
+ * few steps may not win back.  reserved: must be 0. */
+typedef struct { int64_t dense_top; int64_t reserved[3]; } hif_factor_opts_t;
+
+/* hif_factor with options (opts may be NULL: the defaults).  Errors as hif_factor, and
+ * HIF_ERR_ARG for nonzero reserved fields. */
+hif_status_t hif_factor_ex(const double* a_cells_dev, double dt, const hif_grid_t* grid,
+                           double eps, hif_store_t store, const hif_factor_opts_t* opts,
+                           void* hip_stream, hif_handle_t* out);
+
 /* Test fixture: like hif_factor, but the factor blocks are read from `blob_host` (nbytes, host
  * memory) written in the HIFB format below instead of being built, so that hif_apply can be
  * checked independently of the build.  Synchronises `hip_stream`.

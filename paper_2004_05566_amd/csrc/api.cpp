@@ -220,17 +220,27 @@ using namespace hifcn;
 
 extern "C" {
 
-hif_status_t hif_factor(const double* a_cells_dev, double dt, const hif_grid_t* grid, double eps,
-                        hif_store_t store, void* hip_stream, hif_handle_t* out) {
+hif_status_t hif_factor_ex(const double* a_cells_dev, double dt, const hif_grid_t* grid,
+                           double eps, hif_store_t store, const hif_factor_opts_t* opts,
+                           void* hip_stream, hif_handle_t* out) {
   if (out) *out = nullptr;
   return guarded([&] {
     HIF_REQUIRE(out != nullptr, HIF_ERR_ARG, "NULL output handle");
     HIF_REQUIRE(store >= HIF_STORE_F64 && store <= HIF_STORE_BF16, HIF_ERR_ARG, "bad store");
+    if (opts)
+      for (int64_t r : opts->reserved)
+        HIF_REQUIRE(r == 0, HIF_ERR_ARG, "reserved option fields must be 0");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     auto h = make_handle(a_cells_dev, dt, grid, eps, s);
+    h->f.top_budget = opts ? opts->dense_top : -1;
     gpu_build(*h, a_cells_dev, store, s);
     *out = reinterpret_cast<hif_handle_t>(h.release());
   });
+}
+
+hif_status_t hif_factor(const double* a_cells_dev, double dt, const hif_grid_t* grid, double eps,
+                        hif_store_t store, void* hip_stream, hif_handle_t* out) {
+  return hif_factor_ex(a_cells_dev, dt, grid, eps, store, nullptr, hip_stream, out);
 }
 
 hif_status_t hif_import(const double* a_cells_dev, double dt, const hif_grid_t* grid,

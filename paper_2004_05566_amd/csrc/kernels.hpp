@@ -106,6 +106,7 @@ struct FactorDev {
   // ntop rounded up to 32); -1: none.  Inputs: DOF ids (tgid) less the contributions in the
   // slots tgslot[tgptr[i] .. tgptr[i + 1]); row tiles over column ranges of tspan, partial sums
   // in twsc added up by the write-back list tscat.
+  int64_t top_budget = -1;  // entries allowed (set before the build; < 0: default)
   int top = -1, ntop = 0, tspan = 0, ntdt = 0, ntsc = 0;
   int64_t top_bytes = 0;
   DevBuf<unsigned char> tvals;
@@ -186,7 +187,7 @@ void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
 
 // Choose the level from which the rest of the apply runs as one dense matrix, form it and lay
 // it out (no dense top when no level's matrix stays within the element budget
-// HIFCN_DENSE_TOP, default 40M entries; 0 disables).  Call after setup_fusion (it
+// f.top_budget, else HIFCN_DENSE_TOP, else 10M entries; 0 disables).  Call after setup_fusion (it
 // turns the fused root off when it takes over the root).
 void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                      const std::vector<std::vector<GroupDesc>>& groups,

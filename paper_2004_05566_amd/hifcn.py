@@ -48,6 +48,10 @@ class _Info(ctypes.Structure):
                 ("top_level", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class _FactorOpts(ctypes.Structure):
+    _fields_ = [("dense_top", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+
+
 class _StageProf(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("stage", ctypes.c_int32),
                 ("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_int64)]
@@ -58,6 +62,8 @@ STAGES = {"cell_fwd": 0, "group_fwd": 1, "root": 2, "group_bwd": 3, "cell_bwd": 
 _vp = ctypes.c_void_p
 _lib.hif_factor.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), ctypes.c_double,
                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.hif_factor_ex.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), ctypes.c_double,
+                               ctypes.c_int, ctypes.POINTER(_FactorOpts), _vp, ctypes.POINTER(_vp)]
 _lib.hif_import.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), _vp, ctypes.c_size_t,
                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]
 _lib.hif_apply.argtypes = [_vp, _vp, _vp, _vp]
@@ -75,13 +81,13 @@ _lib.hif_profile_read.argtypes = [_vp, ctypes.POINTER(_StageProf)]
 _lib.hif_destroy.argtypes = [_vp]
 _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
-for _f in ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
+for _f in ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
            "cn_batch_step", "hif_get_info", "hif_profile_stage", "hif_profile_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTS = ("hif_factor", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
-           "cn_batch_step", "hif_factor_bytes", "hif_get_info", "hif_profile_stage", "hif_profile_read",
-           "hif_destroy", "hif_last_error")
+EXPORTS = ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step",
+           "cn_solve", "cn_batch_step", "hif_factor_bytes", "hif_get_info", "hif_profile_stage",
+           "hif_profile_read", "hif_destroy", "hif_last_error")
 
 
 def _check(status: int):
@@ -220,12 +226,21 @@ def cn_batch_step(handles, states, reactions, rtols, maxits, streams):
 
 
 def factor(a_cells, dt: float, n: int, dim: int, eps: float, store: str = "f32",
-           leaf: int = 8, stream=None) -> Handle:
-    """hif_factor: build the PHIF factor on the GPU."""
+           leaf: int = 8, stream=None, dense_top=None) -> Handle:
+    """hif_factor (hif_factor_ex when dense_top is given): build the PHIF factor on the GPU.
+
+    dense_top: entries allowed for the dense top of the apply (0: none; None: default)."""
     h = ctypes.c_void_p()
     g = _grid(n, dim, leaf)
-    _check(_lib.hif_factor(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g), float(eps),
-                           STORE[store], _stream(stream), ctypes.byref(h)))
+    if dense_top is None:
+        _check(_lib.hif_factor(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g),
+                               float(eps), STORE[store], _stream(stream), ctypes.byref(h)))
+    else:
+        o = _FactorOpts()
+        o.dense_top = int(dense_top)
+        _check(_lib.hif_factor_ex(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g),
+                                  float(eps), STORE[store], ctypes.byref(o), _stream(stream),
+                                  ctypes.byref(h)))
     return Handle(h, n, dim)
 
 

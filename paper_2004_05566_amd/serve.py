@@ -73,12 +73,12 @@ def estimate_bytes(n: int, dim: int, store: str) -> int:
     The build keeps the factor's blocks in FP64 (up to about 48 entries per DOF for the 2D
     workloads at eps = 1e-4 and 3x that in 3D) besides their stored copy, plus the PCG
     workspace and coefficients (about 12 FP64 vectors).  The dense top of the apply holds at
-    most 40M entries, and fewer than (N/4)^2 (N/4 bounds the separator DOFs of the levels it
+    most 10M entries, and fewer than (N/4)^2 (N/4 bounds the separator DOFs of the levels it
     covers), formed through about six FP64 matrices of its size."""
     N = n ** dim
     entries = 48 if dim == 2 else 144
     eb = {"f64": 8, "f32": 4, "bf16": 2}[store]
-    top = min(40 << 20, (N // 4) ** 2)
+    top = min(10 << 20, (N // 4) ** 2)
     return int(N * (entries * (8 + eb) + 12 * 8) + top * (eb + 48) + (8 << 20))
 
 
@@ -107,9 +107,12 @@ class Server:
     submit() returns a concurrent.futures.Future resolved with a Result (or the error)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 32, builders: int = 2,
-                 device: int = 0, paused: bool = False, lanes: int = 4):
+                 device: int = 0, paused: bool = False, lanes: int = 4, dense_top: int = 0):
         import torch
         self.device = torch.device("cuda", device)
+        # the factors' dense top (hif_factor_ex): off by default, since forming it costs more
+        # build time than a request's few steps win back
+        self.dense_top = dense_top
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self._cv = threading.Condition()
@@ -204,7 +207,8 @@ class Server:
                 self.device, non_blocking=False)
             u = torch.as_tensor(np.ascontiguousarray(r.u0, dtype=np.float64).ravel()).to(
                 self.device, non_blocking=False)
-            h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf, stream=s)
+            h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf, stream=s,
+                             dense_top=self.dense_top)
             s.synchronize()  # u is ready for the slot's stream, a may be released
             del a
         return h, u

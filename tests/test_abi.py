@@ -43,6 +43,20 @@ def test_error_path_without_gpu_work():
     lib.hif_destroy(None)
 
 
+def test_factor_options_errors_without_gpu_work():
+    from paper_2004_05566_amd import hifcn
+    lib = hifcn.raw_library()
+    h = ctypes.c_void_p(123)
+    g = hifcn._Grid()
+    g.dim = 2
+    o = hifcn._FactorOpts()
+    o.reserved[1] = 7
+    st = lib.hif_factor_ex(None, 0.1, ctypes.byref(g), 1e-3, 1, ctypes.byref(o), None,
+                           ctypes.byref(h))
+    assert st == hifcn.HIF_ERR_ARG and not h.value
+    assert b"reserved" in lib.hif_last_error()
+
+
 def test_batch_step_argument_errors_without_gpu_work():
     from paper_2004_05566_amd import hifcn
     lib = hifcn.raw_library()

@@ -91,3 +91,27 @@ def test_dense_top_level_follows_budget(gpu_lib):
     key = [lv if lv >= 0 else 99 for lv in levels]
     assert key == sorted(key, reverse=True), levels
     assert len({lv for lv in levels if lv >= 0}) >= 2, levels
+
+
+def test_factor_option_sets_the_budget(gpu_lib):
+    """hif_factor_ex's dense_top takes precedence over the environment variable."""
+    import torch
+    from paper_2004_05566_amd import hifcn
+    n = 64
+    a = torch.tensor(gen.grf_coefficient(n, 2, 0.15, 85), dtype=torch.float64, device="cuda")
+    old = os.environ.pop("HIFCN_DENSE_TOP", None)
+    try:
+        os.environ["HIFCN_DENSE_TOP"] = "0"
+        h1 = hifcn.factor(a, 0.05, n, 2, 1e-6, store="f32", leaf=8, dense_top=1 << 22)
+        os.environ.pop("HIFCN_DENSE_TOP")
+        h0 = hifcn.factor(a, 0.05, n, 2, 1e-6, store="f32", leaf=8, dense_top=0)
+    finally:
+        os.environ.pop("HIFCN_DENSE_TOP", None)
+        if old is not None:
+            os.environ["HIFCN_DENSE_TOP"] = old
+    assert h1.info()["top_level"] >= 0 and h0.info()["top_level"] == -1
+    x = torch.randn(n * n, dtype=torch.float64, device="cuda")
+    y1, y0 = h1.apply(x), h0.apply(x)
+    assert torch.linalg.norm(y1 - y0) <= 1e-5 * torch.linalg.norm(y0)
+    h1.close()
+    h0.close()

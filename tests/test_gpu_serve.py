@@ -21,12 +21,13 @@ def _req(n, dt, seed, nsteps, reaction=(1, 1.0, 1.0), store="f32", eps=1e-4):
 
 
 def _alone(r):
-    """The request run by itself through the single-solve entry points."""
+    """The request run by itself through the single-solve entry points (with the factor options
+    the Server uses: no dense top)."""
     import torch
     from paper_2004_05566_amd import hifcn
     a = torch.tensor(r.a_cells, dtype=torch.float64, device="cuda:0")
     u = torch.tensor(r.u0.ravel(), dtype=torch.float64, device="cuda:0")
-    h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf)
+    h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf, dense_top=0)
     its, rel = h.cn_solve(u, r.nsteps, rtol=r.rtol, maxit=r.maxit, reaction=r.reaction)
     h.close()
     return u.cpu().numpy().reshape((r.n,) * r.dim), its, rel
@@ -40,7 +41,7 @@ def test_batch_step_equals_single_steps(gpu_lib):
     handles, states, streams = [], [], []
     for r in reqs:
         a = torch.tensor(r.a_cells, dtype=torch.float64, device="cuda:0")
-        handles.append(hifcn.factor(a, r.dt, r.n, 2, r.eps, store=r.store))
+        handles.append(hifcn.factor(a, r.dt, r.n, 2, r.eps, store=r.store, dense_top=0))
         states.append(torch.tensor(r.u0.ravel(), dtype=torch.float64, device="cuda:0"))
         streams.append(torch.cuda.Stream())
     torch.cuda.synchronize()
@@ -83,7 +84,7 @@ def test_batch_step_reports_per_solve_no_convergence(gpu_lib):
     hs, us, ss = [], [], []
     for r in reqs:
         a = torch.tensor(r.a_cells, dtype=torch.float64, device="cuda:0")
-        hs.append(hifcn.factor(a, r.dt, r.n, 2, r.eps))
+        hs.append(hifcn.factor(a, r.dt, r.n, 2, r.eps, dense_top=0))
         us.append(torch.tensor(r.u0.ravel(), dtype=torch.float64, device="cuda:0"))
         ss.append(torch.cuda.Stream())
     its, rel, sts = hifcn.cn_batch_step(hs, us, [r.reaction for r in reqs], [1e-14, 1e-8],
