@@ -147,7 +147,9 @@ size_t hif_factor_bytes(hif_handle_t h);
  * the algorithmic bytes of one hif_apply (the sum over its stages, as hif_profile_read reports
  * them: factor blocks in the form the apply reads them, index lists and FP64 vectors), and the
  * level from which the apply runs as one dense matrix (the group steps of that level and every
- * stage above it, the root included; reported as the root stage), or -1. */
+ * stage above it, the root included; reported as the root stage), or -1.  top_fold: 1 when
+ * the backward cell stage of that level takes the dense top's results straight from its
+ * partial sums (no separate write-back launch), else 0. */
 typedef struct {
   int32_t levels;
   int32_t root;
@@ -160,7 +162,7 @@ typedef struct {
   double build_mfma_ms;
   int64_t apply_bytes;
   int32_t top_level;
-  int32_t reserved;
+  int32_t top_fold;
 } hif_info_t;
 hif_status_t hif_get_info(hif_handle_t h, hif_info_t* info);
 

@@ -204,7 +204,7 @@ int64_t handle_device_bytes(const Handle& h) {
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);
   add(f.tvals); add(f.tgid); add(f.tgptr); add(f.tgslot); add(f.tdtiles); add(f.tscat);
-  add(f.tddoff); add(f.twsc);
+  add(f.tddoff); add(f.twsc); add(f.tpos);
   add(f.rddoff); add(f.rdtiles); add(f.rscat);
   for (const LevelDev& l : f.lv) {
     add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.crec); add(l.grec); add(l.frec);
@@ -434,7 +434,7 @@ hif_status_t hif_get_info(hif_handle_t hh, hif_info_t* info) {
     }
     info->apply_bytes = ab;
     info->top_level = f.top;
-    info->reserved = 0;
+    info->top_fold = f.top >= 0 && f.tfold ? 1 : 0;
   });
 }
 

@@ -233,6 +233,24 @@ struct Col {
   }
 };
 
+// Results of the dense top read by the backward cell stage of its level in place of the
+// boundary values in y (the write-back launch is then not needed).  Per cell: the position among
+// the top's DOFs of each boundary DOF (pos) and `ne` further top DOFs that lie on no cell's
+// boundary (crossings of separators), as (position, DOF id) pairs that this cell writes to y;
+// part: the top's partial sums (nch ranges of n).
+struct TopIn {
+  const int32_t* pos = nullptr;
+  const int32_t* ext = nullptr;
+  int ne = 0;
+  const double* part = nullptr;
+  int nch = 0, n = 0;
+  __device__ double sum(int i) const {
+    double s = 0;
+    for (int c = 0; c < nch; ++c) s += part[(int64_t)c * n + i];
+    return s;
+  }
+};
+
 // ------------------------------------------------------------------------------ cell stages --
 // Sum over the `team` adjacent lanes that share one output (team a power of two <= 64).
 template <typename C>
@@ -333,7 +351,8 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
 template <typename S, typename C, bool ST, int MODE>
 __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* __restrict__ idx,
                                               const S* __restrict__ vals, double* __restrict__ x,
-                                              int blk_elems, int team, unsigned char* smem_raw) {
+                                              int blk_elems, int team, unsigned char* smem_raw,
+                                              const TopIn& top = TopIn{}) {
   C* sm = reinterpret_cast<C*>(smem_raw);
   const int nI = d.nI, nB = d.nB;
   constexpr int mode = MODE;
@@ -346,12 +365,38 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
   C* us = ts + nI;
   int* ib = reinterpret_cast<int*>(us + nI);
   const int32_t* gI = idx + d.offI;
+  const int nBy = top.pos ? 0 : nB;  // boundary values read from y
+  // the first boundary DOF of each lane: its partial sums are loaded before the block is staged
+  constexpr int kTopPre = 8;
+  double tp[kTopPre];
+  const bool pre = top.pos && top.nch <= kTopPre && (int)threadIdx.x < nB;
+  if (pre) {
+    const int i = top.pos[threadIdx.x];
+#pragma unroll
+    for (int c = 0; c < kTopPre; ++c) tp[c] = c < top.nch ? top.part[(int64_t)c * top.n + i] : 0.0;
+  }
   if constexpr (ST) {
-    stage_gather(blk, v, tl + (mode ? nB : nB * nI), x, gI, nI, xs, idx + d.offB, nB, xb,
+    stage_gather(blk, v, tl + (mode ? nB : nB * nI), x, gI, nI, xs, idx + d.offB, nBy, xb,
                  threadIdx.x, blockDim.x);
   } else {
     for (int i = threadIdx.x; i < nI; i += blockDim.x) xs[i] = (C)x[gI[i]];
-    for (int b = threadIdx.x; b < nB; b += blockDim.x) xb[b] = (C)x[idx[d.offB + b]];
+    for (int b = threadIdx.x; b < nBy; b += blockDim.x) xb[b] = (C)x[idx[d.offB + b]];
+  }
+  if (top.pos) {  // the boundary values are the dense top's results: add up its partial sums
+    for (int b = threadIdx.x; b < nB; b += blockDim.x) {
+      double s = 0;
+      if (pre && b == (int)threadIdx.x) {
+#pragma unroll
+        for (int c = 0; c < kTopPre; ++c)
+          if (c < top.nch) s += tp[c];  // the order of TopIn::sum
+      } else {
+        s = top.sum(top.pos[b]);
+      }
+      xb[b] = (C)s;
+      x[idx[d.offB + b]] = s;  // every cell on a separator writes the same sum
+    }
+    for (int e = threadIdx.x; e < top.ne; e += blockDim.x)
+      x[top.ext[2 * e + 1]] = top.sum(top.ext[2 * e]);
   }
   const Tri<S, C, ST> Li{blk, v, nI};
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
@@ -409,7 +454,9 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
                                                   const S* __restrict__ vals,
                                                   double* __restrict__ x,
                                                   const int* __restrict__ done, int blk_elems,
-                                                  int team) {
+                                                  int team, const int32_t* __restrict__ tpos,
+                                                  int tstride, const double* __restrict__ tpart,
+                                                  int tnch, int tn) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
@@ -417,7 +464,12 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
   __syncthreads();
   if (dn) return;
   const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
-  cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride);
+  TopIn top;
+  if (tpos) {  // per cell: ne, (position, id) x ne, then one position per boundary DOF
+    const int32_t* r = tpos + (int64_t)blockIdx.x * tstride;
+    top = TopIn{r + tstride - d.nB, r + 1, r[0], tpart, tnch, tn};
+  }
+  cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride, top);
 }
 
 // ----------------------------------------------------------------------------- group stages --
@@ -1282,8 +1334,11 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
            L.cstride, vals, y, cb, done, p.blk_elems, p.seg);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
+    const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
-           L.cstride, vals, y, done, p.blk_elems, p.seg);
+           L.cstride, vals, y, done, p.blk_elems, p.seg,
+           fold ? (const int32_t*)f.tpos.p : (const int32_t*)nullptr, f.tpstride,
+           (const double*)f.twsc.p, (f.ntop + f.tspan - 1) / std::max(1, f.tspan), f.ntop);
   }
 }
 
@@ -1385,7 +1440,7 @@ void launch_dense_root(const FactorDev& f, double* y, const int* done, hipStream
 template <typename S, typename C>
 void launch_dense_top(const FactorDev& f, double* y, const double* cb, const int* done,
                       hipStream_t s, const StageTimer& t) {
-  TimedSeq ts(t, 2);
+  TimedSeq ts(t, f.tfold ? 1 : 2);
   const size_t sm = sizeof(C) * (size_t)std::max(1, std::min(f.ntop, f.tspan));
   launch(k_dense_rows<S, C, DR_TOP, kDenseThreads>, dim3(f.ntdt), dim3(kDenseThreads), sm, s,
          ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)nullptr,
@@ -1393,6 +1448,7 @@ void launch_dense_top(const FactorDev& f, double* y, const double* cb, const int
          (const int32_t*)f.tgid.p, (const int32_t*)f.tgptr.p, (const int32_t*)f.tgslot.p,
          (const int32_t*)f.idx.p, (const S*)nullptr, reinterpret_cast<const S*>(f.tvals.p), y,
          const_cast<double*>(cb), f.twsc.p, done);
+  if (f.tfold) return;  // the backward cell stage of the level reads the partial sums
   const int grid = std::max(1, std::min(1024, (f.ntsc + 255) / 256));
   launch(k_dense_scatter, dim3(grid), dim3(256), 0, s, ts.next(), (const int4*)f.tscat.p, f.ntsc,
          (const double*)f.twsc.p, y, done);

@@ -431,10 +431,54 @@ void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cel
   f.top_bytes = (int64_t)eb * n * n + 8 * (2 * (int64_t)n + ns + 2 * (int64_t)nch * n) +
                 4 * (3 * (int64_t)n + 1 + ns);
   f.root_fused = false;
+  // When the level's cells run one workgroup each and their boundaries cover every top DOF, the
+  // backward cell stage adds up the partial sums itself and writes them to y.
+  f.tfold = false;
+  const LevelDev& Lk = f.lv[k];
+  if (!Lk.tiled && !Lk.cdense && !std::getenv("HIFCN_NO_TOP_FOLD")) {
+    std::vector<int32_t> at(N, -1);
+    for (int i = 0; i < n; ++i) at[ids[i]] = i;
+    const size_t nc = cells[k].size();
+    int maxB = 1;
+    for (const CellDesc& c : cells[k]) maxB = std::max(maxB, c.nB);
+    std::vector<char> hit(n, 0);
+    bool ok = true;
+    for (size_t c = 0; c < nc && ok; ++c)
+      for (int b = 0; b < cells[k][c].nB && ok; ++b) {
+        const int i = at[idx[cells[k][c].offB + b]];
+        ok = i >= 0;
+        if (ok) hit[i] = 1;
+      }
+    // top DOFs on no cell's boundary (where separators cross): dealt out over the cells
+    std::vector<std::vector<int32_t>> ext(nc);
+    for (int i = 0, e = 0; i < n && ok; ++i)
+      if (!hit[i]) ext[e++ % nc].push_back(i);
+    size_t maxE = 0;
+    for (const auto& v : ext) maxE = std::max(maxE, v.size());
+    // record per cell: ne, (position, id) x maxE, positions of the boundary DOFs at the end
+    const int stride = 1 + 2 * (int)maxE + maxB;
+    std::vector<int32_t> pos(nc * (size_t)stride, 0);
+    for (size_t c = 0; c < nc && ok; ++c) {
+      int32_t* r = pos.data() + c * stride;
+      r[0] = (int32_t)ext[c].size();
+      for (size_t e = 0; e < ext[c].size(); ++e) {
+        r[1 + 2 * e] = ext[c][e];
+        r[2 + 2 * e] = ids[ext[c][e]];
+      }
+      const CellDesc& d = cells[k][c];
+      for (int b = 0; b < d.nB; ++b) r[stride - d.nB + b] = at[idx[d.offB + b]];
+    }
+    if (ok) {
+      f.tpos.upload(pos, s);
+      f.tpstride = stride;
+      f.tfold = true;
+      f.top_bytes += 4 * (int64_t)pos.size();
+    }
+  }
   HIF_CHECK(hipStreamSynchronize(s));
   if (std::getenv("HIFCN_BUILD_LOG"))
-    std::fprintf(stderr, "[hifcn build] dense top from level %d: %d DOFs, %d row tiles\n", k, n,
-                 f.ntdt);
+    std::fprintf(stderr, "[hifcn build] dense top from level %d: %d DOFs, %d row tiles%s\n", k,
+                 n, f.ntdt, f.tfold ? ", write-back in the cell stage" : "");
 }
 
 }  // namespace hifcn

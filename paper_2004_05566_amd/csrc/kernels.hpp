@@ -114,6 +114,12 @@ struct FactorDev {
   DevBuf<int4> tdtiles, tscat;
   DevBuf<int64_t> tddoff;
   DevBuf<double> twsc;
+  // tfold: the backward cell stage of level `top` takes its boundary values from the partial
+  // sums (and writes them to y) instead of a write-back launch; tpos: per cell of that level,
+  // the top position of each boundary DOF (stride tpstride)
+  bool tfold = false;
+  int tpstride = 0;
+  DevBuf<int32_t> tpos;
   // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
   int64_t mfma_flops = 0;
   double mfma_ms = 0;

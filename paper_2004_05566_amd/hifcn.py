@@ -45,7 +45,7 @@ class _Info(ctypes.Structure):
                 ("N", ctypes.c_int64), ("store", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("build_mfma_flops", ctypes.c_int64),
                 ("build_mfma_ms", ctypes.c_double), ("apply_bytes", ctypes.c_int64),
-                ("top_level", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("top_level", ctypes.c_int32), ("top_fold", ctypes.c_int32)]
 
 
 class _FactorOpts(ctypes.Structure):
@@ -189,7 +189,8 @@ class Handle:
         return {"levels": i.levels, "root": i.root, "entries": i.entries, "N": i.N,
                 "store": i.store, "dim": i.dim, "device_bytes": i.device_bytes,
                 "build_mfma_flops": i.build_mfma_flops, "build_mfma_ms": i.build_mfma_ms,
-                "apply_bytes": i.apply_bytes, "top_level": i.top_level}
+                "apply_bytes": i.apply_bytes, "top_level": i.top_level,
+                "top_fold": i.top_fold}
 
     def close(self):
         if self._h:

@@ -19,17 +19,20 @@ CASES = [("2d-n32-m8", 32, 2, 8), ("2d-n64-m8", 64, 2, 8), ("2d-n127-m8", 127, 2
          ("2d-n40-m4", 40, 2, 4), ("3d-n12-m4", 12, 3, 4), ("3d-n16-m4", 16, 3, 4)]
 
 
-def _factor(a, dt, n, dim, leaf, eps, store, top):
+def _factor(a, dt, n, dim, leaf, eps, store, top, fold=True):
     import torch
     from paper_2004_05566_amd import hifcn
     a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
     old = os.environ.pop("HIFCN_DENSE_TOP", None)
     if top is not None:
         os.environ["HIFCN_DENSE_TOP"] = str(top)
+    if not fold:
+        os.environ["HIFCN_NO_TOP_FOLD"] = "1"
     try:
         return hifcn.factor(a_dev, dt, n, dim, eps, store=store, leaf=leaf)
     finally:
         os.environ.pop("HIFCN_DENSE_TOP", None)
+        os.environ.pop("HIFCN_NO_TOP_FOLD", None)
         if old is not None:
             os.environ["HIFCN_DENSE_TOP"] = old
 
@@ -56,6 +59,34 @@ def test_dense_top_matches_stagewise(case, store, gpu_lib):
         assert torch.linalg.norm(y1 - y0) <= tol * torch.linalg.norm(y0)
     h1.close()
     h0.close()
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_write_back_in_cell_stage_is_exact(case, store, gpu_lib):
+    """The backward cell stage adds up the top's partial sums in the order the write-back
+    launch does, so both give the same bits."""
+    import torch
+    name, n, dim, leaf = case
+    print(f"[case] {name} {store}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.1, 86)
+    h1 = _factor(a, 0.05, n, dim, leaf, 1e-4, store, None)
+    h0 = _factor(a, 0.05, n, dim, leaf, 1e-4, store, None, fold=False)
+    assert h1.info()["top_level"] == h0.info()["top_level"] >= 0
+    assert h0.info()["top_fold"] == 0
+    x = torch.tensor(np.random.default_rng(9).normal(size=n ** dim), device="cuda")
+    y1, y0 = h1.apply(x), h0.apply(x)
+    assert torch.equal(y1, y0)
+    h1.close()
+    h0.close()
+
+
+def test_write_back_folds_on_the_2d_grids(gpu_lib):
+    n, dim, leaf = 64, 2, 8
+    a = gen.grf_coefficient(n, dim, 0.1, 87)
+    h = _factor(a, 0.05, n, dim, leaf, 1e-4, "f32", None)
+    assert h.info()["top_level"] >= 0 and h.info()["top_fold"] == 1
+    h.close()
 
 
 @pytest.mark.parametrize("top", [1 << 15, 1 << 18, 1 << 21])
