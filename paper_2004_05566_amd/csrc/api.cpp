@@ -114,13 +114,23 @@ struct StepState {
   int status = 0;
 };
 
+// The convergence test after iteration `it` (-1: of the right-hand side) followed by z = M^-1 r:
+// run by the apply's first stage when the factor allows it, else as its own launch.
+void check_and_apply(Handle& h, int it, double rtol, hipStream_t s) {
+  if (h.f.gate && h.f.gate_n == h.N) {
+    hif_apply_gated(h.f, h.z.p, cg_gate_args(h, it, rtol), s);
+  } else {
+    launch_cg_check_copy(h, it, rtol, s);
+    hif_apply_inplace(h.f, h.z.p, &h.st.p->done, s);
+  }
+}
+
 void step_begin(StepState& st) {
   Handle& h = *st.h;
   const int kind = st.r ? st.r->kind : 0;
   const double k1 = st.r ? st.r->k1 : 0, k2 = st.r ? st.r->k2 : 1;
   launch_cg_rhs(h, st.u, kind, k1, k2, st.o->maxit, st.s);
-  launch_cg_check_copy(h, -1, st.o->rtol, st.s);
-  hif_apply_inplace(h.f, h.z.p, &h.st.p->done, st.s);
+  check_and_apply(h, -1, st.o->rtol, st.s);
   launch_cg_dot_rz(h, 0, st.s);
   st.chunk = std::max(1, h.last_iters);
 }
@@ -140,12 +150,13 @@ void step_queue(StepState& st) {
     double* pout = (it & 1) ? h.p0.p : h.p1.p;
     launch_cg_dir_spmv(h, it, pin, pout, st.s);
     launch_cg_update(h, it, pout, st.s);
-    launch_cg_check_copy(h, it, st.o->rtol, st.s);
     if (c + 1 == st.chunk || st.launched == st.o->maxit) {
+      // the host reads the verdict before it queues another apply
+      launch_cg_check_copy(h, it, st.o->rtol, st.s);
       st.tail_open = true;
       break;
     }
-    hif_apply_inplace(h.f, h.z.p, done, st.s);
+    check_and_apply(h, it, st.o->rtol, st.s);
     launch_cg_dot_rz(h, it + 1, st.s);
   }
   HIF_CHECK(hipGetLastError());
@@ -204,7 +215,7 @@ int64_t handle_device_bytes(const Handle& h) {
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);
   add(f.tvals); add(f.tgid); add(f.tgptr); add(f.tgslot); add(f.tdtiles); add(f.tscat);
-  add(f.tddoff); add(f.twsc); add(f.tpos);
+  add(f.tddoff); add(f.twsc); add(f.tpos); add(f.gcopy);
   add(f.rddoff); add(f.rdtiles); add(f.rscat);
   for (const LevelDev& l : f.lv) {
     add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.crec); add(l.grec); add(l.frec);

@@ -31,6 +31,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "cg_gate.hpp"
 
 namespace hifcn {
 
@@ -268,7 +269,10 @@ template <typename S, typename C, bool ST, int MODE>
 __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* __restrict__ idx,
                                               const S* __restrict__ vals, double* __restrict__ y,
                                               double* __restrict__ cb, int blk_elems, int team,
-                                              bool prestaged, unsigned char* smem_raw) {
+                                              bool prestaged, unsigned char* smem_raw,
+                                              const double* __restrict__ in = nullptr) {
+  // in: where the interior values are read (y unless the input vector is another one)
+  const double* src = in ? in : y;
   C* sm = reinterpret_cast<C*>(smem_raw);
   const int nI = d.nI, nB = d.nB;
   constexpr int mode = MODE;
@@ -281,10 +285,10 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   int* ib = reinterpret_cast<int*>(vs + nI);
   const int32_t* gI = idx + d.offI;
   if (ST && !prestaged) {
-    stage_gather(blk, v, tl + (mode ? nB : nB * nI), y, gI, nI, ys, gI, 0, ys, threadIdx.x,
+    stage_gather(blk, v, tl + (mode ? nB : nB * nI), src, gI, nI, ys, gI, 0, ys, threadIdx.x,
                  blockDim.x);
   } else {
-    for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)y[gI[i]];
+    for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)src[gI[i]];
   }
   const Tri<S, C, ST> Li{blk, v, nI};
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
@@ -334,16 +338,50 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                                                   const S* __restrict__ vals,
                                                   double* __restrict__ y, double* __restrict__ cb,
                                                   const int* __restrict__ done, int blk_elems,
-                                                  int team) {
+                                                  int team, CgGate gate,
+                                                  const int32_t* __restrict__ gcopy, int gcstride) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int gstop;
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  // with a gate, the PCG convergence test comes first: its partials, the state and this
+  // cell's copy list load ahead of the record
+  const bool gated = gate.st != nullptr;
+  CgTotal ct;
+  int g_done = 0, g_maxit = 0, cid = -1, ccnt = 0;
+  double g_tol2 = 0, cval = 0;
+  const int32_t* cp = gcopy + (int64_t)blockIdx.x * gcstride;
+  if (gated) {
+    if (threadIdx.x < 64) ct.load(gate.part, gate.nb);
+    g_done = gate.st->done;
+    g_tol2 = gate.st->tol2;
+    g_maxit = gate.st->maxit;
+    ccnt = cp[0];
+    if ((int)threadIdx.x < gcstride - 1) cid = cp[1 + threadIdx.x];
+  }
   load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
-  const int dn = done ? *done : 0;
+  int dn = 0;
+  if (gated) {
+    if (cid >= 0) cval = gate.src[cid];  // (padding entries read DOF 0; never stored)
+    if (threadIdx.x < 64) {
+      const double t = ct.sum(gate.part, gate.nb);
+      // stopped by an earlier test: nothing to publish
+      if (threadIdx.x == 0)
+        gstop = g_done ? 1 : cg_verdict(gate.st, gate.init, gate.it0, gate.rtol, t, g_tol2,
+                                        g_maxit, blockIdx.x == 0);
+    }
+  } else {
+    dn = done ? *done : 0;
+  }
   __syncthreads();
-  if (dn) return;
+  if (gated ? gstop : dn) return;
   const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
   cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
-                                smem_raw + 4 * stride);
+                                smem_raw + 4 * stride, gate.src);
+  if (gated) {  // the DOFs outside every interior that this cell hands over unchanged
+    if ((int)threadIdx.x < ccnt) y[cid] = cval;
+    for (int e = threadIdx.x + blockDim.x; e < ccnt; e += blockDim.x)
+      y[cp[1 + e]] = gate.src[cp[1 + e]];
+  }
 }
 
 //   mode 0: x_I <- L^-T x_I - H^T x_B as nI dot products over [L^-1 column | H column].
@@ -1326,12 +1364,14 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const S
 
 template <typename S, typename C, int MODE>
 void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
-                 double* cb, const int* done, hipStream_t s, const StageTimer& t) {
+                 double* cb, const int* done, hipStream_t s, const StageTimer& t,
+                 const CgGate* gate = nullptr) {
   const StagePlan p = cell_plan<C>(L);
   if (fwd) {
     auto k = p.staged ? k_cell_fwd<S, C, true, MODE> : k_cell_fwd<S, C, false, MODE>;
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
-           L.cstride, vals, y, cb, done, p.blk_elems, p.seg);
+           L.cstride, vals, y, cb, done, p.blk_elems, p.seg, gate ? *gate : CgGate{},
+           gate ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
@@ -1455,7 +1495,8 @@ void launch_dense_top(const FactorDev& f, double* y, const double* cb, const int
 }
 
 template <typename S, typename C>
-void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
+void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
+                const CgGate* gate = nullptr) {
   const S* vals = reinterpret_cast<const S*>(f.vals.p);
   const int32_t* idx = f.idx.p;
   StageProfiler* prof = f.prof.get();
@@ -1467,8 +1508,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s) {
       const StageTimer t(prof, l, STAGE_CELL_FWD, done, s);
       if (L.cdense) launch_dense_cells<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
       else if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
-      else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t);
-      else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t);
+      else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t,
+                                             l == 0 ? gate : nullptr);
+      else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t, l == 0 ? gate : nullptr);
     }
     if (!L.ngroup) continue;
     if (l == f.top) {  // this level's groups, every level above and the root: one matrix
@@ -1579,6 +1621,54 @@ void hif_apply_inplace(const FactorDev& f, double* y, const int* done, hipStream
     case HIF_STORE_F32: apply_impl<float, float>(f, y, done, s); break;
     case HIF_STORE_BF16: apply_impl<bf16_t, float>(f, y, done, s); break;
   }
+}
+
+void hif_apply_gated(const FactorDev& f, double* y, const CgGate& g, hipStream_t s) {
+  HIF_REQUIRE(f.gate && !f.lv.empty() && f.lv[0].ncell && !f.lv[0].tiled && !f.lv[0].cdense,
+              HIF_ERR_ARG, "factor has no gated apply");
+  const int* done = &g.st->done;
+  switch (f.store) {
+    case HIF_STORE_F64: apply_impl<double, double>(f, y, done, s, &g); break;
+    case HIF_STORE_F32: apply_impl<float, float>(f, y, done, s, &g); break;
+    case HIF_STORE_BF16: apply_impl<bf16_t, float>(f, y, done, s, &g); break;
+  }
+}
+
+void setup_cg_gate(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                   const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
+  f.gate = false;
+  if (f.lv.empty() || cells.empty() || cells[0].empty() || f.lv[0].tiled || f.lv[0].cdense ||
+      std::getenv("HIFCN_NO_CG_GATE"))
+    return;
+  const std::vector<CellDesc>& cs = cells[0];
+  // owner of each DOF outside the interiors: the first cell with it on its boundary, the
+  // rest (no cell's boundary) dealt out in turn
+  std::vector<int32_t> owner(N, -1);
+  for (const CellDesc& c : cs)
+    for (int i = 0; i < c.nI; ++i) owner[idx[c.offI + i]] = -2;
+  for (size_t c = 0; c < cs.size(); ++c)
+    for (int b = 0; b < cs[c].nB; ++b) {
+      int32_t& o = owner[idx[cs[c].offB + b]];
+      if (o == -1) o = (int32_t)c;
+    }
+  std::vector<std::vector<int32_t>> lists(cs.size());
+  int64_t spare = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (owner[i] == -2) continue;
+    const size_t c = owner[i] >= 0 ? (size_t)owner[i] : (size_t)(spare++ % (int64_t)cs.size());
+    lists[c].push_back((int32_t)i);
+  }
+  size_t maxc = 0;
+  for (const auto& v : lists) maxc = std::max(maxc, v.size());
+  f.gcstride = 1 + (int)maxc;
+  std::vector<int32_t> rec(cs.size() * (size_t)f.gcstride, 0);
+  for (size_t c = 0; c < cs.size(); ++c) {
+    rec[c * f.gcstride] = (int32_t)lists[c].size();
+    std::copy(lists[c].begin(), lists[c].end(), rec.begin() + c * f.gcstride + 1);
+  }
+  f.gcopy.upload(rec, s);
+  f.gate_n = N;
+  f.gate = true;
 }
 
 // Allow the apply kernels to use up to `bytes` of dynamic LDS (gfx950: 160 KiB per CU).  The

@@ -1410,6 +1410,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     setup_tiling(f, cells, groups, idx, s);
     setup_fusion(f, cells, groups, idx, hd.N, s);
     setup_dense_top(f, cells, groups, idx, hd.N, s);
+    setup_cg_gate(f, cells, idx, hd.N, s);
   }
   size_t worst = 0;
   apply_smem_need(f, &worst);

@@ -349,6 +349,7 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
     setup_tiling(fd, cells, groups, fh.idx, s);
     setup_fusion(fd, cells, groups, fh.idx, N, s);
     setup_dense_top(fd, cells, groups, fh.idx, N, s);
+    setup_cg_gate(fd, cells, fh.idx, N, s);
   }
   size_t worst = 0;
   apply_smem_need(fd, &worst);

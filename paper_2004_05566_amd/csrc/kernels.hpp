@@ -120,6 +120,13 @@ struct FactorDev {
   bool tfold = false;
   int tpstride = 0;
   DevBuf<int32_t> tpos;
+  // gate: the level-0 cell stage can run the PCG convergence test (CgGate); gcopy: per cell, a
+  // count and the DOFs outside every level-0 interior that it copies from the input (stride
+  // gcstride), each such DOF in exactly one list
+  bool gate = false;
+  int gcstride = 0;
+  int64_t gate_n = 0;  // DOFs the copy lists cover (0 .. gate_n-1)
+  DevBuf<int32_t> gcopy;
   // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
   int64_t mfma_flops = 0;
   double mfma_ms = 0;
@@ -153,6 +160,18 @@ struct CgState {
   double pq;      // p.(A p)
   double rr;      // ||r||^2 after the latest update
   int32_t iters, done, status, maxit;
+};
+
+// A convergence test of the PCG run by the first stage of a preconditioner apply instead of its
+// own launch: the verdict comes from the partial sums (part, nb of them) of ||g||^2 (init) or
+// ||r||^2 after iteration it0; when the iteration goes on, the apply reads its input from src (r)
+// and its output vector receives r's values wherever the apply does not overwrite them.
+struct CgGate {
+  CgState* st = nullptr;
+  const double* part = nullptr;
+  int nb = 0, init = 0, it0 = 0;
+  double rtol = 0;
+  const double* src = nullptr;
 };
 
 struct Handle {
@@ -222,6 +241,13 @@ void set_apply_smem_limits(size_t bytes);
 
 // ---- kernels --------------------------------------------------------------------------------
 void hif_apply_inplace(const FactorDev& f, double* y, const int* done, hipStream_t s);
+// The apply with the convergence test in its first stage (requires f.gate): y <- M^-1 src when
+// the iteration goes on, nothing when it stops; later stages skip on g.st->done.
+void hif_apply_gated(const FactorDev& f, double* y, const CgGate& g, hipStream_t s);
+// Lay out the copy lists of the gated apply (f.gate stays false when level 0 does not run as
+// one workgroup per cell).
+void setup_cg_gate(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                   const std::vector<int32_t>& idx, int64_t N, hipStream_t s);
 void launch_links(const double* a_cells, int dim, int n, double scale, double* links,
                   hipStream_t s);
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
@@ -230,6 +256,8 @@ int cg_partial_slots();
 void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
                    hipStream_t s);
 void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s);
+// The same test as arguments of a gated apply.
+CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol);
 void launch_cg_dot_rz(Handle& h, int it, hipStream_t s);
 void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipStream_t s);
 void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s);

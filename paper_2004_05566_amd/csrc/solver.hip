@@ -13,6 +13,7 @@
 // the step return.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "cg_gate.hpp"
 
 namespace hifcn {
 
@@ -186,32 +187,18 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ z, CgState* st,
                                                             const double* __restrict__ part) {
+  __shared__ int stop;
   if (st->done) return;
   const int nb = gridDim.x;
-  bool stop;
-  if (init) {
-    const double gg = total(part + P_GG * (int64_t)nb, nb);
-    stop = !(gg > 0.0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->gg = gg;
-      st->tol2 = rtol * rtol * gg;
-      st->rr = gg;
-      st->done = stop ? 1 : 0;
-    }
-  } else {
-    const double rr = total(part + P_RR * (int64_t)nb, nb);
-    const int it = it0 + 1;
-    const bool bad = !(rr == rr) || rr > 1.7e308;
-    const bool conv = !bad && rr <= st->tol2;
-    const bool cap = !bad && !conv && it >= st->maxit;
-    stop = bad || conv || cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->rr = rr;
-      st->iters = it;
-      st->done = stop ? 1 : 0;
-      st->status = (bad || cap) ? HIF_ERR_NO_CONV : 0;
-    }
+  if (threadIdx.x < 64) {
+    CgTotal ct;
+    const double* p = part + (init ? P_GG : P_RR) * (int64_t)nb;
+    ct.load(p, nb);
+    const double t = ct.sum(p, nb);
+    if (threadIdx.x == 0)
+      stop = cg_verdict(st, init, it0, rtol, t, st->tol2, st->maxit, blockIdx.x == 0);
   }
+  __syncthreads();
   if (stop) return;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads)
@@ -334,6 +321,18 @@ void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, i
 void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it < 0 ? 1 : 0, it,
                      rtol, h.r.p, h.z.p, h.st.p, h.partials.p);
+}
+
+CgGate cg_gate_args(Handle& h, int it, double rtol) {
+  CgGate g;
+  g.st = h.st.p;
+  g.nb = h.nblk;
+  g.init = it < 0 ? 1 : 0;
+  g.it0 = it;
+  g.rtol = rtol;
+  g.part = h.partials.p + (it < 0 ? P_GG : P_RR) * (int64_t)h.nblk;
+  g.src = h.r.p;
+  return g;
 }
 
 void launch_cg_dot_rz(Handle& h, int it, hipStream_t s) {

@@ -1,0 +1,65 @@
+"""PCG convergence test run by the first stage of the preconditioner apply.
+
+Inside a batch of queued iterations the test after each update (and the one on the right-hand
+side) runs in the level-0 cell stage, which then reads r and hands z = r over for every DOF it
+does not overwrite.  The same factor built with HIFCN_NO_CG_GATE=1 runs the test as its own
+launch; both sum the partials in one order, so the solves agree bit for bit, iteration counts
+and residual reports included.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("2d-n64-f32", 64, 2, 8, "f32"), ("2d-n100-f64", 100, 2, 8, "f64"),
+         ("2d-n48-bf16", 48, 2, 8, "bf16"), ("3d-n16-f32", 16, 3, 4, "f32"),
+         ("2d-n33-f64", 33, 2, 4, "f64")]
+
+
+def _factor(a, n, dim, leaf, store, gate):
+    import torch
+    from paper_2004_05566_amd import hifcn
+    a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
+    if not gate:
+        os.environ["HIFCN_NO_CG_GATE"] = "1"
+    try:
+        return hifcn.factor(a_dev, 0.05, n, dim, 1e-6, store=store, leaf=leaf)
+    finally:
+        os.environ.pop("HIFCN_NO_CG_GATE", None)
+
+
+@pytest.mark.parametrize("rtol", [1e-10, 1e-2])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_gated_solve_is_bitwise_equal(case, rtol, gpu_lib):
+    import torch
+    name, n, dim, leaf, store = case
+    print(f"[case] {name} rtol {rtol}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.12, 91)
+    u0 = gen.bumps(n, dim, 3, 92).ravel()
+    out = []
+    for gate in (True, False):
+        h = _factor(a, n, dim, leaf, store, gate)
+        u = torch.tensor(u0, device="cuda")
+        its, rel = h.cn_solve(u, 4, rtol=rtol, reaction=(1, 1.0, 1.0))
+        out.append((u, list(its), rel.tolist()))
+        h.close()
+    (u1, i1, r1), (u0_, i0, r0) = out
+    assert i1 == i0 and r1 == r0
+    assert torch.equal(u1, u0_)
+    if rtol == 1e-2 and store != "bf16":  # the test after the first update ends the step
+        assert min(i1) <= 1, i1
+
+
+def test_gated_apply_zero_rhs_stops_at_once(gpu_lib):
+    """g = 0: the test in the first stage ends the solve before any work."""
+    import torch
+    n = 64
+    h = _factor(gen.grf_coefficient(n, 2, 0.12, 93), n, 2, 8, "f32", True)
+    u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    its, rel = h.cn_solve(u, 2)
+    assert list(its) == [0, 0] and not u.any()
+    h.close()
