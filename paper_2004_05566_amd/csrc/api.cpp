@@ -115,9 +115,11 @@ struct StepState {
 };
 
 // The convergence test after iteration `it` (-1: of the right-hand side) followed by z = M^-1 r:
-// run by the apply's first stage when the factor allows it, else as its own launch.
+// run by the apply's first stage when the factor allows it, else as its own launch.  Every
+// workgroup of that stage reads all partials of the test, so it stays a launch of its own where
+// that would add up to more than ~8 MB (many level-0 cells: the 1024^2 grid has 16K).
 void check_and_apply(Handle& h, int it, double rtol, hipStream_t s) {
-  if (h.f.gate && h.f.gate_n == h.N) {
+  if (h.f.gate && h.f.gate_n == h.N && (int64_t)h.f.lv[0].ncell * h.nblk <= (int64_t(1) << 20)) {
     hif_apply_gated(h.f, h.z.p, cg_gate_args(h, it, rtol), s);
   } else {
     launch_cg_check_copy(h, it, rtol, s);
@@ -214,8 +216,8 @@ int64_t handle_device_bytes(const Handle& h) {
   add(h.st); add(h.step_iters); add(h.step_relres);
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);
-  add(f.tvals); add(f.tgid); add(f.tgptr); add(f.tgslot); add(f.tdtiles); add(f.tscat);
-  add(f.tddoff); add(f.twsc); add(f.tpos); add(f.gcopy);
+  add(f.tvals); add(f.tgid); add(f.tgslot); add(f.tscat); add(f.twsc); add(f.tpos);
+  add(f.gcopy);
   add(f.rddoff); add(f.rdtiles); add(f.rscat);
   for (const LevelDev& l : f.lv) {
     add(l.cells); add(l.groups); add(l.rtiles); add(l.ctiles); add(l.crec); add(l.grec); add(l.frec);

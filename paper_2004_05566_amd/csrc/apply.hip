@@ -405,7 +405,7 @@ __device__ __forceinline__ void cell_bwd_body(const CellDesc& d, const int32_t* 
   const int32_t* gI = idx + d.offI;
   const int nBy = top.pos ? 0 : nB;  // boundary values read from y
   // the first boundary DOF of each lane: its partial sums are loaded before the block is staged
-  constexpr int kTopPre = 8;
+  constexpr int kTopPre = 16;
   double tp[kTopPre];
   const bool pre = top.pos && top.nch <= kTopPre && (int)threadIdx.x < nB;
   if (pre) {
@@ -1016,12 +1016,10 @@ __global__ __launch_bounds__(TT) void k_tcols(const CellDesc* __restrict__ cd,
 //   DR_CELL_BWD   x_I = A_II^-1 (y_I - A_IB x_B) -> y
 //   DR_GROUP_FWD  the group step G (y_g less the cell contributions) -> scratch
 //   DR_ROOT       partial sums of A_r^-1 y_r over one column range -> scratch
-//   DR_TOP        partial sums of the dense top M_k (y_k less the contributions of level k's
-//                 cells) over one column range -> scratch
 //   column tiles: the backward group step G^T x_g -> scratch
 // Dense group and root results go back to y by a scatter list once every tile has read its
-// inputs.
-enum { DR_CELL_FWD = 0, DR_CELL_BWD, DR_GROUP_FWD, DR_ROOT, DR_TOP };
+// inputs.  (The dense top has a kernel of its own, k_top_rows.)
+enum { DR_CELL_FWD = 0, DR_CELL_BWD, DR_GROUP_FWD, DR_ROOT };
 constexpr int kDenseColsPerTile = 32;
 
 __host__ __device__ inline int dense_ld(int n) { return (n + 31) & ~31; }
@@ -1032,8 +1030,6 @@ __global__ __launch_bounds__(TT) void k_dense_rows(const CellDesc* __restrict__ 
                                                    const int64_t* __restrict__ ddoff,
                                                    const int4* __restrict__ tiles, int span,
                                                    int nroot, const int32_t* __restrict__ ridx,
-                                                   const int32_t* __restrict__ gptr,
-                                                   const int32_t* __restrict__ gslot,
                                                    const int32_t* __restrict__ idx,
                                                    const S* __restrict__ vals,
                                                    const S* __restrict__ dv,
@@ -1088,12 +1084,6 @@ __global__ __launch_bounds__(TT) void k_dense_rows(const CellDesc* __restrict__ 
     for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) {
       double a = y[gi[j]];
       for (int q = gp[j]; q < gp[j + 1]; ++q) a -= cb[slots[q]];
-      xs[j - c0] = (C)a;
-    }
-  } else if constexpr (KIND == DR_TOP) {
-    for (int j = c0 + (int)threadIdx.x; j < c1; j += TT) {
-      double a = y[ridx[j]];
-      for (int q = gptr[j]; q < gptr[j + 1]; ++q) a -= cb[gslot[q]];
       xs[j - c0] = (C)a;
     }
   } else {
@@ -1180,6 +1170,84 @@ __global__ __launch_bounds__(256) void k_dense_scatter(const int4* __restrict__ 
     double a = 0;
     for (int p = 0; p < q.z; ++p) a += wsc[q.y + (int64_t)p * q.w];
     y[q.x] = a;
+  }
+}
+
+// Dense top: the partial sums w[chunk][r] = sum over the chunk's columns c of M_k[r, c]
+// (y_k - c_k)[c].  One workgroup per (row tile, column chunk), chunk-major; each lane covers
+// VecOf<S>::W consecutive rows, read as one 16-byte vector per column (M_k is column-major), so
+// a wave streams 1 KiB per load; the waves split the chunk's columns (wave w takes w, w + NW,
+// ...).  The first U vectors of every lane are loaded before the inputs are gathered and the
+// early-exit flag is looked at, so their latencies overlap.  Same summation order as the
+// 64-row form of k_dense_rows.
+constexpr int kTopThreads = 1024;
+constexpr int kTopUnroll = 16;
+
+template <typename S, typename C>
+__global__ __launch_bounds__(kTopThreads) void k_top_rows(int nrt, int span, int n, int ld,
+                                                          const int32_t* __restrict__ ridx,
+                                                          int kslot,
+                                                          const int32_t* __restrict__ gslot,
+                                                          const S* __restrict__ M,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ cb,
+                                                          double* __restrict__ wsc,
+                                                          const int* __restrict__ done) {
+  using V = typename VecOf<S>::T;
+  constexpr int W = VecOf<S>::W, RT = 64 * W, NW = kTopThreads / 64, U = kTopUnroll;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* xs = reinterpret_cast<C*>(smem_raw);
+  __shared__ C red[NW][RT];
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int ch = b / nrt, r0 = (b - ch * nrt) * RT, c0 = ch * span;
+  const int nc = min(n, c0 + span) - c0;
+  const int dn = done ? *done : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // lanes past the column read its last vector (ld is a multiple of W; their sums are dropped),
+  // and columns past the chunk read its last column with a zero input: no branch separates the
+  // loads of a batch from their use
+  const int rl = min(r0 + lane * W, ld - W);
+  const int64_t ldv = ld / W;
+  const V* col = reinterpret_cast<const V*>(M + rl) + (int64_t)c0 * ldv;
+  V v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = col[(int64_t)min(wave + u * NW, nc - 1) * ldv];
+  // inputs: y less the contributions of level k's cells (kslot slots per DOF, -1 = none)
+  for (int j = threadIdx.x; j < nc; j += kTopThreads) {
+    const int32_t* sl = gslot + (int64_t)(c0 + j) * kslot;
+    double s = y[ridx[c0 + j]];
+    for (int q = 0; q < kslot; ++q)
+      if (sl[q] >= 0) s -= cb[sl[q]];
+    xs[j] = (C)s;
+  }
+  if (dn) return;  // (uniform)
+  __syncthreads();
+  C acc[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) acc[e] = 0;
+  for (int j = wave; j < nc; j += U * NW) {
+    if (j > wave) {  // the next batch (the first one is in flight already)
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = col[(int64_t)min(j + u * NW, nc - 1) * ldv];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      C e[W];
+      unpack<C>(v[u], e);
+      const C x = j + u * NW < nc ? xs[j + u * NW] : (C)0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += e[k] * x;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < W; ++e) red[wave][lane * W + e] = acc[e];
+  __syncthreads();
+  for (int q = threadIdx.x; q < RT; q += kTopThreads) {
+    if (r0 + q >= n) continue;
+    C tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += red[w][q];
+    wsc[(int64_t)ch * n + r0 + q] = (double)tot;
   }
 }
 
@@ -1417,8 +1485,7 @@ void launch_dense_cells_tt(const FactorDev& f, const LevelDev& L, bool fwd, cons
   auto k = fwd ? k_dense_rows<S, C, DR_CELL_FWD, TT> : k_dense_rows<S, C, DR_CELL_BWD, TT>;
   launch(k, dim3(L.ncdt), dim3(TT), sm, s, t, (const CellDesc*)L.cells.p,
          (const GroupDesc*)nullptr, (const int64_t*)L.cddoff.p, (const int4*)L.cdtiles.p,
-         kDenseSpanAll, 0, (const int32_t*)nullptr, (const int32_t*)nullptr,
-         (const int32_t*)nullptr, (const int32_t*)f.idx.p, vals,
+         kDenseSpanAll, 0, (const int32_t*)nullptr, (const int32_t*)f.idx.p, vals,
          reinterpret_cast<const S*>(f.dvals.p), y, cb, f.wsc.p, done);
 }
 
@@ -1452,8 +1519,7 @@ void launch_dense_groups(const FactorDev& f, const LevelDev& L, bool fwd, double
     launch(k_dense_rows<S, C, DR_GROUP_FWD, kDenseThreads>, dim3(L.ngrt), dim3(kDenseThreads),
            sm, s, ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)L.groups.p,
            (const int64_t*)L.gddoff.p, (const int4*)L.grtiles.p, kDenseSpanAll, 0,
-           (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
-           (const int32_t*)f.idx.p, (const S*)nullptr, dv, y,
+           (const int32_t*)nullptr, (const int32_t*)f.idx.p, (const S*)nullptr, dv, y,
            const_cast<double*>(cb), f.wsc.p, done);
   else
     launch(k_dense_gcols<S, C, kDenseThreads>, dim3(L.ngct), dim3(kDenseThreads), sm, s,
@@ -1471,8 +1537,7 @@ void launch_dense_root(const FactorDev& f, double* y, const int* done, hipStream
   launch(k_dense_rows<S, C, DR_ROOT, kDenseThreads>, dim3(f.nrdt), dim3(kDenseThreads), sm, s,
          ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)nullptr,
          (const int64_t*)f.rddoff.p, (const int4*)f.rdtiles.p, f.rspan, f.nroot,
-         (const int32_t*)f.idx.p + f.offRootIdx, (const int32_t*)nullptr, (const int32_t*)nullptr,
-         (const int32_t*)f.idx.p, (const S*)nullptr,
+         (const int32_t*)f.idx.p + f.offRootIdx, (const int32_t*)f.idx.p, (const S*)nullptr,
          reinterpret_cast<const S*>(f.dvals.p), y, (double*)nullptr, f.wsc.p, done);
   launch_scatter(f.rscat, f.nrsc, f, y, done, s, ts.next());
 }
@@ -1482,12 +1547,11 @@ void launch_dense_top(const FactorDev& f, double* y, const double* cb, const int
                       hipStream_t s, const StageTimer& t) {
   TimedSeq ts(t, f.tfold ? 1 : 2);
   const size_t sm = sizeof(C) * (size_t)std::max(1, std::min(f.ntop, f.tspan));
-  launch(k_dense_rows<S, C, DR_TOP, kDenseThreads>, dim3(f.ntdt), dim3(kDenseThreads), sm, s,
-         ts.next(), (const CellDesc*)nullptr, (const GroupDesc*)nullptr,
-         (const int64_t*)f.tddoff.p, (const int4*)f.tdtiles.p, f.tspan, f.ntop,
-         (const int32_t*)f.tgid.p, (const int32_t*)f.tgptr.p, (const int32_t*)f.tgslot.p,
-         (const int32_t*)f.idx.p, (const S*)nullptr, reinterpret_cast<const S*>(f.tvals.p), y,
-         const_cast<double*>(cb), f.twsc.p, done);
+  const int nrt = (f.ntop + 64 * VecOf<S>::W - 1) / (64 * VecOf<S>::W);
+  launch(k_top_rows<S, C>, dim3(f.ntdt), dim3(kTopThreads), sm, s, ts.next(), nrt, f.tspan,
+         f.ntop, (f.ntop + 31) & ~31, (const int32_t*)f.tgid.p, f.tkslot,
+         (const int32_t*)f.tgslot.p,
+         reinterpret_cast<const S*>(f.tvals.p), (const double*)y, cb, f.twsc.p, done);
   if (f.tfold) return;  // the backward cell stage of the level reads the partial sums
   const int grid = std::max(1, std::min(1024, (f.ntsc + 255) / 256));
   launch(k_dense_scatter, dim3(grid), dim3(256), 0, s, ts.next(), (const int4*)f.tscat.p, f.ntsc,

@@ -399,37 +399,47 @@ void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cel
       break;
   }
   HIF_CHECK(hipGetLastError());
-  std::vector<int32_t> ptr(1, 0), slots;
-  for (size_t q = 0; q < groups[k].size(); ++q) {
-    const GroupDesc& gd = groups[k][q];
+  // the contribution slots of each top DOF, padded to the largest count (-1)
+  int kslot = 1;
+  for (const GroupDesc& gd : groups[k]) {
     const int32_t* gp = idx.data() + gd.offGP;
-    const int32_t* sl = gp + gd.n + 1;
-    for (int i = 0; i < gd.n; ++i) {
-      for (int e = gp[i]; e < gp[i + 1]; ++e) slots.push_back(sl[e]);
-      ptr.push_back((int32_t)slots.size());
+    for (int i = 0; i < gd.n; ++i) kslot = std::max(kslot, gp[i + 1] - gp[i]);
+  }
+  std::vector<int32_t> slots((size_t)n * kslot, -1);
+  int64_t ns = 0;
+  {
+    int i0 = 0;
+    for (const GroupDesc& gd : groups[k]) {
+      const int32_t* gp = idx.data() + gd.offGP;
+      const int32_t* sl = gp + gd.n + 1;
+      for (int i = 0; i < gd.n; ++i, ++i0)
+        for (int e = gp[i]; e < gp[i + 1]; ++e, ++ns)
+          slots[(size_t)i0 * kslot + (e - gp[i])] = sl[e];
     }
   }
-  f.tspan = 512;
+  // row tiles of 64 16-byte vectors (256 rows in FP32) times column chunks, chunk-major (the
+  // kernel derives its tile from the workgroup index); enough chunks for ~256 workgroups, at
+  // most 16 (each DOF's result is the sum of one partial per chunk)
+  const int rows = 64 * (16 / (int)eb);
+  const int nrt = (n + rows - 1) / rows;
+  int want = std::max(1, std::min(16, (256 + nrt - 1) / nrt));
+  if (const char* e = std::getenv("HIFCN_TOP_CHUNKS")) want = std::max(1, std::atoi(e));
+  // (a multiple of the 256 columns one batch of the kernel covers)
+  f.tspan = std::max(256, ((n + want - 1) / want + 255) / 256 * 256);
   const int nch = (n + f.tspan - 1) / f.tspan;
-  std::vector<int4> tiles, scat;
-  for (int c = 0; c < nch; ++c)
-    for (int r0 = 0; r0 < n; r0 += 64) tiles.push_back({0, r0, c * f.tspan, c * n});
+  std::vector<int4> scat;
   for (int i = 0; i < n; ++i) scat.push_back({ids[i], i, nch, n});
-  if (slots.empty()) slots.push_back(0);  // (never read: every pointer range is empty)
   f.tgid.upload(ids, s);
-  f.tgptr.upload(ptr, s);
+  f.tkslot = kslot;
   f.tgslot.upload(slots, s);
-  f.tdtiles.upload(tiles, s);
   f.tscat.upload(scat, s);
-  f.tddoff.upload(std::vector<int64_t>{0}, s);
   f.twsc.alloc((size_t)nch * n);
   f.top = k;
   f.ntop = n;
-  f.ntdt = (int)tiles.size();
+  f.ntdt = nch * nrt;
   f.ntsc = (int)scat.size();
-  const int64_t ns = ptr.back();
   f.top_bytes = (int64_t)eb * n * n + 8 * (2 * (int64_t)n + ns + 2 * (int64_t)nch * n) +
-                4 * (3 * (int64_t)n + 1 + ns);
+                4 * (3 * (int64_t)n + (int64_t)n * kslot);
   f.root_fused = false;
   // When the level's cells run one workgroup each and their boundaries cover every top DOF, the
   // backward cell stage adds up the partial sums itself and writes them to y.

@@ -104,15 +104,14 @@ struct FactorDev {
   // Dense top: the stages from the group step of level `top` up to the root and back, applied
   // as one symmetric matrix on that level's group DOFs (tvals, column-major, leading dimension
   // ntop rounded up to 32); -1: none.  Inputs: DOF ids (tgid) less the contributions in the
-  // slots tgslot[tgptr[i] .. tgptr[i + 1]); row tiles over column ranges of tspan, partial sums
-  // in twsc added up by the write-back list tscat.
+  // slots tgslot[i * tkslot ..] (-1: none); ntdt workgroups of row tiles over column ranges of
+  // tspan, partial sums in twsc added up by the write-back list tscat.
   int64_t top_budget = -1;  // entries allowed (set before the build; < 0: default)
-  int top = -1, ntop = 0, tspan = 0, ntdt = 0, ntsc = 0;
+  int top = -1, ntop = 0, tspan = 0, ntdt = 0, ntsc = 0, tkslot = 0;
   int64_t top_bytes = 0;
   DevBuf<unsigned char> tvals;
-  DevBuf<int32_t> tgid, tgptr, tgslot;
-  DevBuf<int4> tdtiles, tscat;
-  DevBuf<int64_t> tddoff;
+  DevBuf<int32_t> tgid, tgslot;
+  DevBuf<int4> tscat;
   DevBuf<double> twsc;
   // tfold: the backward cell stage of level `top` takes its boundary values from the partial
   // sums (and writes them to y) instead of a write-back launch; tpos: per cell of that level,
