@@ -58,7 +58,7 @@ typedef struct hif_handle_s* hif_handle_t;
 typedef struct { int32_t kind; double k1; double k2; } hif_reaction_t;
 
 /* PCG options (Algorithm 1): stop when ||r_i||_2 <= rtol ||g||_2 (recurrence residual),
- * x0 = 0, at most maxit iterations.  warm_start must be 0 (reserved). */
+ * x0 = 0, at most maxit iterations (1 .. 2^24 - 1).  warm_start must be 0 (reserved). */
 typedef struct { double rtol; int32_t maxit; int32_t warm_start; } hif_cg_opts_t;
 
 /* Build the PHIF factor of A = I - dt/2 M (Sec. 2.2: per level cell elimination, block Jacobi,

@@ -81,9 +81,11 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   HIF_CHECK(hipMemsetAsync(h->st.p, 0, sizeof(CgState), s));
   h->step_iters.alloc(1);
   h->step_relres.alloc(1);
-  // [0..2] iters, done, status of the running step; [4..5] the last step's relres (FP64)
+  // see Handle::host_flag
   HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 8 * sizeof(int32_t),
-                          hipHostMallocDefault));
+                          hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(h->host_flag, 0, 8 * sizeof(int32_t));
+  HIF_CHECK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->flag_dev), h->host_flag, 0));
   return h;
 }
 
@@ -110,6 +112,7 @@ struct StepState {
   int launched = 0;        // iterations whose update has been queued
   bool tail_open = false;  // the last queued iteration still owes its apply + r.z
   int chunk = 1;
+  int seq = 0;             // sequence number of the latest posted convergence test
   bool finished = false;
   int status = 0;
 };
@@ -154,7 +157,8 @@ void step_queue(StepState& st) {
     launch_cg_update(h, it, pout, st.s);
     if (c + 1 == st.chunk || st.launched == st.o->maxit) {
       // the host reads the verdict before it queues another apply
-      launch_cg_check_copy(h, it, st.o->rtol, st.s);
+      st.seq = ++h.flag_seq;
+      launch_cg_check_copy(h, it, st.o->rtol, st.s, st.seq);
       st.tail_open = true;
       break;
     }
@@ -162,8 +166,29 @@ void step_queue(StepState& st) {
     launch_cg_dot_rz(h, it + 1, st.s);
   }
   HIF_CHECK(hipGetLastError());
-  HIF_CHECK(hipMemcpyAsync(h.host_flag, &h.st.p->iters, 3 * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, st.s));
+}
+
+// Wait until the batch queued by step_queue has posted its outcome to the host flag: spin on the
+// sequence number (no stream round trip), looking at the stream now and then; an idle stream
+// without the post is an error.
+void step_wait(StepState& st) {
+  int32_t* f = st.h->host_flag;
+  const volatile uint64_t* w = reinterpret_cast<const volatile uint64_t*>(f + 6);
+  uint64_t v = 0;
+  for (int64_t n = 1;; ++n) {
+    v = *w;
+    if ((int32_t)(v >> 32) == st.seq) break;
+    if ((n & 255) != 0) continue;
+    const hipError_t q = hipStreamQuery(st.s);
+    if (q == hipErrorNotReady) continue;
+    HIF_CHECK(q);
+    v = *w;
+    HIF_REQUIRE((int32_t)(v >> 32) == st.seq, HIF_ERR_HIP, "convergence flag was not posted");
+    break;
+  }
+  f[0] = (int32_t)(v & 0xffffff);
+  f[1] = (int32_t)(v >> 24 & 0xf);
+  f[2] = (int32_t)(v >> 28 & 0xf);
 }
 
 // After the stream has been synchronised: finish the step if PCG stopped.
@@ -191,7 +216,7 @@ void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, dou
   step_begin(st);
   while (!st.finished) {
     step_queue(st);
-    HIF_CHECK(hipStreamSynchronize(s));
+    step_wait(st);
     step_after_sync(st);
   }
 }
@@ -199,6 +224,7 @@ void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, dou
 void check_opts(const hif_cg_opts_t* o) {
   HIF_REQUIRE(o != nullptr, HIF_ERR_ARG, "NULL cg options");
   HIF_REQUIRE(o->rtol > 0 && o->maxit > 0, HIF_ERR_ARG, "rtol and maxit must be positive");
+  HIF_REQUIRE(o->maxit < (1 << 24), HIF_ERR_ARG, "maxit must be below 2^24");
   HIF_REQUIRE(o->warm_start == 0, HIF_ERR_ARG, "warm_start is reserved and must be 0");
 }
 
@@ -366,7 +392,7 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
         for (StepState* x : mine)
           if (!x->finished) step_queue(*x);
         for (StepState* x : mine)
-          if (!x->finished) HIF_CHECK(hipStreamSynchronize(x->s));
+          if (!x->finished) step_wait(*x);
         for (StepState* x : mine)
           if (!x->finished) {
             step_after_sync(*x);

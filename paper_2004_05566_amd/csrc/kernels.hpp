@@ -184,7 +184,12 @@ struct Handle {
   DevBuf<CgState> st;
   DevBuf<int32_t> step_iters;
   DevBuf<double> step_relres;
-  int32_t* host_flag = nullptr;  // pinned: done flag mirror
+  // pinned, device-mapped: [0..2] iters, done, status of the running step (decoded by the host
+  // from [6..7], the 64-bit word that the last convergence test of a queued batch of iterations
+  // posts together with its sequence number flag_seq); [4..5] the last batched step's relres
+  int32_t* host_flag = nullptr;
+  int32_t* flag_dev = nullptr;  // host_flag as seen from the device
+  int32_t flag_seq = 0;
   int nblk = 0;
   int last_iters = 2;
   ~Handle();
@@ -254,7 +259,9 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
 int cg_partial_slots();
 void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
                    hipStream_t s);
-void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s);
+// seq > 0: also post [iters, done, status] and then seq to the handle's host flag.
+void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s,
+                          int seq = 0);
 // The same test as arguments of a gated apply.
 CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol);
 void launch_cg_dot_rz(Handle& h, int it, hipStream_t s);

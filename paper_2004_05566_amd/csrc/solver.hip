@@ -182,21 +182,35 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
 // iteration count advanced.  Block 0 publishes the scalars; every block reaches the same verdict.
 // `it` is the 0-based index of the iteration whose update was just made (ignored for init);
 // it comes from the host so that no block reads a scalar that block 0 rewrites in this launch.
+// With hflag, block 0 also posts the outcome to the host as one aligned 64-bit store (seen
+// whole or not at all): seq in the high word, iters | done << 24 | status << 28 in the low one.
+__device__ void post_flag(int32_t* hflag, int seq, int iters, int done, int status) {
+  const uint64_t lo = (uint32_t)iters | (uint32_t)done << 24 | (uint32_t)status << 28;
+  *reinterpret_cast<volatile uint64_t*>(hflag + 6) = (uint64_t)(uint32_t)seq << 32 | lo;
+}
+
 __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init, int it0,
                                                             double rtol,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ z, CgState* st,
-                                                            const double* __restrict__ part) {
+                                                            const double* __restrict__ part,
+                                                            int32_t* hflag, int seq) {
   __shared__ int stop;
-  if (st->done) return;
+  const bool post = hflag && blockIdx.x == 0 && threadIdx.x == 0;
+  if (st->done) {  // stopped by an earlier test of the batch
+    if (post) post_flag(hflag, seq, st->iters, 1, st->status);
+    return;
+  }
   const int nb = gridDim.x;
   if (threadIdx.x < 64) {
     CgTotal ct;
     const double* p = part + (init ? P_GG : P_RR) * (int64_t)nb;
     ct.load(p, nb);
     const double t = ct.sum(p, nb);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
       stop = cg_verdict(st, init, it0, rtol, t, st->tol2, st->maxit, blockIdx.x == 0);
+      if (post) post_flag(hflag, seq, st->iters, st->done, st->status);
+    }
   }
   __syncthreads();
   if (stop) return;
@@ -318,9 +332,10 @@ void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, i
                      kind, k1, k2, h.dt, maxit, h.st.p, h.partials.p);
 }
 
-void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s) {
+void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s, int seq) {
   hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it < 0 ? 1 : 0, it,
-                     rtol, h.r.p, h.z.p, h.st.p, h.partials.p);
+                     rtol, h.r.p, h.z.p, h.st.p, h.partials.p, seq > 0 ? h.flag_dev : nullptr,
+                     seq);
 }
 
 CgGate cg_gate_args(Handle& h, int it, double rtol) {
