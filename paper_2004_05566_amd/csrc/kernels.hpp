@@ -154,9 +154,7 @@ struct FactorHost {
 struct CgState {
   double gg;      // ||g||^2
   double tol2;    // rtol^2 ||g||^2
-  double rz;      // rho = r.z of the current search direction
-  double rz_new;  // r.z after the latest preconditioner apply
-  double pq;      // p.(A p)
+  double rzv[2];  // rho = r.z of direction it, in slot it & 1 (kept by the direction kernel)
   double rr;      // ||r||^2 after the latest update
   int32_t iters, done, status, maxit;
 };

@@ -233,6 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_dot_rz(int64_t N, int it,
 }
 
 // p_out = z + beta p_in (beta = 0 on the first iteration), q = A p_out, partials of p_out.q.
+// rho of this direction is totalled here once (block 0 keeps it in rzv[it & 1] for the update
+// and the next direction; no block reads that slot in this launch).
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N, int it,
                                                           const double* __restrict__ w,
@@ -240,16 +242,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N, int 
                                                           const double* __restrict__ pin,
                                                           double* __restrict__ pout,
                                                           double* __restrict__ q,
-                                                          const CgState* st, double* part) {
+                                                          CgState* st, double* part) {
   if (st->done) return;
   const int nb = gridDim.x;
   const bool first = it == 0;
-  double beta = 0.0;
-  if (!first) {
-    const double rz = total(part + (P_RZ0 + (it & 1)) * (int64_t)nb, nb);
-    const double rz_prev = total(part + (P_RZ0 + ((it + 1) & 1)) * (int64_t)nb, nb);
-    beta = rz / rz_prev;
-  }
+  const double rz = total(part + (P_RZ0 + (it & 1)) * (int64_t)nb, nb);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->rzv[it & 1] = rz;
+  const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
@@ -272,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
                                                         double* part) {
   if (st->done) return;
   const int nb = gridDim.x;
-  const double rz = total(part + (P_RZ0 + (it & 1)) * (int64_t)nb, nb);
+  const double rz = st->rzv[it & 1];
   const double pq = total(part + P_PQ * (int64_t)nb, nb);
   const double alpha = rz / pq;
   double acc = 0;
