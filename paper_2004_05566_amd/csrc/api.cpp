@@ -158,7 +158,7 @@ void step_queue(StepState& st) {
     if (c + 1 == st.chunk || st.launched == st.o->maxit) {
       // the host reads the verdict before it queues another apply
       st.seq = ++h.flag_seq;
-      launch_cg_check_copy(h, it, st.o->rtol, st.s, st.seq);
+      launch_cg_check_finish(h, it, st.o->rtol, st.u, st.step, st.seq, st.s);
       st.tail_open = true;
       break;
     }
@@ -191,15 +191,16 @@ void step_wait(StepState& st) {
   f[2] = (int32_t)(v >> 28 & 0xf);
 }
 
-// After the stream has been synchronised: finish the step if PCG stopped.
+// Once the outcome of the batch is posted: the step is over if PCG stopped (the closing test has
+// then written u and the step's records; PCG always stops by maxit).
 void step_after_sync(StepState& st) {
   Handle& h = *st.h;
-  if (h.host_flag[1] || st.launched >= st.o->maxit) {
+  if (h.host_flag[1]) {
     h.last_iters = h.host_flag[0];
     st.status = h.host_flag[2];
-    launch_cg_finish(h, st.u, st.step, st.s);
     st.finished = true;
   } else {
+    HIF_REQUIRE(st.launched < st.o->maxit, HIF_ERR_HIP, "PCG ran past maxit without stopping");
     st.chunk = 2;
   }
 }

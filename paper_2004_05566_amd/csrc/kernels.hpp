@@ -257,14 +257,16 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
 int cg_partial_slots();
 void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
                    hipStream_t s);
-// seq > 0: also post [iters, done, status] and then seq to the handle's host flag.
-void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s,
-                          int seq = 0);
+void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s);
+// The test closing a queued batch of iterations: as launch_cg_check_copy, and when the iteration
+// stops (here or earlier in the batch) u = x and the records of step `step`; then the outcome is
+// posted to the handle's host flag with sequence number seq.
+void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step, int seq,
+                            hipStream_t s);
 // The same test as arguments of a gated apply.
 CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol);
 void launch_cg_dot_rz(Handle& h, int it, hipStream_t s);
 void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipStream_t s);
 void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s);
-void launch_cg_finish(Handle& h, double* u, int step, hipStream_t s);
 
 }  // namespace hifcn

@@ -189,16 +189,46 @@ __device__ void post_flag(int32_t* hflag, int seq, int iters, int done, int stat
   *reinterpret_cast<volatile uint64_t*>(hflag + 6) = (uint64_t)(uint32_t)seq << 32 | lo;
 }
 
+// The end of a CN step: u = x, and the iteration count and relative residual ||r|| / ||g|| of
+// step `step` recorded (block 0).
+__device__ void finish_step(int64_t N, const double* __restrict__ x, double* __restrict__ u,
+                            int iters, double rr, double gg, int32_t* it_out, double* rel_out,
+                            int step) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads)
+    u[i] = x[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    it_out[step] = iters;
+    rel_out[step] = gg > 0 ? sqrt(rr / gg) : 0.0;
+  }
+}
+
+// The convergence test closing a queued batch of iterations (fin != nullptr) also ends the step
+// when the iteration stops, here or at an earlier test of the batch: finish_step, then the post
+// to the host (block 0).
+struct CgFinish {
+  int32_t* hflag;
+  int seq;
+  const double* x;
+  double* u;
+  int32_t* it_out;
+  double* rel_out;
+  int step;
+};
+
 __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init, int it0,
                                                             double rtol,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ z, CgState* st,
                                                             const double* __restrict__ part,
-                                                            int32_t* hflag, int seq) {
+                                                            CgFinish fin) {
   __shared__ int stop;
-  const bool post = hflag && blockIdx.x == 0 && threadIdx.x == 0;
+  const bool post = fin.hflag && blockIdx.x == 0 && threadIdx.x == 0;
   if (st->done) {  // stopped by an earlier test of the batch
-    if (post) post_flag(hflag, seq, st->iters, 1, st->status);
+    if (fin.hflag) {
+      finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
+      if (post) post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
+    }
     return;
   }
   const int nb = gridDim.x;
@@ -207,13 +237,19 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     const double* p = part + (init ? P_GG : P_RR) * (int64_t)nb;
     ct.load(p, nb);
     const double t = ct.sum(p, nb);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
       stop = cg_verdict(st, init, it0, rtol, t, st->tol2, st->maxit, blockIdx.x == 0);
-      if (post) post_flag(hflag, seq, st->iters, st->done, st->status);
-    }
   }
   __syncthreads();
-  if (stop) return;
+  if (stop) {
+    if (fin.hflag) {
+      // block 0 wrote the scalars it reads here; other blocks only copy x
+      finish_step(N, fin.x, fin.u, it0 + 1, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
+      if (post) post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
+    }
+    return;
+  }
+  if (post) post_flag(fin.hflag, fin.seq, it0 + 1, 0, 0);
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads)
     z[i] = r[i];
@@ -285,18 +321,6 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
   put_partial(acc, part + P_RR * (int64_t)nb);
 }
 
-__global__ __launch_bounds__(kThreads) void k_cg_finish(int64_t N, const double* __restrict__ x,
-                                                        double* __restrict__ u, const CgState* st,
-                                                        int32_t* iters, double* relres, int step) {
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads)
-    u[i] = x[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    iters[step] = st->iters;
-    relres[step] = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
-  }
-}
-
 }  // namespace
 
 int vec_blocks(int64_t N) {
@@ -331,10 +355,16 @@ void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, i
                      kind, k1, k2, h.dt, maxit, h.st.p, h.partials.p);
 }
 
-void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s, int seq) {
+void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it < 0 ? 1 : 0, it,
-                     rtol, h.r.p, h.z.p, h.st.p, h.partials.p, seq > 0 ? h.flag_dev : nullptr,
-                     seq);
+                     rtol, h.r.p, h.z.p, h.st.p, h.partials.p, CgFinish{});
+}
+
+void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step, int seq,
+                            hipStream_t s) {
+  const CgFinish fin{h.flag_dev, seq, h.x.p, u, h.step_iters.p, h.step_relres.p, step};
+  hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, 0, it, rtol,
+                     h.r.p, h.z.p, h.st.p, h.partials.p, fin);
 }
 
 CgGate cg_gate_args(Handle& h, int it, double rtol) {
@@ -363,12 +393,6 @@ void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipS
 void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, p, h.q.p, h.x.p,
                      h.r.p, h.st.p, h.partials.p);
-}
-
-void launch_cg_finish(Handle& h, double* u, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_finish, dim3(h.nblk), dim3(kThreads), 0, s, h.N, h.x.p, u, h.st.p,
-                     h.step_iters.p, h.step_relres.p, step);
-  HIF_CHECK(hipGetLastError());
 }
 
 }  // namespace hifcn
