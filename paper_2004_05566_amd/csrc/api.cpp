@@ -73,9 +73,9 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   h->x.alloc(h->N);
   h->r.alloc(h->N);
   h->z.alloc(h->N);
-  h->p0.alloc(h->N);
-  h->p1.alloc(h->N);
+  h->p.alloc(h->N);
   h->q.alloc(h->N);
+  h->w.alloc(h->N);
   h->partials.alloc((size_t)h->nblk * cg_partial_slots());
   h->st.alloc(1);
   HIF_CHECK(hipMemsetAsync(h->st.p, 0, sizeof(CgState), s));
@@ -136,25 +136,20 @@ void step_begin(StepState& st) {
   const double k1 = st.r ? st.r->k1 : 0, k2 = st.r ? st.r->k2 : 1;
   launch_cg_rhs(h, st.u, kind, k1, k2, st.o->maxit, st.s);
   check_and_apply(h, -1, st.o->rtol, st.s);
-  launch_cg_dot_rz(h, 0, st.s);
   st.chunk = std::max(1, h.last_iters);
 }
 
 // Queue the next chunk of iterations and the read-back of [iters, done, status].
 void step_queue(StepState& st) {
   Handle& h = *st.h;
-  const int* done = &h.st.p->done;
   if (st.tail_open) {  // the previous chunk's last iteration did not converge
-    hif_apply_inplace(h.f, h.z.p, done, st.s);
-    launch_cg_dot_rz(h, st.launched, st.s);
+    hif_apply_inplace(h.f, h.z.p, &h.st.p->done, st.s);
     st.tail_open = false;
   }
   for (int c = 0; c < st.chunk && st.launched < st.o->maxit; ++c) {
     const int it = st.launched++;
-    double* pin = (it & 1) ? h.p1.p : h.p0.p;
-    double* pout = (it & 1) ? h.p0.p : h.p1.p;
-    launch_cg_dir_spmv(h, it, pin, pout, st.s);
-    launch_cg_update(h, it, pout, st.s);
+    launch_cg_dir_dots(h, it, st.s);
+    launch_cg_update(h, it, st.s);
     if (c + 1 == st.chunk || st.launched == st.o->maxit) {
       // the host reads the verdict before it queues another apply
       st.seq = ++h.flag_seq;
@@ -163,7 +158,6 @@ void step_queue(StepState& st) {
       break;
     }
     check_and_apply(h, it, st.o->rtol, st.s);
-    launch_cg_dot_rz(h, it + 1, st.s);
   }
   HIF_CHECK(hipGetLastError());
 }
@@ -239,7 +233,7 @@ void check_reaction(const hif_reaction_t* r) {
 int64_t handle_device_bytes(const Handle& h) {
   int64_t b = 0;
   auto add = [&](const auto& buf) { b += (int64_t)(buf.n * sizeof(*buf.p)); };
-  add(h.links); add(h.x); add(h.r); add(h.z); add(h.p0); add(h.p1); add(h.q); add(h.partials);
+  add(h.links); add(h.x); add(h.r); add(h.z); add(h.p); add(h.q); add(h.w); add(h.partials);
   add(h.st); add(h.step_iters); add(h.step_relres);
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);

@@ -154,7 +154,8 @@ struct FactorHost {
 struct CgState {
   double gg;      // ||g||^2
   double tol2;    // rtol^2 ||g||^2
-  double rzv[2];  // rho = r.z of direction it, in slot it & 1 (kept by the direction kernel)
+  double rzv[2];  // rho = r.z of direction it, in slot it & 1 (kept by the update)
+  double pqv[2];  // p.Ap of direction it, in slot it & 1
   double rr;      // ||r||^2 after the latest update
   int32_t iters, done, status, maxit;
 };
@@ -178,7 +179,7 @@ struct Handle {
   DevBuf<double> links;       // per-axis link weights dt/(2h^2) * a_link, axis-major
   FactorDev f;
   // PCG workspace
-  DevBuf<double> x, r, z, p0, p1, q, partials;
+  DevBuf<double> x, r, z, p, q, w, partials;  // w = A z
   DevBuf<CgState> st;
   DevBuf<int32_t> step_iters;
   DevBuf<double> step_relres;
@@ -265,8 +266,9 @@ void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step,
                             hipStream_t s);
 // The same test as arguments of a gated apply.
 CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol);
-void launch_cg_dot_rz(Handle& h, int it, hipStream_t s);
-void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipStream_t s);
-void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s);
+// Iteration `it` after z = M^-1 r: w = A z with the partials of r.z, z.w, z.q, then the update
+// of p, q = A p, x and r with the partials of ||r||^2.
+void launch_cg_dir_dots(Handle& h, int it, hipStream_t s);
+void launch_cg_update(Handle& h, int it, hipStream_t s);
 
 }  // namespace hifcn

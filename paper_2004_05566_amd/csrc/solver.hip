@@ -5,12 +5,15 @@
 // u - sum_links w (u_j - u_nbr) (Dirichlet: p = 0 beyond the boundary).
 //
 // PCG keeps every scalar on the device (CgState), so a whole iteration is queued without a
-// host round trip: the direction update p = z + beta p is fused into the SpMV (each lane
-// rebuilds the new direction at its stencil points from z and the previous direction, written
-// to a second buffer), p.q, r.z and ||r||^2 are fused reductions with a deterministic two-level
-// sum (per-block partials, re-added in a fixed order by the kernel that consumes them), and
-// the convergence test ||r|| <= rtol ||g|| sets a device flag that makes every later kernel of
-// the step return.
+// host round trip.  The iteration is arranged with one reduction phase between the
+// preconditioner and the update (the single-reduction form of Chronopoulos and Gear): the SpMV
+// is applied to z (w = A z) together with the partial sums of r.z, z.w and z.q (q = A p of the
+// previous direction); the update then forms beta = rho / rho_prev, p.Ap = z.w + 2 beta z.q +
+// beta^2 p_prev.A p_prev (A is symmetric), alpha = rho / p.Ap, p = z + beta p, q = w + beta q,
+// x += alpha p, r -= alpha q: the iterates of Algorithm 1 in exact arithmetic.  Reductions are
+// deterministic two-level sums (per-block partials, re-added in a fixed order by the kernel that
+// consumes them), and the convergence test ||r|| <= rtol ||g|| sets a device flag that makes
+// every later kernel of the step return.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "cg_gate.hpp"
@@ -148,8 +151,31 @@ __device__ __forceinline__ double react(double u, int kind, double k1, double k2
   return kind == 1 ? k1 * u * (1.0 - u / k2) : 0.0;
 }
 
-// Partial-sum slots (each nblk long): ||g||^2, p.q, ||r||^2, r.z for even / odd iterations.
-enum { P_GG = 0, P_PQ = 1, P_RR = 2, P_RZ0 = 3 };
+// Partial-sum slots (each nblk long): ||g||^2, ||r||^2, and the direction kernel's r.z, z.w, z.q.
+enum { P_GG = 0, P_RR = 1, P_RZ = 2, P_ZW = 3, P_ZQ = 4, P_SLOTS = 5 };
+
+// Three block sums at once (one pair of barriers); valid in every lane.
+__device__ void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red[3][kThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  __syncthreads();
+  if (lane == 0) {
+    red[0][wid] = a;
+    red[1][wid] = b;
+    red[2][wid] = c;
+  }
+  __syncthreads();
+  a = b = c = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    a += red[0][w];
+    b += red[1][w];
+    c += red[2][w];
+  }
+}
 
 // g = (I + dt/2 M) u + dt r(u) -> r; x = 0; partials of ||g||^2.
 template <int DIM>
@@ -255,66 +281,73 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     z[i] = r[i];
 }
 
-// r.z for the direction of iteration `it` (slot it & 1).
-__global__ __launch_bounds__(kThreads) void k_cg_dot_rz(int64_t N, int it,
-                                                        const double* __restrict__ r,
-                                                        const double* __restrict__ z,
-                                                        const CgState* st, double* part) {
-  if (st->done) return;
-  double acc = 0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads)
-    acc += r[i] * z[i];
-  put_partial(acc, part + (P_RZ0 + (it & 1)) * (int64_t)gridDim.x);
-}
-
-// p_out = z + beta p_in (beta = 0 on the first iteration), q = A p_out, partials of p_out.q.
-// rho of this direction is totalled here once (block 0 keeps it in rzv[it & 1] for the update
-// and the next direction; no block reads that slot in this launch).
+// w = A z and the partial sums of r.z, z.w and (after the first iteration) z.q.
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_cg_dir_spmv(int n, int64_t N, int it,
-                                                          const double* __restrict__ w,
+__global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int it,
+                                                          const double* __restrict__ lw,
                                                           const double* __restrict__ z,
-                                                          const double* __restrict__ pin,
-                                                          double* __restrict__ pout,
-                                                          double* __restrict__ q,
-                                                          CgState* st, double* part) {
+                                                          const double* __restrict__ r,
+                                                          const double* __restrict__ q,
+                                                          double* __restrict__ w,
+                                                          const CgState* st, double* part) {
   if (st->done) return;
   const int nb = gridDim.x;
-  const bool first = it == 0;
-  const double rz = total(part + (P_RZ0 + (it & 1)) * (int64_t)nb, nb);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->rzv[it & 1] = rz;
-  const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
-  double acc = 0;
+  double rz = 0, zw = 0, zq = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
-    auto pv = [&](int64_t k) { return first ? z[k] : z[k] + beta * pin[k]; };
-    const double pi = pv(i);
-    const double qi = pi + link_sum<DIM>(i, n, w, pi, pv);
-    pout[i] = pi;
-    q[i] = qi;
-    acc += pi * qi;
+    const double zi = z[i];
+    const double wi = zi + link_sum<DIM>(i, n, lw, zi, [&](int64_t k) { return z[k]; });
+    w[i] = wi;
+    rz += r[i] * zi;
+    zw += zi * wi;
+    if (it > 0) zq += zi * q[i];
   }
-  put_partial(acc, part + P_PQ * (int64_t)nb);
+  block_sum3(rz, zw, zq);
+  if (threadIdx.x == 0) {
+    part[P_RZ * (int64_t)nb + blockIdx.x] = rz;
+    part[P_ZW * (int64_t)nb + blockIdx.x] = zw;
+    part[P_ZQ * (int64_t)nb + blockIdx.x] = zq;
+  }
 }
 
-// alpha = r.z / p.q; x += alpha p; r -= alpha q; partials of ||r||^2.
+// rho = r.z, beta = rho / rho_prev (0 on the first iteration), p.Ap from the expansion above,
+// alpha = rho / p.Ap; p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q; partials of
+// ||r||^2.  Block 0 keeps rho and p.Ap in slot it & 1 of the state for the next direction (no
+// block reads that slot in this launch).
 __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
-                                                        const double* __restrict__ p,
-                                                        const double* __restrict__ q,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ p,
+                                                        double* __restrict__ q,
                                                         double* __restrict__ x,
-                                                        double* __restrict__ r, const CgState* st,
+                                                        double* __restrict__ r, CgState* st,
                                                         double* part) {
   if (st->done) return;
   const int nb = gridDim.x;
-  const double rz = st->rzv[it & 1];
-  const double pq = total(part + P_PQ * (int64_t)nb, nb);
+  double rz = 0, zw = 0, zq = 0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    rz += part[P_RZ * (int64_t)nb + i];
+    zw += part[P_ZW * (int64_t)nb + i];
+    zq += part[P_ZQ * (int64_t)nb + i];
+  }
+  block_sum3(rz, zw, zq);
+  const bool first = it == 0;
+  const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
+  const double pq = first ? zw : zw + beta * (2.0 * zq + beta * st->pqv[(it + 1) & 1]);
   const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rzv[it & 1] = rz;
+    st->pqv[it & 1] = pq;
+  }
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+    const double pi = first ? z[i] : z[i] + beta * p[i];
+    const double qi = first ? w[i] : w[i] + beta * q[i];
+    p[i] = pi;
+    q[i] = qi;
+    x[i] += alpha * pi;
+    const double ri = r[i] - alpha * qi;
     r[i] = ri;
     acc += ri * ri;
   }
@@ -328,7 +361,7 @@ int vec_blocks(int64_t N) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 512));
 }
 
-int cg_partial_slots() { return P_RZ0 + 2; }
+int cg_partial_slots() { return P_SLOTS; }
 
 void launch_links(const double* a_cells, int dim, int n, double scale, double* links,
                   hipStream_t s) {
@@ -379,20 +412,15 @@ CgGate cg_gate_args(Handle& h, int it, double rtol) {
   return g;
 }
 
-void launch_cg_dot_rz(Handle& h, int it, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dot_rz, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, h.r.p, h.z.p,
-                     h.st.p, h.partials.p);
+void launch_cg_dir_dots(Handle& h, int it, hipStream_t s) {
+  auto k = h.dim == 2 ? k_cg_dir_dots<2> : k_cg_dir_dots<3>;
+  hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, it, h.links.p, h.z.p, h.r.p,
+                     h.q.p, h.w.p, h.st.p, h.partials.p);
 }
 
-void launch_cg_dir_spmv(Handle& h, int it, const double* pin, double* pout, hipStream_t s) {
-  auto k = h.dim == 2 ? k_cg_dir_spmv<2> : k_cg_dir_spmv<3>;
-  hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, it, h.links.p, h.z.p, pin,
-                     pout, h.q.p, h.st.p, h.partials.p);
-}
-
-void launch_cg_update(Handle& h, int it, const double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, p, h.q.p, h.x.p,
-                     h.r.p, h.st.p, h.partials.p);
+void launch_cg_update(Handle& h, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, h.z.p, h.w.p,
+                     h.p.p, h.q.p, h.x.p, h.r.p, h.st.p, h.partials.p);
 }
 
 }  // namespace hifcn
