@@ -281,7 +281,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     z[i] = r[i];
 }
 
-// w = A z and the partial sums of r.z, z.w and (after the first iteration) z.q.
+// w = A z and the partial sums of r.z, z.w and (after the first iteration) z.q.  Runs whether
+// or not the iteration has stopped: its outputs are scratch that nothing reads once it has, and
+// not waiting for the flag lets the first loads go out at once.
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int it,
                                                           const double* __restrict__ lw,
@@ -289,8 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int 
                                                           const double* __restrict__ r,
                                                           const double* __restrict__ q,
                                                           double* __restrict__ w,
-                                                          const CgState* st, double* part) {
-  if (st->done) return;
+                                                          double* part) {
   const int nb = gridDim.x;
   double rz = 0, zw = 0, zq = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
@@ -313,7 +314,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int 
 // rho = r.z, beta = rho / rho_prev (0 on the first iteration), p.Ap from the expansion above,
 // alpha = rho / p.Ap; p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q; partials of
 // ||r||^2.  Block 0 keeps rho and p.Ap in slot it & 1 of the state for the next direction (no
-// block reads that slot in this launch).
+// block reads that slot in this launch).  Once the iteration has stopped nothing is stored but
+// the partials (scratch): the flag is read with the other loads, not waited for first.
 __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
                                                         const double* __restrict__ z,
                                                         const double* __restrict__ w,
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
                                                         double* __restrict__ x,
                                                         double* __restrict__ r, CgState* st,
                                                         double* part) {
-  if (st->done) return;
+  const int dn = st->done;
   const int nb = gridDim.x;
   double rz = 0, zw = 0, zq = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
   const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
   const double pq = first ? zw : zw + beta * (2.0 * zq + beta * st->pqv[(it + 1) & 1]);
   const double alpha = rz / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !dn) {
     st->rzv[it & 1] = rz;
     st->pqv[it & 1] = pq;
   }
@@ -344,12 +346,15 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
        i += (int64_t)gridDim.x * kThreads) {
     const double pi = first ? z[i] : z[i] + beta * p[i];
     const double qi = first ? w[i] : w[i] + beta * q[i];
-    p[i] = pi;
-    q[i] = qi;
-    x[i] += alpha * pi;
+    const double xi = x[i] + alpha * pi;
     const double ri = r[i] - alpha * qi;
-    r[i] = ri;
     acc += ri * ri;
+    if (!dn) {
+      p[i] = pi;
+      q[i] = qi;
+      x[i] = xi;
+      r[i] = ri;
+    }
   }
   put_partial(acc, part + P_RR * (int64_t)nb);
 }
@@ -415,7 +420,7 @@ CgGate cg_gate_args(Handle& h, int it, double rtol) {
 void launch_cg_dir_dots(Handle& h, int it, hipStream_t s) {
   auto k = h.dim == 2 ? k_cg_dir_dots<2> : k_cg_dir_dots<3>;
   hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, it, h.links.p, h.z.p, h.r.p,
-                     h.q.p, h.w.p, h.st.p, h.partials.p);
+                     h.q.p, h.w.p, h.partials.p);
 }
 
 void launch_cg_update(Handle& h, int it, hipStream_t s) {
