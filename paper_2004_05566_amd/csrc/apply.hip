@@ -264,13 +264,21 @@ __device__ __forceinline__ C team_sum(C v, int team) {
 // of `team` lanes splitting the inner dot product.
 //   mode 0 (dense H):  w = L^-1 y_I and c = H y_I as nI + nB independent dot products.
 //   mode 1 (links):    w = L^-1 y_I, v = L^-T w (= A_II^-1 y_I), c_b = A_BI(b, ib_b) v_ib_b.
-template <typename S, typename C, bool ST, int MODE>
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
 // prestaged: the block is already in LDS (a fused launch loads it while its groups run).
+// hook: run by every lane once the block and inputs are on their way to LDS, before the barrier
+// that publishes them; stop (LDS): looked at after that barrier, nothing is written if set.
+template <typename S, typename C, bool ST, int MODE, typename Hook = NoHook>
 __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* __restrict__ idx,
                                               const S* __restrict__ vals, double* __restrict__ y,
                                               double* __restrict__ cb, int blk_elems, int team,
                                               bool prestaged, unsigned char* smem_raw,
-                                              const double* __restrict__ in = nullptr) {
+                                              const double* __restrict__ in = nullptr,
+                                              Hook hook = Hook{},
+                                              const int* stop = nullptr) {
   // in: where the interior values are read (y unless the input vector is another one)
   const double* src = in ? in : y;
   C* sm = reinterpret_cast<C*>(smem_raw);
@@ -294,7 +302,9 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
   if constexpr (MODE == 1)
     for (int b = threadIdx.x; b < nB; b += blockDim.x) ib[b] = idx[d.offC + b];
+  hook();
   __syncthreads();
+  if (stop && *stop) return;
   const int part = threadIdx.x % team, per = blockDim.x / team;
   const int nout = mode ? nI : nI + nB;
   for (int ob = 0; ob < nout; ob += per) {
@@ -359,24 +369,25 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
     if ((int)threadIdx.x < gcstride - 1) cid = cp[1 + threadIdx.x];
   }
   load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
-  int dn = 0;
-  if (gated) {
-    if (cid >= 0) cval = gate.src[cid];  // (padding entries read DOF 0; never stored)
-    if (threadIdx.x < 64) {
-      const double t = ct.sum(gate.part, gate.nb);
-      // stopped by an earlier test: nothing to publish
-      if (threadIdx.x == 0)
-        gstop = g_done ? 1 : cg_verdict(gate.st, gate.init, gate.it0, gate.rtol, t, g_tol2,
-                                        g_maxit, blockIdx.x == 0);
-    }
-  } else {
-    dn = done ? *done : 0;
-  }
+  const int dn = gated ? 0 : (done ? *done : 0);
+  if (gated && cid >= 0) cval = gate.src[cid];  // (padding entries read DOF 0; never stored)
   __syncthreads();
-  if (gated ? gstop : dn) return;
+  if (dn) return;
   const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  // the test's verdict is reached while the cell's block and inputs load (they are only read
+  // before it is known)
+  auto verdict = [&]() {
+    if (!gated || threadIdx.x >= 64) return;
+    const double t = ct.sum(gate.part, gate.nb);
+    // stopped by an earlier test: nothing to publish
+    if (threadIdx.x == 0)
+      gstop = g_done ? 1 : cg_verdict(gate.st, gate.init, gate.it0, gate.rtol, t, g_tol2,
+                                      g_maxit, blockIdx.x == 0);
+  };
   cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
-                                smem_raw + 4 * stride, gate.src);
+                                smem_raw + 4 * stride, gate.src, verdict,
+                                gated ? &gstop : nullptr);
+  if (gated && gstop) return;
   if (gated) {  // the DOFs outside every interior that this cell hands over unchanged
     if ((int)threadIdx.x < ccnt) y[cid] = cval;
     for (int e = threadIdx.x + blockDim.x; e < ccnt; e += blockDim.x)
