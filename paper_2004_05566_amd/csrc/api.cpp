@@ -82,9 +82,9 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   h->step_iters.alloc(1);
   h->step_relres.alloc(1);
   // see Handle::host_flag
-  HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 8 * sizeof(int32_t),
+  HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h->host_flag), 16 * sizeof(int32_t),
                           hipHostMallocMapped | hipHostMallocCoherent));
-  std::memset(h->host_flag, 0, 8 * sizeof(int32_t));
+  std::memset(h->host_flag, 0, 16 * sizeof(int32_t));
   HIF_CHECK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->flag_dev), h->host_flag, 0));
   return h;
 }
@@ -121,21 +121,23 @@ struct StepState {
 // run by the apply's first stage when the factor allows it, else as its own launch.  Every
 // workgroup of that stage reads all partials of the test, so it stays a launch of its own where
 // that would add up to more than ~8 MB (many level-0 cells: the 1024^2 grid has 16K).
-void check_and_apply(Handle& h, int it, double rtol, hipStream_t s) {
+void check_and_apply(Handle& h, int it, double rtol, int maxit, hipStream_t s) {
   if (h.f.gate && h.f.gate_n == h.N && (int64_t)h.f.lv[0].ncell * h.nblk <= (int64_t(1) << 20)) {
-    hif_apply_gated(h.f, h.z.p, cg_gate_args(h, it, rtol), s);
+    hif_apply_gated(h.f, h.z.p, cg_gate_args(h, it, rtol, maxit), s);
   } else {
-    launch_cg_check_copy(h, it, rtol, s);
+    launch_cg_check_copy(h, it, rtol, maxit, s);
     hif_apply_inplace(h.f, h.z.p, &h.st.p->done, s);
   }
 }
 
-void step_begin(StepState& st) {
+// ahead: queued before the previous step of the same solve is known to have ended well (if it
+// did not, the whole step does nothing and is queued again).
+void step_begin(StepState& st, bool ahead = false) {
   Handle& h = *st.h;
   const int kind = st.r ? st.r->kind : 0;
   const double k1 = st.r ? st.r->k1 : 0, k2 = st.r ? st.r->k2 : 1;
-  launch_cg_rhs(h, st.u, kind, k1, k2, st.o->maxit, st.s);
-  check_and_apply(h, -1, st.o->rtol, st.s);
+  launch_cg_rhs(h, st.u, kind, k1, k2, ahead, st.s);
+  check_and_apply(h, -1, st.o->rtol, st.o->maxit, st.s);
   st.chunk = std::max(1, h.last_iters);
 }
 
@@ -143,6 +145,7 @@ void step_begin(StepState& st) {
 void step_queue(StepState& st) {
   Handle& h = *st.h;
   if (st.tail_open) {  // the previous chunk's last iteration did not converge
+    launch_cg_resume(h, st.s);  // (a step queued ahead may have stopped everything meanwhile)
     hif_apply_inplace(h.f, h.z.p, &h.st.p->done, st.s);
     st.tail_open = false;
   }
@@ -157,7 +160,7 @@ void step_queue(StepState& st) {
       st.tail_open = true;
       break;
     }
-    check_and_apply(h, it, st.o->rtol, st.s);
+    check_and_apply(h, it, st.o->rtol, st.o->maxit, st.s);
   }
   HIF_CHECK(hipGetLastError());
 }
@@ -167,7 +170,7 @@ void step_queue(StepState& st) {
 // without the post is an error.
 void step_wait(StepState& st) {
   int32_t* f = st.h->host_flag;
-  const volatile uint64_t* w = reinterpret_cast<const volatile uint64_t*>(f + 6);
+  const volatile uint64_t* w = reinterpret_cast<const volatile uint64_t*>(f + 8 + 2 * (st.seq & 1));
   uint64_t v = 0;
   for (int64_t n = 1;; ++n) {
     v = *w;
@@ -199,8 +202,8 @@ void step_after_sync(StepState& st) {
   }
 }
 
-void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u, int step,
-                 hipStream_t s) {
+StepState step_state(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u,
+                     int step, hipStream_t s) {
   StepState st;
   st.h = &h;
   st.s = s;
@@ -208,12 +211,45 @@ void cn_step_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, dou
   st.o = o;
   st.u = u;
   st.step = step;
-  step_begin(st);
-  while (!st.finished) {
-    step_queue(st);
-    step_wait(st);
-    step_after_sync(st);
+  return st;
+}
+
+// Steps of one solve.  Step k+1 is queued (ahead) before step k's outcome is read, so the GPU
+// does not wait for the host between steps; when step k did not end well within its predicted
+// iterations, the step queued ahead does nothing (hold) and is queued again once step k is over.
+// Returns the first step that did not converge, or -1.
+int cn_steps_dev(Handle& h, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u,
+                 int nsteps, hipStream_t s) {
+  const bool ahead_on = std::getenv("HIFCN_NO_AHEAD") == nullptr;
+  if (nsteps <= 0) return -1;
+  StepState cur = step_state(h, r, o, u, 0, s);
+  step_begin(cur);
+  step_queue(cur);
+  for (int k = 0; k < nsteps; ++k) {
+    const bool ahead = ahead_on && k + 1 < nsteps;
+    StepState nxt = step_state(h, r, o, u, k + 1, s);
+    if (ahead) {
+      step_begin(nxt, true);
+      step_queue(nxt);
+    }
+    step_wait(cur);
+    step_after_sync(cur);
+    bool held = !cur.finished;
+    while (!cur.finished) {
+      step_queue(cur);
+      step_wait(cur);
+      step_after_sync(cur);
+    }
+    if (cur.status != 0) return k;
+    if (k + 1 == nsteps) break;
+    if (!ahead || held) {
+      nxt = step_state(h, r, o, u, k + 1, s);
+      step_begin(nxt);
+      step_queue(nxt);
+    }
+    cur = nxt;
   }
+  return -1;
 }
 
 void check_opts(const hif_cg_opts_t* o) {
@@ -326,11 +362,7 @@ hif_status_t cn_solve(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opt
       h.step_iters.alloc(std::max(1, nsteps));
       h.step_relres.alloc(std::max(1, nsteps));
     }
-    int failed_step = -1;
-    for (int k = 0; k < nsteps; ++k) {
-      cn_step_dev(h, r, o, u, k, s);
-      if (h.host_flag[2] != 0) { failed_step = k; break; }  // status of the step just made
-    }
+    const int failed_step = cn_steps_dev(h, r, o, u, nsteps, s);
     const int done_steps = failed_step >= 0 ? failed_step + 1 : nsteps;
     std::vector<int32_t> it(std::max(1, done_steps));
     std::vector<double> rr(std::max(1, done_steps));

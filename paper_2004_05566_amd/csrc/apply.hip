@@ -362,9 +362,11 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
   const int32_t* cp = gcopy + (int64_t)blockIdx.x * gcstride;
   if (gated) {
     if (threadIdx.x < 64) ct.load(gate.part, gate.nb);
-    g_done = gate.st->done;
+    // the test of g (init) looks at hold only (the right-hand side just set it; done is the
+    // previous step's); later tests at done (set by an earlier test of the step)
+    g_done = gate.init ? gate.st->hold : gate.st->done;
     g_tol2 = gate.st->tol2;
-    g_maxit = gate.st->maxit;
+    g_maxit = gate.init ? gate.maxit : gate.st->maxit;
     ccnt = cp[0];
     if ((int)threadIdx.x < gcstride - 1) cid = cp[1 + threadIdx.x];
   }
@@ -379,10 +381,14 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
   auto verdict = [&]() {
     if (!gated || threadIdx.x >= 64) return;
     const double t = ct.sum(gate.part, gate.nb);
-    // stopped by an earlier test: nothing to publish
-    if (threadIdx.x == 0)
-      gstop = g_done ? 1 : cg_verdict(gate.st, gate.init, gate.it0, gate.rtol, t, g_tol2,
-                                      g_maxit, blockIdx.x == 0);
+    if (threadIdx.x != 0) return;
+    if (g_done) {  // stopped by an earlier test: nothing to publish (a held step: stop it)
+      if (gate.init && blockIdx.x == 0) gate.st->done = 1;
+      gstop = 1;
+    } else {
+      gstop = cg_verdict(gate.st, gate.init, gate.it0, gate.rtol, t, g_tol2, g_maxit,
+                         blockIdx.x == 0);
+    }
   };
   cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
                                 smem_raw + 4 * stride, gate.src, verdict,

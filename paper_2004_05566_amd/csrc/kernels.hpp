@@ -158,6 +158,11 @@ struct CgState {
   double pqv[2];  // p.Ap of direction it, in slot it & 1
   double rr;      // ||r||^2 after the latest update
   int32_t iters, done, status, maxit;
+  // hold: set by the right-hand side of a step queued ahead of the previous step's outcome when
+  // that step did not end well (it goes on, or failed); the step's test of g then sets done, so
+  // the rest of it does nothing; cleared by the next right-hand side or by the resume of the
+  // previous step
+  int32_t hold, pad;
 };
 
 // A convergence test of the PCG run by the first stage of a preconditioner apply instead of its
@@ -167,7 +172,7 @@ struct CgState {
 struct CgGate {
   CgState* st = nullptr;
   const double* part = nullptr;
-  int nb = 0, init = 0, it0 = 0;
+  int nb = 0, init = 0, it0 = 0, maxit = 0;
   double rtol = 0;
   const double* src = nullptr;
 };
@@ -184,8 +189,9 @@ struct Handle {
   DevBuf<int32_t> step_iters;
   DevBuf<double> step_relres;
   // pinned, device-mapped: [0..2] iters, done, status of the running step (decoded by the host
-  // from [6..7], the 64-bit word that the last convergence test of a queued batch of iterations
-  // posts together with its sequence number flag_seq); [4..5] the last batched step's relres
+  // from [8 + 2 (seq & 1)], the 64-bit word that the last convergence test of a queued batch of
+  // iterations posts together with its sequence number flag_seq: two steps may be in flight);
+  // [4..5] the last batched step's relres
   int32_t* host_flag = nullptr;
   int32_t* flag_dev = nullptr;  // host_flag as seen from the device
   int32_t flag_seq = 0;
@@ -256,16 +262,21 @@ void launch_links(const double* a_cells, int dim, int n, double scale, double* l
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
 // PCG kernels; `it` is the 0-based index of the CG iteration (host-side count).
 int cg_partial_slots();
-void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
+// ahead: the step is queued before the previous one is known to have ended; it does nothing if
+// that one holds.
+void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, bool ahead,
                    hipStream_t s);
-void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, hipStream_t s);
+// Before more iterations of a step whose closing test held: done = hold = 0.
+void launch_cg_resume(Handle& h, hipStream_t s);
+void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, int maxit,
+                          hipStream_t s);
 // The test closing a queued batch of iterations: as launch_cg_check_copy, and when the iteration
 // stops (here or earlier in the batch) u = x and the records of step `step`; then the outcome is
 // posted to the handle's host flag with sequence number seq.
 void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step, int seq,
                             hipStream_t s);
 // The same test as arguments of a gated apply.
-CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol);
+CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol, int maxit);
 // Iteration `it` after z = M^-1 r: w = A z with the partials of r.z, z.w, z.q, then the update
 // of p, q = A p, x and r with the partials of ||r||^2.
 void launch_cg_dir_dots(Handle& h, int it, hipStream_t s);

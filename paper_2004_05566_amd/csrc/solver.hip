@@ -177,13 +177,19 @@ __device__ void block_sum3(double& a, double& b, double& c) {
   }
 }
 
-// g = (I + dt/2 M) u + dt r(u) -> r; x = 0; partials of ||g||^2.
+// g = (I + dt/2 M) u + dt r(u) -> r; x = 0; partials of ||g||^2 (the test of g that follows
+// resets the step's scalars).
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const double* __restrict__ w,
                                                      const double* __restrict__ u,
                                                      double* __restrict__ r, double* __restrict__ x,
                                                      int kind, double k1, double k2, double dt,
-                                                     int maxit, CgState* st, double* part) {
+                                                     int ahead, CgState* st, double* part) {
+  // queued ahead of the previous step's outcome: nothing to do unless that step ended well
+  // (every block reads the same two fields, which no block writes here)
+  const bool held = ahead && (!st->done || st->status);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->hold = held ? 1 : 0;
+  if (held) return;
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
@@ -195,11 +201,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
     acc += g * g;
   }
   put_partial(acc, part + P_GG * (int64_t)gridDim.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->iters = 0;
-    st->status = 0;
+}
+
+__global__ void k_cg_resume(CgState* st) {
+  if (threadIdx.x == 0) {
     st->done = 0;
-    st->maxit = maxit;
+    st->hold = 0;
   }
 }
 
@@ -210,9 +217,11 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
 // it comes from the host so that no block reads a scalar that block 0 rewrites in this launch.
 // With hflag, block 0 also posts the outcome to the host as one aligned 64-bit store (seen
 // whole or not at all): seq in the high word, iters | done << 24 | status << 28 in the low one.
+// The word of sequence number seq is hflag[8 + 2 (seq & 1)].
 __device__ void post_flag(int32_t* hflag, int seq, int iters, int done, int status) {
   const uint64_t lo = (uint32_t)iters | (uint32_t)done << 24 | (uint32_t)status << 28;
-  *reinterpret_cast<volatile uint64_t*>(hflag + 6) = (uint64_t)(uint32_t)seq << 32 | lo;
+  *reinterpret_cast<volatile uint64_t*>(hflag + 8 + 2 * (seq & 1)) =
+      (uint64_t)(uint32_t)seq << 32 | lo;
 }
 
 // The end of a CN step: u = x, and the iteration count and relative residual ||r|| / ||g|| of
@@ -231,7 +240,8 @@ __device__ void finish_step(int64_t N, const double* __restrict__ x, double* __r
 
 // The convergence test closing a queued batch of iterations (fin != nullptr) also ends the step
 // when the iteration stops, here or at an earlier test of the batch: finish_step, then the post
-// to the host (block 0).
+// to the host (block 0).  A closing test that finds hold set belongs to a step queued ahead of
+// one that did not end well, and does nothing.
 struct CgFinish {
   int32_t* hflag;
   int seq;
@@ -243,14 +253,20 @@ struct CgFinish {
 };
 
 __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init, int it0,
-                                                            double rtol,
+                                                            double rtol, int maxit,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ z, CgState* st,
                                                             const double* __restrict__ part,
                                                             CgFinish fin) {
   __shared__ int stop;
   const bool post = fin.hflag && blockIdx.x == 0 && threadIdx.x == 0;
-  if (st->done) {  // stopped by an earlier test of the batch
+  if (fin.hflag && st->hold) return;  // queued ahead of a step that did not end well
+  if (init) {  // the test of the right-hand side publishes the state of the new step
+    if (st->hold) {  // (queued ahead, see k_cg_rhs): later kernels of the step do nothing
+      if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 1;
+      return;
+    }
+  } else if (st->done) {  // stopped by an earlier test of the batch
     if (fin.hflag) {
       finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
       if (post) post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
@@ -264,7 +280,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     ct.load(p, nb);
     const double t = ct.sum(p, nb);
     if (threadIdx.x == 0)
-      stop = cg_verdict(st, init, it0, rtol, t, st->tol2, st->maxit, blockIdx.x == 0);
+      stop = cg_verdict(st, init, it0, rtol, t, st->tol2, init ? maxit : st->maxit,
+                        blockIdx.x == 0);
   }
   __syncthreads();
   if (stop) {
@@ -386,27 +403,32 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
   HIF_CHECK(hipGetLastError());
 }
 
-void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, int maxit,
+void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, bool ahead,
                    hipStream_t s) {
   auto k = h.dim == 2 ? k_cg_rhs<2> : k_cg_rhs<3>;
   hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, u, h.r.p, h.x.p,
-                     kind, k1, k2, h.dt, maxit, h.st.p, h.partials.p);
+                     kind, k1, k2, h.dt, ahead ? 1 : 0, h.st.p, h.partials.p);
 }
 
-void launch_cg_check_copy(Handle& h, int it, double rtol, hipStream_t s) {
+void launch_cg_resume(Handle& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_resume, dim3(1), dim3(64), 0, s, h.st.p);
+}
+
+void launch_cg_check_copy(Handle& h, int it, double rtol, int maxit, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it < 0 ? 1 : 0, it,
-                     rtol, h.r.p, h.z.p, h.st.p, h.partials.p, CgFinish{});
+                     rtol, maxit, h.r.p, h.z.p, h.st.p, h.partials.p, CgFinish{});
 }
 
 void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step, int seq,
                             hipStream_t s) {
   const CgFinish fin{h.flag_dev, seq, h.x.p, u, h.step_iters.p, h.step_relres.p, step};
-  hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, 0, it, rtol,
+  hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, 0, it, rtol, 0,
                      h.r.p, h.z.p, h.st.p, h.partials.p, fin);
 }
 
-CgGate cg_gate_args(Handle& h, int it, double rtol) {
+CgGate cg_gate_args(Handle& h, int it, double rtol, int maxit) {
   CgGate g;
+  g.maxit = maxit;
   g.st = h.st.p;
   g.nb = h.nblk;
   g.init = it < 0 ? 1 : 0;

@@ -63,3 +63,66 @@ def test_gated_apply_zero_rhs_stops_at_once(gpu_lib):
     its, rel = h.cn_solve(u, 2)
     assert list(its) == [0, 0] and not u.any()
     h.close()
+
+
+def _solve(h, u0, steps, **kw):
+    import torch
+    u = torch.tensor(u0, device="cuda")
+    its, rel = h.cn_solve(u, steps, **kw)
+    return u, list(its), list(rel)
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_steps_queued_ahead_match_one_at_a_time(case, gpu_lib):
+    """Each CN step is queued before the previous one's outcome is read; when that step needs
+    more iterations than predicted, the step queued ahead does nothing and is queued again.
+    Same arithmetic either way: bitwise equal to queuing one step at a time (HIFCN_NO_AHEAD)."""
+    name, n, dim, leaf, store = case
+    print(f"[case] {name}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.12, 98)
+    # a large first step then small ones: the predicted iteration count misses in places
+    u0 = (5.0 * gen.bumps(n, dim, 4, 99)).ravel()
+    h = _factor(a, n, dim, leaf, store, True)
+    out = []
+    for ahead in (True, False):
+        if not ahead:
+            os.environ["HIFCN_NO_AHEAD"] = "1"
+        try:
+            out.append(_solve(h, u0, 6, rtol=1e-11, reaction=(1, 1.0, 1.0)))
+        finally:
+            os.environ.pop("HIFCN_NO_AHEAD", None)
+    h.close()
+    (u1, i1, r1), (u0_, i0, r0) = out
+    assert i1 == i0 and r1 == r0
+    assert torch_equal(u1, u0_)
+
+
+def torch_equal(a, b):
+    import torch
+    return torch.equal(a, b)
+
+
+def test_failed_step_stops_the_steps_queued_ahead(gpu_lib):
+    """A step that hits maxit ends the solve there: the step queued behind it changes nothing,
+    so u holds the failed step's last iterate (as when steps are queued one at a time)."""
+    from paper_2004_05566_amd import hifcn
+    n = 48
+    a = gen.grf_coefficient(n, 2, 0.12, 100)
+    u0 = gen.bumps(n, 2, 3, 101).ravel()
+    h = _factor(a, n, 2, 8, "f64", True)
+    res = []
+    for ahead in (True, False):
+        if not ahead:
+            os.environ["HIFCN_NO_AHEAD"] = "1"
+        import torch
+        u = torch.tensor(u0, device="cuda")
+        try:
+            with pytest.raises(hifcn.HifError) as ei:
+                h.cn_solve(u, 4, rtol=1e-30, maxit=1)
+            assert ei.value.status == hifcn.HIF_ERR_NO_CONV
+        finally:
+            os.environ.pop("HIFCN_NO_AHEAD", None)
+        res.append(u)
+    h.close()
+    assert torch_equal(res[0], res[1])
+    assert not torch_equal(res[0], torch.tensor(u0, device="cuda"))
