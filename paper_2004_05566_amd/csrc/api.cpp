@@ -117,6 +117,15 @@ struct StepState {
   int status = 0;
 };
 
+// Whether the first apply stage of a step makes its right-hand side: as for the test in that stage
+// (check_and_apply), and HIFCN_NO_RHS_FUSE unset.
+void setup_rhs(Handle& h) {
+  h.rhs_fused = h.f.gate && h.f.gate_n == h.N &&
+                (int64_t)h.f.lv[0].ncell * h.nblk <= (int64_t(1) << 20) &&
+                !std::getenv("HIFCN_NO_RHS_FUSE");
+  if (h.rhs_fused) h.gpart.alloc(h.f.lv[0].ncell);
+}
+
 // The convergence test after iteration `it` (-1: of the right-hand side) followed by z = M^-1 r:
 // run by the apply's first stage when the factor allows it, else as its own launch.  Every
 // workgroup of that stage reads all partials of the test, so it stays a launch of its own where
@@ -136,8 +145,27 @@ void step_begin(StepState& st, bool ahead = false) {
   Handle& h = *st.h;
   const int kind = st.r ? st.r->kind : 0;
   const double k1 = st.r ? st.r->k1 : 0, k2 = st.r ? st.r->k2 : 1;
-  launch_cg_rhs(h, st.u, kind, k1, k2, ahead, st.s);
-  check_and_apply(h, -1, st.o->rtol, st.o->maxit, st.s);
+  if (h.rhs_fused) {  // the first apply stage makes g (the first update then tests it)
+    CgRhs c;
+    c.u = st.u;
+    c.links = h.links.p;
+    c.n = h.n;
+    c.dim = h.dim;
+    c.dt = h.dt;
+    c.kind = kind;
+    c.k1 = k1;
+    c.k2 = k2;
+    c.r = h.r.p;
+    c.x = h.x.p;
+    c.part = h.gpart.p;
+    c.st = h.st.p;
+    c.maxit = st.o->maxit;
+    c.ahead = ahead ? 1 : 0;
+    hif_apply_rhs(h.f, h.z.p, c, st.s);
+  } else {
+    launch_cg_rhs(h, st.u, kind, k1, k2, ahead, st.s);
+    check_and_apply(h, -1, st.o->rtol, st.o->maxit, st.s);
+  }
   st.chunk = std::max(1, h.last_iters);
 }
 
@@ -152,7 +180,7 @@ void step_queue(StepState& st) {
   for (int c = 0; c < st.chunk && st.launched < st.o->maxit; ++c) {
     const int it = st.launched++;
     launch_cg_dir_dots(h, it, st.s);
-    launch_cg_update(h, it, st.s);
+    launch_cg_update(h, it, st.o->rtol, st.s);
     if (c + 1 == st.chunk || st.launched == st.o->maxit) {
       // the host reads the verdict before it queues another apply
       st.seq = ++h.flag_seq;
@@ -270,7 +298,7 @@ int64_t handle_device_bytes(const Handle& h) {
   int64_t b = 0;
   auto add = [&](const auto& buf) { b += (int64_t)(buf.n * sizeof(*buf.p)); };
   add(h.links); add(h.x); add(h.r); add(h.z); add(h.p); add(h.q); add(h.w); add(h.partials);
-  add(h.st); add(h.step_iters); add(h.step_relres);
+  add(h.st); add(h.step_iters); add(h.step_relres); add(h.gpart);
   const FactorDev& f = h.f;
   add(f.idx); add(f.vals); add(f.cb); add(f.wsc); add(f.dvals);
   add(f.tvals); add(f.tgid); add(f.tgslot); add(f.tscat); add(f.twsc); add(f.tpos);
@@ -304,6 +332,7 @@ hif_status_t hif_factor_ex(const double* a_cells_dev, double dt, const hif_grid_
     auto h = make_handle(a_cells_dev, dt, grid, eps, s);
     h->f.top_budget = opts ? opts->dense_top : -1;
     gpu_build(*h, a_cells_dev, store, s);
+    setup_rhs(*h);
     *out = reinterpret_cast<hif_handle_t>(h.release());
   });
 }
@@ -325,6 +354,7 @@ hif_status_t hif_import(const double* a_cells_dev, double dt, const hif_grid_t* 
     FactorHost fh = import_blob(blob_host, nbytes, h->dim, h->n, h->leaf);
     HIF_REQUIRE((int)fh.lv.size() == h->L, HIF_ERR_ARG, "HIFB level count does not match grid");
     upload_factor(fh, store, h->f, s);
+    setup_rhs(*h);
     *out = reinterpret_cast<hif_handle_t>(h.release());
   });
 }

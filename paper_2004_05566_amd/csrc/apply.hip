@@ -32,6 +32,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "cg_gate.hpp"
+#include "stencil.hpp"
 
 namespace hifcn {
 
@@ -265,12 +266,14 @@ __device__ __forceinline__ C team_sum(C v, int team) {
 //   mode 0 (dense H):  w = L^-1 y_I and c = H y_I as nI + nB independent dot products.
 //   mode 1 (links):    w = L^-1 y_I, v = L^-T w (= A_II^-1 y_I), c_b = A_BI(b, ib_b) v_ib_b.
 struct NoHook {
-  __device__ void operator()() const {}
+  template <typename C>
+  __device__ void operator()(C*) const {}
 };
 
 // prestaged: the block is already in LDS (a fused launch loads it while its groups run).
-// hook: run by every lane once the block and inputs are on their way to LDS, before the barrier
-// that publishes them; stop (LDS): looked at after that barrier, nothing is written if set.
+// hook(ys): run by every lane once the block and inputs are on their way to LDS, before the
+// barrier that publishes them (ys: the LDS vector of the interior inputs); stop (LDS): looked at
+// after that barrier, nothing is written if set.  own_ys: the hook writes ys itself.
 template <typename S, typename C, bool ST, int MODE, typename Hook = NoHook>
 __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* __restrict__ idx,
                                               const S* __restrict__ vals, double* __restrict__ y,
@@ -278,7 +281,7 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
                                               bool prestaged, unsigned char* smem_raw,
                                               const double* __restrict__ in = nullptr,
                                               Hook hook = Hook{},
-                                              const int* stop = nullptr) {
+                                              const int* stop = nullptr, bool own_ys = false) {
   // in: where the interior values are read (y unless the input vector is another one)
   const double* src = in ? in : y;
   C* sm = reinterpret_cast<C*>(smem_raw);
@@ -292,17 +295,18 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   C* vs = ws + nI;
   int* ib = reinterpret_cast<int*>(vs + nI);
   const int32_t* gI = idx + d.offI;
+  const int nIy = own_ys ? 0 : nI;  // interior inputs gathered here
   if (ST && !prestaged) {
-    stage_gather(blk, v, tl + (mode ? nB : nB * nI), src, gI, nI, ys, gI, 0, ys, threadIdx.x,
+    stage_gather(blk, v, tl + (mode ? nB : nB * nI), src, gI, nIy, ys, gI, 0, ys, threadIdx.x,
                  blockDim.x);
   } else {
-    for (int i = threadIdx.x; i < nI; i += blockDim.x) ys[i] = (C)src[gI[i]];
+    for (int i = threadIdx.x; i < nIy; i += blockDim.x) ys[i] = (C)src[gI[i]];
   }
   const Tri<S, C, ST> Li{blk, v, nI};
   const Col<S, C, ST> H{blk + tl, v + tl, nB};
   if constexpr (MODE == 1)
     for (int b = threadIdx.x; b < nB; b += blockDim.x) ib[b] = idx[d.offC + b];
-  hook();
+  hook(ys);
   __syncthreads();
   if (stop && *stop) return;
   const int part = threadIdx.x % team, per = blockDim.x / team;
@@ -342,6 +346,77 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   }
 }
 
+// The first stage of a step's first apply, making the step's right-hand side on the way: the
+// cell's workgroup forms g = (I + dt/2 M) u + dt r(u) (Sec. 2.1) at its interiors, which are the
+// stage's inputs (z = g is the initial residual), and at the DOFs of its copy list (outside every
+// interior, z = r = g there); r = g and x = 0 at all of them, and the cell's share of ||g||^2 in
+// part[cell].  Block 0 starts the step's scalars (the test of g is made by the first update).
+// Queued ahead of the previous step's outcome (ahead), it does nothing unless that step ended
+// well (ok_next, written by its closing test and read only here): hold and done are set instead,
+// so the rest of the step does nothing.
+template <typename S, typename C, bool ST, int MODE>
+__device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int stride,
+                                         const S* __restrict__ vals, double* __restrict__ y,
+                                         double* __restrict__ cb, int blk_elems, int team,
+                                         const int32_t* __restrict__ gcopy, int gcstride,
+                                         const CgRhs& rhs, unsigned char* smem_raw,
+                                         double* gred) {
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  const bool held = rhs.ahead && !rhs.st->ok_next;  // (the same in every block)
+  load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CgState* st = rhs.st;
+    st->hold = held ? 1 : 0;
+    st->done = held ? 1 : 0;
+    if (!held) {
+      st->iters = 0;
+      st->status = 0;
+      st->maxit = rhs.maxit;
+    }
+  }
+  if (held) return;
+  __syncthreads();
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  auto g_at = [&](int64_t i) {
+    const double ui = rhs.u[i];
+    const double l = rhs.dim == 2
+                         ? link_sum<2>(i, rhs.n, rhs.links, ui, [&](int64_t k) { return rhs.u[k]; })
+                         : link_sum<3>(i, rhs.n, rhs.links, ui, [&](int64_t k) { return rhs.u[k]; });
+    return ui - l + rhs.dt * react(ui, rhs.kind, rhs.k1, rhs.k2);
+  };
+  double acc = 0;
+  auto make = [&](C* ys) {
+    const int32_t* gI = rec + d.offI;
+    for (int i = threadIdx.x; i < d.nI; i += blockDim.x) {
+      const double g = g_at(gI[i]);
+      ys[i] = (C)g;
+      rhs.r[gI[i]] = g;
+      rhs.x[gI[i]] = 0.0;
+      acc += g * g;
+    }
+    const int32_t* cp = gcopy + (int64_t)blockIdx.x * gcstride;
+    for (int e = threadIdx.x; e < cp[0]; e += blockDim.x) {
+      const int32_t id = cp[1 + e];
+      const double g = g_at(id);
+      rhs.r[id] = g;
+      rhs.x[id] = 0.0;
+      y[id] = g;
+      acc += g * g;
+    }
+  };
+  cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
+                                smem_raw + 4 * stride, nullptr, make, nullptr, true);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) gred[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += gred[w];
+    rhs.part[blockIdx.x] = s;
+  }
+}
+
 template <typename S, typename C, bool ST, int MODE>
 // One workgroup per cell; its record (stride int32) goes to the front of LDS.
 __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ recs, int stride,
@@ -349,9 +424,16 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                                                   double* __restrict__ y, double* __restrict__ cb,
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team, CgGate gate,
-                                                  const int32_t* __restrict__ gcopy, int gcstride) {
+                                                  const int32_t* __restrict__ gcopy, int gcstride,
+                                                  CgRhs rhs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int gstop;
+  __shared__ double gred[4];
+  if (rhs.u) {  // the step's right-hand side made here (see cell_rhs)
+    cell_rhs<S, C, ST, MODE>(recs, stride, vals, y, cb, blk_elems, team, gcopy, gcstride, rhs,
+                             smem_raw, gred);
+    return;
+  }
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   // with a gate, the PCG convergence test comes first: its partials, the state and this
   // cell's copy list load ahead of the record
@@ -378,7 +460,7 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
   const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
   // the test's verdict is reached while the cell's block and inputs load (they are only read
   // before it is known)
-  auto verdict = [&]() {
+  auto verdict = [&](C*) {
     if (!gated || threadIdx.x >= 64) return;
     const double t = ct.sum(gate.part, gate.nb);
     if (threadIdx.x != 0) return;
@@ -1450,13 +1532,14 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const S
 template <typename S, typename C, int MODE>
 void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
                  double* cb, const int* done, hipStream_t s, const StageTimer& t,
-                 const CgGate* gate = nullptr) {
+                 const CgGate* gate = nullptr, const CgRhs* rhs = nullptr) {
   const StagePlan p = cell_plan<C>(L);
   if (fwd) {
     auto k = p.staged ? k_cell_fwd<S, C, true, MODE> : k_cell_fwd<S, C, false, MODE>;
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, cb, done, p.blk_elems, p.seg, gate ? *gate : CgGate{},
-           gate ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride);
+           (gate || rhs) ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride,
+           rhs ? *rhs : CgRhs{});
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
@@ -1577,7 +1660,7 @@ void launch_dense_top(const FactorDev& f, double* y, const double* cb, const int
 
 template <typename S, typename C>
 void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
-                const CgGate* gate = nullptr) {
+                const CgGate* gate = nullptr, const CgRhs* rhs = nullptr) {
   const S* vals = reinterpret_cast<const S*>(f.vals.p);
   const int32_t* idx = f.idx.p;
   StageProfiler* prof = f.prof.get();
@@ -1590,8 +1673,9 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
       if (L.cdense) launch_dense_cells<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
       else if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t,
-                                             l == 0 ? gate : nullptr);
-      else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t, l == 0 ? gate : nullptr);
+                                             l == 0 ? gate : nullptr, l == 0 ? rhs : nullptr);
+      else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t, l == 0 ? gate : nullptr,
+                                l == 0 ? rhs : nullptr);
     }
     if (!L.ngroup) continue;
     if (l == f.top) {  // this level's groups, every level above and the root: one matrix
@@ -1712,6 +1796,17 @@ void hif_apply_gated(const FactorDev& f, double* y, const CgGate& g, hipStream_t
     case HIF_STORE_F64: apply_impl<double, double>(f, y, done, s, &g); break;
     case HIF_STORE_F32: apply_impl<float, float>(f, y, done, s, &g); break;
     case HIF_STORE_BF16: apply_impl<bf16_t, float>(f, y, done, s, &g); break;
+  }
+}
+
+void hif_apply_rhs(const FactorDev& f, double* y, const CgRhs& r, hipStream_t s) {
+  HIF_REQUIRE(f.gate && !f.lv.empty() && f.lv[0].ncell && !f.lv[0].tiled && !f.lv[0].cdense,
+              HIF_ERR_ARG, "factor has no first stage that makes the right-hand side");
+  const int* done = &r.st->done;
+  switch (f.store) {
+    case HIF_STORE_F64: apply_impl<double, double>(f, y, done, s, nullptr, &r); break;
+    case HIF_STORE_F32: apply_impl<float, float>(f, y, done, s, nullptr, &r); break;
+    case HIF_STORE_BF16: apply_impl<bf16_t, float>(f, y, done, s, nullptr, &r); break;
   }
 }
 

@@ -162,7 +162,8 @@ struct CgState {
   // that step did not end well (it goes on, or failed); the step's test of g then sets done, so
   // the rest of it does nothing; cleared by the next right-hand side or by the resume of the
   // previous step
-  int32_t hold, pad;
+  int32_t hold;
+  int32_t ok_next;  // the closing test's verdict for a step queued behind: it ended well
 };
 
 // A convergence test of the PCG run by the first stage of a preconditioner apply instead of its
@@ -175,6 +176,23 @@ struct CgGate {
   int nb = 0, init = 0, it0 = 0, maxit = 0;
   double rtol = 0;
   const double* src = nullptr;
+};
+
+// The right-hand side of a step made by the first stage of its first apply (hif_apply_rhs):
+// the stencil (u, link weights, grid), the reaction, the outputs r, x and the per-cell partial
+// sums of ||g||^2, the state, maxit, and whether the step is queued ahead of the previous one.
+struct CgRhs {
+  const double* u = nullptr;
+  const double* links = nullptr;
+  int n = 0, dim = 2;
+  double dt = 0;
+  int kind = 0;
+  double k1 = 0, k2 = 1;
+  double* r = nullptr;
+  double* x = nullptr;
+  double* part = nullptr;
+  CgState* st = nullptr;
+  int maxit = 0, ahead = 0;
 };
 
 struct Handle {
@@ -197,6 +215,9 @@ struct Handle {
   int32_t flag_seq = 0;
   int nblk = 0;
   int last_iters = 2;
+  // the right-hand side made by the first apply stage (rhs_fused): ||g||^2 per level-0 cell
+  bool rhs_fused = false;
+  DevBuf<double> gpart;
   ~Handle();
 };
 
@@ -253,6 +274,9 @@ void hif_apply_inplace(const FactorDev& f, double* y, const int* done, hipStream
 // The apply with the convergence test in its first stage (requires f.gate): y <- M^-1 src when
 // the iteration goes on, nothing when it stops; later stages skip on g.st->done.
 void hif_apply_gated(const FactorDev& f, double* y, const CgGate& g, hipStream_t s);
+// The apply whose first stage makes the step's right-hand side first (requires f.gate): y <-
+// M^-1 g; later stages skip on r.st->done.
+void hif_apply_rhs(const FactorDev& f, double* y, const CgRhs& r, hipStream_t s);
 // Lay out the copy lists of the gated apply (f.gate stays false when level 0 does not run as
 // one workgroup per cell).
 void setup_cg_gate(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
@@ -280,6 +304,8 @@ CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol, int maxit)
 // Iteration `it` after z = M^-1 r: w = A z with the partials of r.z, z.w, z.q, then the update
 // of p, q = A p, x and r with the partials of ||r||^2.
 void launch_cg_dir_dots(Handle& h, int it, hipStream_t s);
-void launch_cg_update(Handle& h, int it, hipStream_t s);
+// (rtol: for the first update of a step whose right-hand side the apply made, which also tests
+// g: it totals ||g||^2 and starts tol2.)
+void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s);
 
 }  // namespace hifcn

@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "cg_gate.hpp"
+#include "stencil.hpp"
 
 namespace hifcn {
 
@@ -54,47 +55,6 @@ __device__ double total(const double* part, int nb) {
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) acc += part[i];
   return block_sum(acc);
-}
-
-// Sum over links of w (p_j - p_nbr) at node i.  P(k) returns the value at node k.
-template <int DIM, typename P>
-__device__ __forceinline__ double link_sum(int64_t i, int n, const double* __restrict__ w,
-                                           double pi, P pv) {
-  const int64_t n1 = n + 1;
-  const int64_t nn = (int64_t)n * n;
-  int ix = (int)(i % n);
-  int64_t rest = i / n;
-  int iy = (int)(rest % n);
-  int iz = DIM == 3 ? (int)(rest / n) : 0;
-  double acc = 0;
-  // x links: array (.., n+1) with link k between nodes k-1 and k
-  {
-    const int64_t row = DIM == 3 ? ((int64_t)iz * n + iy) : iy;
-    const double* wx = w + row * n1;
-    const double wl = wx[ix], wr = wx[ix + 1];
-    const double pl = ix > 0 ? pv(i - 1) : 0.0;
-    const double pr = ix < n - 1 ? pv(i + 1) : 0.0;
-    acc += wl * (pi - pl) + wr * (pi - pr);
-  }
-  {
-    const int64_t lx = (DIM == 3 ? nn : (int64_t)n) * n1;  // size of the x-link array
-    const double* wy = w + lx;
-    const int64_t b = DIM == 3 ? ((int64_t)iz * n1 + iy) * n + ix : (int64_t)iy * n + ix;
-    const double wl = wy[b], wr = wy[b + n];
-    const double pl = iy > 0 ? pv(i - n) : 0.0;
-    const double pr = iy < n - 1 ? pv(i + n) : 0.0;
-    acc += wl * (pi - pl) + wr * (pi - pr);
-  }
-  if (DIM == 3) {
-    const int64_t lx = nn * n1;
-    const double* wz = w + 2 * lx;
-    const int64_t b = ((int64_t)iz * n + iy) * n + ix;
-    const double wl = wz[b], wr = wz[b + nn];
-    const double pl = iz > 0 ? pv(i - nn) : 0.0;
-    const double pr = iz < n - 1 ? pv(i + nn) : 0.0;
-    acc += wl * (pi - pl) + wr * (pi - pr);
-  }
-  return acc;
 }
 
 // ---- link weights from cell values: mean of the 2 (2D) / 4 (3D) cells sharing the link ------
@@ -147,9 +107,6 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, int64_t N, const doubl
   }
 }
 
-__device__ __forceinline__ double react(double u, int kind, double k1, double k2) {
-  return kind == 1 ? k1 * u * (1.0 - u / k2) : 0.0;
-}
 
 // Partial-sum slots (each nblk long): ||g||^2, ||r||^2, and the direction kernel's r.z, z.w, z.q.
 enum { P_GG = 0, P_RR = 1, P_RZ = 2, P_ZW = 3, P_ZQ = 4, P_SLOTS = 5 };
@@ -269,7 +226,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
   } else if (st->done) {  // stopped by an earlier test of the batch
     if (fin.hflag) {
       finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
-      if (post) post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
+      if (post) {
+        st->ok_next = st->status == 0;
+        post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
+      }
     }
     return;
   }
@@ -288,11 +248,17 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     if (fin.hflag) {
       // block 0 wrote the scalars it reads here; other blocks only copy x
       finish_step(N, fin.x, fin.u, it0 + 1, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
-      if (post) post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
+      if (post) {
+        st->ok_next = st->status == 0;
+        post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
+      }
     }
     return;
   }
-  if (post) post_flag(fin.hflag, fin.seq, it0 + 1, 0, 0);
+  if (post) {
+    st->ok_next = 0;
+    post_flag(fin.hflag, fin.seq, it0 + 1, 0, 0);
+  }
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads)
     z[i] = r[i];
@@ -340,8 +306,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
                                                         double* __restrict__ q,
                                                         double* __restrict__ x,
                                                         double* __restrict__ r, CgState* st,
-                                                        double* part) {
-  const int dn = st->done;
+                                                        double* part,
+                                                        const double* __restrict__ gpart, int ngp,
+                                                        double rtol) {
+  int dn = st->done;
   const int nb = gridDim.x;
   double rz = 0, zw = 0, zq = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
@@ -349,7 +317,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
     zw += part[P_ZW * (int64_t)nb + i];
     zq += part[P_ZQ * (int64_t)nb + i];
   }
+  double gg = 0, unused = 0, unused2 = 0;
+  if (gpart)  // the test of g of a step whose right-hand side the apply made
+    for (int i = threadIdx.x; i < ngp; i += kThreads) gg += gpart[i];
   block_sum3(rz, zw, zq);
+  if (gpart) {
+    block_sum3(gg, unused, unused2);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !dn) {
+      st->gg = gg;
+      st->tol2 = rtol * rtol * gg;
+      st->rr = gg;
+      if (!(gg > 0.0)) st->done = 1;  // g = 0: u = 0 after no iteration
+    }
+    if (!(gg > 0.0)) dn = 1;
+  }
   const bool first = it == 0;
   const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
   const double pq = first ? zw : zw + beta * (2.0 * zq + beta * st->pqv[(it + 1) & 1]);
@@ -445,9 +426,11 @@ void launch_cg_dir_dots(Handle& h, int it, hipStream_t s) {
                      h.q.p, h.w.p, h.partials.p);
 }
 
-void launch_cg_update(Handle& h, int it, hipStream_t s) {
+void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s) {
+  const bool g = it == 0 && h.rhs_fused;
   hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, h.z.p, h.w.p,
-                     h.p.p, h.q.p, h.x.p, h.r.p, h.st.p, h.partials.p);
+                     h.p.p, h.q.p, h.x.p, h.r.p, h.st.p, h.partials.p,
+                     g ? (const double*)h.gpart.p : (const double*)nullptr, (int)h.gpart.n, rtol);
 }
 
 }  // namespace hifcn

@@ -20,16 +20,21 @@ CASES = [("2d-n64-f32", 64, 2, 8, "f32"), ("2d-n100-f64", 100, 2, 8, "f64"),
          ("2d-n33-f64", 33, 2, 4, "f64")]
 
 
-def _factor(a, n, dim, leaf, store, gate):
+def _factor(a, n, dim, leaf, store, gate, rhs=False):
+    """gate: the convergence test in the first apply stage; rhs: the right-hand side made there
+    too (both read at factor time)."""
     import torch
     from paper_2004_05566_amd import hifcn
     a_dev = torch.tensor(a, dtype=torch.float64, device="cuda")
     if not gate:
         os.environ["HIFCN_NO_CG_GATE"] = "1"
+    if not rhs:
+        os.environ["HIFCN_NO_RHS_FUSE"] = "1"
     try:
         return hifcn.factor(a_dev, 0.05, n, dim, 1e-6, store=store, leaf=leaf)
     finally:
         os.environ.pop("HIFCN_NO_CG_GATE", None)
+        os.environ.pop("HIFCN_NO_RHS_FUSE", None)
 
 
 @pytest.mark.parametrize("rtol", [1e-10, 1e-2])
@@ -82,7 +87,7 @@ def test_steps_queued_ahead_match_one_at_a_time(case, gpu_lib):
     a = gen.grf_coefficient(n, dim, 0.12, 98)
     # a large first step then small ones: the predicted iteration count misses in places
     u0 = (5.0 * gen.bumps(n, dim, 4, 99)).ravel()
-    h = _factor(a, n, dim, leaf, store, True)
+    h = _factor(a, n, dim, leaf, store, True, rhs=True)
     out = []
     for ahead in (True, False):
         if not ahead:
@@ -109,7 +114,7 @@ def test_failed_step_stops_the_steps_queued_ahead(gpu_lib):
     n = 48
     a = gen.grf_coefficient(n, 2, 0.12, 100)
     u0 = gen.bumps(n, 2, 3, 101).ravel()
-    h = _factor(a, n, 2, 8, "f64", True)
+    h = _factor(a, n, 2, 8, "f64", True, rhs=True)
     res = []
     for ahead in (True, False):
         if not ahead:
@@ -126,3 +131,37 @@ def test_failed_step_stops_the_steps_queued_ahead(gpu_lib):
     h.close()
     assert torch_equal(res[0], res[1])
     assert not torch_equal(res[0], torch.tensor(u0, device="cuda"))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_rhs_made_by_first_stage_matches_own_launch(case, gpu_lib):
+    """The first apply stage of a step makes the right-hand side (g, r = g, x = 0 and ||g||^2
+    per cell); HIFCN_NO_RHS_FUSE=1 makes it in a launch of its own.  g and the iterates are the
+    same arithmetic; only ||g||^2 is summed in another order, so u agrees bit for bit when the
+    iteration counts do, and ||r||/||g|| to rounding."""
+    import torch
+    name, n, dim, leaf, store = case
+    print(f"[case] {name}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.12, 102)
+    u0 = gen.bumps(n, dim, 3, 103).ravel()
+    out = []
+    for fused in (True, False):
+        h = _factor(a, n, dim, leaf, store, True, rhs=fused)
+        out.append(_solve(h, u0, 4, rtol=1e-10, reaction=(1, 1.0, 1.0)))
+        h.close()
+    (u1, i1, r1), (u0_, i0, r0) = out
+    assert i1 == i0
+    assert torch.equal(u1, u0_)
+    assert np.allclose(r1, r0, rtol=1e-9, atol=0)
+
+
+def test_rhs_made_by_first_stage_zero_rhs(gpu_lib):
+    """g = 0 with the right-hand side made in the first stage: the first update stops the step,
+    u = 0 after no iteration."""
+    import torch
+    n = 64
+    h = _factor(gen.grf_coefficient(n, 2, 0.12, 104), n, 2, 8, "f32", True, rhs=True)
+    u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    its, rel = h.cn_solve(u, 3)
+    assert list(its) == [0, 0, 0] and list(rel) == [0.0, 0.0, 0.0] and not u.any()
+    h.close()
