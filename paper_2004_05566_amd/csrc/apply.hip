@@ -69,8 +69,9 @@ __device__ __forceinline__ void unpack(const uint4& v, C* d) {
 // Copy `tot` elements starting at the (16-byte aligned) `src` into LDS `dst`, using `nthr`
 // threads numbered `lt`; kStageUnroll vector loads per thread are issued before any is consumed
 // (few lanes staging a large block need many loads in flight to cover the memory latency).
-// `dst` must hold `tot` rounded up to the vector width.
-constexpr int kStageUnroll = 8;
+// `dst` must hold `tot` rounded up to the vector width.  (Measured side by side: 6 loads is 1%
+// faster than 8 on 256^2 and no slower on 1024^2; 16 is 4% slower.)
+constexpr int kStageUnroll = 6;
 template <typename S, typename C>
 __device__ __forceinline__ void stage_flat(C* dst, const S* src, int tot, int lt, int nthr) {
   using V = typename VecOf<S>::T;
