@@ -182,13 +182,12 @@ __device__ void post_flag(int32_t* hflag, int seq, int iters, int done, int stat
 }
 
 // The end of a CN step: u = x, and the iteration count and relative residual ||r|| / ||g|| of
-// step `step` recorded (block 0).
+// step `step` recorded (block 0).  x0: the lane's first element of x, loaded already.
 __device__ void finish_step(int64_t N, const double* __restrict__ x, double* __restrict__ u,
                             int iters, double rr, double gg, int32_t* it_out, double* rel_out,
-                            int step) {
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads)
-    u[i] = x[i];
+                            int step, double x0) {
+  const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) u[i] = i == i0 ? x0 : x[i];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     it_out[step] = iters;
     rel_out[step] = gg > 0 ? sqrt(rr / gg) : 0.0;
@@ -217,6 +216,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
                                                             CgFinish fin) {
   __shared__ int stop;
   const bool post = fin.hflag && blockIdx.x == 0 && threadIdx.x == 0;
+  // the lane's first elements of r (z = r) and x (u = x) load with the flags and partials
+  const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double r0 = 0, x0 = 0;
+  if (i0 < N) {
+    r0 = r[i0];
+    if (fin.hflag) x0 = fin.x[i0];
+  }
   if (fin.hflag && st->hold) return;  // queued ahead of a step that did not end well
   if (init) {  // the test of the right-hand side publishes the state of the new step
     if (st->hold) {  // (queued ahead, see k_cg_rhs): later kernels of the step do nothing
@@ -225,7 +231,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     }
   } else if (st->done) {  // stopped by an earlier test of the batch
     if (fin.hflag) {
-      finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
+      finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step,
+                  x0);
       if (post) {
         st->ok_next = st->status == 0;
         post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
@@ -247,7 +254,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
   if (stop) {
     if (fin.hflag) {
       // block 0 wrote the scalars it reads here; other blocks only copy x
-      finish_step(N, fin.x, fin.u, it0 + 1, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step);
+      finish_step(N, fin.x, fin.u, it0 + 1, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step,
+                  x0);
       if (post) {
         st->ok_next = st->status == 0;
         post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
@@ -259,9 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     st->ok_next = 0;
     post_flag(fin.hflag, fin.seq, it0 + 1, 0, 0);
   }
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads)
-    z[i] = r[i];
+  for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) z[i] = i == i0 ? r0 : r[i];
 }
 
 // w = A z and the partial sums of r.z, z.w and (after the first iteration) z.q.  Runs whether
@@ -311,6 +317,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
                                                         double rtol) {
   int dn = st->done;
   const int nb = gridDim.x;
+  const bool first = it == 0;
+  // the lane's first element is loaded before the totals, so its latency overlaps theirs
+  const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double z0 = 0, w0 = 0, p0 = 0, q0 = 0, x0 = 0, r0 = 0;
+  if (i0 < N) {
+    z0 = z[i0];
+    w0 = w[i0];
+    if (!first) {
+      p0 = p[i0];
+      q0 = q[i0];
+    }
+    x0 = x[i0];
+    r0 = r[i0];
+  }
   double rz = 0, zw = 0, zq = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     rz += part[P_RZ * (int64_t)nb + i];
@@ -331,7 +351,6 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
     }
     if (!(gg > 0.0)) dn = 1;
   }
-  const bool first = it == 0;
   const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
   const double pq = first ? zw : zw + beta * (2.0 * zq + beta * st->pqv[(it + 1) & 1]);
   const double alpha = rz / pq;
@@ -340,12 +359,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
     st->pqv[it & 1] = pq;
   }
   double acc = 0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
-    const double pi = first ? z[i] : z[i] + beta * p[i];
-    const double qi = first ? w[i] : w[i] + beta * q[i];
-    const double xi = x[i] + alpha * pi;
-    const double ri = r[i] - alpha * qi;
+  for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) {
+    const bool pre = i == i0;
+    const double zi = pre ? z0 : z[i], wi = pre ? w0 : w[i];
+    const double pi = first ? zi : zi + beta * (pre ? p0 : p[i]);
+    const double qi = first ? wi : wi + beta * (pre ? q0 : q[i]);
+    const double xi = (pre ? x0 : x[i]) + alpha * pi;
+    const double ri = (pre ? r0 : r[i]) - alpha * qi;
     acc += ri * ri;
     if (!dn) {
       p[i] = pi;
