@@ -252,7 +252,7 @@ def main(argv=None):
         copy_probe(args.copy_probe)
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "hifcn runs on one GPU; --gpus must be 1"}))
         return 2
 
     import numpy as np

@@ -48,3 +48,17 @@ def test_poisson_arrivals():
     t = gen.poisson_arrivals(20000, 40.0, 3)
     assert np.all(np.diff(t) > 0)
     assert abs(len(t) / t[-1] - 40.0) < 1.0
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus above 1 ends with a message and a non-zero status before
+    anything touches a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0
+    assert "one GPU" in json.loads(res.stdout.strip().splitlines()[-1])["error"]
