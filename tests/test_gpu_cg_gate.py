@@ -165,3 +165,35 @@ def test_rhs_made_by_first_stage_zero_rhs(gpu_lib):
     its, rel = h.cn_solve(u, 3)
     assert list(its) == [0, 0, 0] and list(rel) == [0.0, 0.0, 0.0] and not u.any()
     h.close()
+
+
+SWEEP = [(24, 2, 4, "f64", 1e-11, 0.3), (40, 2, 8, "f32", 1e-9, 2.0), (57, 2, 8, "bf16", 1e-8, 1.0),
+         (72, 2, 8, "f32", 1e-12, 4.0), (100, 2, 8, "f64", 1e-10, 0.5), (12, 3, 4, "f32", 1e-10, 1.0),
+         (20, 3, 4, "f64", 1e-12, 3.0)]
+
+
+@pytest.mark.parametrize("cfg", SWEEP, ids=[f"n{c[0]}-d{c[1]}-{c[3]}" for c in SWEEP])
+def test_pipeline_matches_plain_path(cfg, gpu_lib):
+    """Every PCG step folded into the apply and steps queued ahead, against the plain sequence of
+    launches (test, right-hand side and each step on their own): the same iteration counts and u
+    to rounding, over grids, stores, tolerances and amplitudes that make the predicted iteration
+    count miss now and then."""
+    import torch
+    n, dim, leaf, store, rtol, amp = cfg
+    print(f"[case] {cfg}", flush=True)
+    a = gen.grf_coefficient(n, dim, 0.1, 200 + n)
+    u0 = (amp * gen.bumps(n, dim, 3, 300 + n)).ravel()
+    out = []
+    for plain in (False, True):
+        h = _factor(a, n, dim, leaf, store, not plain, rhs=not plain)
+        if plain:
+            os.environ["HIFCN_NO_AHEAD"] = "1"
+        try:
+            out.append(_solve(h, u0, 5, rtol=rtol, reaction=(1, 1.0, 1.0)))
+        finally:
+            os.environ.pop("HIFCN_NO_AHEAD", None)
+        h.close()
+    (u1, i1, r1), (u0_, i0, r0) = out
+    assert i1 == i0, (i1, i0)
+    assert torch.linalg.norm(u1 - u0_) <= 1e-12 * torch.linalg.norm(u0_)
+    assert np.allclose(r1, r0, rtol=1e-8, atol=0)
