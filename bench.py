@@ -209,6 +209,72 @@ def cpu_baseline(w, budget_steps: int):
             "t_factor_s": tf, "host_cpu": model, "host_nproc": os.cpu_count()}
 
 
+def inverse_error(h, N, iters=30, seed=0):
+    """||I - A F^-1||_2 by power iteration on E^T E, E = I - A F^-1 (A and F^-1 symmetric, so
+    E^T = I - F^-1 A), from a seeded random start; applies and products on the GPU."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    x /= torch.linalg.norm(x)
+    t = torch.empty_like(x)
+    s = torch.empty_like(x)
+    lam = 0.0
+    for _ in range(iters):
+        h.apply(x, out=t)       # F^-1 x
+        h.spmv(t, out=s)        # A F^-1 x
+        y = x - s               # E x
+        h.spmv(y, out=t)        # A y
+        h.apply(t, out=s)       # F^-1 A y
+        z = y - s               # E^T E x
+        lam = float(torch.linalg.norm(z))
+        x = z / lam
+    return lam ** 0.5
+
+
+def replica(sizes2d, sizes3d, steps, store, logistic=False):
+    """The paper's Sec. 3 experiments at the given sizes (eps 1e-3 and 1e-6): mean n_i at rtol
+    1e-12, build and per-step time, factor bytes, and at eps 1e-6 the estimate of
+    ||I - A F^-1||, next to the values the paper prints."""
+    import json as _json
+
+    import numpy as np
+    import torch
+
+    from paper_2004_05566_amd import hifcn
+    from workloads import gen
+    gold = _json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
+                                        "golden", "paper_phif_iterations.json")))
+    kind = "logistic" if logistic else "heat"
+    out = []
+    for dim, sizes in ((2, sizes2d), (3, sizes3d)):
+        for n in sizes:
+            for eps in (1e-3, 1e-6):
+                w = gen.paper_heat(n, dim, eps, steps=steps, logistic=logistic)
+                a_dev = torch.tensor(w.a_cells, dtype=torch.float64, device="cuda")
+                u = torch.tensor(w.u0.ravel(), dtype=torch.float64, device="cuda")
+                _sync()
+                t0 = time.perf_counter()
+                h = hifcn.factor(a_dev, w.dt, n, dim, eps, store=store, leaf=w.leaf)
+                _sync()
+                tf = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                its, _ = h.cn_solve(u, steps, rtol=w.rtol, reaction=w.reaction)
+                _sync()
+                ts = (time.perf_counter() - t0) / steps
+                paper = gold.get(f"{kind}_{dim}d", {}).get(f"eps_{eps:.0e}".replace("e-0", "e-"),
+                                                          {}).get(str(n))
+                row = {"case": w.name, "N": w.N, "steps": steps, "store": store,
+                       "n_i_mean": float(np.mean(its)), "n_i_paper": paper,
+                       "t_factor_s": tf, "t_step_s": ts, "factor_GB": h.factor_bytes() / 1e9}
+                if eps == 1e-6:
+                    row["inv_error"] = inverse_error(h, w.N)
+                h.close()
+                del a_dev, u
+                print(_json.dumps(row), flush=True)
+                out.append(row)
+    return out
+
+
 def reference_error(w, u_gpu, nsteps):
     """Relative error of the GPU u against the FP64 sparse direct solution of the same steps."""
     import numpy as np
@@ -247,6 +313,11 @@ def main(argv=None):
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration)")
+    ap.add_argument("--replica", default="",
+                    help="only run the paper's Sec. 3 experiments, e.g. '2d:511,1023;3d:63' "
+                         "(one JSON line per case; --steps steps each, --store storage)")
+    ap.add_argument("--logistic", action="store_true",
+                    help="with --replica: the logistic reaction (Example 2)")
     args = ap.parse_args(argv)
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -254,6 +325,13 @@ def main(argv=None):
     if args.gpus != 1:
         print(json.dumps({"error": "hifcn runs on one GPU; --gpus must be 1"}))
         return 2
+    if args.replica:
+        sz = {"2d": [], "3d": []}
+        for part in args.replica.split(";"):
+            k, v = part.split(":")
+            sz[k.strip()] = [int(s) for s in v.split(",") if s.strip()]
+        replica(sz["2d"], sz["3d"], args.steps, args.store, args.logistic)
+        return 0
 
     import numpy as np
     import torch

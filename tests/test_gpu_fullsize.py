@@ -77,3 +77,37 @@ def test_full_size_steps_solve_their_systems(name, steps, gpu_lib):
         assert 1 <= it <= 20, it
         prev = cur
     h.close()
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_paper_heat2d_511_iterations_and_inverse_error(eps, gpu_lib):
+    """The paper's Example 1 at N = 511^2 (Sec. 3; its coefficient centres are random, so the
+    printed mean iteration counts are compared as ranges: within 1.5 iterations), FP64 factor
+    storage, rtol 1e-12.  At eps = 1e-6 also ||I - A F^-1|| by power iteration: the paper
+    prints 7.9e-6 at 4095^2; at 511^2 it must be of that order (below 1e-4)."""
+    import json
+    import os
+    import sys
+
+    import numpy as np
+    import torch
+    from paper_2004_05566_amd import hifcn
+    from workloads import gen
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    from bench import inverse_error
+    gold = json.load(open(os.path.join(root, "tests", "golden", "paper_phif_iterations.json")))
+    paper = gold["heat_2d"]["eps_1e-3" if eps == 1e-3 else "eps_1e-6"]["511"]
+    w = gen.paper_heat(511, 2, eps, steps=10)
+    a = torch.tensor(w.a_cells, dtype=torch.float64, device="cuda")
+    u = torch.tensor(w.u0.ravel(), dtype=torch.float64, device="cuda")
+    h = hifcn.factor(a, w.dt, w.n, 2, eps, store="f64", leaf=w.leaf)
+    its, rel = h.cn_solve(u, w.steps, rtol=w.rtol)
+    print(f"[case] eps {eps}: n_i {np.mean(its):.2f} (paper {paper})", flush=True)
+    assert abs(float(np.mean(its)) - paper) <= 1.5
+    assert max(rel) <= 1e-12
+    if eps == 1e-6:
+        e = inverse_error(h, w.N, iters=20)
+        print(f"[case] ||I - A F^-1|| ~ {e:.2e}", flush=True)
+        assert e < 1e-4
+    h.close()

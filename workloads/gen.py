@@ -120,6 +120,31 @@ def bumps(n: int, dim: int, count: int, seed: int, width2: float = 0.005) -> np.
     return np.clip(u, 0.0, 1.0)
 
 
+def gaussian_sum_coefficient(n: int, dim: int, m: int, sigma2: float, lo: float, hi: float,
+                             seed: int) -> np.ndarray:
+    """Sec. 3 coefficient (eq 2d_coeff / 3d_coeff): the sum over m centres x_i ~ U(0,1)^d of
+    exp(-|x - x_i|^2 / sigma2), on the cells, rescaled and shifted affinely onto [lo, hi]."""
+    rng = _rng(seed)
+    centres = rng.uniform(0.0, 1.0, size=(m, dim))  # (x, y[, z]) per centre
+    pts = [c for c in cell_centres(n, dim)]          # [x, y(, z)] grids
+    s = np.zeros(pts[0].shape)
+    for c in centres:
+        r2 = sum((pts[k] - c[k]) ** 2 for k in range(dim))
+        s += np.exp(-r2 / sigma2)
+    t = (s - s.min()) / (s.max() - s.min())
+    return lo + (hi - lo) * t
+
+
+def gaussian_initial(n: int, dim: int, centres, sigma2: float) -> np.ndarray:
+    """Sec. 3 initial data (eq 2d_h_u0 / 3d_u0): a sum of Gaussians exp(-|x - c|^2 / sigma2)
+    at the nodes, one per centre c (each centre a coordinate repeated on every axis)."""
+    x = node_coords(n, dim)
+    u = np.zeros(x[0].shape)
+    for c in centres:
+        u += np.exp(-sum((x[k] - c) ** 2 for k in range(dim)) / sigma2)
+    return u
+
+
 @dataclass
 class Workload:
     """One synthetic parabolic solve: grid, coefficient, initial state and solver settings."""
@@ -167,6 +192,27 @@ def _heat3d_64() -> Workload:
     u0 = sine_mode(n, 3) + 0.1 * rng.normal(size=(n,) * 3)
     return Workload("heat3d-64", 3, n, grf_coefficient(n, 3, 0.15, 4001), u0, 1e-2, 20,
                     1e-4, 1e-8)
+
+
+def paper_heat(n: int, dim: int, eps: float, seed: int = 6000, steps: int = 100,
+               logistic: bool = False) -> Workload:
+    """The paper's Sec. 3 experiments: 2D (Example 1, and the logistic reaction of Example 2)
+    with a(x) from m = 100 Gaussians (sigma_2^2 = 0.005) on [0.1, 10], u0 two Gaussians at
+    c = 0.35, 0.65 (sigma^2 = 0.05), dt = h; 3D with m = 1000 Gaussians on [0.05, 20], u0 one
+    Gaussian at c = 0.5, dt = 0.1 h.  The centres are random (no seeds printed), so iteration
+    counts can be compared with the paper's tables as ranges only.  rtol 1e-12."""
+    h = 1.0 / (n + 1)
+    if dim == 2:
+        a = gaussian_sum_coefficient(n, 2, 100, 0.005, 0.1, 10.0, seed)
+        u0 = gaussian_initial(n, 2, (0.35, 0.65), 0.05)
+        dt = h
+    else:
+        a = gaussian_sum_coefficient(n, 3, 1000, 0.005, 0.05, 20.0, seed)
+        u0 = gaussian_initial(n, 3, (0.5,), 0.05)
+        dt = 0.1 * h
+    kind = "logistic" if logistic else "heat"
+    return Workload(f"paper-{kind}{dim}d-{n}-eps{eps:g}", dim, n, a, u0, dt, steps, eps, 1e-12,
+                    reaction=(1, 1.0, 1.0) if logistic else (0, 0.0, 0.0))
 
 
 def serving_request(i: int, seed_base: int = 5000, sizes=(64, 128, 256, 512)) -> Workload:
