@@ -196,23 +196,31 @@ def _heat3d_64() -> Workload:
 
 def paper_heat(n: int, dim: int, eps: float, seed: int = 6000, steps: int = 100,
                logistic: bool = False) -> Workload:
-    """The paper's Sec. 3 experiments: 2D (Example 1, and the logistic reaction of Example 2)
-    with a(x) from m = 100 Gaussians (sigma_2^2 = 0.005) on [0.1, 10], u0 two Gaussians at
-    c = 0.35, 0.65 (sigma^2 = 0.05), dt = h; 3D with m = 1000 Gaussians on [0.05, 20], u0 one
-    Gaussian at c = 0.5, dt = 0.1 h.  The centres are random (no seeds printed), so iteration
-    counts can be compared with the paper's tables as ranges only.  rtol 1e-12."""
+    """The paper's Sec. 3 experiments.  Example 1 (heat): 2D with a(x) from m = 100 Gaussians
+    (sigma_2^2 = 0.005) rescaled onto [0.1, 10], u0 two Gaussians at c = 0.35, 0.65
+    (sigma^2 = 0.05), dt = h; 3D with m = 1000 Gaussians onto [0.05, 20], u0 one Gaussian at
+    c = 0.5, dt = 0.1 h.  Example 2 (logistic, r(u) = k1 u (1 - u/k2), k1 = 1, k2 = 10): the same
+    coefficients (3D: m = 200), u0 one Gaussian at c = 0.5 scaled by 2 / (3 sqrt(2 pi sigma^2))
+    in 2D and (2 pi sigma)^(-3/2) (sigma = sqrt(0.05)) in 3D.  The centres are random (no seeds
+    printed), so iteration counts compare with the paper's tables as ranges only.  rtol 1e-12."""
     h = 1.0 / (n + 1)
+    s2 = 0.05
     if dim == 2:
         a = gaussian_sum_coefficient(n, 2, 100, 0.005, 0.1, 10.0, seed)
-        u0 = gaussian_initial(n, 2, (0.35, 0.65), 0.05)
         dt = h
+        if logistic:
+            u0 = 2.0 / (3.0 * np.sqrt(2.0 * np.pi * s2)) * gaussian_initial(n, 2, (0.5,), s2)
+        else:
+            u0 = gaussian_initial(n, 2, (0.35, 0.65), s2)
     else:
-        a = gaussian_sum_coefficient(n, 3, 1000, 0.005, 0.05, 20.0, seed)
-        u0 = gaussian_initial(n, 3, (0.5,), 0.05)
+        a = gaussian_sum_coefficient(n, 3, 200 if logistic else 1000, 0.005, 0.05, 20.0, seed)
         dt = 0.1 * h
+        u0 = gaussian_initial(n, 3, (0.5,), s2)
+        if logistic:
+            u0 = u0 * (2.0 * np.pi * np.sqrt(s2)) ** -1.5
     kind = "logistic" if logistic else "heat"
     return Workload(f"paper-{kind}{dim}d-{n}-eps{eps:g}", dim, n, a, u0, dt, steps, eps, 1e-12,
-                    reaction=(1, 1.0, 1.0) if logistic else (0, 0.0, 0.0))
+                    reaction=(1, 1.0, 10.0) if logistic else (0, 0.0, 0.0))
 
 
 def serving_request(i: int, seed_base: int = 5000, sizes=(64, 128, 256, 512)) -> Workload:
