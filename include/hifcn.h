@@ -121,6 +121,16 @@ hif_status_t cn_solve(hif_handle_t h, const hif_reaction_t* r, const hif_cg_opts
                       double* u_dev, int32_t nsteps, int32_t* iters_host, double* relres_host,
                       void* hip_stream);
 
+/* nsteps Crank-Nicolson steps with the factor as the solver, without CG (Sec. 3: at
+ * eps = 1e-6 the factor approximates A^-1 well enough to bypass CG): u^{k+1} = F^-1 g^k with
+ * g^k = (I + dt/2 M) u^k + dt r(u^k) as in cn_step.  Since every eigenvalue of A is >= 1, one
+ * step differs from the exact CN step by at most ||I - A F^-1||_2 ||g^k||_2.  u_dev (N FP64) is
+ * replaced by u^{nsteps}.  Queues the steps without synchronising; the values are not checked
+ * (a non-finite u propagates).  Uses the handle's PCG workspace: not concurrently with another
+ * call on the same handle.  Errors: HIF_ERR_ARG (NULL handle or u_dev, nsteps < 0, reaction). */
+hif_status_t cn_solve_direct(hif_handle_t h, const hif_reaction_t* r, double* u_dev,
+                             int32_t nsteps, void* hip_stream);
+
 /* Continuous batching: one Crank-Nicolson step (as cn_step) for each of `count` independent
  * solves, handle h[i] with state u_dev[i] (device, N_i FP64), reaction r[i] (array, may be
  * NULL: none) and options opts[i], each queued on its own stream hip_streams[i] (array, may be

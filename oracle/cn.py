@@ -91,3 +91,17 @@ def cn_solve(A, B, u0: np.ndarray, dt: float, steps: int, precond, rtol: float,
         iters.append(res.iters)
         rel.append(res.relres)
     return us, iters, rel
+
+
+def cn_solve_direct(B, u0: np.ndarray, dt: float, steps: int, solve, react=(0, 0.0, 0.0)):
+    """The factor used as the solver, without CG (Sec. 3, the remark on eps = 1e-6): for
+    k = 1..steps, g = B u^{k-1} + dt r(u^{k-1}) and u^k = solve(g) with solve = F^-1.
+
+    Returns u_steps with u_steps[k] = u^k (u_steps[0] = u0).
+    """
+    u = u0.astype(np.float64).ravel().copy()
+    us = [u.copy()]
+    for _ in range(steps):
+        u = solve(cn_rhs(B, u, dt, react))
+        us.append(u.copy())
+    return us

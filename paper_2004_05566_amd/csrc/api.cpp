@@ -412,6 +412,52 @@ hif_status_t cn_solve(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opt
   });
 }
 
+hif_status_t cn_solve_direct(hif_handle_t hh, const hif_reaction_t* r, double* u, int32_t nsteps,
+                             void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && u, HIF_ERR_ARG, "NULL argument");
+    HIF_REQUIRE(nsteps >= 0, HIF_ERR_ARG, "nsteps must be >= 0");
+    check_reaction(r);
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int kind = r ? r->kind : 0;
+    const double k1 = r ? r->k1 : 0.0, k2 = r ? r->k2 : 1.0;
+    if (!h.rhs_fused) {  // g into r, F^-1 in place there, back into u
+      for (int k = 0; k < nsteps; ++k) {
+        launch_cg_rhs(h, u, kind, k1, k2, false, s);
+        hif_apply_inplace(h.f, h.r.p, nullptr, s);
+        HIF_CHECK(hipMemcpyAsync(u, h.r.p, h.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+      return;
+    }
+    // the first apply stage forms g from the state it reads; the state alternates between u and
+    // the workspace z, with one copy at the end of an odd count
+    double* cur = u;
+    double* nxt = h.z.p;
+    for (int k = 0; k < nsteps; ++k) {
+      CgRhs c;
+      c.u = cur;
+      c.links = h.links.p;
+      c.n = h.n;
+      c.dim = h.dim;
+      c.dt = h.dt;
+      c.kind = kind;
+      c.k1 = k1;
+      c.k2 = k2;
+      c.r = h.r.p;
+      c.x = h.x.p;
+      c.part = h.gpart.p;
+      c.st = h.st.p;
+      c.maxit = 1;
+      c.ahead = 0;
+      hif_apply_rhs(h.f, nxt, c, s);
+      std::swap(cur, nxt);
+    }
+    if (cur != u)
+      HIF_CHECK(hipMemcpyAsync(u, cur, h.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  });
+}
+
 hif_status_t cn_step(hif_handle_t hh, const hif_reaction_t* r, const hif_cg_opts_t* o, double* u,
                      int32_t* iters, double* relres, void* hip_stream) {
   return cn_solve(hh, r, o, u, 1, iters, relres, hip_stream);

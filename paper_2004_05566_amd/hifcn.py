@@ -72,6 +72,7 @@ _lib.cn_step.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts)
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), _vp]
 _lib.cn_solve.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts), _vp,
                           ctypes.c_int32, _vp, _vp, _vp]
+_lib.cn_solve_direct.argtypes = [_vp, ctypes.POINTER(_Reaction), _vp, ctypes.c_int32, _vp]
 _lib.cn_batch_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
 _lib.hif_factor_bytes.argtypes = [_vp]
 _lib.hif_factor_bytes.restype = ctypes.c_size_t
@@ -82,12 +83,13 @@ _lib.hif_destroy.argtypes = [_vp]
 _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
 for _f in ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
-           "cn_batch_step", "hif_get_info", "hif_profile_stage", "hif_profile_read"):
+           "cn_solve_direct", "cn_batch_step", "hif_get_info", "hif_profile_stage",
+           "hif_profile_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step",
-           "cn_solve", "cn_batch_step", "hif_factor_bytes", "hif_get_info", "hif_profile_stage",
-           "hif_profile_read", "hif_destroy", "hif_last_error")
+           "cn_solve", "cn_solve_direct", "cn_batch_step", "hif_factor_bytes", "hif_get_info",
+           "hif_profile_stage", "hif_profile_read", "hif_destroy", "hif_last_error")
 
 
 def _check(status: int):
@@ -159,6 +161,12 @@ class Handle:
             raise HifError(st, _lib.hif_last_error().decode())
         _check(st)
         return its[:nsteps].copy(), rel[:nsteps].copy()
+
+    def cn_solve_direct(self, u, nsteps: int, reaction=(0, 0.0, 1.0), stream=None):
+        """Advance u (in place) by nsteps Crank-Nicolson steps u <- F^-1 g, without CG."""
+        r = _Reaction(int(reaction[0]), float(reaction[1]), float(reaction[2]))
+        _check(_lib.cn_solve_direct(self._p(), ctypes.byref(r), _dev_f64(u, "u"), int(nsteps),
+                                    _stream(stream)))
 
     def cn_step(self, u, rtol: float = 1e-8, maxit: int = 500, reaction=(0, 0.0, 1.0),
                 stream=None):

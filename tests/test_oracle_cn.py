@@ -91,3 +91,43 @@ def test_second_order_in_space_and_time():
         return np.abs(ud - exact).max()
     e1, e2 = err(15), err(31)
     assert 3.0 < e1 / e2 < 5.0
+
+
+def test_direct_steps_with_exact_factor_are_exact_cn_steps():
+    """eps = 0 makes the factor exact (no skeleton is dropped), so F^-1 g is the sparse direct
+    solve of each CN step."""
+    n = 20
+    a = gen.grf_coefficient(n, 2, 0.1, 31)
+    u0 = gen.bumps(n, 2, 3, 32)
+    dt = 2e-2
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, 2, 4, 0.0)
+    react = (1, 1.0, 2.0)
+    us = cn.cn_solve_direct(B, u0, dt, 3, lambda g: phif.phif_apply(F, g), react)
+    assert len(us) == 4 and np.array_equal(us[0], u0.ravel())
+    for k in (1, 3):
+        ud = _direct(A, B, u0, dt, k, react)
+        assert np.linalg.norm(us[k] - ud) <= 1e-11 * np.linalg.norm(ud)
+
+
+def test_direct_step_error_within_the_inverse_error_bound():
+    """Every eigenvalue of A = I - dt/2 M is >= 1, so the direct step's error against the exact
+    step is at most ||I - A F^-1||_2 ||g||_2; the error shrinks with eps (Sec. 3)."""
+    n = 32
+    a = gen.grf_coefficient(n, 2, 0.1, 33)
+    u0 = gen.bumps(n, 2, 3, 34)
+    dt = 1.0 / (n + 1)
+    A, B = fd.cn_matrices(a, dt)
+    g = cn.cn_rhs(B, u0.ravel(), dt)
+    exact = spla.spsolve(A.tocsc(), g)
+    assert np.linalg.eigvalsh(A.toarray()).min() >= 1.0 - 1e-12
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6):
+        F = phif.phif_build(A, n, 2, 8, eps)
+        Fi = np.column_stack([phif.phif_apply(F, e) for e in np.eye(n * n)])
+        bound = np.linalg.norm(np.eye(n * n) - A @ Fi, 2) * np.linalg.norm(g)
+        u1 = cn.cn_solve_direct(B, u0, dt, 1, lambda v: phif.phif_apply(F, v))[1]
+        err = np.linalg.norm(u1 - exact)
+        assert err <= bound * (1 + 1e-9), (eps, err, bound)
+        errs.append(err / np.linalg.norm(exact))
+    assert errs[0] > errs[2] and errs[2] < 1e-5, errs
