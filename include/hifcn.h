@@ -100,6 +100,24 @@ hif_status_t hif_import(const double* a_cells_dev, double dt, const hif_grid_t* 
                         const void* blob_host, size_t nbytes, hif_store_t store,
                         void* hip_stream, hif_handle_t* out);
 
+/* Time-dependent coefficients (Sec. 4: with a(x, t) the factor is rebuilt, or, when a changes
+ * slowly, rebuilt once every few steps and reused in between).
+ *
+ * hif_set_coefficient: the operator of every later call (hif_spmv, the A and the
+ * I + dt/2 M of cn_step, cn_solve, cn_solve_direct, cn_batch_step) becomes the one of
+ * a_cells_dev ((n+1)^dim FP64 values > 0, same grid and dt); the factor is kept, so PCG is
+ * preconditioned by the factor of the coefficient it was built from.  Ordered on hip_stream.
+ *
+ * hif_refactor: rebuilds the factor from a_cells_dev with the handle's grid, dt, eps, storage
+ * and dense-top budget, and sets the operator as hif_set_coefficient does.  The handle keeps
+ * its address; the old factor is freed once the new one is built, so both are resident for a
+ * moment.  Synchronises hip_stream (as hif_factor does); no work on the handle may be in
+ * flight on another stream.  On error the handle keeps its old factor and operator.
+ * Errors: HIF_ERR_ARG (NULL argument; a handle made by hif_import, which has no eps),
+ * HIF_ERR_NOT_SPD, HIF_ERR_OOM, HIF_ERR_HIP. */
+hif_status_t hif_set_coefficient(hif_handle_t h, const double* a_cells_dev, void* hip_stream);
+hif_status_t hif_refactor(hif_handle_t h, const double* a_cells_dev, void* hip_stream);
+
 /* y = F^-1 x (eqAinv: forward sweep E^T C^T K^T over levels 0..L-1, root solve, backward sweep
  * K C E over levels L-1..0).  x_dev, y_dev: N FP64 values; may alias. */
 hif_status_t hif_apply(hif_handle_t h, const double* x_dev, double* y_dev, void* hip_stream);

@@ -105,3 +105,34 @@ def cn_solve_direct(B, u0: np.ndarray, dt: float, steps: int, solve, react=(0, 0
         u = solve(cn_rhs(B, u, dt, react))
         us.append(u.copy())
     return us
+
+
+def cn_solve_varying(a_at, n: int, dim: int, leaf: int, eps: float, dt: float, u0: np.ndarray,
+                     steps: int, refactor_every: int, rtol: float, react=(0, 0.0, 0.0),
+                     maxit: int = 500):
+    """A time-dependent coefficient a(x, t) (Sec. 4): the factor is rebuilt once every
+    `refactor_every` steps and reused in between.
+
+    Read here: step k (from t_k = k dt to t_k + dt) takes the coefficient at the midpoint,
+    a(., t_k + dt/2), on both sides of eq_CN, which keeps the scheme second order in time; the
+    factor is built from that step's coefficient at k = 0, K, 2K, ... (K = refactor_every) and
+    preconditions PCG (Algorithm 1) for the K steps that follow.
+
+    Returns (u_steps, iters): u_steps[k] = u^k (u_steps[0] = u0), iters[k-1] = n_i of step k.
+    """
+    from oracle import fd, phif
+    u = u0.astype(np.float64).ravel().copy()
+    us = [u.copy()]
+    iters = []
+    F = None
+    for k in range(steps):
+        A, B = fd.cn_matrices(a_at((k + 0.5) * dt), dt)
+        if k % refactor_every == 0:
+            F = phif.phif_build(A, n, dim, leaf, eps)
+        res = pcg(A, cn_rhs(B, u, dt, react), lambda r: phif.phif_apply(F, r), rtol, maxit)
+        if not res.converged:
+            raise NoConvergence(f"PCG did not converge in {maxit} iterations")
+        u = res.x
+        us.append(u.copy())
+        iters.append(res.iters)
+    return us, iters

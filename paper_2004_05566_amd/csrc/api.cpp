@@ -333,6 +333,7 @@ hif_status_t hif_factor_ex(const double* a_cells_dev, double dt, const hif_grid_
     h->f.top_budget = opts ? opts->dense_top : -1;
     gpu_build(*h, a_cells_dev, store, s);
     setup_rhs(*h);
+    h->built = true;
     *out = reinterpret_cast<hif_handle_t>(h.release());
   });
 }
@@ -356,6 +357,36 @@ hif_status_t hif_import(const double* a_cells_dev, double dt, const hif_grid_t* 
     upload_factor(fh, store, h->f, s);
     setup_rhs(*h);
     *out = reinterpret_cast<hif_handle_t>(h.release());
+  });
+}
+
+hif_status_t hif_set_coefficient(hif_handle_t hh, const double* a_cells_dev, void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && a_cells_dev, HIF_ERR_ARG, "NULL argument");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    launch_links(a_cells_dev, h.dim, h.n, h.dt / (2.0 * h.h * h.h), h.links.p,
+                 static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+hif_status_t hif_refactor(hif_handle_t hh, const double* a_cells_dev, void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && a_cells_dev, HIF_ERR_ARG, "NULL argument");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    HIF_REQUIRE(h.built, HIF_ERR_ARG, "hif_refactor: the factor was imported (no eps to build with)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const hif_grid_t g{h.dim, {h.n, h.n, h.dim == 3 ? h.n : 0}, h.leaf};
+    // a complete new handle, then its factor and operator moved into this one; the old ones
+    // leave with it (the PCG workspace, state and host flag stay)
+    auto nh = make_handle(a_cells_dev, h.dt, &g, h.eps, s);
+    nh->f.top_budget = h.f.top_budget;
+    gpu_build(*nh, a_cells_dev, h.f.store, s);
+    setup_rhs(*nh);
+    HIF_CHECK(hipStreamSynchronize(s));
+    std::swap(h.f, nh->f);
+    std::swap(h.links, nh->links);
+    std::swap(h.gpart, nh->gpart);
+    h.rhs_fused = nh->rhs_fused;
   });
 }
 

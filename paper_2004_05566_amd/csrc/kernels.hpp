@@ -218,6 +218,7 @@ struct Handle {
   // the right-hand side made by the first apply stage (rhs_fused): ||g||^2 per level-0 cell
   bool rhs_fused = false;
   DevBuf<double> gpart;
+  bool built = false;  // factor built here (hif_factor*), not imported: hif_refactor allowed
   ~Handle();
 };
 

@@ -66,6 +66,8 @@ _lib.hif_factor_ex.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), ctyp
                                ctypes.c_int, ctypes.POINTER(_FactorOpts), _vp, ctypes.POINTER(_vp)]
 _lib.hif_import.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_Grid), _vp, ctypes.c_size_t,
                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.hif_set_coefficient.argtypes = [_vp, _vp, _vp]
+_lib.hif_refactor.argtypes = [_vp, _vp, _vp]
 _lib.hif_apply.argtypes = [_vp, _vp, _vp, _vp]
 _lib.hif_spmv.argtypes = [_vp, _vp, _vp, _vp]
 _lib.cn_step.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts), _vp,
@@ -84,12 +86,13 @@ _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
 for _f in ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
            "cn_solve_direct", "cn_batch_step", "hif_get_info", "hif_profile_stage",
-           "hif_profile_read"):
+           "hif_profile_read", "hif_set_coefficient", "hif_refactor"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step",
            "cn_solve", "cn_solve_direct", "cn_batch_step", "hif_factor_bytes", "hif_get_info",
-           "hif_profile_stage", "hif_profile_read", "hif_destroy", "hif_last_error")
+           "hif_profile_stage", "hif_profile_read", "hif_destroy", "hif_last_error",
+           "hif_set_coefficient", "hif_refactor")
 
 
 def _check(status: int):
@@ -161,6 +164,21 @@ class Handle:
             raise HifError(st, _lib.hif_last_error().decode())
         _check(st)
         return its[:nsteps].copy(), rel[:nsteps].copy()
+
+    def set_coefficient(self, a_cells, stream=None):
+        """Later products and solves use the operator of a_cells ((n+1)^dim FP64 on the device);
+        the factor is kept."""
+        self._check_cells(a_cells)
+        _check(_lib.hif_set_coefficient(self._p(), _dev_f64(a_cells, "a_cells"), _stream(stream)))
+
+    def refactor(self, a_cells, stream=None):
+        """Rebuild the factor (and the operator) from a_cells with this handle's settings."""
+        self._check_cells(a_cells)
+        _check(_lib.hif_refactor(self._p(), _dev_f64(a_cells, "a_cells"), _stream(stream)))
+
+    def _check_cells(self, a_cells):
+        if a_cells.numel() != (self.n + 1) ** self.dim:
+            raise ValueError(f"a_cells must hold (n+1)^dim = {(self.n + 1) ** self.dim} values")
 
     def cn_solve_direct(self, u, nsteps: int, reaction=(0, 0.0, 1.0), stream=None):
         """Advance u (in place) by nsteps Crank-Nicolson steps u <- F^-1 g, without CG."""

@@ -131,3 +131,53 @@ def test_direct_step_error_within_the_inverse_error_bound():
         assert err <= bound * (1 + 1e-9), (eps, err, bound)
         errs.append(err / np.linalg.norm(exact))
     assert errs[0] > errs[2] and errs[2] < 1e-5, errs
+
+
+def _midpoint_direct(a_at, u0, dt, steps, react=(0, 0.0, 0.0)):
+    u = u0.ravel().copy()
+    for k in range(steps):
+        A, B = fd.cn_matrices(a_at((k + 0.5) * dt), dt)
+        u = spla.spsolve(A.tocsc(), B @ u + dt * cn.reaction(u, *react))
+    return u
+
+
+def test_varying_coefficient_exact_factor_is_the_midpoint_cn_solve():
+    n = 16
+    a_at = gen.drifting_coefficient(n, 2, 0.2, 51, amp=0.8, period=0.2)
+    u0 = gen.bumps(n, 2, 3, 52)
+    dt = 0.02
+    react = (1, 1.0, 2.0)
+    us, its = cn.cn_solve_varying(a_at, n, 2, 4, 0.0, dt, u0, 4, 1, 1e-13, react)
+    ref = _midpoint_direct(a_at, u0, dt, 4, react)
+    assert np.linalg.norm(us[-1] - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert its == [1, 1, 1, 1]
+
+
+def test_varying_coefficient_second_order_in_time():
+    """With the midpoint coefficient the time error falls 4x per halving of dt (left-point
+    coefficients would give 2x)."""
+    n = 15
+    a_at = gen.drifting_coefficient(n, 2, 0.3, 53, amp=1.0, period=0.2)
+    u0 = gen.sine_mode(n, 2)
+    T = 0.05
+    ref = _midpoint_direct(a_at, u0, T / 512, 512)
+    errs = []
+    for m in (16, 32, 64):
+        us, _ = cn.cn_solve_varying(a_at, n, 2, 4, 1e-10, T / m, u0, m, 1, 1e-14)
+        errs.append(np.linalg.norm(us[-1] - ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.6 and 3.6 < r2 < 4.6, errs
+
+
+def test_stale_factor_still_converges_to_the_step_solution():
+    """Reusing the first factor for every step changes the iteration counts, not u."""
+    n = 32
+    a_at = gen.drifting_coefficient(n, 2, 0.2, 55, amp=1.0, period=0.4)
+    u0 = gen.bumps(n, 2, 3, 56)
+    dt = 1.0 / 33
+    fresh, it1 = cn.cn_solve_varying(a_at, n, 2, 8, 1e-6, dt, u0, 6, 1, 1e-12)
+    stale, it6 = cn.cn_solve_varying(a_at, n, 2, 8, 1e-6, dt, u0, 6, 6, 1e-12)
+    ref = _midpoint_direct(a_at, u0, dt, 6)
+    for us in (fresh, stale):
+        assert np.linalg.norm(us[-1] - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert it6[0] == it1[0] and sum(it6) > sum(it1), (it1, it6)

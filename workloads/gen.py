@@ -60,6 +60,19 @@ def grf_coefficient(n: int, dim: int, length: float, seed: int, lo: float = 0.1,
     return a.reshape((n + 1,) * dim)
 
 
+def drifting_coefficient(n: int, dim: int, length: float, seed: int, amp: float = 0.5,
+                         period: float = 1.0, lo: float = 0.1, hi: float = 10.0):
+    """A coefficient that changes smoothly in time: a(x, t) = a0(x) exp(amp sin(2 pi t / period)
+    b(x)), with a0 a smooth field on [lo, hi] and b a second one on [-1, 1] (both drawn as in
+    grf_coefficient).  Returns the function t -> a(., t) on the cells."""
+    a0 = grf_coefficient(n, dim, length, seed, lo, hi)
+    b = np.log(grf_coefficient(n, dim, length, seed + 1, np.exp(-1.0), np.exp(1.0)))
+
+    def at(t: float) -> np.ndarray:
+        return a0 * np.exp(amp * np.sin(2.0 * np.pi * t / period) * b)
+    return at
+
+
 def spectral_grf_coefficient(n: int, dim: int, length: float, seed: int, lo: float = 0.1,
                              hi: float = 10.0) -> np.ndarray:
     """Lognormal field a = exp(g) on the cells, mapped to [lo, hi], drawn by FFT filtering.
