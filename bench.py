@@ -287,6 +287,48 @@ def replica(sizes2d, sizes3d, steps, store, logistic=False):
     return out
 
 
+def drift(w, steps, everies, store, amp=0.5):
+    """A coefficient that drifts over the run (a(x, t) = a0(x) exp(amp sin(2 pi t / T) b(x)),
+    T = steps dt; step k takes a(., (k + 1/2) dt)), with the factor rebuilt every K steps and the
+    operator updated in between (K = 0: never rebuilt).  The coefficients are on the device
+    before the clock starts; the rebuilds are inside the timed region."""
+    import numpy as np
+    import torch
+
+    from paper_2004_05566_amd import hifcn
+    from workloads import gen
+    a_at = gen.drifting_coefficient(w.n, w.dim, 0.1, 2001, amp=amp, period=steps * w.dt)
+    coeffs = [torch.tensor(a_at((k + 0.5) * w.dt), dtype=torch.float64, device="cuda")
+              for k in range(steps)]
+    out = []
+    for every in everies:
+        h = hifcn.factor(coeffs[0], w.dt, w.n, w.dim, w.eps, store=store, leaf=w.leaf)
+        u = torch.tensor(w.u0.ravel(), dtype=torch.float64, device="cuda")
+        its, t_re = [], 0.0
+        _sync()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            if k and every and k % every == 0:
+                t1 = time.perf_counter()
+                h.refactor(coeffs[k])
+                t_re += time.perf_counter() - t1
+            elif k:
+                h.set_coefficient(coeffs[k])
+            it, _ = h.cn_solve(u, 1, rtol=w.rtol, reaction=w.reaction)
+            its.append(int(it[0]))
+        _sync()
+        tt = time.perf_counter() - t0
+        nre = (steps - 1) // every if every else 0
+        row = {"case": w.name, "drift_amp": amp, "refactor_every": every, "steps": steps,
+               "store": store, "steps_per_s": steps / tt, "t_total_s": tt,
+               "refactors": nre, "t_refactor_s": t_re / nre if nre else None,
+               "n_i_mean": float(np.mean(its)), "n_i_max": int(max(its))}
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        h.close()
+    return out
+
+
 def reference_error(w, u_gpu, nsteps):
     """Relative error of the GPU u against the FP64 sparse direct solution of the same steps."""
     import numpy as np
@@ -330,6 +372,9 @@ def main(argv=None):
                          "(one JSON line per case; --steps steps each, --store storage)")
     ap.add_argument("--logistic", action="store_true",
                     help="with --replica: the logistic reaction (Example 2)")
+    ap.add_argument("--drift", default="",
+                    help="only run the workload with a drifting coefficient, the factor rebuilt "
+                         "every K steps for each K listed, e.g. '1,5,20,0' (0: never)")
     args = ap.parse_args(argv)
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -337,6 +382,11 @@ def main(argv=None):
     if args.gpus != 1:
         print(json.dumps({"error": "hifcn runs on one GPU; --gpus must be 1"}))
         return 2
+    if args.drift:
+        from workloads import gen
+        w = gen.workload(args.workload)
+        drift(w, args.steps, [int(s) for s in args.drift.split(",")], args.store)
+        return 0
     if args.replica:
         sz = {"2d": [], "3d": []}
         for part in args.replica.split(";"):
