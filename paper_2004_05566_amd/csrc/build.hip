@@ -784,6 +784,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     // level 0: A_IB is the stencil, one link per boundary DOF; keep that link instead of H
     const int cmode = lev == 0 ? 1 : 0;
     std::vector<std::vector<int32_t>> cell_ib(P.cells.size());
+    // position of a DOF in the interior of the cell at hand (-1 elsewhere), reset after each cell
+    std::vector<int32_t> pos(cmode ? hd.N : 0, -1);
     for (size_t ci = 0; ci < P.cells.size(); ++ci) {
       int nB = 0;
       for (int b : P.cellB[ci]) nB += gsz(b);
@@ -793,21 +795,20 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       const int nI = gsz(P.cells[ci]);
       voff += tri64(nI) + (cmode ? (int64_t)nB : (int64_t)nB * nI);
       if (cmode) {
-        std::unordered_map<int32_t, int32_t> pos;
         const std::vector<int32_t>& I = P.groups[P.cells[ci]].dofs;
         for (int i = 0; i < nI; ++i) pos[I[i]] = i;
         const int64_t nn = (int64_t)hd.n * hd.n;
+        cell_ib[ci].reserve(nB);
         for (int b : P.cellB[ci])
           for (int32_t id : P.groups[b].dofs) {
             int found = -1;
             const int64_t cand[6] = {id - 1, id + 1, id - hd.n, id + hd.n, id - nn, id + nn};
-            for (int q = 0; q < (hd.dim == 3 ? 6 : 4) && found < 0; ++q) {
-              auto it = pos.find((int32_t)cand[q]);
-              if (it != pos.end()) found = it->second;
-            }
+            for (int q = 0; q < (hd.dim == 3 ? 6 : 4) && found < 0; ++q)
+              if (cand[q] >= 0 && cand[q] < hd.N) found = pos[cand[q]];
             HIF_REQUIRE(found >= 0, HIF_ERR_ARG, "internal: boundary DOF without a stencil link");
             cell_ib[ci].push_back(found);
           }
+        for (int i = 0; i < nI; ++i) pos[I[i]] = -1;
       }
     }
     for (int g : P.seps) {
@@ -880,7 +881,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       HIF_CHECK(hipGetLastError());
       build_fronts(fronts, fsubs, A.p, schur.p, fv.p, err.p, s, &fstats, dibl.p);
       // Schur assembly into every separator block touched by some cell
-      std::vector<std::vector<Contrib>> per_block(P.blocks.size());
+      // contributions grouped by block (counting sort: per block in cell order)
+      std::vector<int32_t> hit;      // block of each contribution, in visiting order
+      std::vector<Contrib> visit;
       for (size_t ci = 0; ci < P.cells.size(); ++ci) {
         const std::vector<int>& B = P.cellB[ci];
         std::vector<int> boff(B.size());
@@ -890,17 +893,24 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
           for (size_t b = 0; b < B.size(); ++b) {
             const int blk = P.find_block(B[a], B[b]);
             HIF_REQUIRE(blk >= 0, HIF_ERR_ARG, "internal: missing separator block");
-            per_block[blk].push_back({cell_soff[ci], cell_nB[ci], boff[a], boff[b], 0});
+            hit.push_back(blk);
+            visit.push_back({cell_soff[ci], cell_nB[ci], boff[a], boff[b], 0});
           }
       }
+      std::vector<int32_t> start(P.blocks.size() + 1, 0);
+      for (int32_t blk : hit) ++start[blk + 1];
+      for (size_t b = 0; b < P.blocks.size(); ++b) start[b + 1] += start[b];
+      std::vector<Contrib> con(visit.size());
+      {
+        std::vector<int32_t> fillp(start.begin(), start.end() - 1);
+        for (size_t e = 0; e < visit.size(); ++e) con[fillp[hit[e]]++] = visit[e];
+      }
       std::vector<SchurTask> stk;
-      std::vector<Contrib> con;
       for (size_t b = 0; b < P.blocks.size(); ++b) {
-        if (per_block[b].empty()) continue;
+        const int32_t cnt = start[b + 1] - start[b];
+        if (!cnt) continue;
         const int g = P.blocks[b].first, h = P.blocks[b].second;
-        stk.push_back({P.block_off[b], gsz(g), gsz(h), (int32_t)per_block[b].size(),
-                       (int32_t)con.size()});
-        con.insert(con.end(), per_block[b].begin(), per_block[b].end());
+        stk.push_back({P.block_off[b], gsz(g), gsz(h), cnt, start[b]});
       }
       DevBuf<SchurTask> dst;
       DevBuf<Contrib> dcon;

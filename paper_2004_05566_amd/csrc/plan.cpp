@@ -172,6 +172,9 @@ void finish_plan(const Geometry& geo, LevelPlan& P) {
     off += (int64_t)P.groups[g].dofs.size() * (int64_t)P.groups[h].dofs.size();
   }
   P.block_keys = std::move(pairs);
+  P.block_row.assign(G + 1, 0);
+  for (const auto& b : P.blocks) ++P.block_row[b.first + 1];
+  for (int g = 0; g < G; ++g) P.block_row[g + 1] += P.block_row[g];
   P.nvals = off;
 }
 
@@ -183,16 +186,37 @@ LevelPlan plan_level0(const Geometry& geo) {
   int64_t N = 1;
   for (int d = 0; d < geo.dim; ++d) N *= geo.n;
   std::vector<int> gid(geo.nslots(0), -1);  // slot -> group
-  for (int64_t id = 0; id < N; ++id) {
-    int kind;
-    const uint64_t k = geo.key((int32_t)id, 0, &kind);
-    int& g = gid[geo.slot(k, 0)];
-    if (g < 0) {
-      g = (int)P.groups.size();
-      P.groups.push_back({k, kind, {}});
-    }
-    P.groups[g].dofs.push_back((int32_t)id);
+  // per coordinate x = 1..n: its field of the key, its term of the slot, whether it lies on a
+  // separator (Geometry::key and Geometry::slot, one axis at a time)
+  const int n = geo.n, st = geo.step(0), ns = geo.nsep(0);
+  const int64_t R = 2 * ns + 1;
+  std::vector<uint64_t> kv(n + 1);
+  std::vector<int64_t> sv(n + 1);
+  std::vector<int> onv(n + 1);
+  for (int x = 1; x <= n; ++x) {
+    const bool on = ns > 0 && x % st == 0 && x / st >= 1 && x / st <= ns;
+    kv[x] = on ? ((1ull << 20) | (uint64_t)x) : (uint64_t)std::min((x - 1) / st, ns);
+    sv[x] = on ? ns + x / st : (int64_t)kv[x];
+    onv[x] = on ? 1 : 0;
   }
+  const int nz = geo.dim == 3 ? n : 1;
+  int32_t id = 0;
+  for (int z = 1; z <= nz; ++z) {
+    const uint64_t kz = geo.dim == 3 ? kv[z] << 42 : 0;
+    const int64_t sz = geo.dim == 3 ? sv[z] * R * R : 0;
+    const int oz = geo.dim == 3 ? onv[z] : 0;
+    for (int y = 1; y <= n; ++y)
+      for (int x = 1; x <= n; ++x, ++id) {
+        const uint64_t k = kv[x] | kv[y] << 21 | kz;
+        int& g = gid[sv[x] + sv[y] * R + sz];
+        if (g < 0) {
+          g = (int)P.groups.size();
+          P.groups.push_back({k, onv[x] + onv[y] + oz, {}});
+        }
+        P.groups[g].dofs.push_back(id);
+      }
+  }
+  HIF_REQUIRE(id == N, HIF_ERR_ARG, "internal: level-0 DOF count");
   finish_plan(geo, P);
   return P;
 }

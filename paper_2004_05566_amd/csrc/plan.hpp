@@ -39,6 +39,7 @@ struct LevelPlan {
   std::vector<std::pair<int, int>> blocks;
   std::vector<uint64_t> block_keys;           // (g << 32 | h) of each block, ascending
   std::vector<int64_t> block_off;             // value offsets (row-major |g| x |h|)
+  std::vector<int32_t> block_row;             // blocks of group g: [block_row[g], block_row[g+1])
   int64_t nvals = 0;
   // provenance of each group's DOFs from the previous level (empty at level 0)
   std::vector<std::vector<int>> subs;         // per group: previous-level groups, in order
@@ -46,8 +47,13 @@ struct LevelPlan {
 
   int find_block(int g, int h) const {
     const uint64_t k = ((uint64_t)(uint32_t)g << 32) | (uint32_t)h;
-    auto it = std::lower_bound(block_keys.begin(), block_keys.end(), k);
-    return (it == block_keys.end() || *it != k) ? -1 : (int)(it - block_keys.begin());
+    auto lo = block_keys.begin(), hi = block_keys.end();
+    if (g >= 0 && (size_t)g + 1 < block_row.size()) {  // search only the blocks of row g
+      lo = block_keys.begin() + block_row[g];
+      hi = block_keys.begin() + block_row[g + 1];
+    }
+    auto it = std::lower_bound(lo, hi, k);
+    return (it == hi || *it != k) ? -1 : (int)(it - block_keys.begin());
   }
 };
 
