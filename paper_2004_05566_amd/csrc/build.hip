@@ -1173,14 +1173,26 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     // gather map of boundary contributions, in cell order
     std::vector<int> sep_index(G, -1);
     for (size_t q = 0; q < P.seps.size(); ++q) sep_index[P.seps[q]] = (int)q;
-    std::vector<std::vector<std::vector<int32_t>>> slots(P.seps.size());
-    for (size_t q = 0; q < P.seps.size(); ++q) slots[q].resize(gsz(P.seps[q]));
-    for (size_t ci = 0; ci < P.cells.size(); ++ci) {
-      int64_t o = cell_cb[ci];
+    // slots of separator DOF p of group q: sstart[sbase[q] + p] .. (counting sort, cell order)
+    std::vector<int64_t> sbase(P.seps.size() + 1, 0);
+    for (size_t q = 0; q < P.seps.size(); ++q) sbase[q + 1] = sbase[q] + gsz(P.seps[q]);
+    std::vector<int32_t> sstart(sbase.back() + 1, 0);
+    for (size_t ci = 0; ci < P.cells.size(); ++ci)
       for (int b : P.cellB[ci]) {
-        const int q = sep_index[b];
-        for (int p = 0; p < gsz(b); ++p) slots[q][p].push_back((int32_t)(o + p));
-        o += gsz(b);
+        const int64_t s0 = sbase[sep_index[b]];
+        for (int p = 0; p < gsz(b); ++p) ++sstart[s0 + p + 1];
+      }
+    for (int64_t e = 0; e < sbase.back(); ++e) sstart[e + 1] += sstart[e];
+    std::vector<int32_t> sval(sstart.back());
+    {
+      std::vector<int32_t> fillp(sstart.begin(), sstart.end() - 1);
+      for (size_t ci = 0; ci < P.cells.size(); ++ci) {
+        int64_t o = cell_cb[ci];
+        for (int b : P.cellB[ci]) {
+          const int64_t s0 = sbase[sep_index[b]];
+          for (int p = 0; p < gsz(b); ++p) sval[fillp[s0 + p]++] = (int32_t)(o + p);
+          o += gsz(b);
+        }
       }
     }
     std::vector<std::vector<int32_t>> surv(G);
@@ -1201,12 +1213,10 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
         for (int i = 0; i < n; ++i) surv[g][i] = i;
       }
       lo.gperm.push_back(pm);
-      std::vector<int32_t> ptr{0};
-      std::vector<int32_t> sl;
-      for (int p = 0; p < n; ++p) {
-        sl.insert(sl.end(), slots[q][p].begin(), slots[q][p].end());
-        ptr.push_back((int32_t)sl.size());
-      }
+      const int32_t* sp = sstart.data() + sbase[q];
+      std::vector<int32_t> ptr(n + 1);
+      for (int p = 0; p <= n; ++p) ptr[p] = sp[p] - sp[0];
+      std::vector<int32_t> sl(sval.begin() + sp[0], sval.begin() + sp[n]);
       lo.gslots_ptr.push_back(std::move(ptr));
       lo.gslots.push_back(std::move(sl));
       lo.groups.push_back(d);
