@@ -136,3 +136,31 @@ def test_refactor_errors_keep_the_old_factor(gpu_lib):
         hi.refactor(_dev(a))
     hi.close()
     h.close()
+
+
+def test_refactored_handle_serves_every_step_entry_point(gpu_lib):
+    """After hif_refactor: the direct steps, the PCG steps and the batched step all see the new
+    factor and operator (a handle factored from scratch is the reference for each)."""
+    import torch
+    from paper_2004_05566_amd import hifcn
+    n, dt = 64, 1.0 / 65
+    a_at = gen.drifting_coefficient(n, 2, 0.2, 71, amp=1.0, period=1.0)
+    a1 = a_at(0.4)
+    h = _factor(a_at(0.0), dt, n, 2, 8, 1e-6)
+    h.refactor(_dev(a1))
+    h1 = _factor(a1, dt, n, 2, 8, 1e-6)
+    u0 = torch.tensor(gen.bumps(n, 2, 3, 72).ravel(), device="cuda")
+    react = (1, 1.0, 10.0)
+    ua, ub = u0.clone(), u0.clone()
+    h.cn_solve_direct(ua, 3, reaction=react)
+    h1.cn_solve_direct(ub, 3, reaction=react)
+    assert torch.linalg.norm(ua - ub) <= 1e-12 * torch.linalg.norm(ub)
+    ua, ub = u0.clone(), u0.clone()
+    s = torch.cuda.Stream()
+    its, _, sts = hifcn.cn_batch_step([h], [ua], [react], [1e-12], [100], [s])
+    torch.cuda.synchronize()
+    it1, _ = h1.cn_step(ub, rtol=1e-12, maxit=100, reaction=react)
+    assert int(sts[0]) == hifcn.HIF_OK and int(its[0]) == it1
+    assert torch.linalg.norm(ua - ub) <= 1e-12 * torch.linalg.norm(ub)
+    h.close()
+    h1.close()
