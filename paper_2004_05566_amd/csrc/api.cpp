@@ -380,6 +380,8 @@ hif_status_t hif_refactor(hif_handle_t hh, const double* a_cells_dev, void* hip_
     // leave with it (the PCG workspace, state and host flag stay)
     auto nh = make_handle(a_cells_dev, h.dt, &g, h.eps, s);
     nh->f.top_budget = h.f.top_budget;
+    nh->plan0 = h.plan0;
+    nh->keep_plan0 = true;
     gpu_build(*nh, a_cells_dev, h.f.store, s);
     setup_rhs(*nh);
     HIF_CHECK(hipStreamSynchronize(s));
@@ -387,6 +389,7 @@ hif_status_t hif_refactor(hif_handle_t hh, const double* a_cells_dev, void* hip_
     std::swap(h.links, nh->links);
     std::swap(h.gpart, nh->gpart);
     h.rhs_fused = nh->rhs_fused;
+    h.plan0 = nh->plan0;
   });
 }
 

@@ -732,7 +732,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
                 std::string("non-positive Cholesky pivot during ") + where);
   };
 
-  LevelPlan P = plan_level0(geo);
+  LevelPlan P = hd.plan0 ? LevelPlan(*hd.plan0) : plan_level0(geo);
+  if (hd.keep_plan0 && !hd.plan0) hd.plan0 = std::make_shared<const LevelPlan>(P);
   mark("plan", 0);
   DevBuf<double> A(std::max<int64_t>(1, P.nvals), s);
   {  // level-0 blocks straight from the stencil

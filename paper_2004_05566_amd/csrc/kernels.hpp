@@ -8,6 +8,8 @@
 
 namespace hifcn {
 
+struct LevelPlan;
+
 // One level of the factor as the apply kernels read it.
 struct LevelDev {
   int ncell = 0, ngroup = 0;
@@ -219,6 +221,10 @@ struct Handle {
   bool rhs_fused = false;
   DevBuf<double> gpart;
   bool built = false;  // factor built here (hif_factor*), not imported: hif_refactor allowed
+  // the level-0 structure (it depends on the grid only), kept once the factor has been rebuilt
+  // so that later rebuilds skip planning it
+  std::shared_ptr<const LevelPlan> plan0;
+  bool keep_plan0 = false;
   ~Handle();
 };
 
