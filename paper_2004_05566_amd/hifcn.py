@@ -168,17 +168,17 @@ class Handle:
     def set_coefficient(self, a_cells, stream=None):
         """Later products and solves use the operator of a_cells ((n+1)^dim FP64 on the device);
         the factor is kept."""
-        self._check_cells(a_cells)
-        _check(_lib.hif_set_coefficient(self._p(), _dev_f64(a_cells, "a_cells"), _stream(stream)))
+        _check(_lib.hif_set_coefficient(self._p(), self._cells(a_cells), _stream(stream)))
 
     def refactor(self, a_cells, stream=None):
         """Rebuild the factor (and the operator) from a_cells with this handle's settings."""
-        self._check_cells(a_cells)
-        _check(_lib.hif_refactor(self._p(), _dev_f64(a_cells, "a_cells"), _stream(stream)))
+        _check(_lib.hif_refactor(self._p(), self._cells(a_cells), _stream(stream)))
 
-    def _check_cells(self, a_cells):
+    def _cells(self, a_cells):
+        p = _dev_f64(a_cells, "a_cells")
         if a_cells.numel() != (self.n + 1) ** self.dim:
             raise ValueError(f"a_cells must hold (n+1)^dim = {(self.n + 1) ** self.dim} values")
+        return p
 
     def cn_solve_direct(self, u, nsteps: int, reaction=(0, 0.0, 1.0), stream=None):
         """Advance u (in place) by nsteps Crank-Nicolson steps u <- F^-1 g, without CG."""
