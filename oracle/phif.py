@@ -97,7 +97,24 @@ def _chol(Amat: np.ndarray) -> np.ndarray:
 
 
 def _dense(Acur: sp.csr_matrix, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
-    return Acur[rows][:, cols].toarray()
+    """The dense block Acur[rows, cols].  The nonzeros of the selected rows are matched to the
+    requested columns by binary search over the sorted column list, so the cost follows the
+    nonzeros of those rows rather than the order of the matrix."""
+    out = np.zeros((len(rows), len(cols)))
+    if len(rows) == 0 or len(cols) == 0:
+        return out
+    rows = np.asarray(rows)
+    start, stop = Acur.indptr[rows], Acur.indptr[rows + 1]
+    cnt = stop - start
+    row = np.repeat(np.arange(len(rows)), cnt)               # output row of each nonzero
+    k = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt) + np.repeat(start, cnt)
+    col, val = Acur.indices[k], Acur.data[k]
+    order = np.argsort(cols, kind="stable")
+    scol = np.asarray(cols)[order]
+    pos = np.minimum(np.searchsorted(scol, col), len(scol) - 1)
+    hit = scol[pos] == col
+    out[row[hit], order[pos[hit]]] = val[hit]
+    return out
 
 
 def _keep(Acur: sp.csr_matrix, keep: np.ndarray) -> sp.csr_matrix:
@@ -247,14 +264,3 @@ def phif_apply(F: Factor, r: np.ndarray) -> np.ndarray:
 def phif_dense_inverse(F: Factor) -> np.ndarray:
     """F^-1 as a dense matrix, applied to the identity (tiny grids only)."""
     return phif_apply(F, np.eye(F.N))
-
-
-def factor_entries(F: Factor) -> int:
-    """Number of stored factor entries (triangles counted packed, dense blocks in full)."""
-    tri = lambda k: k * (k + 1) // 2  # noqa: E731
-    tot = tri(len(F.root_idx))
-    for lv in F.levels:
-        tot += sum(tri(len(c.I)) + c.G.size for c in lv.cells)
-        tot += sum(tri(len(g.idx)) for g in lv.groups)
-        tot += sum(s.T.size + tri(len(s.redund)) for s in lv.skels)
-    return tot

@@ -47,10 +47,45 @@ def test_cn_matches_sparse_direct_solve_with_reaction():
     assert np.linalg.norm(us[-1] - ud) <= 1e-10 * np.linalg.norm(ud)
 
 
-def test_reaction_pointwise():
-    u = np.array([-0.5, 0.0, 0.3, 1.0, 2.0])
-    assert np.allclose(cn.reaction(u, 1, 2.0, 4.0), [2.0 * x * (1 - x / 4.0) for x in u])
-    assert np.all(cn.reaction(u, 0, 1.0, 1.0) == 0)
+def test_reaction_logistic_fixed_points_slope_and_peak():
+    """r(u) = k1 u (1 - u/k2) (Sec. 3, Example 2) is fixed by facts of the logistic law rather
+    than by its formula: it vanishes at the two equilibria u = 0 and u = k2, grows at rate k1
+    near 0, is a quadratic (its second difference is the constant -2 k1 / k2 h^2), peaks at
+    u = k2/2 with value k1 k2 / 4, and is negative beyond k2 and below 0.  k1, k2 are chosen
+    distinct from each other and from 1 so that a swapped or dropped parameter fails."""
+    k1, k2 = 3.0, 5.0
+    r = lambda u: cn.reaction(np.asarray(u, dtype=float), 1, k1, k2)  # noqa: E731
+    assert np.array_equal(r([0.0, k2]), [0.0, 0.0])
+    h = 1e-3   # the central difference of a quadratic is exact up to rounding
+    assert abs((r([h])[0] - r([-h])[0]) / (2 * h) - k1) < 1e-9
+    u = np.linspace(-2.0, 8.0, 41)
+    d2 = (r(u + h) - 2 * r(u) + r(u - h)) / h ** 2
+    assert np.allclose(d2, -2 * k1 / k2, rtol=0, atol=1e-4)
+    assert r([k2 / 2])[0] == k1 * k2 / 4
+    grid = np.linspace(-1.0, 6.0, 7001)
+    assert np.isclose(grid[np.argmax(r(grid))], k2 / 2)
+    assert np.all(r([-0.5, k2 + 0.5]) < 0) and np.all(r([0.5, k2 - 0.5]) > 0)
+    # the logistic workloads take k1 = k2 = 1: r(u) = u (1 - u), zero at 0 and 1, peak 1/4
+    r1 = cn.reaction(np.array([0.0, 0.5, 1.0]), 1, 1.0, 1.0)
+    assert np.array_equal(r1, [0.0, 0.25, 0.0])
+    assert not cn.reaction(u, 0, k1, k2).any()
+
+
+def test_reaction_enters_the_step_explicitly():
+    """With the reaction explicit (Sec. 2.1), one CN step from a spatially constant state on
+    a grid with a = 0 (no diffusion) is the forward-Euler step of the logistic ODE: the right
+    side is u + dt r(u) and A = I.  Checked against the ODE's Euler step written out."""
+    n, dt = 6, 0.05
+    A, B = fd.cn_matrices(np.zeros((n + 1, n + 1)), dt)
+    assert abs(A - _eye(n * n)).max() == 0
+    u0 = np.full(n * n, 0.3)
+    g = cn.cn_rhs(B, u0, dt, (1, 2.0, 4.0))
+    assert np.allclose(g, 0.3 + dt * 2.0 * 0.3 * (1 - 0.3 / 4.0), rtol=0, atol=1e-15)
+
+
+def _eye(N):
+    import scipy.sparse as sp
+    return sp.identity(N, format="csr")
 
 
 def test_pcg_exact_preconditioner_one_iteration_and_zero_rhs():
