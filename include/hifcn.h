@@ -128,7 +128,10 @@ hif_status_t hif_spmv(hif_handle_t h, const double* x_dev, double* y_dev, void* 
 /* One Crank-Nicolson step (eq_CN, Algorithm 1): g = (I + dt/2 M)u + dt r(u), then PCG with
  * preconditioner F^-1 from x0 = 0; u_dev (N FP64) is replaced by u^{k+1}.  *iters_host and
  * *relres_host (may be NULL) receive the iteration count and ||r||/||g||.  Synchronises the
- * stream.  HIF_ERR_NO_CONV: u_dev holds the last iterate and *iters_host = maxit. */
+ * stream.  HIF_ERR_NO_CONV: u_dev holds the last iterate and *iters_host = maxit; or, when
+ * ||g||^2 is not finite (a NaN or Inf in u, or an overflowing reaction), the step stops before
+ * its first iteration with u_dev unchanged and *iters_host = 0.  g = 0 gives u = 0, 0 iterations,
+ * HIF_OK. */
 hif_status_t cn_step(hif_handle_t h, const hif_reaction_t* r, const hif_cg_opts_t* opts,
                      double* u_dev, int32_t* iters_host, double* relres_host, void* hip_stream);
 

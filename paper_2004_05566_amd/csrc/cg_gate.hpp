@@ -36,29 +36,35 @@ struct CgTotal {
   }
 };
 
+// Whether a total of squares is unusable (NaN, or large enough that later products overflow).
+__device__ inline bool cg_bad_total(double total) { return !(total == total) || total > 1.7e308; }
+
 // The test once the total is known: init (the right-hand side g just formed): total = ||g||^2,
-// the solve ends at once when g = 0; otherwise total = ||r||^2 after the update of iteration
-// it0 (0-based), tested against rtol^2 ||g||^2, the iteration cap and overflow / NaN.
+// the solve ends at once when g = 0 (u = 0, no iteration) or when ||g||^2 is not finite
+// (HIF_ERR_NO_CONV after no iteration, u left as it was); otherwise total = ||r||^2 after the
+// update of iteration it0 (0-based), tested against rtol^2 ||g||^2, the iteration cap and
+// overflow / NaN.
 // tol2 and maxit are the state's (read by the caller, possibly ahead of time); for init, maxit is
 // the new step's cap.  Returns whether the iteration stops; `publish` (one lane of one block)
 // writes the scalars.
 __device__ inline bool cg_verdict(CgState* st, int init, int it0, double rtol, double total,
                                   double tol2, int maxit, bool publish) {
   if (init) {  // a new step: its scalars (maxit is the step's cap)
-    const bool stop = !(total > 0.0);
+    const bool bad = cg_bad_total(total);
+    const bool stop = bad || total == 0.0;
     if (publish) {
       st->gg = total;
       st->tol2 = rtol * rtol * total;
       st->rr = total;
       st->iters = 0;
-      st->status = 0;
+      st->status = bad ? HIF_ERR_NO_CONV : 0;
       st->maxit = maxit;
       st->done = stop ? 1 : 0;
     }
     return stop;
   }
   const int it = it0 + 1;
-  const bool bad = !(total == total) || total > 1.7e308;
+  const bool bad = cg_bad_total(total);
   const bool conv = !bad && total <= tol2;
   const bool cap = !bad && !conv && it >= maxit;
   const bool stop = bad || conv || cap;

@@ -182,12 +182,14 @@ __device__ void post_flag(int32_t* hflag, int seq, int iters, int done, int stat
 }
 
 // The end of a CN step: u = x, and the iteration count and relative residual ||r|| / ||g|| of
-// step `step` recorded (block 0).  x0: the lane's first element of x, loaded already.
+// step `step` recorded (block 0).  x0: the lane's first element of x, loaded already.  keep_u:
+// the step failed before its first iteration (a non-finite right-hand side), so u stays.
 __device__ void finish_step(int64_t N, const double* __restrict__ x, double* __restrict__ u,
                             int iters, double rr, double gg, int32_t* it_out, double* rel_out,
-                            int step, double x0) {
+                            int step, double x0, bool keep_u = false) {
   const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) u[i] = i == i0 ? x0 : x[i];
+  if (!keep_u)
+    for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) u[i] = i == i0 ? x0 : x[i];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     it_out[step] = iters;
     rel_out[step] = gg > 0 ? sqrt(rr / gg) : 0.0;
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
   } else if (st->done) {  // stopped by an earlier test of the batch
     if (fin.hflag) {
       finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step,
-                  x0);
+                  x0, st->status != 0 && st->iters == 0);
       if (post) {
         st->ok_next = st->status == 0;
         post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
@@ -343,13 +345,16 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
   block_sum3(rz, zw, zq);
   if (gpart) {
     block_sum3(gg, unused, unused2);
+    // g = 0: u = 0 after no iteration; ||g||^2 not finite: HIF_ERR_NO_CONV after none
+    const bool bad = cg_bad_total(gg);
     if (blockIdx.x == 0 && threadIdx.x == 0 && !dn) {
       st->gg = gg;
       st->tol2 = rtol * rtol * gg;
       st->rr = gg;
-      if (!(gg > 0.0)) st->done = 1;  // g = 0: u = 0 after no iteration
+      if (bad || gg == 0.0) st->done = 1;
+      if (bad) st->status = HIF_ERR_NO_CONV;
     }
-    if (!(gg > 0.0)) dn = 1;
+    if (bad || gg == 0.0) dn = 1;
   }
   const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
   const double pq = first ? zw : zw + beta * (2.0 * zq + beta * st->pqv[(it + 1) & 1]);

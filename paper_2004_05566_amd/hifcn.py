@@ -106,12 +106,20 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _dev_f64(t, name):
+def _dev_f64(t, name, numel=None):
+    """The device address of a contiguous FP64 tensor.  The library takes raw pointers, so the
+    length is checked here (ValueError before any launch) whenever the caller knows it."""
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
             and t.is_contiguous()):
         raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} values, not {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _cells_numel(n: int, dim: int) -> int:
+    return (n + 1) ** dim
 
 
 def _grid(n: int, dim: int, leaf: int) -> _Grid:
@@ -140,14 +148,16 @@ class Handle:
         """out = F^-1 x."""
         import torch
         out = torch.empty_like(x) if out is None else out
-        _check(_lib.hif_apply(self._p(), _dev_f64(x, "x"), _dev_f64(out, "out"), _stream(stream)))
+        _check(_lib.hif_apply(self._p(), _dev_f64(x, "x", self.N), _dev_f64(out, "out", self.N),
+                              _stream(stream)))
         return out
 
     def spmv(self, x, out=None, stream=None):
         """out = (I - dt/2 M) x."""
         import torch
         out = torch.empty_like(x) if out is None else out
-        _check(_lib.hif_spmv(self._p(), _dev_f64(x, "x"), _dev_f64(out, "out"), _stream(stream)))
+        _check(_lib.hif_spmv(self._p(), _dev_f64(x, "x", self.N), _dev_f64(out, "out", self.N),
+                             _stream(stream)))
         return out
 
     def cn_solve(self, u, nsteps: int, rtol: float = 1e-8, maxit: int = 500,
@@ -157,7 +167,7 @@ class Handle:
         o = _CgOpts(float(rtol), int(maxit), 0)
         its = np.zeros(max(1, nsteps), np.int32)
         rel = np.zeros(max(1, nsteps), np.float64)
-        st = _lib.cn_solve(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u"),
+        st = _lib.cn_solve(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u", self.N),
                            int(nsteps), its.ctypes.data_as(_vp), rel.ctypes.data_as(_vp),
                            _stream(stream))
         if st == HIF_ERR_NO_CONV:
@@ -175,15 +185,13 @@ class Handle:
         _check(_lib.hif_refactor(self._p(), self._cells(a_cells), _stream(stream)))
 
     def _cells(self, a_cells):
-        p = _dev_f64(a_cells, "a_cells")
-        if a_cells.numel() != (self.n + 1) ** self.dim:
-            raise ValueError(f"a_cells must hold (n+1)^dim = {(self.n + 1) ** self.dim} values")
-        return p
+        return _dev_f64(a_cells, "a_cells", _cells_numel(self.n, self.dim))
 
     def cn_solve_direct(self, u, nsteps: int, reaction=(0, 0.0, 1.0), stream=None):
         """Advance u (in place) by nsteps Crank-Nicolson steps u <- F^-1 g, without CG."""
         r = _Reaction(int(reaction[0]), float(reaction[1]), float(reaction[2]))
-        _check(_lib.cn_solve_direct(self._p(), ctypes.byref(r), _dev_f64(u, "u"), int(nsteps),
+        _check(_lib.cn_solve_direct(self._p(), ctypes.byref(r), _dev_f64(u, "u", self.N),
+                                    int(nsteps),
                                     _stream(stream)))
 
     def cn_step(self, u, rtol: float = 1e-8, maxit: int = 500, reaction=(0, 0.0, 1.0),
@@ -192,7 +200,7 @@ class Handle:
         o = _CgOpts(float(rtol), int(maxit), 0)
         it = ctypes.c_int32()
         rel = ctypes.c_double()
-        _check(_lib.cn_step(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u"),
+        _check(_lib.cn_step(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u", self.N),
                             ctypes.byref(it), ctypes.byref(rel), _stream(stream)))
         return it.value, rel.value
 
@@ -235,8 +243,10 @@ def cn_batch_step(handles, states, reactions, rtols, maxits, streams):
     its own stream.  Returns (iters, relres, status) arrays; a solve that did not converge has
     status HIF_ERR_NO_CONV (the others are still advanced); any other failure raises."""
     count = len(handles)
+    if not (len(states) == len(reactions) == len(rtols) == len(maxits) == len(streams) == count):
+        raise ValueError("cn_batch_step: every per-solve list must have one entry per handle")
     hs = (_vp * max(1, count))(*[h._p() for h in handles])
-    us = (_vp * max(1, count))(*[_dev_f64(u, "u") for u in states])
+    us = (_vp * max(1, count))(*[_dev_f64(u, "u", h.N) for h, u in zip(handles, states)])
     rs = (_Reaction * max(1, count))(*[_Reaction(int(r[0]), float(r[1]), float(r[2]))
                                       for r in reactions])
     os_ = (_CgOpts * max(1, count))(*[_CgOpts(float(t), int(m), 0)
@@ -260,12 +270,14 @@ def factor(a_cells, dt: float, n: int, dim: int, eps: float, store: str = "f32",
     h = ctypes.c_void_p()
     g = _grid(n, dim, leaf)
     if dense_top is None:
-        _check(_lib.hif_factor(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g),
+        _check(_lib.hif_factor(_dev_f64(a_cells, "a_cells", _cells_numel(n, dim)), float(dt),
+                               ctypes.byref(g),
                                float(eps), STORE[store], _stream(stream), ctypes.byref(h)))
     else:
         o = _FactorOpts()
         o.dense_top = int(dense_top)
-        _check(_lib.hif_factor_ex(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g),
+        _check(_lib.hif_factor_ex(_dev_f64(a_cells, "a_cells", _cells_numel(n, dim)), float(dt),
+                                  ctypes.byref(g),
                                   float(eps), STORE[store], ctypes.byref(o), _stream(stream),
                                   ctypes.byref(h)))
     return Handle(h, n, dim)
@@ -277,7 +289,8 @@ def import_factor(a_cells, dt: float, n: int, dim: int, blob: bytes, store: str 
     h = ctypes.c_void_p()
     g = _grid(n, dim, leaf)
     buf = ctypes.create_string_buffer(blob, len(blob))
-    _check(_lib.hif_import(_dev_f64(a_cells, "a_cells"), float(dt), ctypes.byref(g), buf,
+    _check(_lib.hif_import(_dev_f64(a_cells, "a_cells", _cells_numel(n, dim)), float(dt),
+                           ctypes.byref(g), buf,
                            len(blob), STORE[store], _stream(stream), ctypes.byref(h)))
     return Handle(h, n, dim)
 

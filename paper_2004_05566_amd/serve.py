@@ -241,6 +241,10 @@ class Server:
                 job.fut.set_exception(e)
                 self._cv.notify_all()
                 return
+            if self._error is not None:  # a lane failed meanwhile: no lane will run this one
+                self._abandon_locked(job, self._error)
+                self._cv.notify_all()
+                return
             actual = int(job.handle.info()["device_bytes"])
             self._held += actual - job.held
             job.held = actual
@@ -254,6 +258,20 @@ class Server:
         self._held -= job.held
         job.held = 0
         self._free_streams.append(self._streams.index(job.stream))
+
+    def _abandon_locked(self, job: _Job, exc: BaseException):
+        """Fail an admitted job that will not run (its handle is freed, its slot returned)."""
+        if not job.fut.done():
+            job.fut.set_exception(exc)
+        if job.handle is not None:
+            try:
+                job.handle.close()
+            except Exception:  # noqa: BLE001 - already failing; the slot is returned anyway
+                pass
+            job.handle, job.u = None, None
+        if job.stream is not None:
+            self._release_locked(job)
+            job.stream = None
 
     def _finish(self, job: _Job, status: int):
         r = job.req
@@ -288,7 +306,11 @@ class Server:
         try:
             while True:
                 with self._cv:
-                    if self._error is not None:
+                    if self._error is not None:  # another lane failed: fail this lane's solves
+                        for j in active:
+                            self._abandon_locked(j, self._error)
+                        active.clear()
+                        self._cv.notify_all()
                         return
                     self._admit_locked()
                     if not self._paused:
@@ -324,10 +346,14 @@ class Server:
             with self._cv:
                 if self._error is None:
                     self._error = e
-                for j in list(self._waiting) + self._ready + active:
+                for j in list(self._waiting):  # not admitted: nothing held
                     if not j.fut.done():
                         j.fut.set_exception(e)
                 self._waiting.clear()
+                for j in self._ready + active:
+                    self._abandon_locked(j, e)
+                self._ready.clear()
+                active.clear()
                 self._cv.notify_all()
 
 def percentiles(latencies, qs=(50, 99)) -> dict:

@@ -184,3 +184,39 @@ def test_server_lanes_mix_equals_alone(gpu_lib):
     for r, x in zip(reqs, res):
         u, its, _ = _alone(r)
         assert np.array_equal(x.u, u) and np.array_equal(x.iters, its)
+
+
+def test_server_lane_failure_resolves_every_future(gpu_lib, monkeypatch):
+    """When one scheduler lane's batched step raises, every submitted request still resolves
+    (with that error or its result): the failing lane's solves, the other lanes' active solves,
+    solves whose factor finishes building after the failure, and those still waiting."""
+    import threading
+    from concurrent.futures import wait
+
+    from paper_2004_05566_amd import hifcn
+    from paper_2004_05566_amd.serve import Server
+    real = hifcn.cn_batch_step
+    calls = {"n": 0}
+    lock = threading.Lock()
+
+    def flaky(handles, *a, **k):
+        with lock:
+            calls["n"] += 1
+            boom = calls["n"] == 3 and any(h.n == 64 for h in handles)
+        if boom:
+            raise RuntimeError("planted failure in one lane")
+        return real(handles, *a, **k)
+
+    monkeypatch.setattr(hifcn, "cn_batch_step", flaky)
+    specs = [(32, 1e-2, 6), (64, 1e-1, 6), (128, 1e-3, 6), (64, 1e-2, 6), (32, 1e-1, 6),
+             (128, 1e-2, 6), (96, 1e-2, 6), (48, 1e-3, 6)]
+    reqs = [_req(n, dt, 700 + 10 * i, k) for i, (n, dt, k) in enumerate(specs)]
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=4, builders=2, lanes=3)
+    futs = [srv.submit(r) for r in reqs]
+    done, pending = wait(futs, timeout=120)
+    assert not pending, f"{len(pending)} futures never resolved"
+    errs = [f.exception() for f in futs]
+    assert any(isinstance(e, RuntimeError) for e in errs)
+    with pytest.raises(RuntimeError):
+        srv.close()
+    assert srv._slots == 0 and srv._held == 0
