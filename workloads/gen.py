@@ -94,6 +94,16 @@ def spectral_grf_coefficient(n: int, dim: int, length: float, seed: int, lo: flo
     return np.exp(np.log(lo) + (np.log(hi) - np.log(lo)) * t)
 
 
+def normal_vector(N: int, seed: int) -> np.ndarray:
+    """N iid standard normal values (probe vectors of the parity tests)."""
+    return _rng(seed).normal(size=N)
+
+
+def sample_indices(N: int, count: int, seed: int) -> np.ndarray:
+    """min(N, count) distinct indices in [0, N), sorted (where a full-size comparison samples)."""
+    return np.sort(_rng(seed).choice(N, size=min(N, count), replace=False)).astype(np.int64)
+
+
 def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
     """Arrival times (s, from 0) of a Poisson process of `rate` requests per second."""
     return np.cumsum(_rng(seed).exponential(1.0 / rate, size=count))
