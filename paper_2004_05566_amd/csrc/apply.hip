@@ -349,6 +349,167 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   }
 }
 
+// ------------------------------------------------------------ symmetric-inverse cells (mode 2) --
+// A level-0 cell stored as M = A_II^-1 (= L^-T L^-1, packed column-major lower triangle) and the
+// single stencil coupling of each boundary DOF.  Forward: c_b = A_BI(b, ib_b) (M y_I)_{ib_b},
+// with y_I left as it is; backward: x_I = M (y_I - A_IB x_B).  In exact arithmetic this is the
+// pair of triangular passes of each sweep (E^T: y_I <- L^-1 y_I, c_B = A_BI L^-T (L^-1 y_I);
+// E: x_I <- L^-T (L^-1 y_I - L^-1 A_IB x_B)), since nothing between the two sweeps reads the
+// interior values.  One wavefront per cell (interiors of at most 64 DOFs): the packed triangle
+// is copied into an LDS square with both halves filled (a table gives the two positions of
+// every packed element), then lane i forms (M t)_i by walking column i of the square: lanes
+// read consecutive words, and the mirrored writes of consecutive elements land kSymLd (odd)
+// words apart, so neither the writes nor the walk meet bank conflicts.
+constexpr int kSymPer = (kSymMaxCell * (kSymMaxCell + 1) / 2 + 63) / 64;  // elements per lane
+
+// LDS elements of the compute type a symmetric cell stage needs besides its record.
+__host__ __device__ inline int sym_smem_elems(int maxB) {
+  return kSymMaxCell * kSymLd + 2 * kSymMaxCell + 2 * round_up(maxB, 4);
+}
+
+// Every packed element of the cell block into the square sq (all loads are issued first).
+template <typename S, typename C>
+__device__ __forceinline__ void sym_stage(C* sq, const S* __restrict__ v, int tl,
+                                          const int32_t* __restrict__ tab, int lane) {
+  C e[kSymPer];
+  int32_t t[kSymPer];
+#pragma unroll
+  for (int u = 0; u < kSymPer; ++u) {
+    const int p = lane + 64 * u;
+    if (p < tl) {
+      e[u] = load_as<C>(v + p);
+      t[u] = tab[p];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kSymPer; ++u) {
+    const int p = lane + 64 * u;
+    if (p < tl) {
+      sq[t[u] & 0xffff] = e[u];
+      sq[t[u] >> 16] = e[u];
+    }
+  }
+}
+
+// (M t)_lane for lane < n: column `lane` of the square against t (broadcast from LDS), four
+// running sums added in a fixed order.
+template <typename C>
+__device__ __forceinline__ C sym_col(const C* sq, const C* ts, int n, int lane) {
+  const C* col = sq + lane;
+  C a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int k = 0;
+  for (; k + 8 <= n; k += 8) {
+    C m[8], t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      m[u] = col[(k + u) * kSymLd];
+      t[u] = ts[k + u];
+    }
+    a0 += m[0] * t[0];
+    a1 += m[1] * t[1];
+    a2 += m[2] * t[2];
+    a3 += m[3] * t[3];
+    a0 += m[4] * t[4];
+    a1 += m[5] * t[5];
+    a2 += m[6] * t[6];
+    a3 += m[7] * t[7];
+  }
+  for (; k < n; ++k) a0 += col[k * kSymLd] * ts[k];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// Forward stage of a symmetric cell (one wavefront).  idx: the cell's record (LDS).  in: where
+// the interior inputs are read (y unless another vector; the output y then receives them at the
+// interiors).  hook(ts) runs while the block loads, before the barrier that publishes ts; with
+// own_ys the hook writes ts (and y_I) itself.  stop: looked at after that barrier.
+template <typename S, typename C, typename Hook = NoHook>
+__device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* __restrict__ idx,
+                                             const S* __restrict__ vals, double* __restrict__ y,
+                                             double* __restrict__ cb,
+                                             const int32_t* __restrict__ sqtab,
+                                             unsigned char* smem_raw,
+                                             const double* __restrict__ in = nullptr,
+                                             Hook hook = Hook{}, const int* stop = nullptr,
+                                             bool own_ys = false) {
+  const double* src = in ? in : y;
+  C* sq = reinterpret_cast<C*>(smem_raw);
+  C* ts = sq + kSymMaxCell * kSymLd;
+  C* zs = ts + kSymMaxCell;
+  const int lane = threadIdx.x;
+  const int nI = d.nI, nB = d.nB, tl = tri_count(nI);
+  const S* v = vals + d.offV;
+  const int32_t* gI = idx + d.offI;
+  const int32_t* ibp = idx + d.offC;
+  int gi = -1;
+  double yv = 0;
+  if (!own_ys && lane < nI) {
+    gi = gI[lane];
+    yv = src[gi];
+  }
+  sym_stage<S, C>(sq, v, tl, sqtab + sym_tab_start(nI), lane);
+  if (!own_ys) ts[lane] = (C)yv;
+  hook(ts);
+  __syncthreads();
+  if (stop && *stop) return;
+  if (lane < nI) zs[lane] = sym_col(sq, ts, nI, lane);
+  __syncthreads();
+  for (int b = lane; b < nB; b += 64)
+    cb[d.offCB + b] = (double)(load_as<C>(v + tl + b) * zs[ibp[b]]);
+  if (in && in != y && lane < nI) y[gi] = yv;  // the output takes the inputs at the interiors
+}
+
+// Backward stage of a symmetric cell (one wavefront): x_I = M (x_I - A_IB x_B), the boundary
+// values read from x or, with a dense top folded into this level, added up from its partial
+// sums (and written to x, as every cell on that boundary does).
+template <typename S, typename C>
+__device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* __restrict__ idx,
+                                             const S* __restrict__ vals, double* __restrict__ x,
+                                             const int32_t* __restrict__ sqtab,
+                                             unsigned char* smem_raw, const TopIn& top) {
+  C* sq = reinterpret_cast<C*>(smem_raw);
+  C* ts = sq + kSymMaxCell * kSymLd;
+  C* xbs = ts + 2 * kSymMaxCell;
+  const int lane = threadIdx.x;
+  const int nI = d.nI, nB = d.nB, tl = tri_count(nI);
+  C* abs_ = xbs + round_up(nB, 4);
+  const S* v = vals + d.offV;
+  const int32_t* gI = idx + d.offI;
+  const int32_t* gB = idx + d.offB;
+  const int32_t* rp = idx + d.offC + nB;
+  const int32_t* bl = rp + nI + 1;
+  int gi = -1;
+  double xi = 0;
+  if (lane < nI) {
+    gi = gI[lane];
+    xi = x[gi];
+  }
+  for (int b = lane; b < nB; b += 64) {
+    double xv;
+    if (top.pos) {
+      xv = top.sum(top.pos[b]);
+      x[gB[b]] = xv;
+    } else {
+      xv = x[gB[b]];
+    }
+    xbs[b] = (C)xv;
+    abs_[b] = load_as<C>(v + tl + b);
+  }
+  if (top.pos)
+    for (int e = lane; e < top.ne; e += 64) x[top.ext[2 * e + 1]] = top.sum(top.ext[2 * e]);
+  sym_stage<S, C>(sq, v, tl, sqtab + sym_tab_start(nI), lane);
+  __syncthreads();
+  if (lane < nI) {
+    C t = (C)xi;
+    for (int q = rp[lane]; q < rp[lane + 1]; ++q) {
+      const int b = bl[q];
+      t -= abs_[b] * xbs[b];
+    }
+    ts[lane] = t;
+  }
+  __syncthreads();
+  if (lane < nI) x[gi] = (double)sym_col(sq, ts, nI, lane);
+}
+
 // The first stage of a step's first apply, making the step's right-hand side on the way: the
 // cell's workgroup forms g = (I + dt/2 M) u + dt r(u) (Sec. 2.1) at its interiors, which are the
 // stage's inputs (z = g is the initial residual), and at the DOFs of its copy list (outside every
@@ -363,7 +524,7 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
                                          double* __restrict__ cb, int blk_elems, int team,
                                          const int32_t* __restrict__ gcopy, int gcstride,
                                          const CgRhs& rhs, unsigned char* smem_raw,
-                                         double* gred) {
+                                         double* gred, const int32_t* __restrict__ sqtab) {
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   const bool held = rhs.ahead && !rhs.st->ok_next;  // (the same in every block)
   load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
@@ -395,6 +556,7 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
       ys[i] = (C)g;
       rhs.r[gI[i]] = g;
       rhs.x[gI[i]] = 0.0;
+      if constexpr (MODE == 2) y[gI[i]] = g;  // (the symmetric stage keeps y_I = its input)
       acc += g * g;
     }
     const int32_t* cp = gcopy + (int64_t)blockIdx.x * gcstride;
@@ -407,8 +569,12 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
       acc += g * g;
     }
   };
-  cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
-                                smem_raw + 4 * stride, nullptr, make, nullptr, true);
+  if constexpr (MODE == 2)
+    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sqtab, smem_raw + 4 * stride, nullptr, make, nullptr,
+                       true);
+  else
+    cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
+                                  smem_raw + 4 * stride, nullptr, make, nullptr, true);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) gred[threadIdx.x >> 6] = acc;
@@ -428,13 +594,13 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team, CgGate gate,
                                                   const int32_t* __restrict__ gcopy, int gcstride,
-                                                  CgRhs rhs) {
+                                                  CgRhs rhs, const int32_t* __restrict__ sqtab) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int gstop;
   __shared__ double gred[4];
   if (rhs.u) {  // the step's right-hand side made here (see cell_rhs)
     cell_rhs<S, C, ST, MODE>(recs, stride, vals, y, cb, blk_elems, team, gcopy, gcstride, rhs,
-                             smem_raw, gred);
+                             smem_raw, gred, sqtab);
     return;
   }
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
@@ -475,9 +641,13 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                          blockIdx.x == 0);
     }
   };
-  cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
-                                smem_raw + 4 * stride, gate.src, verdict,
-                                gated ? &gstop : nullptr);
+  if constexpr (MODE == 2)
+    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sqtab, smem_raw + 4 * stride, gate.src, verdict,
+                       gated ? &gstop : nullptr);
+  else
+    cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
+                                  smem_raw + 4 * stride, gate.src, verdict,
+                                  gated ? &gstop : nullptr);
   if (gated && gstop) return;
   if (gated) {  // the DOFs outside every interior that this cell hands over unchanged
     if ((int)threadIdx.x < ccnt) y[cid] = cval;
@@ -596,7 +766,8 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team, const int32_t* __restrict__ tpos,
                                                   int tstride, const double* __restrict__ tpart,
-                                                  int tnch, int tn) {
+                                                  int tnch, int tn,
+                                                  const int32_t* __restrict__ sqtab) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
@@ -609,7 +780,10 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
     const int32_t* r = tpos + (int64_t)blockIdx.x * tstride;
     top = TopIn{r + tstride - d.nB, r + 1, r[0], tpart, tnch, tn};
   }
-  cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride, top);
+  if constexpr (MODE == 2)
+    cell_bwd_sym<S, C>(d, rec, vals, x, sqtab, smem_raw + 4 * stride, top);
+  else
+    cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride, top);
 }
 
 // ----------------------------------------------------------------------------- group stages --
@@ -1372,6 +1546,16 @@ struct StagePlan {
 template <typename C>
 StagePlan cell_plan(const LevelDev& L) {
   StagePlan p{};
+  if (L.cmode == 2) {  // symmetric-inverse cells: one wavefront each, the square in LDS
+    p.staged = true;
+    p.threads = 64;
+    p.seg = 1;
+    p.blk_elems = 0;
+    p.rec = 4 * (size_t)L.cstride;
+    p.smem = sizeof(C) * (size_t)sym_smem_elems(L.maxB);
+    p.grid = L.ncell;
+    return p;
+  }
   p.blk_elems = round_up(L.maxCV, 8);
   const size_t vec = 3 * (size_t)L.maxI + 2 * (size_t)L.maxB + 4;
   const size_t budget = L.ncell >= 2048 ? kStageBudget : kStageMax;
@@ -1558,14 +1742,15 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, cb, done, p.blk_elems, p.seg, gate ? *gate : CgGate{},
            (gate || rhs) ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride,
-           rhs ? *rhs : CgRhs{});
+           rhs ? *rhs : CgRhs{}, (const int32_t*)f.sqtab.p);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, done, p.blk_elems, p.seg,
            fold ? (const int32_t*)f.tpos.p : (const int32_t*)nullptr, f.tpstride,
-           (const double*)f.twsc.p, (f.ntop + f.tspan - 1) / std::max(1, f.tspan), f.ntop);
+           (const double*)f.twsc.p, (f.ntop + f.tspan - 1) / std::max(1, f.tspan), f.ntop,
+           (const int32_t*)f.sqtab.p);
   }
 }
 
@@ -1691,6 +1876,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
       const StageTimer t(prof, l, STAGE_CELL_FWD, done, s);
       if (L.cdense) launch_dense_cells<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
       else if (L.tiled) launch_tiled<S, C>(f, L, true, vals, y, cbl(l), done, s, t);
+      else if (L.cmode == 2) launch_cell<S, C, 2>(f, L, true, vals, y, cbl(l), done, s, t,
+                                                  l == 0 ? gate : nullptr, l == 0 ? rhs : nullptr);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, true, vals, y, cbl(l), done, s, t,
                                              l == 0 ? gate : nullptr, l == 0 ? rhs : nullptr);
       else launch_cell<S, C, 0>(f, L, true, vals, y, cbl(l), done, s, t, l == 0 ? gate : nullptr,
@@ -1758,6 +1945,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
       const StageTimer t(prof, l, STAGE_CELL_BWD, done, s);
       if (L.cdense) launch_dense_cells<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
       else if (L.tiled) launch_tiled<S, C>(f, L, false, vals, y, cbl(l), done, s, t);
+      else if (L.cmode == 2) launch_cell<S, C, 2>(f, L, false, vals, y, cbl(l), done, s, t);
       else if (L.cmode) launch_cell<S, C, 1>(f, L, false, vals, y, cbl(l), done, s, t);
       else launch_cell<S, C, 0>(f, L, false, vals, y, cbl(l), done, s, t);
     }

@@ -201,7 +201,22 @@ __global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict_
     for (int i = 0; i < nI; ++i) acc += G[(int64_t)i * nB + a] * G[(int64_t)i * nB + b];
     schur[t.offS + e] = acc;
   }
-  // apply blocks: packed L^-1, then (mode 0) H = G^T L^-1 column-major (H[j*nB + b])
+  // apply blocks: packed L^-1 (mode 2: packed A_II^-1 = L^-T L^-1), then (mode 0)
+  // H = G^T L^-1 column-major (H[j*nB + b])
+  if (t.mode == 2) {
+    // (A_II^-1)_ij = sum over k >= max(i, j) of (L^-1)_ki (L^-1)_kj; packed column-major lower
+    const int64_t tl = tri_count(nI);
+    for (int64_t e = threadIdx.x; e < tl; e += blockDim.x) {
+      int j = 0;
+      int64_t c = e;
+      while (c >= nI - j) c -= nI - j++;
+      const int i = j + (int)c;
+      double acc = 0;
+      for (int k = i; k < nI; ++k) acc += X[(int64_t)k * nI + i] * X[(int64_t)k * nI + j];
+      V[e] = acc;
+    }
+    return;
+  }
   wg_store_packed(V, X, nI, nI);
   if (t.mode) return;
   double* H = V + tri_count(nI);
@@ -782,8 +797,17 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     int64_t voff = 0;
     std::vector<int64_t> cell_voff(P.cells.size()), grp_voff(G, -1);
     std::vector<int> cell_nB(P.cells.size());
-    // level 0: A_IB is the stencil, one link per boundary DOF; keep that link instead of H
-    const int cmode = lev == 0 ? 1 : 0;
+    // level 0: A_IB is the stencil, one link per boundary DOF; keep that link instead of H.
+    // Where every level-0 interior fits one wavefront (at most 64 DOFs) and none goes through
+    // the front elimination, the cell block is A_II^-1 itself (mode 2, applied as one symmetric
+    // product per sweep), else L^-1 (mode 1, two triangular products).  BF16 keeps L^-1: with
+    // 8-bit significands the rounded A_II^-1 of a stiff cell (kappa(A_II) ~ 1e7 at dt = 0.1 and
+    // contrast 1e4) is no longer positive definite, while L~^-T L~^-1 always is.
+    int maxI_lev = 0;
+    for (int c : P.cells) maxI_lev = std::max(maxI_lev, gsz(c));
+    const bool sym_ok = maxI_lev <= kSymMaxCell && maxI_lev < front_min &&
+                        store != HIF_STORE_BF16 && !sym_cells_off();
+    const int cmode = lev != 0 ? 0 : sym_ok ? 2 : 1;
     std::vector<std::vector<int32_t>> cell_ib(P.cells.size());
     // position of a DOF in the interior of the cell at hand (-1 elsewhere), reset after each cell
     std::vector<int32_t> pos(cmode ? hd.N : 0, -1);
@@ -1343,7 +1367,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       idx.insert(idx.end(), lo.cellB[c].begin(), lo.cellB[c].end());
       d.offC = (int32_t)idx.size();
       idx.insert(idx.end(), lo.cellIb[c].begin(), lo.cellIb[c].end());
-      if (d.mode == 1) {  // links grouped by interior DOF: rowptr[nI + 1], blist[nB]
+      if (d.mode >= 1) {  // links grouped by interior DOF: rowptr[nI + 1], blist[nB]
         const std::vector<int32_t>& ib = lo.cellIb[c];
         std::vector<int32_t> rp(d.nI + 1, 0), bl(ib.size());
         for (int32_t i : ib) ++rp[i + 1];
@@ -1375,6 +1399,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     ld.maxCV = lo.maxCV;
     ld.maxGV = lo.maxGV;
     ld.cmode = lo.cells.empty() ? 0 : lo.cells[0].mode;
+    if (ld.cmode == 2) build_sym_table(f, ld.maxI, s);
     {
       std::vector<int64_t> nsl(lo.groups.size());
       for (size_t q = 0; q < lo.groups.size(); ++q) nsl[q] = (int64_t)lo.gslots[q].size();

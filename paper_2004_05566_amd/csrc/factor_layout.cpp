@@ -10,6 +10,7 @@
 // no serial triangular-solve chain.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <unordered_map>
 
@@ -77,8 +78,12 @@ void level_stage_bytes(const std::vector<CellDesc>& cells, const std::vector<Gro
     const int64_t nI = d.nI, nB = d.nB;
     const int64_t blk = (int64_t)eb * (tri_count(nI) + (d.mode ? nB : nB * nI));
     const int64_t ib = d.mode ? 4 * nB : 0;
-    cf += blk + 8 * (2 * nI + nB) + 4 * nI + ib + (int64_t)sizeof(CellDesc);
-    cbk += blk + 8 * (2 * nI + nB) + 4 * (nI + nB) + ib + (int64_t)sizeof(CellDesc);
+    // mode 2 leaves the interior values in place in the forward sweep (reads y_I, writes c_B);
+    // link modes read the links grouped by interior DOF in the backward sweep
+    const int64_t fvec = d.mode == 2 ? 8 * (nI + nB) : 8 * (2 * nI + nB);
+    const int64_t links = d.mode ? 4 * (nI + 1 + nB) : 0;
+    cf += blk + fvec + 4 * nI + ib + (int64_t)sizeof(CellDesc);
+    cbk += blk + 8 * (2 * nI + nB) + 4 * (nI + nB) + ib + links + (int64_t)sizeof(CellDesc);
   }
   for (size_t q = 0; q < groups.size(); ++q) {
     const GroupDesc& d = groups[q];
@@ -93,6 +98,20 @@ void level_stage_bytes(const std::vector<CellDesc>& cells, const std::vector<Gro
   ld.cell_bytes[1] = cbk;
   ld.group_bytes[0] = gf;
   ld.group_bytes[1] = gbk;
+}
+
+bool sym_cells_off() { return std::getenv("HIFCN_NO_SYM_CELLS") != nullptr; }
+
+void build_sym_table(FactorDev& f, int max_n, hipStream_t s) {
+  HIF_REQUIRE(max_n >= 1 && max_n <= kSymMaxCell, HIF_ERR_ARG, "internal: symmetric cell size");
+  std::vector<int32_t> tab((size_t)sym_tab_start(max_n + 1));
+  for (int n = 1; n <= max_n; ++n) {
+    int32_t* t = tab.data() + sym_tab_start(n);
+    int p = 0;
+    for (int j = 0; j < n; ++j)
+      for (int i = j; i < n; ++i) t[p++] = (j * kSymLd + i) | (i * kSymLd + j) << 16;
+  }
+  f.sqtab.upload(tab, s);
 }
 
 FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf) {

@@ -131,7 +131,21 @@ struct FactorDev {
   // factor build on the matrix cores (front path): algorithmic FP64 flops, kernel time
   int64_t mfma_flops = 0;
   double mfma_ms = 0;
+  // symmetric-inverse cells (CellDesc.mode 2): for every interior size n up to the level's
+  // largest, the two LDS square positions (column-major, leading dimension kSymLd) of each
+  // packed element, (j kSymLd + i) | (i kSymLd + j) << 16, from sym_tab_start(n)
+  DevBuf<int32_t> sqtab;
 };
+
+// ---- symmetric-inverse level-0 cells ---------------------------------------------------------
+constexpr int kSymMaxCell = 64;  // largest interior held as A_II^-1 by one wavefront
+constexpr int kSymLd = 65;       // LDS leading dimension of the mirrored square (odd)
+// First table entry of interior size n: sum over m < n of m (m + 1) / 2.
+__host__ __device__ inline int sym_tab_start(int n) { return (n - 1) * n * (n + 1) / 6; }
+// HIFCN_NO_SYM_CELLS set: level-0 cells keep L^-1 (two triangular products per sweep).
+bool sym_cells_off();
+// Upload f.sqtab for interiors of up to max_n DOFs.
+void build_sym_table(FactorDev& f, int max_n, hipStream_t s);
 
 // Host-side, FP64 version of the same layout (used by import; the GPU build writes the device
 // arrays directly with the same descriptors).
@@ -314,5 +328,9 @@ void launch_cg_dir_dots(Handle& h, int it, hipStream_t s);
 // (rtol: for the first update of a step whose right-hand side the apply made, which also tests
 // g: it totals ||g||^2 and starts tol2.)
 void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s);
+// ||I - A F^-1||_2 by `iters` power-iteration steps on E^T E from x0 (device, N values), its
+// scratch allocated for the call; *est_host receives the estimate (synchronises s).
+hif_status_t inverse_error_impl(Handle& h, const double* x0, int iters, double* est_host,
+                                hipStream_t s);
 
 }  // namespace hifcn
