@@ -1,12 +1,15 @@
 """Benchmark: HIF-preconditioned Crank-Nicolson steps per second on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fisher2d-256] [--store f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat2d-1024] [--store f32]
 
 One timed "step" is one Crank-Nicolson step of the whole hot path: the right-hand side
 (I + dt/2 M) u + dt r(u), then PCG to rtol 1e-8 with the HIF preconditioner (every CG
 iteration: fused direction update + SpMV, vector update, HIF apply, r.z).  The factor is
 built once before timing (its time is reported as t_factor_s).  Inputs are synthetic and
-resident in HBM before the timed region.  Prints one JSON line.
+resident in HBM before the timed region.  The headline is the 1024^2 heat workload (N = 1M,
+per-cell coefficient 10^U(-2,2), dt = 0.1, eps = 1e-3) with FP32 factor storage; the FP64 and
+BF16 stores, the 256^2 Fisher-KPP and 64^3 heat workloads and the serving workload are reported
+beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,6 +28,11 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix, published
 STAGES = ["cell_fwd", "group_fwd", "root", "group_bwd", "cell_bwd"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "cell_stage_level0_pmc.json")
 APPLY_SRC = os.path.join(ROOT, "paper_2004_05566_amd", "csrc", "apply.hip")
+
+
+def _log(msg: str):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def _sync():
@@ -58,6 +66,53 @@ def _time_op(fn, reps):
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def _time_replays(fn, reps=100):
+    """Median duration of `fn` over `reps` replays of a HIP graph holding one call of it, each
+    replay bracketed by HIP events on the replay stream; per-call events on the current stream
+    if the call cannot be captured.  Returns (seconds, how)."""
+    import statistics
+
+    import torch
+    cur = torch.cuda.current_stream()
+    how = "median of %d hipGraph replays" % reps
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                fn()
+        cur.wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        run = g.replay
+    except Exception:  # noqa: BLE001 - fall back to plain launches
+        torch.cuda.synchronize()
+        run, how = fn, "median of %d calls" % reps
+        for _ in range(3):
+            fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        run()
+        e1.record()
+    torch.cuda.synchronize()
+    return statistics.median(e0.elapsed_time(e1) for e0, e1 in ev) / 1e3, how
+
+
+def method_apply_bytes(factor_bytes: int, N: int, dim: int) -> int:
+    """Bytes one F^-1 application must move by the method's count: every stored factor block
+    read once per sweep (2 F_b) plus the FP64 input and output and the level-0 working vector
+    (32 N in 2D; 40 N in 3D, whose level-0 cells exchange more boundary values)."""
+    return 2 * factor_bytes + (32 if dim == 2 else 40) * N
+
+
+def spmv_bytes(N: int, dim: int) -> int:
+    """x and y (FP64) and one link array per axis: 8 (2 + dim) bytes per DOF."""
+    return (8 + 8 + 8 * dim) * N
 
 
 def _build_mfma(info: dict) -> dict:
@@ -179,21 +234,29 @@ def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
     return out
 
 
-def cpu_baseline(w, budget_steps: int):
-    """The FP64 oracle on the same workload: factor build, then `budget_steps` CN steps."""
+def cpu_baseline(w, budget_steps: int, rtol: float = 1e-8):
+    """The FP64 oracle on the same workload: its factor build (reported, not in the value), then
+    `budget_steps` CN steps with BLAS threads = the host's cores, and the same steps again on
+    one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import cn, fd, phif
-    with threadpool_limits(limits=1):
-        A, B = fd.cn_matrices(w.a_cells, w.dt)
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    A, B = fd.cn_matrices(w.a_cells, w.dt)
+    _log(f"cpu baseline: oracle build of {w.name}")
+    with threadpool_limits(limits=nproc):
         t0 = time.perf_counter()
         F = phif.phif_build(A, w.n, w.dim, w.leaf, w.eps)
         tf = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _, its, _ = cn.cn_solve(A, B, w.u0, w.dt, budget_steps,
-                                lambda r: phif.phif_apply(F, r), 1e-8, w.reaction)
-        ts = time.perf_counter() - t0
+    times, its = {}, []
+    for threads in (nproc, 1):
+        _log(f"cpu baseline: {budget_steps} step(s) on {threads} thread(s)")
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            _, its, _ = cn.cn_solve(A, B, w.u0, w.dt, budget_steps,
+                                    lambda r: phif.phif_apply(F, r), rtol, w.reaction)
+            times[threads] = time.perf_counter() - t0
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -202,33 +265,13 @@ def cpu_baseline(w, budget_steps: int):
                 break
     except OSError:
         pass
-    return {"value": budget_steps / ts, "unit": "CN steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.name}: oracle PHIF build ({tf:.1f} s, untimed in value) then "
-                      f"{budget_steps} CN steps at rtol 1e-8, mean n_i {np.mean(its):.2f}, "
-                      f"one thread",
+    return {"value": budget_steps / times[nproc], "unit": "CN steps/s", "cores": nproc,
+            "kind": "oracle",
+            "sample": f"{w.name}: oracle PHIF build ({tf:.1f} s, not in the value) then the first "
+                      f"{budget_steps} CN step(s) at rtol {rtol:g}, n_i {list(its)}, BLAS "
+                      f"threads = {nproc}",
+            "one_thread": {"value": budget_steps / times[1], "cores": 1},
             "t_factor_s": tf, "host_cpu": model, "host_nproc": os.cpu_count()}
-
-
-def inverse_error(h, N, iters=30, seed=0):
-    """||I - A F^-1||_2 by power iteration on E^T E, E = I - A F^-1 (A and F^-1 symmetric, so
-    E^T = I - F^-1 A), from a seeded random start; applies and products on the GPU."""
-    import torch
-    g = torch.Generator(device="cuda").manual_seed(seed)
-    x = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
-    x /= torch.linalg.norm(x)
-    t = torch.empty_like(x)
-    s = torch.empty_like(x)
-    lam = 0.0
-    for _ in range(iters):
-        h.apply(x, out=t)       # F^-1 x
-        h.spmv(t, out=s)        # A F^-1 x
-        y = x - s               # E x
-        h.spmv(y, out=t)        # A y
-        h.apply(t, out=s)       # F^-1 A y
-        z = y - s               # E^T E x
-        lam = float(torch.linalg.norm(z))
-        x = z / lam
-    return lam ** 0.5
 
 
 def replica(sizes2d, sizes3d, steps, store, logistic=False):
@@ -268,7 +311,8 @@ def replica(sizes2d, sizes3d, steps, store, logistic=False):
                        "n_i_mean": float(np.mean(its)), "n_i_paper": paper,
                        "t_factor_s": tf, "t_step_s": ts, "factor_GB": h.factor_bytes() / 1e9}
                 if eps == 1e-6:
-                    row["inv_error"] = inverse_error(h, w.N)
+                    row["inv_error"] = h.inverse_error(
+                        torch.tensor(gen.normal_vector(w.N, 0), device="cuda"), 30)
                     # the same steps with the factor as the solver (no CG)
                     ud = torch.tensor(w.u0.ravel(), dtype=torch.float64, device="cuda")
                     h.cn_solve_direct(ud, 1, reaction=w.reaction)
@@ -329,32 +373,22 @@ def drift(w, steps, everies, store, amp=0.5):
     return out
 
 
-def reference_error(w, u_gpu, nsteps):
-    """Relative error of the GPU u against the FP64 sparse direct solution of the same steps."""
-    import numpy as np
-    import scipy.sparse.linalg as spla
-
-    from oracle import cn, fd
-    A, B = fd.cn_matrices(w.a_cells, w.dt)
-    lu = spla.splu(A.tocsc())
-    u = w.u0.ravel().copy()
-    for _ in range(nsteps):
-        u = lu.solve(cn.cn_rhs(B, u, w.dt, w.reaction))
-    return float(np.linalg.norm(u_gpu - u) / np.linalg.norm(u))
-
-
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fisher2d-256")
+    ap.add_argument("--workload", default="heat2d-1024")
     ap.add_argument("--store", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--leaf", type=int, default=0, help="leaf box size (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the error check")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the 256^2 and 64^3 workloads reported beside the headline")
+    ap.add_argument("--cpu-steps", type=int, default=1,
+                    help="CN steps of the oracle in the CPU baseline sample")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving workload (0: skip)")
     ap.add_argument("--serving-rate", type=float, default=-1.0,
@@ -395,10 +429,7 @@ def main(argv=None):
         replica(sz["2d"], sz["3d"], args.steps, args.store, args.logistic)
         return 0
 
-    import numpy as np
-    import torch
-
-    from paper_2004_05566_amd import hifcn
+    from paper_2004_05566_amd import hifcn  # noqa: F401  (fails loudly without the library)
     from workloads import gen
 
     def serving():
@@ -423,62 +454,31 @@ def main(argv=None):
     w = gen.workload(args.workload)
     if args.leaf:
         w.leaf = args.leaf
-    dev = torch.device("cuda:0")
-    a_dev = torch.tensor(w.a_cells, dtype=torch.float64, device=dev)
-    u0 = torch.tensor(w.u0.ravel(), dtype=torch.float64, device=dev)
-    react = w.reaction
-
-    _sync()
-    t0 = time.perf_counter()
-    h = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store=args.store, leaf=w.leaf)
-    _sync()
-    t_factor = time.perf_counter() - t0
-
-    elapsed, its, rel, u = _time_cn(h, u0, args.steps, args.warmup, args.rtol, react)
-    value = args.steps / elapsed
-
-    # dominant kernel: the level-0 cell stages, timed live with HIP events on the stream they
-    # run on, over a second pass of the same timed steps
-    roof = {}
-    for st in ("cell_fwd", "cell_bwd"):
-        h.profile_stage(0, st, True)
-        _time_cn(h, u0, args.steps, 0, args.rtol, react)
-        p = h.profile_read()
-        h.profile_stage(0, st, False)
-        roof[st] = p
-    dom = max(roof, key=lambda k: roof[k]["ms"])
-    pd = roof[dom]
-    avg_s = pd["ms"] / 1e3 / max(1, pd["launches"])
-    achieved = pd["bytes"] / avg_s / 1e9
-    kname = {"cell_fwd": "k_cell_fwd", "cell_bwd": "k_cell_bwd"}[dom]
-    traffic = pmc_traffic(kname, args.store, w.name)
-
-    # FP64-stored factor, same workload (the metric compares both forms)
-    h64 = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store="f64", leaf=w.leaf)
-    el64, its64, _, _ = _time_cn(h64, u0, args.steps, args.warmup, args.rtol, react)
-
-    # apply and SpMV bandwidth (algorithmic bytes: the sum over the apply's stages of the factor
-    # blocks in the form they are read, their index lists and the FP64 vectors they move)
-    x = torch.randn(w.N, dtype=torch.float64, device=dev)
-    y = torch.empty_like(x)
-    t_apply = _time_op(lambda: h.apply(x, out=y), 50)
-    apply_bytes = h.info()["apply_bytes"]
-    t_spmv = _time_op(lambda: h.spmv(x, out=y), 200)
-    spmv_bytes = (8 + 8 + 8 * w.dim) * w.N
-    stages = None if args.no_stages else stage_breakdown(h, x, y, h.info()["levels"])
-
-    err = None
-    if not args.no_check:
-        err = reference_error(w, u.cpu().numpy(), args.warmup + args.steps)
-
+    head = measure(w, args.store, args.steps, args.warmup, args.rtol, roofline=True,
+                   stages=not args.no_stages, check=not args.no_check)
+    side = {}
+    for st in ("f64", "bf16"):
+        if st != args.store:
+            side[st] = measure(w, st, args.steps, args.warmup, args.rtol,
+                               check=not args.no_check)
+    others = {}
+    if not args.no_others:
+        for name in ("fisher2d-256", "heat3d-64"):
+            if name == w.name:
+                continue
+            wo = gen.workload(name)
+            others[name] = {st: measure(wo, st, args.steps, args.warmup, args.rtol,
+                                        check=not args.no_check)
+                            for st in ("f32", "f64")}
+    roof = head.pop("roofline")
     out = {
         "metric": "CN steps/s at 1e-8 rel. resid (FP32-HIF vs FP64), HIF-apply GB/s; p99 latency",
-        "value": value,
+        "value": head["value"],
         "unit": "CN steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -487,34 +487,127 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "dim": w.dim, "n": w.n, "eps": w.eps,
                    "dt": w.dt, "leaf": w.leaf, "store": args.store, "rtol": args.rtol,
-                   "reaction": list(react)},
-        "n_i_mean": float(np.mean(its)),
-        "f64_store": {"value": args.steps / el64, "n_i_mean": float(np.mean(its64))},
-        "t_factor_s": t_factor,
-        "build_mfma": _build_mfma(h.info()),
-        "factor_bytes": h.factor_bytes(),
-        "device_bytes": h.info()["device_bytes"],
-        "apply": {"us": t_apply * 1e6, "GB/s": apply_bytes / t_apply / 1e9,
-                  "bytes": apply_bytes},
-        "spmv": {"us": t_spmv * 1e6, "GB/s": spmv_bytes / t_spmv / 1e9, "bytes": spmv_bytes},
-        "rel_err_vs_direct": err,
-        "roofline": {"bound": "hbm", "kernel": f"{kname} (level 0, {dom})",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": pd["bytes"],
-                     "avg_us": avg_s * 1e6, "launches": pd["launches"],
-                     "other_level0_stage_us": {k: 1e3 * v["ms"] / max(1, v["launches"])
-                                               for k, v in roof.items()}},
-        "apply_stages": stages,
+                   "reaction": list(w.reaction)},
+        **head,
+        "roofline": roof,
+        "f64_store": side.get("f64"),
+        "bf16_store": side.get("bf16"),
+        "other_workloads": others,
     }
-    h.close()
-    h64.close()
     if args.serving:
         out["serving"] = serving()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, 10)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out))
     return 0
+
+
+def oracle_error(w, h, store, rtol):
+    """Error of two GPU CN steps at `rtol` from u0 against the oracle's (FP64 block PHIF, PCG at
+    rtol 1e-12) at the sampled nodes of the committed expected values (tests/golden/
+    fullsize_*.npz, written by tests/golden/make_fullsize.py from the oracle alone); None for a
+    workload without them."""
+    import numpy as np
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{w.name}.npz")
+    u = torch.tensor(w.u0.ravel(), dtype=torch.float64, device="cuda")
+    if os.path.exists(path):
+        g = np.load(path)
+        out = {"against": "oracle PHIF-PCG at rtol 1e-12, sampled nodes", "steps": []}
+        for k in range(1, int(g["steps"]) + 1):
+            h.cn_solve(u, 1, rtol=rtol, reaction=w.reaction)
+            ug = u.cpu().numpy()
+            out["steps"].append({
+                "max_rel": float(np.abs(ug[g["idx"]] - g[f"u{k}"]).max() / g[f"amax{k}"]),
+                "norm_rel": float(abs(np.linalg.norm(ug) - g[f"norm{k}"]) / g[f"norm{k}"])})
+        out["max_rel"] = max(x["max_rel"] for x in out["steps"])
+        return out
+    return None
+
+
+def measure(w, store, steps, warmup, rtol, roofline=False, stages=False, check=True):
+    """Build the factor of workload w in `store` precision, time `steps` CN steps (after
+    `warmup`), the apply and the SpMV; optionally the dominant kernel's roofline, the per-stage
+    breakdown and the error against the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2004_05566_amd import hifcn
+    _log(f"measure {w.name} store {store}")
+    dev = torch.device("cuda:0")
+    a_dev = torch.tensor(w.a_cells, dtype=torch.float64, device=dev)
+    u0 = torch.tensor(w.u0.ravel(), dtype=torch.float64, device=dev)
+    _sync()
+    t0 = time.perf_counter()
+    h = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store=store, leaf=w.leaf)
+    _sync()
+    t_factor = time.perf_counter() - t0
+    elapsed, its, rel, u = _time_cn(h, u0, steps, warmup, rtol, w.reaction)
+    info = h.info()
+    fb = h.factor_bytes()
+    x = torch.randn(w.N, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    t_apply, how = _time_replays(lambda: h.apply(x, out=y))
+    t_spmv, _ = _time_replays(lambda: h.spmv(x, out=y))
+    mb = method_apply_bytes(fb, w.N, w.dim)
+    sb = spmv_bytes(w.N, w.dim)
+    res = {
+        "value": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "n_i_mean": float(np.mean(its)),
+        "n_i": [int(i) for i in its],
+        "t_factor_s": t_factor,
+        "factor_bytes": fb,
+        "device_bytes": info["device_bytes"],
+        "build_mfma": _build_mfma(info),
+        "apply": {"us": t_apply * 1e6, "GB/s": mb / t_apply / 1e9,
+                  "frac_of_peak": mb / t_apply / 1e9 / HBM_PEAK_GBS, "method_bytes": mb,
+                  "read_bytes": info["apply_bytes"],
+                  "read_amplification": info["apply_bytes"] / mb, "timing": how},
+        "spmv": {"us": t_spmv * 1e6, "GB/s": sb / t_spmv / 1e9,
+                 "frac_of_peak": sb / t_spmv / 1e9 / HBM_PEAK_GBS, "bytes": sb, "timing": how},
+    }
+    if stages:
+        res["apply_stages"] = stage_breakdown(h, x, y, info["levels"])
+    if roofline:
+        res["roofline"] = dominant_roofline(h, w, store, u0, steps, rtol, res.get("apply_stages"))
+    if check:
+        res["err_vs_oracle"] = oracle_error(w, h, store, rtol)
+    h.close()
+    del a_dev, u0, u, x, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def dominant_roofline(h, w, store, u0, steps, rtol, stages):
+    """The apply stage that takes the most time per apply, timed live with HIP events on the
+    stream it runs on over a second pass of the timed CN steps: algorithmic bytes per launch
+    over the average launch duration, against the HBM peak."""
+    cands = [("cell_fwd", 0), ("cell_bwd", 0)]
+    if stages:
+        top = max(stages, key=lambda r: r["us"])
+        cands = [(top["stage"], top["level"])] + [c for c in cands
+                                                  if c != (top["stage"], top["level"])]
+    roof = {}
+    for st, lev in cands:
+        h.profile_stage(lev, st, True)
+        _time_cn(h, u0, steps, 0, rtol, w.reaction)
+        p = h.profile_read()
+        h.profile_stage(lev, st, False)
+        roof[(st, lev)] = p
+    key = max(roof, key=lambda k: roof[k]["ms"])
+    pd = roof[key]
+    avg_s = pd["ms"] / 1e3 / max(1, pd["launches"])
+    achieved = pd["bytes"] / avg_s / 1e9
+    kname = {"cell_fwd": "k_cell_fwd", "cell_bwd": "k_cell_bwd", "group_fwd": "k_fuse_fwd",
+             "group_bwd": "k_group_bwd", "root": "k_top_rows"}[key[0]]
+    return {"bound": "hbm", "kernel": f"{kname} (level {key[1]}, {key[0]})",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pmc_traffic(kname, store, w.name), "bytes_per_launch": pd["bytes"],
+            "avg_us": avg_s * 1e6, "launches": pd["launches"],
+            "stage_us": {f"{k[0]}@{k[1]}": 1e3 * v["ms"] / max(1, v["launches"])
+                         for k, v in roof.items()}}
 
 
 if __name__ == "__main__":

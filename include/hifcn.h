@@ -166,6 +166,19 @@ hif_status_t cn_batch_step(hif_handle_t* h, const hif_reaction_t* r, const hif_c
                            double** u_dev, int32_t count, int32_t* iters_host,
                            double* relres_host, int32_t* status_host, void** hip_streams);
 
+/* Estimate of ||I - A F^-1||_2, how far the factor is from A^-1 (Sec. 3, Example 1, where the
+ * paper estimates this norm by a randomized power iteration: 7.9e-6 at eps = 1e-6 on 4095^2).
+ * With E = I - A F^-1 (E^T = I - F^-1 A, A and F^-1 being symmetric): x = x0 / ||x0||, then
+ * `iters` times y = E^T E x, lambda = ||y||, x = y / lambda; *est_host = sqrt(lambda), a lower
+ * bound of ||E||_2 that rises towards it (0 for iters = 0).  x0_dev: the caller's start vector
+ * (device, N FP64, not modified; a random one makes the bound hold with high probability).
+ * Scratch: 4 N + 520 FP64 values, allocated for the call and freed before it returns.  The
+ * estimate is deterministic (fixed-order reductions).  Synchronises `hip_stream`.  Uses the
+ * handle's apply buffers: not concurrently with another call on the same handle.
+ * Errors: HIF_ERR_ARG (NULL argument, iters < 0), HIF_ERR_OOM, HIF_ERR_HIP. */
+hif_status_t hif_inverse_error(hif_handle_t h, const double* x0_dev, int32_t iters,
+                               double* est_host, void* hip_stream);
+
 /* Stored factor bytes (unpadded, in the storage precision; without the dense forms that
  * hif_get_info's device_bytes includes). */
 size_t hif_factor_bytes(hif_handle_t h);

@@ -14,6 +14,7 @@ Modules (each function cites the passage of the paper it follows):
   phif        -- block PHIF build (steps 1-3 per level, root) and apply of eqAinv (Sec. 2.2)
   phif_dense  -- dense-literal PHIF: the N x N factors of eqs eq2_3, jacobi-precond, eq_T,
                  eq2_9 formed and multiplied as written; pins ``phif`` on tiny grids
+  estimate    -- power-iteration estimate of ||I - A F^-1||_2 (Sec. 3, Example 1)
 
 Parity status: ``fd``, ``cn`` and the PHIF build/apply are pinned by tests (closed forms,
 direct solves, the dense-literal transcription, the exactness at eps = 0, structural

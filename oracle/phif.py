@@ -122,8 +122,19 @@ def _keep(Acur: sp.csr_matrix, keep: np.ndarray) -> sp.csr_matrix:
     return (D @ Acur @ D).tocsr()
 
 
-def phif_build(A: sp.spmatrix, n: int, dim: int, leaf: int, eps: float) -> Factor:
-    """Build the PHIF factor of the SPD matrix A on the n^dim grid (Sec. 2.2)."""
+def phif_build(A: sp.spmatrix, n: int, dim: int, leaf: int, eps: float,
+               id_order: str = "level") -> Factor:
+    """Build the PHIF factor of the SPD matrix A on the n^dim grid (Sec. 2.2).
+
+    id_order: how the edges of a level meet each other's eliminations in step (3) (eq3_3 takes
+    the product over the edges but not their order).  "level": every ID sees the matrix after
+    step (2) of the level (the reading used throughout).  "sequential": the edges are
+    skeletonized one after another in key order, each ID from the matrix the earlier ones left.
+    An earlier edge's skeletonization drops its (R, I~) residual and eliminates I~; the
+    couplings of its skeleton are unchanged, so the only difference a later edge sees is that
+    the rows of the earlier edges' redundant DOFs are gone from its block."""
+    if id_order not in ("level", "sequential"):
+        raise ValueError(f"unknown id_order {id_order!r}")
     A = sp.csr_matrix(A, dtype=np.float64)
     N = A.shape[0]
     assert N == n ** dim
@@ -199,6 +210,8 @@ def phif_build(A: sp.spmatrix, n: int, dim: int, leaf: int, eps: float) -> Facto
             col = Acsc[:, g]
             nz = np.unique(col.nonzero()[0])
             R = np.setdiff1d(nz, g)
+            if id_order == "sequential":
+                R = R[~red_all[R]]
             Mblk = _dense(Acur, R, g)
             sk_pos, rd_pos, T = interp_decomp(Mblk, eps)
             nr = len(rd_pos)

@@ -10,6 +10,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its HIP runtime is then the one the library binds to (both carry the same
+# soname), so device pointers and streams from torch are valid in the library's calls.  With the
+# library loaded first, its runtime came up without the device in a later torch process.
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhifcn.so")
 if not os.path.exists(_LIB_PATH):
@@ -76,6 +80,8 @@ _lib.cn_solve.argtypes = [_vp, ctypes.POINTER(_Reaction), ctypes.POINTER(_CgOpts
                           ctypes.c_int32, _vp, _vp, _vp]
 _lib.cn_solve_direct.argtypes = [_vp, ctypes.POINTER(_Reaction), _vp, ctypes.c_int32, _vp]
 _lib.cn_batch_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
+_lib.hif_inverse_error.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                  _vp]
 _lib.hif_factor_bytes.argtypes = [_vp]
 _lib.hif_factor_bytes.restype = ctypes.c_size_t
 _lib.hif_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
@@ -86,13 +92,13 @@ _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
 for _f in ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
            "cn_solve_direct", "cn_batch_step", "hif_get_info", "hif_profile_stage",
-           "hif_profile_read", "hif_set_coefficient", "hif_refactor"):
+           "hif_profile_read", "hif_set_coefficient", "hif_refactor", "hif_inverse_error"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step",
            "cn_solve", "cn_solve_direct", "cn_batch_step", "hif_factor_bytes", "hif_get_info",
            "hif_profile_stage", "hif_profile_read", "hif_destroy", "hif_last_error",
-           "hif_set_coefficient", "hif_refactor")
+           "hif_set_coefficient", "hif_refactor", "hif_inverse_error")
 
 
 def _check(status: int):
@@ -213,6 +219,13 @@ class Handle:
         _check(_lib.hif_profile_read(self._p(), ctypes.byref(p)))
         return {"level": p.level, "stage": p.stage, "launches": p.launches, "ms": p.ms,
                 "bytes": p.bytes}
+
+    def inverse_error(self, x0, iters: int = 30, stream=None) -> float:
+        """hif_inverse_error: the power-iteration estimate of ||I - A F^-1||_2 from x0."""
+        est = ctypes.c_double()
+        _check(_lib.hif_inverse_error(self._p(), _dev_f64(x0, "x0", self.N), int(iters),
+                                      ctypes.byref(est), _stream(stream)))
+        return est.value
 
     def factor_bytes(self) -> int:
         return int(_lib.hif_factor_bytes(self._p()))

@@ -171,3 +171,45 @@ def test_iterations_do_not_grow_with_n():
         its.append(np.mean(it))
     assert max(its) - min(its) <= 1.5
     assert max(its) <= 8
+
+
+def test_inverse_error_estimate_against_dense_norm():
+    """The power-iteration estimate of ||I - A F^-1||_2 (Sec. 3, Example 1) against the exact
+    2-norm from an SVD of the dense I - A F^-1: never above it (every Rayleigh-type ratio of
+    E^T E is at most ||E||^2), within 2% of it after enough steps, and 0 at eps = 0 (F = A)."""
+    from oracle import estimate
+    n, m = 31, 8
+    a = gen.iid_loguniform_cells(n, 2, 41)
+    A, _ = fd.cn_matrices(a, 0.05)
+    x0 = gen.normal_vector(n * n, 42)
+    for eps in (1e-2, 1e-4):
+        F = phif.phif_build(A, n, 2, m, eps)
+        E = np.eye(n * n) - A @ phif.phif_dense_inverse(F)
+        exact = np.linalg.norm(E, 2)
+        est = estimate.inverse_error_power(A, lambda r: phif.phif_apply(F, r), x0, 200)
+        assert est <= exact * (1 + 1e-10), (est, exact)
+        assert est >= 0.98 * exact, (est, exact)
+        assert exact > 0
+    F0 = phif.phif_build(A, n, 2, m, 0.0)
+    assert estimate.inverse_error_power(A, lambda r: phif.phif_apply(F0, r), x0, 20) < 1e-12
+
+
+def test_sequential_id_order_exact_at_eps0_and_close_otherwise():
+    """The sequential order of the edge IDs within a level (each from the matrix the earlier
+    edges left) against the level-synchronous reading: both exact at eps = 0 (no compression,
+    F = A), the same structure of levels, and inverse errors of the same order at eps > 0."""
+    import scipy.sparse.linalg as spla
+    n, m = 63, 8
+    a = gen.iid_loguniform_cells(n, 2, 43)
+    A, _ = fd.cn_matrices(a, 0.05)
+    r = gen.normal_vector(n * n, 44)
+    ref = spla.spsolve(A.tocsc(), r)
+    for order in ("level", "sequential"):
+        F = phif.phif_build(A, n, 2, m, 0.0, id_order=order)
+        assert np.linalg.norm(phif.phif_apply(F, r) - ref) <= 1e-11 * np.linalg.norm(ref)
+    Fl = phif.phif_build(A, n, 2, m, 1e-3, id_order="level")
+    Fs = phif.phif_build(A, n, 2, m, 1e-3, id_order="sequential")
+    assert len(Fl.levels) == len(Fs.levels)
+    el = np.linalg.norm(r - A @ phif.phif_apply(Fl, r)) / np.linalg.norm(r)
+    es = np.linalg.norm(r - A @ phif.phif_apply(Fs, r)) / np.linalg.norm(r)
+    assert 0.1 < es / el < 10, (el, es)
