@@ -196,13 +196,13 @@ def test_server_lane_failure_resolves_every_future(gpu_lib, monkeypatch):
     from paper_2004_05566_amd import hifcn
     from paper_2004_05566_amd.serve import Server
     real = hifcn.cn_batch_step
-    calls = {"n": 0}
+    fired = {"done": False}
     lock = threading.Lock()
 
     def flaky(handles, *a, **k):
-        with lock:
-            calls["n"] += 1
-            boom = calls["n"] == 3 and any(h.n == 64 for h in handles)
+        with lock:  # the first batch holding a 64^2 solve fails
+            boom = not fired["done"] and any(h.n == 64 for h in handles)
+            fired["done"] = fired["done"] or boom
         if boom:
             raise RuntimeError("planted failure in one lane")
         return real(handles, *a, **k)
