@@ -524,10 +524,11 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
                                          double* __restrict__ cb, int blk_elems, int team,
                                          const int32_t* __restrict__ gcopy, int gcstride,
                                          const CgRhs& rhs, unsigned char* smem_raw,
-                                         double* gred, const int32_t* __restrict__ sqtab) {
+                                         double* gred, const int32_t* __restrict__ sqtab,
+                                         int flen) {
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   const bool held = rhs.ahead && !rhs.st->ok_next;  // (the same in every block)
-  load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
+  load_record(rec, recs + (int64_t)blockIdx.x * stride, flen, threadIdx.x, blockDim.x);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     CgState* st = rhs.st;
     st->hold = held ? 1 : 0;
@@ -546,7 +547,7 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
     const double l = rhs.dim == 2
                          ? link_sum<2>(i, rhs.n, rhs.links, ui, [&](int64_t k) { return rhs.u[k]; })
                          : link_sum<3>(i, rhs.n, rhs.links, ui, [&](int64_t k) { return rhs.u[k]; });
-    return ui - l + rhs.dt * react(ui, rhs.kind, rhs.k1, rhs.k2);
+    return cn_rhs_value(ui, l, rhs.dt, rhs.kind, rhs.k1, rhs.k2);
   };
   double acc = 0;
   auto make = [&](C* ys) {
@@ -594,13 +595,14 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team, CgGate gate,
                                                   const int32_t* __restrict__ gcopy, int gcstride,
-                                                  CgRhs rhs, const int32_t* __restrict__ sqtab) {
+                                                  CgRhs rhs, const int32_t* __restrict__ sqtab,
+                                                  int flen) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int gstop;
   __shared__ double gred[4];
   if (rhs.u) {  // the step's right-hand side made here (see cell_rhs)
     cell_rhs<S, C, ST, MODE>(recs, stride, vals, y, cb, blk_elems, team, gcopy, gcstride, rhs,
-                             smem_raw, gred, sqtab);
+                             smem_raw, gred, sqtab, flen);
     return;
   }
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
     ccnt = cp[0];
     if ((int)threadIdx.x < gcstride - 1) cid = cp[1 + threadIdx.x];
   }
-  load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
+  load_record(rec, recs + (int64_t)blockIdx.x * stride, flen, threadIdx.x, blockDim.x);
   const int dn = gated ? 0 : (done ? *done : 0);
   if (gated && cid >= 0) cval = gate.src[cid];  // (padding entries read DOF 0; never stored)
   __syncthreads();
@@ -1742,7 +1744,7 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, cb, done, p.blk_elems, p.seg, gate ? *gate : CgGate{},
            (gate || rhs) ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride,
-           rhs ? *rhs : CgRhs{}, (const int32_t*)f.sqtab.p);
+           rhs ? *rhs : CgRhs{}, (const int32_t*)f.sqtab.p, L.cfwd);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
@@ -2091,12 +2093,12 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM_ALL(double, double);
   HIF_SMEM_ALL(float, float);
   HIF_SMEM_ALL(bf16_t, float);
+
 #undef HIF_SMEM_ALL
 #undef HIF_SMEM_TILES
 #undef HIF_SMEM
   granted = bytes;
 }
-
 
 namespace {
 // Tiles of one level; its cells' interiors take scratch [*base, *base + sum nI): every level
@@ -2122,21 +2124,25 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
 }  // namespace
 
 namespace {
-// Record of one cell: the descriptor with record-relative index offsets, then I, B and (link
-// mode) the interior positions of the couplings.
+// Record of one cell: the descriptor with record-relative index offsets, then I, (link modes)
+// the interior position of each boundary DOF's coupling and the couplings grouped by interior
+// DOF, then B.  The forward stage reads only the prefix up to the coupling positions
+// (cell_fwd_len); the backward stage reads the whole record.
 int cell_record_len(const CellDesc& d) {
   return round_up(8 + d.nI + d.nB + (d.mode ? 2 * d.nB + d.nI + 1 : 0), 4);
 }
+int cell_fwd_len(const CellDesc& d) { return round_up(8 + d.nI + (d.mode ? d.nB : 0), 4); }
 void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& idx) {
+  const int nc = d.mode ? 2 * d.nB + d.nI + 1 : 0;
   CellDesc e = d;
   e.offI = 8;
-  e.offB = 8 + d.nI;
-  e.offC = d.mode ? 8 + d.nI + d.nB : 0;
+  e.offC = d.mode ? 8 + d.nI : 0;
+  e.offB = 8 + d.nI + nc;
   std::memcpy(r, &e, sizeof(CellDesc));
   for (int i = 0; i < d.nI; ++i) r[8 + i] = idx[d.offI + i];
-  for (int b = 0; b < d.nB; ++b) r[8 + d.nI + b] = idx[d.offB + b];
-  if (d.mode)  // ib[nB], then the links grouped by interior DOF: rowptr[nI + 1], blist[nB]
-    for (int q = 0; q < 2 * d.nB + d.nI + 1; ++q) r[8 + d.nI + d.nB + q] = idx[d.offC + q];
+  // ib[nB], then the links grouped by interior DOF: rowptr[nI + 1], blist[nB]
+  for (int q = 0; q < nc; ++q) r[8 + d.nI + q] = idx[d.offC + q];
+  for (int b = 0; b < d.nB; ++b) r[e.offB + b] = idx[d.offB + b];
 }
 // Record of one group: the descriptor, then DOF ids, pivot order, gather pointers and slots.
 int group_record_len(const GroupDesc& g, const std::vector<int32_t>& idx) {
@@ -2166,7 +2172,11 @@ void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
   for (int l = 0; l < nlev; ++l) {
     LevelDev& L = f.lv[l];
     L.cstride = 4;
-    for (const CellDesc& d : cells[l]) L.cstride = std::max(L.cstride, cell_record_len(d));
+    L.cfwd = 4;
+    for (const CellDesc& d : cells[l]) {
+      L.cstride = std::max(L.cstride, cell_record_len(d));
+      L.cfwd = std::max(L.cfwd, cell_fwd_len(d));
+    }
     std::vector<int32_t> cr((size_t)cells[l].size() * L.cstride, 0);
     for (size_t c = 0; c < cells[l].size(); ++c)
       put_cell_record(cr.data() + c * L.cstride, cells[l][c], idx);

@@ -46,6 +46,7 @@ struct LevelDev {
   // followed by those of the groups it owns.
   DevBuf<int32_t> crec, grec, frec;
   int cstride = 0, gstride = 0, fstride = 0;
+  int cfwd = 0;  // int32 of each cell record the forward stage reads (descriptor, I, couplings)
 };
 
 // Stages of one apply, as timed by the profiler.

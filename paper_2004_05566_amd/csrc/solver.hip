@@ -96,14 +96,26 @@ __global__ void k_links3d(const double* __restrict__ a, int n, double scale, dou
   }
 }
 
+// y = A x, two nodes per lane per turn (i and i + stride) so that both nodes' loads are in
+// flight together; node coordinates by NodeWalk (no division per node).
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_spmv(int n, int64_t N, const double* __restrict__ w,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y) {
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
-    const double xi = x[i];
-    y[i] = xi + link_sum<DIM>(i, n, w, xi, [&](int64_t k) { return x[k]; });
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  NodeWalk<DIM> a(blockIdx.x * (int64_t)kThreads + threadIdx.x, 2 * stride, n);
+  NodeWalk<DIM> b(a.i + stride, 2 * stride, n);
+  auto X = [&](int64_t k) { return x[k]; };
+  for (; b.i < N; a.next(n), b.next(n)) {
+    const double xa = x[a.i], xb = x[b.i];
+    const double la = link_sum_at<DIM>(a.i, a.ix, a.iy, a.iz, n, w, xa, X);
+    const double lb = link_sum_at<DIM>(b.i, b.ix, b.iy, b.iz, n, w, xb, X);
+    y[a.i] = xa + la;
+    y[b.i] = xb + lb;
+  }
+  if (a.i < N) {
+    const double xa = x[a.i];
+    y[a.i] = xa + link_sum_at<DIM>(a.i, a.ix, a.iy, a.iz, n, w, xa, X);
   }
 }
 
@@ -148,11 +160,14 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
   if (blockIdx.x == 0 && threadIdx.x == 0) st->hold = held ? 1 : 0;
   if (held) return;
   double acc = 0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (NodeWalk<DIM> a(blockIdx.x * (int64_t)kThreads + threadIdx.x, stride, n); a.i < N;
+       a.next(n)) {
+    const int64_t i = a.i;
     const double ui = u[i];
-    const double g = ui - link_sum<DIM>(i, n, w, ui, [&](int64_t k) { return u[k]; }) +
-                     dt * react(ui, kind, k1, k2);
+    const double g = cn_rhs_value(ui, link_sum_at<DIM>(i, a.ix, a.iy, a.iz, n, w, ui,
+                                                       [&](int64_t k) { return u[k]; }),
+                                  dt, kind, k1, k2);
     r[i] = g;
     x[i] = 0.0;
     acc += g * g;
@@ -285,15 +300,25 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int 
                                                           double* part) {
   const int nb = gridDim.x;
   double rz = 0, zw = 0, zq = 0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
-    const double zi = z[i];
-    const double wi = zi + link_sum<DIM>(i, n, lw, zi, [&](int64_t k) { return z[k]; });
-    w[i] = wi;
-    rz += r[i] * zi;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  auto Z = [&](int64_t k) { return z[k]; };
+  NodeWalk<DIM> a(blockIdx.x * (int64_t)kThreads + threadIdx.x, 2 * stride, n);
+  NodeWalk<DIM> b(a.i + stride, 2 * stride, n);
+  auto one = [&](const NodeWalk<DIM>& c, double zi, double ri, double qi) {
+    const double wi = zi + link_sum_at<DIM>(c.i, c.ix, c.iy, c.iz, n, lw, zi, Z);
+    w[c.i] = wi;
+    rz += ri * zi;
     zw += zi * wi;
-    if (it > 0) zq += zi * q[i];
+    if (it > 0) zq += zi * qi;
+  };
+  // nodes in the order i, i + stride, i + 2 stride, ... as a one-node loop would take them
+  for (; b.i < N; a.next(n), b.next(n)) {
+    const double za = z[a.i], zb = z[b.i], ra = r[a.i], rb = r[b.i];
+    const double qa = it > 0 ? q[a.i] : 0.0, qb = it > 0 ? q[b.i] : 0.0;
+    one(a, za, ra, qa);
+    one(b, zb, rb, qb);
   }
+  if (a.i < N) one(a, z[a.i], r[a.i], it > 0 ? q[a.i] : 0.0);
   block_sum3(rz, zw, zq);
   if (threadIdx.x == 0) {
     part[P_RZ * (int64_t)nb + blockIdx.x] = rz;
