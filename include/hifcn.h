@@ -179,6 +179,18 @@ hif_status_t cn_batch_step(hif_handle_t* h, const hif_reaction_t* r, const hif_c
 hif_status_t hif_inverse_error(hif_handle_t h, const double* x0_dev, int32_t iters,
                                double* est_host, void* hip_stream);
 
+/* hif_inverse_error without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same iteration and kernels, with its scratch in a fixed device array that the library holds
+ * on each GPU it runs on until the process ends (8.4 MB: N <= 262144, e.g. 512^2 or 64^3
+ * grids).  Results equal hif_inverse_error's bit for bit.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams or host threads) race and must be
+ * serialised by the caller.  Calls no hipMalloc, hipFree or allocating library routine.
+ * Synchronises `hip_stream`.  Errors: HIF_ERR_ARG (NULL argument, iters < 0, N above the
+ * limit: nothing is launched), HIF_ERR_HIP. */
+hif_status_t hif_inverse_error_noalloc(hif_handle_t h, const double* x0_dev, int32_t iters,
+                                       double* est_host, void* hip_stream);
+
 /* Stored factor bytes (unpadded, in the storage precision; without the dense forms that
  * hif_get_info's device_bytes includes). */
 size_t hif_factor_bytes(hif_handle_t h);

@@ -590,6 +590,17 @@ hif_status_t hif_inverse_error(hif_handle_t hh, const double* x0_dev, int32_t it
   });
 }
 
+hif_status_t hif_inverse_error_noalloc(hif_handle_t hh, const double* x0_dev, int32_t iters,
+                                       double* est_host, void* hip_stream) {
+  return guarded([&] {
+    HIF_REQUIRE(hh && x0_dev && est_host, HIF_ERR_ARG, "NULL argument");
+    HIF_REQUIRE(iters >= 0, HIF_ERR_ARG, "iters must be >= 0");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    (void)inverse_error_noalloc_impl(h, x0_dev, iters, est_host,
+                                     static_cast<hipStream_t>(hip_stream));
+  });
+}
+
 size_t hif_factor_bytes(hif_handle_t hh) {
   if (!hh) return 0;
   const Handle& h = *reinterpret_cast<const Handle*>(hh);

@@ -7,6 +7,8 @@
 // towards it.  Everything stays on the device: the norms are per-block partial sums re-added
 // in a fixed order by the kernel that scales, so the result is deterministic and no step waits
 // for the host.
+#include <mutex>
+#include <string>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -107,12 +109,50 @@ void est_run(Handle& h, const double* x0, int iters, double* work, double* est_h
   *est_host = iters > 0 ? std::sqrt(l) : 0.0;
 }
 
+// Scratch of the allocation-free estimate: est_scratch_doubles(N) values for N up to
+// kNoAllocMaxN, at file scope so that each GPU the library runs on holds one copy until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the host it is only a
+// stand-in for the symbol): it uses the device address looked up by scratch_ptr().
+constexpr int64_t kNoAllocMaxN = 262144;
+static __device__ __align__(256) double scratch[4 * kNoAllocMaxN + kEstBlocks + 8];
+
+// The device address of `scratch` on the current GPU, looked up once per device with that
+// device current and kept.
+double* scratch_ptr() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  HIF_CHECK(hipGetDevice(&dev));
+  HIF_REQUIRE(dev >= 0 && dev < kMaxDevices, HIF_ERR_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    HIF_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    HIF_REQUIRE(p != nullptr, HIF_ERR_HIP, "no device address for the estimate's scratch");
+    ptrs[dev] = static_cast<double*>(p);
+  }
+  return ptrs[dev];
+}
+
 }  // namespace
 
 hif_status_t inverse_error_impl(Handle& h, const double* x0, int iters, double* est_host,
                                 hipStream_t s) {
   DevBuf<double> work(est_scratch_doubles(h.N), s);
   est_run(h, x0, iters, work.p, est_host, s);
+  return HIF_OK;
+}
+
+// Every value est_run reads from the scratch is written by it first in the same call (x from
+// x0, the partial sums and lambda by the kernels before the ones that read them), so nothing
+// needs clearing between calls.
+hif_status_t inverse_error_noalloc_impl(Handle& h, const double* x0, int iters,
+                                        double* est_host, hipStream_t s) {
+  HIF_REQUIRE(h.N <= kNoAllocMaxN, HIF_ERR_ARG,
+              "hif_inverse_error_noalloc: N = " + std::to_string(h.N) +
+                  " exceeds the fixed scratch of N <= " + std::to_string(kNoAllocMaxN));
+  est_run(h, x0, iters, scratch_ptr(), est_host, s);
   return HIF_OK;
 }
 

@@ -333,5 +333,8 @@ void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s);
 // scratch allocated for the call; *est_host receives the estimate (synchronises s).
 hif_status_t inverse_error_impl(Handle& h, const double* x0, int iters, double* est_host,
                                 hipStream_t s);
+// The same on the library's fixed device scratch (N up to its size): no allocation.
+hif_status_t inverse_error_noalloc_impl(Handle& h, const double* x0, int iters,
+                                        double* est_host, hipStream_t s);
 
 }  // namespace hifcn

@@ -82,6 +82,8 @@ _lib.cn_solve_direct.argtypes = [_vp, ctypes.POINTER(_Reaction), _vp, ctypes.c_i
 _lib.cn_batch_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
 _lib.hif_inverse_error.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   _vp]
+_lib.hif_inverse_error_noalloc.argtypes = [_vp, _vp, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double), _vp]
 _lib.hif_factor_bytes.argtypes = [_vp]
 _lib.hif_factor_bytes.restype = ctypes.c_size_t
 _lib.hif_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
@@ -92,13 +94,15 @@ _lib.hif_destroy.restype = None
 _lib.hif_last_error.restype = ctypes.c_char_p
 for _f in ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step", "cn_solve",
            "cn_solve_direct", "cn_batch_step", "hif_get_info", "hif_profile_stage",
-           "hif_profile_read", "hif_set_coefficient", "hif_refactor", "hif_inverse_error"):
+           "hif_profile_read", "hif_set_coefficient", "hif_refactor", "hif_inverse_error",
+           "hif_inverse_error_noalloc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("hif_factor", "hif_factor_ex", "hif_import", "hif_apply", "hif_spmv", "cn_step",
            "cn_solve", "cn_solve_direct", "cn_batch_step", "hif_factor_bytes", "hif_get_info",
            "hif_profile_stage", "hif_profile_read", "hif_destroy", "hif_last_error",
-           "hif_set_coefficient", "hif_refactor", "hif_inverse_error")
+           "hif_set_coefficient", "hif_refactor", "hif_inverse_error",
+           "hif_inverse_error_noalloc")
 
 
 def _check(status: int):
@@ -225,6 +229,13 @@ class Handle:
         est = ctypes.c_double()
         _check(_lib.hif_inverse_error(self._p(), _dev_f64(x0, "x0", self.N), int(iters),
                                       ctypes.byref(est), _stream(stream)))
+        return est.value
+
+    def inverse_error_noalloc(self, x0, iters: int = 30, stream=None) -> float:
+        """hif_inverse_error_noalloc: the same estimate on the library's fixed scratch."""
+        est = ctypes.c_double()
+        _check(_lib.hif_inverse_error_noalloc(self._p(), _dev_f64(x0, "x0", self.N), int(iters),
+                                              ctypes.byref(est), _stream(stream)))
         return est.value
 
     def factor_bytes(self) -> int:
