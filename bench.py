@@ -176,7 +176,7 @@ def copy_probe(nbytes: int):
 
 
 def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
-                  builders: int = 8, seed_base: int = 5000) -> dict:
+                  builders: int = 8, seed_base: int = 5000, lanes: int = 1) -> dict:
     """The serving workload: `count` independent 2D Fisher-KPP solves of mixed size, dt and
     coefficient (50 CN steps each), arriving as a Poisson process of `rate` requests/s (rate 0:
     all at once), served by continuous batching.  Inputs are drawn before the clock starts."""
@@ -191,14 +191,14 @@ def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
 
     reqs = [req(gen.serving_request(i, seed_base)) for i in range(count)]
     # first-use costs (kernel loading, LDS attributes) outside the clock: one of each size
-    warm = Server(budget_bytes, max_slots, builders)
+    warm = Server(budget_bytes, max_slots, builders, lanes=lanes)
     for f in [warm.submit(req(gen.serving_request(10_000 + i, seed_base, sizes=(n,))))
               for i, n in enumerate((64, 128, 256, 512))]:
         f.result()
     warm.close()
     arrivals = (gen.poisson_arrivals(count, rate, seed_base + 7) if rate > 0
                 else np.zeros(count))
-    srv = Server(budget_bytes, max_slots, builders)
+    srv = Server(budget_bytes, max_slots, builders, lanes=lanes)
     finished = [0]
 
     def progress(_f):
@@ -230,6 +230,7 @@ def serving_bench(count: int, rate: float, max_slots: int, budget_bytes: int,
            "mean_queue_s": float(np.mean([r.t_admit - r.t_arrival for r in res])),
            "n_i_mean": float(np.mean(np.concatenate([r.iters for r in res]))),
            "sizes": sorted({int(r.u.shape[0]) for r in res}), "builders": builders,
+           "lanes": lanes,
            **st}
     return out
 
@@ -398,6 +399,8 @@ def main(argv=None):
     ap.add_argument("--serving-builders", type=int, default=8,
                     help="threads (each with its own stream) building factors concurrently")
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serving-lanes", type=int, default=1,
+                    help="scheduler lanes (each runs its own batch of solves of similar size)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration)")
@@ -436,7 +439,8 @@ def main(argv=None):
         """Saturated run (all requests at t = 0) to measure the throughput mu, then Poisson
         arrivals at the stated rate (default 0.7 mu)."""
         budget = int(args.serving_budget_gb * (1 << 30))
-        sat = serving_bench(args.serving, 0.0, args.serving_slots, budget, args.serving_builders)
+        sat = serving_bench(args.serving, 0.0, args.serving_slots, budget, args.serving_builders,
+                            lanes=args.serving_lanes)
         out = {"saturated": sat}
         rate = args.serving_rate
         if rate < 0:
@@ -444,7 +448,7 @@ def main(argv=None):
             out["rate_rule"] = "0.7 x saturated requests/s"
         if rate > 0:
             out["poisson"] = serving_bench(args.serving, rate, args.serving_slots, budget,
-                                           args.serving_builders)
+                                           args.serving_builders, lanes=args.serving_lanes)
         return out
 
     if args.serving_only:

@@ -1,9 +1,12 @@
 // C-ABI entry points of libhifcn (declared in include/hifcn.h).
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <exception>
+#include <map>
 #include <string>
 #include <thread>
+#include <tuple>
 
 #include "kernels.hpp"
 
@@ -14,6 +17,11 @@ int vec_blocks(int64_t N);
 
 Handle::~Handle() {
   if (host_flag) (void)hipHostFree(host_flag);
+}
+
+uint64_t next_handle_gen() {
+  static std::atomic<uint64_t> g{0};
+  return ++g;
 }
 
 namespace {
@@ -56,6 +64,7 @@ std::unique_ptr<Handle> make_handle(const double* a_cells, double dt, const hif_
   HIF_REQUIRE(dt > 0 && std::isfinite(dt), HIF_ERR_ARG, "dt must be positive");
   HIF_REQUIRE(eps >= 0 && std::isfinite(eps), HIF_ERR_ARG, "eps must be >= 0");
   auto h = std::make_unique<Handle>();
+  h->gen = next_handle_gen();
   h->dim = grid->dim;
   h->n = n;
   h->leaf = grid->leaf;
@@ -311,6 +320,141 @@ int64_t handle_device_bytes(const Handle& h) {
   return b;
 }
 
+// ---- batched kernels over all solves of a batch ---------------------------------------------
+// One Crank-Nicolson step of every solve with one launch per stage for all of them: the PCG
+// vector kernels over a table of the solves (launch_bcg_*) and the apply as the batched stage
+// launches of build_batch_apply (levels aligned from the leaves).  Every solve keeps its own
+// block counts and stage plans, so its iterates do not depend on its companions.  The plan is
+// kept while the batch's composition and options stay the same.
+struct FusedBatch {
+  std::vector<std::tuple<const Handle*, uint64_t, const double*, int, double, double, double,
+                         int>> key;
+  BatchApplyPlan plan;
+  DevBuf<BatchCg> cg;
+  int blocks = 0, dim = 2, maxit = 1;
+};
+
+bool batch_kernels_on() { return std::getenv("HIFCN_NO_BATCH_KERNELS") == nullptr; }
+
+// The batch key of a solve whose factor allows the batched kernels (dimension and storage: one
+// batched launch holds one of each), or -1.
+int fused_batch_key(const Handle& h) {
+  if (!batch_kernels_on() || !batchable(h.f)) return -1;
+  return h.dim * 4 + (int)h.f.store;
+}
+
+void fused_batch_setup(FusedBatch& fb, std::vector<StepState>& st, hipStream_t s) {
+  decltype(fb.key) key;
+  for (const StepState& x : st)
+    key.emplace_back(x.h, x.h->gen, x.u, x.r ? x.r->kind : 0,
+                     x.r ? x.r->k1 : 0.0, x.r ? x.r->k2 : 1.0, x.o->rtol, x.o->maxit);
+  if (key == fb.key) return;
+  std::vector<const FactorDev*> fs;
+  std::vector<double*> ys;
+  std::vector<const int*> dn;
+  std::vector<BatchCg> cg;
+  int blocks = 0, maxit = 1;
+  for (const StepState& x : st) {
+    Handle& h = *x.h;
+    fs.push_back(&h.f);
+    ys.push_back(h.z.p);
+    dn.push_back(&h.st.p->done);
+    BatchCg a{};
+    a.N = h.N;
+    a.n = h.n;
+    a.nb = h.nblk;
+    a.first = blocks;
+    a.maxit = x.o->maxit;
+    a.links = h.links.p;
+    a.u = x.u;
+    a.x = h.x.p;
+    a.r = h.r.p;
+    a.z = h.z.p;
+    a.p = h.p.p;
+    a.q = h.q.p;
+    a.w = h.w.p;
+    a.part = h.partials.p;
+    a.st = h.st.p;
+    a.hflag = h.flag_dev;
+    a.it_out = h.step_iters.p;
+    a.rel_out = h.step_relres.p;
+    a.dt = h.dt;
+    a.kind = x.r ? x.r->kind : 0;
+    a.k1 = x.r ? x.r->k1 : 0.0;
+    a.k2 = x.r ? x.r->k2 : 1.0;
+    a.rtol = x.o->rtol;
+    cg.push_back(a);
+    blocks += h.nblk;
+    maxit = std::max(maxit, x.o->maxit);
+  }
+  build_batch_apply(fs, ys, dn, fb.plan, s);
+  fb.cg.upload(cg, s);
+  fb.blocks = blocks;
+  fb.dim = st[0].h->dim;
+  fb.maxit = maxit;
+  fb.key = std::move(key);
+}
+
+// Wait for every solve's post of sequence number seq; fills each StepState's finished/status.
+void fused_batch_wait(std::vector<StepState>& st, int seq, hipStream_t s) {
+  for (StepState& x : st) {
+    int32_t* f = x.h->host_flag;
+    const volatile uint64_t* w = reinterpret_cast<const volatile uint64_t*>(f + 8 + 2 * (seq & 1));
+    uint64_t v = 0;
+    for (int64_t n = 1;; ++n) {
+      v = *w;
+      if ((int32_t)(v >> 32) == seq) break;
+      if ((n & 255) != 0) continue;
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipErrorNotReady) continue;
+      HIF_CHECK(q);
+      v = *w;
+      HIF_REQUIRE((int32_t)(v >> 32) == seq, HIF_ERR_HIP, "convergence flag was not posted");
+      break;
+    }
+    x.finished = (v >> 24 & 0xf) != 0;
+    x.status = (int)(v >> 28 & 0xf);
+    x.launched = (int)(v & 0xffffff);
+  }
+}
+
+// One CN step of every solve in st, all on stream s.
+void fused_batch_step(FusedBatch& fb, std::vector<StepState>& st, hipStream_t s) {
+  fused_batch_setup(fb, st, s);
+  const int ns = (int)st.size();
+  const BatchCg* cg = fb.cg.p;
+  launch_bcg_rhs(cg, ns, fb.blocks, fb.dim, s);
+  launch_bcg_check(cg, ns, fb.blocks, 1, -1, 0, 0, s);
+  run_batch_apply(fb.plan, s);
+  int chunk = 1;
+  for (const StepState& x : st) chunk = std::max(chunk, x.h->last_iters);
+  int it = 0;
+  for (;;) {
+    int seq = 0;
+    for (const StepState& x : st) seq = std::max(seq, x.h->flag_seq);
+    ++seq;
+    for (StepState& x : st) x.h->flag_seq = seq;
+    for (int c = 0; c < chunk; ++c) {
+      launch_bcg_dir_dots(cg, ns, fb.blocks, fb.dim, it, s);
+      launch_bcg_update(cg, ns, fb.blocks, it, s);
+      const bool close = c + 1 == chunk || it + 1 >= fb.maxit;
+      launch_bcg_check(cg, ns, fb.blocks, 0, it, close ? 1 : 0, seq, s);
+      ++it;
+      if (close) break;
+      run_batch_apply(fb.plan, s);
+    }
+    HIF_CHECK(hipGetLastError());
+    fused_batch_wait(st, seq, s);
+    bool all = true;
+    for (const StepState& x : st) all = all && x.finished;
+    if (all) break;
+    HIF_REQUIRE(it < fb.maxit, HIF_ERR_HIP, "PCG ran past maxit without stopping");
+    run_batch_apply(fb.plan, s);  // the solves that go on: z = r was copied by the test
+    chunk = 2;
+  }
+  for (StepState& x : st) x.h->last_iters = std::max(1, x.launched);
+}
+
 }  // namespace
 }  // namespace hifcn
 
@@ -366,6 +510,7 @@ hif_status_t hif_set_coefficient(hif_handle_t hh, const double* a_cells_dev, voi
     Handle& h = *reinterpret_cast<Handle*>(hh);
     launch_links(a_cells_dev, h.dim, h.n, h.dt / (2.0 * h.h * h.h), h.links.p,
                  static_cast<hipStream_t>(hip_stream));
+    h.gen = next_handle_gen();
   });
 }
 
@@ -387,6 +532,7 @@ hif_status_t hif_refactor(hif_handle_t hh, const double* a_cells_dev, void* hip_
     HIF_CHECK(hipStreamSynchronize(s));
     std::swap(h.f, nh->f);
     std::swap(h.links, nh->links);
+    h.gen = next_handle_gen();
     std::swap(h.gpart, nh->gpart);
     h.rhs_fused = nh->rhs_fused;
     h.plan0 = nh->plan0;
@@ -517,12 +663,57 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
       st[i].u = us[i];
       st[i].step = 0;
     }
+    // Solves whose factors allow it run with one launch per stage for every solve of the same
+    // dimension and storage (batched kernels), on the first such solve's stream, with the other
+    // streams joined before and after; the rest take the per-solve launches below.
+    std::map<int, std::vector<StepState>> fused;
+    std::vector<int> fused_at(count, -1);
+    std::vector<StepState> rest;
+    std::vector<int> rest_at;
+    for (int i = 0; i < count; ++i) {
+      const int k = fused_batch_key(*st[i].h);
+      if (k >= 0) {
+        fused_at[i] = (int)fused[k].size();
+        fused[k].push_back(st[i]);
+      } else {
+        rest_at.push_back(i);
+        rest.push_back(st[i]);
+      }
+    }
+    for (auto& [k, grp] : fused) {
+      thread_local std::map<int, FusedBatch> fbs;
+      hipStream_t s0 = grp[0].s;
+      std::vector<hipEvent_t> evs;
+      auto join = [&](hipStream_t from, hipStream_t to) {
+        if (from == to) return;
+        hipEvent_t e;
+        HIF_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIF_CHECK(hipEventRecord(e, from));
+        HIF_CHECK(hipStreamWaitEvent(to, e, 0));
+        evs.push_back(e);
+      };
+      for (size_t i = 1; i < grp.size(); ++i) join(grp[i].s, s0);
+      fused_batch_step(fbs[k], grp, s0);
+      for (StepState& x : grp) {
+        Handle& h = *x.h;
+        HIF_CHECK(hipMemcpyAsync(h.host_flag, h.step_iters.p, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s0));
+        HIF_CHECK(hipMemcpyAsync(h.host_flag + 4, h.step_relres.p, sizeof(double),
+                                 hipMemcpyDeviceToHost, s0));
+      }
+      HIF_CHECK(hipStreamSynchronize(s0));
+      for (size_t i = 1; i < grp.size(); ++i) join(s0, grp[i].s);
+      for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    }
+    for (int i = 0; i < count; ++i)
+      if (fused_at[i] >= 0) st[i] = fused[fused_batch_key(*st[i].h)][fused_at[i]];
+    const int nrest = (int)rest.size();
     // Solves are split over host threads (launching is host-bound when many solves run), each
     // thread advancing its share in lockstep with one read-back per round.
     auto run = [&](int w, int W, int dev) {
       HIF_CHECK(hipSetDevice(dev));
       std::vector<StepState*> mine;
-      for (int i = w; i < count; i += W) mine.push_back(&st[i]);
+      for (int i = w; i < nrest; i += W) mine.push_back(&rest[i]);
       for (StepState* x : mine) step_begin(*x);
       size_t open = mine.size();
       while (open > 0) {
@@ -544,13 +735,12 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
       }
       for (StepState* x : mine) HIF_CHECK(hipStreamSynchronize(x->s));
     };
-    if (count == 0) return;
     int dev = 0;
     HIF_CHECK(hipGetDevice(&dev));
-    const int W = std::min(count, batch_threads());
-    if (W <= 1) {
+    const int W = std::min(nrest, batch_threads());
+    if (W == 1) {
       run(0, 1, dev);
-    } else {
+    } else if (W > 1) {
       std::vector<std::thread> pool;
       std::vector<std::exception_ptr> errs(W);
       for (int w = 0; w < W; ++w)
@@ -565,6 +755,7 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
       for (std::exception_ptr& e : errs)
         if (e) std::rethrow_exception(e);
     }
+    for (int q = 0; q < nrest; ++q) st[rest_at[q]] = rest[q];
     int failed = -1;
     for (int i = 0; i < count; ++i) {
       const Handle& h = *st[i].h;

@@ -1955,6 +1955,129 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
   HIF_CHECK(hipGetLastError());
 }
 
+
+// ------------------------------------------------------------------- batched stage launches --
+// Continuous batching: one launch runs a stage of several independent solves.  Every solve's
+// blocks form a contiguous range of the launch's blocks; a workgroup finds its solve by a
+// binary search over the first blocks (every lane the same, so the loads are uniform) and runs
+// that solve's stage exactly as a launch of its own would, with its own records, values,
+// vectors and stop flag.  A solve's arithmetic therefore does not depend on its companions.
+__device__ __forceinline__ BatchArg batch_arg(const BatchArg* __restrict__ args, int nslot,
+                                              int* vb) {
+  int lo = 0, hi = nslot - 1;
+  const int b = (int)blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (args[mid].first <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  *vb = b - args[lo].first;
+  return args[lo];
+}
+
+template <typename S, typename C, int MODE>
+__global__ __launch_bounds__(256) void k_bcell_fwd(const BatchArg* __restrict__ args, int nslot,
+                                                   int recmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int vb;
+  const BatchArg a = batch_arg(args, nslot, &vb);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, a.recs + (int64_t)vb * a.stride, a.len, threadIdx.x, blockDim.x);
+  const int dn = a.done ? *a.done : 0;
+  __syncthreads();
+  if (dn) return;
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  const S* vals = reinterpret_cast<const S*>(a.vals);
+  unsigned char* sm = smem_raw + 4 * recmax;
+  if constexpr (MODE == 2)
+    cell_fwd_sym<S, C>(d, rec, vals, a.y, a.cb, a.sqtab, sm);
+  else if (a.staged)
+    cell_fwd_body<S, C, true, 0>(d, rec, vals, a.y, a.cb, a.blk_elems, a.team, false, sm);
+  else
+    cell_fwd_body<S, C, false, 0>(d, rec, vals, a.y, a.cb, a.blk_elems, a.team, false, sm);
+}
+
+template <typename S, typename C, int MODE>
+__global__ __launch_bounds__(256) void k_bcell_bwd(const BatchArg* __restrict__ args, int nslot,
+                                                   int recmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int vb;
+  const BatchArg a = batch_arg(args, nslot, &vb);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, a.recs + (int64_t)vb * a.stride, a.len, threadIdx.x, blockDim.x);
+  const int dn = a.done ? *a.done : 0;
+  __syncthreads();
+  if (dn) return;
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  const S* vals = reinterpret_cast<const S*>(a.vals);
+  unsigned char* sm = smem_raw + 4 * recmax;
+  if constexpr (MODE == 2)
+    cell_bwd_sym<S, C>(d, rec, vals, a.y, a.sqtab, sm, TopIn{});
+  else if (a.staged)
+    cell_bwd_body<S, C, true, 0>(d, rec, vals, a.y, a.blk_elems, a.team, sm);
+  else
+    cell_bwd_body<S, C, false, 0>(d, rec, vals, a.y, a.blk_elems, a.team, sm);
+}
+
+// Group stages: blockDim / seg groups per workgroup (seg: the solve's lanes per group).
+template <typename S, typename C, bool FWD>
+__global__ __launch_bounds__(256) void k_bgroup(const BatchArg* __restrict__ args, int nslot,
+                                                int recmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int vb;
+  const BatchArg a = batch_arg(args, nslot, &vb);
+  const int per = blockDim.x / a.seg, g0 = vb * per, cnt = min(per, a.count - g0);
+  int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
+  load_record(rec, a.recs + (int64_t)g0 * a.stride, cnt * a.stride, threadIdx.x, blockDim.x);
+  const int dn = a.done ? *a.done : 0;
+  __syncthreads();
+  if (dn) return;
+  const int gsel = threadIdx.x / a.seg;
+  const int32_t* rb = rec + gsel * a.stride;
+  GroupDesc d{};
+  if (gsel < cnt) d = *reinterpret_cast<const GroupDesc*>(rb);
+  const S* vals = reinterpret_cast<const S*>(a.vals);
+  if constexpr (FWD)
+    group_fwd_body<S, C, true>(d, a.seg, a.per_group, a.blk_elems, a.team, rb, vals, a.y, a.cb,
+                               smem_raw + 4 * recmax);
+  else
+    group_bwd_body<S, C, true>(d, a.seg, a.per_group, a.blk_elems, a.team, rb, vals, a.y,
+                               smem_raw + 4 * recmax);
+}
+
+// Roots: one workgroup per solve.
+template <typename S, typename C>
+__global__ __launch_bounds__(kRootThreads) void k_broot(const BatchArg* __restrict__ args,
+                                                        int nslot) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BatchArg a = args[blockIdx.x];
+  if (a.done && *a.done) return;
+  root_body<S, C>(a.count, a.recs, reinterpret_cast<const S*>(a.vals), a.y, a.staged != 0,
+                  smem_raw);
+}
+
+template <typename S, typename C>
+void batch_launch(const BatchApplyPlan& plan, const BatchLaunch& l, hipStream_t s) {
+  const BatchArg* a = plan.args.p + l.off;
+  const dim3 g(l.blocks), b(l.threads);
+  switch (l.kind) {
+    case BK_CELL_FWD_SYM:
+      hipLaunchKernelGGL((k_bcell_fwd<S, C, 2>), g, b, l.smem, s, a, l.nslot, l.recmax); break;
+    case BK_CELL_FWD:
+      hipLaunchKernelGGL((k_bcell_fwd<S, C, 0>), g, b, l.smem, s, a, l.nslot, l.recmax); break;
+    case BK_GROUP_FWD:
+      hipLaunchKernelGGL((k_bgroup<S, C, true>), g, b, l.smem, s, a, l.nslot, l.recmax); break;
+    case BK_ROOT:
+      hipLaunchKernelGGL((k_broot<S, C>), g, b, l.smem, s, a, l.nslot); break;
+    case BK_GROUP_BWD:
+      hipLaunchKernelGGL((k_bgroup<S, C, false>), g, b, l.smem, s, a, l.nslot, l.recmax); break;
+    case BK_CELL_BWD_SYM:
+      hipLaunchKernelGGL((k_bcell_bwd<S, C, 2>), g, b, l.smem, s, a, l.nslot, l.recmax); break;
+    default:
+      hipLaunchKernelGGL((k_bcell_bwd<S, C, 0>), g, b, l.smem, s, a, l.nslot, l.recmax); break;
+  }
+}
+
 }  // namespace
 
 size_t apply_smem_need(const FactorDev& f, size_t* worst) {
@@ -2090,14 +2213,199 @@ void set_apply_smem_limits(size_t bytes) {
   HIF_SMEM((k_fuse_fwd<S, C, true>));                                                         \
   HIF_SMEM((k_fuse_fwd<S, C, false>));                                                        \
   HIF_SMEM((k_fuse_root<S, C>))
+#define HIF_SMEM_BATCH(S, C)                                                                  \
+  HIF_SMEM((k_bcell_fwd<S, C, 0>));                                                           \
+  HIF_SMEM((k_bcell_bwd<S, C, 0>));                                                           \
+  HIF_SMEM((k_bcell_fwd<S, C, 2>));                                                           \
+  HIF_SMEM((k_bcell_bwd<S, C, 2>));                                                           \
+  HIF_SMEM((k_bgroup<S, C, true>));                                                           \
+  HIF_SMEM((k_bgroup<S, C, false>));                                                          \
+  HIF_SMEM((k_broot<S, C>))
   HIF_SMEM_ALL(double, double);
   HIF_SMEM_ALL(float, float);
   HIF_SMEM_ALL(bf16_t, float);
-
+  HIF_SMEM_BATCH(double, double);
+  HIF_SMEM_BATCH(float, float);
+#undef HIF_SMEM_BATCH
 #undef HIF_SMEM_ALL
 #undef HIF_SMEM_TILES
 #undef HIF_SMEM
   granted = bytes;
+}
+
+bool batchable(const FactorDev& f) {
+  if (f.store == HIF_STORE_BF16 || f.top >= 0 || f.root_tiled) return false;
+  for (size_t l = 0; l < f.lv.size(); ++l) {
+    const LevelDev& L = f.lv[l];
+    if (L.tiled || L.cdense || L.gtiled) return false;
+    if (L.ncell && L.cmode != (l == 0 ? 2 : 0)) return false;
+    if (L.ngroup && !(f.store == HIF_STORE_F64 ? group_plan<double>(L).staged
+                                               : group_plan<float>(L).staged))
+      return false;
+  }
+  return true;
+}
+
+namespace {
+
+constexpr int kBatchThreads = 256;
+
+// The launch plan of one solve's stage inside a batched launch (the solve's own plan with the
+// launch's block size).
+template <typename C>
+void batch_cell(const FactorDev& f, int l, double* y, const int* done, BatchArg& a,
+                BatchLaunch& bl, bool fwd) {
+  const LevelDev& L = f.lv[l];
+  a.recs = L.crec.p;
+  a.vals = f.vals.p;
+  a.y = y;
+  a.cb = f.cb.p + (int64_t)(l & 1) * f.cbstride;
+  a.done = done;
+  a.sqtab = f.sqtab.p;
+  a.stride = L.cstride;
+  a.len = fwd ? L.cfwd : L.cstride;
+  a.count = L.ncell;
+  if (L.cmode == 2) {
+    bl.threads = 64;
+    bl.smem = std::max(bl.smem, sizeof(C) * (size_t)sym_smem_elems(L.maxB));
+  } else {
+    const size_t vec = 3 * (size_t)L.maxI + 2 * (size_t)L.maxB + 4;
+    a.blk_elems = round_up(L.maxCV, 8);
+    a.staged = sizeof(C) * (a.blk_elems + vec) <= kStageMax ? 1 : 0;
+    if (!a.staged) a.blk_elems = 0;
+    int team = 1;
+    while (team < 8 && (team * 2) * L.maxI <= kBatchThreads) team <<= 1;
+    a.team = team;
+    bl.threads = kBatchThreads;
+    bl.smem = std::max(bl.smem, sizeof(C) * (a.blk_elems + vec));
+  }
+  bl.recmax = std::max(bl.recmax, L.cstride);
+  a.first = bl.blocks;
+  bl.blocks += L.ncell;
+}
+
+template <typename C>
+void batch_group(const FactorDev& f, int l, double* y, const int* done, BatchArg& a,
+                 BatchLaunch& bl) {
+  const LevelDev& L = f.lv[l];
+  const StagePlan p = group_plan<C>(L);
+  a.recs = L.grec.p;
+  a.vals = f.vals.p;
+  a.y = y;
+  a.cb = f.cb.p + (int64_t)(l & 1) * f.cbstride;
+  a.done = done;
+  a.stride = L.gstride;
+  a.count = L.ngroup;
+  a.seg = p.seg;
+  a.team = p.team;
+  a.blk_elems = p.blk_elems;
+  a.per_group = p.per_group;
+  // as many groups per workgroup as fit the block size and the LDS budget
+  int per = kBatchThreads / p.seg;
+  while (per > 1 && sizeof(C) * (size_t)per * p.per_group > kStageBudget) per >>= 1;
+  a.seg = kBatchThreads / per;  // lanes per group (the extra ones idle in the body's loops)
+  bl.threads = kBatchThreads;
+  bl.smem = std::max(bl.smem, sizeof(C) * (size_t)per * p.per_group);
+  bl.recmax = std::max(bl.recmax, per * L.gstride);
+  a.first = bl.blocks;
+  bl.blocks += (L.ngroup + per - 1) / per;
+}
+
+template <typename C>
+void build_batch_impl(const std::vector<const FactorDev*>& fs, const std::vector<double*>& y,
+                      const std::vector<const int*>& done, BatchApplyPlan& plan, hipStream_t s) {
+  const int ns = (int)fs.size();
+  int lmax = 0;
+  for (const FactorDev* f : fs) lmax = std::max(lmax, (int)f->lv.size());
+  std::vector<BatchArg> args;
+  plan.launches.clear();
+  auto close = [&](BatchLaunch& bl, std::vector<BatchArg>& part) {
+    if (part.empty()) return;
+    bl.off = (int)args.size();
+    bl.nslot = (int)part.size();
+    args.insert(args.end(), part.begin(), part.end());
+    plan.launches.push_back(bl);
+  };
+  auto stage = [&](int l, int kind) {
+    BatchLaunch bl;
+    std::vector<BatchArg> part;
+    for (int i = 0; i < ns; ++i) {
+      const FactorDev& f = *fs[i];
+      if (l >= (int)f.lv.size()) continue;
+      const LevelDev& L = f.lv[l];
+      BatchArg a{};
+      if (kind == BK_CELL_FWD || kind == BK_CELL_BWD) {
+        if (!L.ncell) continue;
+        batch_cell<C>(f, l, y[i], done[i], a, bl, kind == BK_CELL_FWD);
+        bl.kind = L.cmode == 2 ? (kind == BK_CELL_FWD ? BK_CELL_FWD_SYM : BK_CELL_BWD_SYM) : kind;
+      } else {
+        if (!L.ngroup) continue;
+        batch_group<C>(f, l, y[i], done[i], a, bl);
+        bl.kind = kind;
+      }
+      part.push_back(a);
+    }
+    bl.smem += 4 * (size_t)bl.recmax;
+    close(bl, part);
+  };
+  for (int l = 0; l < lmax; ++l) {
+    stage(l, BK_CELL_FWD);
+    stage(l, BK_GROUP_FWD);
+  }
+  {
+    BatchLaunch bl;
+    bl.kind = BK_ROOT;
+    bl.threads = kRootThreads;
+    std::vector<BatchArg> part;
+    for (int i = 0; i < ns; ++i) {
+      const FactorDev& f = *fs[i];
+      if (!f.nroot) continue;
+      BatchArg a{};
+      bool rs;
+      bl.smem = std::max(bl.smem, root_smem<C>(f.nroot, &rs));
+      a.recs = f.idx.p + f.offRootIdx;
+      a.vals = reinterpret_cast<const unsigned char*>(f.vals.p) +
+               (size_t)f.offRootV * store_elem_bytes(f.store);
+      a.y = y[i];
+      a.done = done[i];
+      a.count = f.nroot;
+      a.staged = rs ? 1 : 0;
+      a.first = bl.blocks++;
+      part.push_back(a);
+    }
+    close(bl, part);
+  }
+  for (int l = lmax - 1; l >= 0; --l) {
+    stage(l, BK_GROUP_BWD);
+    stage(l, BK_CELL_BWD);
+  }
+  size_t need = 0;
+  for (const BatchLaunch& bl : plan.launches) need = std::max(need, bl.smem);
+  set_apply_smem_limits(need);
+  plan.args.upload(args, s);
+}
+
+}  // namespace
+
+void build_batch_apply(const std::vector<const FactorDev*>& fs, const std::vector<double*>& y,
+                       const std::vector<const int*>& done, BatchApplyPlan& plan,
+                       hipStream_t s) {
+  HIF_REQUIRE(!fs.empty() && fs.size() == y.size() && fs.size() == done.size(), HIF_ERR_ARG,
+              "internal: batch apply lists");
+  plan.store = fs[0]->store;
+  for (const FactorDev* f : fs)
+    HIF_REQUIRE(f->store == plan.store && batchable(*f), HIF_ERR_ARG,
+                "internal: factor not batchable");
+  if (plan.store == HIF_STORE_F64) build_batch_impl<double>(fs, y, done, plan, s);
+  else build_batch_impl<float>(fs, y, done, plan, s);
+}
+
+void run_batch_apply(const BatchApplyPlan& plan, hipStream_t s) {
+  for (const BatchLaunch& l : plan.launches) {
+    if (plan.store == HIF_STORE_F64) batch_launch<double, double>(plan, l, s);
+    else batch_launch<float, float>(plan, l, s);
+  }
+  HIF_CHECK(hipGetLastError());
 }
 
 namespace {

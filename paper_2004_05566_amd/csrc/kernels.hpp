@@ -138,6 +138,45 @@ struct FactorDev {
   DevBuf<int32_t> sqtab;
 };
 
+// ---- batched apply over several solves (continuous batching) ----------------------------------
+// One solve's part of a batched stage launch: its blocks are launch blocks first .. first +
+// nblk - 1.  Cell and group stages read block records; the root reads its DOF ids (recs) and
+// packed L_r^-1 (vals).
+struct BatchArg {
+  const int32_t* recs;
+  const void* vals;
+  double* y;
+  double* cb;
+  const int* done;
+  const int32_t* sqtab;
+  int32_t stride, len;   // record stride (int32) and the part of it one block reads
+  int32_t count;         // cells or groups of the level, or the root's DOFs
+  int32_t first;         // first launch block of this solve
+  int32_t blk_elems, team, seg, per_group, staged, pad;
+};
+enum BatchKind { BK_CELL_FWD_SYM = 0, BK_CELL_FWD = 1, BK_GROUP_FWD = 2, BK_ROOT = 3,
+                 BK_GROUP_BWD = 4, BK_CELL_BWD_SYM = 5, BK_CELL_BWD = 6 };
+// One launch of a batched apply: its arguments are args[off .. off + nslot) of the plan's array.
+struct BatchLaunch {
+  int kind = 0, off = 0, nslot = 0, blocks = 0, threads = 0, recmax = 0;
+  size_t smem = 0;
+};
+struct BatchApplyPlan {
+  std::vector<BatchLaunch> launches;
+  DevBuf<BatchArg> args;
+  hif_store_t store = HIF_STORE_F32;
+};
+// Whether a factor can take part in a batched apply (2D or 3D, level 0 symmetric cells or none,
+// no dense top, no tiled or dense-form levels, no tiled root).
+bool batchable(const FactorDev& f);
+// The launches of one apply of every factor in fs (all batchable, one storage precision): the
+// stages of level l of all of them together, levels aligned from the leaves, then all roots,
+// then the backward stages from the top level down.  y[i], done[i]: solve i's vector and stop
+// flag (may be null).
+void build_batch_apply(const std::vector<const FactorDev*>& fs, const std::vector<double*>& y,
+                       const std::vector<const int*>& done, BatchApplyPlan& plan, hipStream_t s);
+void run_batch_apply(const BatchApplyPlan& plan, hipStream_t s);
+
 // ---- symmetric-inverse level-0 cells ---------------------------------------------------------
 constexpr int kSymMaxCell = 64;  // largest interior held as A_II^-1 by one wavefront
 constexpr int kSymLd = 65;       // LDS leading dimension of the mirrored square (odd)
@@ -240,8 +279,12 @@ struct Handle {
   // so that later rebuilds skip planning it
   std::shared_ptr<const LevelPlan> plan0;
   bool keep_plan0 = false;
+  // changes whenever the factor or the operator is replaced (plans that point into them, such
+  // as a batched step's, are made again)
+  uint64_t gen = 0;
   ~Handle();
 };
+uint64_t next_handle_gen();
 
 // ---- factor layout ---------------------------------------------------------------------------
 // Every block of values starts at a multiple of kValAlign elements (16-byte aligned in every
@@ -329,6 +372,32 @@ void launch_cg_dir_dots(Handle& h, int it, hipStream_t s);
 // (rtol: for the first update of a step whose right-hand side the apply made, which also tests
 // g: it totals ||g||^2 and starts tol2.)
 void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s);
+// One solve's part of a batched PCG vector launch: its blocks are launch blocks first ..
+// first + nb - 1 (nb: the solve's own block count, so its reductions are those it makes alone).
+struct BatchCg {
+  int64_t N;
+  int32_t n, nb, first, maxit;
+  const double* links;
+  double *u, *x, *r, *z, *p, *q, *w, *part;
+  CgState* st;
+  int32_t* hflag;
+  int32_t* it_out;
+  double* rel_out;
+  double dt, k1, k2, rtol;
+  int32_t kind, pad;
+};
+// The PCG kernels of Algorithm 1 over a batch of solves of one dimension (args on the device,
+// nslot entries, `blocks` launch blocks in all): the right-hand side (and a new step's
+// scalars), the convergence test (init: of g; else after iteration it0) with z = r when the
+// iteration goes on (fin: closing a queued batch of iterations, u = x and the outcome posted to
+// hflag with sequence number seq when it stops), the direction kernel and the update.
+void launch_bcg_rhs(const BatchCg* args, int nslot, int blocks, int dim, hipStream_t s);
+void launch_bcg_check(const BatchCg* args, int nslot, int blocks, int init, int it0, int fin,
+                      int seq, hipStream_t s);
+void launch_bcg_dir_dots(const BatchCg* args, int nslot, int blocks, int dim, int it,
+                         hipStream_t s);
+void launch_bcg_update(const BatchCg* args, int nslot, int blocks, int it, hipStream_t s);
+
 // ||I - A F^-1||_2 by `iters` power-iteration steps on E^T E from x0 (device, N values), its
 // scratch allocated for the call; *est_host receives the estimate (synchronises s).
 hif_status_t inverse_error_impl(Handle& h, const double* x0, int iters, double* est_host,

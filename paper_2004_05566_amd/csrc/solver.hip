@@ -407,7 +407,187 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
   put_partial(acc, part + P_RR * (int64_t)nb);
 }
 
+// ------------------------------------------------------------------- batched PCG kernels --
+// The kernels above over several solves at once (continuous batching): each solve keeps its own
+// block count, so its partial sums, and with them its iterates, are those it makes alone.
+__device__ __forceinline__ const BatchCg* bcg_arg(const BatchCg* __restrict__ args, int nslot,
+                                                  int* vb) {
+  int lo = 0, hi = nslot - 1;
+  const int b = (int)blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (args[mid].first <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  *vb = b - args[lo].first;
+  return args + lo;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_bcg_rhs(const BatchCg* __restrict__ args,
+                                                      int nslot) {
+  int vb;
+  const BatchCg& a = *bcg_arg(args, nslot, &vb);
+  if (vb == 0 && threadIdx.x == 0) {  // a new step (no block reads these here)
+    CgState* st = a.st;
+    st->iters = 0;
+    st->status = 0;
+    st->done = 0;
+    st->hold = 0;
+    st->maxit = a.maxit;
+  }
+  double acc = 0;
+  const int64_t stride = (int64_t)a.nb * kThreads;
+  for (NodeWalk<DIM> c(vb * (int64_t)kThreads + threadIdx.x, stride, a.n); c.i < a.N;
+       c.next(a.n)) {
+    const double ui = a.u[c.i];
+    const double g = cn_rhs_value(ui, link_sum_at<DIM>(c.i, c.ix, c.iy, c.iz, a.n, a.links, ui,
+                                                       [&](int64_t k) { return a.u[k]; }),
+                                  a.dt, a.kind, a.k1, a.k2);
+    a.r[c.i] = g;
+    a.x[c.i] = 0.0;
+    acc += g * g;
+  }
+  const double sblk = block_sum(acc);
+  if (threadIdx.x == 0) a.part[P_GG * (int64_t)a.nb + vb] = sblk;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bcg_check(const BatchCg* __restrict__ args,
+                                                        int nslot, int init, int it0, int fin,
+                                                        int seq) {
+  __shared__ int stop;
+  int vb;
+  const BatchCg& a = *bcg_arg(args, nslot, &vb);
+  CgState* st = a.st;
+  const int nb = a.nb;
+  const bool lead = vb == 0 && threadIdx.x == 0;
+  const int64_t stride = (int64_t)nb * kThreads, i0 = vb * (int64_t)kThreads + threadIdx.x;
+  auto finish = [&](int iters, bool keep_u) {  // u = x; the step's records (lead lane)
+    if (!keep_u)
+      for (int64_t i = i0; i < a.N; i += stride) a.u[i] = a.x[i];
+    if (lead) {
+      a.it_out[0] = iters;
+      a.rel_out[0] = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
+      post_flag(a.hflag, seq, iters, 1, st->status);
+    }
+  };
+  if (!init && st->done) {  // stopped by an earlier test of this step
+    if (fin) finish(st->iters, st->status != 0 && st->iters == 0);
+    return;
+  }
+  if (threadIdx.x < 64) {
+    CgTotal ct;
+    const double* part = a.part + (init ? P_GG : P_RR) * (int64_t)nb;
+    ct.load(part, nb);
+    const double t = ct.sum(part, nb);
+    if (threadIdx.x == 0)
+      stop = cg_verdict(st, init, it0, a.rtol, t, st->tol2, init ? a.maxit : st->maxit, vb == 0);
+  }
+  __syncthreads();
+  if (stop) {
+    // block 0 published the scalars; the other blocks only copy x (init stops copy nothing)
+    if (fin && !init) {
+      for (int64_t i = i0; i < a.N; i += stride) a.u[i] = a.x[i];
+      if (lead) {
+        a.it_out[0] = it0 + 1;
+        a.rel_out[0] = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
+        post_flag(a.hflag, seq, it0 + 1, 1, st->status);
+      }
+    }
+    return;
+  }
+  if (fin && lead) post_flag(a.hflag, seq, it0 + 1, 0, 0);
+  for (int64_t i = i0; i < a.N; i += stride) a.z[i] = a.r[i];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_bcg_dir_dots(const BatchCg* __restrict__ args,
+                                                           int nslot, int it) {
+  int vb;
+  const BatchCg& a = *bcg_arg(args, nslot, &vb);
+  if (a.st->done) return;
+  const int nb = a.nb;
+  double rz = 0, zw = 0, zq = 0;
+  const int64_t stride = (int64_t)nb * kThreads;
+  auto Z = [&](int64_t k) { return a.z[k]; };
+  for (NodeWalk<DIM> c(vb * (int64_t)kThreads + threadIdx.x, stride, a.n); c.i < a.N;
+       c.next(a.n)) {
+    const double zi = a.z[c.i];
+    const double wi = zi + link_sum_at<DIM>(c.i, c.ix, c.iy, c.iz, a.n, a.links, zi, Z);
+    a.w[c.i] = wi;
+    rz += a.r[c.i] * zi;
+    zw += zi * wi;
+    if (it > 0) zq += zi * a.q[c.i];
+  }
+  block_sum3(rz, zw, zq);
+  if (threadIdx.x == 0) {
+    a.part[P_RZ * (int64_t)nb + vb] = rz;
+    a.part[P_ZW * (int64_t)nb + vb] = zw;
+    a.part[P_ZQ * (int64_t)nb + vb] = zq;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bcg_update(const BatchCg* __restrict__ args,
+                                                         int nslot, int it) {
+  int vb;
+  const BatchCg& a = *bcg_arg(args, nslot, &vb);
+  CgState* st = a.st;
+  if (st->done) return;
+  const int nb = a.nb;
+  const bool first = it == 0;
+  double rz = 0, zw = 0, zq = 0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    rz += a.part[P_RZ * (int64_t)nb + i];
+    zw += a.part[P_ZW * (int64_t)nb + i];
+    zq += a.part[P_ZQ * (int64_t)nb + i];
+  }
+  block_sum3(rz, zw, zq);
+  const double beta = first ? 0.0 : rz / st->rzv[(it + 1) & 1];
+  const double pq = first ? zw : zw + beta * (2.0 * zq + beta * st->pqv[(it + 1) & 1]);
+  const double alpha = rz / pq;
+  if (vb == 0 && threadIdx.x == 0) {
+    st->rzv[it & 1] = rz;
+    st->pqv[it & 1] = pq;
+  }
+  double acc = 0;
+  const int64_t stride = (int64_t)nb * kThreads;
+  for (int64_t i = vb * (int64_t)kThreads + threadIdx.x; i < a.N; i += stride) {
+    const double zi = a.z[i], wi = a.w[i];
+    const double pi = first ? zi : zi + beta * a.p[i];
+    const double qi = first ? wi : wi + beta * a.q[i];
+    const double ri = a.r[i] - alpha * qi;
+    a.x[i] += alpha * pi;
+    a.p[i] = pi;
+    a.q[i] = qi;
+    a.r[i] = ri;
+    acc += ri * ri;
+  }
+  const double sblk = block_sum(acc);
+  if (threadIdx.x == 0) a.part[P_RR * (int64_t)nb + vb] = sblk;
+}
+
 }  // namespace
+
+void launch_bcg_rhs(const BatchCg* args, int nslot, int blocks, int dim, hipStream_t s) {
+  auto k = dim == 2 ? k_bcg_rhs<2> : k_bcg_rhs<3>;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), 0, s, args, nslot);
+}
+
+void launch_bcg_check(const BatchCg* args, int nslot, int blocks, int init, int it0, int fin,
+                      int seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcg_check, dim3(blocks), dim3(kThreads), 0, s, args, nslot, init, it0,
+                     fin, seq);
+}
+
+void launch_bcg_dir_dots(const BatchCg* args, int nslot, int blocks, int dim, int it,
+                         hipStream_t s) {
+  auto k = dim == 2 ? k_bcg_dir_dots<2> : k_bcg_dir_dots<3>;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), 0, s, args, nslot, it);
+}
+
+void launch_bcg_update(const BatchCg* args, int nslot, int blocks, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcg_update, dim3(blocks), dim3(kThreads), 0, s, args, nslot, it);
+}
 
 int vec_blocks(int64_t N) {
   int64_t b = (N + kThreads - 1) / kThreads;

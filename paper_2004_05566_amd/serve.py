@@ -7,10 +7,11 @@ eq1 and eq_CN, Sec. 2.1) preconditioned by its own HIF factor (Sec. 2.2).  The s
     (a request that could never fit is rejected at once, one that does not fit now waits),
   * builds its factor on a builder thread, on a stream of its own, while the batch runs,
   * advances every resident solve by one Crank-Nicolson step per round with one call of the
-    library's batched entry point (each solve on its own stream, PCG iterations queued in
-    lockstep, one convergence read-back per round for the whole batch), so the kernels of
-    different solves overlap on the device and newly built solves join at the next round;
-    solves of similar size share one of several scheduler lanes, which run concurrently,
+    library's batched entry point (one launch per stage for all solves of a storage precision:
+    the PCG vector kernels over a table of the solves and the apply with its levels aligned
+    from the leaves; PCG iterations in lockstep, one convergence read-back per round for the
+    whole batch), and newly built solves join at the next round; optionally several scheduler
+    lanes (solves of similar size share one) run their batches concurrently,
   * copies a finished solve's state to the host, resolves its future and frees its memory.
 
 A solve's arithmetic does not depend on the other solves in the batch (every kernel touches only
@@ -107,7 +108,7 @@ class Server:
     submit() returns a concurrent.futures.Future resolved with a Result (or the error)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 32, builders: int = 2,
-                 device: int = 0, paused: bool = False, lanes: int = 4, dense_top: int = 0):
+                 device: int = 0, paused: bool = False, lanes: int = 1, dense_top: int = 0):
         import torch
         self.device = torch.device("cuda", device)
         # the factors' dense top (hif_factor_ex): off by default, since forming it costs more
@@ -121,6 +122,7 @@ class Server:
         self._held = 0       # bytes reserved by admitted solves
         self._slots = 0      # admitted solves (building, ready or active)
         self._streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
+        # the batched step of a lane runs all its solves on one stream (the lane's)
         self._free_streams = list(range(self.max_slots))
         self._builders = ThreadPoolExecutor(max_workers=max(1, builders),
                                             thread_name_prefix="hif-build")
@@ -129,9 +131,11 @@ class Server:
         self._paused = bool(paused)  # admit and build, but run no rounds until resume()
         self.rounds = 0
         self.batch_sizes: list[int] = []
+        self.step_seconds = 0.0  # time spent in the batched step calls
         self.peak_held = 0
         self._error: BaseException | None = None
         self.lanes = max(1, int(lanes))
+        self._lane_streams = [torch.cuda.Stream(device=self.device) for _ in range(self.lanes)]
         self._threads = [threading.Thread(target=self._run_lane, args=(k,),
                                           name=f"hif-serve-{k}", daemon=True)
                          for k in range(self.lanes)]
@@ -187,6 +191,7 @@ class Server:
     def stats(self) -> dict:
         b = np.array(self.batch_sizes or [0])
         return {"rounds": self.rounds, "mean_batch": float(b.mean()), "max_batch": int(b.max()),
+                "step_call_s": self.step_seconds,
                 "peak_held_bytes": int(self.peak_held), "budget_bytes": self.budget,
                 "max_slots": self.max_slots}
 
@@ -325,11 +330,14 @@ class Server:
                         self._cv.wait(timeout=0.02)
                         continue
                     batch = list(active)
+                t0 = time.perf_counter()
                 its, rel, sts = hifcn.cn_batch_step(
                     [j.handle for j in batch], [j.u for j in batch],
                     [j.req.reaction for j in batch], [j.req.rtol for j in batch],
-                    [j.req.maxit for j in batch], [j.stream for j in batch])
+                    [j.req.maxit for j in batch], [self._lane_streams[lane]] * len(batch))
+                dt_step = time.perf_counter() - t0
                 with self._cv:
+                    self.step_seconds += dt_step
                     self.rounds += 1
                     self.batch_sizes.append(len(batch))
                 finished = []

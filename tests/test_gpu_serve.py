@@ -1,9 +1,12 @@
 """Continuous batching: cn_batch_step and the Server (GPU).
 
-Each solve's result must be the same alone and in the mix.  Every kernel of a solve reads and
-writes only its own handle's buffers and every reduction has a fixed order, so the bar is
-bitwise equality (iteration counts included).  One solve of the mix is also checked against the
-oracle, to the FP64 parity bar.
+cn_batch_step runs the solves whose factors allow it with one launch per stage for all of them
+(batched kernels over a table of solves; levels aligned from the leaves); the rest (BF16
+storage) with per-solve launches.  Either way every solve keeps its own block counts and stage
+plans, so its result is bitwise the same alone (a batch of one) and in any mix, iteration
+counts included.  The batched kernels split some dot products differently from the single-solve
+entry points (cn_step, cn_solve), so against those the bar is the FP64 parity bar: 1e-10 at
+rtol 1e-12.  One solve of the mix is also checked against the oracle.
 """
 import numpy as np
 import pytest
@@ -21,23 +24,47 @@ def _req(n, dt, seed, nsteps, reaction=(1, 1.0, 1.0), store="f32", eps=1e-4):
 
 
 def _alone(r):
-    """The request run by itself through the single-solve entry points (with the factor options
-    the Server uses: no dense top)."""
+    """The request run by itself through cn_batch_step, a batch of one per step (with the
+    factor options the Server uses: no dense top)."""
     import torch
     from paper_2004_05566_amd import hifcn
     a = torch.tensor(r.a_cells, dtype=torch.float64, device="cuda:0")
     u = torch.tensor(r.u0.ravel(), dtype=torch.float64, device="cuda:0")
     h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf, dense_top=0)
-    its, rel = h.cn_solve(u, r.nsteps, rtol=r.rtol, maxit=r.maxit, reaction=r.reaction)
+    s = torch.cuda.current_stream()
+    its, rels = [], []
+    for _ in range(r.nsteps):
+        it, rel, st = hifcn.cn_batch_step([h], [u], [r.reaction], [r.rtol], [r.maxit], [s])
+        assert st[0] == hifcn.HIF_OK
+        its.append(int(it[0]))
+        rels.append(float(rel[0]))
+    h.close()
+    return u.cpu().numpy().reshape((r.n,) * r.dim), np.array(its, np.int32), np.array(rels)
+
+
+def _single(r, rtol):
+    """The request through cn_solve (the single-solve entry point)."""
+    import torch
+    from paper_2004_05566_amd import hifcn
+    a = torch.tensor(r.a_cells, dtype=torch.float64, device="cuda:0")
+    u = torch.tensor(r.u0.ravel(), dtype=torch.float64, device="cuda:0")
+    h = hifcn.factor(a, r.dt, r.n, r.dim, r.eps, store=r.store, leaf=r.leaf, dense_top=0)
+    its, rel = h.cn_solve(u, r.nsteps, rtol=rtol, maxit=r.maxit, reaction=r.reaction)
     h.close()
     return u.cpu().numpy().reshape((r.n,) * r.dim), its, rel
 
 
 def test_batch_step_equals_single_steps(gpu_lib):
+    """A mixed batch (sizes, dt, reaction, FP32/FP64 storage, which the batched kernels run as
+    one launch per stage each, and BF16, which takes per-solve launches): each solve bitwise as
+    alone, and within 1e-10 of cn_solve at rtol 1e-12."""
     import torch
     from paper_2004_05566_amd import hifcn
     reqs = [_req(40, 1e-2, 101, 3), _req(64, 1e-1, 111, 3, reaction=(0, 0.0, 1.0)),
-            _req(33, 1e-3, 121, 3, store="f64")]
+            _req(33, 1e-3, 121, 3, store="f64"), _req(48, 1e-2, 131, 3, store="bf16"),
+            _req(128, 1e-2, 141, 3), _req(24, 1e-1, 151, 3, store="f64")]
+    for r in reqs:
+        r.rtol = 1e-12
     handles, states, streams = [], [], []
     for r in reqs:
         a = torch.tensor(r.a_cells, dtype=torch.float64, device="cuda:0")
@@ -53,9 +80,15 @@ def test_batch_step_equals_single_steps(gpu_lib):
         assert (sts == hifcn.HIF_OK).all()
         hist.append(its)
     for k, r in enumerate(reqs):
+        print(f"[case] batch entry {k}: n={r.n} store={r.store}", flush=True)
         u, its, _ = _alone(r)
-        assert np.array_equal(states[k].cpu().numpy().reshape(u.shape), u), k
+        got = states[k].cpu().numpy().reshape(u.shape)
+        assert np.array_equal(got, u), k
         assert [int(h[k]) for h in hist] == list(its)
+        us, its_s, _ = _single(r, 1e-12)
+        assert np.linalg.norm(got - us) <= 1e-10 * np.linalg.norm(us), k
+        assert np.abs(got - us).max() <= 1e-10 * np.abs(us).max(), k
+        assert all(abs(int(x) - int(y)) <= 1 for x, y in zip(its, its_s))
     for h in handles:
         h.close()
 
