@@ -10,7 +10,8 @@ root:
   (2) block Jacobi (jacobi-precond, eq3_2): for every edge and corner (3D: face, edge, corner)
       g, A_gg = L_g L_g^T and every coupling becomes L_g^-1 A_gh L_h^-T; the diagonal blocks
       are then the identity (set exactly).
-  (3) skeletonization (eq2_4, eq2_5, eq_T, eq2_9, eq3_3) of every edge (3D: face): an ID of the
+  (3) skeletonization (eq2_4, eq2_5, eq_T, eq2_9, eq3_3) of every edge (3D: face, and with
+      skel_edges also every edge, the variant the 3D paragraph of Sec. 2.2 allows): an ID of the
       coupling of the edge to the rest of the active DOFs splits it into redundant I~ and
       skeleton I^ with A_{R,I~} ~= A_{R,I^} T; the residual block is dropped, the redundant DOFs
       are eliminated with L_s = chol(I + T^T T) and the skeleton diagonal block becomes
@@ -122,9 +123,19 @@ def _keep(Acur: sp.csr_matrix, keep: np.ndarray) -> sp.csr_matrix:
     return (D @ Acur @ D).tocsr()
 
 
+def skel_kinds(dim: int, skel_edges: bool) -> tuple:
+    """Group kinds (axes on a separator) skeletonized in step (3): 2D edges; 3D faces, and 3D
+    edges too when skel_edges is set (Sec. 2.2, 3D paragraph).  2D edges are always
+    skeletonized, so the flag changes nothing there."""
+    return (1, 2) if dim == 3 and skel_edges else (1,)
+
+
 def phif_build(A: sp.spmatrix, n: int, dim: int, leaf: int, eps: float,
-               id_order: str = "level") -> Factor:
+               id_order: str = "level", skel_edges: bool = False) -> Factor:
     """Build the PHIF factor of the SPD matrix A on the n^dim grid (Sec. 2.2).
+
+    skel_edges: in 3D, skeletonize the edges of every level as well as its faces (kinds from
+    skel_kinds); faces come first in the sequential order.
 
     id_order: how the edges of a level meet each other's eliminations in step (3) (eq3_3 takes
     the product over the edges but not their order).  "level": every ID sees the matrix after
@@ -200,8 +211,10 @@ def phif_build(A: sp.spmatrix, n: int, dim: int, leaf: int, eps: float,
             Acur = (Acur + sp.coo_matrix(((dr == dc).astype(float) - old, (dr, dc)),
                                          shape=(N, N))).tocsr()
 
-        # (3) skeletonization of every edge (3D: face), IDs from the matrix after step (2)
-        skel_keys = [k for k in sep_keys if key_kind(k) == 1]
+        # (3) skeletonization of every edge (3D: face, and edge with skel_edges), IDs from the
+        # matrix after step (2)
+        skel_keys = [k for kd in skel_kinds(dim, skel_edges) for k in sep_keys
+                     if key_kind(k) == kd]
         red_all = np.zeros(N, dtype=bool)
         xr, xc, xv = [], [], []
         Acsc = Acur.tocsc()

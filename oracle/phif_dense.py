@@ -7,7 +7,8 @@ Every factor is formed as a full N x N matrix exactly in the block layout the pa
             -A_II^-1 A_BI^T on (I, B); E_l = prod_i E_{I_i} (eq3_1); A <- E_l^T A E_l.
   step (2)  C_{I} of jacobi-precond: identity except L_I^-T on (I, I); C_l = prod_i C_{I_i}
             (eq3_2); A <- C_l^T A C_l.
-  step (3)  for each edge (3D: face) with the ID taken from A after step (2): Z_I of eq_T
+  step (3)  for each edge (3D: face; with skel_edges faces, then edges) with the ID taken from
+            A after step (2): Z_I of eq_T
             (-T in the (I^, I~) position), A <- Z^T A Z, the O(eps) coupling between I~ and the
             rest is dropped (the approximation sign of eq_T), then E_{I~} of eq2_9 (L_s^-T on
             (I~, I~), (I + T^T T)^-1 T^T on (I~, I^)), A <- E^T A E; K_l = prod_i Z_i E_i (eq3_3).
@@ -47,7 +48,8 @@ def _put(Mat: sp.lil_matrix, rows, cols, block):
             Mat[i, j] = block[a, b]
 
 
-def phif_dense(A: np.ndarray, n: int, dim: int, leaf: int, eps: float) -> DenseResult:
+def phif_dense(A: np.ndarray, n: int, dim: int, leaf: int, eps: float,
+               skel_edges: bool = False) -> DenseResult:
     A = np.asarray(A, dtype=np.float64)
     N = A.shape[0]
     coords = node_grid_coords(n, dim)
@@ -91,8 +93,10 @@ def phif_dense(A: np.ndarray, n: int, dim: int, leaf: int, eps: float) -> DenseR
         Acur = np.asarray(Cl.T @ Acur @ Cl)
         snaps.append((lev, 2, Acur.copy(), {"groups": [groups[k] for k in seps]}))
 
-        # step (3): skeletonize edges (3D: faces); every ID from the matrix after step (2)
-        edges = [k for k in seps if key_kind(k) == 1]
+        # step (3): skeletonize edges (3D: faces, then edges with skel_edges); every ID from the
+        # matrix after step (2)
+        kinds = (1, 2) if dim == 3 and skel_edges else (1,)
+        edges = [k for kd in kinds for k in seps if key_kind(k) == kd]
         act_ids = np.flatnonzero(active)
         ids = []
         for ek in edges:

@@ -213,3 +213,63 @@ def test_sequential_id_order_exact_at_eps0_and_close_otherwise():
     el = np.linalg.norm(r - A @ phif.phif_apply(Fl, r)) / np.linalg.norm(r)
     es = np.linalg.norm(r - A @ phif.phif_apply(Fs, r)) / np.linalg.norm(r)
     assert 0.1 < es / el < 10, (el, es)
+
+
+def _skel_kind(F, lev, s):
+    """Axes on a separator of level lev for the DOFs of skeletonized group s (3D: 1 face,
+    2 edge)."""
+    coords = fd.node_grid_coords(F.n, F.dim)
+    S = geometry.separators(F.n, F.leaf, lev)
+    dof = (s.redund if len(s.redund) else s.skel)[0]
+    return int(np.isin(coords[dof], S).sum())
+
+
+EDGE_CASES = [(7, 4, 0.0), (7, 4, 1e-6), (7, 4, 1e-3), (7, 4, 0.4),
+              (8, 4, 0.0), (8, 4, 1e-6), (8, 4, 1e-3), (8, 4, 0.4),
+              (12, 3, 1e-3), (12, 3, 0.4)]
+
+
+@pytest.mark.parametrize("n,m,eps", EDGE_CASES)
+def test_edge_skeletonization_block_equals_dense_literal(n, m, eps):
+    """3D with the edges skeletonized as well as the faces (Sec. 2.2, 3D paragraph): the block
+    oracle against the paper's N x N factor matrices multiplied out, with the same skeleton size
+    on every face and edge; eps = 0 gives A^-1.  Only at eps = 0.4 do the edges of these grids
+    lose DOFs (see the test below), so that case runs the edge path with compression."""
+    A, _ = _problem(n, 3)
+    F = phif.phif_build(A, n, 3, m, eps, skel_edges=True)
+    D = phif_dense.phif_dense(A.toarray(), n, 3, m, eps, skel_edges=True)
+    Fi = phif.phif_dense_inverse(F)
+    assert np.linalg.norm(Fi - D.Finv) <= 1e-12 * np.linalg.norm(D.Finv)
+    ranks_block = [sorted(len(s.skel) for s in lv.skels) for lv in F.levels]
+    ranks_dense = [sorted(k for _, k in r) for r in D.ranks]
+    assert ranks_block == ranks_dense
+    kinds = [_skel_kind(F, l, s) for l, lv in enumerate(F.levels) for s in lv.skels]
+    assert kinds.count(2) > 0 and set(kinds) == {1, 2}
+    if eps == 0.0:
+        Ainv = np.linalg.inv(A.toarray())
+        assert np.linalg.norm(Fi - Ainv) <= 1e-11 * np.linalg.norm(Ainv)
+    if eps == 0.4:
+        red = sum(len(s.redund) for l, lv in enumerate(F.levels) for s in lv.skels
+                  if _skel_kind(F, l, s) == 2)
+        assert red > 0
+        F0 = phif.phif_build(A, n, 3, m, eps)
+        assert F.active_counts[-1][2] < F0.active_counts[-1][2]
+
+
+@pytest.mark.parametrize("order", ["level", "sequential"])
+def test_edges_keep_full_rank_under_stencil_coupling(order):
+    """Under the stencil, each DOF of a 3D edge is a direct neighbour of DOFs on the four faces
+    around it, which stay active through the level (cell elimination removes only interiors), so
+    the coupling block of an edge holds a full-rank part and its ID keeps every column at any
+    practical eps: the factor with skeletonized edges is the faces-only factor."""
+    n, m = 16, 4
+    a = gen.grf_coefficient(n, 3, 0.15, 7)
+    A, _ = fd.cn_matrices(a, 0.05)
+    r = gen.normal_vector(n ** 3, 8)
+    for eps in (1e-3, 1e-2):
+        F = phif.phif_build(A, n, 3, m, eps, skel_edges=True, id_order=order)
+        F0 = phif.phif_build(A, n, 3, m, eps, id_order=order)
+        edges = [s for l, lv in enumerate(F.levels) for s in lv.skels if _skel_kind(F, l, s) == 2]
+        assert len(edges) > 0 and all(len(s.redund) == 0 for s in edges)
+        assert F.active_counts == F0.active_counts
+        assert np.array_equal(phif.phif_apply(F, r), phif.phif_apply(F0, r))
