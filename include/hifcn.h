@@ -73,11 +73,17 @@ hif_status_t hif_factor(const double* a_cells_dev, double dt, const hif_grid_t* 
  * (the stages from some level's group step up to the root and back, formed at build time as
  * one symmetric matrix; see hif_get_info's top_level): < 0 the library's default (or the
  * HIFCN_DENSE_TOP environment variable), 0 none.  Forming it costs build time that a solve of
- * few steps may not win back.  reserved: must be 0. */
-typedef struct { int64_t dense_top; int64_t reserved[3]; } hif_factor_opts_t;
+ * few steps may not win back.  flags: 0 or HIF_FACTOR_SKEL_EDGES.  reserved: must be 0. */
+typedef struct { int64_t dense_top; int64_t flags; int64_t reserved[2]; } hif_factor_opts_t;
+
+/* 3D: skeletonize the edges of every level as well as its faces in step (3) (Sec. 2.2, 3D
+ * paragraph: the paper's variant that lowers the build's complexity).  Edges are ID'd from the
+ * same matrix as the faces (level-synchronous).  No effect in 2D, where the edges are the
+ * skeletonized groups anyway. */
+#define HIF_FACTOR_SKEL_EDGES 1
 
 /* hif_factor with options (opts may be NULL: the defaults).  Errors as hif_factor, and
- * HIF_ERR_ARG for nonzero reserved fields. */
+ * HIF_ERR_ARG for unknown flags or nonzero reserved fields. */
 hif_status_t hif_factor_ex(const double* a_cells_dev, double dt, const hif_grid_t* grid,
                            double eps, hif_store_t store, const hif_factor_opts_t* opts,
                            void* hip_stream, hif_handle_t* out);

@@ -469,12 +469,16 @@ hif_status_t hif_factor_ex(const double* a_cells_dev, double dt, const hif_grid_
   return guarded([&] {
     HIF_REQUIRE(out != nullptr, HIF_ERR_ARG, "NULL output handle");
     HIF_REQUIRE(store >= HIF_STORE_F64 && store <= HIF_STORE_BF16, HIF_ERR_ARG, "bad store");
-    if (opts)
+    if (opts) {
       for (int64_t r : opts->reserved)
         HIF_REQUIRE(r == 0, HIF_ERR_ARG, "reserved option fields must be 0");
+      HIF_REQUIRE((opts->flags & ~(int64_t)HIF_FACTOR_SKEL_EDGES) == 0, HIF_ERR_ARG,
+                  "unknown factor flags");
+    }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     auto h = make_handle(a_cells_dev, dt, grid, eps, s);
     h->f.top_budget = opts ? opts->dense_top : -1;
+    h->f.skel_edges = opts && (opts->flags & HIF_FACTOR_SKEL_EDGES) != 0;
     gpu_build(*h, a_cells_dev, store, s);
     setup_rhs(*h);
     h->built = true;
@@ -525,6 +529,7 @@ hif_status_t hif_refactor(hif_handle_t hh, const double* a_cells_dev, void* hip_
     // leave with it (the PCG workspace, state and host flag stay)
     auto nh = make_handle(a_cells_dev, h.dt, &g, h.eps, s);
     nh->f.top_budget = h.f.top_budget;
+    nh->f.skel_edges = h.f.skel_edges;
     nh->plan0 = h.plan0;
     nh->keep_plan0 = true;
     gpu_build(*nh, a_cells_dev, h.f.store, s);
@@ -736,7 +741,7 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
       for (StepState* x : mine) HIF_CHECK(hipStreamSynchronize(x->s));
     };
     int dev = 0;
-    HIF_CHECK(hipGetDevice(&dev));
+    if (nrest > 0) HIF_CHECK(hipGetDevice(&dev));
     const int W = std::min(nrest, batch_threads());
     if (W == 1) {
       run(0, 1, dev);

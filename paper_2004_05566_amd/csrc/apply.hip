@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <mutex>
 #include <queue>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -355,55 +356,95 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
 // with y_I left as it is; backward: x_I = M (y_I - A_IB x_B).  In exact arithmetic this is the
 // pair of triangular passes of each sweep (E^T: y_I <- L^-1 y_I, c_B = A_BI L^-T (L^-1 y_I);
 // E: x_I <- L^-T (L^-1 y_I - L^-1 A_IB x_B)), since nothing between the two sweeps reads the
-// interior values.  One wavefront per cell (interiors of at most 64 DOFs): the packed triangle
-// is copied into an LDS square with both halves filled (a table gives the two positions of
-// every packed element), then lane i forms (M t)_i by walking column i of the square: lanes
-// read consecutive words, and the mirrored writes of consecutive elements land kSymLd (odd)
-// words apart, so neither the writes nor the walk meet bank conflicts.
-constexpr int kSymPer = (kSymMaxCell * (kSymMaxCell + 1) / 2 + 63) / 64;  // elements per lane
+// interior values.  One wavefront per cell (interiors of at most 64 DOFs), lane i forming
+// (M t)_i.  A cell of at most the level's square order (SymCfg::n, the usual interior size) is
+// copied into an LDS square with both halves filled (a table gives the two positions of every
+// element), then lane i walks row i.  The leading dimension is odd, so the mirrored stores of
+// consecutive packed elements and the row walks of consecutive lanes meet no bank conflicts.
+// The block is stored in the order of sym_store_index: each lane loads 16-byte vectors and the
+// wavefront's k-th store of a vector covers consecutive packed elements.  A larger cell (the
+// few of the last row and column of cells) stays a packed triangle in LDS and lane i walks its
+// row i (consecutive lanes, consecutive words) and then its column i.  The LDS of a launch is
+// sized for the usual cell, so more wavefronts stay resident.
 
 // LDS elements of the compute type a symmetric cell stage needs besides its record.
-__host__ __device__ inline int sym_smem_elems(int maxB) {
-  return kSymMaxCell * kSymLd + 2 * kSymMaxCell + 2 * round_up(maxB, 4);
+__host__ __device__ inline int sym_smem_elems(int mat, int maxB) {
+  return mat + 2 * kSymMaxCell + 2 * round_up(maxB, 4);
 }
 
-// Every packed element of the cell block into the square sq (all loads are issued first).
+// Every element of the cell block into LDS: to both of its square positions (tab: this order's
+// entries, in storage order) or, with tab null, to its packed position.  All loads are issued
+// before the first store.  A block starts 16-byte aligned and its storage runs to sym_coff(tl),
+// so every vector lies inside it; the spare slots of the last chunk land on the spare word (tab)
+// or below the packed triangle's padded end (no tab), where nothing reads them.
 template <typename S, typename C>
 __device__ __forceinline__ void sym_stage(C* sq, const S* __restrict__ v, int tl,
                                           const int32_t* __restrict__ tab, int lane) {
-  C e[kSymPer];
-  int32_t t[kSymPer];
+  constexpr int E = 16 / sizeof(S);                      // elements per vector
+  constexpr int kTri = kSymMaxCell * (kSymMaxCell + 1) / 2;
+  constexpr int P = (kTri + 64 * E - 1) / (64 * E);      // vectors per lane (chunks)
+  const int4* vv = reinterpret_cast<const int4*>(v);
+  const int nv = (tl + E - 1) / E;
+  int4 e[P];
+  int32_t t[P][E];
 #pragma unroll
-  for (int u = 0; u < kSymPer; ++u) {
-    const int p = lane + 64 * u;
-    if (p < tl) {
-      e[u] = load_as<C>(v + p);
-      t[u] = tab[p];
+  for (int u = 0; u < P; ++u) {
+    const int q = lane + 64 * u;
+    if (q < nv) {
+      e[u] = vv[q];
+      if (tab) {
+        if constexpr (E == 2) {
+          const int2 w = reinterpret_cast<const int2*>(tab)[q];
+          t[u][0] = w.x;
+          t[u][1] = w.y;
+        } else {
+#pragma unroll
+          for (int h = 0; h < E / 4; ++h) {
+            const int4 w = reinterpret_cast<const int4*>(tab)[q * (E / 4) + h];
+            t[u][4 * h] = w.x;
+            t[u][4 * h + 1] = w.y;
+            t[u][4 * h + 2] = w.z;
+            t[u][4 * h + 3] = w.w;
+          }
+        }
+      }
     }
   }
 #pragma unroll
-  for (int u = 0; u < kSymPer; ++u) {
-    const int p = lane + 64 * u;
-    if (p < tl) {
-      sq[t[u] & 0xffff] = e[u];
-      sq[t[u] >> 16] = e[u];
+  for (int u = 0; u < P; ++u) {
+    const int q = lane + 64 * u;
+    if (q < nv) {
+      S ev[E];
+      __builtin_memcpy(ev, &e[u], 16);
+      if (tab) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const C x = load_as<C>(ev + k);
+          sq[t[u][k] & 0xffff] = x;
+          sq[t[u][k] >> 16] = x;
+        }
+      } else {
+        const int qc = sym_chunk_q(u, tl, E);  // packed element lane + qc k of chunk u
+#pragma unroll
+        for (int k = 0; k < E; ++k) sq[64 * E * u + lane + qc * k] = load_as<C>(ev + k);
+      }
     }
   }
 }
 
-// (M t)_lane for lane < n: column `lane` of the square against t (broadcast from LDS), four
-// running sums added in a fixed order.
+// (M t)_lane for lane < n from the square (leading dimension ld): row `lane` against t
+// (broadcast from LDS), eight terms per batch into four running sums, added in a fixed order.
 template <typename C>
-__device__ __forceinline__ C sym_col(const C* sq, const C* ts, int n, int lane) {
-  const C* col = sq + lane;
+__device__ __forceinline__ C sym_row(const C* sq, const C* ts, int n, int ld, int lane) {
+  const C* row = sq + lane * ld;
   C a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  int k = 0;
-  for (; k + 8 <= n; k += 8) {
+  int c = 0;
+  for (; c + 8 <= n; c += 8) {
     C m[8], t[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      m[u] = col[(k + u) * kSymLd];
-      t[u] = ts[k + u];
+      m[u] = row[c + u];
+      t[u] = ts[c + u];
     }
     a0 += m[0] * t[0];
     a1 += m[1] * t[1];
@@ -414,8 +455,32 @@ __device__ __forceinline__ C sym_col(const C* sq, const C* ts, int n, int lane) 
     a2 += m[6] * t[6];
     a3 += m[7] * t[7];
   }
-  for (; k < n; ++k) a0 += col[k * kSymLd] * ts[k];
+  for (; c < n; ++c) a0 += row[c] * ts[c];
   return (a0 + a1) + (a2 + a3);
+}
+
+// (M t)_lane for lane < n from the packed column-major lower triangle P: row `lane` left of
+// the diagonal (entry (lane, j) at colstart(j) + lane - j, consecutive across lanes), then
+// column `lane` from the diagonal down (contiguous).
+template <typename C>
+__device__ __forceinline__ C sym_packed(const C* P, const C* ts, int n, int lane) {
+  C a = 0;
+  int o = lane;  // colstart(j) + lane - j for j = 0
+  for (int j = 0; j < lane; ++j) {
+    a += P[o] * ts[j];
+    o += n - j - 1;
+  }
+  const C* col = P + o;  // o = colstart(lane): the diagonal entry
+  C b = 0;
+  for (int j = lane; j < n; ++j) b += col[j - lane] * ts[j];
+  return a + b;
+}
+
+// (M t)_lane: the square or the packed form, as the cell's size decided.
+template <typename C>
+__device__ __forceinline__ C sym_apply(const C* sq, const C* ts, int nI, const SymCfg& cfg,
+                                       int lane) {
+  return nI <= cfg.n ? sym_row(sq, ts, nI, cfg.ld, lane) : sym_packed(sq, ts, nI, lane);
 }
 
 // Forward stage of a symmetric cell (one wavefront).  idx: the cell's record (LDS).  in: where
@@ -425,15 +490,14 @@ __device__ __forceinline__ C sym_col(const C* sq, const C* ts, int n, int lane) 
 template <typename S, typename C, typename Hook = NoHook>
 __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* __restrict__ idx,
                                              const S* __restrict__ vals, double* __restrict__ y,
-                                             double* __restrict__ cb,
-                                             const int32_t* __restrict__ sqtab,
+                                             double* __restrict__ cb, const SymCfg& cfg,
                                              unsigned char* smem_raw,
                                              const double* __restrict__ in = nullptr,
                                              Hook hook = Hook{}, const int* stop = nullptr,
                                              bool own_ys = false) {
   const double* src = in ? in : y;
   C* sq = reinterpret_cast<C*>(smem_raw);
-  C* ts = sq + kSymMaxCell * kSymLd;
+  C* ts = sq + cfg.mat;
   C* zs = ts + kSymMaxCell;
   const int lane = threadIdx.x;
   const int nI = d.nI, nB = d.nB, tl = tri_count(nI);
@@ -446,15 +510,15 @@ __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* _
     gi = gI[lane];
     yv = src[gi];
   }
-  sym_stage<S, C>(sq, v, tl, sqtab + sym_tab_start(nI), lane);
+  sym_stage<S, C>(sq, v, tl, nI <= cfg.n ? cfg.tab + cfg.tab[nI] : nullptr, lane);
   if (!own_ys) ts[lane] = (C)yv;
   hook(ts);
   __syncthreads();
   if (stop && *stop) return;
-  if (lane < nI) zs[lane] = sym_col(sq, ts, nI, lane);
+  if (lane < nI) zs[lane] = sym_apply(sq, ts, nI, cfg, lane);
   __syncthreads();
   for (int b = lane; b < nB; b += 64)
-    cb[d.offCB + b] = (double)(load_as<C>(v + tl + b) * zs[ibp[b]]);
+    cb[d.offCB + b] = (double)(load_as<C>(v + sym_coff(tl) + b) * zs[ibp[b]]);
   if (in && in != y && lane < nI) y[gi] = yv;  // the output takes the inputs at the interiors
 }
 
@@ -464,10 +528,10 @@ __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* _
 template <typename S, typename C>
 __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* __restrict__ idx,
                                              const S* __restrict__ vals, double* __restrict__ x,
-                                             const int32_t* __restrict__ sqtab,
-                                             unsigned char* smem_raw, const TopIn& top) {
+                                             const SymCfg& cfg, unsigned char* smem_raw,
+                                             const TopIn& top) {
   C* sq = reinterpret_cast<C*>(smem_raw);
-  C* ts = sq + kSymMaxCell * kSymLd;
+  C* ts = sq + cfg.mat;
   C* xbs = ts + 2 * kSymMaxCell;
   const int lane = threadIdx.x;
   const int nI = d.nI, nB = d.nB, tl = tri_count(nI);
@@ -492,11 +556,11 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
       xv = x[gB[b]];
     }
     xbs[b] = (C)xv;
-    abs_[b] = load_as<C>(v + tl + b);
+    abs_[b] = load_as<C>(v + sym_coff(tl) + b);
   }
   if (top.pos)
     for (int e = lane; e < top.ne; e += 64) x[top.ext[2 * e + 1]] = top.sum(top.ext[2 * e]);
-  sym_stage<S, C>(sq, v, tl, sqtab + sym_tab_start(nI), lane);
+  sym_stage<S, C>(sq, v, tl, nI <= cfg.n ? cfg.tab + cfg.tab[nI] : nullptr, lane);
   __syncthreads();
   if (lane < nI) {
     C t = (C)xi;
@@ -507,7 +571,7 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
     ts[lane] = t;
   }
   __syncthreads();
-  if (lane < nI) x[gi] = (double)sym_col(sq, ts, nI, lane);
+  if (lane < nI) x[gi] = (double)sym_apply(sq, ts, nI, cfg, lane);
 }
 
 // The first stage of a step's first apply, making the step's right-hand side on the way: the
@@ -524,8 +588,7 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
                                          double* __restrict__ cb, int blk_elems, int team,
                                          const int32_t* __restrict__ gcopy, int gcstride,
                                          const CgRhs& rhs, unsigned char* smem_raw,
-                                         double* gred, const int32_t* __restrict__ sqtab,
-                                         int flen) {
+                                         double* gred, SymCfg sym, int flen) {
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   const bool held = rhs.ahead && !rhs.st->ok_next;  // (the same in every block)
   load_record(rec, recs + (int64_t)blockIdx.x * stride, flen, threadIdx.x, blockDim.x);
@@ -571,7 +634,7 @@ __device__ __forceinline__ void cell_rhs(const int32_t* __restrict__ recs, int s
     }
   };
   if constexpr (MODE == 2)
-    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sqtab, smem_raw + 4 * stride, nullptr, make, nullptr,
+    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sym, smem_raw + 4 * stride, nullptr, make, nullptr,
                        true);
   else
     cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
@@ -595,14 +658,13 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team, CgGate gate,
                                                   const int32_t* __restrict__ gcopy, int gcstride,
-                                                  CgRhs rhs, const int32_t* __restrict__ sqtab,
-                                                  int flen) {
+                                                  CgRhs rhs, SymCfg sym, int flen) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int gstop;
   __shared__ double gred[4];
   if (rhs.u) {  // the step's right-hand side made here (see cell_rhs)
     cell_rhs<S, C, ST, MODE>(recs, stride, vals, y, cb, blk_elems, team, gcopy, gcstride, rhs,
-                             smem_raw, gred, sqtab, flen);
+                             smem_raw, gred, sym, flen);
     return;
   }
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
@@ -644,7 +706,7 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
     }
   };
   if constexpr (MODE == 2)
-    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sqtab, smem_raw + 4 * stride, gate.src, verdict,
+    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sym, smem_raw + 4 * stride, gate.src, verdict,
                        gated ? &gstop : nullptr);
   else
     cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
@@ -768,8 +830,7 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
                                                   const int* __restrict__ done, int blk_elems,
                                                   int team, const int32_t* __restrict__ tpos,
                                                   int tstride, const double* __restrict__ tpart,
-                                                  int tnch, int tn,
-                                                  const int32_t* __restrict__ sqtab) {
+                                                  int tnch, int tn, SymCfg sym) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
@@ -783,7 +844,7 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
     top = TopIn{r + tstride - d.nB, r + 1, r[0], tpart, tnch, tn};
   }
   if constexpr (MODE == 2)
-    cell_bwd_sym<S, C>(d, rec, vals, x, sqtab, smem_raw + 4 * stride, top);
+    cell_bwd_sym<S, C>(d, rec, vals, x, sym, smem_raw + 4 * stride, top);
   else
     cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride, top);
 }
@@ -1554,7 +1615,7 @@ StagePlan cell_plan(const LevelDev& L) {
     p.seg = 1;
     p.blk_elems = 0;
     p.rec = 4 * (size_t)L.cstride;
-    p.smem = sizeof(C) * (size_t)sym_smem_elems(L.maxB);
+    p.smem = sizeof(C) * (size_t)sym_smem_elems(L.sqmat, L.maxB);
     p.grid = L.ncell;
     return p;
   }
@@ -1734,6 +1795,10 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const S
     hipLaunchKernelGGL(kernel, grid, block, smem, s, args...);
 }
 
+SymCfg sym_cfg(const FactorDev& f, const LevelDev& L) {
+  return SymCfg{f.sqtab.p, L.sqn, L.sqld, L.sqmat};
+}
+
 template <typename S, typename C, int MODE>
 void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals, double* y,
                  double* cb, const int* done, hipStream_t s, const StageTimer& t,
@@ -1744,7 +1809,7 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
     launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, cb, done, p.blk_elems, p.seg, gate ? *gate : CgGate{},
            (gate || rhs) ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride,
-           rhs ? *rhs : CgRhs{}, (const int32_t*)f.sqtab.p, L.cfwd);
+           rhs ? *rhs : CgRhs{}, sym_cfg(f, L), L.cfwd);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
@@ -1752,7 +1817,7 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
            L.cstride, vals, y, done, p.blk_elems, p.seg,
            fold ? (const int32_t*)f.tpos.p : (const int32_t*)nullptr, f.tpstride,
            (const double*)f.twsc.p, (f.ntop + f.tspan - 1) / std::max(1, f.tspan), f.ntop,
-           (const int32_t*)f.sqtab.p);
+           sym_cfg(f, L));
   }
 }
 
@@ -1990,7 +2055,7 @@ __global__ __launch_bounds__(256) void k_bcell_fwd(const BatchArg* __restrict__ 
   const S* vals = reinterpret_cast<const S*>(a.vals);
   unsigned char* sm = smem_raw + 4 * recmax;
   if constexpr (MODE == 2)
-    cell_fwd_sym<S, C>(d, rec, vals, a.y, a.cb, a.sqtab, sm);
+    cell_fwd_sym<S, C>(d, rec, vals, a.y, a.cb, SymCfg{a.sqtab, a.sqn, a.sqld, a.sqmat}, sm);
   else if (a.staged)
     cell_fwd_body<S, C, true, 0>(d, rec, vals, a.y, a.cb, a.blk_elems, a.team, false, sm);
   else
@@ -2012,7 +2077,8 @@ __global__ __launch_bounds__(256) void k_bcell_bwd(const BatchArg* __restrict__ 
   const S* vals = reinterpret_cast<const S*>(a.vals);
   unsigned char* sm = smem_raw + 4 * recmax;
   if constexpr (MODE == 2)
-    cell_bwd_sym<S, C>(d, rec, vals, a.y, a.sqtab, sm, TopIn{});
+    cell_bwd_sym<S, C>(d, rec, vals, a.y, SymCfg{a.sqtab, a.sqn, a.sqld, a.sqmat}, sm,
+                       TopIn{});
   else if (a.staged)
     cell_bwd_body<S, C, true, 0>(d, rec, vals, a.y, a.blk_elems, a.team, sm);
   else
@@ -2262,12 +2328,15 @@ void batch_cell(const FactorDev& f, int l, double* y, const int* done, BatchArg&
   a.cb = f.cb.p + (int64_t)(l & 1) * f.cbstride;
   a.done = done;
   a.sqtab = f.sqtab.p;
+  a.sqn = L.sqn;
+  a.sqld = L.sqld;
+  a.sqmat = L.sqmat;
   a.stride = L.cstride;
   a.len = fwd ? L.cfwd : L.cstride;
   a.count = L.ncell;
   if (L.cmode == 2) {
     bl.threads = 64;
-    bl.smem = std::max(bl.smem, sizeof(C) * (size_t)sym_smem_elems(L.maxB));
+    bl.smem = std::max(bl.smem, sizeof(C) * (size_t)sym_smem_elems(L.sqmat, L.maxB));
   } else {
     const size_t vec = 3 * (size_t)L.maxI + 2 * (size_t)L.maxB + 4;
     a.blk_elems = round_up(L.maxCV, 8);

@@ -38,6 +38,7 @@ struct CellTask {
   int32_t nI, nB, nsub, offSub;
   int64_t offAII, offW, offS, offV;
   int32_t mode, offIb;  // mode 1: keep A_IB(ib_b, b) per boundary DOF instead of H
+  int32_t symE, pad;    // mode 2: elements of the storage type per 16 bytes (storage order)
 };
 struct Contrib { int64_t offS; int32_t ld, r0, c0, pad; };
 struct SchurTask { int64_t dst; int32_t rows, cols, ncontrib, offC; };
@@ -187,9 +188,10 @@ __global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict_
   wg_identity(X, nI, nI);
   __syncthreads();
   double* V = fv + t.offV;
+  const int64_t coff = t.mode == 2 ? sym_coff(tri_count(nI)) : tri_count(nI);
   if (t.mode)   // the single coupling of each boundary DOF, before G overwrites A_IB
     for (int b = threadIdx.x; b < nB; b += blockDim.x)
-      V[tri_count(nI) + b] = G[(int64_t)ibl[t.offIb + b] * nB + b];
+      V[coff + b] = G[(int64_t)ibl[t.offIb + b] * nB + b];
   wg_potrf(W, nI, nI, err);
   wg_trsm_lower(W, nI, nI, X, nI, nI, true);
   if (nB) wg_trsm_lower(W, nI, nI, G, nB, nB, false);
@@ -204,16 +206,19 @@ __global__ __launch_bounds__(kBT) void k_build_cells(const CellTask* __restrict_
   // apply blocks: packed L^-1 (mode 2: packed A_II^-1 = L^-T L^-1), then (mode 0)
   // H = G^T L^-1 column-major (H[j*nB + b])
   if (t.mode == 2) {
-    // (A_II^-1)_ij = sum over k >= max(i, j) of (L^-1)_ki (L^-1)_kj; packed column-major lower
-    const int64_t tl = tri_count(nI);
-    for (int64_t e = threadIdx.x; e < tl; e += blockDim.x) {
-      int j = 0;
-      int64_t c = e;
-      while (c >= nI - j) c -= nI - j++;
-      const int i = j + (int)c;
+    // (A_II^-1)_ij = sum over k >= max(i, j) of (L^-1)_ki (L^-1)_kj; packed column-major lower,
+    // in the storage order of sym_store_index (padding slots up to sym_coff: zero)
+    const int tl = (int)tri_count(nI);
+    for (int s = threadIdx.x; s < (int)coff; s += blockDim.x) {
+      const int e = sym_packed_index(s, tl, t.symE);
       double acc = 0;
-      for (int k = i; k < nI; ++k) acc += X[(int64_t)k * nI + i] * X[(int64_t)k * nI + j];
-      V[e] = acc;
+      if (s < (tl + t.symE - 1) / t.symE * t.symE && e < tl) {
+        int j = 0, c = e;
+        while (c >= nI - j) c -= nI - j++;
+        const int i = j + c;
+        for (int k = i; k < nI; ++k) acc += X[(int64_t)k * nI + i] * X[(int64_t)k * nI + j];
+      }
+      V[s] = acc;
     }
     return;
   }
@@ -715,7 +720,7 @@ int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 // Build the factor of the handle's operator on the device and lay it out for the apply.
 void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t s) {
   (void)a_cells;  // the link weights were already derived from it
-  const Geometry geo{hd.dim, hd.n, hd.leaf, hd.L};
+  const Geometry geo{hd.dim, hd.n, hd.leaf, hd.L, hd.f.skel_edges};
   DevBuf<int> err(1, s);
   HIF_CHECK(hipMemsetAsync(err.p, 0, sizeof(int), s));
   // cells with at least this many interior DOFs (and the root) use the blocked front path;
@@ -818,7 +823,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       voff = align_vals(voff);
       cell_voff[ci] = voff;
       const int nI = gsz(P.cells[ci]);
-      voff += tri64(nI) + (cmode ? (int64_t)nB : (int64_t)nB * nI);
+      voff += (cmode == 2 ? sym_coff(tri64(nI)) : tri64(nI)) +
+              (cmode ? (int64_t)nB : (int64_t)nB * nI);
       if (cmode) {
         const std::vector<int32_t>& I = P.groups[P.cells[ci]].dofs;
         for (int i = 0; i < nI; ++i) pos[I[i]] = i;
@@ -839,7 +845,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     for (int g : P.seps) {
       voff = align_vals(voff);
       grp_voff[g] = voff;
-      voff += tri64(gsz(g)) * (P.groups[g].kind == 1 ? 2 : 1);
+      voff += tri64(gsz(g)) * (geo.skeletonized(P.groups[g].kind) ? 2 : 1);
     }
     voff = align_vals(voff);
     DevBuf<double> fv(std::max<int64_t>(1, voff), s);
@@ -871,6 +877,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       soff += (int64_t)nB * nB;
       t.offV = cell_voff[ci];
       t.mode = cmode;
+      t.symE = (int32_t)(16 / store_elem_bytes(store));
       t.offIb = (int32_t)ibl.size();
       ibl.insert(ibl.end(), cell_ib[ci].begin(), cell_ib[ci].end());
     }
@@ -1018,7 +1025,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     }
 
     mark("jacobi", lev);
-    // ---- (3) skeletonization of every edge (3D: face)
+    // ---- (3) skeletonization of every edge (3D: face, and edge with skel_edges)
     std::vector<int32_t> kval(P.skel.size());
     std::vector<int32_t> permv;
     std::vector<int32_t> perm_off(G, -1);
@@ -1029,7 +1036,8 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       std::vector<std::vector<int>> rows_of(G);
       for (size_t b = 0; b < P.blocks.size(); ++b) {
         const int h = P.blocks[b].first, g = P.blocks[b].second;
-        if (h != g && P.groups[h].kind > 0 && P.groups[g].kind == 1) rows_of[g].push_back((int)b);
+        if (h != g && P.groups[h].kind > 0 && geo.skeletonized(P.groups[g].kind))
+          rows_of[g].push_back((int)b);
       }
       std::vector<IdTask> it;
       std::vector<SubBlk> rs;
@@ -1399,7 +1407,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     ld.maxCV = lo.maxCV;
     ld.maxGV = lo.maxGV;
     ld.cmode = lo.cells.empty() ? 0 : lo.cells[0].mode;
-    if (ld.cmode == 2) build_sym_table(f, ld.maxI, s);
+    if (ld.cmode == 2) build_sym_table(f, lo.cells, s);
     {
       std::vector<int64_t> nsl(lo.groups.size());
       for (size_t q = 0; q < lo.groups.size(); ++q) nsl[q] = (int64_t)lo.gslots[q].size();

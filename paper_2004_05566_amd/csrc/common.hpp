@@ -139,6 +139,28 @@ struct GroupDesc {
 };
 
 __host__ __device__ inline int64_t tri_count(int64_t n) { return n * (n + 1) / 2; }
+
+// Storage order of a symmetric level-0 cell block (A_II^-1 of a cell held as one matrix): its
+// tl packed elements (column-major lower triangle) go in chunks of 64 E, E being the elements of
+// the storage type in 16 bytes.  In a chunk of m elements, with q = ceil(m / E), the E stored
+// elements E L .. E L + E - 1 hold the packed elements L, L + q, ..., L + (E - 1) q, so a
+// wavefront that loads one 16-byte vector per lane stores consecutive packed elements across
+// its lanes with each of its E stores.  The block's couplings follow at sym_coff(tl).
+__host__ __device__ inline int sym_chunk_q(int c, int tl, int E) {
+  const int m = tl - 64 * E * c;
+  return ((m < 64 * E ? m : 64 * E) + E - 1) / E;
+}
+__host__ __device__ inline int sym_store_index(int p, int tl, int E) {
+  const int c = p / (64 * E), w = p - 64 * E * c, q = sym_chunk_q(c, tl, E);
+  const int k = w / q, L = w - k * q;
+  return 64 * E * c + E * L + k;
+}
+// The packed element at stored position s (tl or more: a padding slot of the last chunk).
+__host__ __device__ inline int sym_packed_index(int s, int tl, int E) {
+  const int c = s / (64 * E), w = s - 64 * E * c, q = sym_chunk_q(c, tl, E);
+  return 64 * E * c + w / E + q * (w % E);
+}
+__host__ __device__ inline int64_t sym_coff(int64_t tl) { return (tl + 7) / 8 * 8; }
 // start of column j of a packed column-major lower triangle of order n
 __host__ __device__ inline int colstart(int j, int n) { return j * n - (j * (j - 1)) / 2; }
 

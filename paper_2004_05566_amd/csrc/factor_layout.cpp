@@ -102,14 +102,48 @@ void level_stage_bytes(const std::vector<CellDesc>& cells, const std::vector<Gro
 
 bool sym_cells_off() { return std::getenv("HIFCN_NO_SYM_CELLS") != nullptr; }
 
-void build_sym_table(FactorDev& f, int max_n, hipStream_t s) {
-  HIF_REQUIRE(max_n >= 1 && max_n <= kSymMaxCell, HIF_ERR_ARG, "internal: symmetric cell size");
-  std::vector<int32_t> tab((size_t)sym_tab_start(max_n + 1));
-  for (int n = 1; n <= max_n; ++n) {
-    int32_t* t = tab.data() + sym_tab_start(n);
-    int p = 0;
-    for (int j = 0; j < n; ++j)
-      for (int i = j; i < n; ++i) t[p++] = (j * kSymLd + i) | (i * kSymLd + j) << 16;
+void build_sym_table(FactorDev& f, const std::vector<CellDesc>& cells, hipStream_t s) {
+  HIF_REQUIRE(!cells.empty() && !f.lv.empty(), HIF_ERR_ARG, "internal: symmetric cells");
+  HIF_REQUIRE(f.store == HIF_STORE_F32 || f.store == HIF_STORE_F64, HIF_ERR_ARG,
+              "internal: symmetric cells need FP32 or FP64 storage");
+  std::vector<int> sizes;
+  for (const CellDesc& d : cells) sizes.push_back(d.nI);
+  std::sort(sizes.begin(), sizes.end());
+  const int maxI = sizes.back();
+  HIF_REQUIRE(maxI <= kSymMaxCell, HIF_ERR_ARG, "internal: symmetric cell size");
+  LevelDev& L = f.lv[0];
+  // With 2048 cells or more the launch runs many waves of workgroups and the LDS footprint sets
+  // how many cells are in flight, so the square fits the median cell and the few larger cells
+  // (the last cell of each axis absorbs the extra nodes) read the packed triangle.  With fewer
+  // cells every workgroup is resident at once and the launch lasts as long as its slowest cell,
+  // so every cell gets the square.
+  L.sqn = cells.size() >= 2048 ? sizes[sizes.size() / 2] : maxI;
+  // odd leading dimension: the mirrored stores of consecutive packed elements (consecutive rows
+  // of one column) and the row walks of consecutive lanes fall in different banks
+  L.sqld = L.sqn | 1;
+  // the square or the packed triangle (padded to its storage length), then one spare word that
+  // takes the stores of the storage order's padding slots
+  const int E = (int)(16 / store_elem_bytes(f.store));
+  L.sqmat = (int)((std::max<int64_t>((int64_t)L.sqn * L.sqld, sym_coff(tri_count(maxI))) + 3) /
+                  4 * 4) + 4;
+  const int32_t dump = L.sqmat - 1;
+  // header: the start of each order's entries (16-byte aligned); entries in storage order
+  std::vector<int32_t> tab(kSymTabHead, 0);
+  for (int n = 1; n <= L.sqn; ++n) {
+    tab[n] = (int32_t)tab.size();
+    const int tl = (int)tri_count(n), ns = (tl + E - 1) / E * E;
+    for (int sidx = 0; sidx < ns; ++sidx) {
+      int p = sym_packed_index(sidx, tl, E);
+      if (p >= tl) {
+        tab.push_back(dump | dump << 16);
+        continue;
+      }
+      int j = 0;
+      while (p >= n - j) p -= n - j++;
+      const int i = j + p;
+      tab.push_back((j * L.sqld + i) | (i * L.sqld + j) << 16);
+    }
+    tab.resize((tab.size() + 3) / 4 * 4, 0);
   }
   f.sqtab.upload(tab, s);
 }

@@ -47,6 +47,9 @@ struct LevelDev {
   DevBuf<int32_t> crec, grec, frec;
   int cstride = 0, gstride = 0, fstride = 0;
   int cfwd = 0;  // int32 of each cell record the forward stage reads (descriptor, I, couplings)
+  // symmetric-inverse cells (cmode 2): cells of at most sqn interior DOFs go to an LDS square of
+  // leading dimension sqld (odd), larger ones stay packed; sqmat: LDS elements for either
+  int sqn = 0, sqld = 0, sqmat = 0;
 };
 
 // Stages of one apply, as timed by the profiler.
@@ -110,6 +113,7 @@ struct FactorDev {
   // slots tgslot[i * tkslot ..] (-1: none); ntdt workgroups of row tiles over column ranges of
   // tspan, partial sums in twsc added up by the write-back list tscat.
   int64_t top_budget = -1;  // entries allowed (set before the build; < 0: default)
+  bool skel_edges = false;  // 3D: edges skeletonized as well as faces (set before the build)
   int top = -1, ntop = 0, tspan = 0, ntdt = 0, ntsc = 0, tkslot = 0;
   int64_t top_bytes = 0;
   DevBuf<unsigned char> tvals;
@@ -133,8 +137,10 @@ struct FactorDev {
   int64_t mfma_flops = 0;
   double mfma_ms = 0;
   // symmetric-inverse cells (CellDesc.mode 2): for every interior size n up to the level's
-  // largest, the two LDS square positions (column-major, leading dimension kSymLd) of each
-  // packed element, (j kSymLd + i) | (i kSymLd + j) << 16, from sym_tab_start(n)
+  // square order sqn, the two LDS square positions (column-major, leading dimension sqld) of
+  // per interior order up to sqn (after a header of kSymTabHead starts), in the blocks' storage
+  // order: the two square positions (j sqld + i) | (i sqld + j) << 16 of each element, a spare
+  // word (sqmat - 1, twice) for padding slots
   DevBuf<int32_t> sqtab;
 };
 
@@ -152,7 +158,9 @@ struct BatchArg {
   int32_t stride, len;   // record stride (int32) and the part of it one block reads
   int32_t count;         // cells or groups of the level, or the root's DOFs
   int32_t first;         // first launch block of this solve
-  int32_t blk_elems, team, seg, per_group, staged, pad;
+  int32_t blk_elems, team, seg, per_group, staged;
+  int32_t sqn, sqld, sqmat;  // symmetric cells (LevelDev)
+  int32_t pad;
 };
 enum BatchKind { BK_CELL_FWD_SYM = 0, BK_CELL_FWD = 1, BK_GROUP_FWD = 2, BK_ROOT = 3,
                  BK_GROUP_BWD = 4, BK_CELL_BWD_SYM = 5, BK_CELL_BWD = 6 };
@@ -179,13 +187,21 @@ void run_batch_apply(const BatchApplyPlan& plan, hipStream_t s);
 
 // ---- symmetric-inverse level-0 cells ---------------------------------------------------------
 constexpr int kSymMaxCell = 64;  // largest interior held as A_II^-1 by one wavefront
-constexpr int kSymLd = 65;       // LDS leading dimension of the mirrored square (odd)
-// First table entry of interior size n: sum over m < n of m (m + 1) / 2.
-__host__ __device__ inline int sym_tab_start(int n) { return (n - 1) * n * (n + 1) / 6; }
+// The LDS form of a symmetric cell stage: the table of square positions, the square order, its
+// leading dimension (odd) and the LDS elements reserved for the block (the last one spare).
+struct SymCfg {
+  const int32_t* tab;
+  int n, ld, mat;
+};
+// The table's header: entry n (1 <= n <= SymCfg::n) is where the entries of interior order n
+// start (a multiple of 4).
+constexpr int kSymTabHead = (kSymMaxCell + 1 + 3) / 4 * 4;
 // HIFCN_NO_SYM_CELLS set: level-0 cells keep L^-1 (two triangular products per sweep).
 bool sym_cells_off();
-// Upload f.sqtab for interiors of up to max_n DOFs.
-void build_sym_table(FactorDev& f, int max_n, hipStream_t s);
+// Choose level 0's square order (the median interior size with 2048 cells or more, else the
+// largest), leading dimension and LDS size for
+// its symmetric cells, and upload f.sqtab for interiors of up to that order.
+void build_sym_table(FactorDev& f, const std::vector<CellDesc>& cells, hipStream_t s);
 
 // Host-side, FP64 version of the same layout (used by import; the GPU build writes the device
 // arrays directly with the same descriptors).

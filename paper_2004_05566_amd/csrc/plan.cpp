@@ -104,7 +104,7 @@ void finish_plan(const Geometry& geo, LevelPlan& P) {
   for (int i = 0; i < G; ++i) {
     if (P.groups[i].kind == 0) P.cells.push_back(i);
     else P.seps.push_back(i);
-    if (P.groups[i].kind == 1) P.skel.push_back(i);
+    if (geo.skeletonized(P.groups[i].kind)) P.skel.push_back(i);
   }
   const int st = geo.step(P.level), ns = geo.nsep(P.level);
   P.cellB.assign(P.cells.size(), {});

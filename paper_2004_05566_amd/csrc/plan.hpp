@@ -33,7 +33,7 @@ struct LevelPlan {
   std::vector<PGroup> groups;                 // sorted by key
   std::vector<int> cells;                     // groups of kind 0
   std::vector<int> seps;                      // groups of kind > 0
-  std::vector<int> skel;                      // groups of kind 1 (skeletonized)
+  std::vector<int> skel;                      // skeletonized groups (Geometry::skeletonized)
   std::vector<std::vector<int>> cellB;        // per cell: boundary groups coupled to it
   // dense blocks (g, h) that may be non-zero: every ordered pair inside a cell closure
   std::vector<std::pair<int, int>> blocks;
@@ -59,6 +59,10 @@ struct LevelPlan {
 
 struct Geometry {
   int dim, n, m, L;
+  bool skel_edges = false;  // 3D: edges skeletonized too
+  // Groups that step (3) skeletonizes: kind 1 (2D edges, 3D faces), and 3D edges (kind 2)
+  // with skel_edges.
+  bool skeletonized(int kind) const { return kind == 1 || (skel_edges && dim == 3 && kind == 2); }
   int step(int lev) const { return m << lev; }
   int nsep(int lev) const { return lev >= L ? 0 : (1 << (L - lev)) - 1; }
   void coords(int32_t id, int c[3]) const {  // 1-based (x, y, z)

@@ -53,7 +53,11 @@ class _Info(ctypes.Structure):
 
 
 class _FactorOpts(ctypes.Structure):
-    _fields_ = [("dense_top", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+    _fields_ = [("dense_top", ctypes.c_int64), ("flags", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2)]
+
+
+FACTOR_SKEL_EDGES = 1
 
 
 class _StageProf(ctypes.Structure):
@@ -287,19 +291,21 @@ def cn_batch_step(handles, states, reactions, rtols, maxits, streams):
 
 
 def factor(a_cells, dt: float, n: int, dim: int, eps: float, store: str = "f32",
-           leaf: int = 8, stream=None, dense_top=None) -> Handle:
-    """hif_factor (hif_factor_ex when dense_top is given): build the PHIF factor on the GPU.
+           leaf: int = 8, stream=None, dense_top=None, skel_edges: bool = False) -> Handle:
+    """hif_factor (hif_factor_ex when an option is given): build the PHIF factor on the GPU.
 
-    dense_top: entries allowed for the dense top of the apply (0: none; None: default)."""
+    dense_top: entries allowed for the dense top of the apply (0: none; None: default).
+    skel_edges: 3D, skeletonize the edges of every level as well as its faces."""
     h = ctypes.c_void_p()
     g = _grid(n, dim, leaf)
-    if dense_top is None:
+    if dense_top is None and not skel_edges:
         _check(_lib.hif_factor(_dev_f64(a_cells, "a_cells", _cells_numel(n, dim)), float(dt),
                                ctypes.byref(g),
                                float(eps), STORE[store], _stream(stream), ctypes.byref(h)))
     else:
         o = _FactorOpts()
-        o.dense_top = int(dense_top)
+        o.dense_top = -1 if dense_top is None else int(dense_top)
+        o.flags = FACTOR_SKEL_EDGES if skel_edges else 0
         _check(_lib.hif_factor_ex(_dev_f64(a_cells, "a_cells", _cells_numel(n, dim)), float(dt),
                                   ctypes.byref(g),
                                   float(eps), STORE[store], ctypes.byref(o), _stream(stream),
