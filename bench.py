@@ -68,15 +68,16 @@ def _time_op(fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def _time_replays(fn, reps=100):
-    """Median duration of `fn` over `reps` replays of a HIP graph holding one call of it, each
-    replay bracketed by HIP events on the replay stream; per-call events on the current stream
-    if the call cannot be captured.  Returns (seconds, how)."""
+def _time_replays(fn, reps=100, per=10):
+    """Per-call duration of `fn`: the median over `reps` replays of a HIP graph holding `per`
+    calls of it, each replay bracketed by HIP events on the replay stream, divided by `per` (the
+    graph's own launch cost, ~15 us here, is spread over the calls it holds); per-call events on
+    the current stream if the call cannot be captured.  Returns (seconds, how)."""
     import statistics
 
     import torch
     cur = torch.cuda.current_stream()
-    how = "median of %d hipGraph replays" % reps
+    how = "median of %d hipGraph replays of %d calls, per call" % (reps, per)
     try:
         side = torch.cuda.Stream()
         side.wait_stream(cur)
@@ -86,10 +87,12 @@ def _time_replays(fn, reps=100):
         cur.wait_stream(side)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            fn()
+            for _ in range(per):
+                fn()
         run = g.replay
     except Exception:  # noqa: BLE001 - fall back to plain launches
         torch.cuda.synchronize()
+        per = 1
         run, how = fn, "median of %d calls" % reps
         for _ in range(3):
             fn()
@@ -100,7 +103,7 @@ def _time_replays(fn, reps=100):
         run()
         e1.record()
     torch.cuda.synchronize()
-    return statistics.median(e0.elapsed_time(e1) for e0, e1 in ev) / 1e3, how
+    return statistics.median(e0.elapsed_time(e1) for e0, e1 in ev) / 1e3 / per, how
 
 
 def method_apply_bytes(factor_bytes: int, N: int, dim: int) -> int:

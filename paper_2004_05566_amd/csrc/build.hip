@@ -744,6 +744,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
   // overrides it (tests force either path on small grids)
   int qr_multi = 96;
   if (const char* e = std::getenv("HIFCN_QR_MULTI_MIN")) qr_multi = std::max(1, std::atoi(e));
+  // the one-workgroup ID (k_id) keeps the pivot order of at most 1024 columns in LDS; every
+  // larger ID takes the multi-workgroup QR
+  qr_multi = std::min(qr_multi, 1024);
   auto check_err = [&](const char* where) {
     int e = 0;
     HIF_CHECK(hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1046,7 +1049,6 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       for (size_t q = 0; q < P.skel.size(); ++q) {
         const int g = P.skel[q];
         const int n = gsz(g);
-        HIF_REQUIRE(n <= 1024, HIF_ERR_ARG, "edge/face group larger than 1024 DOFs");
         IdTask t{};
         t.n = n;
         t.offRS = (int32_t)rs.size();

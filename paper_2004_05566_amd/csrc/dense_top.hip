@@ -347,11 +347,11 @@ void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cel
                      const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
   f.top = -1;
   const int nlev = (int)f.lv.size();
-  // entries of M_k: up to ~10M (40 MiB in FP32) one pass over M_k costs less than the launches
-  // it replaces on the 2D workloads, and forming it adds a few ms to the build; larger budgets
-  // still pay off per apply on the 1024^2 grid (level 4 at 40M: -5% apply time) but not over
-  // the 50 steps of a serving request
-  int64_t budget = int64_t(10) << 20;
+  // entries of M_k: up to 40M (160 MiB in FP32, within the 256 MiB Infinity Cache) one pass
+  // over M_k costs less than the launches it replaces (1024^2 grid: level 4 instead of 5, -7%
+  // apply time; 256^2 and 64^3 keep the level a 10M budget gives them).  The serving scheduler
+  // builds without it (forming it costs more than a 50-step request wins back).
+  int64_t budget = int64_t(40) << 20;
   if (const char* e = std::getenv("HIFCN_DENSE_TOP")) budget = std::atoll(e);
   if (f.top_budget >= 0) budget = f.top_budget;
   if (budget <= 0 || nlev == 0 || f.nroot == 0) return;

@@ -38,13 +38,45 @@ constexpr int kThreads = 256;  // 4 wavefronts; wave w owns the 32 x 32 quadrant
 
 __device__ __forceinline__ int64_t front_ld(const FrontTask& t) { return t.nI + t.nB; }
 
-// Stage rows [0, rows) x columns [0, kv) of src (leading dimension ld) into S (64 x kKc,
-// stride kLd), zero elsewhere.
-__device__ __forceinline__ void stage(double* S, const double* src, int64_t ld, int rows, int kv) {
-  for (int e = threadIdx.x; e < kT * kKc; e += kThreads) {
-    const int r = e / kKc, c = e - r * kKc;
-    S[r * kLd + c] = (r < rows && c < kv) ? src[(int64_t)r * ld + c] : 0.0;
+// A 64 x kKc chunk of an operand on its way to LDS: each thread holds 8 of its elements, so a
+// chunk's global loads can be issued while the matrix cores work on the previous chunk.
+struct Chunk {
+  double v[kT * kKc / kThreads];
+};
+constexpr int kChunkPer = kT * kKc / kThreads;
+
+// Rows [0, rows) x columns [0, kv) of src (leading dimension ld), zero elsewhere; thread t holds
+// row t / kKc + 8 u, column t % kKc (32 consecutive lanes read one row segment).
+__device__ __forceinline__ void load_chunk(Chunk& R, const double* src, int64_t ld, int rows,
+                                           int kv) {
+  const int c = threadIdx.x % kKc, r0 = threadIdx.x / kKc;
+#pragma unroll
+  for (int u = 0; u < kChunkPer; ++u) {
+    const int r = r0 + (kThreads / kKc) * u;
+    R.v[u] = (r < rows && c < kv) ? src[(int64_t)r * ld + c] : 0.0;
   }
+}
+// Rows [0, kv) x columns [0, cols) of src, to be stored transposed; thread t holds row
+// t / kT + 4 u, column t % kT.
+__device__ __forceinline__ void load_chunk_t(Chunk& R, const double* src, int64_t ld, int kv,
+                                             int cols) {
+  const int j = threadIdx.x % kT, k0 = threadIdx.x / kT;
+#pragma unroll
+  for (int u = 0; u < kChunkPer; ++u) {
+    const int k = k0 + (kThreads / kT) * u;
+    R.v[u] = (k < kv && j < cols) ? src[(int64_t)k * ld + j] : 0.0;
+  }
+}
+// The chunk into S (64 x kKc, stride kLd): as loaded, or transposed (S[j][k] = src[k][j]).
+__device__ __forceinline__ void store_chunk(double* S, const Chunk& R) {
+  const int c = threadIdx.x % kKc, r0 = threadIdx.x / kKc;
+#pragma unroll
+  for (int u = 0; u < kChunkPer; ++u) S[(r0 + (kThreads / kKc) * u) * kLd + c] = R.v[u];
+}
+__device__ __forceinline__ void store_chunk_t(double* S, const Chunk& R) {
+  const int j = threadIdx.x % kT, k0 = threadIdx.x / kT;
+#pragma unroll
+  for (int u = 0; u < kChunkPer; ++u) S[j * kLd + k0 + (kThreads / kT) * u] = R.v[u];
 }
 
 // acc += As (64 x kKc) * Bs (64 x kKc)^T.  MFMA 16x16x4 FP64 operands: lane l holds A[l%16][l/16]
@@ -74,17 +106,29 @@ __device__ __forceinline__ void acc_pos(int a, int b, int r, int* row, int* col)
   *col = 32 * (w & 1) + 16 * b + (lane & 15);
 }
 
-// acc = A (rows x K) * B (cols x K)^T over k in [k_begin, k_end), both row-major with ld.
+// acc = A (rows x K) * B (cols x K)^T over k in [k_begin, k_end), both row-major with ld.  The
+// next chunk's loads are in flight while the matrix cores multiply the current one.
 __device__ void tile_nt(const double* A, const double* B, int64_t ld, int rows, int cols,
                         int k_begin, int k_end, d4 acc[2][2]) {
   __shared__ double As[kT * kLd], Bs[kT * kLd];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  Chunk ra, rb;
+  if (k_begin < k_end) {
+    const int kv = min(kKc, k_end - k_begin);
+    load_chunk(ra, A + k_begin, ld, rows, kv);
+    load_chunk(rb, B + k_begin, ld, cols, kv);
+  }
   for (int k0 = k_begin; k0 < k_end; k0 += kKc) {
-    const int kv = min(kKc, k_end - k0);
-    stage(As, A + k0, ld, rows, kv);
-    stage(Bs, B + k0, ld, cols, kv);
+    store_chunk(As, ra);
+    store_chunk(Bs, rb);
     __syncthreads();
+    const int k1 = k0 + kKc;
+    if (k1 < k_end) {
+      const int kv = min(kKc, k_end - k1);
+      load_chunk(ra, A + k1, ld, rows, kv);
+      load_chunk(rb, B + k1, ld, cols, kv);
+    }
     mfma_chunk(As, Bs, acc);
     __syncthreads();
   }
@@ -221,11 +265,18 @@ __global__ __launch_bounds__(kThreads) void k_front_panel(const FrontTask* __res
   __shared__ double As[kT * kLd], Bs[kT * kLd];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  Chunk ra, rb;
+  load_chunk(ra, Fr, ld, rows, min(kKc, w));
+  load_chunk(rb, D + t.offD, kT, kT, min(kKc, w));
   for (int k0 = 0; k0 < w; k0 += kKc) {
-    const int kv = min(kKc, w - k0);
-    stage(As, Fr + k0, ld, rows, kv);
-    stage(Bs, D + t.offD + k0, kT, kT, kv);
+    store_chunk(As, ra);
+    store_chunk(Bs, rb);
     __syncthreads();
+    const int k1 = k0 + kKc;
+    if (k1 < w) {
+      load_chunk(ra, Fr + k1, ld, rows, min(kKc, w - k1));
+      load_chunk(rb, D + t.offD + k1, kT, kT, min(kKc, w - k1));
+    }
     mfma_chunk(As, Bs, acc);
     __syncthreads();
   }
@@ -310,14 +361,6 @@ __global__ __launch_bounds__(kThreads) void k_front_h(const FrontTask* __restric
       }
 }
 
-// Stage rows [0, kv) x columns [0, cols) of src (row-major, ld) transposed: S[j][k] = src[k][j].
-__device__ __forceinline__ void stage_t(double* S, const double* src, int64_t ld, int kv,
-                                        int cols) {
-  for (int e = threadIdx.x; e < kT * kKc; e += kThreads) {
-    const int k = e / kT, j = e - k * kT;
-    S[j * kLd + k] = (k < kv && j < cols) ? src[(int64_t)k * ld + j] : 0.0;
-  }
-}
 
 // One 64 x 64 tile (task, first row, first column) of a batched product.
 __global__ __launch_bounds__(kThreads) void k_gemm_tiles(const GemmTask* __restrict__ tasks,
@@ -334,13 +377,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tiles(const GemmTask* __restr
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kbeg; k0 < kend; k0 += kKc) {
+  // the operands of chunk k0 into registers (A transposed when ta, B when not nt)
+  Chunk ra, rb;
+  auto load = [&](int k0) {
     const int kv = min(kKc, kend - k0);
-    if (t.ta) stage_t(As, t.A + (int64_t)k0 * t.lda + r0, t.lda, kv, rows);
-    else stage(As, t.A + (int64_t)r0 * t.lda + k0, t.lda, rows, kv);
-    if (t.nt) stage(Bs, t.B + (int64_t)c0 * t.ldb + k0, t.ldb, cols, kv);
-    else stage_t(Bs, t.B + (int64_t)k0 * t.ldb + c0, t.ldb, kv, cols);
+    if (t.ta) load_chunk_t(ra, t.A + (int64_t)k0 * t.lda + r0, t.lda, kv, rows);
+    else load_chunk(ra, t.A + (int64_t)r0 * t.lda + k0, t.lda, rows, kv);
+    if (t.nt) load_chunk(rb, t.B + (int64_t)c0 * t.ldb + k0, t.ldb, cols, kv);
+    else load_chunk_t(rb, t.B + (int64_t)k0 * t.ldb + c0, t.ldb, kv, cols);
+  };
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kKc) {
+    if (t.ta) store_chunk_t(As, ra);
+    else store_chunk(As, ra);
+    if (t.nt) store_chunk(Bs, rb);
+    else store_chunk_t(Bs, rb);
     __syncthreads();
+    if (k0 + kKc < kend) load(k0 + kKc);  // in flight during the products below
     mfma_chunk(As, Bs, acc);
     __syncthreads();
   }

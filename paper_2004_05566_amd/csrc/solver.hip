@@ -19,6 +19,10 @@
 #include "cg_gate.hpp"
 #include "stencil.hpp"
 
+#include <cstdint>
+#include <cstdlib>
+#include <initializer_list>
+
 namespace hifcn {
 
 namespace {
@@ -120,6 +124,37 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, int64_t N, const doubl
 }
 
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD b mod 8), each XCD
+// with its own L2.  The stencil kernels give each XCD a contiguous run of chunks instead, so the
+// rows above and below a chunk are mostly read through the same L2 (a bijection of [0, nb)).
+__device__ __forceinline__ int xcd_chunk(int b, int nb) {
+  const int per = nb / 8;
+  return b < 8 * per ? (b % 8) * per + b / 8 : b;
+}
+
+// y = A x over x-pairs of nodes (n even): one 16-byte load of the pair, of each neighbouring
+// pair across y (and z) and of the pair's y (z) link weights, instead of one load per node and
+// neighbour.  Each node's value is the arithmetic of link_sum_at.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_spmv_pairs(int n, int64_t N,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ y) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  const double2* x2 = reinterpret_cast<const double2*>(x);
+  double2* y2 = reinterpret_cast<double2*>(y);
+  auto X = [&](int64_t k) { return x[k]; };
+  auto X2 = [&](int64_t k) { return x2[k >> 1]; };
+  for (NodeWalk<DIM> a(2 * (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kThreads + threadIdx.x),
+                          2 * stride, n);
+       a.i < N; a.next(n)) {
+    const double2 v = x2[a.i >> 1];
+    double s0, s1;
+    link_sum_pair<DIM>(a.i, a.ix, a.iy, a.iz, n, w, v, X, X2, s0, s1);
+    y2[a.i >> 1] = double2{v.x + s0, v.y + s1};
+  }
+}
+
 // Partial-sum slots (each nblk long): ||g||^2, ||r||^2, and the direction kernel's r.z, z.w, z.q.
 enum { P_GG = 0, P_RR = 1, P_RZ = 2, P_ZW = 3, P_ZQ = 4, P_SLOTS = 5 };
 
@@ -171,6 +206,39 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
     r[i] = g;
     x[i] = 0.0;
     acc += g * g;
+  }
+  put_partial(acc, part + P_GG * (int64_t)gridDim.x);
+}
+
+// k_cg_rhs over x-pairs of nodes (n even; see k_spmv_pairs): the same g at every node.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_cg_rhs_pairs(int n, int64_t N,
+                                                           const double* __restrict__ w,
+                                                           const double* __restrict__ u,
+                                                           double* __restrict__ r,
+                                                           double* __restrict__ x, int kind,
+                                                           double k1, double k2, double dt,
+                                                           int ahead, CgState* st, double* part) {
+  const bool held = ahead && (!st->done || st->status);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->hold = held ? 1 : 0;
+  if (held) return;
+  double acc = 0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  const double2* u2 = reinterpret_cast<const double2*>(u);
+  auto U = [&](int64_t k) { return u[k]; };
+  auto U2 = [&](int64_t k) { return u2[k >> 1]; };
+  for (NodeWalk<DIM> a(2 * (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kThreads + threadIdx.x),
+                          2 * stride, n);
+       a.i < N; a.next(n)) {
+    const double2 v = u2[a.i >> 1];
+    double s0, s1;
+    link_sum_pair<DIM>(a.i, a.ix, a.iy, a.iz, n, w, v, U, U2, s0, s1);
+    const double g0 = cn_rhs_value(v.x, s0, dt, kind, k1, k2);
+    const double g1 = cn_rhs_value(v.y, s1, dt, kind, k1, k2);
+    reinterpret_cast<double2*>(r)[a.i >> 1] = double2{g0, g1};
+    reinterpret_cast<double2*>(x)[a.i >> 1] = double2{0.0, 0.0};
+    acc += g0 * g0;
+    acc += g1 * g1;
   }
   put_partial(acc, part + P_GG * (int64_t)gridDim.x);
 }
@@ -319,6 +387,47 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int 
     one(b, zb, rb, qb);
   }
   if (a.i < N) one(a, z[a.i], r[a.i], it > 0 ? q[a.i] : 0.0);
+  block_sum3(rz, zw, zq);
+  if (threadIdx.x == 0) {
+    part[P_RZ * (int64_t)nb + blockIdx.x] = rz;
+    part[P_ZW * (int64_t)nb + blockIdx.x] = zw;
+    part[P_ZQ * (int64_t)nb + blockIdx.x] = zq;
+  }
+}
+
+// k_cg_dir_dots over x-pairs of nodes (n even; see k_spmv_pairs).
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_cg_dir_dots_pairs(int n, int64_t N, int it,
+                                                                const double* __restrict__ lw,
+                                                                const double* __restrict__ z,
+                                                                const double* __restrict__ r,
+                                                                const double* __restrict__ q,
+                                                                double* __restrict__ w,
+                                                                double* part) {
+  const int nb = gridDim.x;
+  double rz = 0, zw = 0, zq = 0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  const double2* z2 = reinterpret_cast<const double2*>(z);
+  auto Z = [&](int64_t k) { return z[k]; };
+  auto Z2 = [&](int64_t k) { return z2[k >> 1]; };
+  for (NodeWalk<DIM> a(2 * (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kThreads + threadIdx.x),
+                          2 * stride, n);
+       a.i < N; a.next(n)) {
+    const int64_t h = a.i >> 1;
+    const double2 zv = z2[h];
+    const double2 rv = reinterpret_cast<const double2*>(r)[h];
+    const double2 qv = it > 0 ? reinterpret_cast<const double2*>(q)[h] : double2{0.0, 0.0};
+    double s0, s1;
+    link_sum_pair<DIM>(a.i, a.ix, a.iy, a.iz, n, lw, zv, Z, Z2, s0, s1);
+    const double w0 = zv.x + s0, w1 = zv.y + s1;
+    reinterpret_cast<double2*>(w)[h] = double2{w0, w1};
+    rz += rv.x * zv.x;
+    rz += rv.y * zv.y;
+    zw += zv.x * w0;
+    zw += zv.y * w1;
+    zq += zv.x * qv.x;
+    zq += zv.y * qv.y;
+  }
   block_sum3(rz, zw, zq);
   if (threadIdx.x == 0) {
     part[P_RZ * (int64_t)nb + blockIdx.x] = rz;
@@ -605,7 +714,24 @@ void launch_links(const double* a_cells, int dim, int n, double scale, double* l
   HIF_CHECK(hipGetLastError());
 }
 
+// The stencil kernels take x-pairs of nodes where n is even and the vectors are 16-byte aligned
+// (HIFCN_NO_PAIRS=1: one node per lane everywhere).
+bool use_pairs(const Handle& h, std::initializer_list<const void*> vecs) {
+  static const bool off = std::getenv("HIFCN_NO_PAIRS") != nullptr;
+  if (off || h.n % 2 != 0) return false;
+  for (const void* p : vecs)
+    if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return false;
+  return true;
+}
+
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
+  if (use_pairs(h, {x, y})) {
+    const int nb = (int)std::min<int64_t>((h.N / 2 + kThreads - 1) / kThreads, 4096);
+    auto k = h.dim == 2 ? k_spmv_pairs<2> : k_spmv_pairs<3>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(kThreads), 0, s, h.n, h.N, h.links.p, x, y);
+    HIF_CHECK(hipGetLastError());
+    return;
+  }
   const int nb = (int)std::min<int64_t>((h.N + kThreads - 1) / kThreads, 4096);
   if (h.dim == 2)
     hipLaunchKernelGGL(k_spmv<2>, dim3(nb), dim3(kThreads), 0, s, h.n, h.N, h.links.p, x, y);
@@ -616,7 +742,8 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
 
 void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, bool ahead,
                    hipStream_t s) {
-  auto k = h.dim == 2 ? k_cg_rhs<2> : k_cg_rhs<3>;
+  auto k = use_pairs(h, {u, h.r.p, h.x.p}) ? (h.dim == 2 ? k_cg_rhs_pairs<2> : k_cg_rhs_pairs<3>)
+                        : (h.dim == 2 ? k_cg_rhs<2> : k_cg_rhs<3>);
   hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, u, h.r.p, h.x.p,
                      kind, k1, k2, h.dt, ahead ? 1 : 0, h.st.p, h.partials.p);
 }
@@ -651,7 +778,9 @@ CgGate cg_gate_args(Handle& h, int it, double rtol, int maxit) {
 }
 
 void launch_cg_dir_dots(Handle& h, int it, hipStream_t s) {
-  auto k = h.dim == 2 ? k_cg_dir_dots<2> : k_cg_dir_dots<3>;
+  auto k = use_pairs(h, {h.z.p, h.r.p, h.q.p, h.w.p})
+               ? (h.dim == 2 ? k_cg_dir_dots_pairs<2> : k_cg_dir_dots_pairs<3>)
+                        : (h.dim == 2 ? k_cg_dir_dots<2> : k_cg_dir_dots<3>);
   hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, it, h.links.p, h.z.p, h.r.p,
                      h.q.p, h.w.p, h.partials.p);
 }

@@ -13,6 +13,21 @@
 
 namespace hifcn {
 
+// Sum over the links of a node of w (p_i - p_nbr) from the values at hand: the x links (l, r),
+// the y links (d, u) and, in 3D, the z links (b, f), in that order.
+template <int DIM>
+__device__ __forceinline__ double link_sum_vals(double pi, double pl, double pr, double wl,
+                                                double wr, double pd, double pu, double wd,
+                                                double wu, double pb = 0, double pf = 0,
+                                                double wb = 0, double wf = 0) {
+#pragma clang fp contract(off)
+  double acc = 0;
+  acc += wl * (pi - pl) + wr * (pi - pr);
+  acc += wd * (pi - pd) + wu * (pi - pu);
+  if (DIM == 3) acc += wb * (pi - pb) + wf * (pi - pf);
+  return acc;
+}
+
 // Sum over the links of node i = (ix, iy, iz) of w (p_i - p_nbr).  P(k) returns the value at
 // node k; neighbours beyond the boundary are the Dirichlet zeros.
 // Contraction into fused multiply-adds is off here and in cn_rhs_value: the value of a node must
@@ -21,32 +36,61 @@ namespace hifcn {
 template <int DIM, typename P>
 __device__ __forceinline__ double link_sum_at(int64_t i, int ix, int iy, int iz, int n,
                                               const double* __restrict__ w, double pi, P pv) {
-#pragma clang fp contract(off)
   const int64_t n1 = n + 1;
   const int64_t nn = (int64_t)n * n;
-  double acc = 0;
-  {  // x links
-    const int64_t row = DIM == 3 ? (int64_t)iz * n + iy : iy;
-    const double* wx = w + row * n1 + ix;
-    const double pl = ix > 0 ? pv(i - 1) : 0.0;
-    const double pr = ix < n - 1 ? pv(i + 1) : 0.0;
-    acc += wx[0] * (pi - pl) + wx[1] * (pi - pr);
-  }
-  {  // y links
-    const int64_t lx = (DIM == 3 ? nn : (int64_t)n) * n1;
-    const int64_t b = DIM == 3 ? ((int64_t)iz * n1 + iy) * n + ix : (int64_t)iy * n + ix;
-    const double* wy = w + lx + b;
-    const double pl = iy > 0 ? pv(i - n) : 0.0;
-    const double pr = iy < n - 1 ? pv(i + n) : 0.0;
-    acc += wy[0] * (pi - pl) + wy[n] * (pi - pr);
-  }
-  if (DIM == 3) {  // z links
+  const int64_t row = DIM == 3 ? (int64_t)iz * n + iy : iy;
+  const double* wx = w + row * n1 + ix;
+  const double pl = ix > 0 ? pv(i - 1) : 0.0;
+  const double pr = ix < n - 1 ? pv(i + 1) : 0.0;
+  const int64_t lx = (DIM == 3 ? nn : (int64_t)n) * n1;
+  const int64_t b = DIM == 3 ? ((int64_t)iz * n1 + iy) * n + ix : (int64_t)iy * n + ix;
+  const double* wy = w + lx + b;
+  const double pd = iy > 0 ? pv(i - n) : 0.0;
+  const double pu = iy < n - 1 ? pv(i + n) : 0.0;
+  if (DIM == 3) {
     const double* wz = w + 2 * nn * n1 + i;
-    const double pl = iz > 0 ? pv(i - nn) : 0.0;
-    const double pr = iz < n - 1 ? pv(i + nn) : 0.0;
-    acc += wz[0] * (pi - pl) + wz[nn] * (pi - pr);
+    const double pb = iz > 0 ? pv(i - nn) : 0.0;
+    const double pf = iz < n - 1 ? pv(i + nn) : 0.0;
+    return link_sum_vals<3>(pi, pl, pr, wx[0], wx[1], pd, pu, wy[0], wy[n], pb, pf, wz[0],
+                            wz[nn]);
   }
-  return acc;
+  return link_sum_vals<2>(pi, pl, pr, wx[0], wx[1], pd, pu, wy[0], wy[n]);
+}
+
+// The link sums of the two nodes i, i + 1 of an x-pair (n even, i and ix even, so the pair is
+// in one row and every pair-wide load is 16-byte aligned): (s0, s1), each as link_sum_at forms
+// it.  v = (p_i, p_{i+1}); P(k) and P2(k) return the value at node k and the pair at k, k + 1.
+template <int DIM, typename P, typename P2>
+__device__ __forceinline__ void link_sum_pair(int64_t i, int ix, int iy, int iz, int n,
+                                              const double* __restrict__ w, double2 v, P pv,
+                                              P2 pv2, double& s0, double& s1) {
+  const int64_t n1 = n + 1;
+  const int64_t nn = (int64_t)n * n;
+  const double2 zero{0.0, 0.0};
+  const int64_t row = DIM == 3 ? (int64_t)iz * n + iy : iy;
+  const double* wx = w + row * n1 + ix;
+  const double wx0 = wx[0], wx1 = wx[1], wx2 = wx[2];
+  const double pl = ix > 0 ? pv(i - 1) : 0.0;
+  const double pr = ix + 2 < n ? pv(i + 2) : 0.0;
+  const int64_t lx = (DIM == 3 ? nn : (int64_t)n) * n1;
+  const int64_t b = DIM == 3 ? ((int64_t)iz * n1 + iy) * n + ix : (int64_t)iy * n + ix;
+  const double2 wd = *reinterpret_cast<const double2*>(w + lx + b);
+  const double2 wu = *reinterpret_cast<const double2*>(w + lx + b + n);
+  const double2 pd = iy > 0 ? pv2(i - n) : zero;
+  const double2 pu = iy < n - 1 ? pv2(i + n) : zero;
+  if (DIM == 3) {
+    const double2 wb = *reinterpret_cast<const double2*>(w + 2 * nn * n1 + i);
+    const double2 wf = *reinterpret_cast<const double2*>(w + 2 * nn * n1 + i + nn);
+    const double2 pb = iz > 0 ? pv2(i - nn) : zero;
+    const double2 pf = iz < n - 1 ? pv2(i + nn) : zero;
+    s0 = link_sum_vals<3>(v.x, pl, v.y, wx0, wx1, pd.x, pu.x, wd.x, wu.x, pb.x, pf.x, wb.x,
+                          wf.x);
+    s1 = link_sum_vals<3>(v.y, v.x, pr, wx1, wx2, pd.y, pu.y, wd.y, wu.y, pb.y, pf.y, wb.y,
+                          wf.y);
+  } else {
+    s0 = link_sum_vals<2>(v.x, pl, v.y, wx0, wx1, pd.x, pu.x, wd.x, wu.x);
+    s1 = link_sum_vals<2>(v.y, v.x, pr, wx1, wx2, pd.y, pu.y, wd.y, wu.y);
+  }
 }
 
 // link_sum_at for a node given only by its index (N < 2^31: 32-bit division).
