@@ -373,55 +373,67 @@ __host__ __device__ inline int sym_smem_elems(int mat, int maxB) {
 }
 
 // Every element of the cell block into LDS: to both of its square positions (tab: this order's
-// entries, in storage order) or, with tab null, to its packed position.  All loads are issued
-// before the first store.  A block starts 16-byte aligned and its storage runs to sym_coff(tl),
-// so every vector lies inside it; the spare slots of the last chunk land on the spare word (tab)
-// or below the packed triangle's padded end (no tab), where nothing reads them.
-template <typename S, typename C>
-__device__ __forceinline__ void sym_stage(C* sq, const S* __restrict__ v, int tl,
-                                          const int32_t* __restrict__ tab, int lane) {
-  constexpr int E = 16 / sizeof(S);                      // elements per vector
-  constexpr int kTri = kSymMaxCell * (kSymMaxCell + 1) / 2;
-  constexpr int P = (kTri + 64 * E - 1) / (64 * E);      // vectors per lane (chunks)
-  const int4* vv = reinterpret_cast<const int4*>(v);
-  const int nv = (tl + E - 1) / E;
+// entries, in storage order) or, with tab null, to its packed position.  sym_load issues the
+// loads (so that a stage can issue its other loads before it waits for them) and sym_store
+// makes the stores.  A block starts 16-byte aligned and its storage runs to sym_coff(tl), so
+// every vector lies inside it; the spare slots of the last chunk land on the spare word (tab) or
+// below the packed triangle's padded end (no tab), where nothing reads them.
+template <typename S>
+struct SymRegs {
+  static constexpr int E = 16 / sizeof(S);  // elements per vector
+  static constexpr int P =                  // vectors per lane (chunks)
+      (kSymMaxCell * (kSymMaxCell + 1) / 2 + 64 * E - 1) / (64 * E);
   int4 e[P];
   int32_t t[P][E];
+};
+
+template <typename S>
+__device__ __forceinline__ void sym_load(SymRegs<S>& R, const S* __restrict__ v, int tl,
+                                         const int32_t* __restrict__ tab, int lane) {
+  constexpr int E = SymRegs<S>::E, P = SymRegs<S>::P;
+  const int4* vv = reinterpret_cast<const int4*>(v);
+  const int nv = (tl + E - 1) / E;
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     const int q = lane + 64 * u;
     if (q < nv) {
-      e[u] = vv[q];
+      R.e[u] = vv[q];
       if (tab) {
         if constexpr (E == 2) {
           const int2 w = reinterpret_cast<const int2*>(tab)[q];
-          t[u][0] = w.x;
-          t[u][1] = w.y;
+          R.t[u][0] = w.x;
+          R.t[u][1] = w.y;
         } else {
 #pragma unroll
           for (int h = 0; h < E / 4; ++h) {
             const int4 w = reinterpret_cast<const int4*>(tab)[q * (E / 4) + h];
-            t[u][4 * h] = w.x;
-            t[u][4 * h + 1] = w.y;
-            t[u][4 * h + 2] = w.z;
-            t[u][4 * h + 3] = w.w;
+            R.t[u][4 * h] = w.x;
+            R.t[u][4 * h + 1] = w.y;
+            R.t[u][4 * h + 2] = w.z;
+            R.t[u][4 * h + 3] = w.w;
           }
         }
       }
     }
   }
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void sym_store(C* sq, const SymRegs<S>& R, int tl, bool tab, int lane) {
+  constexpr int E = SymRegs<S>::E, P = SymRegs<S>::P;
+  const int nv = (tl + E - 1) / E;
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     const int q = lane + 64 * u;
     if (q < nv) {
       S ev[E];
-      __builtin_memcpy(ev, &e[u], 16);
+      __builtin_memcpy(ev, &R.e[u], 16);
       if (tab) {
 #pragma unroll
         for (int k = 0; k < E; ++k) {
           const C x = load_as<C>(ev + k);
-          sq[t[u][k] & 0xffff] = x;
-          sq[t[u][k] >> 16] = x;
+          sq[R.t[u][k] & 0xffff] = x;
+          sq[R.t[u][k] >> 16] = x;
         }
       } else {
         const int qc = sym_chunk_q(u, tl, E);  // packed element lane + qc k of chunk u
@@ -504,21 +516,31 @@ __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* _
   const S* v = vals + d.offV;
   const int32_t* gI = idx + d.offI;
   const int32_t* ibp = idx + d.offC;
+  const S* cw = v + sym_coff(tl);  // the couplings
+  // loads in order of need: the interior ids, the block, the inputs, the first couplings
   int gi = -1;
+  if (!own_ys && lane < nI) gi = gI[lane];
+  const bool square = nI <= cfg.n;
+  SymRegs<S> R;
+  sym_load<S>(R, v, tl, square ? cfg.tab + cfg.tab[nI] : nullptr, lane);
   double yv = 0;
-  if (!own_ys && lane < nI) {
-    gi = gI[lane];
-    yv = src[gi];
+  if (!own_ys && lane < nI) yv = src[gi];
+  int ib0 = 0;
+  C a0 = 0;
+  if (lane < nB) {
+    ib0 = ibp[lane];
+    a0 = load_as<C>(cw + lane);
   }
-  sym_stage<S, C>(sq, v, tl, nI <= cfg.n ? cfg.tab + cfg.tab[nI] : nullptr, lane);
+  sym_store<S, C>(sq, R, tl, square, lane);
   if (!own_ys) ts[lane] = (C)yv;
   hook(ts);
   __syncthreads();
   if (stop && *stop) return;
   if (lane < nI) zs[lane] = sym_apply(sq, ts, nI, cfg, lane);
   __syncthreads();
-  for (int b = lane; b < nB; b += 64)
-    cb[d.offCB + b] = (double)(load_as<C>(v + sym_coff(tl) + b) * zs[ibp[b]]);
+  if (lane < nB) cb[d.offCB + lane] = (double)(a0 * zs[ib0]);
+  for (int b = lane + 64; b < nB; b += 64)
+    cb[d.offCB + b] = (double)(load_as<C>(cw + b) * zs[ibp[b]]);
   if (in && in != y && lane < nI) y[gi] = yv;  // the output takes the inputs at the interiors
 }
 
@@ -539,12 +561,13 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
   const S* v = vals + d.offV;
   const int32_t* gI = idx + d.offI;
   const int32_t* gB = idx + d.offB;
-  const int32_t* rp = idx + d.offC + nB;
-  const int32_t* bl = rp + nI + 1;
-  int gi = -1;
+  const int32_t* lw = idx + d.offC + nB;  // per interior DOF: link count, boundary positions
+  // the ids and link words, the gathers, then the block
+  int gi = -1, w = 0;
   double xi = 0;
   if (lane < nI) {
     gi = gI[lane];
+    w = lw[lane];
     xi = x[gi];
   }
   for (int b = lane; b < nB; b += 64) {
@@ -560,12 +583,16 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
   }
   if (top.pos)
     for (int e = lane; e < top.ne; e += 64) x[top.ext[2 * e + 1]] = top.sum(top.ext[2 * e]);
-  sym_stage<S, C>(sq, v, tl, nI <= cfg.n ? cfg.tab + cfg.tab[nI] : nullptr, lane);
+  const bool square = nI <= cfg.n;
+  SymRegs<S> R;
+  sym_load<S>(R, v, tl, square ? cfg.tab + cfg.tab[nI] : nullptr, lane);
+  sym_store<S, C>(sq, R, tl, square, lane);
   __syncthreads();
   if (lane < nI) {
     C t = (C)xi;
-    for (int q = rp[lane]; q < rp[lane + 1]; ++q) {
-      const int b = bl[q];
+    const int cnt = w & 255;
+    for (int q = 0; q < cnt; ++q) {
+      const int b = (w >> (8 * (q + 1))) & 255;
       t -= abs_[b] * xbs[b];
     }
     ts[lane] = t;
@@ -667,6 +694,9 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
                              smem_raw, gred, sym, flen);
     return;
   }
+  // symmetric cells read their record in place (global memory) and keep all of LDS for the
+  // block; the other modes copy it to the front of LDS first
+  const int32_t* grec = recs + (int64_t)blockIdx.x * stride;
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   // with a gate, the PCG convergence test comes first: its partials, the state and this
   // cell's copy list load ahead of the record
@@ -685,12 +715,12 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
     ccnt = cp[0];
     if ((int)threadIdx.x < gcstride - 1) cid = cp[1 + threadIdx.x];
   }
-  load_record(rec, recs + (int64_t)blockIdx.x * stride, flen, threadIdx.x, blockDim.x);
+  if constexpr (MODE != 2) load_record(rec, grec, flen, threadIdx.x, blockDim.x);
   const int dn = gated ? 0 : (done ? *done : 0);
   if (gated && cid >= 0) cval = gate.src[cid];  // (padding entries read DOF 0; never stored)
-  __syncthreads();
+  if constexpr (MODE != 2) __syncthreads();
   if (dn) return;
-  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(MODE == 2 ? grec : rec);
   // the test's verdict is reached while the cell's block and inputs load (they are only read
   // before it is known)
   auto verdict = [&](C*) {
@@ -706,7 +736,7 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
     }
   };
   if constexpr (MODE == 2)
-    cell_fwd_sym<S, C>(d, rec, vals, y, cb, sym, smem_raw + 4 * stride, gate.src, verdict,
+    cell_fwd_sym<S, C>(d, grec, vals, y, cb, sym, smem_raw, gate.src, verdict,
                        gated ? &gstop : nullptr);
   else
     cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
@@ -832,19 +862,21 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
                                                   int tstride, const double* __restrict__ tpart,
                                                   int tnch, int tn, SymCfg sym) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // symmetric cells read their record in place (see k_cell_fwd)
+  const int32_t* grec = recs + (int64_t)blockIdx.x * stride;
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
-  load_record(rec, recs + (int64_t)blockIdx.x * stride, stride, threadIdx.x, blockDim.x);
+  if constexpr (MODE != 2) load_record(rec, grec, stride, threadIdx.x, blockDim.x);
   const int dn = done ? *done : 0;
-  __syncthreads();
+  if constexpr (MODE != 2) __syncthreads();
   if (dn) return;
-  const CellDesc d = *reinterpret_cast<const CellDesc*>(rec);
+  const CellDesc d = *reinterpret_cast<const CellDesc*>(MODE == 2 ? grec : rec);
   TopIn top;
   if (tpos) {  // per cell: ne, (position, id) x ne, then one position per boundary DOF
     const int32_t* r = tpos + (int64_t)blockIdx.x * tstride;
     top = TopIn{r + tstride - d.nB, r + 1, r[0], tpart, tnch, tn};
   }
   if constexpr (MODE == 2)
-    cell_bwd_sym<S, C>(d, rec, vals, x, sym, smem_raw + 4 * stride, top);
+    cell_bwd_sym<S, C>(d, grec, vals, x, sym, smem_raw, top);
   else
     cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride, top);
 }
@@ -862,12 +894,12 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
                                                const S* __restrict__ vals,
                                                double* __restrict__ y,
                                                const double* __restrict__ cb,
-                                               unsigned char* smem_raw) {
+                                               unsigned char* smem_raw, bool dense = false) {
   const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
-  const int n = d.n, nr = d.nr, k = n - nr;
+  const int n = d.n, nr = dense ? 0 : d.nr, k = n - nr;
   C* base = reinterpret_cast<C*>(smem_raw) + (int64_t)gsel * per_group;
   const S* v = vals + d.offV;
-  const int tg = tri_count(n), tt = k * nr, tr = tri_count(nr);
+  const int tg = dense ? n * n : tri_count(n), tt = k * nr, tr = tri_count(nr);
   C* blk = base;
   C* yg = ST ? base + blk_elems : base;
   C* zg = yg + n;
@@ -896,6 +928,17 @@ __device__ __forceinline__ void group_fwd_body(const GroupDesc& d, int seg, int 
   __syncthreads();
   // Every product is split over `team` adjacent lanes per output.
   const int part = lt % team, per_t = seg / team;
+  if (dense) {  // the whole step at once: y_g = G (y_g - contributions)
+    const Col<S, C, ST> G{blk, v, n};
+    for (int ob = 0; ob < n; ob += per_t) {
+      const int i = ob + lt / team;
+      C acc = 0;
+      if (i < n) acc = G.row_dot(i, part, n, team, [&](int j) { return yg[j]; });
+      acc = team_sum(acc, team);
+      if (part == 0 && i < n) y[gi_idx[i]] = (double)acc;
+    }
+    return;
+  }
   for (int ob = 0; ob < n; ob += per_t) {    // C^T: z = L_g^-1 y_g
     const int i = ob + lt / team;
     C acc = 0;
@@ -956,7 +999,7 @@ __global__ __launch_bounds__(256) void k_group_fwd(const int32_t* __restrict__ r
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ y,
                                                    const double* __restrict__ cb,
-                                                   const int* __restrict__ done) {
+                                                   const int* __restrict__ done, int gdense) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int per = blockDim.x / seg, g0 = blockIdx.x * per, cnt = min(per, ngroup - g0);
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
@@ -969,7 +1012,7 @@ __global__ __launch_bounds__(256) void k_group_fwd(const int32_t* __restrict__ r
   GroupDesc d{};
   if (gsel < cnt) d = *reinterpret_cast<const GroupDesc*>(rb);
   group_fwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, rb, vals, y, cb,
-                           smem_raw + 4 * per * stride);
+                           smem_raw + 4 * per * stride, gdense != 0);
 }
 
 template <typename S, typename C, bool ST>
@@ -977,12 +1020,13 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
                                                int blk_elems, int team,
                                                const int32_t* __restrict__ idx,
                                                const S* __restrict__ vals,
-                                               double* __restrict__ x, unsigned char* smem_raw) {
+                                               double* __restrict__ x, unsigned char* smem_raw,
+                                               bool dense = false) {
   const int gsel = threadIdx.x / seg, lt = threadIdx.x - gsel * seg;
-  const int n = d.n, nr = d.nr, k = n - nr;
+  const int n = d.n, nr = dense ? 0 : d.nr, k = n - nr;
   C* base = reinterpret_cast<C*>(smem_raw) + (int64_t)gsel * per_group;
   const S* v = vals + d.offV;
-  const int tg = tri_count(n), tt = k * nr, tr = tri_count(nr);
+  const int tg = dense ? n * n : tri_count(n), tt = k * nr, tr = tri_count(nr);
   C* blk = base;
   C* xg = ST ? base + blk_elems : base;
   C* zg = xg + n;
@@ -997,6 +1041,17 @@ __device__ __forceinline__ void group_bwd_body(const GroupDesc& d, int seg, int 
   for (int i = lt; i < n; i += seg) xg[i] = (C)x[gi_idx[i]];
   __syncthreads();
   const int part = lt % team, per_t = seg / team;
+  if (dense) {  // the whole step at once: x_g = G^T x_g
+    const Col<S, C, ST> G{blk, v, n};
+    for (int ob = 0; ob < n; ob += per_t) {
+      const int i = ob + lt / team;
+      C acc = 0;
+      if (i < n) acc = G.col_dot(i, part, n, team, [&](int j) { return xg[j]; });
+      acc = team_sum(acc, team);
+      if (part == 0 && i < n) x[gi_idx[i]] = (double)acc;
+    }
+    return;
+  }
   for (int ob = 0; ob < nr; ob += per_t) {   // a = T^T x_I^
     const int i = ob + lt / team;
     C acc = 0;
@@ -1054,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_group_bwd(const int32_t* __restrict__ r
                                                    int blk_elems, int team,
                                                    const S* __restrict__ vals,
                                                    double* __restrict__ x,
-                                                   const int* __restrict__ done) {
+                                                   const int* __restrict__ done, int gdense) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int per = blockDim.x / seg, g0 = blockIdx.x * per, cnt = min(per, ngroup - g0);
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
@@ -1067,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_group_bwd(const int32_t* __restrict__ r
   GroupDesc d{};
   if (gsel < cnt) d = *reinterpret_cast<const GroupDesc*>(rb);
   group_bwd_body<S, C, ST>(d, seg, per_group, blk_elems, team, rb, vals, x,
-                           smem_raw + 4 * per * stride);
+                           smem_raw + 4 * per * stride, gdense != 0);
 }
 
 // ------------------------------------------------------------------------------------ root --
@@ -1149,7 +1204,7 @@ __global__ __launch_bounds__(1024) void k_fuse_fwd(const int32_t* __restrict__ f
                                                    double* __restrict__ y,
                                                    const double* __restrict__ cb_in,
                                                    double* __restrict__ cb_out,
-                                                   const int* __restrict__ done) {
+                                                   const int* __restrict__ done, int gdense) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the record of cell p, then those of the groups it owns (padded to maxown)
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
@@ -1167,7 +1222,8 @@ __global__ __launch_bounds__(1024) void k_fuse_fwd(const int32_t* __restrict__ f
     if (prestage)
       stage_flat(reinterpret_cast<C*>(work), vals + d.offV, tri_count(d.nI) + d.nB * d.nI,
                  threadIdx.x, blockDim.x);
-  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, team_g, rb, vals, y, cb_in, work + goff);
+  group_fwd_body<S, C, true>(g, seg, per_group, blk_g, team_g, rb, vals, y, cb_in, work + goff,
+                             gdense != 0);
   __syncthreads();
   cell_fwd_body<S, C, CST, 0>(d, rec, vals, y, cb_out, blk_c, team_c, prestage != 0, work);
 }
@@ -1185,7 +1241,8 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
                                                     const S* __restrict__ vals,
                                                     double* __restrict__ y,
                                                     const double* __restrict__ cb_in,
-                                                    int rstaged, const int* __restrict__ done) {
+                                                    int rstaged, const int* __restrict__ done,
+                                                    int gdense) {
   const int gsel = threadIdx.x / seg;
   GroupDesc g{};
   if (gsel < per && gsel < ngroup) g = gd[gsel];
@@ -1196,7 +1253,8 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
       g = GroupDesc{};
       if (gsel < per && b + gsel < ngroup) g = gd[b + gsel];
     }
-    group_fwd_body<S, C, true>(g, seg, per_group, blk_g, team, idx, vals, y, cb_in, smem_raw);
+    group_fwd_body<S, C, true>(g, seg, per_group, blk_g, team, idx, vals, y, cb_in, smem_raw,
+                               gdense != 0);
     __syncthreads();
   }
   root_body<S, C>(nr, ridx, Lv, y, rstaged != 0, smem_raw);
@@ -1204,7 +1262,8 @@ __global__ __launch_bounds__(1024) void k_fuse_root(const GroupDesc* __restrict_
   for (int b = 0; b < ngroup; b += per) {
     g = GroupDesc{};
     if (gsel < per && b + gsel < ngroup) g = gd[b + gsel];
-    group_bwd_body<S, C, true>(g, seg, per_group, blk_g, team, idx, vals, y, smem_raw);
+    group_bwd_body<S, C, true>(g, seg, per_group, blk_g, team, idx, vals, y, smem_raw,
+                               gdense != 0);
     __syncthreads();
   }
 }
@@ -1804,16 +1863,19 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
                  double* cb, const int* done, hipStream_t s, const StageTimer& t,
                  const CgGate* gate = nullptr, const CgRhs* rhs = nullptr) {
   const StagePlan p = cell_plan<C>(L);
+  // symmetric cells keep their record out of LDS, except where the first stage makes the
+  // right-hand side
+  const size_t lds = p.smem + (MODE == 2 && !(fwd && rhs) ? 0 : p.rec);
   if (fwd) {
     auto k = p.staged ? k_cell_fwd<S, C, true, MODE> : k_cell_fwd<S, C, false, MODE>;
-    launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
+    launch(k, dim3(p.grid), dim3(p.threads), lds, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, cb, done, p.blk_elems, p.seg, gate ? *gate : CgGate{},
            (gate || rhs) ? (const int32_t*)f.gcopy.p : (const int32_t*)nullptr, f.gcstride,
            rhs ? *rhs : CgRhs{}, sym_cfg(f, L), L.cfwd);
   } else {
     auto k = p.staged ? k_cell_bwd<S, C, true, MODE> : k_cell_bwd<S, C, false, MODE>;
     const bool fold = &L == &f.lv[std::max(0, f.top)] && f.top >= 0 && f.tfold;
-    launch(k, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t, (const int32_t*)L.crec.p,
+    launch(k, dim3(p.grid), dim3(p.threads), lds, s, t, (const int32_t*)L.crec.p,
            L.cstride, vals, y, done, p.blk_elems, p.seg,
            fold ? (const int32_t*)f.tpos.p : (const int32_t*)nullptr, f.tpstride,
            (const double*)f.twsc.p, (f.ntop + f.tspan - 1) / std::max(1, f.tspan), f.ntop,
@@ -1964,7 +2026,8 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
       launch(k, dim3(P.ncell), dim3(fp.threads), fp.rec + fp.smem, s, t,
              (const int32_t*)L.frec.p, L.fstride, P.cstride, L.gstride, L.maxown,
              fp.g.seg * fp.team_g, fp.team_g, fp.g.per_group, fp.g.blk_elems, fp.goff, fp.blk_c,
-             fp.team_c, (int)fp.prestage, vals, y, (const double*)cbl(l), cbl(l + 1), done);
+             fp.team_c, (int)fp.prestage, vals, y, (const double*)cbl(l), cbl(l + 1), done,
+             L.gdense);
     } else if (l == nlev - 1 && f.root_fused) {  // + root + this level's backward groups
       const FusePlan fp = fuse_plan<C>(L, nullptr, f.nroot);
       const StageTimer t(prof, nlev, STAGE_ROOT, done, s);
@@ -1972,7 +2035,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
              (const GroupDesc*)L.groups.p, L.ngroup, fp.g.seg * fp.team_g, fp.team_g, fp.per,
              fp.g.per_group,
              fp.g.blk_elems, f.nroot, idx + f.offRootIdx, vals + f.offRootV, idx, vals, y,
-             (const double*)cbl(l), (int)fp.prestage, done);
+             (const double*)cbl(l), (int)fp.prestage, done, L.gdense);
     } else if (L.gtiled) {
       const StageTimer t(prof, l, STAGE_GROUP_FWD, done, s);
       launch_dense_groups<S, C>(f, L, true, y, cbl(l), done, s, t);
@@ -1981,7 +2044,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
       const StagePlan p = group_plan<C>(L);
       launch(k_group_fwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t,
              (const int32_t*)L.grec.p, L.gstride, L.ngroup, p.seg, p.per_group, p.blk_elems,
-             p.team, vals, y, (const double*)cbl(l), done);
+             p.team, vals, y, (const double*)cbl(l), done, L.gdense);
     }
   }
   if (f.nroot && !f.root_fused && f.top < 0) {
@@ -2005,7 +2068,7 @@ void apply_impl(const FactorDev& f, double* y, const int* done, hipStream_t s,
         const StagePlan p = group_plan<C>(L);
         launch(k_group_bwd<S, C, true>, dim3(p.grid), dim3(p.threads), p.rec + p.smem, s, t,
                (const int32_t*)L.grec.p, L.gstride, L.ngroup, p.seg, p.per_group, p.blk_elems,
-               p.team, vals, y, done);
+               p.team, vals, y, done, L.gdense);
       }
     }
     if (L.ncell) {
@@ -2105,10 +2168,10 @@ __global__ __launch_bounds__(256) void k_bgroup(const BatchArg* __restrict__ arg
   const S* vals = reinterpret_cast<const S*>(a.vals);
   if constexpr (FWD)
     group_fwd_body<S, C, true>(d, a.seg, a.per_group, a.blk_elems, a.team, rb, vals, a.y, a.cb,
-                               smem_raw + 4 * recmax);
+                               smem_raw + 4 * recmax, a.gdense != 0);
   else
     group_bwd_body<S, C, true>(d, a.seg, a.per_group, a.blk_elems, a.team, rb, vals, a.y,
-                               smem_raw + 4 * recmax);
+                               smem_raw + 4 * recmax, a.gdense != 0);
 }
 
 // Roots: one workgroup per solve.
@@ -2365,6 +2428,7 @@ void batch_group(const FactorDev& f, int l, double* y, const int* done, BatchArg
   a.done = done;
   a.stride = L.gstride;
   a.count = L.ngroup;
+  a.gdense = L.gdense;
   a.seg = p.seg;
   a.team = p.team;
   a.blk_elems = p.blk_elems;
@@ -2517,8 +2581,25 @@ void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& 
   e.offB = 8 + d.nI + nc;
   std::memcpy(r, &e, sizeof(CellDesc));
   for (int i = 0; i < d.nI; ++i) r[8 + i] = idx[d.offI + i];
-  // ib[nB], then the links grouped by interior DOF: rowptr[nI + 1], blist[nB]
-  for (int q = 0; q < nc; ++q) r[8 + d.nI + q] = idx[d.offC + q];
+  // ib[nB], then the links grouped by interior DOF: rowptr[nI + 1], blist[nB]; symmetric cells
+  // (mode 2) instead keep one word per interior DOF: its link count, then up to three boundary
+  // positions of 8 bits each (a 5- or 7-point stencil gives an interior node at most three
+  // boundary neighbours, and boundaries stay below 256 DOFs), so the backward stage needs one
+  // load per DOF where the lists need two dependent ones
+  if (d.mode == 2) {
+    for (int b = 0; b < d.nB; ++b) r[8 + d.nI + b] = idx[d.offC + b];
+    const int32_t* rp = idx.data() + d.offC + d.nB;
+    const int32_t* bl = rp + d.nI + 1;
+    for (int i = 0; i < d.nI; ++i) {
+      const int cnt = rp[i + 1] - rp[i];
+      HIF_REQUIRE(cnt <= 3 && d.nB < 256, HIF_ERR_ARG, "internal: level-0 link count");
+      int32_t w = cnt;
+      for (int q = 0; q < cnt; ++q) w |= bl[rp[i] + q] << (8 * (q + 1));
+      r[8 + d.nI + d.nB + i] = w;
+    }
+  } else {
+    for (int q = 0; q < nc; ++q) r[8 + d.nI + q] = idx[d.offC + q];
+  }
   for (int b = 0; b < d.nB; ++b) r[e.offB + b] = idx[d.offB + b];
 }
 // Record of one group: the descriptor, then DOF ids, pivot order, gather pointers and slots.
@@ -2636,6 +2717,130 @@ int tile_threads(int maxI) {
   return maxI <= small_max ? small_threads : 1024;
 }
 }  // namespace
+
+// ------------------------------------------------------------------------ dense groups --
+struct DenseGroupTask {
+  int64_t offV, offW;  // the group's storage in vals; its work area (doubles)
+  int32_t n, nr, offPerm, pad;
+};
+
+// One workgroup per group: column c of G = (the forward group step applied to e_c), in FP64
+// from the stored blocks (packed L_g^-1, T, packed L_s^-1; see group_fwd_body), then G over
+// the blocks (column-major, storage precision) once every column is formed.
+template <typename S>
+__global__ __launch_bounds__(256) void k_group_dense(const DenseGroupTask* __restrict__ tasks,
+                                                     S* __restrict__ vals,
+                                                     const int32_t* __restrict__ idx,
+                                                     double* __restrict__ work) {
+  const DenseGroupTask t = tasks[blockIdx.x];
+  const int n = t.n, nr = t.nr, k = n - nr;
+  const S* v = vals + t.offV;
+  const S* T = v + tri_count(n);            // k x nr, T[i k + s]
+  const S* Ls = T + (int64_t)k * nr;         // packed L_s^-1
+  const int32_t* perm = idx + t.offPerm;
+  double* G = work + t.offW;                 // n x n, column-major
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double* z = work + t.offW + (int64_t)n * n + (int64_t)c * (n + 3 * nr);
+    double* tv = z + n;
+    double* uv = tv + nr;
+    double* wv = uv + nr;
+    double* out = G + (int64_t)c * n;
+    for (int i = 0; i < n; ++i)  // z = L_g^-1 e_c
+      z[i] = i >= c ? load_as<double>(v + colstart(c, n) + (i - c)) : 0.0;
+    if (nr == 0) {
+      for (int i = 0; i < n; ++i) out[i] = z[i];
+      continue;
+    }
+    for (int i = 0; i < nr; ++i) {  // z_I~ - T^T z_I^
+      double a = 0;
+      for (int q = 0; q < k; ++q) a += load_as<double>(T + (int64_t)i * k + q) * z[perm[nr + q]];
+      tv[i] = z[perm[i]] - a;
+    }
+    for (int i = 0; i < nr; ++i) {  // u = L_s^-1 (...)
+      double a = 0;
+      for (int j = 0; j <= i; ++j) a += load_as<double>(Ls + colstart(j, nr) + (i - j)) * tv[j];
+      uv[i] = a;
+    }
+    for (int i = 0; i < nr; ++i) {  // w = L_s^-T u
+      double a = 0;
+      for (int j = i; j < nr; ++j) a += load_as<double>(Ls + colstart(i, nr) + (j - i)) * uv[j];
+      wv[i] = a;
+    }
+    for (int q = 0; q < k; ++q) {  // z_I^ + T w, and u at the redundant DOFs
+      double a = 0;
+      for (int i = 0; i < nr; ++i) a += load_as<double>(T + (int64_t)i * k + q) * wv[i];
+      out[perm[nr + q]] = z[perm[nr + q]] + a;
+    }
+    for (int i = 0; i < nr; ++i) out[perm[i]] = uv[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) vals[t.offV + e] = (S)G[e];
+}
+
+void setup_dense_groups(FactorDev& f, const std::vector<std::vector<GroupDesc>>& groups,
+                        const std::vector<int32_t>& idx, int top, hipStream_t s) {
+  if (std::getenv("HIFCN_NO_DENSE_GROUPS") || f.store == HIF_STORE_BF16) return;
+  const bool f64 = f.store == HIF_STORE_F64;
+  const int64_t eb = (int64_t)store_elem_bytes(f.store);
+  for (size_t l = 0; l < f.lv.size(); ++l) {
+    LevelDev& L = f.lv[l];
+    if (!L.ngroup || L.gtiled || (top >= 0 && (int)l >= top)) continue;
+    int64_t dense = 0, packed = 0;
+    int maxsq = 0;
+    bool fits = true;
+    for (const GroupDesc& d : groups[l]) {
+      const int64_t n = d.n, nr = d.nr;
+      dense += n * n;
+      packed += tri_count(n) + (n - nr) * nr + tri_count(nr);
+      maxsq = std::max<int>(maxsq, (int)(n * n));
+      fits = fits && d.cap >= n * n;
+    }
+    if (!fits || dense > 2 * packed) continue;
+    // the level must stay staged (one workgroup's LDS holds its blocks) with G in them
+    const int gv0 = L.maxGV, r0 = L.maxR;
+    L.maxGV = maxsq;
+    L.maxR = 0;
+    const bool staged = f64 ? group_plan<double>(L).staged : group_plan<float>(L).staged;
+    L.maxGV = gv0;
+    L.maxR = r0;
+    if (!staged) continue;
+    // form G in every group of the level, over its blocks
+    std::vector<DenseGroupTask> tasks;
+    int64_t wo = 0;
+    for (const GroupDesc& d : groups[l]) {
+      tasks.push_back({d.offV, wo, d.n, d.nr, d.offPerm, 0});
+      wo += (int64_t)d.n * d.n + (int64_t)d.n * (d.n + 3 * d.nr);
+    }
+    DevBuf<DenseGroupTask> dt(tasks.size(), s);
+    dt.upload(tasks, s);
+    DevBuf<double> work(std::max<int64_t>(1, wo), s);
+    switch (f.store) {
+      case HIF_STORE_F64:
+        hipLaunchKernelGGL(k_group_dense<double>, dim3(tasks.size()), dim3(256), 0, s,
+                           (const DenseGroupTask*)dt.p, reinterpret_cast<double*>(f.vals.p),
+                           (const int32_t*)f.idx.p, work.p);
+        break;
+      default:
+        hipLaunchKernelGGL(k_group_dense<float>, dim3(tasks.size()), dim3(256), 0, s,
+                           (const DenseGroupTask*)dt.p, reinterpret_cast<float*>(f.vals.p),
+                           (const int32_t*)f.idx.p, work.p);
+    }
+    HIF_CHECK(hipGetLastError());
+    HIF_CHECK(hipStreamSynchronize(s));
+    L.gdense = 1;
+    L.maxGV = maxsq;
+    L.maxR = 0;
+    // bytes per sweep: G, the group's vectors and indices (forward: also the gathered slots)
+    int64_t gf = 0, gb = 0;
+    for (const GroupDesc& d : groups[l]) {
+      const int64_t n = d.n, nsl = idx[d.offGP + n];
+      gf += eb * n * n + 16 * n + 12 * nsl + 4 * n + 4 * (n + 1) + (int64_t)sizeof(GroupDesc);
+      gb += eb * n * n + 16 * n + 4 * n + (int64_t)sizeof(GroupDesc);
+    }
+    L.group_bytes[0] = gf;
+    L.group_bytes[1] = gb;
+  }
+}
 
 void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                   const std::vector<std::vector<GroupDesc>>& groups,

@@ -1238,6 +1238,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       d.n = n;
       d.nr = gk[g] >= 0 ? n - gk[g] : 0;
       d.offV = (int32_t)grp_voff[g];
+      d.cap = (int32_t)(tri64(n) * (geo.skeletonized(P.groups[g].kind) ? 2 : 1));
       lo.gids.push_back(P.groups[g].dofs);
       std::vector<int32_t> pm;
       if (gk[g] >= 0) {
@@ -1464,6 +1465,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       groups.push_back(lo.groups);
     }
     setup_tiling(f, cells, groups, idx, s);
+    setup_dense_groups(f, groups, idx, dense_top_level(f, cells, groups), s);
     setup_fusion(f, cells, groups, idx, hd.N, s);
     setup_dense_top(f, cells, groups, idx, hd.N, s);
     setup_cg_gate(f, cells, idx, hd.N, s);

@@ -135,7 +135,8 @@ struct GroupDesc {
   int32_t offV;        // values: packed L_g^-1 (n(n+1)/2), T column-major (k x nr, T[j*k + s]),
                        //         packed L_s^-1 (nr(nr+1)/2), with k = n - nr
   int32_t offGP;       // gather map: ptr[n+1] (relative), then slots[] into the contributions
-  int32_t pad0, pad1;
+  int32_t pad0;
+  int32_t cap;         // elements the storage at offV holds (room for a dense n x n form)
 };
 
 __host__ __device__ inline int64_t tri_count(int64_t n) { return n * (n + 1) / 2; }

@@ -342,10 +342,8 @@ DevBuf<double> build_top(FactorDev& f, const std::vector<std::vector<CellDesc>>&
 
 }  // namespace
 
-void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
-                     const std::vector<std::vector<GroupDesc>>& groups,
-                     const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
-  f.top = -1;
+int dense_top_level(const FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                    const std::vector<std::vector<GroupDesc>>& groups) {
   const int nlev = (int)f.lv.size();
   // entries of M_k: up to 40M (160 MiB in FP32, within the 256 MiB Infinity Cache) one pass
   // over M_k costs less than the launches it replaces (1024^2 grid: level 4 instead of 5, -7%
@@ -354,7 +352,7 @@ void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cel
   int64_t budget = int64_t(40) << 20;
   if (const char* e = std::getenv("HIFCN_DENSE_TOP")) budget = std::atoll(e);
   if (f.top_budget >= 0) budget = f.top_budget;
-  if (budget <= 0 || nlev == 0 || f.nroot == 0) return;
+  if (budget <= 0 || nlev == 0 || f.nroot == 0) return -1;
   // the lowest level whose M_k fits, with every level from it up to the top eligible
   int k = -1;
   for (int l = nlev - 1; l >= 0; --l) {
@@ -368,6 +366,14 @@ void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cel
     }
     k = l;
   }
+  return k;
+}
+
+void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                     const std::vector<std::vector<GroupDesc>>& groups,
+                     const std::vector<int32_t>& idx, int64_t N, hipStream_t s) {
+  f.top = -1;
+  const int k = dense_top_level(f, cells, groups);
   if (k < 0) return;
   DevBuf<double> M;
   switch (f.store) {

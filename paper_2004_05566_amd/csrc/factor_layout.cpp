@@ -315,6 +315,7 @@ FactorHost import_blob(const void* blob, size_t nbytes, int dim, int n, int leaf
         push_packed(fh.vals, sk[g].Lsinv, d.nr);
       }
       fh.nvals_used += tri_count(gn) + (int64_t)(gn - d.nr) * d.nr + tri_count(d.nr);
+      d.cap = (int32_t)(tri_count(gn) + (int64_t)(gn - d.nr) * d.nr + tri_count(d.nr));
       lh.maxG = std::max(lh.maxG, gn);
       lh.maxR = std::max(lh.maxR, d.nr);
       lh.maxK = std::max(lh.maxK, gn - d.nr);
@@ -400,6 +401,7 @@ void upload_factor(const FactorHost& fh, hif_store_t store, FactorDev& fd, hipSt
     }
     for (int i = 0; i < fh.nroot; ++i) N = std::max<int64_t>(N, fh.idx[fh.offRootIdx + i] + 1);
     setup_tiling(fd, cells, groups, fh.idx, s);
+    setup_dense_groups(fd, groups, fh.idx, dense_top_level(fd, cells, groups), s);
     setup_fusion(fd, cells, groups, fh.idx, N, s);
     setup_dense_top(fd, cells, groups, fh.idx, N, s);
     setup_cg_gate(fd, cells, fh.idx, N, s);

@@ -50,6 +50,8 @@ struct LevelDev {
   // symmetric-inverse cells (cmode 2): cells of at most sqn interior DOFs go to an LDS square of
   // leading dimension sqld (odd), larger ones stay packed; sqmat: LDS elements for either
   int sqn = 0, sqld = 0, sqmat = 0;
+  // group stages as one dense product G (forward) / G^T (backward) per group (setup_dense_groups)
+  int gdense = 0;
 };
 
 // Stages of one apply, as timed by the profiler.
@@ -160,7 +162,7 @@ struct BatchArg {
   int32_t first;         // first launch block of this solve
   int32_t blk_elems, team, seg, per_group, staged;
   int32_t sqn, sqld, sqmat;  // symmetric cells (LevelDev)
-  int32_t pad;
+  int32_t gdense;            // group stages: one dense product per group (LevelDev)
 };
 enum BatchKind { BK_CELL_FWD_SYM = 0, BK_CELL_FWD = 1, BK_GROUP_FWD = 2, BK_ROOT = 3,
                  BK_GROUP_BWD = 4, BK_CELL_BWD_SYM = 5, BK_CELL_BWD = 6 };
@@ -321,10 +323,24 @@ void setup_tiling(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                   const std::vector<std::vector<GroupDesc>>& groups,
                   const std::vector<int32_t>& idx, hipStream_t s);
 
-// Choose the level from which the rest of the apply runs as one dense matrix, form it and lay
-// it out (no dense top when no level's matrix stays within the element budget
-// f.top_budget, else HIFCN_DENSE_TOP, else 10M entries; 0 disables).  Call after setup_fusion (it
-// turns the fused root off when it takes over the root).
+// Levels whose group stages run as one dense product per group (LevelDev::gdense): each
+// group's forward step C^T K^T (block Jacobi, then the skeletonization of eq_T / eq2_9) is
+// multiplied out into G (n x n, column-major) in place of its packed blocks, and the backward
+// step is G^T.  A level qualifies when it is neither tiled nor under the dense top `top`,
+// every group's storage holds n^2 elements (GroupDesc::cap) and G costs at most twice the
+// packed blocks' elements (group stages are latency-bound: fewer dependent steps matter more
+// than the extra bytes).  HIFCN_NO_DENSE_GROUPS=1: none.  Call after setup_tiling and before
+// setup_fusion (the fused plans size LDS for the level's blocks).
+void setup_dense_groups(FactorDev& f, const std::vector<std::vector<GroupDesc>>& groups,
+                        const std::vector<int32_t>& idx, int top, hipStream_t s);
+
+// The level from which the rest of the apply runs as one dense matrix (-1: none, when no level's
+// matrix stays within the element budget f.top_budget, else HIFCN_DENSE_TOP, else 40M entries;
+// 0 disables).
+int dense_top_level(const FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
+                    const std::vector<std::vector<GroupDesc>>& groups);
+// Choose that level, form its matrix and lay it out.  Call after setup_fusion (it turns the
+// fused root off when it takes over the root).
 void setup_dense_top(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
                      const std::vector<std::vector<GroupDesc>>& groups,
                      const std::vector<int32_t>& idx, int64_t N, hipStream_t s);
