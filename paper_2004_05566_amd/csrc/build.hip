@@ -848,7 +848,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
     for (int g : P.seps) {
       voff = align_vals(voff);
       grp_voff[g] = voff;
-      voff += tri64(gsz(g)) * (geo.skeletonized(P.groups[g].kind) ? 2 : 1);
+      // twice the packed triangle: room for T and L_s^-1 after an ID, or for the dense form
+      // of the group step (n^2 <= n (n + 1))
+      voff += 2 * tri64(gsz(g));
     }
     voff = align_vals(voff);
     DevBuf<double> fv(std::max<int64_t>(1, voff), s);
@@ -1238,7 +1240,7 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
       d.n = n;
       d.nr = gk[g] >= 0 ? n - gk[g] : 0;
       d.offV = (int32_t)grp_voff[g];
-      d.cap = (int32_t)(tri64(n) * (geo.skeletonized(P.groups[g].kind) ? 2 : 1));
+      d.cap = (int32_t)(2 * tri64(n));
       lo.gids.push_back(P.groups[g].dofs);
       std::vector<int32_t> pm;
       if (gk[g] >= 0) {

@@ -14,21 +14,23 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    # name, n, leaf, eps, store, tolerance of the F^-1 comparison
-    ("2d-n64-f64", 64, 8, 1e-3, "f64", 1e-12),
-    ("2d-n127-f64-eps1e-6", 127, 8, 1e-6, "f64", 1e-12),
-    ("2d-n128-f32", 128, 8, 1e-3, "f32", 1e-5),
+    # name, n, dim, leaf, eps, store, tolerance of the F^-1 comparison
+    ("2d-n64-f64", 64, 2, 8, 1e-3, "f64", 1e-12),
+    ("2d-n127-f64-eps1e-6", 127, 2, 8, 1e-6, "f64", 1e-12),
+    ("2d-n128-f32", 128, 2, 8, 1e-3, "f32", 1e-5),
+    ("3d-n16-f64", 16, 3, 4, 1e-3, "f64", 1e-12),
+    ("3d-n16-f32", 16, 3, 4, 1e-3, "f32", 1e-5),
 ]
 
 
-def _pair(n, leaf, eps, store, monkeypatch, dt=0.1):
+def _pair(n, dim, leaf, eps, store, monkeypatch, dt=0.1):
     import torch
     from paper_2004_05566_amd import hifcn
-    a = torch.tensor(gen.grf_coefficient(n, 2, 0.15, 81), device="cuda")
+    a = torch.tensor(gen.grf_coefficient(n, dim, 0.15, 81), device="cuda")
     monkeypatch.delenv("HIFCN_NO_DENSE_GROUPS", raising=False)
-    hd = hifcn.factor(a, dt, n, 2, eps, store=store, leaf=leaf, dense_top=0)
+    hd = hifcn.factor(a, dt, n, dim, eps, store=store, leaf=leaf, dense_top=0)
     monkeypatch.setenv("HIFCN_NO_DENSE_GROUPS", "1")
-    hp = hifcn.factor(a, dt, n, 2, eps, store=store, leaf=leaf, dense_top=0)
+    hp = hifcn.factor(a, dt, n, dim, eps, store=store, leaf=leaf, dense_top=0)
     monkeypatch.delenv("HIFCN_NO_DENSE_GROUPS")
     return hd, hp
 
@@ -36,10 +38,10 @@ def _pair(n, leaf, eps, store, monkeypatch, dt=0.1):
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_dense_groups_apply_equals_stepwise(case, gpu_lib, monkeypatch):
     import torch
-    name, n, leaf, eps, store, tol = case
+    name, n, dim, leaf, eps, store, tol = case
     print(f"[case] {name}", flush=True)
-    hd, hp = _pair(n, leaf, eps, store, monkeypatch)
-    N = n * n
+    hd, hp = _pair(n, dim, leaf, eps, store, monkeypatch)
+    N = n ** dim
     for seed in (1, 2):
         x = torch.tensor(gen.normal_vector(N, seed), device="cuda")
         zd, zp = hd.apply(x), hp.apply(x)
