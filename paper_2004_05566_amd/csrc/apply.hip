@@ -2826,7 +2826,6 @@ void setup_dense_groups(FactorDev& f, const std::vector<std::vector<GroupDesc>>&
                            (const int32_t*)f.idx.p, work.p);
     }
     HIF_CHECK(hipGetLastError());
-    HIF_CHECK(hipStreamSynchronize(s));
     L.gdense = 1;
     L.maxGV = maxsq;
     L.maxR = 0;
