@@ -395,7 +395,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots(int n, int64_t N, int 
   }
 }
 
-// k_cg_dir_dots over x-pairs of nodes (n even; see k_spmv_pairs).
+// k_cg_dir_dots over x-pairs of nodes (n even; see k_spmv_pairs), two pairs per lane and turn
+// (their loads in flight together).
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_cg_dir_dots_pairs(int n, int64_t N, int it,
                                                                 const double* __restrict__ lw,
@@ -410,15 +411,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots_pairs(int n, int64_t N
   const double2* z2 = reinterpret_cast<const double2*>(z);
   auto Z = [&](int64_t k) { return z[k]; };
   auto Z2 = [&](int64_t k) { return z2[k >> 1]; };
-  for (NodeWalk<DIM> a(2 * (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kThreads + threadIdx.x),
-                          2 * stride, n);
-       a.i < N; a.next(n)) {
-    const int64_t h = a.i >> 1;
+  auto one = [&](const NodeWalk<DIM>& c) {
+    const int64_t h = c.i >> 1;
     const double2 zv = z2[h];
     const double2 rv = reinterpret_cast<const double2*>(r)[h];
     const double2 qv = it > 0 ? reinterpret_cast<const double2*>(q)[h] : double2{0.0, 0.0};
     double s0, s1;
-    link_sum_pair<DIM>(a.i, a.ix, a.iy, a.iz, n, lw, zv, Z, Z2, s0, s1);
+    link_sum_pair<DIM>(c.i, c.ix, c.iy, c.iz, n, lw, zv, Z, Z2, s0, s1);
     const double w0 = zv.x + s0, w1 = zv.y + s1;
     reinterpret_cast<double2*>(w)[h] = double2{w0, w1};
     rz += rv.x * zv.x;
@@ -427,7 +426,16 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots_pairs(int n, int64_t N
     zw += zv.y * w1;
     zq += zv.x * qv.x;
     zq += zv.y * qv.y;
+  };
+  // pairs in the order t, t + stride, t + 2 stride, ... (t: this lane's first pair)
+  NodeWalk<DIM> a(2 * (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kThreads + threadIdx.x),
+                  4 * stride, n);
+  NodeWalk<DIM> b(a.i + 2 * stride, 4 * stride, n);
+  for (; b.i < N; a.next(n), b.next(n)) {
+    one(a);
+    one(b);
   }
+  if (a.i < N) one(a);
   block_sum3(rz, zw, zq);
   if (threadIdx.x == 0) {
     part[P_RZ * (int64_t)nb + blockIdx.x] = rz;
@@ -436,37 +444,17 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir_dots_pairs(int n, int64_t N
   }
 }
 
-// rho = r.z, beta = rho / rho_prev (0 on the first iteration), p.Ap from the expansion above,
-// alpha = rho / p.Ap; p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q; partials of
-// ||r||^2.  Block 0 keeps rho and p.Ap in slot it & 1 of the state for the next direction (no
-// block reads that slot in this launch).  Once the iteration has stopped nothing is stored but
-// the partials (scratch): the flag is read with the other loads, not waited for first.
-__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
-                                                        const double* __restrict__ z,
-                                                        const double* __restrict__ w,
-                                                        double* __restrict__ p,
-                                                        double* __restrict__ q,
-                                                        double* __restrict__ x,
-                                                        double* __restrict__ r, CgState* st,
-                                                        double* part,
-                                                        const double* __restrict__ gpart, int ngp,
-                                                        double rtol) {
-  int dn = st->done;
+// The update's scalars from this iteration's partial sums (every block adds them up in the same
+// order): beta, alpha; with gpart, the test of g first (it may stop the step: dn).  Block 0
+// records rho and p.Ap for the next direction and, with gpart, the step's ||g||^2 and tolerance.
+struct CgCoef {
+  double alpha, beta;
+  int dn;
+};
+__device__ CgCoef cg_coef(int it, CgState* st, const double* part, const double* gpart, int ngp,
+                          double rtol, int dn) {
   const int nb = gridDim.x;
   const bool first = it == 0;
-  // the lane's first element is loaded before the totals, so its latency overlaps theirs
-  const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  double z0 = 0, w0 = 0, p0 = 0, q0 = 0, x0 = 0, r0 = 0;
-  if (i0 < N) {
-    z0 = z[i0];
-    w0 = w[i0];
-    if (!first) {
-      p0 = p[i0];
-      q0 = q[i0];
-    }
-    x0 = x[i0];
-    r0 = r[i0];
-  }
   double rz = 0, zw = 0, zq = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     rz += part[P_RZ * (int64_t)nb + i];
@@ -497,6 +485,38 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
     st->rzv[it & 1] = rz;
     st->pqv[it & 1] = pq;
   }
+  return CgCoef{alpha, beta, dn};
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ p,
+                                                        double* __restrict__ q,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ r, CgState* st,
+                                                        double* part,
+                                                        const double* __restrict__ gpart, int ngp,
+                                                        double rtol) {
+  const int dn0 = st->done;
+  const int nb = gridDim.x;
+  const bool first = it == 0;
+  // the lane's first element is loaded before the totals, so its latency overlaps theirs
+  const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double z0 = 0, w0 = 0, p0 = 0, q0 = 0, x0 = 0, r0 = 0;
+  if (i0 < N) {
+    z0 = z[i0];
+    w0 = w[i0];
+    if (!first) {
+      p0 = p[i0];
+      q0 = q[i0];
+    }
+    x0 = x[i0];
+    r0 = r[i0];
+  }
+  const CgCoef c = cg_coef(it, st, part, gpart, ngp, rtol, dn0);
+  const double alpha = c.alpha, beta = c.beta;
+  const int dn = c.dn;
   double acc = 0;
   for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) {
     const bool pre = i == i0;
@@ -511,6 +531,80 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t N, int it,
       q[i] = qi;
       x[i] = xi;
       r[i] = ri;
+    }
+  }
+  put_partial(acc, part + P_RR * (int64_t)nb);
+}
+
+// k_cg_update over pairs of elements (N even, 16-byte aligned vectors): two pairs per lane and
+// turn, every load of both issued before the first store, so twice the bytes are in flight.
+__global__ __launch_bounds__(kThreads) void k_cg_update_pairs(int64_t N, int it,
+                                                              const double* __restrict__ z,
+                                                              const double* __restrict__ w,
+                                                              double* __restrict__ p,
+                                                              double* __restrict__ q,
+                                                              double* __restrict__ x,
+                                                              double* __restrict__ r,
+                                                              CgState* st, double* part,
+                                                              const double* __restrict__ gpart,
+                                                              int ngp, double rtol) {
+  const int dn0 = st->done;
+  const int nb = gridDim.x;
+  const bool first = it == 0;
+  const int64_t H = N / 2, S = (int64_t)gridDim.x * kThreads;
+  const double2* z2 = reinterpret_cast<const double2*>(z);
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  double2* p2 = reinterpret_cast<double2*>(p);
+  double2* q2 = reinterpret_cast<double2*>(q);
+  double2* x2 = reinterpret_cast<double2*>(x);
+  double2* r2 = reinterpret_cast<double2*>(r);
+  const double2 zero{0.0, 0.0};
+  // the lane's first two pairs are loaded before the totals, so their latency overlaps theirs
+  const int64_t h0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double2 zv[2], wv[2], pv[2], qv[2], xv[2], rv[2];
+  auto load = [&](int64_t h0_, int u) {
+    const int64_t h = h0_ + u * S;
+    if (h < H) {
+      zv[u] = z2[h];
+      wv[u] = w2[h];
+      pv[u] = first ? zero : p2[h];
+      qv[u] = first ? zero : q2[h];
+      xv[u] = x2[h];
+      rv[u] = r2[h];
+    }
+  };
+  load(h0, 0);
+  load(h0, 1);
+  const CgCoef c = cg_coef(it, st, part, gpart, ngp, rtol, dn0);
+  const double alpha = c.alpha, beta = c.beta;
+  const int dn = c.dn;
+  double acc = 0;
+  for (int64_t hb = h0; hb < H; hb += 2 * S) {
+    if (hb != h0) {
+      load(hb, 0);
+      load(hb, 1);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t h = hb + u * S;
+      if (h >= H) break;
+      double2 pi, qi, xi, ri;
+      pi.x = first ? zv[u].x : zv[u].x + beta * pv[u].x;
+      pi.y = first ? zv[u].y : zv[u].y + beta * pv[u].y;
+      qi.x = first ? wv[u].x : wv[u].x + beta * qv[u].x;
+      qi.y = first ? wv[u].y : wv[u].y + beta * qv[u].y;
+      xi.x = xv[u].x + alpha * pi.x;
+      xi.y = xv[u].y + alpha * pi.y;
+      ri.x = rv[u].x - alpha * qi.x;
+      ri.y = rv[u].y - alpha * qi.y;
+      acc += ri.x * ri.x;
+      acc += ri.y * ri.y;
+      if (!dn) {
+        p2[h] = pi;
+        q2[h] = qi;
+        x2[h] = xi;
+        r2[h] = ri;
+      }
     }
   }
   put_partial(acc, part + P_RR * (int64_t)nb);
@@ -716,12 +810,15 @@ void launch_links(const double* a_cells, int dim, int n, double scale, double* l
 
 // The stencil kernels take x-pairs of nodes where n is even and the vectors are 16-byte aligned
 // (HIFCN_NO_PAIRS=1: one node per lane everywhere).
-bool use_pairs(const Handle& h, std::initializer_list<const void*> vecs) {
+bool use_pairs_ptrs(std::initializer_list<const void*> vecs) {
   static const bool off = std::getenv("HIFCN_NO_PAIRS") != nullptr;
-  if (off || h.n % 2 != 0) return false;
+  if (off) return false;
   for (const void* p : vecs)
     if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return false;
   return true;
+}
+bool use_pairs(const Handle& h, std::initializer_list<const void*> vecs) {
+  return h.n % 2 == 0 && use_pairs_ptrs(vecs);
 }
 
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
@@ -787,7 +884,9 @@ void launch_cg_dir_dots(Handle& h, int it, hipStream_t s) {
 
 void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s) {
   const bool g = it == 0 && h.rhs_fused;
-  hipLaunchKernelGGL(k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it, h.z.p, h.w.p,
+  const bool pairs = h.N % 2 == 0 && use_pairs_ptrs({h.z.p, h.w.p, h.p.p, h.q.p, h.x.p, h.r.p});
+  hipLaunchKernelGGL(pairs ? k_cg_update_pairs : k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s,
+                     h.N, it, h.z.p, h.w.p,
                      h.p.p, h.q.p, h.x.p, h.r.p, h.st.p, h.partials.p,
                      g ? (const double*)h.gpart.p : (const double*)nullptr, (int)h.gpart.n, rtol);
 }
