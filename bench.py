@@ -606,8 +606,9 @@ def dominant_roofline(h, w, store, u0, steps, rtol, stages):
     pd = roof[key]
     avg_s = pd["ms"] / 1e3 / max(1, pd["launches"])
     achieved = pd["bytes"] / avg_s / 1e9
-    kname = {"cell_fwd": "k_cell_fwd", "cell_bwd": "k_cell_bwd", "group_fwd": "k_fuse_fwd",
-             "group_bwd": "k_group_bwd", "root": "k_top_rows"}[key[0]]
+    kname = pd.get("kernel") or {"cell_fwd": "k_cell_fwd", "cell_bwd": "k_cell_bwd",
+                                 "group_fwd": "k_fuse_fwd", "group_bwd": "k_group_bwd",
+                                 "root": "k_top_rows"}[key[0]]
     return {"bound": "hbm", "kernel": f"{kname} (level {key[1]}, {key[0]})",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,

@@ -240,6 +240,7 @@ typedef struct {
   double ms;         /* their total elapsed time */
   int64_t bytes;     /* algorithmic bytes one launch moves: factor blocks in the storage
                         precision + FP64 vector and contribution traffic + int32 indices */
+  char kernel[32];   /* the kernel the last timed launch used, NUL-terminated ("" if not named) */
 } hif_stage_prof_t;
 
 /* Start (enable != 0: counters reset) or stop timing the launches of (level, stage). */

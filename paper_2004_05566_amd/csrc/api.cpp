@@ -1,6 +1,7 @@
 // C-ABI entry points of libhifcn (declared in include/hifcn.h).
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <exception>
 #include <map>
@@ -330,7 +331,7 @@ struct FusedBatch {
   std::vector<std::tuple<const Handle*, uint64_t, const double*, int, double, double, double,
                          int>> key;
   BatchApplyPlan plan;
-  DevBuf<BatchCg> cg;
+  StagedBuf<BatchCg> cg;
   int blocks = 0, dim = 2, maxit = 1;
 };
 
@@ -541,6 +542,8 @@ hif_status_t hif_refactor(hif_handle_t hh, const double* a_cells_dev, void* hip_
     std::swap(h.gpart, nh->gpart);
     h.rhs_fused = nh->rhs_fused;
     h.plan0 = nh->plan0;
+    DeviceIdle idle;  // the old factor leaves with nh: released after one synchronisation
+    nh.reset();
   });
 }
 
@@ -699,14 +702,10 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
       };
       for (size_t i = 1; i < grp.size(); ++i) join(grp[i].s, s0);
       fused_batch_step(fbs[k], grp, s0);
-      for (StepState& x : grp) {
-        Handle& h = *x.h;
-        HIF_CHECK(hipMemcpyAsync(h.host_flag, h.step_iters.p, sizeof(int32_t),
-                                 hipMemcpyDeviceToHost, s0));
-        HIF_CHECK(hipMemcpyAsync(h.host_flag + 4, h.step_relres.p, sizeof(double),
-                                 hipMemcpyDeviceToHost, s0));
-      }
-      HIF_CHECK(hipStreamSynchronize(s0));
+      // the closing test posted each solve's iteration count and wrote its relative residual
+      // to host_flag[4..5] ahead of the post
+      for (StepState& x : grp) x.h->host_flag[0] = x.launched;
+      HIF_CHECK(hipStreamSynchronize(s0));  // u = x may still be under way in other blocks
       for (size_t i = 1; i < grp.size(); ++i) join(s0, grp[i].s);
       for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     }
@@ -895,12 +894,14 @@ hif_status_t hif_profile_read(hif_handle_t hh, hif_stage_prof_t* out) {
       if (p.stage == STAGE_GROUP_FWD && L.fuse) bytes += h.f.lv[p.level + 1].cell_bytes[0];
     }
     out->bytes = bytes;
+    std::snprintf(out->kernel, sizeof(out->kernel), "%s", p.kernel);
   });
 }
 
 void hif_destroy(hif_handle_t hh) {
   if (!hh) return;
-  (void)hipDeviceSynchronize();
+  // one device synchronisation, then every buffer back to the pool without another
+  hifcn::DeviceIdle idle;
   delete reinterpret_cast<Handle*>(hh);
 }
 

@@ -350,6 +350,11 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
   }
 }
 
+// A stop flag that is never set: symmetric cell stages read their flag through a pointer to it
+// when none is given, so that the flag, the descriptor and the ids load without a branch
+// between them.
+__device__ const int kNeverStop = 0;
+
 // ------------------------------------------------------------ symmetric-inverse cells (mode 2) --
 // A level-0 cell stored as M = A_II^-1 (= L^-T L^-1, packed column-major lower triangle) and the
 // single stencil coupling of each boundary DOF.  Forward: c_b = A_BI(b, ib_b) (M y_I)_{ib_b},
@@ -367,9 +372,11 @@ __device__ __forceinline__ void cell_fwd_body(const CellDesc& d, const int32_t* 
 // row i (consecutive lanes, consecutive words) and then its column i.  The LDS of a launch is
 // sized for the usual cell, so more wavefronts stay resident.
 
-// LDS elements of the compute type a symmetric cell stage needs besides its record.
+// LDS elements of the compute type a symmetric cell stage needs besides its record: the matrix,
+// t, and (M t) forward or the boundary values and their couplings backward.
 __host__ __device__ inline int sym_smem_elems(int mat, int maxB) {
-  return mat + 2 * kSymMaxCell + 2 * round_up(maxB, 4);
+  const int b2 = 2 * round_up(maxB, 4);
+  return mat + kSymMaxCell + (b2 > kSymMaxCell ? b2 : kSymMaxCell);
 }
 
 // Every element of the cell block into LDS: to both of its square positions (tab: this order's
@@ -444,6 +451,12 @@ __device__ __forceinline__ void sym_store(C* sq, const SymRegs<S>& R, int tl, bo
   }
 }
 
+// The table entries of interior order n (n <= cfg.n): the square's own order from the offset
+// kept with the level (no dependent load before the block's loads), any other from the header.
+__device__ __forceinline__ const int32_t* sym_tab(const SymCfg& cfg, int n) {
+  return cfg.tab + (n == cfg.n ? cfg.sqoff : cfg.tab[n]);
+}
+
 // (M t)_lane for lane < n from the square (leading dimension ld): row `lane` against t
 // (broadcast from LDS), eight terms per batch into four running sums, added in a fixed order.
 template <typename C>
@@ -506,7 +519,8 @@ __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* _
                                              unsigned char* smem_raw,
                                              const double* __restrict__ in = nullptr,
                                              Hook hook = Hook{}, const int* stop = nullptr,
-                                             bool own_ys = false) {
+                                             bool own_ys = false, int pre_gi = 0,
+                                             bool pre = false) {
   const double* src = in ? in : y;
   C* sq = reinterpret_cast<C*>(smem_raw);
   C* ts = sq + cfg.mat;
@@ -517,22 +531,32 @@ __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* _
   const int32_t* gI = idx + d.offI;
   const int32_t* ibp = idx + d.offC;
   const S* cw = v + sym_coff(tl);  // the couplings
-  // loads in order of need: the interior ids, the block, the inputs, the first couplings
+  // loads in order of need: the interior ids (pre: already loaded with the descriptor, so the
+  // gathers go out first, idle lanes at the first interior DOF), the block, the inputs, the
+  // first couplings
   int gi = -1;
-  if (!own_ys && lane < nI) gi = gI[lane];
+  double yv = 0;
+  if (!own_ys && pre) {
+    const int g0 = __builtin_amdgcn_readfirstlane(pre_gi);
+    gi = lane < nI ? pre_gi : -1;
+    yv = src[lane < nI ? pre_gi : g0];
+    if (lane >= nI) yv = 0;
+  } else if (!own_ys && lane < nI) {
+    gi = gI[lane];
+  }
   const bool square = nI <= cfg.n;
   SymRegs<S> R;
-  sym_load<S>(R, v, tl, square ? cfg.tab + cfg.tab[nI] : nullptr, lane);
-  double yv = 0;
-  if (!own_ys && lane < nI) yv = src[gi];
+  sym_load<S>(R, v, tl, square ? sym_tab(cfg, nI) : nullptr, lane);
+  if (!own_ys && !pre && lane < nI) yv = src[gi];
   int ib0 = 0;
   C a0 = 0;
   if (lane < nB) {
     ib0 = ibp[lane];
     a0 = load_as<C>(cw + lane);
   }
+  if (!own_ys && pre) ts[lane] = (C)yv;
   sym_store<S, C>(sq, R, tl, square, lane);
-  if (!own_ys) ts[lane] = (C)yv;
+  if (!own_ys && !pre) ts[lane] = (C)yv;
   hook(ts);
   __syncthreads();
   if (stop && *stop) return;
@@ -551,10 +575,11 @@ template <typename S, typename C>
 __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* __restrict__ idx,
                                              const S* __restrict__ vals, double* __restrict__ x,
                                              const SymCfg& cfg, unsigned char* smem_raw,
-                                             const TopIn& top) {
+                                             const TopIn& top, int r0 = 0, int r1 = 0,
+                                             bool pre = false) {
   C* sq = reinterpret_cast<C*>(smem_raw);
   C* ts = sq + cfg.mat;
-  C* xbs = ts + 2 * kSymMaxCell;
+  C* xbs = ts + kSymMaxCell;
   const int lane = threadIdx.x;
   const int nI = d.nI, nB = d.nB, tl = tri_count(nI);
   C* abs_ = xbs + round_up(nB, 4);
@@ -562,15 +587,30 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
   const int32_t* gI = idx + d.offI;
   const int32_t* gB = idx + d.offB;
   const int32_t* lw = idx + d.offC + nB;  // per interior DOF: link count, boundary positions
-  // the ids and link words, the gathers, then the block
+  // pre: the record's first 128 words after the descriptor (r0: word 8 + lane, r1: word
+  // 72 + lane) came with the descriptor and hold both id lists, so the gathers go out at once
+  // (idle lanes at the first interior DOF), then the link words, couplings and the block
+  const bool fast = pre && !top.pos && nI + nB <= 128 && nB <= 64;
   int gi = -1, w = 0;
-  double xi = 0;
-  if (lane < nI) {
+  double xi = 0, xv = 0;
+  C ab = 0;
+  if (fast) {
+    const int k = (nI + lane) & 63;  // boundary DOF lane is word 8 + nI + lane
+    const int blo = __shfl(r0, k, 64), bhi = __shfl(r1, k, 64);
+    const int gb = nI + lane < 64 ? blo : bhi;
+    const int g0 = __builtin_amdgcn_readfirstlane(r0);
+    gi = lane < nI ? r0 : -1;
+    xi = x[lane < nI ? r0 : g0];
+    xv = x[lane < nB ? gb : g0];
+    if (lane >= nI) xi = 0;
+    if (lane < nI) w = lw[lane];
+    if (lane < nB) ab = load_as<C>(v + sym_coff(tl) + lane);
+  } else if (lane < nI) {
     gi = gI[lane];
     w = lw[lane];
     xi = x[gi];
   }
-  for (int b = lane; b < nB; b += 64) {
+  for (int b = fast ? nB : lane; b < nB; b += 64) {
     double xv;
     if (top.pos) {
       xv = top.sum(top.pos[b]);
@@ -585,7 +625,11 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
     for (int e = lane; e < top.ne; e += 64) x[top.ext[2 * e + 1]] = top.sum(top.ext[2 * e]);
   const bool square = nI <= cfg.n;
   SymRegs<S> R;
-  sym_load<S>(R, v, tl, square ? cfg.tab + cfg.tab[nI] : nullptr, lane);
+  sym_load<S>(R, v, tl, square ? sym_tab(cfg, nI) : nullptr, lane);
+  if (fast && lane < nB) {
+    xbs[lane] = (C)xv;
+    abs_[lane] = ab;
+  }
   sym_store<S, C>(sq, R, tl, square, lane);
   __syncthreads();
   if (lane < nI) {
@@ -716,11 +760,20 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
     if ((int)threadIdx.x < gcstride - 1) cid = cp[1 + threadIdx.x];
   }
   if constexpr (MODE != 2) load_record(rec, grec, flen, threadIdx.x, blockDim.x);
-  const int dn = gated ? 0 : (done ? *done : 0);
+  // symmetric cells: the descriptor and (records of 72 words or more) the interior ids load
+  // together with the stop flag
+  const bool pre = MODE == 2 && stride >= 72;
+  CellDesc dsym{};
+  int pre_gi = 0;
+  if constexpr (MODE == 2) {
+    dsym = *reinterpret_cast<const CellDesc*>(grec);
+    if (pre) pre_gi = grec[8 + threadIdx.x];
+  }
+  const int dn = gated ? 0 : MODE == 2 ? *(done ? done : &kNeverStop) : (done ? *done : 0);
   if (gated && cid >= 0) cval = gate.src[cid];  // (padding entries read DOF 0; never stored)
   if constexpr (MODE != 2) __syncthreads();
-  if (dn) return;
-  const CellDesc d = *reinterpret_cast<const CellDesc*>(MODE == 2 ? grec : rec);
+  if (dn || (MODE == 2 && dsym.nI < 0)) return;  // (the descriptor's load stays ahead of this)
+  const CellDesc d = MODE == 2 ? dsym : *reinterpret_cast<const CellDesc*>(rec);
   // the test's verdict is reached while the cell's block and inputs load (they are only read
   // before it is known)
   auto verdict = [&](C*) {
@@ -737,7 +790,7 @@ __global__ __launch_bounds__(256) void k_cell_fwd(const int32_t* __restrict__ re
   };
   if constexpr (MODE == 2)
     cell_fwd_sym<S, C>(d, grec, vals, y, cb, sym, smem_raw, gate.src, verdict,
-                       gated ? &gstop : nullptr);
+                       gated ? &gstop : nullptr, false, pre_gi, pre);
   else
     cell_fwd_body<S, C, ST, MODE>(d, rec, vals, y, cb, blk_elems, team, false,
                                   smem_raw + 4 * stride, gate.src, verdict,
@@ -866,17 +919,29 @@ __global__ __launch_bounds__(256) void k_cell_bwd(const int32_t* __restrict__ re
   const int32_t* grec = recs + (int64_t)blockIdx.x * stride;
   int32_t* rec = reinterpret_cast<int32_t*>(smem_raw);
   if constexpr (MODE != 2) load_record(rec, grec, stride, threadIdx.x, blockDim.x);
-  const int dn = done ? *done : 0;
+  // symmetric cells: the descriptor and (records of 136 words or more, no dense top folded in)
+  // the 128 words after it, which hold both id lists, load together with the stop flag
+  const bool pre = MODE == 2 && stride >= 136 && !tpos;
+  CellDesc dsym{};
+  int r0 = 0, r1 = 0;
+  if constexpr (MODE == 2) {
+    dsym = *reinterpret_cast<const CellDesc*>(grec);
+    if (pre) {
+      r0 = grec[8 + threadIdx.x];
+      r1 = grec[72 + threadIdx.x];
+    }
+  }
+  const int dn = MODE == 2 ? *(done ? done : &kNeverStop) : (done ? *done : 0);
   if constexpr (MODE != 2) __syncthreads();
-  if (dn) return;
-  const CellDesc d = *reinterpret_cast<const CellDesc*>(MODE == 2 ? grec : rec);
+  if (dn || (MODE == 2 && dsym.nI < 0)) return;  // (the descriptor's load stays ahead of this)
+  const CellDesc d = MODE == 2 ? dsym : *reinterpret_cast<const CellDesc*>(rec);
   TopIn top;
   if (tpos) {  // per cell: ne, (position, id) x ne, then one position per boundary DOF
     const int32_t* r = tpos + (int64_t)blockIdx.x * tstride;
     top = TopIn{r + tstride - d.nB, r + 1, r[0], tpart, tnch, tn};
   }
   if constexpr (MODE == 2)
-    cell_bwd_sym<S, C>(d, grec, vals, x, sym, smem_raw, top);
+    cell_bwd_sym<S, C>(d, grec, vals, x, sym, smem_raw, top, r0, r1, pre);
   else
     cell_bwd_body<S, C, ST, MODE>(d, rec, vals, x, blk_elems, team, smem_raw + 4 * stride, top);
 }
@@ -1855,7 +1920,7 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t s, const S
 }
 
 SymCfg sym_cfg(const FactorDev& f, const LevelDev& L) {
-  return SymCfg{f.sqtab.p, L.sqn, L.sqld, L.sqmat};
+  return SymCfg{f.sqtab.p, L.sqn, L.sqld, L.sqmat, L.sqoff};
 }
 
 template <typename S, typename C, int MODE>
@@ -1863,6 +1928,7 @@ void launch_cell(const FactorDev& f, const LevelDev& L, bool fwd, const S* vals,
                  double* cb, const int* done, hipStream_t s, const StageTimer& t,
                  const CgGate* gate = nullptr, const CgRhs* rhs = nullptr) {
   const StagePlan p = cell_plan<C>(L);
+  if (t.p) t.p->kernel = fwd ? "k_cell_fwd" : "k_cell_bwd";
   // symmetric cells keep their record out of LDS, except where the first stage makes the
   // right-hand side
   const size_t lds = p.smem + (MODE == 2 && !(fwd && rhs) ? 0 : p.rec);
@@ -2118,7 +2184,8 @@ __global__ __launch_bounds__(256) void k_bcell_fwd(const BatchArg* __restrict__ 
   const S* vals = reinterpret_cast<const S*>(a.vals);
   unsigned char* sm = smem_raw + 4 * recmax;
   if constexpr (MODE == 2)
-    cell_fwd_sym<S, C>(d, rec, vals, a.y, a.cb, SymCfg{a.sqtab, a.sqn, a.sqld, a.sqmat}, sm);
+    cell_fwd_sym<S, C>(d, rec, vals, a.y, a.cb,
+                       SymCfg{a.sqtab, a.sqn, a.sqld, a.sqmat, a.sqoff}, sm);
   else if (a.staged)
     cell_fwd_body<S, C, true, 0>(d, rec, vals, a.y, a.cb, a.blk_elems, a.team, false, sm);
   else
@@ -2140,7 +2207,7 @@ __global__ __launch_bounds__(256) void k_bcell_bwd(const BatchArg* __restrict__ 
   const S* vals = reinterpret_cast<const S*>(a.vals);
   unsigned char* sm = smem_raw + 4 * recmax;
   if constexpr (MODE == 2)
-    cell_bwd_sym<S, C>(d, rec, vals, a.y, SymCfg{a.sqtab, a.sqn, a.sqld, a.sqmat}, sm,
+    cell_bwd_sym<S, C>(d, rec, vals, a.y, SymCfg{a.sqtab, a.sqn, a.sqld, a.sqmat, a.sqoff}, sm,
                        TopIn{});
   else if (a.staged)
     cell_bwd_body<S, C, true, 0>(d, rec, vals, a.y, a.blk_elems, a.team, sm);
@@ -2394,6 +2461,7 @@ void batch_cell(const FactorDev& f, int l, double* y, const int* done, BatchArg&
   a.sqn = L.sqn;
   a.sqld = L.sqld;
   a.sqmat = L.sqmat;
+  a.sqoff = L.sqoff;
   a.stride = L.cstride;
   a.len = fwd ? L.cfwd : L.cstride;
   a.count = L.ncell;
@@ -2565,29 +2633,31 @@ void tile_level(LevelDev& L, const std::vector<CellDesc>& cells, int64_t* base, 
 }  // namespace
 
 namespace {
-// Record of one cell: the descriptor with record-relative index offsets, then I, (link modes)
-// the interior position of each boundary DOF's coupling and the couplings grouped by interior
-// DOF, then B.  The forward stage reads only the prefix up to the coupling positions
-// (cell_fwd_len); the backward stage reads the whole record.
+// Record of one cell: the descriptor with record-relative index offsets, then its index lists.
+// Modes 0 and 1: interior ids, then (mode 1) ib[nB] and the links grouped by interior DOF
+// (rowptr[nI + 1], blist[nB]), then the boundary ids; the forward stage reads only the prefix
+// up to the coupling positions (cell_fwd_len), the backward stage the whole record.  Symmetric cells (mode 2): interior ids, boundary ids, ib[nB], then one word
+// per interior DOF: its link count and up to three boundary positions of 8 bits each (a 5- or
+// 7-point stencil gives an interior node at most three boundary neighbours, and boundaries stay
+// below 256 DOFs), so the backward stage needs one load per DOF where the lists need two
+// dependent ones.  Both id lists then lie in the 128 words after the descriptor, which a stage
+// loads together with the descriptor itself (their positions need only nI).
 int cell_record_len(const CellDesc& d) {
+  if (d.mode == 2) return round_up(8 + 2 * d.nI + 2 * d.nB, 4);
   return round_up(8 + d.nI + d.nB + (d.mode ? 2 * d.nB + d.nI + 1 : 0), 4);
 }
-int cell_fwd_len(const CellDesc& d) { return round_up(8 + d.nI + (d.mode ? d.nB : 0), 4); }
+int cell_fwd_len(const CellDesc& d) {
+  return round_up(8 + d.nI + (d.mode == 2 ? 2 * d.nB : d.mode ? d.nB : 0), 4);
+}
 void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& idx) {
-  const int nc = d.mode ? 2 * d.nB + d.nI + 1 : 0;
   CellDesc e = d;
   e.offI = 8;
-  e.offC = d.mode ? 8 + d.nI : 0;
-  e.offB = 8 + d.nI + nc;
-  std::memcpy(r, &e, sizeof(CellDesc));
   for (int i = 0; i < d.nI; ++i) r[8 + i] = idx[d.offI + i];
-  // ib[nB], then the links grouped by interior DOF: rowptr[nI + 1], blist[nB]; symmetric cells
-  // (mode 2) instead keep one word per interior DOF: its link count, then up to three boundary
-  // positions of 8 bits each (a 5- or 7-point stencil gives an interior node at most three
-  // boundary neighbours, and boundaries stay below 256 DOFs), so the backward stage needs one
-  // load per DOF where the lists need two dependent ones
   if (d.mode == 2) {
-    for (int b = 0; b < d.nB; ++b) r[8 + d.nI + b] = idx[d.offC + b];
+    e.offB = 8 + d.nI;
+    e.offC = 8 + d.nI + d.nB;
+    for (int b = 0; b < d.nB; ++b) r[e.offB + b] = idx[d.offB + b];
+    for (int b = 0; b < d.nB; ++b) r[e.offC + b] = idx[d.offC + b];
     const int32_t* rp = idx.data() + d.offC + d.nB;
     const int32_t* bl = rp + d.nI + 1;
     for (int i = 0; i < d.nI; ++i) {
@@ -2595,12 +2665,16 @@ void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& 
       HIF_REQUIRE(cnt <= 3 && d.nB < 256, HIF_ERR_ARG, "internal: level-0 link count");
       int32_t w = cnt;
       for (int q = 0; q < cnt; ++q) w |= bl[rp[i] + q] << (8 * (q + 1));
-      r[8 + d.nI + d.nB + i] = w;
+      r[e.offC + d.nB + i] = w;
     }
   } else {
+    const int nc = d.mode ? 2 * d.nB + d.nI + 1 : 0;
+    e.offC = d.mode ? 8 + d.nI : 0;
+    e.offB = 8 + d.nI + nc;
     for (int q = 0; q < nc; ++q) r[8 + d.nI + q] = idx[d.offC + q];
+    for (int b = 0; b < d.nB; ++b) r[e.offB + b] = idx[d.offB + b];
   }
-  for (int b = 0; b < d.nB; ++b) r[e.offB + b] = idx[d.offB + b];
+  std::memcpy(r, &e, sizeof(CellDesc));
 }
 // Record of one group: the descriptor, then DOF ids, pivot order, gather pointers and slots.
 int group_record_len(const GroupDesc& g, const std::vector<int32_t>& idx) {

@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -34,30 +36,94 @@ struct HifError : std::runtime_error {
   } while (0)
 
 // ---------------------------------------------------------------------------------------------
-// Owning device buffer.  alloc() uses hipMalloc (long-lived buffers); alloc_on() uses the
-// stream-ordered allocator, so that the many short-lived buffers of a factor build neither take
-// a device-wide lock nor wait for other streams when they are freed (hipFree synchronises the
-// device; hipFreeAsync only orders the release on the buffer's stream).
+// The stream on which long-lived buffers are taken from the device's stream-ordered pool (one
+// per device, default priority, created on first use).  Each allocation waits for it, so the
+// memory is ready for every stream as soon as alloc() returns.
+inline hipStream_t pool_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  HIF_CHECK(hipGetDevice(&dev));
+  HIF_REQUIRE(dev >= 0 && dev < 64, HIF_ERR_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev]) HIF_CHECK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
+}
+
+// The library's stream-ordered memory pool of the current device (created on first use).  It
+// keeps up to 4 GiB of released memory for later allocations instead of handing it back to the
+// driver at every synchronisation, so the temporaries of one factor build reuse those of the
+// last one.
+inline hipMemPool_t lib_pool() {
+  static std::mutex mu;
+  static hipMemPool_t pools[64] = {};
+  int dev = 0;
+  HIF_CHECK(hipGetDevice(&dev));
+  HIF_REQUIRE(dev >= 0 && dev < 64, HIF_ERR_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pools[dev]) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    HIF_CHECK(hipMemPoolCreate(&pool, &props));
+    uint64_t keep = uint64_t(4) << 30;
+    HIF_CHECK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    pools[dev] = pool;
+  }
+  return pools[dev];
+}
+
+// Set on a thread while every stream of the device is known to be idle (DeviceIdle): long-lived
+// buffers released meanwhile skip the device synchronisation each release otherwise makes.
+inline bool& device_idle_flag() {
+  thread_local bool idle = false;
+  return idle;
+}
+struct DeviceIdle {  // synchronise the device once, then release any number of buffers
+  DeviceIdle() {
+    (void)hipDeviceSynchronize();
+    device_idle_flag() = true;
+  }
+  ~DeviceIdle() { device_idle_flag() = false; }
+  DeviceIdle(const DeviceIdle&) = delete;
+  DeviceIdle& operator=(const DeviceIdle&) = delete;
+};
+
+// Owning device buffer.  Both kinds of allocation come from the library's pool, so that
+// releasing them never waits for other streams the way hipFree does (it synchronises the
+// device):
+//   alloc()     long-lived buffers (a factor, a solve's vectors): taken on pool_stream(); a
+//               release first waits for the device's queued work, as hipFree would, unless the
+//               device is known idle (DeviceIdle: a handle's whole set after one synchronisation);
+//   alloc_on()  the many short-lived buffers of a factor build: taken and released in the order
+//               of their own stream.
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
-  hipStream_t so = nullptr;  // stream-ordered: the stream it was allocated on
-  bool ordered = false;
+  hipStream_t so = nullptr;  // the stream it was allocated on
+  bool ordered = false;      // alloc_on: released in the order of so
+  bool pooled = false;       // alloc: released after the device's queued work
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(size_t count, hipStream_t s) { alloc_on(count, s); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), so(o.so), ordered(o.ordered) {
+  DevBuf(DevBuf&& o) noexcept
+      : p(o.p), n(o.n), so(o.so), ordered(o.ordered), pooled(o.pooled) {
     o.p = nullptr;
     o.n = 0;
+    o.ordered = o.pooled = false;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; n = o.n; so = o.so; ordered = o.ordered;
-      o.p = nullptr; o.n = 0;
+      p = o.p; n = o.n; so = o.so; ordered = o.ordered; pooled = o.pooled;
+      o.p = nullptr; o.n = 0; o.ordered = o.pooled = false;
     }
     return *this;
   }
@@ -65,28 +131,80 @@ struct DevBuf {
   void alloc(size_t count) {
     release();
     n = count;
-    if (count) HIF_CHECK(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    if (count) {
+      so = pool_stream();
+      HIF_CHECK(hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), count * sizeof(T),
+                                       lib_pool(), so));
+      pooled = true;
+      HIF_CHECK(hipStreamSynchronize(so));
+    }
   }
   void alloc_on(size_t count, hipStream_t s) {
     release();
     n = count;
     so = s;
     ordered = true;
-    if (count) HIF_CHECK(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), s));
+    if (count)
+      HIF_CHECK(hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), count * sizeof(T),
+                                       lib_pool(), s));
   }
   void release() {
     if (p) {
-      if (ordered) (void)hipFreeAsync(p, so);
-      else (void)hipFree(p);
+      if (pooled && !device_idle_flag()) (void)hipDeviceSynchronize();
+      (void)hipFreeAsync(p, so);
     }
     p = nullptr;
     n = 0;
-    ordered = false;
+    ordered = pooled = false;
     so = nullptr;
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     if (h.size() != n) alloc(h.size());
     if (n) HIF_CHECK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// A small table uploaded again and again between launches (the batched step's per-solve
+// arguments): device storage that only grows (by doubling, so a growing hipFree, which waits for
+// the device, is rare) filled from pinned host memory that is written again only once the copy
+// out of it has ended (an event).  A refill thus leaves the device running.
+template <typename T>
+struct StagedBuf {
+  T* p = nullptr;  // device
+  size_t n = 0;    // elements of the last upload
+  size_t cap = 0;
+  T* h = nullptr;  // pinned host staging, cap elements
+  hipEvent_t copied = nullptr;
+  StagedBuf() = default;
+  StagedBuf(const StagedBuf&) = delete;
+  StagedBuf& operator=(const StagedBuf&) = delete;
+  ~StagedBuf() {
+    if (copied) {
+      (void)hipEventSynchronize(copied);
+      (void)hipEventDestroy(copied);
+    }
+    if (p) (void)hipFree(p);
+    if (h) (void)hipHostFree(h);
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    if (!copied) HIF_CHECK(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+    HIF_CHECK(hipEventSynchronize(copied));  // the previous copy out of h has ended
+    if (v.size() > cap) {
+      const size_t c = std::max(v.size(), 2 * cap);
+      if (p) HIF_CHECK(hipFree(p));
+      p = nullptr;
+      if (h) HIF_CHECK(hipHostFree(h));
+      h = nullptr;
+      cap = 0;
+      HIF_CHECK(hipMalloc(reinterpret_cast<void**>(&p), c * sizeof(T)));
+      HIF_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h), c * sizeof(T), hipHostMallocDefault));
+      cap = c;
+    }
+    n = v.size();
+    if (!n) return;
+    std::memcpy(h, v.data(), n * sizeof(T));
+    HIF_CHECK(hipMemcpyAsync(p, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+    HIF_CHECK(hipEventRecord(copied, s));
   }
 };
 

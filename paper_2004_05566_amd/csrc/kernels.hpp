@@ -50,6 +50,7 @@ struct LevelDev {
   // symmetric-inverse cells (cmode 2): cells of at most sqn interior DOFs go to an LDS square of
   // leading dimension sqld (odd), larger ones stay packed; sqmat: LDS elements for either
   int sqn = 0, sqld = 0, sqmat = 0;
+  int sqoff = 0;  // start of order sqn's entries in f.sqtab (its header entry, kept on the host)
   // group stages as one dense product G (forward) / G^T (backward) per group (setup_dense_groups)
   int gdense = 0;
 };
@@ -68,6 +69,7 @@ struct StageProfiler {
   DevBuf<int32_t> live;   // per pending launch: 1 if the kernel did work (0: early exit)
   int64_t launches = 0;
   double ms = 0;
+  const char* kernel = "";  // the kernel of the last timed launch (set by its launch site)
   hipEvent_t next_event() {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -161,7 +163,7 @@ struct BatchArg {
   int32_t count;         // cells or groups of the level, or the root's DOFs
   int32_t first;         // first launch block of this solve
   int32_t blk_elems, team, seg, per_group, staged;
-  int32_t sqn, sqld, sqmat;  // symmetric cells (LevelDev)
+  int32_t sqn, sqld, sqmat, sqoff;  // symmetric cells (LevelDev)
   int32_t gdense;            // group stages: one dense product per group (LevelDev)
 };
 enum BatchKind { BK_CELL_FWD_SYM = 0, BK_CELL_FWD = 1, BK_GROUP_FWD = 2, BK_ROOT = 3,
@@ -173,7 +175,7 @@ struct BatchLaunch {
 };
 struct BatchApplyPlan {
   std::vector<BatchLaunch> launches;
-  DevBuf<BatchArg> args;
+  StagedBuf<BatchArg> args;
   hif_store_t store = HIF_STORE_F32;
 };
 // Whether a factor can take part in a batched apply (2D or 3D, level 0 symmetric cells or none,
@@ -194,6 +196,7 @@ constexpr int kSymMaxCell = 64;  // largest interior held as A_II^-1 by one wave
 struct SymCfg {
   const int32_t* tab;
   int n, ld, mat;
+  int sqoff;  // tab[n]: where the entries of the square's own order start
 };
 // The table's header: entry n (1 <= n <= SymCfg::n) is where the entries of interior order n
 // start (a multiple of 4).

@@ -665,14 +665,20 @@ __global__ __launch_bounds__(kThreads) void k_bcg_check(const BatchCg* __restric
   const int nb = a.nb;
   const bool lead = vb == 0 && threadIdx.x == 0;
   const int64_t stride = (int64_t)nb * kThreads, i0 = vb * (int64_t)kThreads + threadIdx.x;
-  auto finish = [&](int iters, bool keep_u) {  // u = x; the step's records (lead lane)
+  // the step's records (lead lane): iteration count and relative residual on the device and,
+  // for the host, the residual in the mapped flag block ahead of the posted word
+  auto record = [&](int iters) {
+    const double rel = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
+    a.it_out[0] = iters;
+    a.rel_out[0] = rel;
+    *reinterpret_cast<volatile double*>(a.hflag + 4) = rel;
+    __threadfence_system();
+    post_flag(a.hflag, seq, iters, 1, st->status);
+  };
+  auto finish = [&](int iters, bool keep_u) {  // u = x; the step's records
     if (!keep_u)
       for (int64_t i = i0; i < a.N; i += stride) a.u[i] = a.x[i];
-    if (lead) {
-      a.it_out[0] = iters;
-      a.rel_out[0] = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
-      post_flag(a.hflag, seq, iters, 1, st->status);
-    }
+    if (lead) record(iters);
   };
   if (!init && st->done) {  // stopped by an earlier test of this step
     if (fin) finish(st->iters, st->status != 0 && st->iters == 0);
@@ -689,14 +695,7 @@ __global__ __launch_bounds__(kThreads) void k_bcg_check(const BatchCg* __restric
   __syncthreads();
   if (stop) {
     // block 0 published the scalars; the other blocks only copy x (init stops copy nothing)
-    if (fin && !init) {
-      for (int64_t i = i0; i < a.N; i += stride) a.u[i] = a.x[i];
-      if (lead) {
-        a.it_out[0] = it0 + 1;
-        a.rel_out[0] = st->gg > 0 ? sqrt(st->rr / st->gg) : 0.0;
-        post_flag(a.hflag, seq, it0 + 1, 1, st->status);
-      }
-    }
+    if (fin && !init) finish(it0 + 1, false);
     return;
   }
   if (fin && lead) post_flag(a.hflag, seq, it0 + 1, 0, 0);

@@ -62,7 +62,8 @@ FACTOR_SKEL_EDGES = 1
 
 class _StageProf(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("stage", ctypes.c_int32),
-                ("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_int64)]
+                ("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_int64),
+                ("kernel", ctypes.c_char * 32)]
 
 
 STAGES = {"cell_fwd": 0, "group_fwd": 1, "root": 2, "group_bwd": 3, "cell_bwd": 4}
@@ -226,7 +227,7 @@ class Handle:
         p = _StageProf()
         _check(_lib.hif_profile_read(self._p(), ctypes.byref(p)))
         return {"level": p.level, "stage": p.stage, "launches": p.launches, "ms": p.ms,
-                "bytes": p.bytes}
+                "bytes": p.bytes, "kernel": p.kernel.decode()}
 
     def inverse_error(self, x0, iters: int = 30, stream=None) -> float:
         """hif_inverse_error: the power-iteration estimate of ||I - A F^-1||_2 from x0."""

@@ -126,12 +126,17 @@ class Server:
         self._free_streams = list(range(self.max_slots))
         self._builders = ThreadPoolExecutor(max_workers=max(1, builders),
                                             thread_name_prefix="hif-build")
+        # finished solves are released on a thread of their own (hif_destroy waits for the
+        # device once), so that releases never hold up builds
+        self._freer = ThreadPoolExecutor(max_workers=1, thread_name_prefix="hif-free")
         self._tls = threading.local()
         self._closing = False
         self._paused = bool(paused)  # admit and build, but run no rounds until resume()
         self.rounds = 0
         self.batch_sizes: list[int] = []
         self.step_seconds = 0.0  # time spent in the batched step calls
+        self.build_seconds = 0.0  # builder-thread time in factor builds
+        self.free_seconds = 0.0   # builder-thread time releasing finished solves
         self.peak_held = 0
         self._error: BaseException | None = None
         self.lanes = max(1, int(lanes))
@@ -185,13 +190,15 @@ class Server:
             for t in self._threads:
                 t.join()
         self._builders.shutdown(wait=wait)
+        self._freer.shutdown(wait=wait)
         if self._error is not None:
             raise self._error
 
     def stats(self) -> dict:
         b = np.array(self.batch_sizes or [0])
         return {"rounds": self.rounds, "mean_batch": float(b.mean()), "max_batch": int(b.max()),
-                "step_call_s": self.step_seconds,
+                "step_call_s": self.step_seconds, "build_thread_s": self.build_seconds,
+                "free_thread_s": self.free_seconds,
                 "peak_held_bytes": int(self.peak_held), "budget_bytes": self.budget,
                 "max_slots": self.max_slots}
 
@@ -204,6 +211,15 @@ class Server:
         return s
 
     def _build(self, job: _Job):
+        t0 = time.perf_counter()
+        try:
+            return self._build_body(job)
+        finally:
+            dt = time.perf_counter() - t0
+            with self._cv:
+                self.build_seconds += dt
+
+    def _build_body(self, job: _Job):
         import torch
         r = job.req
         s = self._build_stream()
@@ -219,7 +235,11 @@ class Server:
         return h, u
 
     def _destroy(self, handle):
+        t0 = time.perf_counter()
         handle.close()
+        dt = time.perf_counter() - t0
+        with self._cv:
+            self.free_seconds += dt
 
     # -- scheduler ---------------------------------------------------------------------------
     def _admit_locked(self):
@@ -259,10 +279,16 @@ class Server:
             self._cv.notify_all()
 
     def _release_locked(self, job: _Job):
+        self._release_slot_locked(job)
+        self._release_bytes_locked(job)
+
+    def _release_slot_locked(self, job: _Job):
         self._slots -= 1
+        self._free_streams.append(self._streams.index(job.stream))
+
+    def _release_bytes_locked(self, job: _Job):
         self._held -= job.held
         job.held = 0
-        self._free_streams.append(self._streams.index(job.stream))
 
     def _abandon_locked(self, job: _Job, exc: BaseException):
         """Fail an admitted job that will not run (its handle is freed, its slot returned)."""
@@ -285,8 +311,12 @@ class Server:
             res = Result(u, np.array(job.iters, np.int32), np.array(job.relres), job.t_arrival,
                          job.t_admit, job.t_ready, time.perf_counter(), job.held, r.tag)
         h, job.handle, job.u = job.handle, None, None
-        # hipFree waits for the whole device: release on a builder thread, off the batch loop
-        done = self._builders.submit(self._destroy, h)
+        # the slot is free at once; the memory counts against the budget until it is released
+        # (off the batch loop: the release waits for the device)
+        with self._cv:
+            self._release_slot_locked(job)
+            self._cv.notify_all()
+        done = self._freer.submit(self._destroy, h)
         done.add_done_callback(lambda _f, job=job: self._freed(job))
         if status == hifcn.HIF_OK:
             job.fut.set_result(res)
@@ -296,7 +326,7 @@ class Server:
 
     def _freed(self, job: _Job):
         with self._cv:
-            self._release_locked(job)
+            self._release_bytes_locked(job)
             self._cv.notify_all()
 
     @staticmethod
