@@ -380,11 +380,15 @@ __host__ __device__ inline int sym_smem_elems(int mat, int maxB) {
 }
 
 // Every element of the cell block into LDS: to both of its square positions (tab: this order's
-// entries, in storage order) or, with tab null, to its packed position.  sym_load issues the
-// loads (so that a stage can issue its other loads before it waits for them) and sym_store
-// makes the stores.  A block starts 16-byte aligned and its storage runs to sym_coff(tl), so
-// every vector lies inside it; the spare slots of the last chunk land on the spare word (tab) or
-// below the packed triangle's padded end (no tab), where nothing reads them.
+// entries, in storage order) or to its packed position.  sym_load issues the loads (so that a
+// stage can issue its other loads before it waits for them) and sym_store makes the stores.
+// Every lane issues every load, the vector index clamped to the block's last vector and the
+// table index to the table's last (a cell in the packed form reads the square's order's table
+// and ignores it): loads under a lane condition would make the compiler wait for every
+// outstanding load where the paths join, and move the gathers of the inputs behind the
+// block's loads.  A block starts 16-byte aligned and its storage runs to sym_coff(tl), so every
+// vector lies inside it; the spare slots of the last chunk land on the spare word (tab) or
+// below the packed triangle's padded end (packed), where nothing reads them.
 template <typename S>
 struct SymRegs {
   static constexpr int E = 16 / sizeof(S);  // elements per vector
@@ -396,30 +400,27 @@ struct SymRegs {
 
 template <typename S>
 __device__ __forceinline__ void sym_load(SymRegs<S>& R, const S* __restrict__ v, int tl,
-                                         const int32_t* __restrict__ tab, int lane) {
+                                         const int32_t* __restrict__ tab, int ttl, int lane) {
   constexpr int E = SymRegs<S>::E, P = SymRegs<S>::P;
   const int4* vv = reinterpret_cast<const int4*>(v);
-  const int nv = (tl + E - 1) / E;
+  const int last = max((tl + E - 1) / E - 1, 0), tlast = max((ttl + E - 1) / E - 1, 0);
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     const int q = lane + 64 * u;
-    if (q < nv) {
-      R.e[u] = vv[q];
-      if (tab) {
-        if constexpr (E == 2) {
-          const int2 w = reinterpret_cast<const int2*>(tab)[q];
-          R.t[u][0] = w.x;
-          R.t[u][1] = w.y;
-        } else {
+    R.e[u] = vv[min(q, last)];
+    const int tq = min(q, tlast);
+    if constexpr (E == 2) {
+      const int2 w = reinterpret_cast<const int2*>(tab)[tq];
+      R.t[u][0] = w.x;
+      R.t[u][1] = w.y;
+    } else {
 #pragma unroll
-          for (int h = 0; h < E / 4; ++h) {
-            const int4 w = reinterpret_cast<const int4*>(tab)[q * (E / 4) + h];
-            R.t[u][4 * h] = w.x;
-            R.t[u][4 * h + 1] = w.y;
-            R.t[u][4 * h + 2] = w.z;
-            R.t[u][4 * h + 3] = w.w;
-          }
-        }
+      for (int h = 0; h < E / 4; ++h) {
+        const int4 w = reinterpret_cast<const int4*>(tab)[tq * (E / 4) + h];
+        R.t[u][4 * h] = w.x;
+        R.t[u][4 * h + 1] = w.y;
+        R.t[u][4 * h + 2] = w.z;
+        R.t[u][4 * h + 3] = w.w;
       }
     }
   }
@@ -449,12 +450,6 @@ __device__ __forceinline__ void sym_store(C* sq, const SymRegs<S>& R, int tl, bo
       }
     }
   }
-}
-
-// The table entries of interior order n (n <= cfg.n): the square's own order from the offset
-// kept with the level (no dependent load before the block's loads), any other from the header.
-__device__ __forceinline__ const int32_t* sym_tab(const SymCfg& cfg, int n) {
-  return cfg.tab + (n == cfg.n ? cfg.sqoff : cfg.tab[n]);
 }
 
 // (M t)_lane for lane < n from the square (leading dimension ld): row `lane` against t
@@ -544,16 +539,15 @@ __device__ __forceinline__ void cell_fwd_sym(const CellDesc& d, const int32_t* _
   } else if (!own_ys && lane < nI) {
     gi = gI[lane];
   }
-  const bool square = nI <= cfg.n;
+  // the record's mode word: where the cell's order's table entries start (-1: packed form)
+  const bool square = d.mode >= 0;
   SymRegs<S> R;
-  sym_load<S>(R, v, tl, square ? sym_tab(cfg, nI) : nullptr, lane);
+  sym_load<S>(R, v, tl, cfg.tab + (square ? d.mode : cfg.sqoff),
+              square ? tl : (int)tri_count(cfg.n), lane);
   if (!own_ys && !pre && lane < nI) yv = src[gi];
-  int ib0 = 0;
-  C a0 = 0;
-  if (lane < nB) {
-    ib0 = ibp[lane];
-    a0 = load_as<C>(cw + lane);
-  }
+  const int lb = min(lane, max(nB - 1, 0));  // (clamped: no load under a lane condition)
+  int ib0 = ibp[lb];
+  C a0 = load_as<C>(cw + lb);
   if (!own_ys && pre) ts[lane] = (C)yv;
   sym_store<S, C>(sq, R, tl, square, lane);
   if (!own_ys && !pre) ts[lane] = (C)yv;
@@ -603,8 +597,9 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
     xi = x[lane < nI ? r0 : g0];
     xv = x[lane < nB ? gb : g0];
     if (lane >= nI) xi = 0;
-    if (lane < nI) w = lw[lane];
-    if (lane < nB) ab = load_as<C>(v + sym_coff(tl) + lane);
+    w = lw[min(lane, nI - 1)];  // (clamped: no load under a lane condition)
+    ab = load_as<C>(v + sym_coff(tl) + min(lane, nB - 1));
+    if (lane >= nI) w = 0;
   } else if (lane < nI) {
     gi = gI[lane];
     w = lw[lane];
@@ -623,9 +618,10 @@ __device__ __forceinline__ void cell_bwd_sym(const CellDesc& d, const int32_t* _
   }
   if (top.pos)
     for (int e = lane; e < top.ne; e += 64) x[top.ext[2 * e + 1]] = top.sum(top.ext[2 * e]);
-  const bool square = nI <= cfg.n;
+  const bool square = d.mode >= 0;  // see cell_fwd_sym
   SymRegs<S> R;
-  sym_load<S>(R, v, tl, square ? sym_tab(cfg, nI) : nullptr, lane);
+  sym_load<S>(R, v, tl, cfg.tab + (square ? d.mode : cfg.sqoff),
+              square ? tl : (int)tri_count(cfg.n), lane);
   if (fast && lane < nB) {
     xbs[lane] = (C)xv;
     abs_[lane] = ab;
@@ -2649,11 +2645,15 @@ int cell_record_len(const CellDesc& d) {
 int cell_fwd_len(const CellDesc& d) {
   return round_up(8 + d.nI + (d.mode == 2 ? 2 * d.nB : d.mode ? d.nB : 0), 4);
 }
-void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& idx) {
+void put_cell_record(int32_t* r, const CellDesc& d, const std::vector<int32_t>& idx,
+                     const LevelDev* sym = nullptr) {
   CellDesc e = d;
   e.offI = 8;
   for (int i = 0; i < d.nI; ++i) r[8 + i] = idx[d.offI + i];
   if (d.mode == 2) {
+    HIF_REQUIRE(sym && (int)sym->sqhead.size() == kSymTabHead, HIF_ERR_ARG,
+                "internal: symmetric cell record without its table");
+    e.mode = d.nI <= sym->sqn ? sym->sqhead[d.nI] : -1;  // see SymCfg
     e.offB = 8 + d.nI;
     e.offC = 8 + d.nI + d.nB;
     for (int b = 0; b < d.nB; ++b) r[e.offB + b] = idx[d.offB + b];
@@ -2711,7 +2711,7 @@ void setup_fusion(FactorDev& f, const std::vector<std::vector<CellDesc>>& cells,
     }
     std::vector<int32_t> cr((size_t)cells[l].size() * L.cstride, 0);
     for (size_t c = 0; c < cells[l].size(); ++c)
-      put_cell_record(cr.data() + c * L.cstride, cells[l][c], idx);
+      put_cell_record(cr.data() + c * L.cstride, cells[l][c], idx, &L);
     L.crec.upload(cr, s);
     L.gstride = 8;
     for (const GroupDesc& g : groups[l]) L.gstride = std::max(L.gstride, group_record_len(g, idx));

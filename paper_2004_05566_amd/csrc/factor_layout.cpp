@@ -146,6 +146,7 @@ void build_sym_table(FactorDev& f, const std::vector<CellDesc>& cells, hipStream
     tab.resize((tab.size() + 3) / 4 * 4, 0);
   }
   L.sqoff = tab[L.sqn];
+  L.sqhead.assign(tab.begin(), tab.begin() + kSymTabHead);
   f.sqtab.upload(tab, s);
 }
 

@@ -51,6 +51,7 @@ struct LevelDev {
   // leading dimension sqld (odd), larger ones stay packed; sqmat: LDS elements for either
   int sqn = 0, sqld = 0, sqmat = 0;
   int sqoff = 0;  // start of order sqn's entries in f.sqtab (its header entry, kept on the host)
+  std::vector<int32_t> sqhead;  // f.sqtab's header on the host (written into the records)
   // group stages as one dense product G (forward) / G^T (backward) per group (setup_dense_groups)
   int gdense = 0;
 };
@@ -198,6 +199,9 @@ struct SymCfg {
   int n, ld, mat;
   int sqoff;  // tab[n]: where the entries of the square's own order start
 };
+// In the records of a level of symmetric cells the descriptor's mode word holds the start of
+// the cell's order's entries in the table (from the header; at least kSymTabHead), or -1 for a
+// cell above the square's order (packed triangle).
 // The table's header: entry n (1 <= n <= SymCfg::n) is where the entries of interior order n
 // start (a multiple of 4).
 constexpr int kSymTabHead = (kSymMaxCell + 1 + 3) / 4 * 4;
