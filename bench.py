@@ -377,6 +377,23 @@ def drift(w, steps, everies, store, amp=0.5):
     return out
 
 
+def apply_loop(name: str, store: str, reps: int):
+    """The factor of a workload, then `reps` applies to one vector (counter runs)."""
+    import torch
+    from paper_2004_05566_amd import hifcn
+    from workloads import gen
+    w = gen.workload(name)
+    h = hifcn.factor(torch.tensor(w.a_cells, device="cuda"), w.dt, w.n, w.dim, w.eps,
+                     store=store, leaf=w.leaf)
+    x = torch.tensor(gen.normal_vector(w.N, 1), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        h.apply(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"apply_loop": name, "store": store, "applies": reps}), flush=True)
+    h.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +424,9 @@ def main(argv=None):
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration)")
+    ap.add_argument("--apply-loop", type=int, default=0,
+                    help="only build the workload's factor and run this many applies (plain "
+                         "launches on one stream, for hardware-counter runs)")
     ap.add_argument("--replica", default="",
                     help="only run the paper's Sec. 3 experiments, e.g. '2d:511,1023;3d:63' "
                          "(one JSON line per case; --steps steps each, --store storage)")
@@ -418,6 +438,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return 0
+    if args.apply_loop:
+        apply_loop(args.workload, args.store, args.apply_loop)
         return 0
     if args.gpus != 1:
         print(json.dumps({"error": "hifcn runs on one GPU; --gpus must be 1"}))
