@@ -17,10 +17,14 @@
 // Root: chol of the last remaining block (eq3_4).  The host plans the index structure between
 // launches; only ranks and pivot orders come back from the device once per level.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <list>
+#include <memory>
+#include <mutex>
 #include <unordered_map>
 
 #include "front.hpp"
@@ -715,6 +719,41 @@ void upload(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
 
 int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 
+// Level-0 plans by grid.  A level-0 plan depends on the geometry only, so factors of one grid
+// (the requests of one size on a server, the rebuilds of a drifting coefficient) share it.
+// The most recently used plans are kept, up to 8M DOFs of grids in all.
+std::shared_ptr<const LevelPlan> level0_plan(const Geometry& geo) {
+  using Key = std::array<int, 5>;
+  static std::mutex mu;
+  static std::list<std::pair<Key, std::shared_ptr<const LevelPlan>>> kept;  // most recent first
+  const Key key{geo.dim, geo.n, geo.m, geo.L, geo.skel_edges ? 1 : 0};
+  auto dofs = [](const Key& k) {
+    int64_t N = 1;
+    for (int d = 0; d < k[0]; ++d) N *= k[1];
+    return N;
+  };
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto it = kept.begin(); it != kept.end(); ++it)
+      if (it->first == key) {
+        kept.splice(kept.begin(), kept, it);
+        return kept.front().second;
+      }
+  }
+  auto plan = std::make_shared<const LevelPlan>(plan_level0(geo));
+  constexpr int64_t kKeepDofs = int64_t(1) << 23;
+  if (dofs(key) > kKeepDofs) return plan;
+  std::lock_guard<std::mutex> lock(mu);
+  kept.emplace_front(key, plan);
+  int64_t total = 0;
+  for (auto it = kept.begin(); it != kept.end();) {
+    total += dofs(it->first);
+    if (total > kKeepDofs) it = kept.erase(it);
+    else ++it;
+  }
+  return plan;
+}
+
 }  // namespace
 
 // Build the factor of the handle's operator on the device and lay it out for the apply.
@@ -755,8 +794,9 @@ void gpu_build(Handle& hd, const double* a_cells, hif_store_t store, hipStream_t
                 std::string("non-positive Cholesky pivot during ") + where);
   };
 
-  LevelPlan P = hd.plan0 ? LevelPlan(*hd.plan0) : plan_level0(geo);
-  if (hd.keep_plan0 && !hd.plan0) hd.plan0 = std::make_shared<const LevelPlan>(P);
+  const std::shared_ptr<const LevelPlan> plan0 = hd.plan0 ? hd.plan0 : level0_plan(geo);
+  LevelPlan P(*plan0);
+  if (hd.keep_plan0 && !hd.plan0) hd.plan0 = plan0;
   mark("plan", 0);
   DevBuf<double> A(std::max<int64_t>(1, P.nvals), s);
   {  // level-0 blocks straight from the stencil
