@@ -301,13 +301,15 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
                                                             CgFinish fin) {
   __shared__ int stop;
   const bool post = fin.hflag && blockIdx.x == 0 && threadIdx.x == 0;
-  // the lane's first elements of r (z = r) and x (u = x) load with the flags and partials
+  // the lane's first elements of r (z = r, as a 16-byte pair) and x (u = x) load with the flags
+  // and partials
   const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  double r0 = 0, x0 = 0;
-  if (i0 < N) {
-    r0 = r[i0];
-    if (fin.hflag) x0 = fin.x[i0];
-  }
+  const int64_t N2 = N / 2;
+  const double2* __restrict__ r2 = reinterpret_cast<const double2*>(r);
+  double x0 = 0;
+  double2 rp{0, 0};
+  if (i0 < N2) rp = r2[i0];
+  if (i0 < N && fin.hflag) x0 = fin.x[i0];
   if (fin.hflag && st->hold) return;  // queued ahead of a step that did not end well
   if (init) {  // the test of the right-hand side publishes the state of the new step
     if (st->hold) {  // (queued ahead, see k_cg_rhs): later kernels of the step do nothing
@@ -352,7 +354,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     st->ok_next = 0;
     post_flag(fin.hflag, fin.seq, it0 + 1, 0, 0);
   }
-  for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) z[i] = i == i0 ? r0 : r[i];
+  // z = r in 16-byte pairs, four in flight per lane (r and z are 16-byte aligned)
+  double2* __restrict__ z2 = reinterpret_cast<double2*>(z);
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  if (i0 < N2) z2[i0] = rp;
+  int64_t i = i0 + stride;
+  for (; i + 3 * stride < N2; i += 4 * stride) {
+    const double2 a = r2[i], b = r2[i + stride], c = r2[i + 2 * stride], d = r2[i + 3 * stride];
+    z2[i] = a;
+    z2[i + stride] = b;
+    z2[i + 2 * stride] = c;
+    z2[i + 3 * stride] = d;
+  }
+  for (; i < N2; i += stride) z2[i] = r2[i];
+  if ((N & 1) && i0 == 0) z[N - 1] = r[N - 1];
 }
 
 // w = A z and the partial sums of r.z, z.w and (after the first iteration) z.q.  Runs whether
