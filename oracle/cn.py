@@ -6,6 +6,8 @@ and solves (I - dt/2 M) u^{k+1} = g by preconditioned conjugate gradient (Algori
 PCG details the paper leaves open, as read here: standard PCG with x0 = 0, beta = rho_new/rho;
 stop as soon as the recurrence residual satisfies ||r_i||_2 <= rtol ||g||_2; the iteration
 count n_i is the number of products of A with a search direction; g = 0 gives u = 0 and n_i = 0.
+Optionally (warm start, off by default) x0 = u^k, the state before the step: r_0 = g - A x0,
+the same test against rtol ||g||_2 (already met at r_0: n_i = 0, u^{k+1} = u^k).
 """
 from __future__ import annotations
 
@@ -40,16 +42,26 @@ class PcgResult:
     converged: bool
 
 
-def pcg(A, b: np.ndarray, precond, rtol: float, maxit: int = 500) -> PcgResult:
+def pcg(A, b: np.ndarray, precond, rtol: float, maxit: int = 500, x0=None) -> PcgResult:
     """Preconditioned CG for SPD A (the pcg(A, b, P) of Algorithm 1).
 
-    ``A`` is anything supporting ``A @ x``; ``precond(r)`` returns P r.
+    ``A`` is anything supporting ``A @ x``; ``precond(r)`` returns P r.  ``x0``: the initial
+    guess (None: 0); with one, r_0 = b - A x0 and PCG stops at once if ||r_0|| <= rtol ||b||.
     """
     nb = float(np.linalg.norm(b))
     x = np.zeros_like(b)
     if nb == 0.0:
         return PcgResult(x, 0, 0.0, True)
-    r = b.copy()
+    if x0 is None:
+        r = b.copy()
+    else:
+        x = np.array(x0, dtype=np.float64).copy()
+        r = b - A @ x
+        nr0 = float(np.linalg.norm(r))
+        if not np.isfinite(nr0):
+            return PcgResult(x, 0, nr0 / nb, False)
+        if nr0 <= rtol * nb:
+            return PcgResult(x, 0, nr0 / nb, True)
     z = precond(r)
     p = z.copy()
     rho = float(r @ z)
@@ -73,8 +85,9 @@ def pcg(A, b: np.ndarray, precond, rtol: float, maxit: int = 500) -> PcgResult:
 
 
 def cn_solve(A, B, u0: np.ndarray, dt: float, steps: int, precond, rtol: float,
-             react=(0, 0.0, 0.0), maxit: int = 500):
-    """Algorithm 1: for k = 1..steps, g = B u^{k-1} + dt r^{k-1}; u^k = pcg(A, g, F^-1).
+             react=(0, 0.0, 0.0), maxit: int = 500, warm_start: bool = False):
+    """Algorithm 1: for k = 1..steps, g = B u^{k-1} + dt r^{k-1}; u^k = pcg(A, g, F^-1)
+    (with warm_start, from the initial guess u^{k-1}).
 
     Returns (u_steps, iters, relres) with u_steps[k] = u^k (u_steps[0] = u0).
     """
@@ -83,7 +96,7 @@ def cn_solve(A, B, u0: np.ndarray, dt: float, steps: int, precond, rtol: float,
     iters, rel = [], []
     for _ in range(steps):
         g = cn_rhs(B, u, dt, react)
-        res = pcg(A, g, precond, rtol, maxit)
+        res = pcg(A, g, precond, rtol, maxit, x0=u if warm_start else None)
         if not res.converged:
             raise NoConvergence(f"PCG did not converge in {maxit} iterations")
         u = res.x

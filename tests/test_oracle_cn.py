@@ -100,6 +100,46 @@ def test_pcg_exact_preconditioner_one_iteration_and_zero_rhs():
     assert res0.iters == 0 and not res0.x.any()
 
 
+def test_pcg_initial_guess_exact_preconditioner_and_exact_guess():
+    """Warm start (x0 given): with F = A (eps = 0) one iteration lands on A^-1 b from any x0,
+    which fixes r0 = b - A x0 (a wrong sign or a missing product misses A^-1 b); the exact
+    solution as x0 takes no iteration; b = 0 gives x = 0 whatever x0."""
+    n = 15
+    a = gen.iid_loguniform_cells(n, 2, 4)
+    A, _ = fd.cn_matrices(a, 0.1)
+    F = phif.phif_build(A, n, 2, 4, 0.0)
+    rng = np.random.default_rng(1)
+    b = rng.normal(size=n * n)
+    xs = spla.spsolve(A.tocsc(), b)
+    x0 = rng.normal(size=n * n)
+    res = cn.pcg(A, b, lambda r: phif.phif_apply(F, r), 1e-12, x0=x0)
+    assert res.converged and res.iters == 1
+    assert np.abs(res.x - xs).max() <= 1e-10 * np.abs(xs).max()
+    res = cn.pcg(A, b, lambda r: phif.phif_apply(F, r), 1e-12, x0=xs)
+    assert res.converged and res.iters == 0 and np.array_equal(res.x, xs)
+    res = cn.pcg(A, np.zeros(n * n), lambda r: phif.phif_apply(F, r), 1e-12, x0=x0)
+    assert res.converged and res.iters == 0 and not res.x.any()
+
+
+def test_warm_started_steps_within_the_tolerance_of_direct_steps():
+    """x0 = u^k: every step's solution is within rtol ||g|| of the exact step solution
+    (A = I - dt/2 M >= I, so ||A^-1|| <= 1), as it is from x0 = 0."""
+    n, dt, steps, rtol = 31, 0.05, 3, 1e-8
+    a = gen.grf_coefficient(n, 2, 0.15, 12)
+    A, B = fd.cn_matrices(a, dt)
+    F = phif.phif_build(A, n, 2, 8, 1e-3)
+    u0 = gen.bumps(n, 2, 3, 13)
+    react = (1, 1.0, 1.0)
+    us, its, _ = cn.cn_solve(A, B, u0, dt, steps, lambda r: phif.phif_apply(F, r), rtol, react,
+                             warm_start=True)
+    lu = spla.splu(A.tocsc())
+    for k in range(steps):
+        g = cn.cn_rhs(B, us[k], dt, react)
+        exact = lu.solve(g)
+        assert np.linalg.norm(us[k + 1] - exact) <= 1.01 * rtol * np.linalg.norm(g)
+    assert min(its) >= 1
+
+
 def test_pcg_unpreconditioned_matches_textbook_cg_solution():
     n = 10
     A, _ = fd.cn_matrices(np.ones((n + 1, n + 1)), 0.01)
