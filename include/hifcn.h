@@ -57,8 +57,11 @@ typedef struct hif_handle_s* hif_handle_t;
 /* Reaction term r(u) (eq1, eq_nr): kind 0 -> none; kind 1 -> k1 u (1 - u/k2). */
 typedef struct { int32_t kind; double k1; double k2; } hif_reaction_t;
 
-/* PCG options (Algorithm 1): stop when ||r_i||_2 <= rtol ||g||_2 (recurrence residual),
- * x0 = 0, at most maxit iterations (1 .. 2^24 - 1).  warm_start must be 0 (reserved). */
+/* PCG options (Algorithm 1): stop when ||r_i||_2 <= rtol ||g||_2 (recurrence residual), at
+ * most maxit iterations (1 .. 2^24 - 1).  warm_start 0: x0 = 0 (the default reading of
+ * Algorithm 1's pcg); 1: x0 = u^k, the state before the step (r0 = g - A u^k, the same test;
+ * a step whose r0 already meets it takes no iteration and keeps u; g = 0 still gives u = 0).
+ * cn_step and cn_solve take either; cn_batch_step requires 0 (HIF_ERR_ARG otherwise). */
 typedef struct { double rtol; int32_t maxit; int32_t warm_start; } hif_cg_opts_t;
 
 /* Build the PHIF factor of A = I - dt/2 M (Sec. 2.2: per level cell elimination, block Jacobi,

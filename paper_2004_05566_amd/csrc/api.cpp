@@ -140,11 +140,14 @@ void setup_rhs(Handle& h) {
 // run by the apply's first stage when the factor allows it, else as its own launch.  Every
 // workgroup of that stage reads all partials of the test, so it stays a launch of its own where
 // that would add up to more than ~8 MB (many level-0 cells: the 1024^2 grid has 16K).
-void check_and_apply(Handle& h, int it, double rtol, int maxit, hipStream_t s) {
-  if (h.f.gate && h.f.gate_n == h.N && (int64_t)h.f.lv[0].ncell * h.nblk <= (int64_t(1) << 20)) {
+// A warm-started step's initial test (two totals) is always a launch of its own.
+void check_and_apply(Handle& h, int it, double rtol, int maxit, hipStream_t s,
+                     bool warm = false) {
+  if (!(warm && it < 0) && h.f.gate && h.f.gate_n == h.N &&
+      (int64_t)h.f.lv[0].ncell * h.nblk <= (int64_t(1) << 20)) {
     hif_apply_gated(h.f, h.z.p, cg_gate_args(h, it, rtol, maxit), s);
   } else {
-    launch_cg_check_copy(h, it, rtol, maxit, s);
+    launch_cg_check_copy(h, it, rtol, maxit, s, warm);
     hif_apply_inplace(h.f, h.z.p, &h.st.p->done, s);
   }
 }
@@ -155,7 +158,8 @@ void step_begin(StepState& st, bool ahead = false) {
   Handle& h = *st.h;
   const int kind = st.r ? st.r->kind : 0;
   const double k1 = st.r ? st.r->k1 : 0, k2 = st.r ? st.r->k2 : 1;
-  if (h.rhs_fused) {  // the first apply stage makes g (the first update then tests it)
+  const bool warm = st.o->warm_start != 0;  // x0 = u^k: the right-hand side launch forms r0
+  if (h.rhs_fused && !warm) {  // the first apply stage makes g (the first update then tests it)
     CgRhs c;
     c.u = st.u;
     c.links = h.links.p;
@@ -173,8 +177,8 @@ void step_begin(StepState& st, bool ahead = false) {
     c.ahead = ahead ? 1 : 0;
     hif_apply_rhs(h.f, h.z.p, c, st.s);
   } else {
-    launch_cg_rhs(h, st.u, kind, k1, k2, ahead, st.s);
-    check_and_apply(h, -1, st.o->rtol, st.o->maxit, st.s);
+    launch_cg_rhs(h, st.u, kind, k1, k2, ahead, st.s, warm);
+    check_and_apply(h, -1, st.o->rtol, st.o->maxit, st.s, warm);
   }
   st.chunk = std::max(1, h.last_iters);
 }
@@ -182,6 +186,7 @@ void step_begin(StepState& st, bool ahead = false) {
 // Queue the next chunk of iterations and the read-back of [iters, done, status].
 void step_queue(StepState& st) {
   Handle& h = *st.h;
+  const bool warm = st.o->warm_start != 0;
   if (st.tail_open) {  // the previous chunk's last iteration did not converge
     launch_cg_resume(h, st.s);  // (a step queued ahead may have stopped everything meanwhile)
     hif_apply_inplace(h.f, h.z.p, &h.st.p->done, st.s);
@@ -190,11 +195,11 @@ void step_queue(StepState& st) {
   for (int c = 0; c < st.chunk && st.launched < st.o->maxit; ++c) {
     const int it = st.launched++;
     launch_cg_dir_dots(h, it, st.s);
-    launch_cg_update(h, it, st.o->rtol, st.s);
+    launch_cg_update(h, it, st.o->rtol, st.s, h.rhs_fused && !warm);
     if (c + 1 == st.chunk || st.launched == st.o->maxit) {
       // the host reads the verdict before it queues another apply
       st.seq = ++h.flag_seq;
-      launch_cg_check_finish(h, it, st.o->rtol, st.u, st.step, st.seq, st.s);
+      launch_cg_check_finish(h, it, st.o->rtol, st.u, st.step, st.seq, st.s, warm);
       st.tail_open = true;
       break;
     }
@@ -294,7 +299,8 @@ void check_opts(const hif_cg_opts_t* o) {
   HIF_REQUIRE(o != nullptr, HIF_ERR_ARG, "NULL cg options");
   HIF_REQUIRE(o->rtol > 0 && o->maxit > 0, HIF_ERR_ARG, "rtol and maxit must be positive");
   HIF_REQUIRE(o->maxit < (1 << 24), HIF_ERR_ARG, "maxit must be below 2^24");
-  HIF_REQUIRE(o->warm_start == 0, HIF_ERR_ARG, "warm_start is reserved and must be 0");
+  HIF_REQUIRE(o->warm_start == 0 || o->warm_start == 1, HIF_ERR_ARG,
+              "warm_start must be 0 (x0 = 0) or 1 (x0 = u^k)");
 }
 
 void check_reaction(const hif_reaction_t* r) {
@@ -661,6 +667,8 @@ hif_status_t cn_batch_step(hif_handle_t* hs, const hif_reaction_t* rs, const hif
     for (int i = 0; i < count; ++i) {
       HIF_REQUIRE(hs[i] && us[i], HIF_ERR_ARG, "NULL handle or state");
       check_opts(&os[i]);
+      HIF_REQUIRE(os[i].warm_start == 0, HIF_ERR_ARG,
+                  "cn_batch_step: warm start is available in cn_step and cn_solve only");
       if (rs) check_reaction(&rs[i]);
       for (int j = 0; j < i; ++j)
         HIF_REQUIRE(hs[j] != hs[i], HIF_ERR_ARG, "a handle appears twice in one batch");

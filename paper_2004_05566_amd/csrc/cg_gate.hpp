@@ -77,4 +77,24 @@ __device__ inline bool cg_verdict(CgState* st, int init, int it0, double rtol, d
   return stop;
 }
 
+// The test of a warm-started step (x0 = u^k): gtot = ||g||^2 sets the tolerance, rtot =
+// ||r0||^2 = ||g - A u^k||^2 is tested against it; the step ends at once when g = 0 (u = 0),
+// when r0 already meets it (u = u^k, no iteration) or when either total is not finite.
+__device__ inline bool cg_verdict_warm(CgState* st, double rtol, double gtot, double rtot,
+                                       int maxit, bool publish) {
+  const bool bad = cg_bad_total(gtot) || cg_bad_total(rtot);
+  const double tol2 = rtol * rtol * gtot;
+  const bool stop = bad || gtot == 0.0 || rtot <= tol2;
+  if (publish) {
+    st->gg = gtot;
+    st->tol2 = tol2;
+    st->rr = rtot;
+    st->iters = 0;
+    st->status = bad ? HIF_ERR_NO_CONV : 0;
+    st->maxit = maxit;
+    st->done = stop ? 1 : 0;
+  }
+  return stop;
+}
+
 }  // namespace hifcn

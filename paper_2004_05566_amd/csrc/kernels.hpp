@@ -392,17 +392,21 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
 int cg_partial_slots();
 // ahead: the step is queued before the previous one is known to have ended; it does nothing if
 // that one holds.
+// warm: r = g - A u (the warm-started step's r0) and its partials of ||r0||^2 beside ||g||^2.
 void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, bool ahead,
-                   hipStream_t s);
+                   hipStream_t s, bool warm = false);
 // Before more iterations of a step whose closing test held: done = hold = 0.
 void launch_cg_resume(Handle& h, hipStream_t s);
+// warm: the step started from x0 = u^k, so PCG runs on the correction d = x - u^k from 0
+// (r0 = g - A u^k); its initial test takes ||g||^2 and ||r0||^2.
 void launch_cg_check_copy(Handle& h, int it /* -1: initial */, double rtol, int maxit,
-                          hipStream_t s);
+                          hipStream_t s, bool warm = false);
 // The test closing a queued batch of iterations: as launch_cg_check_copy, and when the iteration
 // stops (here or earlier in the batch) u = x and the records of step `step`; then the outcome is
 // posted to the handle's host flag with sequence number seq.
+// warm: the step ends with u = u^k + d (u = 0 when g = 0).
 void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step, int seq,
-                            hipStream_t s);
+                            hipStream_t s, bool warm = false);
 // The same test as arguments of a gated apply.
 CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol, int maxit);
 // Iteration `it` after z = M^-1 r: w = A z with the partials of r.z, z.w, z.q, then the update
@@ -410,7 +414,8 @@ CgGate cg_gate_args(Handle& h, int it /* -1: initial */, double rtol, int maxit)
 void launch_cg_dir_dots(Handle& h, int it, hipStream_t s);
 // (rtol: for the first update of a step whose right-hand side the apply made, which also tests
 // g: it totals ||g||^2 and starts tol2.)
-void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s);
+// fused_g: the step's g was made by the first apply stage (iteration 0 then tests it)
+void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s, bool fused_g);
 // One solve's part of a batched PCG vector launch: its blocks are launch blocks first ..
 // first + nb - 1 (nb: the solve's own block count, so its reductions are those it makes alone).
 struct BatchCg {

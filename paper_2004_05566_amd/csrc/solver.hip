@@ -188,26 +188,31 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs(int n, int64_t N, const dou
                                                      const double* __restrict__ u,
                                                      double* __restrict__ r, double* __restrict__ x,
                                                      int kind, double k1, double k2, double dt,
-                                                     int ahead, CgState* st, double* part) {
+                                                     int ahead, int warm, CgState* st,
+                                                     double* part) {
   // queued ahead of the previous step's outcome: nothing to do unless that step ended well
   // (every block reads the same two fields, which no block writes here)
   const bool held = ahead && (!st->done || st->status);
   if (blockIdx.x == 0 && threadIdx.x == 0) st->hold = held ? 1 : 0;
   if (held) return;
-  double acc = 0;
+  double acc = 0, accr = 0;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (NodeWalk<DIM> a(blockIdx.x * (int64_t)kThreads + threadIdx.x, stride, n); a.i < N;
        a.next(n)) {
     const int64_t i = a.i;
     const double ui = u[i];
-    const double g = cn_rhs_value(ui, link_sum_at<DIM>(i, a.ix, a.iy, a.iz, n, w, ui,
-                                                       [&](int64_t k) { return u[k]; }),
-                                  dt, kind, k1, k2);
-    r[i] = g;
+    const double sl = link_sum_at<DIM>(i, a.ix, a.iy, a.iz, n, w, ui,
+                                       [&](int64_t k) { return u[k]; });
+    const double g = cn_rhs_value(ui, sl, dt, kind, k1, k2);
+    // warm start: r0 = g - A u (A u = u + the link sum), x0 = 0 for the correction
+    const double r0 = warm ? g - (ui + sl) : g;
+    r[i] = r0;
     x[i] = 0.0;
     acc += g * g;
+    accr += r0 * r0;
   }
   put_partial(acc, part + P_GG * (int64_t)gridDim.x);
+  if (warm) put_partial(accr, part + P_RR * (int64_t)gridDim.x);
 }
 
 // k_cg_rhs over x-pairs of nodes (n even; see k_spmv_pairs): the same g at every node.
@@ -218,11 +223,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs_pairs(int n, int64_t N,
                                                            double* __restrict__ r,
                                                            double* __restrict__ x, int kind,
                                                            double k1, double k2, double dt,
-                                                           int ahead, CgState* st, double* part) {
+                                                           int ahead, int warm, CgState* st,
+                                                           double* part) {
   const bool held = ahead && (!st->done || st->status);
   if (blockIdx.x == 0 && threadIdx.x == 0) st->hold = held ? 1 : 0;
   if (held) return;
-  double acc = 0;
+  double acc = 0, accr = 0;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   const double2* u2 = reinterpret_cast<const double2*>(u);
   auto U = [&](int64_t k) { return u[k]; };
@@ -235,12 +241,16 @@ __global__ __launch_bounds__(kThreads) void k_cg_rhs_pairs(int n, int64_t N,
     link_sum_pair<DIM>(a.i, a.ix, a.iy, a.iz, n, w, v, U, U2, s0, s1);
     const double g0 = cn_rhs_value(v.x, s0, dt, kind, k1, k2);
     const double g1 = cn_rhs_value(v.y, s1, dt, kind, k1, k2);
-    reinterpret_cast<double2*>(r)[a.i >> 1] = double2{g0, g1};
+    const double r0 = warm ? g0 - (v.x + s0) : g0, r1 = warm ? g1 - (v.y + s1) : g1;
+    reinterpret_cast<double2*>(r)[a.i >> 1] = double2{r0, r1};
     reinterpret_cast<double2*>(x)[a.i >> 1] = double2{0.0, 0.0};
     acc += g0 * g0;
     acc += g1 * g1;
+    accr += r0 * r0;
+    accr += r1 * r1;
   }
   put_partial(acc, part + P_GG * (int64_t)gridDim.x);
+  if (warm) put_partial(accr, part + P_RR * (int64_t)gridDim.x);
 }
 
 __global__ void k_cg_resume(CgState* st) {
@@ -266,13 +276,17 @@ __device__ void post_flag(int32_t* hflag, int seq, int iters, int done, int stat
 
 // The end of a CN step: u = x, and the iteration count and relative residual ||r|| / ||g|| of
 // step `step` recorded (block 0).  x0: the lane's first element of x, loaded already.  keep_u:
-// the step failed before its first iteration (a non-finite right-hand side), so u stays.
+// the step failed before its first iteration (a non-finite right-hand side), so u stays.  warm:
+// x is the correction of a step started from u^k, so u = u^k + x (u = 0 when g = 0).
 __device__ void finish_step(int64_t N, const double* __restrict__ x, double* __restrict__ u,
                             int iters, double rr, double gg, int32_t* it_out, double* rel_out,
-                            int step, double x0, bool keep_u = false) {
+                            int step, double x0, bool keep_u = false, bool warm = false) {
   const int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (!keep_u)
+  if (!keep_u && !warm)
     for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads) u[i] = i == i0 ? x0 : x[i];
+  if (!keep_u && warm)  // u^k + the correction, or 0 when g = 0
+    for (int64_t i = i0; i < N; i += (int64_t)gridDim.x * kThreads)
+      u[i] = gg == 0.0 ? 0.0 : u[i] + (i == i0 ? x0 : x[i]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     it_out[step] = iters;
     rel_out[step] = gg > 0 ? sqrt(rr / gg) : 0.0;
@@ -282,7 +296,8 @@ __device__ void finish_step(int64_t N, const double* __restrict__ x, double* __r
 // The convergence test closing a queued batch of iterations (fin != nullptr) also ends the step
 // when the iteration stops, here or at an earlier test of the batch: finish_step, then the post
 // to the host (block 0).  A closing test that finds hold set belongs to a step queued ahead of
-// one that did not end well, and does nothing.
+// one that did not end well, and does nothing.  warm: the step started from x0 = u^k (its
+// initial test takes ||g||^2 and ||r0||^2; its end adds the correction to u).
 struct CgFinish {
   int32_t* hflag;
   int seq;
@@ -298,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ z, CgState* st,
                                                             const double* __restrict__ part,
-                                                            CgFinish fin) {
+                                                            CgFinish fin, int warm) {
   __shared__ int stop;
   const bool post = fin.hflag && blockIdx.x == 0 && threadIdx.x == 0;
   // the lane's first elements of r (z = r, as a 16-byte pair) and x (u = x) load with the flags
@@ -319,7 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
   } else if (st->done) {  // stopped by an earlier test of the batch
     if (fin.hflag) {
       finish_step(N, fin.x, fin.u, st->iters, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step,
-                  x0, st->status != 0 && st->iters == 0);
+                  x0, st->status != 0 && st->iters == 0, warm != 0);
       if (post) {
         st->ok_next = st->status == 0;
         post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
@@ -333,16 +348,23 @@ __global__ __launch_bounds__(kThreads) void k_cg_check_copy(int64_t N, int init,
     const double* p = part + (init ? P_GG : P_RR) * (int64_t)nb;
     ct.load(p, nb);
     const double t = ct.sum(p, nb);
-    if (threadIdx.x == 0)
+    if (init && warm) {  // the test of r0 = g - A u^k against rtol ||g|| (g's total above)
+      CgTotal cr;
+      const double* q = part + P_RR * (int64_t)nb;
+      cr.load(q, nb);
+      const double tr = cr.sum(q, nb);
+      if (threadIdx.x == 0) stop = cg_verdict_warm(st, rtol, t, tr, maxit, blockIdx.x == 0);
+    } else if (threadIdx.x == 0) {
       stop = cg_verdict(st, init, it0, rtol, t, st->tol2, init ? maxit : st->maxit,
                         blockIdx.x == 0);
+    }
   }
   __syncthreads();
   if (stop) {
     if (fin.hflag) {
       // block 0 wrote the scalars it reads here; other blocks only copy x
       finish_step(N, fin.x, fin.u, it0 + 1, st->rr, st->gg, fin.it_out, fin.rel_out, fin.step,
-                  x0);
+                  x0, false, warm != 0);
       if (post) {
         st->ok_next = st->status == 0;
         post_flag(fin.hflag, fin.seq, st->iters, 1, st->status);
@@ -852,27 +874,28 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
 }
 
 void launch_cg_rhs(Handle& h, const double* u, int kind, double k1, double k2, bool ahead,
-                   hipStream_t s) {
+                   hipStream_t s, bool warm) {
   auto k = use_pairs(h, {u, h.r.p, h.x.p}) ? (h.dim == 2 ? k_cg_rhs_pairs<2> : k_cg_rhs_pairs<3>)
                         : (h.dim == 2 ? k_cg_rhs<2> : k_cg_rhs<3>);
   hipLaunchKernelGGL(k, dim3(h.nblk), dim3(kThreads), 0, s, h.n, h.N, h.links.p, u, h.r.p, h.x.p,
-                     kind, k1, k2, h.dt, ahead ? 1 : 0, h.st.p, h.partials.p);
+                     kind, k1, k2, h.dt, ahead ? 1 : 0, warm ? 1 : 0, h.st.p, h.partials.p);
 }
 
 void launch_cg_resume(Handle& h, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_resume, dim3(1), dim3(64), 0, s, h.st.p);
 }
 
-void launch_cg_check_copy(Handle& h, int it, double rtol, int maxit, hipStream_t s) {
+void launch_cg_check_copy(Handle& h, int it, double rtol, int maxit, hipStream_t s,
+                          bool warm) {
   hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, it < 0 ? 1 : 0, it,
-                     rtol, maxit, h.r.p, h.z.p, h.st.p, h.partials.p, CgFinish{});
+                     rtol, maxit, h.r.p, h.z.p, h.st.p, h.partials.p, CgFinish{}, warm ? 1 : 0);
 }
 
 void launch_cg_check_finish(Handle& h, int it, double rtol, double* u, int step, int seq,
-                            hipStream_t s) {
+                            hipStream_t s, bool warm) {
   const CgFinish fin{h.flag_dev, seq, h.x.p, u, h.step_iters.p, h.step_relres.p, step};
   hipLaunchKernelGGL(k_cg_check_copy, dim3(h.nblk), dim3(kThreads), 0, s, h.N, 0, it, rtol, 0,
-                     h.r.p, h.z.p, h.st.p, h.partials.p, fin);
+                     h.r.p, h.z.p, h.st.p, h.partials.p, fin, warm ? 1 : 0);
 }
 
 CgGate cg_gate_args(Handle& h, int it, double rtol, int maxit) {
@@ -896,8 +919,8 @@ void launch_cg_dir_dots(Handle& h, int it, hipStream_t s) {
                      h.q.p, h.w.p, h.partials.p);
 }
 
-void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s) {
-  const bool g = it == 0 && h.rhs_fused;
+void launch_cg_update(Handle& h, int it, double rtol, hipStream_t s, bool fused_g) {
+  const bool g = it == 0 && fused_g;
   const bool pairs = h.N % 2 == 0 && use_pairs_ptrs({h.z.p, h.w.p, h.p.p, h.q.p, h.x.p, h.r.p});
   hipLaunchKernelGGL(pairs ? k_cg_update_pairs : k_cg_update, dim3(h.nblk), dim3(kThreads), 0, s,
                      h.N, it, h.z.p, h.w.p,

@@ -176,10 +176,11 @@ class Handle:
         return out
 
     def cn_solve(self, u, nsteps: int, rtol: float = 1e-8, maxit: int = 500,
-                 reaction=(0, 0.0, 1.0), stream=None):
-        """Advance u (in place) by nsteps Crank-Nicolson steps; returns (iters, relres)."""
+                 reaction=(0, 0.0, 1.0), stream=None, warm_start: bool = False):
+        """Advance u (in place) by nsteps Crank-Nicolson steps; returns (iters, relres).
+        warm_start: PCG starts from x0 = u^k instead of 0."""
         r = _Reaction(int(reaction[0]), float(reaction[1]), float(reaction[2]))
-        o = _CgOpts(float(rtol), int(maxit), 0)
+        o = _CgOpts(float(rtol), int(maxit), 1 if warm_start else 0)
         its = np.zeros(max(1, nsteps), np.int32)
         rel = np.zeros(max(1, nsteps), np.float64)
         st = _lib.cn_solve(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u", self.N),
@@ -210,9 +211,9 @@ class Handle:
                                     _stream(stream)))
 
     def cn_step(self, u, rtol: float = 1e-8, maxit: int = 500, reaction=(0, 0.0, 1.0),
-                stream=None):
+                stream=None, warm_start: bool = False):
         r = _Reaction(int(reaction[0]), float(reaction[1]), float(reaction[2]))
-        o = _CgOpts(float(rtol), int(maxit), 0)
+        o = _CgOpts(float(rtol), int(maxit), 1 if warm_start else 0)
         it = ctypes.c_int32()
         rel = ctypes.c_double()
         _check(_lib.cn_step(self._p(), ctypes.byref(r), ctypes.byref(o), _dev_f64(u, "u", self.N),
