@@ -12,27 +12,18 @@
 #include <vector>
 
 #include "../../include/hifcn.h"
+#include "errors.hpp"
 
 namespace hifcn {
 
 // ---------------------------------------------------------------------------------------------
-// Errors: internal code throws HifError; the C entry points translate it to a status code.
-struct HifError : std::runtime_error {
-  hif_status_t status;
-  HifError(hif_status_t s, const std::string& m) : std::runtime_error(m), status(s) {}
-};
-
+// Errors of HIP calls become HifError (errors.hpp) with HIF_ERR_OOM or HIF_ERR_HIP.
 #define HIF_CHECK(expr)                                                                       \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \
     if (e_ != hipSuccess)                                                                     \
       throw ::hifcn::HifError(e_ == hipErrorOutOfMemory ? HIF_ERR_OOM : HIF_ERR_HIP,          \
                               std::string(#expr) + ": " + hipGetErrorString(e_));             \
-  } while (0)
-
-#define HIF_REQUIRE(cond, status, msg)                                                        \
-  do {                                                                                        \
-    if (!(cond)) throw ::hifcn::HifError((status), (msg));                                    \
   } while (0)
 
 // ---------------------------------------------------------------------------------------------

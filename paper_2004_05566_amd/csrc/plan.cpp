@@ -4,7 +4,7 @@
 #include <algorithm>
 #include <numeric>
 
-#include "common.hpp"
+#include "errors.hpp"
 
 namespace hifcn {
 
