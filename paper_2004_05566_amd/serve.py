@@ -12,7 +12,10 @@ eq1 and eq_CN, Sec. 2.1) preconditioned by its own HIF factor (Sec. 2.2).  The s
     from the leaves; PCG iterations in lockstep, one convergence read-back per round for the
     whole batch), and newly built solves join at the next round; optionally several scheduler
     lanes (solves of similar size share one) run their batches concurrently,
-  * copies a finished solve's state to the host, resolves its future and frees its memory.
+  * copies a finished solve's state to the host, resolves its future and frees its memory,
+  * honours Future.cancel() at any time before the future is resolved: a waiting request is
+    dropped, one being built is freed once its build ends, a running one leaves the batch before
+    the next round (its slot and memory are released like a finished solve's).
 
 A solve's arithmetic does not depend on the other solves in the batch (every kernel touches only
 its own handle's buffers and every reduction has a fixed order), so its result is bitwise the
@@ -24,7 +27,7 @@ from __future__ import annotations
 import collections
 import threading
 import time
-from concurrent.futures import Future, ThreadPoolExecutor
+from concurrent.futures import Future, InvalidStateError, ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -105,7 +108,8 @@ class Server:
 
     `lanes` scheduler threads each advance their own batch of resident solves (solves of similar
     size share a lane) with the batched step entry point, concurrently with each other.
-    submit() returns a concurrent.futures.Future resolved with a Result (or the error)."""
+    submit() returns a concurrent.futures.Future resolved with a Result (or the error); its
+    cancel() withdraws the request until the future is resolved."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 32, builders: int = 2,
                  device: int = 0, paused: bool = False, lanes: int = 1, dense_top: int = 0):
@@ -137,6 +141,7 @@ class Server:
         self.step_seconds = 0.0  # time spent in the batched step calls
         self.build_seconds = 0.0  # builder-thread time in factor builds
         self.free_seconds = 0.0   # builder-thread time releasing finished solves
+        self.cancelled = 0        # requests withdrawn by Future.cancel()
         self.peak_held = 0
         self._error: BaseException | None = None
         self.lanes = max(1, int(lanes))
@@ -198,7 +203,7 @@ class Server:
         b = np.array(self.batch_sizes or [0])
         return {"rounds": self.rounds, "mean_batch": float(b.mean()), "max_batch": int(b.max()),
                 "step_call_s": self.step_seconds, "build_thread_s": self.build_seconds,
-                "free_thread_s": self.free_seconds,
+                "free_thread_s": self.free_seconds, "cancelled": self.cancelled,
                 "peak_held_bytes": int(self.peak_held), "budget_bytes": self.budget,
                 "max_slots": self.max_slots}
 
@@ -243,6 +248,14 @@ class Server:
 
     # -- scheduler ---------------------------------------------------------------------------
     def _admit_locked(self):
+        if any(j.fut.cancelled() for j in self._waiting):  # withdrawn before admission
+            keep: collections.deque[_Job] = collections.deque()
+            for j in self._waiting:
+                if j.fut.cancelled():
+                    self.cancelled += 1
+                else:
+                    keep.append(j)
+            self._waiting = keep
         while self._waiting and self._slots < self.max_slots:
             job = self._waiting[0]
             if self._held + job.est > self.budget:
@@ -263,7 +276,11 @@ class Server:
                 job.handle, job.u = f.result()
             except BaseException as e:  # factor failed: report it and give the slot back
                 self._release_locked(job)
-                job.fut.set_exception(e)
+                _resolve(job.fut, exc=e)
+                self._cv.notify_all()
+                return
+            if job.fut.cancelled():  # withdrawn while it was built
+                self._cancel_locked(job)
                 self._cv.notify_all()
                 return
             if self._error is not None:  # a lane failed meanwhile: no lane will run this one
@@ -292,8 +309,7 @@ class Server:
 
     def _abandon_locked(self, job: _Job, exc: BaseException):
         """Fail an admitted job that will not run (its handle is freed, its slot returned)."""
-        if not job.fut.done():
-            job.fut.set_exception(exc)
+        _resolve(job.fut, exc=exc)
         if job.handle is not None:
             try:
                 job.handle.close()
@@ -303,6 +319,17 @@ class Server:
         if job.stream is not None:
             self._release_locked(job)
             job.stream = None
+
+    def _cancel_locked(self, job: _Job):
+        """Release a withdrawn solve: its slot at once, its memory once the handle is freed."""
+        self.cancelled += 1
+        h, job.handle, job.u = job.handle, None, None
+        self._release_slot_locked(job)
+        if h is None:
+            self._release_bytes_locked(job)
+            return
+        done = self._freer.submit(self._destroy, h)
+        done.add_done_callback(lambda _f, job=job: self._freed(job))
 
     def _finish(self, job: _Job, status: int):
         r = job.req
@@ -319,9 +346,9 @@ class Server:
         done = self._freer.submit(self._destroy, h)
         done.add_done_callback(lambda _f, job=job: self._freed(job))
         if status == hifcn.HIF_OK:
-            job.fut.set_result(res)
+            _resolve(job.fut, result=res)
         else:
-            job.fut.set_exception(hifcn.HifError(status, f"PCG did not converge at step "
+            _resolve(job.fut, exc=hifcn.HifError(status, f"PCG did not converge at step "
                                                          f"{job.step} of {r.nsteps}"))
 
     def _freed(self, job: _Job):
@@ -348,6 +375,12 @@ class Server:
                         self._cv.notify_all()
                         return
                     self._admit_locked()
+                    for j in [j for j in self._ready if j.fut.cancelled()]:
+                        self._ready.remove(j)
+                        self._cancel_locked(j)
+                    for j in [j for j in active if j.fut.cancelled()]:
+                        active.remove(j)
+                        self._cancel_locked(j)
                     if not self._paused:
                         mine = [j for j in self._ready if self._lane_of(j, self.lanes) == lane]
                         for j in mine:
@@ -385,14 +418,25 @@ class Server:
                 if self._error is None:
                     self._error = e
                 for j in list(self._waiting):  # not admitted: nothing held
-                    if not j.fut.done():
-                        j.fut.set_exception(e)
+                    _resolve(j.fut, exc=e)
                 self._waiting.clear()
                 for j in self._ready + active:
                     self._abandon_locked(j, e)
                 self._ready.clear()
                 active.clear()
                 self._cv.notify_all()
+
+
+def _resolve(fut: Future, result=None, exc: BaseException | None = None):
+    """Resolve a request's future unless the client cancelled it meanwhile."""
+    try:
+        if exc is not None:
+            fut.set_exception(exc)
+        else:
+            fut.set_result(result)
+    except InvalidStateError:  # cancelled (or already resolved): nothing to report
+        pass
+
 
 def percentiles(latencies, qs=(50, 99)) -> dict:
     """p50/p99 (nearest-rank) of a list of latencies in seconds."""

@@ -253,3 +253,39 @@ def test_server_lane_failure_resolves_every_future(gpu_lib, monkeypatch):
     with pytest.raises(RuntimeError):
         srv.close()
     assert srv._slots == 0 and srv._held == 0
+
+
+def test_server_cancel_waiting_building_and_running(gpu_lib):
+    """Future.cancel() withdraws a request at any stage: one still waiting for a slot, one whose
+    factor is being built or ready (the server is paused), and one in the middle of its steps.
+    Each leaves its slot and memory; the requests left run to results bitwise equal to running
+    alone."""
+    import time
+    from paper_2004_05566_amd.serve import Server
+    keep = _req(48, 0.02, 71, 3)
+    long_run = _req(64, 0.02, 73, 100000)    # would run for minutes if not withdrawn
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=2, builders=2, paused=True, lanes=1)
+    f_keep = srv.submit(keep)
+    f_ready = srv.submit(_req(40, 0.02, 75, 3))
+    f_wait = srv.submit(_req(32, 0.02, 77, 3))   # no slot while the other two hold both
+    assert f_wait.cancel()
+    t0 = time.perf_counter()
+    while srv.ready_count() < 2 and time.perf_counter() - t0 < 120:
+        time.sleep(0.01)
+    assert srv.ready_count() == 2
+    assert f_ready.cancel()
+    srv.resume()
+    res = f_keep.result(timeout=120)
+    f_long = srv.submit(long_run)
+    t0 = time.perf_counter()
+    while srv.rounds < 20 and time.perf_counter() - t0 < 120:  # the long solve is running
+        time.sleep(0.01)
+    assert f_long.cancel()
+    srv.close(wait=True)
+    assert f_wait.cancelled() and f_ready.cancelled() and f_long.cancelled()
+    u, its, rel = _alone(keep)
+    assert np.array_equal(res.u, u) and np.array_equal(res.iters, its)
+    st = srv.stats()
+    assert st["cancelled"] == 3
+    assert srv._slots == 0 and srv._held == 0
+    assert st["rounds"] < 100000
