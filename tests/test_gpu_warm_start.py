@@ -96,3 +96,48 @@ def test_batched_step_refuses_warm_start(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(u, u_before)
     h.close()
+
+
+def test_warm_steps_one_call_each_equal_warm_solve(gpu_lib):
+    """cn_step called step by step and cn_solve (which queues each step behind the previous one)
+    run the same warm-started arithmetic: bitwise equal states and iteration counts."""
+    import torch
+    from paper_2004_05566_amd import hifcn
+    n = 64
+    a = torch.tensor(gen.grf_coefficient(n, 2, 0.15, 41), device="cuda")
+    h = hifcn.factor(a, 0.05, n, 2, 1e-3, store="f32", leaf=8)
+    u0 = gen.bumps(n, 2, 3, 42).ravel()
+    react = (1, 1.0, 1.0)
+    u1 = torch.tensor(u0, device="cuda")
+    its_solve, _ = h.cn_solve(u1, 4, rtol=1e-10, reaction=react, warm_start=True)
+    u2 = torch.tensor(u0, device="cuda")
+    its_step = []
+    for _ in range(4):
+        it, _ = h.cn_step(u2, rtol=1e-10, reaction=react, warm_start=True)
+        its_step.append(int(it))
+    assert torch.equal(u1, u2)
+    assert [int(v) for v in its_solve] == its_step
+    h.close()
+
+
+def test_warm_start_nan_state_reports_no_convergence_and_keeps_u(gpu_lib):
+    """A NaN in u^k makes ||g||^2 and ||r0||^2 NaN: HIF_ERR_NO_CONV after no iteration, u left
+    as it was (as for x0 = 0)."""
+    import torch
+    from paper_2004_05566_amd import hifcn
+    n = 32
+    a = torch.tensor(gen.grf_coefficient(n, 2, 0.15, 43), device="cuda")
+    h = hifcn.factor(a, 0.05, n, 2, 1e-3, store="f64", leaf=8)
+    u0 = gen.bumps(n, 2, 3, 44).ravel()
+    u0[77] = np.nan
+    for call in ("step", "solve"):
+        u = torch.tensor(u0, device="cuda")
+        with pytest.raises(hifcn.HifError) as ei:
+            if call == "step":
+                h.cn_step(u, rtol=1e-10, warm_start=True)
+            else:
+                h.cn_solve(u, 3, rtol=1e-10, warm_start=True)
+        assert ei.value.status == hifcn.HIF_ERR_NO_CONV, call
+        got = u.cpu().numpy()
+        assert np.isnan(got[77]) and np.array_equal(np.delete(got, 77), np.delete(u0, 77)), call
+    h.close()
