@@ -40,14 +40,14 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def _time_cn(h, u0, steps, warmup, rtol, reaction):
+def _time_cn(h, u0, steps, warmup, rtol, reaction, maxit=500, warm=False):
     import torch
     u = u0.clone()
     if warmup:
-        h.cn_solve(u, warmup, rtol=rtol, reaction=reaction)
+        h.cn_solve(u, warmup, rtol=rtol, maxit=maxit, reaction=reaction, warm_start=warm)
     _sync()
     t0 = time.perf_counter()
-    its, rel = h.cn_solve(u, steps, rtol=rtol, reaction=reaction)
+    its, rel = h.cn_solve(u, steps, rtol=rtol, maxit=maxit, reaction=reaction, warm_start=warm)
     _sync()
     dt = time.perf_counter() - t0
     return dt, its, rel, u
@@ -259,7 +259,8 @@ def cpu_baseline(w, budget_steps: int, rtol: float = 1e-8):
         with threadpool_limits(limits=threads):
             t0 = time.perf_counter()
             _, its, _ = cn.cn_solve(A, B, w.u0, w.dt, budget_steps,
-                                    lambda r: phif.phif_apply(F, r), rtol, w.reaction)
+                                    lambda r: phif.phif_apply(F, r), rtol, w.reaction,
+                                    maxit=w.maxit, warm_start=w.x0 == "previous")
             times[threads] = time.perf_counter() - t0
     model = ""
     try:
@@ -399,7 +400,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="heat2d-1024")
+    ap.add_argument("--workload", default="heat2d-1024",
+                    help="a committed workload (workloads/configs/<name>.json) or a config path")
     ap.add_argument("--store", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--leaf", type=int, default=0, help="leaf box size (default: the workload's)")
@@ -517,7 +519,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "dim": w.dim, "n": w.n, "eps": w.eps,
                    "dt": w.dt, "leaf": w.leaf, "store": args.store, "rtol": args.rtol,
-                   "reaction": list(w.reaction)},
+                   "maxit": w.maxit, "x0": w.x0, "reaction": list(w.reaction)},
         **head,
         "roofline": roof,
         "f64_store": side.get("f64"),
@@ -572,7 +574,8 @@ def measure(w, store, steps, warmup, rtol, roofline=False, stages=False, check=T
     h = hifcn.factor(a_dev, w.dt, w.n, w.dim, w.eps, store=store, leaf=w.leaf)
     _sync()
     t_factor = time.perf_counter() - t0
-    elapsed, its, rel, u = _time_cn(h, u0, steps, warmup, rtol, w.reaction)
+    elapsed, its, rel, u = _time_cn(h, u0, steps, warmup, rtol, w.reaction, w.maxit,
+                                    w.x0 == "previous")
     info = h.info()
     fb = h.factor_bytes()
     x = torch.randn(w.N, dtype=torch.float64, device=dev)
@@ -621,7 +624,7 @@ def dominant_roofline(h, w, store, u0, steps, rtol, stages):
     roof = {}
     for st, lev in cands:
         h.profile_stage(lev, st, True)
-        _time_cn(h, u0, steps, 0, rtol, w.reaction)
+        _time_cn(h, u0, steps, 0, rtol, w.reaction, w.maxit, w.x0 == "previous")
         p = h.profile_read()
         h.profile_stage(lev, st, False)
         roof[(st, lev)] = p

@@ -19,4 +19,6 @@ from .gen import (  # noqa: F401
     sine_mode,
     workload,
     WORKLOADS,
+    load_config,
+    config_names,
 )

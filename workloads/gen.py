@@ -11,6 +11,8 @@ All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
 """
 from __future__ import annotations
 
+import json
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -184,37 +186,13 @@ class Workload:
     reaction: tuple = (0, 0.0, 0.0)  # (kind, k1, k2): 0 none, 1 k1*u*(1-u/k2)
     leaf: int = 8
     store: str = "f32"
+    maxit: int = 500
+    x0: str = "zero"  # PCG initial guess: "zero" (x0 = 0) or "previous" (x0 = u^k)
     extra: dict = field(default_factory=dict)
 
     @property
     def N(self) -> int:
         return self.n ** self.dim
-
-
-def _heat_small() -> Workload:
-    n = 32
-    return Workload("heat2d-32", 2, n, np.ones((n + 1, n + 1)), sine_mode(n, 2), 1e-2, 10,
-                    1e-6, 1e-10, store="f64")
-
-
-def _fisher_256() -> Workload:
-    n = 256
-    return Workload("fisher2d-256", 2, n, grf_coefficient(n, 2, 0.1, 2001),
-                    bumps(n, 2, 10, 2002), 1e-3, 100, 1e-4, 1e-8, reaction=(1, 1.0, 1.0))
-
-
-def _heat_1024(eps: float = 1e-3) -> Workload:
-    n = 1024
-    return Workload("heat2d-1024", 2, n, iid_loguniform_cells(n, 2, 3001),
-                    iid_uniform_nodes(n, 2, 3002), 1e-1, 20, eps, 1e-8)
-
-
-def _heat3d_64() -> Workload:
-    n = 64
-    rng = _rng(4002)
-    u0 = sine_mode(n, 3) + 0.1 * rng.normal(size=(n,) * 3)
-    return Workload("heat3d-64", 3, n, grf_coefficient(n, 3, 0.15, 4001), u0, 1e-2, 20,
-                    1e-4, 1e-8)
 
 
 def paper_heat(n: int, dim: int, eps: float, seed: int = 6000, steps: int = 100,
@@ -263,13 +241,89 @@ def serving_requests(count: int = 256, seed_base: int = 5000, sizes=(64, 128, 25
     return [serving_request(i, seed_base, sizes) for i in range(count)]
 
 
-WORKLOADS = {
-    "heat2d-32": _heat_small,
-    "fisher2d-256": _fisher_256,
-    "heat2d-1024": _heat_1024,
-    "heat3d-64": _heat3d_64,
-}
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def _coefficient(n: int, dim: int, spec: dict) -> np.ndarray:
+    """Cell coefficients a on the (n+1)^dim cells from a config's "a" object."""
+    k = spec["kind"]
+    if k == "constant":
+        return np.full((n + 1,) * dim, float(spec["value"]))
+    if k == "grf":
+        return grf_coefficient(n, dim, float(spec["length"]), int(spec["seed"]),
+                               float(spec.get("lo", 0.1)), float(spec.get("hi", 10.0)))
+    if k == "spectral_grf":
+        return spectral_grf_coefficient(n, dim, float(spec["length"]), int(spec["seed"]),
+                                        float(spec.get("lo", 0.1)), float(spec.get("hi", 10.0)))
+    if k == "iid_loguniform":
+        return iid_loguniform_cells(n, dim, int(spec["seed"]), float(spec.get("lo_exp", -2.0)),
+                                    float(spec.get("hi_exp", 2.0)))
+    if k == "gaussian_sum":
+        return gaussian_sum_coefficient(n, dim, int(spec["m"]), float(spec["sigma2"]),
+                                        float(spec["lo"]), float(spec["hi"]), int(spec["seed"]))
+    raise ValueError(f"unknown coefficient kind {k!r}")
+
+
+def _initial(n: int, dim: int, spec: dict) -> np.ndarray:
+    """Initial state u0 on the n^dim nodes from a config's "u0" object."""
+    k = spec["kind"]
+    if k == "sine_mode":
+        return sine_mode(n, dim, int(spec.get("p", 1)))
+    if k == "sine_plus_noise":  # the sine mode plus `noise` times standard normal values
+        rng = _rng(int(spec["seed"]))
+        return sine_mode(n, dim, int(spec.get("p", 1))) + float(spec["noise"]) * rng.normal(
+            size=(n,) * dim)
+    if k == "bumps":
+        return bumps(n, dim, int(spec["count"]), int(spec["seed"]),
+                     float(spec.get("width2", 0.005)))
+    if k == "iid_uniform":
+        return iid_uniform_nodes(n, dim, int(spec["seed"]))
+    if k == "gaussian":
+        return float(spec.get("scale", 1.0)) * gaussian_initial(n, dim, tuple(spec["centres"]),
+                                                                float(spec["sigma2"]))
+    raise ValueError(f"unknown initial-state kind {k!r}")
+
+
+CONFIG_FIELDS = ("name", "dim", "n", "leaf", "a", "u0", "dt", "steps", "eps", "store", "rtol",
+                 "maxit", "x0", "reaction")
+
+
+def load_config(cfg, **override) -> Workload:
+    """A workload from a JSON config (a path or an already parsed dict): grid (dim, n), leaf box
+    size m, the recipes of a and u0 with their seeds, dt, steps, eps, storage, rtol, maxit, the
+    PCG initial guess ("zero": x0 = 0, "previous": x0 = u^k) and the reaction (kind, k1, k2).
+    Keyword arguments replace top-level fields."""
+    if not isinstance(cfg, dict):
+        with open(cfg) as f:
+            cfg = json.load(f)
+    cfg = {**cfg, **override}
+    missing = [k for k in CONFIG_FIELDS if k not in cfg]
+    if missing:
+        raise ValueError(f"config {cfg.get('name')!r} lacks {missing}")
+    if cfg["x0"] not in ("zero", "previous"):
+        raise ValueError("x0 must be 'zero' or 'previous'")
+    if cfg["store"] not in ("f32", "f64", "bf16"):
+        raise ValueError("store must be f32, f64 or bf16")
+    n, dim = int(cfg["n"]), int(cfg["dim"])
+    return Workload(cfg["name"], dim, n, _coefficient(n, dim, cfg["a"]), _initial(n, dim, cfg["u0"]),
+                    float(cfg["dt"]), int(cfg["steps"]), float(cfg["eps"]), float(cfg["rtol"]),
+                    reaction=tuple(cfg["reaction"]), leaf=int(cfg["leaf"]),
+                    store=cfg["store"], maxit=int(cfg["maxit"]), x0=cfg["x0"],
+                    extra={"config": cfg})
+
+
+def config_names() -> list[str]:
+    """Names of the committed workload configs (configs/<name>.json)."""
+    return sorted(f[:-5] for f in os.listdir(CONFIG_DIR) if f.endswith(".json"))
+
+
+WORKLOADS = {name: (lambda name=name, **kw: load_config(os.path.join(CONFIG_DIR, name + ".json"),
+                                                        **kw))
+             for name in config_names()}
 
 
 def workload(name: str, **kw) -> Workload:
+    """A committed workload by name (configs/<name>.json), or any config file by its path."""
+    if name.endswith(".json"):
+        return load_config(name, **kw)
     return WORKLOADS[name](**kw)
